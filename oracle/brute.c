@@ -1,0 +1,105 @@
+/* Brute-force FP64 sums for the oracle.  Test infrastructure only.
+ *
+ * A grid holds nx*ny*nz voxels stored [z][y][x].  Gaussian i has an index-frame centre
+ * c[i] (3), conic C[i] (3x3, row-major, the inverse covariance in the grid's index frame),
+ * amplitude amp[i] and an inclusive integer box lo[i]..hi[i] (x, y, z) that is used only
+ * when nonempty[i] != 0.  The value of Gaussian i at voxel v is
+ *     amp[i] * exp(-0.5 * (v - c)^T C (v - c))     when v lies in its box, else 0
+ * (the paper's volumetric rendering, Eq. 7, truncated to the box).
+ *
+ * Sums run over Gaussians in ascending index.  No tiles, no binning, no reordering.
+ */
+#include <math.h>
+#include <stdint.h>
+
+static double gauss_value(const double* c, const double* C, double amp,
+                          double x, double y, double z)
+{
+    const double d0 = x - c[0], d1 = y - c[1], d2 = z - c[2];
+    const double q = d0 * (C[0] * d0 + C[1] * d1 + C[2] * d2)
+                   + d1 * (C[3] * d0 + C[4] * d1 + C[5] * d2)
+                   + d2 * (C[6] * d0 + C[7] * d1 + C[8] * d2);
+    return amp * exp(-0.5 * q);
+}
+
+static int in_box(const int64_t* lo, const int64_t* hi, int64_t x, int64_t y, int64_t z)
+{
+    return x >= lo[0] && x <= hi[0] && y >= lo[1] && y <= hi[1] && z >= lo[2] && z <= hi[2];
+}
+
+/* out[z][y][x] = sum over every Gaussian i (ascending) of its value, if v is in its box. */
+void oracle_render(int64_t nx, int64_t ny, int64_t nz, int64_t n, const double* c,
+                   const double* C, const double* amp, const int64_t* lo, const int64_t* hi,
+                   const uint8_t* nonempty, double* out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t z = 0; z < nz; ++z) {
+        for (int64_t y = 0; y < ny; ++y) {
+            for (int64_t x = 0; x < nx; ++x) {
+                double acc = 0.0;
+                for (int64_t i = 0; i < n; ++i) {
+                    if (!nonempty[i] || !in_box(lo + 3 * i, hi + 3 * i, x, y, z)) continue;
+                    acc += gauss_value(c + 3 * i, C + 9 * i, amp[i], (double)x, (double)y,
+                                       (double)z);
+                }
+                out[(z * ny + y) * nx + x] = acc;
+            }
+        }
+    }
+}
+
+/* The same sum at selected voxels pts[k] = (x, y, z). */
+void oracle_render_points(int64_t npts, const int64_t* pts, int64_t n, const double* c,
+                          const double* C, const double* amp, const int64_t* lo,
+                          const int64_t* hi, const uint8_t* nonempty, double* out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < npts; ++k) {
+        const int64_t x = pts[3 * k], y = pts[3 * k + 1], z = pts[3 * k + 2];
+        double acc = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            if (!nonempty[i] || !in_box(lo + 3 * i, hi + 3 * i, x, y, z)) continue;
+            acc += gauss_value(c + 3 * i, C + 9 * i, amp[i], (double)x, (double)y, (double)z);
+        }
+        out[k] = acc;
+    }
+}
+
+/* For L = sum_v g[v] I[v]: per Gaussian, over the voxels of its box,
+ *   d_amp[i]  = sum g * e            (e = exp(-q/2), w = amp * e)
+ *   d_c[i]    = sum g * w * C (v - c)
+ *   G_C[i]    = sum g * w * (-1/2) (v - c)(v - c)^T      (dL/dC, 3x3 row-major)     */
+void oracle_partials(int64_t nx, int64_t ny, int64_t nz, int64_t n, const double* c,
+                     const double* C, const double* amp, const int64_t* lo,
+                     const int64_t* hi, const uint8_t* nonempty, const double* g,
+                     double* d_amp, double* d_c, double* G_C)
+{
+    (void)nz;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        double s_amp = 0.0, s_c[3] = {0, 0, 0}, s_C[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if (nonempty[i]) {
+            const double* ci = c + 3 * i;
+            const double* Ci = C + 9 * i;
+            for (int64_t z = lo[3 * i + 2]; z <= hi[3 * i + 2]; ++z)
+                for (int64_t y = lo[3 * i + 1]; y <= hi[3 * i + 1]; ++y)
+                    for (int64_t x = lo[3 * i]; x <= hi[3 * i]; ++x) {
+                        const double gv = g[(z * ny + y) * nx + x];
+                        const double d[3] = {(double)x - ci[0], (double)y - ci[1],
+                                             (double)z - ci[2]};
+                        const double e = gauss_value(ci, Ci, 1.0, (double)x, (double)y,
+                                                     (double)z);
+                        const double gw = gv * amp[i] * e;
+                        s_amp += gv * e;
+                        for (int a = 0; a < 3; ++a) {
+                            s_c[a] += gw * (Ci[3 * a] * d[0] + Ci[3 * a + 1] * d[1]
+                                            + Ci[3 * a + 2] * d[2]);
+                            for (int b = 0; b < 3; ++b) s_C[3 * a + b] += -0.5 * gw * d[a] * d[b];
+                        }
+                    }
+        }
+        d_amp[i] = s_amp;
+        for (int a = 0; a < 3; ++a) d_c[3 * i + a] = s_c[a];
+        for (int a = 0; a < 9; ++a) G_C[9 * i + a] = s_C[a];
+    }
+}

@@ -1,0 +1,323 @@
+"""Plain FP64 definitions of Magnetic-Gaussian rendering on voxel grids and its gradients.
+
+Test infrastructure only (see the package docstring).
+
+The model (paper Sec. 3.2-3.3): a Gaussian G_i = {mu_i, Sigma_i, alpha_i} (Eq. 2) with
+Sigma = R S S^T R^T, S = diag(exp s), R from the normalised quaternion (Eq. 3), contributes
+alpha_i exp(-1/2 (x - mu_i)^T Sigma_i^-1 (x - mu_i)) to the intensity at x (Eq. 7).
+
+Evaluated on a grid g with world->index affine [L | t] at integer voxel index v, in the
+grid's index frame:
+    c = L mu + t,   Sigma_idx = L Sigma L^T.
+Stacks carry a Gaussian slice profile of std-dev sig along index z (the slice normal); the
+recorded value is the Gaussian convolved with that normalised 1D profile, which is again a
+Gaussian with
+    Sigma_g = Sigma_idx + sig^2 e_z e_z^T,   amp = alpha sqrt(det Sigma_idx / det Sigma_g),
+so  I_g[v] = sum_i 1[v in Box_g(i)] amp_i exp(-1/2 (v - c_i)^T Sigma_g,i^-1 (v - c_i)).
+With sig = 0 this is Eq. 7 at voxel centres.  Box_g(i) comes from oracle.recipe.
+alpha = sigmoid(logit) keeps the intensity in [0, 1] (Eq. 2 states alpha in [0, 1]).
+
+Everything here is computed in float64 from the float32 inputs; functions taking
+``dtype`` also run in complex128 for complex-step differentiation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import numpy as np
+
+from . import recipe
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(os.path.dirname(__file__), "_build", "libbrute.so")
+        if not os.path.exists(path):
+            from . import build
+            build.build()
+        lib = ctypes.CDLL(path)
+        P = ctypes.c_void_p
+        I = ctypes.c_int64
+        lib.oracle_render.argtypes = [I, I, I, I, P, P, P, P, P, P, P]
+        lib.oracle_render_points.argtypes = [I, P, I, P, P, P, P, P, P, P]
+        lib.oracle_partials.argtypes = [I, I, I, I, P, P, P, P, P, P, P, P, P, P]
+        lib.oracle_render.restype = None
+        lib.oracle_render_points.restype = None
+        lib.oracle_partials.restype = None
+        _LIB = lib
+    return _LIB
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ----------------------------------------------------------------------------------------
+# per-Gaussian quantities (Eq. 2-3, slice profile)
+# ----------------------------------------------------------------------------------------
+
+def quat_to_rot(qn):
+    """Hamilton rotation matrix of unit quaternions qn[..., (w,x,y,z)]; columns are the
+    rotated coordinate axes."""
+    w, x, y, z = qn[..., 0], qn[..., 1], qn[..., 2], qn[..., 3]
+    R = np.empty(qn.shape[:-1] + (3, 3), dtype=qn.dtype)
+    R[..., 0, 0] = 1 - 2 * (y * y + z * z)
+    R[..., 0, 1] = 2 * (x * y - w * z)
+    R[..., 0, 2] = 2 * (x * z + w * y)
+    R[..., 1, 0] = 2 * (x * y + w * z)
+    R[..., 1, 1] = 1 - 2 * (x * x + z * z)
+    R[..., 1, 2] = 2 * (y * z - w * x)
+    R[..., 2, 0] = 2 * (x * z - w * y)
+    R[..., 2, 1] = 2 * (y * z + w * x)
+    R[..., 2, 2] = 1 - 2 * (x * x + y * y)
+    return R
+
+
+def sigmoid(a):
+    return 1.0 / (1.0 + np.exp(-a))
+
+
+def params64(g, dtype=np.float64):
+    """(mean, quat, log_scale, logit) of a Gaussians object as arrays of ``dtype``."""
+    return tuple(np.asarray(getattr(g, k), np.float32).astype(np.float64).astype(dtype)
+                 for k in ("mean", "quat", "log_scale", "logit"))
+
+
+def world_terms(mean, quat, log_scale, logit):
+    """World-space quantities: normalised quaternion, R, S^2 = exp(2 s), Sigma, alpha."""
+    qnorm = np.sqrt((quat * quat).sum(-1))
+    qn = quat / qnorm[:, None]
+    R = quat_to_rot(qn)
+    S2 = np.exp(2 * log_scale)
+    Sigma = np.einsum("nij,nj,nkj->nik", R, S2, R)
+    alpha = sigmoid(logit)
+    return dict(qnorm=qnorm, qn=qn, R=R, S2=S2, Sigma=Sigma, alpha=alpha)
+
+
+def grid_terms(mean, quat, log_scale, logit, grid, wt=None):
+    """Index-frame quantities on one grid: centre c, Sigma_idx, Sigma_g, conic C =
+    Sigma_g^-1 and amplitude amp (slice-profile convolution in closed form)."""
+    if wt is None:
+        wt = world_terms(mean, quat, log_scale, logit)
+    A = np.asarray(grid.world_to_index, np.float64)
+    L, t = A[:, :3], A[:, 3]
+    c = mean @ L.T + t
+    Sig_idx = np.einsum("ij,njk,lk->nil", L, wt["Sigma"], L)
+    Sig_g = Sig_idx.copy()
+    Sig_g[:, 2, 2] = Sig_g[:, 2, 2] + grid.psf_sigma_z ** 2
+    C = np.linalg.inv(Sig_g)
+    amp = wt["alpha"] * np.sqrt(np.linalg.det(Sig_idx) / np.linalg.det(Sig_g))
+    return dict(c=c, Sig_idx=Sig_idx, Sig_g=Sig_g, C=C, amp=amp, L=L, wt=wt)
+
+
+# ----------------------------------------------------------------------------------------
+# rendering
+# ----------------------------------------------------------------------------------------
+
+def _f64c(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _boxes_c(lo, hi, nonempty):
+    return (np.ascontiguousarray(lo, np.int64), np.ascontiguousarray(hi, np.int64),
+            np.ascontiguousarray(nonempty, np.uint8))
+
+
+def render(grid, gt, lo, hi, nonempty):
+    """Brute force FP64 over every voxel and every Gaussian (ascending i), box-tested."""
+    lib = _lib()
+    n = gt["c"].shape[0]
+    out = np.zeros(grid.shape, np.float64)
+    c, C, amp = _f64c(gt["c"]), _f64c(gt["C"]), _f64c(gt["amp"])
+    lo, hi, ne = _boxes_c(lo, hi, nonempty)
+    lib.oracle_render(grid.nx, grid.ny, grid.nz, n, _ptr(c), _ptr(C), _ptr(amp), _ptr(lo),
+                      _ptr(hi), _ptr(ne), _ptr(out))
+    return out
+
+
+def render_points(points, gt, lo, hi, nonempty):
+    """Values at selected voxels points[k] = (x, y, z), brute force over all Gaussians."""
+    lib = _lib()
+    pts = np.ascontiguousarray(points, np.int64)
+    n = gt["c"].shape[0]
+    out = np.zeros(pts.shape[0], np.float64)
+    c, C, amp = _f64c(gt["c"]), _f64c(gt["C"]), _f64c(gt["amp"])
+    lo, hi, ne = _boxes_c(lo, hi, nonempty)
+    lib.oracle_render_points(pts.shape[0], _ptr(pts), n, _ptr(c), _ptr(C), _ptr(amp),
+                             _ptr(lo), _ptr(hi), _ptr(ne), _ptr(out))
+    return out
+
+
+def render_numpy(grid, gt, lo, hi, nonempty):
+    """Same sum as render(), vectorised in numpy for tiny inputs; works in complex128."""
+    dt = np.result_type(gt["c"].dtype, gt["C"].dtype, gt["amp"].dtype)
+    z, y, x = np.meshgrid(np.arange(grid.nz), np.arange(grid.ny), np.arange(grid.nx),
+                          indexing="ij")
+    v = np.stack([x, y, z], -1).reshape(-1, 3).astype(np.float64)
+    out = np.zeros(v.shape[0], dtype=dt)
+    for i in range(gt["c"].shape[0]):
+        if not nonempty[i]:
+            continue
+        inside = ((v >= lo[i]) & (v <= hi[i])).all(1)
+        d = v[inside] - gt["c"][i]
+        q = np.einsum("kj,jl,kl->k", d, gt["C"][i], d)
+        out[inside] = out[inside] + gt["amp"][i] * np.exp(-0.5 * q)
+    return out.reshape(grid.shape)
+
+
+# ----------------------------------------------------------------------------------------
+# gradients
+# ----------------------------------------------------------------------------------------
+
+def grid_partials(grid, gt, lo, hi, nonempty, dl_di):
+    """Per-Gaussian sums over its box of the derivatives of sum_v dl_di[v] I[v] with respect
+    to the grid-frame quantities: d_amp [N], d_c [N,3] and G_C [N,3,3] = dL/dC (C taken as
+    a full matrix; symmetric)."""
+    lib = _lib()
+    n = gt["c"].shape[0]
+    c, C, amp = _f64c(gt["c"]), _f64c(gt["C"]), _f64c(gt["amp"])
+    lo, hi, ne = _boxes_c(lo, hi, nonempty)
+    g = _f64c(dl_di)
+    d_amp = np.zeros(n)
+    d_c = np.zeros((n, 3))
+    G_C = np.zeros((n, 3, 3))
+    lib.oracle_partials(grid.nx, grid.ny, grid.nz, n, _ptr(c), _ptr(C), _ptr(amp), _ptr(lo),
+                        _ptr(hi), _ptr(ne), _ptr(g), _ptr(d_amp), _ptr(d_c), _ptr(G_C))
+    return d_amp, d_c, G_C
+
+
+def chain(mean, quat, log_scale, logit, grids, partials):
+    """Raw-parameter gradients from the grid-frame partials of every grid.
+
+    Per grid: dL/dmu += L^T d_c;  dL/dSigma_g = -C G_C C;  log amp = log alpha
+    + 1/2 log det Sigma_idx - 1/2 log det Sigma_g gives dL/dSigma_idx = dL/dSigma_g
+    + 1/2 d_amp amp Sigma_idx^-1 - ... (the Sigma_g part: -1/2 d_amp amp C), and
+    dL/dSigma += L^T dL/dSigma_idx L;  dL/dalpha += d_amp amp / alpha.
+    Then Sigma = R diag(e^2s) R^T: dL/dR = 2 G R D, dL/ds_m = 2 e^{2 s_m} (R^T G R)_mm;
+    R(q_hat) by the Hamilton formula; q_hat = q/|q|; alpha = sigmoid(logit).
+    """
+    wt = world_terms(mean, quat, log_scale, logit)
+    n = mean.shape[0]
+    dt = np.result_type(mean.dtype, np.float64)
+    d_mu = np.zeros((n, 3), dt)
+    G_S = np.zeros((n, 3, 3), dt)
+    d_alpha = np.zeros(n, dt)
+    for grid, (d_amp, d_c, G_C) in zip(grids, partials):
+        gt = grid_terms(mean, quat, log_scale, logit, grid, wt)
+        L = gt["L"]
+        d_mu += d_c @ L
+        C = gt["C"]
+        G_g = -np.einsum("nij,njk,nkl->nil", C, G_C, C) - 0.5 * (d_amp * gt["amp"])[:, None, None] * C
+        G_idx = G_g + 0.5 * (d_amp * gt["amp"])[:, None, None] * np.linalg.inv(gt["Sig_idx"])
+        G_S += np.einsum("ji,njk,kl->nil", L, G_idx, L)
+        d_alpha += d_amp * gt["amp"] / wt["alpha"]
+    R, S2 = wt["R"], wt["S2"]
+    GR = 2 * np.einsum("nij,njk,nk->nik", G_S, R, S2)
+    RtGR = np.einsum("nji,njk,nkl->nil", R, G_S, R)
+    d_s = 2 * S2 * np.einsum("nii->ni", RtGR)
+    qn = wt["qn"]
+    w, x, y, z = qn[:, 0], qn[:, 1], qn[:, 2], qn[:, 3]
+    g = GR
+    d_qn = np.stack([
+        2 * (-z * g[:, 0, 1] + y * g[:, 0, 2] + z * g[:, 1, 0] - x * g[:, 1, 2]
+             - y * g[:, 2, 0] + x * g[:, 2, 1]),
+        2 * (y * g[:, 0, 1] + z * g[:, 0, 2] + y * g[:, 1, 0] - 2 * x * g[:, 1, 1]
+             - w * g[:, 1, 2] + z * g[:, 2, 0] + w * g[:, 2, 1] - 2 * x * g[:, 2, 2]),
+        2 * (-2 * y * g[:, 0, 0] + x * g[:, 0, 1] + w * g[:, 0, 2] + x * g[:, 1, 0]
+             + z * g[:, 1, 2] - w * g[:, 2, 0] + z * g[:, 2, 1] - 2 * y * g[:, 2, 2]),
+        2 * (-2 * z * g[:, 0, 0] - w * g[:, 0, 1] + x * g[:, 0, 2] + w * g[:, 1, 0]
+             - 2 * z * g[:, 1, 1] + y * g[:, 1, 2] + x * g[:, 2, 0] + y * g[:, 2, 1]),
+    ], axis=1)
+    d_q = (d_qn - qn * (qn * d_qn).sum(1, keepdims=True)) / wt["qnorm"][:, None]
+    d_logit = d_alpha * wt["alpha"] * (1 - wt["alpha"])
+    return d_mu, d_q, d_s, d_logit
+
+
+def aniso(log_scale, lam_r):
+    """Eq. 13 with the ratio of the actual scales: mean_i max(0, e^{max s - min s} - lam_r).
+    Gradient: +-e^D/N on the first argmax / first argmin where the hinge is active."""
+    s = np.asarray(log_scale, np.float32).astype(np.float64)
+    n = s.shape[0]
+    if n == 0:
+        return 0.0, np.zeros_like(s)
+    imax = np.argmax(s, axis=1)
+    imin = np.argmin(s, axis=1)
+    D = s[np.arange(n), imax] - s[np.arange(n), imin]
+    ratio = np.exp(D)
+    act = ratio > lam_r
+    val = float(np.where(act, ratio - lam_r, 0.0).sum() / n)
+    grad = np.zeros_like(s)
+    gr = np.where(act, ratio / n, 0.0)
+    np.add.at(grad, (np.arange(n), imax), gr)
+    np.add.at(grad, (np.arange(n), imin), -gr)
+    return val, grad
+
+
+def smooth_l1(preds: Sequence[np.ndarray], targets: Sequence[np.ndarray]):
+    """Eq. 11 (beta = 1) averaged over every voxel of every stack; returns the value and
+    dL/dI per stack."""
+    ntot = sum(p.size for p in preds)
+    val = 0.0
+    grads = []
+    for p, y in zip(preds, targets):
+        d = np.asarray(p, np.float64) - np.asarray(y, np.float64)
+        ad = np.abs(d)
+        val += float(np.where(ad < 1.0, 0.5 * d * d, ad - 0.5).sum())
+        grads.append(np.clip(d, -1.0, 1.0) / ntot)
+    return val / ntot, grads
+
+
+def adam(param, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step in the PyTorch arrangement, FP64.  Returns (param, m, v)."""
+    p = np.asarray(param, np.float64)
+    g = np.asarray(grad, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1 - beta2) * g * g
+    bc1 = 1 - beta1 ** step
+    bc2 = 1 - beta2 ** step
+    p = p - (lr / bc1) * m / (np.sqrt(v) / np.sqrt(bc2) + eps)
+    return p, m, v
+
+
+def psnr(vol, ref):
+    mse = float(np.mean((np.asarray(vol, np.float64) - np.asarray(ref, np.float64)) ** 2))
+    return float("inf") if mse == 0 else 10.0 * np.log10(1.0 / mse)
+
+
+# ----------------------------------------------------------------------------------------
+# convenience: everything for one set of Gaussians on several grids
+# ----------------------------------------------------------------------------------------
+
+def prepare(g, grids, cutoff=3.0):
+    """Per grid: (terms, lo, hi, nonempty, valid) for a Gaussians object."""
+    mean, quat, ls, logit = params64(g)
+    wt = world_terms(mean, quat, ls, logit)
+    out = []
+    for gr in grids:
+        lo, hi, ne, valid = recipe.boxes(g.mean, g.quat, g.log_scale, g.logit, gr, cutoff)
+        gt = grid_terms(mean, quat, ls, logit, gr, wt)
+        out.append((gt, lo, hi, ne, valid))
+    return out
+
+
+def render_all(g, grids, cutoff=3.0):
+    return [render(gr, gt, lo, hi, ne) for gr, (gt, lo, hi, ne, _) in
+            zip(grids, prepare(g, grids, cutoff))]
+
+
+def gradients(g, grids, dl_dis, cutoff=3.0, lam_aniso=0.0, lam_r=1.5):
+    """Analytic FP64 raw-parameter gradients of sum_g sum_v dl_di_g[v] I_g[v]
+    (+ lam_aniso * aniso loss), boxes held fixed."""
+    mean, quat, ls, logit = params64(g)
+    prep = prepare(g, grids, cutoff)
+    parts = [grid_partials(gr, gt, lo, hi, ne, d) for gr, (gt, lo, hi, ne, _), d in
+             zip(grids, prep, dl_dis)]
+    d_mu, d_q, d_s, d_a = chain(mean, quat, ls, logit, grids, parts)
+    if lam_aniso:
+        d_s = d_s + lam_aniso * aniso(g.log_scale, lam_r)[1]
+    return d_mu, d_q, d_s, d_a

@@ -1,0 +1,216 @@
+/* gm.h - C ABI of the Magnetic-Gaussian voxel-evaluation library (libgm.so, gfx950).
+ *
+ * The library evaluates the paper's Magnetic Gaussian primitives (M-Gaussian, arXiv
+ * 2603.00145, Sec. 3.2, Eq. 2-3) onto voxel grids - the thick-slice stacks a
+ * reconstruction is fitted to (Sec. 3.3.2, Eq. 7, with a Gaussian slice profile along each
+ * stack's slice normal) and the isotropic target volume (Sec. 3.1, inference) - and runs
+ * the matching backward pass, the losses of Sec. 3.5.2 and the Adam update of Sec. 4.1.4.
+ *
+ * Conventions shared by every entry point
+ *   - Pointers are DEVICE pointers unless marked [host].  The caller allocates and frees
+ *     every buffer; the library allocates no device memory and keeps no pointer after a
+ *     call returns.  Buffers must be 16-byte aligned (PyTorch allocations are).
+ *   - Every call enqueues its kernels on `stream` (a hipStream_t; NULL = default stream)
+ *     and returns without synchronising, except gm_bin (one synchronisation, see there).
+ *   - Every call returns a gm_status.  Arguments are validated on the host before anything
+ *     is enqueued; on error nothing is enqueued and gm_last_error() describes the problem.
+ *     An asynchronous device fault surfaces as GM_ERR_HIP from a later call.
+ *   - Gaussian parameters (Eq. 2-3), float32, row-major:
+ *       mean[n][3]       centre in normalised world coordinates ([-1,1]^3 is the volume)
+ *       quat[n][4]       rotation quaternion (w, x, y, z), unnormalised; normalised before
+ *                        use (Sec. 3.2)
+ *       log_scale[n][3]  log of the world-space standard deviations (S = diag(exp s))
+ *       logit[n]         intensity alpha = 1 / (1 + exp(-logit)), so alpha is in [0, 1]
+ *   - Voxel arrays are float32 [nz][ny][nx] (x fastest).  Voxel v of a grid sits at the
+ *     integer index v of that grid's index frame.
+ *   - Reentrant.  The only global state is the thread-local error string.
+ */
+#ifndef GM_H
+#define GM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GM_ABI_VERSION 1
+#define GM_MAX_GRIDS 8
+#define GM_RECORD_FLOATS 16       /* floats per (grid, Gaussian) record                */
+#define GM_GRID_GRAD_FLOATS 10    /* floats per (grid, Gaussian) backward partial      */
+#define GM_REDUCE_WORKSPACE_BYTES 16384 /* workspace for the reductions below           */
+
+typedef void* gm_stream; /* hipStream_t */
+
+typedef enum gm_status {
+    GM_OK = 0,
+    GM_ERR_INVALID_ARGUMENT = 1, /* bad size, NULL or misaligned pointer, bad descriptor */
+    GM_ERR_CAPACITY = 2,         /* pair buffer too small; *n_pairs holds the need        */
+    GM_ERR_NONFINITE = 3,        /* NaN/Inf parameter, zero quaternion or exp overflow    */
+    GM_ERR_HIP = 4,              /* HIP runtime error (launch failure, device fault)      */
+    GM_ERR_UNSUPPORTED = 5
+} gm_status;
+
+/* Gaussian parameters (read only) and their gradients (accumulated with +=). */
+typedef struct gm_gaussians {
+    int64_t n;
+    const float* mean;
+    const float* quat;
+    const float* log_scale;
+    const float* logit;
+} gm_gaussians;
+
+typedef struct gm_gaussian_grads {
+    int64_t n;
+    float* mean;
+    float* quat;
+    float* log_scale;
+    float* logit;
+} gm_gaussian_grads;
+
+/* [host] A voxel grid.  world_to_index is the row-major 3x4 affine [L | t] taking normalised
+ * world coordinates to this grid's voxel indices; for a stack it folds in the stack's rigid
+ * placement T_k (Sec. 3.3.2).  psf_sigma_z is the standard deviation, in index units along
+ * index z (the slice normal), of the Gaussian slice profile the stack was acquired with;
+ * 0 means point sampling (Eq. 7 exactly, used for the target volume). */
+typedef struct gm_grid {
+    int32_t nx, ny, nz, reserved;
+    double world_to_index[12];
+    double psf_sigma_z;
+} gm_grid;
+
+/* [host] Binning options.  cutoff_sigma: a Gaussian is evaluated on the voxels of the
+ * axis-aligned box of +-cutoff_sigma marginal standard deviations around its centre in the
+ * grid's index frame (3 = the 3-sigma box); it stands in for the paper's cell-neighbourhood
+ * query (Sec. 3.3.1, Eq. 4-6). */
+typedef struct gm_bin_opts {
+    double cutoff_sigma;
+} gm_bin_opts;
+
+/* Binning state: caller-allocated device buffers (sizes from gm_bin_query) plus host fields
+ * that gm_bin fills in and later calls read.
+ *   records     [n_grids][n_gauss][16] float: per (grid, Gaussian)
+ *               c_rel(3) = centre - lo, amp, K(6) = -1/2 log2(e) x conic with the three
+ *               off-diagonal terms doubled (xx, yy, zz, xy, xz, yz), lo(3), hi(3) (int32
+ *               bit patterns, inclusive voxel box; lo > hi means empty)
+ *   tile_count  [n_grids][n_gauss] int32: tiles the box overlaps
+ *   box_volume  [n_grids] int64: sum of box volumes = contributing (Gaussian, voxel) pairs
+ *   tile_start  [total_tiles + 1] int32: CSR row starts of the per-tile lists
+ *   pair_gauss  [capacity_pairs] int32: Gaussian ids grouped by tile, ascending per tile
+ *   grid_grads  [n_grids][n_gauss][10] float: written by gm_backward (grid-frame partials
+ *               d amp, d c(3), d K(6))
+ *   scratch     scratch_bytes of device memory for sorting                              */
+typedef struct gm_bins {
+    int32_t n_grids;
+    int32_t reserved;
+    int64_t n_gauss;
+    int64_t capacity_pairs;
+    float* records;
+    int32_t* tile_count;
+    int64_t* box_volume;
+    int32_t* tile_start;
+    int32_t* pair_gauss;
+    float* grid_grads;
+    void* scratch;
+    size_t scratch_bytes;
+    /* [host] filled by gm_bin */
+    gm_grid grids[GM_MAX_GRIDS];
+    int64_t tile_base[GM_MAX_GRIDS + 1]; /* global tile id of each grid's first tile */
+    int64_t n_pairs;                     /* (tile, Gaussian) pairs of the last gm_bin   */
+    double cutoff_sigma;
+} gm_bins;
+
+/* Library identity. */
+int32_t gm_abi_version(void);
+/* Thread-local description of the last error; valid until the next gm_* call. */
+const char* gm_last_error(void);
+/* [host out] tile edge lengths (x, y, z) in voxels used by the binning. */
+void gm_tile_dims(int32_t out_xyz[3]);
+
+/* Sizes of the buffers a gm_bins needs for n Gaussians on the given grids with a pair
+ * capacity of capacity_pairs.  All outputs [host]; any may be NULL. */
+gm_status gm_bin_query(int64_t n, const gm_grid* grids, int32_t n_grids,
+                       int64_t capacity_pairs, size_t* records_bytes,
+                       int64_t* total_tiles, size_t* scratch_bytes);
+
+/* Spatial query (stands in for Sec. 3.3.1): per (grid, Gaussian) compute the record and
+ * the box, then list for every tile of every grid the Gaussians whose box overlaps it, in
+ * ascending Gaussian id (a stable device radix sort of (tile, Gaussian) keys).
+ * Synchronises `stream` once to read the pair total; *n_pairs [host] receives it.
+ * GM_ERR_CAPACITY if it exceeds bins->capacity_pairs (records, counts and box volumes are
+ * still valid; lists are not).  GM_ERR_NONFINITE if any parameter is non-finite, a
+ * quaternion is zero or exp(log_scale) overflows (those Gaussians get empty boxes; the
+ * rest of the binning is complete and valid).  bins->n_grids / n_gauss / capacity_pairs /
+ * buffers must be set by the caller; the host fields are filled in. */
+gm_status gm_bin(const gm_gaussians* g, const gm_grid* grids, int32_t n_grids,
+                 const gm_bin_opts* opts, gm_bins* bins, int64_t* n_pairs, gm_stream stream);
+
+/* Forward rendering (Eq. 7 with the slice profile): for each listed grid (indices into the
+ * binned grids) write out[k][v] = sum over Gaussians i whose box contains v of
+ * amp_i exp(-1/2 (v - c_i)^T C_i (v - c_i)).  outs [host] array of n_ids device pointers,
+ * each [nz][ny][nx].  Overwrites.  Bit-deterministic run to run. */
+gm_status gm_render_stacks(const gm_bins* bins, const int32_t* grid_ids, int32_t n_ids,
+                           float* const* outs, gm_stream stream);
+
+/* Neural residual field parameters for the fused volume epilogue (Eq. 8).  Weights are
+ * bf16 stored as uint16 bit patterns, row-major [out][in]; biases float32.
+ * n_freq frequency bands: input features (x, sin(2^k pi x), cos(2^k pi x)), k < n_freq,
+ * dimension 3 + 6 n_freq, zero-padded to in_pad (a multiple of 32).  depth hidden layers of
+ * width (SiLU), then a linear output; r = out_scale * tanh(output). */
+typedef struct gm_nrf {
+    int32_t n_freq, depth, width, in_pad;
+    float out_scale;
+    int32_t reserved;
+    const uint16_t* w_in;    /* [width][in_pad]              */
+    const float* b_in;       /* [width]                      */
+    const uint16_t* w_hid;   /* [depth - 1][width][width]    */
+    const float* b_hid;      /* [depth - 1][width]           */
+    const uint16_t* w_out;   /* [width]                      */
+    const float* b_out;      /* [1]                          */
+} gm_nrf;
+
+/* Inference (Sec. 3.1): render binned grid grid_id into out [nz][ny][nx]; when nrf is not
+ * NULL add the residual r(x) at each voxel's world coordinate (Eq. 8, I_final = I + r). */
+gm_status gm_render_volume(const gm_bins* bins, int32_t grid_id, const gm_nrf* nrf,
+                           float* out, gm_stream stream);
+
+/* smooth-L1 data term (Eq. 11, beta = 1) averaged over every voxel of the listed stacks:
+ * *loss (device float) = mean smoothL1(pred - target); dl_di[k][v] = clamp(pred - target,
+ * -1, 1) / N_total (overwritten).  preds/targets/dl_di: [host] arrays of device pointers;
+ * sizes [host] voxel counts.  workspace: GM_REDUCE_WORKSPACE_BYTES device bytes. */
+gm_status gm_loss_smooth_l1(int32_t n_stacks, const float* const* preds,
+                            const float* const* targets, const int64_t* sizes,
+                            float* const* dl_di, float* loss, void* workspace,
+                            gm_stream stream);
+
+/* Anisotropy regulariser (Eq. 13, reading the ratio as exp(max s - min s), the ratio of the
+ * actual scales): *value (device float) = mean_i max(0, exp(max s_i - min s_i) - lambda_r). */
+gm_status gm_aniso_reg(const gm_gaussians* g, float lambda_r, float* value, void* workspace,
+                       gm_stream stream);
+
+/* Backward of sum_k sum_v dl_di[k][v] I_k[v] (+ lambda_aniso * aniso) with respect to every
+ * Gaussian parameter, boxes held fixed (Sec. 3.5).  Recomputes each Gaussian's values
+ * instead of storing per-voxel contributions.  Writes bins->grid_grads for the listed
+ * grids, then ACCUMULATES (+=) into grad (caller zeroes it).  g must be the parameters
+ * bins was built from.  dl_di [host] array of n_ids device pointers. */
+gm_status gm_backward(const gm_gaussians* g, const gm_bins* bins, const int32_t* grid_ids,
+                      int32_t n_ids, const float* const* dl_di, float lambda_aniso,
+                      float lambda_r, gm_gaussian_grads* grad, gm_stream stream);
+
+/* Adam (Sec. 4.1.4; PyTorch arrangement, no weight decay) on n float32 elements in place:
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * p -= (lr / (1 - b1^step)) m / (sqrt(v) / sqrt(1 - b2^step) + eps).  step >= 1. */
+gm_status gm_adam_step(float* param, const float* grad, float* m, float* v, int64_t n,
+                       float lr, float beta1, float beta2, float eps, int32_t step,
+                       gm_stream stream);
+
+/* Mean squared error of vol against ref over n voxels into *mse (device float);
+ * PSNR = 10 log10(1 / mse) for intensities in [0, 1] (Sec. 4.1.3). */
+gm_status gm_mse(const float* vol, const float* ref, int64_t n, float* mse, void* workspace,
+                 gm_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GM_H */

@@ -1,0 +1,270 @@
+// K7 + K8: gradients of L = sum_k sum_v dL/dI_k[v] I_k[v] (+ lambda_aniso * L_aniso,
+// Eq. 12-13) with respect to every Gaussian parameter, boxes held fixed.
+//
+// K7 (grid-frame partials): one wavefront per Gaussian gathers dL/dI over the voxels of the
+// Gaussian's box on each listed grid, recomputing w = amp 2^Q (no per-voxel contributions
+// are stored), and forms per lane the sums
+//     d amp = sum g 2^Q,   d c = -sum g w ln2 dQ/ddelta,   d K_ab = sum g w ln2 delta_a delta_b
+// which are then reduced across the wavefront with DPP before one store per (grid,
+// Gaussian).  No global atomics are needed: each Gaussian's sums are owned by one wave.
+//
+// K8 (chain rule, FP64): thread per Gaussian.  The partials of every grid are pulled back
+// through c = L mu + t, C = Sigma_g^-1, amp = alpha sqrt(det Sigma_idx / det Sigma_g),
+// Sigma_idx = L Sigma L^T, Sigma = R diag(e^{2s}) R^T (Eq. 3), R(q/|q|) and
+// alpha = sigmoid(logit), summed over grids, and added (+=) to the gradient buffers.
+#include "gm_internal.h"
+
+namespace {
+
+__device__ __forceinline__ int sgpr(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t gid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (gid >= a.n) return;
+#pragma unroll 1
+    for (int k = 0; k < a.n_ids; ++k) {
+        const int gi = a.grid_index[k];
+        const float4* rp = reinterpret_cast<const float4*>(a.records + ((size_t)gi * a.n + gid) * 16);
+        const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2], r3 = rp[3];
+        const int lox = sgpr(__float_as_int(r2.z)), loy = sgpr(__float_as_int(r2.w));
+        const int loz = sgpr(__float_as_int(r3.x));
+        const int hix = sgpr(__float_as_int(r3.y)), hiy = sgpr(__float_as_int(r3.z));
+        const int hiz = sgpr(__float_as_int(r3.w));
+        float s[10];
+#pragma unroll
+        for (int t = 0; t < 10; ++t) s[t] = 0.0f;
+        if (lox <= hix && loy <= hiy && loz <= hiz) {
+            const int wx = hix - lox + 1, wy = hiy - loy + 1, wz = hiz - loz + 1;
+            const int wxy = wx * wy;
+            const int64_t V = (int64_t)wxy * wz;
+            const float inv_wxy = 1.0f / (float)wxy;
+            const float inv_wx = 1.0f / (float)wx;
+            const float cx = r0.x, cy = r0.y, cz = r0.z, amp = r0.w;
+            const float kxx = r1.x, kyy = r1.y, kzz = r1.z, kxy = r1.w, kxz = r2.x, kyz = r2.y;
+            const float* g = a.dl_di[k];
+            const int nx = a.nx[k], ny = a.ny[k];
+            // q = z * wxy + y * wx + x, stepped by 64 with carries
+            int x, y, z;
+            {
+                z = (int)(((float)lane + 0.5f) * inv_wxy);
+                const int rm = lane - z * wxy;
+                y = (int)(((float)rm + 0.5f) * inv_wx);
+                x = rm - y * wx;
+            }
+            const int sz = (int)((64.0f + 0.5f) * inv_wxy);
+            const int srm = 64 - sz * wxy;
+            const int sy = (int)(((float)srm + 0.5f) * inv_wx);
+            const int sx = srm - sy * wx;
+#pragma unroll 1
+            for (int64_t q = lane; q < V; q += 64) {
+                const float gv = g[((size_t)(z + loz) * ny + (y + loy)) * nx + (x + lox)];
+                const float dx = (float)x - cx, dy = (float)y - cy, dz = (float)z - cz;
+                const float tx = 2.0f * kxx * dx + kxy * dy + kxz * dz;
+                const float ty = kxy * dx + 2.0f * kyy * dy + kyz * dz;
+                const float tz = kxz * dx + kyz * dy + 2.0f * kzz * dz;
+                const float Q = 0.5f * (dx * tx + dy * ty + dz * tz);
+                const float E = __builtin_amdgcn_exp2f(Q);
+                const float ge = gv * E;
+                const float gw = ge * amp * GM_LN2F;
+                s[0] += ge;
+                s[1] -= gw * tx;
+                s[2] -= gw * ty;
+                s[3] -= gw * tz;
+                s[4] += gw * dx * dx;
+                s[5] += gw * dy * dy;
+                s[6] += gw * dz * dz;
+                s[7] += gw * dx * dy;
+                s[8] += gw * dx * dz;
+                s[9] += gw * dy * dz;
+                // advance (x, y, z) by 64 in box-linear order
+                x += sx;
+                int cxr = x >= wx;
+                x -= cxr ? wx : 0;
+                y += sy + cxr;
+                int cyr = y >= wy;
+                y -= cyr ? wy : 0;
+                z += sz + cyr;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 10; ++t) s[t] = wave_sum(s[t]);
+        if (lane == 0) {
+            float2* o = reinterpret_cast<float2*>(a.grid_grads + ((size_t)gi * a.n + gid) * 10);
+            o[0] = make_float2(s[0], s[1]);
+            o[1] = make_float2(s[2], s[3]);
+            o[2] = make_float2(s[4], s[5]);
+            o[3] = make_float2(s[6], s[7]);
+            o[4] = make_float2(s[8], s[9]);
+        }
+    }
+}
+
+// symmetric 3x3 stored full, row-major
+__device__ __forceinline__ void mm3(const double* A, const double* B, double* C)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+}
+
+__device__ __forceinline__ double inv3(const double* A, double* Ai)
+{
+    const double c00 = A[4] * A[8] - A[5] * A[7];
+    const double c01 = A[5] * A[6] - A[3] * A[8];
+    const double c02 = A[3] * A[7] - A[4] * A[6];
+    const double det = A[0] * c00 + A[1] * c01 + A[2] * c02;
+    const double id = 1.0 / det;
+    Ai[0] = c00 * id;
+    Ai[1] = (A[2] * A[7] - A[1] * A[8]) * id;
+    Ai[2] = (A[1] * A[5] - A[2] * A[4]) * id;
+    Ai[3] = c01 * id;
+    Ai[4] = (A[0] * A[8] - A[2] * A[6]) * id;
+    Ai[5] = (A[2] * A[3] - A[0] * A[5]) * id;
+    Ai[6] = c02 * id;
+    Ai[7] = (A[1] * A[6] - A[0] * A[7]) * id;
+    Ai[8] = (A[0] * A[4] - A[1] * A[3]) * id;
+    return det;
+}
+
+__global__ __launch_bounds__(128) void k_chain(const ChainArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const double qw = a.quat[4 * i], qx = a.quat[4 * i + 1], qy = a.quat[4 * i + 2],
+                 qz = a.quat[4 * i + 3];
+    const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    const double w = qw / qn, x = qx / qn, y = qy / qn, z = qz / qn;
+    double R[9];
+    R[0] = 1.0 - 2.0 * (y * y + z * z);
+    R[1] = 2.0 * (x * y - w * z);
+    R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);
+    R[4] = 1.0 - 2.0 * (x * x + z * z);
+    R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);
+    R[7] = 2.0 * (y * z + w * x);
+    R[8] = 1.0 - 2.0 * (x * x + y * y);
+    const double ls[3] = {a.log_scale[3 * i], a.log_scale[3 * i + 1], a.log_scale[3 * i + 2]};
+    const double S2[3] = {exp(2.0 * ls[0]), exp(2.0 * ls[1]), exp(2.0 * ls[2])};
+    double Sig[9];  // R diag(S2) R^T
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            Sig[3 * p + q] = R[3 * p] * S2[0] * R[3 * q] + R[3 * p + 1] * S2[1] * R[3 * q + 1] +
+                             R[3 * p + 2] * S2[2] * R[3 * q + 2];
+    const double alpha = 1.0 / (1.0 + exp(-(double)a.logit[i]));
+
+    double dmu[3] = {0, 0, 0}, GS[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, dalpha = 0.0;
+#pragma unroll 1
+    for (int k = 0; k < a.n_ids; ++k) {
+        const GridConst& G = a.g[k];
+        const int gi = a.grid_index[k];
+        const float* pg = a.grid_grads + ((size_t)gi * a.n + i) * 10;
+        const float* rc = a.records + ((size_t)gi * a.n + i) * 16;
+        const int* ri = reinterpret_cast<const int*>(rc);
+        if (ri[10] > ri[13] || ri[11] > ri[14] || ri[12] > ri[15]) continue;  // empty box
+        const double damp = pg[0];
+        const double dc[3] = {pg[1], pg[2], pg[3]};
+        // full-matrix dL/dC from the base-2 conic partials: C-entry = K-entry * KAPPA
+        const double GC[9] = {GM_KAPPA * pg[4], GM_KAPPA * pg[7], GM_KAPPA * pg[8],
+                              GM_KAPPA * pg[7], GM_KAPPA * pg[5], GM_KAPPA * pg[9],
+                              GM_KAPPA * pg[8], GM_KAPPA * pg[9], GM_KAPPA * pg[6]};
+        const double* L = G.L;
+        double T[9], SI[9];
+        mm3(L, Sig, T);
+        double Lt[9] = {L[0], L[3], L[6], L[1], L[4], L[7], L[2], L[5], L[8]};
+        mm3(T, Lt, SI);  // Sigma_idx
+        double SG[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) SG[t] = SI[t];
+        SG[8] += G.sig * G.sig;
+        double C[9], SIi[9];
+        const double detG = inv3(SG, C);
+        const double detI = inv3(SI, SIi);
+        const double amp = alpha * sqrt(detI / detG);
+        // mu
+#pragma unroll
+        for (int m = 0; m < 3; ++m) dmu[m] += L[m] * dc[0] + L[3 + m] * dc[1] + L[6 + m] * dc[2];
+        // Sigma_g then Sigma_idx
+        double CG[9], CGC[9];
+        mm3(C, GC, CG);
+        mm3(CG, C, CGC);
+        const double ha = 0.5 * damp * amp;
+        double Gi[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) Gi[t] = -CGC[t] - ha * C[t] + ha * SIi[t];
+        // Sigma = L^T Gi L
+        double U[9], V9[9];
+        mm3(Lt, Gi, U);
+        mm3(U, L, V9);
+#pragma unroll
+        for (int t = 0; t < 9; ++t) GS[t] += V9[t];
+        dalpha += damp * amp / alpha;
+    }
+    // Sigma = R diag(S2) R^T
+    double GR[9], RtGR[9], GRR[9];
+    mm3(GS, R, GR);  // G R
+    double Rt[9] = {R[0], R[3], R[6], R[1], R[4], R[7], R[2], R[5], R[8]};
+    mm3(Rt, GR, RtGR);
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) GRR[3 * p + q] = 2.0 * GR[3 * p + q] * S2[q];  // dL/dR
+    double ds[3] = {2.0 * S2[0] * RtGR[0], 2.0 * S2[1] * RtGR[4], 2.0 * S2[2] * RtGR[8]};
+    const double* g = GRR;
+    double dq[4];
+    dq[0] = 2.0 * (-z * g[1] + y * g[2] + z * g[3] - x * g[5] - y * g[6] + x * g[7]);
+    dq[1] = 2.0 * (y * g[1] + z * g[2] + y * g[3] - 2.0 * x * g[4] - w * g[5] + z * g[6] +
+                   w * g[7] - 2.0 * x * g[8]);
+    dq[2] = 2.0 * (-2.0 * y * g[0] + x * g[1] + w * g[2] + x * g[3] + z * g[5] - w * g[6] +
+                   z * g[7] - 2.0 * y * g[8]);
+    dq[3] = 2.0 * (-2.0 * z * g[0] - w * g[1] + x * g[2] + w * g[3] - 2.0 * z * g[4] + y * g[5] +
+                   x * g[6] + y * g[7]);
+    const double dot = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
+    const double qh[4] = {w, x, y, z};
+    // anisotropy regulariser (Eq. 13 on the actual scales)
+    if (a.lambda_aniso != 0.0f) {
+        int im = 0, in = 0;
+#pragma unroll
+        for (int m = 1; m < 3; ++m) {
+            if (a.log_scale[3 * i + m] > a.log_scale[3 * i + im]) im = m;
+            if (a.log_scale[3 * i + m] < a.log_scale[3 * i + in]) in = m;
+        }
+        const double ratio = exp(ls[im] - ls[in]);
+        if (ratio > (double)a.lambda_r) {
+            const double gr = (double)a.lambda_aniso * ratio / (double)a.n;
+            ds[im] += gr;
+            ds[in] -= gr;
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        a.g_mean[3 * i + m] += (float)dmu[m];
+        a.g_log_scale[3 * i + m] += (float)ds[m];
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) a.g_quat[4 * i + m] += (float)((dq[m] - qh[m] * dot) / qn);
+    a.g_logit[i] += (float)(dalpha * alpha * (1.0 - alpha));
+}
+
+}  // namespace
+
+hipError_t launch_backward_partials(const BackwardArgs& a, hipStream_t s)
+{
+    if (a.n == 0 || a.n_ids == 0) return hipSuccess;
+    const int64_t blocks = (a.n + 3) / 4;
+    hipLaunchKernelGGL(k_partials, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_chain(const ChainArgs& a, hipStream_t s)
+{
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_chain, dim3((unsigned)((a.n + 127) / 128)), dim3(128), 0, s, a);
+    return hipGetLastError();
+}

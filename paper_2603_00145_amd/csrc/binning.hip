@@ -1,0 +1,326 @@
+// K2-K5: exclusive scan of tile counts, (tile, Gaussian) key emission, stable LSD radix sort
+// of the keys, and per-tile list ranges.  Together they list, for every voxel tile of every
+// grid, the Gaussians whose box overlaps it in ascending Gaussian id (the spatial query that
+// stands in for the paper's block partition, Sec. 3.3.1).
+#include "gm_internal.h"
+
+namespace {
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_CHUNK = SCAN_THREADS * SCAN_ITEMS;
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, uint32_t v, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_copy_u32(const uint32_t* src, uint32_t* dst, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// block-wide exclusive scan of one int64 per thread; returns the block total in *total
+__device__ int64_t block_exclusive_scan(int64_t v, int64_t* total)
+{
+    __shared__ int64_t s_wave[SCAN_THREADS / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) s_wave[wave] = incl;
+    __syncthreads();
+    int64_t before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < SCAN_THREADS / 64; ++w) {
+        const int64_t x = s_wave[w];
+        if (w < wave) before += x;
+        tot += x;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + incl - v;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const int32_t* in, int64_t n,
+                                                               int64_t* part)
+{
+    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK;
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const int64_t i = base + (int64_t)k * SCAN_THREADS + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    int64_t tot;
+    block_exclusive_scan(s, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// single block: exclusive scan of the block partials in place
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_partials(int64_t* part, int64_t nb)
+{
+    int64_t carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += SCAN_THREADS) {
+        const int64_t i = b0 + threadIdx.x;
+        const int64_t v = i < nb ? part[i] : 0;
+        int64_t tot;
+        const int64_t ex = block_exclusive_scan(v, &tot);
+        if (i < nb) part[i] = carry + ex;
+        carry += tot;
+    }
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(const int32_t* in, int64_t n,
+                                                              const int64_t* part,
+                                                              int64_t* out)
+{
+    // each thread owns SCAN_ITEMS consecutive elements of the block's chunk
+    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_ITEMS;
+    int32_t v[SCAN_ITEMS];
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const int64_t i = base + k;
+        v[k] = i < n ? in[i] : 0;
+        s += v[k];
+    }
+    int64_t tot;
+    int64_t run = block_exclusive_scan(s, &tot) + part[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const int64_t i = base + k;
+        if (i < n) out[i] = run;
+        run += v[k];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_THREADS - 1) out[n] = run;
+}
+
+// Thread per (grid, Gaussian): write its overlapped tiles (z, y, x order) at its offset.
+__global__ __launch_bounds__(256) void k_emit(const EmitArgs a)
+{
+    const int64_t total = (int64_t)a.n_grids * a.n;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int cnt = a.tile_count[idx];
+    if (cnt == 0) return;
+    const int k = (int)(idx / a.n);
+    const uint32_t gid = (uint32_t)(idx - (int64_t)k * a.n);
+    const GridConst& G = a.g[k];
+    const int* rec = reinterpret_cast<const int*>(a.records + idx * 16);
+    const int lx = rec[10], ly = rec[11], lz = rec[12], hx = rec[13], hy = rec[14], hz = rec[15];
+    int64_t o = a.offsets[idx];
+    for (int tz = lz / GM_TZ; tz <= hz / GM_TZ; ++tz)
+        for (int ty = ly / GM_TY; ty <= hy / GM_TY; ++ty)
+            for (int tx = lx / GM_TX; tx <= hx / GM_TX; ++tx) {
+                a.keys[o] = (uint32_t)(G.tile_base + ((int64_t)tz * G.nty + ty) * G.ntx + tx);
+                a.vals[o] = gid;
+                ++o;
+            }
+}
+
+// ---- radix sort --------------------------------------------------------------------------
+constexpr int RS_THREADS = 256;
+constexpr int RS_WAVES = RS_THREADS / 64;
+constexpr int RS_ROUNDS = 16;
+constexpr int RS_WAVE_KEYS = 64 * RS_ROUNDS;
+constexpr int RS_BLOCK_KEYS = RS_WAVE_KEYS * RS_WAVES;
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t* keys, int64_t n,
+                                                         int shift, uint32_t mask,
+                                                         int32_t* ghist, int64_t nblocks)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_BLOCK_KEYS;
+    for (int k = threadIdx.x; k < RS_BLOCK_KEYS; k += RS_THREADS) {
+        const int64_t i = base + k;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
+    }
+    __syncthreads();
+    ghist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = (int32_t)h[threadIdx.x];
+}
+
+// Stable scatter.  Wave w of the block owns keys [base + w*1024, base + (w+1)*1024) and takes
+// them in 16 rounds of 64 consecutive keys; lanes with equal digits are matched with ballots,
+// so every key learns how many equal-digit keys precede it in the block.
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* kin,
+                                                            const uint32_t* vin, uint32_t* kout,
+                                                            uint32_t* vout, int64_t n, int shift,
+                                                            int dbits, const int64_t* goff,
+                                                            int64_t nblocks)
+{
+    __shared__ uint32_t wcnt[RS_WAVES][256];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t mask = (1u << dbits) - 1u;
+    for (int d = lane; d < 256; d += 64) wcnt[wave][d] = 0;
+    __syncthreads();
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const int64_t wbase = (int64_t)blockIdx.x * RS_BLOCK_KEYS + (int64_t)wave * RS_WAVE_KEYS;
+    uint32_t key[RS_ROUNDS], val[RS_ROUNDS], rank[RS_ROUNDS];
+#pragma unroll
+    for (int r = 0; r < RS_ROUNDS; ++r) {
+        const int64_t i = wbase + r * 64 + lane;
+        const bool ok = i < n;
+        key[r] = ok ? kin[i] : 0u;
+        val[r] = ok ? vin[i] : 0u;
+        const uint32_t dg = (key[r] >> shift) & mask;
+        uint64_t peers = __ballot(ok);
+        for (int b = 0; b < dbits; ++b) {
+            const bool bit = (dg >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t before = (uint32_t)__popcll(peers & lt);
+        uint32_t base = 0;
+        if (ok) base = wcnt[wave][dg];
+        rank[r] = base + before;
+        if (ok && before == 0) wcnt[wave][dg] = base + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    {
+        const int d = threadIdx.x;  // RS_THREADS == 256 digits
+        uint32_t run = 0;
+#pragma unroll
+        for (int w = 0; w < RS_WAVES; ++w) {
+            const uint32_t t = wcnt[w][d];
+            wcnt[w][d] = run;
+            run += t;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RS_ROUNDS; ++r) {
+        const int64_t i = wbase + r * 64 + lane;
+        if (i < n) {
+            const uint32_t dg = (key[r] >> shift) & mask;
+            const int64_t pos = goff[(int64_t)dg * nblocks + blockIdx.x] + wcnt[wave][dg] + rank[r];
+            kout[pos] = key[r];
+            vout[pos] = val[r];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* keys, int64_t n,
+                                                      int32_t* start, int64_t T)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > T) return;
+    int64_t lo = 0, hi = n;  // first index with keys[idx] >= t
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (keys[mid] < (uint32_t)t) lo = mid + 1;
+        else hi = mid;
+    }
+    start[t] = (int32_t)lo;
+}
+
+inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    unsigned nb = grid_for(n, 256);
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_fill_u32, dim3(nb), dim3(256), 0, s, p, value, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_u32(const uint32_t* src, uint32_t* dst, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    unsigned nb = grid_for(n, 256);
+    if (nb > 8192) nb = 8192;
+    hipLaunchKernelGGL(k_copy_u32, dim3(nb), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+size_t scan_workspace_bytes(int64_t n)
+{
+    return (size_t)(grid_for(n > 0 ? n : 1, SCAN_CHUNK)) * sizeof(int64_t) + 256;
+}
+
+hipError_t launch_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, void* ws,
+                                  hipStream_t s)
+{
+    if (n <= 0) {
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, reinterpret_cast<uint32_t*>(out),
+                           0u, (int64_t)2);
+        return hipGetLastError();
+    }
+    const unsigned nb = grid_for(n, SCAN_CHUNK);
+    int64_t* part = reinterpret_cast<int64_t*>(ws);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(SCAN_THREADS), 0, s, in, n, part);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, part, (int64_t)nb);
+    hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(SCAN_THREADS), 0, s, in, n, part, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(const EmitArgs& a, hipStream_t s)
+{
+    const int64_t total = (int64_t)a.n_grids * a.n;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_emit, dim3(grid_for(total, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+size_t radix_workspace_bytes(int64_t n)
+{
+    const int64_t nb = (n + RS_BLOCK_KEYS - 1) / RS_BLOCK_KEYS;
+    const int64_t hn = 256 * (nb > 0 ? nb : 1);
+    // ghist (int32), offsets (int64, hn + 1), scan partials
+    return (size_t)hn * 4 + 256 + (size_t)(hn + 1) * 8 + 256 + scan_workspace_bytes(hn) + 256;
+}
+
+hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                             uint32_t* vals_alt, int64_t n, int bits, void* ws,
+                             int* result_in_alt, hipStream_t s)
+{
+    *result_in_alt = 0;
+    if (n <= 1 || bits <= 0) return hipSuccess;
+    const int passes = (bits + 7) / 8;
+    const int dbits = (bits + passes - 1) / passes;
+    const int64_t nb = (n + RS_BLOCK_KEYS - 1) / RS_BLOCK_KEYS;
+    const int64_t hn = 256 * nb;
+    char* w = reinterpret_cast<char*>(ws);
+    int32_t* ghist = reinterpret_cast<int32_t*>(w);
+    w += ((size_t)hn * 4 + 255) / 256 * 256 + 256;
+    int64_t* goff = reinterpret_cast<int64_t*>(w);
+    w += ((size_t)(hn + 1) * 8 + 255) / 256 * 256 + 256;
+    void* sws = w;
+    uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
+    hipError_t err = hipSuccess;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = p * dbits;
+        const int db = (bits - shift) < dbits ? (bits - shift) : dbits;
+        const uint32_t mask = (1u << db) - 1u;
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(RS_THREADS), 0, s, ki, n, shift,
+                           mask, ghist, nb);
+        err = launch_scan_i32_to_i64(ghist, goff, hn, sws, s);
+        if (err != hipSuccess) return err;
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(RS_THREADS), 0, s, ki, vi, ko,
+                           vo, n, shift, db, goff, nb);
+        uint32_t* t = ki; ki = ko; ko = t;
+        t = vi; vi = vo; vo = t;
+    }
+    *result_in_alt = (passes & 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_ranges(const uint32_t* sorted_keys, int64_t n_pairs, int32_t* tile_start,
+                              int64_t total_tiles, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tile_ranges, dim3(grid_for(total_tiles + 1, 256)), dim3(256), 0, s,
+                       sorted_keys, n_pairs, tile_start, total_tiles);
+    return hipGetLastError();
+}

@@ -1,0 +1,518 @@
+// Host side of the C ABI declared in include/gm.h: argument validation, workspace layout,
+// launch configuration and status codes.  Nothing here allocates device memory.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "gm_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+gm_status fail(gm_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+gm_status fail(gm_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+gm_status hip_fail(hipError_t e, const char* where)
+{
+    return fail(GM_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define GM_HIP(call, where)                                  \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return hip_fail(e_, where);    \
+    } while (0)
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+#define REQ_PTR(p, name)                                                                   \
+    do {                                                                                   \
+        if ((p) == nullptr) return fail(GM_ERR_INVALID_ARGUMENT, "%s is NULL", name);     \
+        if (!aligned16(p)) return fail(GM_ERR_INVALID_ARGUMENT, "%s is not 16-byte aligned", name); \
+    } while (0)
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+gm_status check_grid(const gm_grid& g, int k)
+{
+    if (g.nx <= 0 || g.ny <= 0 || g.nz <= 0 || g.nx > 32768 || g.ny > 32768 || g.nz > 32768)
+        return fail(GM_ERR_INVALID_ARGUMENT, "grid %d: dims (%d, %d, %d) outside [1, 32768]", k,
+                    g.nx, g.ny, g.nz);
+    for (int i = 0; i < 12; ++i)
+        if (!isfinite(g.world_to_index[i]))
+            return fail(GM_ERR_INVALID_ARGUMENT, "grid %d: non-finite world_to_index", k);
+    if (!(g.psf_sigma_z >= 0.0) || !isfinite(g.psf_sigma_z))
+        return fail(GM_ERR_INVALID_ARGUMENT, "grid %d: psf_sigma_z must be finite and >= 0", k);
+    const double* A = g.world_to_index;
+    const double det = A[0] * (A[5] * A[10] - A[6] * A[9]) - A[1] * (A[4] * A[10] - A[6] * A[8]) +
+                       A[2] * (A[4] * A[9] - A[5] * A[8]);
+    if (!(fabs(det) > 0.0) || !isfinite(det))
+        return fail(GM_ERR_INVALID_ARGUMENT, "grid %d: world_to_index is singular", k);
+    return GM_OK;
+}
+
+GridConst make_const(const gm_grid& g, int64_t tile_base)
+{
+    GridConst c;
+    c.nx = g.nx;
+    c.ny = g.ny;
+    c.nz = g.nz;
+    c.ntx = (int32_t)cdiv(g.nx, GM_TX);
+    c.nty = (int32_t)cdiv(g.ny, GM_TY);
+    c.ntz = (int32_t)cdiv(g.nz, GM_TZ);
+    c.tile_base = tile_base;
+    for (int r = 0; r < 3; ++r) {
+        for (int j = 0; j < 3; ++j) c.L[3 * r + j] = g.world_to_index[4 * r + j];
+        c.t[r] = g.world_to_index[4 * r + 3];
+    }
+    c.sig = g.psf_sigma_z;
+    return c;
+}
+
+int64_t grid_tiles(const gm_grid& g)
+{
+    return cdiv(g.nx, GM_TX) * cdiv(g.ny, GM_TY) * cdiv(g.nz, GM_TZ);
+}
+
+// scratch layout of gm_bins
+struct BinScratch {
+    int64_t* offsets;   // [n_grids * n + 1]
+    void* scan_ws;
+    uint32_t* keys0;
+    uint32_t* keys1;
+    uint32_t* vals0;
+    void* radix_ws;
+    uint32_t* flags;
+    size_t bytes;
+};
+
+BinScratch scratch_layout(char* base, int64_t n, int32_t n_grids, int64_t cap)
+{
+    BinScratch s;
+    size_t o = 0;
+    const int64_t m = (int64_t)n_grids * n;
+    auto take = [&](size_t b) { char* p = base ? base + o : nullptr; o += align256(b); return p; };
+    s.offsets = reinterpret_cast<int64_t*>(take((size_t)(m + 1) * 8));
+    s.scan_ws = take(scan_workspace_bytes(m));
+    const int64_t c = cap > 0 ? cap : 1;
+    s.keys0 = reinterpret_cast<uint32_t*>(take((size_t)c * 4));
+    s.keys1 = reinterpret_cast<uint32_t*>(take((size_t)c * 4));
+    s.vals0 = reinterpret_cast<uint32_t*>(take((size_t)c * 4));
+    s.radix_ws = take(radix_workspace_bytes(c));
+    s.flags = reinterpret_cast<uint32_t*>(take(16));
+    s.bytes = o;
+    return s;
+}
+
+gm_status check_gauss(const gm_gaussians* g)
+{
+    if (!g) return fail(GM_ERR_INVALID_ARGUMENT, "gaussians is NULL");
+    if (g->n < 0 || g->n > 0x7fffffffLL)
+        return fail(GM_ERR_INVALID_ARGUMENT, "n = %lld outside [0, 2^31)", (long long)g->n);
+    if (g->n > 0) {
+        REQ_PTR(g->mean, "mean");
+        REQ_PTR(g->quat, "quat");
+        REQ_PTR(g->log_scale, "log_scale");
+        REQ_PTR(g->logit, "logit");
+    }
+    return GM_OK;
+}
+
+gm_status check_bins(const gm_bins* b, bool need_lists)
+{
+    if (!b) return fail(GM_ERR_INVALID_ARGUMENT, "bins is NULL");
+    if (b->n_grids < 1 || b->n_grids > GM_MAX_GRIDS)
+        return fail(GM_ERR_INVALID_ARGUMENT, "bins->n_grids = %d outside [1, %d]", b->n_grids,
+                    GM_MAX_GRIDS);
+    if (need_lists && (b->n_pairs < 0 || b->n_pairs > b->capacity_pairs))
+        return fail(GM_ERR_INVALID_ARGUMENT,
+                    "bins hold no valid tile lists (last gm_bin needed %lld pairs, capacity %lld)",
+                    (long long)b->n_pairs, (long long)b->capacity_pairs);
+    return GM_OK;
+}
+
+gm_status check_ids(const gm_bins* b, const int32_t* ids, int32_t n_ids)
+{
+    if (n_ids < 0 || n_ids > GM_MAX_GRIDS)
+        return fail(GM_ERR_INVALID_ARGUMENT, "n_ids = %d outside [0, %d]", n_ids, GM_MAX_GRIDS);
+    if (n_ids > 0 && !ids) return fail(GM_ERR_INVALID_ARGUMENT, "grid_ids is NULL");
+    for (int k = 0; k < n_ids; ++k) {
+        if (ids[k] < 0 || ids[k] >= b->n_grids)
+            return fail(GM_ERR_INVALID_ARGUMENT, "grid id %d outside [0, %d)", ids[k], b->n_grids);
+        for (int j = 0; j < k; ++j)
+            if (ids[j] == ids[k])
+                return fail(GM_ERR_INVALID_ARGUMENT, "grid id %d listed twice", ids[k]);
+    }
+    return GM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t gm_abi_version(void) { return GM_ABI_VERSION; }
+
+const char* gm_last_error(void) { return g_err.c_str(); }
+
+void gm_tile_dims(int32_t out_xyz[3])
+{
+    if (!out_xyz) return;
+    out_xyz[0] = GM_TX;
+    out_xyz[1] = GM_TY;
+    out_xyz[2] = GM_TZ;
+}
+
+gm_status gm_bin_query(int64_t n, const gm_grid* grids, int32_t n_grids, int64_t capacity_pairs,
+                       size_t* records_bytes, int64_t* total_tiles, size_t* scratch_bytes)
+{
+    g_err.clear();
+    if (n < 0 || n > 0x7fffffffLL) return fail(GM_ERR_INVALID_ARGUMENT, "n outside [0, 2^31)");
+    if (n_grids < 1 || n_grids > GM_MAX_GRIDS || !grids)
+        return fail(GM_ERR_INVALID_ARGUMENT, "n_grids must be in [1, %d] with grids != NULL",
+                    GM_MAX_GRIDS);
+    if (capacity_pairs < 0 || capacity_pairs > 0x7fffffffLL)
+        return fail(GM_ERR_INVALID_ARGUMENT, "capacity_pairs outside [0, 2^31)");
+    int64_t T = 0;
+    for (int k = 0; k < n_grids; ++k) {
+        gm_status st = check_grid(grids[k], k);
+        if (st != GM_OK) return st;
+        T += grid_tiles(grids[k]);
+    }
+    if (T >= 0x7fffffffLL) return fail(GM_ERR_INVALID_ARGUMENT, "too many tiles");
+    if (records_bytes) *records_bytes = (size_t)n_grids * (size_t)n * 16 * sizeof(float);
+    if (total_tiles) *total_tiles = T;
+    if (scratch_bytes) *scratch_bytes = scratch_layout(nullptr, n, n_grids, capacity_pairs).bytes;
+    return GM_OK;
+}
+
+gm_status gm_bin(const gm_gaussians* g, const gm_grid* grids, int32_t n_grids,
+                 const gm_bin_opts* opts, gm_bins* bins, int64_t* n_pairs, gm_stream stream)
+{
+    g_err.clear();
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    gm_status st = check_gauss(g);
+    if (st != GM_OK) return st;
+    if (!bins || !n_pairs) return fail(GM_ERR_INVALID_ARGUMENT, "bins / n_pairs is NULL");
+    int64_t T = 0;
+    size_t need_scratch = 0;
+    st = gm_bin_query(g->n, grids, n_grids, bins->capacity_pairs, nullptr, &T, &need_scratch);
+    if (st != GM_OK) return st;
+    if (bins->n_grids != n_grids || bins->n_gauss != g->n)
+        return fail(GM_ERR_INVALID_ARGUMENT, "bins sized for %d grids x %lld Gaussians, got %d x %lld",
+                    bins->n_grids, (long long)bins->n_gauss, n_grids, (long long)g->n);
+    const double cutoff = opts ? opts->cutoff_sigma : 3.0;
+    if (!(cutoff > 0.0) || !isfinite(cutoff))
+        return fail(GM_ERR_INVALID_ARGUMENT, "cutoff_sigma must be finite and > 0");
+    REQ_PTR(bins->tile_start, "bins->tile_start");
+    REQ_PTR(bins->box_volume, "bins->box_volume");
+    REQ_PTR(bins->scratch, "bins->scratch");
+    if (g->n > 0) {
+        REQ_PTR(bins->records, "bins->records");
+        REQ_PTR(bins->tile_count, "bins->tile_count");
+    }
+    if (bins->capacity_pairs > 0) REQ_PTR(bins->pair_gauss, "bins->pair_gauss");
+    if (bins->scratch_bytes < need_scratch)
+        return fail(GM_ERR_INVALID_ARGUMENT, "scratch_bytes %zu < required %zu",
+                    bins->scratch_bytes, need_scratch);
+
+    // host fields
+    int64_t base = 0;
+    PreprocessArgs pa;
+    memset(&pa, 0, sizeof pa);
+    for (int k = 0; k < n_grids; ++k) {
+        bins->grids[k] = grids[k];
+        bins->tile_base[k] = base;
+        pa.g[k] = make_const(grids[k], base);
+        base += grid_tiles(grids[k]);
+    }
+    bins->tile_base[n_grids] = base;
+    bins->cutoff_sigma = cutoff;
+    bins->n_pairs = -1;
+
+    const int64_t n = g->n;
+    const int64_t m = (int64_t)n_grids * n;
+    BinScratch sc = scratch_layout(reinterpret_cast<char*>(bins->scratch), n, n_grids,
+                                   bins->capacity_pairs);
+    GM_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(bins->box_volume), 0u, 2 * n_grids, s),
+           "zero box volumes");
+    GM_HIP(launch_fill_u32(sc.flags, 0u, 4, s), "zero flags");
+    pa.n = n;
+    pa.n_grids = n_grids;
+    pa.cutoff = cutoff;
+    pa.mean = g->mean;
+    pa.quat = g->quat;
+    pa.log_scale = g->log_scale;
+    pa.logit = g->logit;
+    pa.records = bins->records;
+    pa.tile_count = bins->tile_count;
+    pa.box_volume = reinterpret_cast<unsigned long long*>(bins->box_volume);
+    pa.flags = sc.flags;
+    GM_HIP(launch_preprocess(pa, s), "preprocess");
+    GM_HIP(launch_scan_i32_to_i64(bins->tile_count, sc.offsets, m, sc.scan_ws, s), "scan");
+
+    int64_t total = 0;
+    uint32_t flags = 0;
+    GM_HIP(hipMemcpyAsync(&total, sc.offsets + m, sizeof total, hipMemcpyDeviceToHost, s), "read total");
+    GM_HIP(hipMemcpyAsync(&flags, sc.flags, sizeof flags, hipMemcpyDeviceToHost, s), "read flags");
+    GM_HIP(hipStreamSynchronize(s), "synchronise");
+    *n_pairs = total;
+    bins->n_pairs = total;
+    if (total > bins->capacity_pairs) {
+        fail(GM_ERR_CAPACITY, "%lld (tile, Gaussian) pairs exceed capacity %lld", (long long)total,
+             (long long)bins->capacity_pairs);
+        return GM_ERR_CAPACITY;
+    }
+
+    int bits = 0;
+    while ((int64_t(1) << bits) < T) ++bits;
+    const int passes = (bits + 7) / 8;
+    uint32_t* pg = reinterpret_cast<uint32_t*>(bins->pair_gauss);
+    // arrange the ping-pong buffers so the last pass lands in pair_gauss
+    uint32_t *k_in = sc.keys0, *k_alt = sc.keys1;
+    uint32_t *v_in = (passes & 1) ? sc.vals0 : pg, *v_alt = (passes & 1) ? pg : sc.vals0;
+    if (total > 0) {
+        EmitArgs ea;
+        memset(&ea, 0, sizeof ea);
+        ea.n = n;
+        ea.n_grids = n_grids;
+        ea.records = bins->records;
+        ea.tile_count = bins->tile_count;
+        ea.offsets = sc.offsets;
+        ea.keys = k_in;
+        ea.vals = v_in;
+        for (int k = 0; k < n_grids; ++k) ea.g[k] = pa.g[k];
+        GM_HIP(launch_emit(ea, s), "emit");
+        int in_alt = 0;
+        GM_HIP(launch_radix_sort(k_in, v_in, k_alt, v_alt, total, bits, sc.radix_ws, &in_alt, s),
+               "radix sort");
+        GM_HIP(launch_tile_ranges(in_alt ? k_alt : k_in, total, bins->tile_start, T, s),
+               "tile ranges");
+    } else {
+        GM_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(bins->tile_start), 0u, T + 1, s),
+               "zero tile starts");
+    }
+    if (flags & 1u)
+        return fail(GM_ERR_NONFINITE,
+                    "non-finite parameter, zero quaternion or overflowing scale (empty boxes)");
+    return GM_OK;
+}
+
+static gm_status render_impl(const gm_bins* bins, const int32_t* ids, int32_t n_ids,
+                             float* const* outs, hipStream_t s)
+{
+    gm_status st = check_bins(bins, true);
+    if (st != GM_OK) return st;
+    st = check_ids(bins, ids, n_ids);
+    if (st != GM_OK) return st;
+    if (n_ids > 0 && !outs) return fail(GM_ERR_INVALID_ARGUMENT, "outs is NULL");
+    RenderArgs ra;
+    memset(&ra, 0, sizeof ra);
+    int64_t blocks = 0;
+    for (int k = 0; k < n_ids; ++k) {
+        REQ_PTR(outs[k], "outs[k]");
+        const gm_grid& g = bins->grids[ids[k]];
+        RenderGrid& r = ra.rg[k];
+        r.nx = g.nx;
+        r.ny = g.ny;
+        r.nz = g.nz;
+        r.ntx = (int32_t)cdiv(g.nx, GM_TX);
+        r.nty = (int32_t)cdiv(g.ny, GM_TY);
+        r.ntz = (int32_t)cdiv(g.nz, GM_TZ);
+        r.grid_index = ids[k];
+        r.first_block = (int32_t)blocks;
+        r.bin_tile_base = bins->tile_base[ids[k]];
+        r.out = outs[k];
+        blocks += grid_tiles(g);
+    }
+    if (blocks >= 0x7fffffffLL) return fail(GM_ERR_INVALID_ARGUMENT, "too many tiles");
+    if (blocks == 0) return GM_OK;
+    if (bins->n_gauss > 0) REQ_PTR(bins->records, "bins->records");
+    REQ_PTR(bins->tile_start, "bins->tile_start");
+    ra.n_render = n_ids;
+    ra.total_blocks = (int32_t)blocks;
+    ra.n_gauss = bins->n_gauss;
+    ra.records = bins->records;
+    ra.tile_start = bins->tile_start;
+    ra.pair_gauss = bins->pair_gauss;
+    GM_HIP(launch_render(ra, s), "render");
+    return GM_OK;
+}
+
+gm_status gm_render_stacks(const gm_bins* bins, const int32_t* grid_ids, int32_t n_ids,
+                           float* const* outs, gm_stream stream)
+{
+    g_err.clear();
+    return render_impl(bins, grid_ids, n_ids, outs, reinterpret_cast<hipStream_t>(stream));
+}
+
+gm_status gm_render_volume(const gm_bins* bins, int32_t grid_id, const gm_nrf* nrf, float* out,
+                           gm_stream stream)
+{
+    g_err.clear();
+    if (nrf) return fail(GM_ERR_UNSUPPORTED, "neural residual epilogue not built into this library");
+    float* outs[1] = {out};
+    return render_impl(bins, &grid_id, 1, outs, reinterpret_cast<hipStream_t>(stream));
+}
+
+gm_status gm_backward(const gm_gaussians* g, const gm_bins* bins, const int32_t* grid_ids,
+                      int32_t n_ids, const float* const* dl_di, float lambda_aniso, float lambda_r,
+                      gm_gaussian_grads* grad, gm_stream stream)
+{
+    g_err.clear();
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    gm_status st = check_gauss(g);
+    if (st != GM_OK) return st;
+    st = check_bins(bins, false);
+    if (st != GM_OK) return st;
+    st = check_ids(bins, grid_ids, n_ids);
+    if (st != GM_OK) return st;
+    if (bins->n_gauss != g->n)
+        return fail(GM_ERR_INVALID_ARGUMENT, "bins were built for %lld Gaussians, got %lld",
+                    (long long)bins->n_gauss, (long long)g->n);
+    if (!grad || grad->n != g->n) return fail(GM_ERR_INVALID_ARGUMENT, "grad missing or wrong n");
+    if (!isfinite(lambda_aniso) || !isfinite(lambda_r))
+        return fail(GM_ERR_INVALID_ARGUMENT, "non-finite lambda");
+    if (n_ids > 0 && !dl_di) return fail(GM_ERR_INVALID_ARGUMENT, "dl_di is NULL");
+    if (g->n == 0) return GM_OK;
+    REQ_PTR(grad->mean, "grad->mean");
+    REQ_PTR(grad->quat, "grad->quat");
+    REQ_PTR(grad->log_scale, "grad->log_scale");
+    REQ_PTR(grad->logit, "grad->logit");
+    REQ_PTR(bins->records, "bins->records");
+    if (n_ids > 0) REQ_PTR(bins->grid_grads, "bins->grid_grads");
+    BackwardArgs ba;
+    memset(&ba, 0, sizeof ba);
+    ChainArgs ca;
+    memset(&ca, 0, sizeof ca);
+    ba.n = g->n;
+    ba.n_ids = n_ids;
+    ba.records = bins->records;
+    ba.grid_grads = bins->grid_grads;
+    for (int k = 0; k < n_ids; ++k) {
+        REQ_PTR(dl_di[k], "dl_di[k]");
+        const gm_grid& gr = bins->grids[grid_ids[k]];
+        ba.grid_index[k] = grid_ids[k];
+        ba.nx[k] = gr.nx;
+        ba.ny[k] = gr.ny;
+        ba.nz[k] = gr.nz;
+        ba.dl_di[k] = dl_di[k];
+        ca.grid_index[k] = grid_ids[k];
+        ca.g[k] = make_const(gr, bins->tile_base[grid_ids[k]]);
+    }
+    GM_HIP(launch_backward_partials(ba, s), "backward partials");
+    ca.n = g->n;
+    ca.n_ids = n_ids;
+    ca.lambda_aniso = lambda_aniso;
+    ca.lambda_r = lambda_r;
+    ca.mean = g->mean;
+    ca.quat = g->quat;
+    ca.log_scale = g->log_scale;
+    ca.logit = g->logit;
+    ca.records = bins->records;
+    ca.grid_grads = bins->grid_grads;
+    ca.g_mean = grad->mean;
+    ca.g_quat = grad->quat;
+    ca.g_log_scale = grad->log_scale;
+    ca.g_logit = grad->logit;
+    GM_HIP(launch_chain(ca, s), "chain rule");
+    return GM_OK;
+}
+
+gm_status gm_loss_smooth_l1(int32_t n_stacks, const float* const* preds,
+                            const float* const* targets, const int64_t* sizes, float* const* dl_di,
+                            float* loss, void* workspace, gm_stream stream)
+{
+    g_err.clear();
+    if (n_stacks < 1 || n_stacks > GM_MAX_GRIDS)
+        return fail(GM_ERR_INVALID_ARGUMENT, "n_stacks outside [1, %d]", GM_MAX_GRIDS);
+    if (!preds || !targets || !sizes || !dl_di)
+        return fail(GM_ERR_INVALID_ARGUMENT, "NULL array argument");
+    REQ_PTR(loss, "loss");
+    REQ_PTR(workspace, "workspace");
+    LossArgs la;
+    memset(&la, 0, sizeof la);
+    la.n_stacks = n_stacks;
+    int64_t tot = 0;
+    for (int k = 0; k < n_stacks; ++k) {
+        if (sizes[k] < 0) return fail(GM_ERR_INVALID_ARGUMENT, "negative size");
+        if (sizes[k] > 0) {
+            REQ_PTR(preds[k], "preds[k]");
+            REQ_PTR(targets[k], "targets[k]");
+            REQ_PTR(dl_di[k], "dl_di[k]");
+        }
+        la.begin[k] = tot;
+        la.pred[k] = preds[k];
+        la.target[k] = targets[k];
+        la.dl[k] = dl_di[k];
+        tot += sizes[k];
+    }
+    la.begin[n_stacks] = tot;
+    la.total = tot;
+    GM_HIP(launch_smooth_l1(la, loss, workspace, reinterpret_cast<hipStream_t>(stream)), "smooth-L1");
+    return GM_OK;
+}
+
+gm_status gm_aniso_reg(const gm_gaussians* g, float lambda_r, float* value, void* workspace,
+                       gm_stream stream)
+{
+    g_err.clear();
+    gm_status st = check_gauss(g);
+    if (st != GM_OK) return st;
+    REQ_PTR(value, "value");
+    REQ_PTR(workspace, "workspace");
+    GM_HIP(launch_aniso(g->log_scale, g->n, lambda_r, value, workspace,
+                        reinterpret_cast<hipStream_t>(stream)), "aniso");
+    return GM_OK;
+}
+
+gm_status gm_adam_step(float* param, const float* grad, float* m, float* v, int64_t n, float lr,
+                       float beta1, float beta2, float eps, int32_t step, gm_stream stream)
+{
+    g_err.clear();
+    if (n < 0) return fail(GM_ERR_INVALID_ARGUMENT, "n < 0");
+    if (step < 1) return fail(GM_ERR_INVALID_ARGUMENT, "step must be >= 1");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f) ||
+        !isfinite(lr))
+        return fail(GM_ERR_INVALID_ARGUMENT, "bad Adam hyperparameters");
+    if (n == 0) return GM_OK;
+    REQ_PTR(param, "param");
+    REQ_PTR(grad, "grad");
+    REQ_PTR(m, "m");
+    REQ_PTR(v, "v");
+    const double bc1 = 1.0 - pow((double)beta1, (double)step);
+    const double bc2 = 1.0 - pow((double)beta2, (double)step);
+    GM_HIP(launch_adam(param, grad, m, v, n, lr, beta1, beta2, eps, (float)bc1, (float)sqrt(bc2),
+                       reinterpret_cast<hipStream_t>(stream)), "adam");
+    return GM_OK;
+}
+
+gm_status gm_mse(const float* vol, const float* ref, int64_t n, float* mse, void* workspace,
+                 gm_stream stream)
+{
+    g_err.clear();
+    if (n < 0) return fail(GM_ERR_INVALID_ARGUMENT, "n < 0");
+    if (n > 0) {
+        REQ_PTR(vol, "vol");
+        REQ_PTR(ref, "ref");
+    }
+    REQ_PTR(mse, "mse");
+    REQ_PTR(workspace, "workspace");
+    GM_HIP(launch_mse(vol, ref, n, mse, workspace, reinterpret_cast<hipStream_t>(stream)), "mse");
+    return GM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,169 @@
+// Internal declarations shared by the HIP translation units of libgm (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gm.h"
+
+// Tile of the forward render: one wavefront owns one tile and accumulates it in LDS.
+#define GM_TX 16
+#define GM_TY 16
+#define GM_TZ 4
+#define GM_TILE_VOX (GM_TX * GM_TY * GM_TZ)
+
+// -1/2 log2(e): folds the Gaussian's -1/2 and the change to base 2 into the conic.
+#define GM_KAPPA (-0.72134752044448170368)
+#define GM_LN2F 0.69314718055994530942f
+
+struct GridConst {
+    int32_t nx, ny, nz;
+    int32_t ntx, nty, ntz;   // tiles per axis
+    int64_t tile_base;       // global id of the grid's first tile
+    double L[9];             // world -> index linear part, row-major
+    double t[3];
+    double sig;              // slice-profile sigma along index z
+};
+
+// ---- launchers (one per kernel family) --------------------------------------------------
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
+
+struct PreprocessArgs {
+    int64_t n;
+    int32_t n_grids;
+    double cutoff;
+    const float* mean;
+    const float* quat;
+    const float* log_scale;
+    const float* logit;
+    float* records;          // [n_grids][n][16]
+    int32_t* tile_count;     // [n_grids][n]
+    unsigned long long* box_volume;  // [n_grids]
+    uint32_t* flags;         // bit 0: invalid parameter seen
+    GridConst g[GM_MAX_GRIDS];
+};
+hipError_t launch_preprocess(const PreprocessArgs& a, hipStream_t s);
+
+// exclusive scan of int32 counts into int64 offsets; total at out[n]
+size_t scan_workspace_bytes(int64_t n);
+hipError_t launch_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, void* ws,
+                                  hipStream_t s);
+
+struct EmitArgs {
+    int64_t n;
+    int32_t n_grids;
+    const float* records;
+    const int32_t* tile_count;
+    const int64_t* offsets;  // [n_grids * n + 1]
+    uint32_t* keys;
+    uint32_t* vals;
+    GridConst g[GM_MAX_GRIDS];
+};
+hipError_t launch_emit(const EmitArgs& a, hipStream_t s);
+
+// stable LSD radix sort of (key, value) pairs on the low `bits` key bits.
+size_t radix_workspace_bytes(int64_t n);
+hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                             uint32_t* vals_alt, int64_t n, int bits, void* ws,
+                             int* result_in_alt, hipStream_t s);
+
+hipError_t launch_tile_ranges(const uint32_t* sorted_keys, int64_t n_pairs, int32_t* tile_start,
+                              int64_t total_tiles, hipStream_t s);
+hipError_t launch_copy_u32(const uint32_t* src, uint32_t* dst, int64_t n, hipStream_t s);
+
+struct RenderGrid {
+    int32_t nx, ny, nz, ntx, nty, ntz;
+    int32_t grid_index;      // index into the binned grids (records)
+    int32_t first_block;     // first flattened tile of this grid in the launch
+    int64_t bin_tile_base;   // global tile id of the grid's first tile in the binning
+    float* out;
+};
+struct RenderArgs {
+    int32_t n_render;
+    int32_t total_blocks;
+    int64_t n_gauss;
+    const float* records;
+    const int32_t* tile_start;
+    const int32_t* pair_gauss;
+    RenderGrid rg[GM_MAX_GRIDS];
+};
+hipError_t launch_render(const RenderArgs& a, hipStream_t s);
+
+struct BackwardArgs {
+    int64_t n;
+    int32_t n_ids;
+    const float* records;
+    float* grid_grads;
+    int32_t grid_index[GM_MAX_GRIDS];
+    int32_t nx[GM_MAX_GRIDS], ny[GM_MAX_GRIDS], nz[GM_MAX_GRIDS];
+    const float* dl_di[GM_MAX_GRIDS];
+};
+hipError_t launch_backward_partials(const BackwardArgs& a, hipStream_t s);
+
+struct ChainArgs {
+    int64_t n;
+    int32_t n_ids;
+    float lambda_aniso, lambda_r;
+    const float* mean;
+    const float* quat;
+    const float* log_scale;
+    const float* logit;
+    const float* records;
+    const float* grid_grads;
+    float* g_mean;
+    float* g_quat;
+    float* g_log_scale;
+    float* g_logit;
+    int32_t grid_index[GM_MAX_GRIDS];
+    GridConst g[GM_MAX_GRIDS];
+};
+hipError_t launch_chain(const ChainArgs& a, hipStream_t s);
+
+struct LossArgs {
+    int32_t n_stacks;
+    int64_t total;
+    int64_t begin[GM_MAX_GRIDS + 1];
+    const float* pred[GM_MAX_GRIDS];
+    const float* target[GM_MAX_GRIDS];
+    float* dl[GM_MAX_GRIDS];
+};
+hipError_t launch_smooth_l1(const LossArgs& a, float* loss, void* ws, hipStream_t s);
+hipError_t launch_aniso(const float* log_scale, int64_t n, float lambda_r, float* value,
+                        void* ws, hipStream_t s);
+hipError_t launch_mse(const float* a, const float* b, int64_t n, float* mse, void* ws,
+                      hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                       float b1, float b2, float eps, float bc1, float bc2_sqrt,
+                       hipStream_t s);
+
+// ---- device helpers ---------------------------------------------------------------------
+#ifdef __HIPCC__
+// Sum of v over the 64 lanes of the wavefront, returned in every lane (DPP adds within each
+// row of 16, row broadcasts across rows, then lane 63 read back).
+__device__ __forceinline__ float wave_sum(float v)
+{
+    int xi;
+    xi = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false); // quad xor 1
+    v += __int_as_float(xi);
+    xi = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false); // quad xor 2
+    v += __int_as_float(xi);
+    xi = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false); // half mirror
+    v += __int_as_float(xi);
+    xi = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false); // mirror
+    v += __int_as_float(xi);
+    xi = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false); // bcast15
+    v += __int_as_float(xi);
+    xi = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false); // bcast31
+    v += __int_as_float(xi);
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+// Bijective blockIdx -> work-item map that gives each XCD (workgroups are dealt to the 8 XCDs
+// round robin) a contiguous range of work items, so neighbouring tiles share an L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7;
+    const int xcd = b & 7, k = b >> 3;
+    return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + k;
+}
+#endif

@@ -1,0 +1,225 @@
+"""Benchmark: Magnetic-Gaussian reconstruction iterations on one MI355X.
+
+One step = one training iteration of the plain method on the 256^3 workload: bin the 1M
+Gaussians onto the three 256x256x64 thick-slice stacks, render the stacks, smooth-L1 loss and
+its per-voxel gradient, backward to every Gaussian parameter (+ anisotropy regulariser), Adam
+on the four parameter groups.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line (see the keys below).  --gpus N with N > 1 is refused: this build runs
+on a single GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gaussian·voxel evals/s fwd+bwd; ms/iter and iters-to-PSNR at 256^3 vs plain"
+UNIT = "Gaussian·voxel evals/s"
+
+# Algorithmic work per contributing (Gaussian, voxel) pair of the forward render: 3 SUB for
+# delta, 3 MUL + 6 FMA for C delta, 1 MUL + 2 FMA for delta . C delta, 1 FMA to accumulate
+# (FMA = 2 FLOP) = 25 FLOP, plus one exp2.  Backward recompute + 10 partial sums: 52 FLOP +
+# one exp2.
+FLOP_FWD = 25
+FLOP_BWD = 52
+# VALU issue model of MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 39.3e12 lane-ops/s
+# (78.6 TFLOP/s counting an FMA as 2; packed FP32 is not used).  Instructions per pair of
+# the direct forward formula: 16 non-transcendental + one v_exp_f32 whose issue cost, in
+# FMA slots, is measured by the probe and stated in the design doc.
+LANE_OPS = 256 * 4 * 16 * 2.4e9
+FWD_VALU_INSTR = 16
+EXP_SLOTS = 4.0
+
+
+def alu_peak_tflops(flop_per_pair, instr_per_pair):
+    """FLOP/s ceiling of a kernel whose every pair costs instr_per_pair VALU issue slots."""
+    return LANE_OPS / instr_per_pair * flop_per_pair / 1e12
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c256")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-voxels", type=int, default=4096)
+    ap.add_argument("--cpu-sample-gauss", type=int, default=100000)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only (this build has no multi-GPU path); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2603_00145_amd import api, inputs
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    w = inputs.workload(args.workload, with_data=True, device=dev)
+    stacks = w.stacks
+    targets = [d.contiguous() for d in w.stack_data]
+    p = api.GaussParams.from_host(w.gauss, dev)
+    grads = api.GaussParams.zeros_like(p)
+    m = api.GaussParams.zeros_like(p)
+    v = api.GaussParams.zeros_like(p)
+    bins = api.Bins(p.n, stacks, capacity=int(12 * p.n * len(stacks)))
+    outs = [torch.empty(g.shape, dtype=torch.float32, device=dev) for g in stacks]
+    dls = [torch.empty(g.shape, dtype=torch.float32, device=dev) for g in stacks]
+    ids = list(range(len(stacks)))
+    lrs = (1e-3, 1e-3, 5e-3, 5e-2)  # mean, quat (rotation), log_scale, logit (intensity)
+    print(f"# setup {time.time() - t0:.1f}s: {p.n} Gaussians, stacks "
+          f"{[g.shape for g in stacks]}", file=sys.stderr, flush=True)
+
+    ev = {k: [] for k in ("bin", "render", "loss", "backward", "adam")}
+    step_no = [0]
+
+    def step(record):
+        s = torch.cuda.current_stream()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(6)] if record else None
+        if record:
+            e[0].record(s)
+        bins.bin(p)
+        if record:
+            e[1].record(s)
+        api.render(bins, ids, outs)
+        if record:
+            e[2].record(s)
+        loss, _ = api.smooth_l1(outs, targets, dls)
+        for t in grads.tensors():
+            t.zero_()
+        if record:
+            e[3].record(s)
+        api.backward(p, bins, ids, dls, grads, 0.1, 1.5)
+        if record:
+            e[4].record(s)
+        step_no[0] += 1
+        for prm, gr, mm, vv, lr in zip(p.tensors(), grads.tensors(), m.tensors(), v.tensors(), lrs):
+            api.adam_step(prm, gr, mm, vv, lr, step_no[0])
+        if record:
+            e[5].record(s)
+            return e, loss
+        return None, loss
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    recs = []
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(args.steps):
+        e, loss = step(True)
+        recs.append(e)
+    stop.record()
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    ms_step = total_ms / args.steps
+    for e in recs:
+        for k, (a, b) in zip(ev, zip(e[:-1], e[1:])):
+            ev[k].append(a.elapsed_time(b))
+    stage_ms = {k: float(np.mean(x)) for k, x in ev.items()}
+
+    pairs = bins.pair_count()           # contributing (Gaussian, voxel) pairs on the stacks
+    tile_pairs = bins.n_pairs
+    value = pairs / (ms_step / 1e3)
+    fwd_rate = pairs / (stage_ms["render"] / 1e3)
+    bwd_rate = pairs / (stage_ms["backward"] / 1e3)
+    # dominant kernel and its roofline
+    dom = "render" if stage_ms["render"] >= stage_ms["backward"] else "backward"
+    if dom == "render":
+        flop, instr = FLOP_FWD, FWD_VALU_INSTR + EXP_SLOTS
+        kname = "k_render"
+    else:
+        flop, instr = FLOP_BWD, 2 * FWD_VALU_INSTR + EXP_SLOTS
+        kname = "k_partials+k_chain"
+    achieved = flop * pairs / (stage_ms[dom] / 1e3) / 1e12
+    peak = alu_peak_tflops(flop, instr)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, args.cpu_sample_voxels, args.cpu_sample_gauss)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: 256^3 phantom, 3 orthogonal stacks "
+                   f"256x256x64 (slice FWHM 4 voxels, rigid offsets), {p.n} anisotropic "
+                   "Gaussians, plain method (smooth-L1 + anisotropy, Adam)",
+                   "n_gauss": p.n, "stacks": [list(g.shape) for g in stacks],
+                   "tile": list(api._lib.tile_dims())},
+        "pairs_per_step": pairs, "tile_pairs": tile_pairs,
+        "stage_ms": stage_ms, "fwd_evals_per_s": fwd_rate, "bwd_evals_per_s": bwd_rate,
+        "fwd_bwd_evals_per_s": pairs / ((stage_ms["render"] + stage_ms["backward"]) / 1e3),
+        "final_loss": float(loss),
+        "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "flop_per_pair": flop, "avg_kernel_ms": stage_ms[dom]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+def cpu_baseline(w, n_vox, n_gauss):
+    """The FP64 oracle, untuned, on a bounded sample of the same workload: forward values
+    at n_vox random stack voxels (brute force over every Gaussian) and the backward partials
+    + chain rule of n_gauss random Gaussians over their boxes on the three stacks."""
+    from oracle import gauss
+    rng = np.random.default_rng(123)
+    g = w.gauss
+    sub = np.sort(rng.choice(g.n, size=min(n_gauss, g.n), replace=False))
+    t_prep = time.time()
+    prep = gauss.prepare(g, w.stacks)
+    t_prep = time.time() - t_prep
+    # forward sample
+    t_f = 0.0
+    p_f = 0
+    per = max(1, n_vox // len(w.stacks))
+    for grid, (gt, lo, hi, ne, _) in zip(w.stacks, prep):
+        pts = np.stack([rng.integers(0, grid.nx, per), rng.integers(0, grid.ny, per),
+                        rng.integers(0, grid.nz, per)], 1)
+        t = time.time()
+        gauss.render_points(pts, gt, lo, hi, ne)
+        t_f += time.time() - t
+        inside = ((pts[:, None, :] >= lo[None]) & (pts[:, None, :] <= hi[None])).all(2) & ne[None]
+        p_f += int(inside.sum())
+    # backward sample
+    t_b = 0.0
+    p_b = 0
+    dl = [np.asarray(d.cpu().numpy() if hasattr(d, "cpu") else d, np.float64) * 1e-6
+          for d in w.stack_data]
+    mean, quat, ls, logit = gauss.params64(g.subset(sub))
+    parts = []
+    for grid, (gt, lo, hi, ne, _), d in zip(w.stacks, prep, dl):
+        gs = {k: (v[sub] if isinstance(v, np.ndarray) and v.shape[:1] == (g.n,) else v)
+              for k, v in gt.items() if k != "wt"}
+        t = time.time()
+        parts.append(gauss.grid_partials(grid, gs, lo[sub], hi[sub], ne[sub], d))
+        t_b += time.time() - t
+        p_b += int(np.where(ne[sub], np.prod(hi[sub] - lo[sub] + 1, axis=1), 0).sum())
+    t = time.time()
+    gauss.chain(mean, quat, ls, logit, w.stacks, parts)
+    t_b += time.time() - t
+    rate = 1.0 / (t_f / max(p_f, 1) + t_b / max(p_b, 1))
+    return {"value": rate, "unit": UNIT, "cores": gauss.threads(), "kind": "oracle",
+            "sample": f"forward at {per * len(w.stacks)} random stack voxels (brute force over "
+                      f"all {g.n} Gaussians: {p_f} contributing pairs, {t_f:.2f}s) + backward "
+                      f"of {len(sub)} random Gaussians over their boxes on 3 stacks "
+                      f"({p_b} pairs, {t_b:.2f}s); FP64 per-Gaussian setup {t_prep:.1f}s "
+                      "excluded"}
+
+
+if __name__ == "__main__":
+    main()

@@ -200,9 +200,11 @@ gm_status gm_backward(const gm_gaussians* g, const gm_bins* bins, const int32_t*
 
 /* Adam (Sec. 4.1.4; PyTorch arrangement, no weight decay) on n float32 elements in place:
  * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
- * p -= (lr / (1 - b1^step)) m / (sqrt(v) / sqrt(1 - b2^step) + eps).  step >= 1. */
+ * p -= (lr / (1 - b1^step)) m / (sqrt(v) / sqrt(1 - b2^step) + eps).  step >= 1.
+ * The scalars (1 - b1), (1 - b2), lr / (1 - b1^step) and sqrt(1 - b2^step) are formed in
+ * double from the double hyperparameters and rounded once to float. */
 gm_status gm_adam_step(float* param, const float* grad, float* m, float* v, int64_t n,
-                       float lr, float beta1, float beta2, float eps, int32_t step,
+                       double lr, double beta1, double beta2, double eps, int32_t step,
                        gm_stream stream);
 
 /* Mean squared error of vol against ref over n voxels into *mse (device float);

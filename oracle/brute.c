@@ -103,3 +103,16 @@ void oracle_partials(int64_t nx, int64_t ny, int64_t nz, int64_t n, const double
         for (int a = 0; a < 9; ++a) G_C[9 * i + a] = s_C[a];
     }
 }
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+/* Threads the OpenMP loops above use. */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

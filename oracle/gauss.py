@@ -49,8 +49,15 @@ def _lib():
         lib.oracle_render.restype = None
         lib.oracle_render_points.restype = None
         lib.oracle_partials.restype = None
+        lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_threads.argtypes = []
         _LIB = lib
     return _LIB
+
+
+def threads() -> int:
+    """OpenMP threads the brute-force sums run on."""
+    return int(_lib().oracle_threads())
 
 
 def _ptr(a):

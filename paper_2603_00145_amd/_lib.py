@@ -87,8 +87,9 @@ _SIGS = [
                                     ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
                                     ctypes.POINTER(P), ctypes.c_float, ctypes.c_float,
                                     ctypes.POINTER(GmGrads), P]),
-    ("gm_adam_step", ctypes.c_int, [P, P, P, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
-                                     ctypes.c_float, ctypes.c_float, ctypes.c_int32, P]),
+    ("gm_adam_step", ctypes.c_int, [P, P, P, P, ctypes.c_int64, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_int32, P]),
     ("gm_mse", ctypes.c_int, [P, P, ctypes.c_int64, P, P, P]),
 ]
 

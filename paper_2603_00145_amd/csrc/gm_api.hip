@@ -479,23 +479,24 @@ gm_status gm_aniso_reg(const gm_gaussians* g, float lambda_r, float* value, void
     return GM_OK;
 }
 
-gm_status gm_adam_step(float* param, const float* grad, float* m, float* v, int64_t n, float lr,
-                       float beta1, float beta2, float eps, int32_t step, gm_stream stream)
+gm_status gm_adam_step(float* param, const float* grad, float* m, float* v, int64_t n, double lr,
+                       double beta1, double beta2, double eps, int32_t step, gm_stream stream)
 {
     g_err.clear();
     if (n < 0) return fail(GM_ERR_INVALID_ARGUMENT, "n < 0");
     if (step < 1) return fail(GM_ERR_INVALID_ARGUMENT, "step must be >= 1");
-    if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f) ||
-        !isfinite(lr))
+    if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0) || !(eps >= 0.0) ||
+        !isfinite(lr) || !isfinite(eps))
         return fail(GM_ERR_INVALID_ARGUMENT, "bad Adam hyperparameters");
     if (n == 0) return GM_OK;
     REQ_PTR(param, "param");
     REQ_PTR(grad, "grad");
     REQ_PTR(m, "m");
     REQ_PTR(v, "v");
-    const double bc1 = 1.0 - pow((double)beta1, (double)step);
-    const double bc2 = 1.0 - pow((double)beta2, (double)step);
-    GM_HIP(launch_adam(param, grad, m, v, n, lr, beta1, beta2, eps, (float)bc1, (float)sqrt(bc2),
+    const double bc1 = 1.0 - pow(beta1, (double)step);
+    const double bc2 = 1.0 - pow(beta2, (double)step);
+    GM_HIP(launch_adam(param, grad, m, v, n, (float)beta1, (float)(1.0 - beta1), (float)beta2,
+                       (float)(1.0 - beta2), (float)eps, (float)(lr / bc1), (float)sqrt(bc2),
                        reinterpret_cast<hipStream_t>(stream)), "adam");
     return GM_OK;
 }

@@ -132,9 +132,11 @@ hipError_t launch_aniso(const float* log_scale, int64_t n, float lambda_r, float
                         void* ws, hipStream_t s);
 hipError_t launch_mse(const float* a, const float* b, int64_t n, float* mse, void* ws,
                       hipStream_t s);
-hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
-                       float b1, float b2, float eps, float bc1, float bc2_sqrt,
-                       hipStream_t s);
+// scalars formed in double on the host and rounded once: 1 - beta, lr / (1 - beta1^t),
+// sqrt(1 - beta2^t)
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float b1,
+                       float omb1, float b2, float omb2, float eps, float step_size,
+                       float bc2_sqrt, hipStream_t s);
 
 // ---- device helpers ---------------------------------------------------------------------
 #ifdef __HIPCC__

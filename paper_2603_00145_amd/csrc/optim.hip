@@ -84,14 +84,15 @@ __global__ __launch_bounds__(RED_THREADS) void k_sqdiff(const float* a, const fl
 
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
                                                float* __restrict__ m, float* __restrict__ v,
-                                               int64_t n, float lr, float b1, float b2, float eps,
-                                               float step_size, float bc2_sqrt)
+                                               int64_t n, float b1, float omb1, float b2,
+                                               float omb2, float eps, float step_size,
+                                               float bc2_sqrt)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const float gi = g[i];
-        const float mi = b1 * m[i] + (1.0f - b1) * gi;
-        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        const float mi = b1 * m[i] + omb1 * gi;
+        const float vi = b2 * v[i] + omb2 * gi * gi;
         m[i] = mi;
         v[i] = vi;
         p[i] -= step_size * mi / (sqrtf(vi) / bc2_sqrt + eps);
@@ -140,13 +141,14 @@ hipError_t launch_mse(const float* a, const float* b, int64_t n, float* mse, voi
     return hipGetLastError();
 }
 
-hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
-                       float b1, float b2, float eps, float bc1, float bc2_sqrt, hipStream_t s)
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float b1,
+                       float omb1, float b2, float omb2, float eps, float step_size,
+                       float bc2_sqrt, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     int64_t nb = (n + 255) / 256;
     if (nb > 8192) nb = 8192;
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)nb), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2,
-                       eps, lr / bc1, bc2_sqrt);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)nb), dim3(256), 0, s, p, g, m, v, n, b1, omb1, b2,
+                       omb2, eps, step_size, bc2_sqrt);
     return hipGetLastError();
 }

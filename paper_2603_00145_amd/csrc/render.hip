@@ -3,11 +3,12 @@
 // record's amplitude and conic).
 //
 // One wavefront owns one GM_TX x GM_TY x GM_TZ tile and accumulates it in LDS.  It walks
-// the tile's Gaussian list (ascending id) in batches of 64 records staged in LDS; for each
-// Gaussian the lanes take the voxels of (box intersect tile) densely, evaluate
-// amp * 2^(delta^T K delta) and add it into the tile accumulator.  Within one Gaussian every
-// lane holds a different voxel, and Gaussians are taken one after another, so each voxel's
-// sum is formed in ascending Gaussian order and the result is the same on every run.
+// the tile's Gaussian list (ascending id) in batches of 64: each lane loads one record and
+// prepares that Gaussian's piece (box intersect tile) in LDS; then, Gaussian after Gaussian,
+// the lanes take the piece's voxels densely, evaluate amp * 2^(delta^T K delta) and add it
+// into the tile accumulator.  Within one Gaussian every lane holds a different voxel, and
+// Gaussians are taken one after another, so each voxel's sum is formed in ascending
+// Gaussian order and the result is the same on every run.
 #include "gm_internal.h"
 
 namespace {
@@ -18,10 +19,26 @@ __device__ __forceinline__ float sgprf(float v)
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
+// Division by a per-Gaussian d in [1, 1024] of q in [0, 1024): floor(q / d) equals
+// (q * M) >> 20 with M = ceil(2^20 / d), because q * d < 2^20.
+__device__ __forceinline__ uint32_t magic20(uint32_t d) { return ((1u << 20) + d - 1u) / d; }
+__device__ __forceinline__ uint32_t div20(uint32_t q, uint32_t M) { return __umul24(q, M) >> 20; }
+
+// Per (Gaussian, tile) piece, prepared lane-parallel for a batch of 64 list entries:
+// centre relative to the intersection origin, amplitude, base-2 conic, intersection size,
+// magic divisors and the LDS offset of the intersection origin.
+struct Piece {
+    float ux, uy, uz, amp;
+    float kxx, kyy, kzz, kxy;
+    float kxz, kyz;
+    int wx, wxy;
+    int V, mx, mxy, base;
+};
+
 __global__ __launch_bounds__(64) void k_render(const RenderArgs a)
 {
     __shared__ float acc[GM_TILE_VOX];
-    __shared__ float4 rec[64 * 4];
+    __shared__ Piece pc[64];
     const int lane = threadIdx.x;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     int r = 0;
@@ -31,6 +48,8 @@ __global__ __launch_bounds__(64) void k_render(const RenderArgs a)
     const int lt = blk - G.first_block;
     const int tx = lt % G.ntx, ty = (lt / G.ntx) % G.nty, tz = lt / (G.ntx * G.nty);
     const int t0x = tx * GM_TX, t0y = ty * GM_TY, t0z = tz * GM_TZ;
+    const float* __restrict__ recbase = a.records + (size_t)G.grid_index * a.n_gauss * 16;
+    const int* __restrict__ pg = a.pair_gauss;
 
 #pragma unroll
     for (int i = lane; i < GM_TILE_VOX; i += 64) acc[i] = 0.0f;
@@ -38,60 +57,64 @@ __global__ __launch_bounds__(64) void k_render(const RenderArgs a)
     const int64_t bt = G.bin_tile_base + lt;
     const int s = sgpr(a.tile_start[bt]);
     const int e = sgpr(a.tile_start[bt + 1]);
-    const float* recbase = a.records + (size_t)G.grid_index * a.n_gauss * 16;
 
 #pragma unroll 1
     for (int b0 = s; b0 < e; b0 += 64) {
         const int nb = min(64, e - b0);
         __syncthreads();
         if (lane < nb) {
-            const int gid = a.pair_gauss[b0 + lane];
+            const int gid = pg[b0 + lane];
             const float4* src = reinterpret_cast<const float4*>(recbase + (size_t)gid * 16);
-            rec[lane * 4 + 0] = src[0];
-            rec[lane * 4 + 1] = src[1];
-            rec[lane * 4 + 2] = src[2];
-            rec[lane * 4 + 3] = src[3];
-        }
-        __syncthreads();
-#pragma unroll 1
-        for (int j = 0; j < nb; ++j) {
-            const float4 r0 = rec[j * 4 + 0];
-            const float4 r1 = rec[j * 4 + 1];
-            const float4 r2 = rec[j * 4 + 2];
-            const float4 r3 = rec[j * 4 + 3];
-            const int lox = sgpr(__float_as_int(r2.z)), loy = sgpr(__float_as_int(r2.w));
-            const int loz = sgpr(__float_as_int(r3.x));
-            const int hix = sgpr(__float_as_int(r3.y)), hiy = sgpr(__float_as_int(r3.z));
-            const int hiz = sgpr(__float_as_int(r3.w));
+            const float4 r0 = src[0], r1 = src[1], r2 = src[2], r3 = src[3];
+            const int lox = __float_as_int(r2.z), loy = __float_as_int(r2.w);
+            const int loz = __float_as_int(r3.x), hix = __float_as_int(r3.y);
+            const int hiy = __float_as_int(r3.z), hiz = __float_as_int(r3.w);
             const int ix0 = max(lox, t0x), iy0 = max(loy, t0y), iz0 = max(loz, t0z);
             const int wx = min(hix, t0x + GM_TX - 1) - ix0 + 1;
             const int wy = min(hiy, t0y + GM_TY - 1) - iy0 + 1;
             const int wz = min(hiz, t0z + GM_TZ - 1) - iz0 + 1;
-            if (wx <= 0 || wy <= 0 || wz <= 0) continue;  // cannot happen for a listed tile
-            const int wxy = wx * wy;
-            const int V = wxy * wz;
-            const float inv_wxy = __builtin_amdgcn_rcpf((float)wxy);
-            const float inv_wx = __builtin_amdgcn_rcpf((float)wx);
-            // offsets of the intersection from the box origin (for delta) and tile origin
-            const int bx = ix0 - lox, by = iy0 - loy, bz = iz0 - loz;
-            const int ox = ix0 - t0x, oy = iy0 - t0y, oz = iz0 - t0z;
-            const float cx = sgprf(r0.x), cy = sgprf(r0.y), cz = sgprf(r0.z);
-            const float amp = sgprf(r0.w);
-            const float kxx = sgprf(r1.x), kyy = sgprf(r1.y), kzz = sgprf(r1.z);
-            const float kxy = sgprf(r1.w), kxz = sgprf(r2.x), kyz = sgprf(r2.y);
+            const bool ok = wx > 0 && wy > 0 && wz > 0;  // always true for a listed tile
+            Piece p;
+            p.ux = r0.x - (float)(ix0 - lox);
+            p.uy = r0.y - (float)(iy0 - loy);
+            p.uz = r0.z - (float)(iz0 - loz);
+            p.amp = r0.w;
+            p.kxx = r1.x; p.kyy = r1.y; p.kzz = r1.z; p.kxy = r1.w;
+            p.kxz = r2.x; p.kyz = r2.y;
+            p.wx = ok ? wx : 1;
+            p.wxy = ok ? wx * wy : 1;
+            p.V = ok ? wx * wy * wz : 0;
+            p.mx = (int)magic20((uint32_t)p.wx);
+            p.mxy = (int)magic20((uint32_t)p.wxy);
+            p.base = ((iz0 - t0z) * GM_TY + (iy0 - t0y)) * GM_TX + (ix0 - t0x);
+            pc[lane] = p;
+        }
+        __syncthreads();
 #pragma unroll 1
-            for (int q = lane; q < V; q += 64) {
-                const int z = (int)(((float)q + 0.5f) * inv_wxy);
-                const int rm = q - z * wxy;
-                const int y = (int)(((float)rm + 0.5f) * inv_wx);
-                const int x = rm - y * wx;
-                const float dx = (float)(x + bx) - cx;
-                const float dy = (float)(y + by) - cy;
-                const float dz = (float)(z + bz) - cz;
-                const float Q = dx * (kxx * dx + kxy * dy + kxz * dz) + dy * (kyy * dy + kyz * dz) +
-                                dz * (kzz * dz);
-                const float w = amp * __builtin_amdgcn_exp2f(Q);
-                atomicAdd(&acc[((z + oz) * GM_TY + (y + oy)) * GM_TX + (x + ox)], w);
+        for (int j = 0; j < nb; ++j) {
+            const Piece p = pc[j];
+            const int V = sgpr(p.V);
+#pragma unroll 1
+            for (int q0 = 0; q0 < V; q0 += 64) {
+                const uint32_t q = (uint32_t)(q0 + lane);
+                if (q < (uint32_t)V) {
+                    const uint32_t z = div20(q, (uint32_t)p.mxy);
+                    const uint32_t rm = q - __umul24(z, (uint32_t)p.wxy);
+                    const uint32_t y = div20(rm, (uint32_t)p.mx);
+                    const uint32_t x = rm - __umul24(y, (uint32_t)p.wx);
+                    const float dx = (float)x - p.ux;
+                    const float dy = (float)y - p.uy;
+                    const float dz = (float)z - p.uz;
+                    const float Q = dx * (p.kxx * dx + p.kxy * dy + p.kxz * dz) +
+                                    dy * (p.kyy * dy + p.kyz * dz) + dz * (p.kzz * dz);
+                    const float w = p.amp * __builtin_amdgcn_exp2f(Q);
+                    // one wave owns the tile and the lanes of one Gaussian hold distinct
+                    // voxels, so a plain read-add-write is race-free (and far faster than
+                    // an LDS atomic)
+                    static_assert(GM_TX == 16 && GM_TY == 16, "index shifts assume 16x16 tiles");
+                    const int idx = p.base + (int)((z << 8) + (y << 4) + x);
+                    acc[idx] += w;
+                }
             }
         }
     }

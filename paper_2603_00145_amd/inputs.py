@@ -152,75 +152,63 @@ def _random_rotation(rng) -> np.ndarray:
 
 
 def make_phantom(n: int, n_ellipsoids: int, rng: np.random.Generator, bias: bool = False,
-                 noise: float = 0.0) -> np.ndarray:
+                 noise: float = 0.0, device="cpu"):
     """Piecewise-constant ellipsoid phantom on an n^3 cell-centred grid, values in [0, 1].
 
     Centres U[-0.6,0.6]^3, semi-axes U[0.08,0.45], uniform random orientation, intensity
     U(0.2, 1), composited by maximum over a zero background.  With ``bias`` the volume is
     multiplied by a smooth field exp(sum of degree 1..2 monomials, coefficients N(0, 0.1^2)).
+    Random draws come from ``rng``; the voxel arithmetic runs in torch on ``device``.
+    Returns a float32 torch tensor [n, n, n] on ``device``.
     """
-    coords = (-1.0 + (2.0 * np.arange(n) + 1.0) / n).astype(np.float32)
-    vol = np.zeros((n, n, n), dtype=np.float32)
+    import torch
+    dev = torch.device(device)
+    coords = (-1.0 + (2.0 * torch.arange(n, device=dev, dtype=torch.float32) + 1.0) / n)
+    vol = torch.zeros((n, n, n), dtype=torch.float32, device=dev)
+    cnp = coords.cpu().numpy()
     for _ in range(n_ellipsoids):
         c = rng.uniform(-0.6, 0.6, size=3)
         ax = rng.uniform(0.08, 0.45, size=3)
         R = _random_rotation(rng)
-        val = np.float32(rng.uniform(0.2, 1.0))
+        val = float(rng.uniform(0.2, 1.0))
         r = float(ax.max())
-        lo = np.searchsorted(coords, c - r, side="left")
-        hi = np.searchsorted(coords, c + r, side="right")
+        lo = np.searchsorted(cnp, c - r, side="left")
+        hi = np.searchsorted(cnp, c + r, side="right")
         if np.any(hi <= lo):
             continue
         zs, ys, xs = (coords[lo[2]:hi[2]], coords[lo[1]:hi[1]], coords[lo[0]:hi[0]])
-        Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
-        P = np.stack([X - c[0], Y - c[1], Z - c[2]], axis=-1) @ R  # body-frame coords
-        inside = ((P / ax) ** 2).sum(-1) <= 1.0
+        Z, Y, X = torch.meshgrid(zs, ys, xs, indexing="ij")
+        Rt = torch.tensor(R, dtype=torch.float32, device=dev)
+        P = torch.stack([X - float(c[0]), Y - float(c[1]), Z - float(c[2])], dim=-1) @ Rt
+        axt = torch.tensor(ax, dtype=torch.float32, device=dev)
+        inside = ((P / axt) ** 2).sum(-1) <= 1.0
         sub = vol[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
-        np.maximum(sub, np.where(inside, val, np.float32(0)), out=sub)
+        torch.maximum(sub, inside.to(torch.float32) * val, out=sub)
     if bias:
-        Z, Y, X = np.meshgrid(coords, coords, coords, indexing="ij")
+        Z, Y, X = torch.meshgrid(coords, coords, coords, indexing="ij")
         mons = [X, Y, Z, X * X, Y * Y, Z * Z, X * Y, X * Z, Y * Z]
         coef = rng.normal(0.0, 0.1, size=len(mons))
-        field = np.exp(sum(float(cf) * m for cf, m in zip(coef, mons)))
-        vol = np.clip(vol * field.astype(np.float32), 0.0, 1.0)
+        field = torch.exp(sum(float(cf) * m for cf, m in zip(coef, mons)))
+        vol = torch.clamp(vol * field, 0.0, 1.0)
     if noise > 0:
-        vol = vol + rng.normal(0.0, noise, size=vol.shape).astype(np.float32)
-    return vol.astype(np.float32)
+        vol = vol + torch.from_numpy(rng.normal(0.0, noise, size=vol.shape).astype(np.float32)).to(dev)
+    return vol.contiguous()
 
 
-def _trilinear(vol: np.ndarray, idx: np.ndarray) -> np.ndarray:
-    """Trilinear sample of vol[z,y,x] at float index points idx[..., (x,y,z)], zero outside."""
-    n = vol.shape[0]
-    out = np.zeros(idx.shape[:-1], dtype=np.float64)
-    base = np.floor(idx).astype(np.int64)
-    frac = idx - base
-    for dz in (0, 1):
-        for dy in (0, 1):
-            for dx in (0, 1):
-                ix = base[..., 0] + dx
-                iy = base[..., 1] + dy
-                iz = base[..., 2] + dz
-                wgt = ((frac[..., 0] if dx else 1 - frac[..., 0])
-                       * (frac[..., 1] if dy else 1 - frac[..., 1])
-                       * (frac[..., 2] if dz else 1 - frac[..., 2]))
-                ok = (ix >= 0) & (ix < n) & (iy >= 0) & (iy < n) & (iz >= 0) & (iz < n)
-                v = vol[np.clip(iz, 0, n - 1), np.clip(iy, 0, n - 1), np.clip(ix, 0, n - 1)]
-                out += np.where(ok, v * wgt, 0.0)
-    return out
-
-
-def simulate_stack(vol: np.ndarray, grid: Grid, rng: np.random.Generator, noise: float = 0.01,
-                   samples_per_slice: int = 8) -> np.ndarray:
-    """Acquire a thick-slice stack of the cell-centred volume ``vol``.
+def simulate_stack(vol, grid: Grid, rng: np.random.Generator, noise: float = 0.01,
+                   samples_per_slice: int = 8):
+    """Acquire a thick-slice stack of the cell-centred volume ``vol`` (torch [n,n,n]).
 
     Each stack voxel integrates the volume along the slice normal with the grid's Gaussian
     slice profile (supersampled ``samples_per_slice`` per slice spacing over +-3 sigma) and
-    point-samples in-plane by trilinear interpolation; then N(0, noise^2) is added.
+    point-samples in-plane by trilinear interpolation (zero outside the volume); then
+    N(0, noise^2) is added.  Runs in torch on vol's device; returns a float32 tensor
+    [nz, ny, nx] on that device.
     """
-    n = vol.shape[0]
-    vgrid = volume_grid(n)
-    Av = vgrid.world_to_index
-    Ainv = grid.index_to_world()
+    import torch
+    import torch.nn.functional as F
+    dev = vol.device
+    Ainv = torch.tensor(grid.index_to_world(), dtype=torch.float64, device=dev)
     sig = grid.psf_sigma_z
     if sig > 0:
         half = 3.0 * sig
@@ -230,20 +218,23 @@ def simulate_stack(vol: np.ndarray, grid: Grid, rng: np.random.Generator, noise:
         ws /= ws.sum()
     else:
         us, ws = np.array([0.0]), np.array([1.0])
-    out = np.zeros(grid.shape, dtype=np.float64)
-    ys, xs = np.meshgrid(np.arange(grid.ny), np.arange(grid.nx), indexing="ij")
-    for z in range(grid.nz):
-        acc = np.zeros((grid.ny, grid.nx))
-        for u, w in zip(us, ws):
-            p = np.stack([xs, ys, np.full_like(xs, z)], axis=-1).astype(np.float64)
-            p[..., 2] += u
-            world = p @ Ainv[:, :3].T + Ainv[:, 3]
-            vidx = world @ Av[:, :3].T + Av[:, 3]
-            acc += w * _trilinear(vol, vidx)
-        out[z] = acc
+    out = torch.zeros(grid.shape, dtype=torch.float64, device=dev)
+    zz, yy, xx = torch.meshgrid(torch.arange(grid.nz, device=dev, dtype=torch.float64),
+                                torch.arange(grid.ny, device=dev, dtype=torch.float64),
+                                torch.arange(grid.nx, device=dev, dtype=torch.float64),
+                                indexing="ij")
+    v5 = vol[None, None]
+    for u, w in zip(us, ws):
+        p = torch.stack([xx, yy, zz + float(u)], dim=-1)
+        world = p @ Ainv[:, :3].T + Ainv[:, 3]
+        # grid_sample with align_corners=False addresses voxel centres at -1 + (2i+1)/n,
+        # the same cell-centred convention as the world frame here
+        smp = F.grid_sample(v5, world.to(torch.float32)[None], mode="bilinear",
+                            padding_mode="zeros", align_corners=False)[0, 0]
+        out += float(w) * smp.to(torch.float64)
     if noise > 0:
-        out += rng.normal(0.0, noise, size=out.shape)
-    return out.astype(np.float32)
+        out += torch.from_numpy(rng.normal(0.0, noise, size=grid.shape)).to(dev)
+    return out.to(torch.float32).contiguous()
 
 
 # ----------------------------------------------------------------------------------------
@@ -297,8 +288,8 @@ class Workload:
     stacks: List[Grid]
     volume: Grid
     gauss: Gaussians
-    phantom: Optional[np.ndarray] = None
-    stack_data: Optional[List[np.ndarray]] = None
+    phantom: Optional[object] = None     # [n,n,n] float32 (numpy on cpu, else torch)
+    stack_data: Optional[List[object]] = None
 
 
 def orthogonal_stacks(n: int, n_slices: int, fwhm_slices: float, rng=None,
@@ -321,7 +312,8 @@ def oblique_stacks(n: int, n_slices: int, fwhm_slices: float, deg: float = 30.0)
                        _rotation_axis_angle([0, 1, 0], a), None, "oblique_y")]
 
 
-def workload(name: str, with_data: bool = True, seed: Optional[int] = None) -> Workload:
+def workload(name: str, with_data: bool = True, seed: Optional[int] = None,
+             device="cpu") -> Workload:
     """The synthetic workloads.
 
     small     : 24^3 volume, 3 stacks 24x24x6, 300 anisotropic Gaussians (fast tests)
@@ -354,8 +346,11 @@ def workload(name: str, with_data: bool = True, seed: Optional[int] = None) -> W
         g = init_anisotropic(n, cfg["ng"], r_init)
     w = Workload(name, n, stacks, vol, g)
     if with_data:
-        w.phantom = make_phantom(n, cfg["ell"], r_ph, bias=cfg["bias"])
+        w.phantom = make_phantom(n, cfg["ell"], r_ph, bias=cfg["bias"], device=device)
         w.stack_data = [simulate_stack(w.phantom, s, r_noise, 0.01) for s in stacks]
+        if str(device) == "cpu":
+            w.phantom = w.phantom.numpy()
+            w.stack_data = [d.numpy() for d in w.stack_data]
     return w
 
 

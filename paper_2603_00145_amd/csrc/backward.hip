@@ -1,12 +1,12 @@
 // K7 + K8: gradients of L = sum_k sum_v dL/dI_k[v] I_k[v] (+ lambda_aniso * L_aniso,
 // Eq. 12-13) with respect to every Gaussian parameter, boxes held fixed.
 //
-// K7 (grid-frame partials): one wavefront per Gaussian gathers dL/dI over the voxels of the
-// Gaussian's box on each listed grid, recomputing w = amp 2^Q (no per-voxel contributions
-// are stored), and forms per lane the sums
+// K7 (grid-frame partials): half a wavefront per Gaussian gathers dL/dI over the voxels of
+// the Gaussian's box on each listed grid, recomputing w = amp 2^Q (no per-voxel
+// contributions are stored), and forms per lane the sums
 //     d amp = sum g 2^Q,   d c = -sum g w ln2 dQ/ddelta,   d K_ab = sum g w ln2 delta_a delta_b
-// which are then reduced across the wavefront with DPP before one store per (grid,
-// Gaussian).  No global atomics are needed: each Gaussian's sums are owned by one wave.
+// which are then reduced across the half-wavefront with DPP before one store per (grid,
+// Gaussian).  No global atomics are needed: each Gaussian's sums are owned by 32 lanes.
 //
 // K8 (chain rule, FP64): thread per Gaussian.  The partials of every grid are pulled back
 // through c = L mu + t, C = Sigma_g^-1, amp = alpha sqrt(det Sigma_idx / det Sigma_g),
@@ -18,79 +18,116 @@ namespace {
 
 __device__ __forceinline__ int sgpr(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Sum of v over each 32-lane half of the wavefront: DPP adds within rows of 16, then row 0
+// into row 1 and row 2 into row 3.  Lane 31 ends with the first half's total, lane 63 with
+// the second's.
+__device__ __forceinline__ float half_sum(float v)
+{
+    int xi;
+    xi = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false);  // xor 1
+    v += __int_as_float(xi);
+    xi = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false);  // xor 2
+    v += __int_as_float(xi);
+    xi = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false); // half mirror
+    v += __int_as_float(xi);
+    xi = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false); // mirror
+    v += __int_as_float(xi);
+    xi = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false); // bcast15
+    v += __int_as_float(xi);
+    return v;
+}
+
+// Two Gaussians per wavefront, one per 32-lane half.  A half maps its lanes onto chunks of
+// 32 (x, y) positions of the Gaussian's box and walks the box along z; the exponent Q and
+// its gradient t = Ks delta (Ks the symmetric base-2 conic, Q = delta^T Ks delta) change by
+// constants per z step, so each voxel costs a few adds, one exp2 and the ten sums.
 __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t gid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (gid >= a.n) return;
+    const int hl = lane & 31;
+    const int64_t first = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 2;
+    if (first >= a.n) return;  // wave-uniform: both halves past the end
+    const int64_t gid = first + (lane >> 5);
+    const bool gvalid = gid < a.n;
 #pragma unroll 1
     for (int k = 0; k < a.n_ids; ++k) {
         const int gi = a.grid_index[k];
-        const float4* rp = reinterpret_cast<const float4*>(a.records + ((size_t)gi * a.n + gid) * 16);
-        const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2], r3 = rp[3];
-        const int lox = sgpr(__float_as_int(r2.z)), loy = sgpr(__float_as_int(r2.w));
-        const int loz = sgpr(__float_as_int(r3.x));
-        const int hix = sgpr(__float_as_int(r3.y)), hiy = sgpr(__float_as_int(r3.z));
-        const int hiz = sgpr(__float_as_int(r3.w));
+        float4 r0 = make_float4(0, 0, 0, 0), r1 = r0, r2 = r0, r3 = r0;
+        if (gvalid) {
+            const float4* rp = reinterpret_cast<const float4*>(a.records + ((size_t)gi * a.n + gid) * 16);
+            r0 = rp[0];
+            r1 = rp[1];
+            r2 = rp[2];
+            r3 = rp[3];
+        }
+        const int lox = __float_as_int(r2.z), loy = __float_as_int(r2.w), loz = __float_as_int(r3.x);
+        const int hix = __float_as_int(r3.y), hiy = __float_as_int(r3.z), hiz = __float_as_int(r3.w);
+        const bool nonempty = gvalid && lox <= hix && loy <= hiy && loz <= hiz;
+        const int wx = nonempty ? hix - lox + 1 : 1;
+        const int wy = nonempty ? hiy - loy + 1 : 0;
+        const int wz = nonempty ? hiz - loz + 1 : 0;
+        const int fp = wx * wy;                       // (x, y) footprint of the box
+        const int chunks = (fp + 31) >> 5;
+        const int max_chunks = max(__builtin_amdgcn_readlane(chunks, 0),
+                                   __builtin_amdgcn_readlane(chunks, 32));
+        const int max_wz = max(__builtin_amdgcn_readlane(wz, 0), __builtin_amdgcn_readlane(wz, 32));
+        const float cx = r0.x, cy = r0.y, cz = r0.z;
+        const float A2 = 2.0f * r0.w * GM_LN2F;        // d(amp 2^Q)/dQ = amp ln2 2^Q; t = dQ/2
+        const float sxx = r1.x, syy = r1.y, szz = r1.z;
+        const float sxy = 0.5f * r1.w, sxz = 0.5f * r2.x, syz = 0.5f * r2.y;
+        const float inv_wx = 1.0f / (float)wx;
+        const int nx = a.nx[k], ny = a.ny[k];
+        const int nxy = nx * ny;
+        const float* __restrict__ g = a.dl_di[k];
         float s[10];
 #pragma unroll
         for (int t = 0; t < 10; ++t) s[t] = 0.0f;
-        if (lox <= hix && loy <= hiy && loz <= hiz) {
-            const int wx = hix - lox + 1, wy = hiy - loy + 1, wz = hiz - loz + 1;
-            const int wxy = wx * wy;
-            const int64_t V = (int64_t)wxy * wz;
-            const float inv_wxy = 1.0f / (float)wxy;
-            const float inv_wx = 1.0f / (float)wx;
-            const float cx = r0.x, cy = r0.y, cz = r0.z, amp = r0.w;
-            const float kxx = r1.x, kyy = r1.y, kzz = r1.z, kxy = r1.w, kxz = r2.x, kyz = r2.y;
-            const float* g = a.dl_di[k];
-            const int nx = a.nx[k], ny = a.ny[k];
-            // q = z * wxy + y * wx + x, stepped by 64 with carries
-            int x, y, z;
-            {
-                z = (int)(((float)lane + 0.5f) * inv_wxy);
-                const int rm = lane - z * wxy;
-                y = (int)(((float)rm + 0.5f) * inv_wx);
-                x = rm - y * wx;
-            }
-            const int sz = (int)((64.0f + 0.5f) * inv_wxy);
-            const int srm = 64 - sz * wxy;
-            const int sy = (int)(((float)srm + 0.5f) * inv_wx);
-            const int sx = srm - sy * wx;
 #pragma unroll 1
-            for (int64_t q = lane; q < V; q += 64) {
-                const float gv = g[((size_t)(z + loz) * ny + (y + loy)) * nx + (x + lox)];
-                const float dx = (float)x - cx, dy = (float)y - cy, dz = (float)z - cz;
-                const float tx = 2.0f * kxx * dx + kxy * dy + kxz * dz;
-                const float ty = kxy * dx + 2.0f * kyy * dy + kyz * dz;
-                const float tz = kxz * dx + kyz * dy + 2.0f * kzz * dz;
-                const float Q = 0.5f * (dx * tx + dy * ty + dz * tz);
-                const float E = __builtin_amdgcn_exp2f(Q);
-                const float ge = gv * E;
-                const float gw = ge * amp * GM_LN2F;
-                s[0] += ge;
-                s[1] -= gw * tx;
-                s[2] -= gw * ty;
-                s[3] -= gw * tz;
-                s[4] += gw * dx * dx;
-                s[5] += gw * dy * dy;
-                s[6] += gw * dz * dz;
-                s[7] += gw * dx * dy;
-                s[8] += gw * dx * dz;
-                s[9] += gw * dy * dz;
-                // advance (x, y, z) by 64 in box-linear order
-                x += sx;
-                int cxr = x >= wx;
-                x -= cxr ? wx : 0;
-                y += sy + cxr;
-                int cyr = y >= wy;
-                y -= cyr ? wy : 0;
-                z += sz + cyr;
+        for (int c = 0; c < max_chunks; ++c) {
+            const int f = c * 32 + hl;
+            const bool act = f < fp;
+            const int y = (int)(((float)f + 0.5f) * inv_wx);
+            const int x = f - y * wx;
+            const float dx = (float)x - cx, dy = (float)y - cy;
+            float dz = -cz;
+            float tx = sxx * dx + sxy * dy + sxz * dz;
+            float ty = sxy * dx + syy * dy + syz * dz;
+            float tz = sxz * dx + syz * dy + szz * dz;
+            float Q = dx * tx + dy * ty + dz * tz;
+            int addr = (loz * ny + (loy + y)) * nx + (lox + x);  // grids hold < 2^31 voxels
+            float gnext = (act && wz > 0) ? g[addr] : 0.0f;  // loaded one z step ahead
+#pragma unroll 1
+            for (int z = 0; z < max_wz; ++z) {
+                const float gv = gnext;
+                addr += nxy;
+                if (act && z + 1 < wz) gnext = g[addr];
+                if (act && z < wz) {
+                    const float E = __builtin_amdgcn_exp2f(Q);
+                    const float ge = gv * E;
+                    const float gw = ge * A2;
+                    s[0] += ge;
+                    s[1] -= gw * tx;
+                    s[2] -= gw * ty;
+                    s[3] -= gw * tz;
+                    const float hx = 0.5f * gw * dx, hy = 0.5f * gw * dy, hz = 0.5f * gw * dz;
+                    s[4] += hx * dx;
+                    s[5] += hy * dy;
+                    s[6] += hz * dz;
+                    s[7] += hx * dy;
+                    s[8] += hx * dz;
+                    s[9] += hy * dz;
+                }
+                // step one voxel along z
+                Q += 2.0f * tz + szz;
+                tx += sxz;
+                ty += syz;
+                tz += szz;
+                dz += 1.0f;
             }
         }
 #pragma unroll
-        for (int t = 0; t < 10; ++t) s[t] = wave_sum(s[t]);
-        if (lane == 0) {
+        for (int t = 0; t < 10; ++t) s[t] = half_sum(s[t]);
+        if (hl == 31 && gvalid) {
             float2* o = reinterpret_cast<float2*>(a.grid_grads + ((size_t)gi * a.n + gid) * 10);
             o[0] = make_float2(s[0], s[1]);
             o[1] = make_float2(s[2], s[3]);
@@ -257,7 +294,7 @@ __global__ __launch_bounds__(128) void k_chain(const ChainArgs a)
 hipError_t launch_backward_partials(const BackwardArgs& a, hipStream_t s)
 {
     if (a.n == 0 || a.n_ids == 0) return hipSuccess;
-    const int64_t blocks = (a.n + 3) / 4;
+    const int64_t blocks = (a.n + 7) / 8;  // 4 wavefronts x 2 Gaussians per block
     hipLaunchKernelGGL(k_partials, dim3((unsigned)blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }

@@ -52,6 +52,8 @@ gm_status check_grid(const gm_grid& g, int k)
     if (g.nx <= 0 || g.ny <= 0 || g.nz <= 0 || g.nx > 32768 || g.ny > 32768 || g.nz > 32768)
         return fail(GM_ERR_INVALID_ARGUMENT, "grid %d: dims (%d, %d, %d) outside [1, 32768]", k,
                     g.nx, g.ny, g.nz);
+    if ((int64_t)g.nx * g.ny * g.nz >= 0x7fffffffLL)
+        return fail(GM_ERR_INVALID_ARGUMENT, "grid %d: more than 2^31 - 1 voxels", k);
     for (int i = 0; i < 12; ++i)
         if (!isfinite(g.world_to_index[i]))
             return fail(GM_ERR_INVALID_ARGUMENT, "grid %d: non-finite world_to_index", k);

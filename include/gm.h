@@ -207,6 +207,18 @@ gm_status gm_adam_step(float* param, const float* grad, float* m, float* v, int6
                        double lr, double beta1, double beta2, double eps, int32_t step,
                        gm_stream stream);
 
+/* Devoxelization initialisation (Sec. 3.1; Fig. 1b): fill n = g^3 Gaussians (g >= 1) laid on
+ * the cell centres of a uniform g^3 grid over [-1,1]^3 (Gaussian i = (iz g + iy) g + ix), with
+ * identity rotation, isotropic log-scale ln(h/2) (h = 2/g) and intensity
+ * alpha = clip(mean over the stacks containing the centre of the stack sampled trilinearly at
+ * the centre, times 8 / (2 pi)^{3/2}, 1e-3, 1 - 1e-3) (the factor makes the lattice of
+ * Gaussians sum back to the sampled intensity); logit = log(alpha / (1 - alpha)).
+ * stacks [host] n_stacks descriptors; stack_data [host] array of device pointers [nz][ny][nx].
+ * Outputs: mean [n][3], quat [n][4], log_scale [n][3], logit [n] (overwritten). */
+gm_status gm_devox_init(int32_t g, const gm_grid* stacks, int32_t n_stacks,
+                        const float* const* stack_data, float* mean, float* quat,
+                        float* log_scale, float* logit, gm_stream stream);
+
 /* Mean squared error of vol against ref over n voxels into *mse (device float);
  * PSNR = 10 log10(1 / mse) for intensities in [0, 1] (Sec. 4.1.3). */
 gm_status gm_mse(const float* vol, const float* ref, int64_t n, float* mse, void* workspace,

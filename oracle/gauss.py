@@ -328,3 +328,54 @@ def gradients(g, grids, dl_dis, cutoff=3.0, lam_aniso=0.0, lam_r=1.5):
     if lam_aniso:
         d_s = d_s + lam_aniso * aniso(g.log_scale, lam_r)[1]
     return d_mu, d_q, d_s, d_a
+
+
+# ----------------------------------------------------------------------------------------
+# devoxelization initialisation (Sec. 3.1, Fig. 1b)
+# ----------------------------------------------------------------------------------------
+
+def _trilinear_index(vol, p):
+    """Trilinear value of vol[z,y,x] at index point p = (x, y, z) inside [0, n-1]^3."""
+    nz, ny, nx = vol.shape
+    x0 = min(int(np.floor(p[0])), max(nx - 2, 0))
+    y0 = min(int(np.floor(p[1])), max(ny - 2, 0))
+    z0 = min(int(np.floor(p[2])), max(nz - 2, 0))
+    x1, y1, z1 = min(x0 + 1, nx - 1), min(y0 + 1, ny - 1), min(z0 + 1, nz - 1)
+    fx, fy, fz = p[0] - x0, p[1] - y0, p[2] - z0
+    v = np.asarray(vol, np.float64)
+    c = 0.0
+    for zz, wz in ((z0, 1 - fz), (z1, fz)):
+        for yy, wy in ((y0, 1 - fy), (y1, fy)):
+            for xx, wx in ((x0, 1 - fx), (x1, fx)):
+                c += wz * wy * wx * v[zz, yy, xx]
+    return c
+
+
+def devox_init(g, stacks, stack_data):
+    """g^3 Gaussians at the cell centres of [-1,1]^3, identity rotation, sigma = h/2, and
+    alpha = clip(mean over the stacks whose index domain contains the centre of the stack
+    sampled trilinearly there, times h^3 / ((2 pi)^{3/2} sigma^3), 1e-3, 1 - 1e-3).
+    Returns (mean, quat, log_scale, logit) in float64."""
+    h = 2.0 / g
+    sigma = h / 2
+    pu = h ** 3 / ((2 * np.pi) ** 1.5 * sigma ** 3)
+    n = g ** 3
+    mean = np.zeros((n, 3))
+    logit = np.zeros(n)
+    for i in range(n):
+        ix, iy, iz = i % g, (i // g) % g, i // (g * g)
+        x = np.array([-1 + (2 * ix + 1) / g, -1 + (2 * iy + 1) / g, -1 + (2 * iz + 1) / g])
+        mean[i] = x
+        vals = []
+        for grid, data in zip(stacks, stack_data):
+            A = np.asarray(grid.world_to_index, np.float64)
+            p = A[:, :3] @ x + A[:, 3]
+            if np.all(p >= 0) and p[0] <= grid.nx - 1 and p[1] <= grid.ny - 1 and p[2] <= grid.nz - 1:
+                vals.append(_trilinear_index(data, p))
+        v = np.mean(vals) if vals else 0.0
+        a = min(max(v * pu, 1e-3), 1 - 1e-3)
+        logit[i] = np.log(a / (1 - a))
+    quat = np.zeros((n, 4))
+    quat[:, 0] = 1
+    log_scale = np.full((n, 3), np.log(sigma))
+    return mean, quat, log_scale, logit

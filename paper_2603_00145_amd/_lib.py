@@ -91,6 +91,8 @@ _SIGS = [
                                      ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_int32, P]),
     ("gm_mse", ctypes.c_int, [P, P, ctypes.c_int64, P, P, P]),
+    ("gm_devox_init", ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(GmGrid), ctypes.c_int32,
+                                      ctypes.POINTER(P), P, P, P, P, P]),
 ]
 
 EXPORTED = [s[0] for s in _SIGS]

@@ -155,6 +155,11 @@ class Bins:
         self.n_pairs = int(npairs.value)
         return self.n_pairs
 
+    @property
+    def tile_base_host(self):
+        """Global id of each grid's first tile (filled by gm_bin)."""
+        return [int(self._s.tile_base[k]) for k in range(len(self.grids) + 1)]
+
     # -- views for tests -------------------------------------------------------------------
     def boxes(self, k: int):
         r = self.records[k, :self.n].view(torch.int32)
@@ -240,3 +245,17 @@ def mse(vol: torch.Tensor, ref: torch.Tensor):
     out = torch.empty(4, dtype=torch.float32, device=vol.device)
     check(load().gm_mse(_p(vol), _p(ref), vol.numel(), _p(out), _p(workspace()), _stream()))
     return out[0]
+
+
+def devox_init(g: int, stacks, stack_data: Sequence[torch.Tensor]) -> GaussParams:
+    """gm_devox_init: g^3 Gaussians on a uniform grid initialised from the stacks."""
+    n = g ** 3
+    dev = stack_data[0].device
+    for t in stack_data:
+        _need(t, torch.float32, "stack data")
+    p = GaussParams(torch.empty((n, 3), device=dev), torch.empty((n, 4), device=dev),
+                    torch.empty((n, 3), device=dev), torch.empty((n,), device=dev))
+    cg = (_lib.GmGrid * len(stacks))(*[_lib.grid_struct(s) for s in stacks])
+    check(load().gm_devox_init(int(g), cg, len(stacks), ptr_array([t.data_ptr() for t in stack_data]),
+                               _p(p.mean), _p(p.quat), _p(p.log_scale), _p(p.logit), _stream()))
+    return p

@@ -503,6 +503,37 @@ gm_status gm_adam_step(float* param, const float* grad, float* m, float* v, int6
     return GM_OK;
 }
 
+gm_status gm_devox_init(int32_t g, const gm_grid* stacks, int32_t n_stacks,
+                        const float* const* stack_data, float* mean, float* quat,
+                        float* log_scale, float* logit, gm_stream stream)
+{
+    g_err.clear();
+    if (g < 1 || g > 1290) return fail(GM_ERR_INVALID_ARGUMENT, "g outside [1, 1290]");
+    if (n_stacks < 1 || n_stacks > GM_MAX_GRIDS || !stacks || !stack_data)
+        return fail(GM_ERR_INVALID_ARGUMENT, "n_stacks outside [1, %d] or NULL arrays", GM_MAX_GRIDS);
+    REQ_PTR(mean, "mean");
+    REQ_PTR(quat, "quat");
+    REQ_PTR(log_scale, "log_scale");
+    REQ_PTR(logit, "logit");
+    DevoxArgs da;
+    memset(&da, 0, sizeof da);
+    da.g = g;
+    da.n_stacks = n_stacks;
+    for (int k = 0; k < n_stacks; ++k) {
+        gm_status st = check_grid(stacks[k], k);
+        if (st != GM_OK) return st;
+        REQ_PTR(stack_data[k], "stack_data[k]");
+        da.s[k] = make_const(stacks[k], 0);
+        da.data[k] = stack_data[k];
+    }
+    da.mean = mean;
+    da.quat = quat;
+    da.log_scale = log_scale;
+    da.logit = logit;
+    GM_HIP(launch_devox(da, reinterpret_cast<hipStream_t>(stream)), "devox init");
+    return GM_OK;
+}
+
 gm_status gm_mse(const float* vol, const float* ref, int64_t n, float* mse, void* workspace,
                  gm_stream stream)
 {

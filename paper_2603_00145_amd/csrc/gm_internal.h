@@ -138,6 +138,18 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
                        float omb1, float b2, float omb2, float eps, float step_size,
                        float bc2_sqrt, hipStream_t s);
 
+struct DevoxArgs {
+    int32_t g;
+    int32_t n_stacks;
+    const float* data[GM_MAX_GRIDS];
+    GridConst s[GM_MAX_GRIDS];
+    float* mean;
+    float* quat;
+    float* log_scale;
+    float* logit;
+};
+hipError_t launch_devox(const DevoxArgs& a, hipStream_t s);
+
 // ---- device helpers ---------------------------------------------------------------------
 #ifdef __HIPCC__
 // Sum of v over the 64 lanes of the wavefront, returned in every lane (DPP adds within each

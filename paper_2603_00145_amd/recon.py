@@ -1,0 +1,118 @@
+"""Reconstruction driver: the paper's training loop (Sec. 3.5; settings of Sec. 4.1.4) run on
+the HIP path.  Each iteration bins the Gaussians onto the stacks, renders them, forms the
+smooth-L1 data term and its per-voxel gradient, backpropagates to every Gaussian parameter
+(with the anisotropy regulariser), and takes one Adam step per parameter group.  Optionally a
+neural residual field (Sec. 3.4) is switched on part-way through (delayed activation).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import api
+
+
+@dataclasses.dataclass
+class TrainConfig:
+    n_iter: int = 200
+    lr_mean: float = 1e-3        # position
+    lr_quat: float = 1e-3        # rotation
+    lr_scale: float = 5e-3       # scale
+    lr_logit: float = 5e-2       # intensity
+    lambda_aniso: float = 0.1
+    lambda_r: float = 1.5
+    psnr_every: int = 10
+    nrf: Optional[object] = None  # an nrf.NRF to train jointly (None = Gaussians only)
+    nrf_start: float = 0.5        # fraction of n_iter after which the NRF is active
+    lr_nrf: float = 1e-4
+
+
+class Reconstruction:
+    """State of one reconstruction: parameters, Adam moments, bins and buffers."""
+
+    def __init__(self, stacks: Sequence, targets: Sequence[torch.Tensor], params: api.GaussParams,
+                 cfg: TrainConfig = TrainConfig(), volume_grid=None,
+                 phantom: Optional[torch.Tensor] = None):
+        self.cfg = cfg
+        self.stacks = list(stacks)
+        self.targets = [t.contiguous() for t in targets]
+        self.p = params
+        self.g = api.GaussParams.zeros_like(params)
+        self.m = api.GaussParams.zeros_like(params)
+        self.v = api.GaussParams.zeros_like(params)
+        dev = params.mean.device
+        self.bins = api.Bins(params.n, self.stacks, capacity=int(10 * params.n * len(self.stacks)) + 4096)
+        self.ids = list(range(len(self.stacks)))
+        self.outs = [torch.empty(s.shape, dtype=torch.float32, device=dev) for s in self.stacks]
+        self.dls = [torch.empty(s.shape, dtype=torch.float32, device=dev) for s in self.stacks]
+        self.volume_grid = volume_grid
+        self.phantom = phantom
+        self.vbins = api.Bins(params.n, [volume_grid], capacity=int(12 * params.n) + 4096) \
+            if volume_grid is not None else None
+        self.it = 0
+        self.nrf_on = False
+
+    def lrs(self):
+        c = self.cfg
+        return (c.lr_mean, c.lr_quat, c.lr_scale, c.lr_logit)
+
+    def step(self) -> torch.Tensor:
+        c = self.cfg
+        self.it += 1
+        if c.nrf is not None and not self.nrf_on and self.it > int(c.nrf_start * c.n_iter):
+            self.nrf_on = True
+        self.bins.bin(self.p)
+        api.render(self.bins, self.ids, self.outs)
+        if self.nrf_on:
+            for k, s in enumerate(self.stacks):
+                c.nrf.forward_add(s, self.outs[k])
+        loss, _ = api.smooth_l1(self.outs, self.targets, self.dls)
+        for t in self.g.tensors():
+            t.zero_()
+        api.backward(self.p, self.bins, self.ids, self.dls, self.g, c.lambda_aniso, c.lambda_r)
+        if self.nrf_on:
+            c.nrf.zero_grad()
+            for k, s in enumerate(self.stacks):
+                c.nrf.backward(s, self.dls[k])
+            c.nrf.adam_step(c.lr_nrf)
+        for prm, gr, mm, vv, lr in zip(self.p.tensors(), self.g.tensors(), self.m.tensors(),
+                                       self.v.tensors(), self.lrs()):
+            api.adam_step(prm, gr, mm, vv, lr, self.it)
+        return loss
+
+    def render_volume(self) -> torch.Tensor:
+        self.vbins.bin(self.p)
+        vol = api.render_volume(self.vbins, 0)
+        if self.nrf_on:
+            self.cfg.nrf.forward_add(self.volume_grid, vol)
+        return vol
+
+    def psnr(self) -> float:
+        vol = self.render_volume()
+        mse = float(api.mse(vol, self.phantom))
+        return float("inf") if mse == 0 else 10.0 * math.log10(1.0 / mse)
+
+    def run(self, n_iter: Optional[int] = None, log=None) -> List[dict]:
+        n_iter = self.cfg.n_iter if n_iter is None else n_iter
+        hist = []
+        if self.phantom is not None:
+            hist.append({"it": self.it, "loss": None, "psnr": self.psnr()})
+        for _ in range(n_iter):
+            loss = self.step()
+            if self.phantom is not None and (self.it % self.cfg.psnr_every == 0):
+                rec = {"it": self.it, "loss": float(loss), "psnr": self.psnr()}
+                hist.append(rec)
+                if log:
+                    log(rec)
+        return hist
+
+
+def iters_to_psnr(hist: List[dict], target: float) -> Optional[int]:
+    """First logged iteration whose PSNR reaches target (None if never)."""
+    for rec in hist:
+        if rec["psnr"] is not None and rec["psnr"] >= target:
+            return rec["it"]
+    return None

@@ -269,3 +269,23 @@ def test_tile_lists_against_brute_force_tile_enumeration():
     assert list(zip(tiles.tolist(), gids.tolist())) == ref
     counts = recipe.tile_counts(lo, hi, ne, tile)
     assert counts.sum() == len(ref)
+
+
+def test_devox_constant_stacks_partition_of_unity():
+    """Constant stacks of value v: interior Gaussians get alpha = v 8/(2 pi)^{3/2}, and the
+    rendered lattice of Gaussians reproduces v on average over whole lattice periods (Poisson
+    summation: the lattice sum of sigma = h/2 Gaussians is (2 pi)^{3/2} sigma^3 / h^3 times
+    1 + a ripple of period h whose mean over a period vanishes)."""
+    n, g = 24, 8
+    stacks = inputs.orthogonal_stacks(n, 6, 1.0)
+    data = [np.full(s.shape, 0.7, np.float32) for s in stacks]
+    mean, quat, ls, logit = gauss.devox_init(g, stacks, data)
+    alpha = 1 / (1 + np.exp(-logit))
+    inner = (np.abs(mean) < 0.7).all(1)
+    assert np.allclose(alpha[inner], 0.7 * 8 / (2 * math.pi) ** 1.5, rtol=1e-12)
+    gs = inputs.Gaussians(mean.astype(np.float32), quat.astype(np.float32),
+                          ls.astype(np.float32), logit.astype(np.float32))
+    vol = gauss.render_all(gs, [inputs.volume_grid(n)], cutoff=8.0)[0]
+    core = vol[6:18, 6:18, 6:18]            # 12 voxels = 4 lattice periods (h = 3 voxels)
+    assert core.mean() == pytest.approx(0.7, rel=2e-6)   # float32-stored alpha and sigma
+    assert 0.02 < (core.max() - core.min()) / 0.7 < 0.1    # the ripple is there

@@ -156,7 +156,7 @@ gm_status gm_render_stacks(const gm_bins* bins, const int32_t* grid_ids, int32_t
 /* Neural residual field parameters for the fused volume epilogue (Eq. 8).  Weights are
  * bf16 stored as uint16 bit patterns, row-major [out][in]; biases float32.
  * n_freq frequency bands: input features (x, sin(2^k pi x), cos(2^k pi x)), k < n_freq,
- * dimension 3 + 6 n_freq, zero-padded to in_pad (a multiple of 32).  depth hidden layers of
+ * dimension 3 + 6 n_freq, zero-padded to in_pad (64 or 128).  depth hidden layers of
  * width (SiLU), then a linear output; r = out_scale * tanh(output). */
 typedef struct gm_nrf {
     int32_t n_freq, depth, width, in_pad;
@@ -174,6 +174,45 @@ typedef struct gm_nrf {
  * NULL add the residual r(x) at each voxel's world coordinate (Eq. 8, I_final = I + r). */
 gm_status gm_render_volume(const gm_bins* bins, int32_t grid_id, const gm_nrf* nrf,
                            float* out, gm_stream stream);
+
+/* [host out] The index->world affine (row-major 3x4, binary64) of a grid: the inverse of its
+ * world_to_index.  The residual field encodes the world coordinate of voxel v as, per row a,
+ * float32(((M[a][0] vx + M[a][1] vy) + M[a][2] vz) + M[a][3]) evaluated in binary64 without
+ * contraction. */
+gm_status gm_index_to_world(const gm_grid* grid, double out[12]);
+
+/* Neural residual field forward (Sec. 3.4, Eq. 8) on every voxel of grid: out[v] += r(x_v).
+ * Requires width 64, 1 <= depth <= 4, in_pad 64 or 128 with 3 + 6 n_freq <= in_pad.  MFMA BF16 x BF16 -> FP32 for the layers; encoding, bias, SiLU, the output layer
+ * and tanh in FP32. */
+gm_status gm_nrf_forward(const gm_nrf* nrf, const gm_grid* grid, float* out, gm_stream stream);
+
+/* Weight gradients (FP32) of the field, accumulated (+=); same shapes as gm_nrf's weights. */
+typedef struct gm_nrf_grads {
+    float* w_in;   /* [width][in_pad]           */
+    float* b_in;   /* [width]                   */
+    float* w_hid;  /* [depth - 1][width][width] */
+    float* b_hid;  /* [depth - 1][width]        */
+    float* w_out;  /* [width]                   */
+    float* b_out;  /* [1]                       */
+} gm_nrf_grads;
+
+/* [host out] device workspace bytes gm_nrf_backward needs for n_points points. */
+gm_status gm_nrf_workspace(const gm_nrf* nrf, int64_t n_points, size_t* bytes);
+
+/* Backward of scale * sum_{k < n_points} dl_dr[v_k] r(x_{v_k}) over the voxels v_k = idx[k]
+ * (linear indices into grid; idx NULL = every voxel in order) with respect to every weight
+ * and bias of the field; accumulates into grads.  dl_dr is grid-sized [nz][ny][nx].  With a
+ * random subset of n voxels and scale = (grid voxels) / n this is an unbiased estimate of the
+ * full gradient (the paper trains on sampled points).  Recomputes the forward, writes the
+ * per-layer dZ and activations in BF16 to the workspace, forms dA = W^T dZ and
+ * dW = dZ A^T on MFMA (split over points, partial sums added in fixed order). */
+gm_status gm_nrf_backward(const gm_nrf* nrf, const gm_grid* grid, const int32_t* idx,
+                          int64_t n_points, const float* dl_dr, float scale,
+                          gm_nrf_grads* grads, void* workspace, size_t workspace_bytes,
+                          gm_stream stream);
+
+/* out[i] = bfloat16(in[i]) (round to nearest even), as uint16 bit patterns. */
+gm_status gm_f32_to_bf16(const float* in, uint16_t* out, int64_t n, gm_stream stream);
 
 /* smooth-L1 data term (Eq. 11, beta = 1) averaged over every voxel of the listed stacks:
  * *loss (device float) = mean smoothL1(pred - target); dl_di[k][v] = clamp(pred - target,

@@ -56,6 +56,10 @@ class GmBins(ctypes.Structure):
                 ("n_pairs", ctypes.c_int64), ("cutoff_sigma", ctypes.c_double)]
 
 
+class GmNrfGrads(ctypes.Structure):
+    _fields_ = [("w_in", P), ("b_in", P), ("w_hid", P), ("b_hid", P), ("w_out", P), ("b_out", P)]
+
+
 class GmNrf(ctypes.Structure):
     _fields_ = [("n_freq", ctypes.c_int32), ("depth", ctypes.c_int32), ("width", ctypes.c_int32),
                 ("in_pad", ctypes.c_int32), ("out_scale", ctypes.c_float),
@@ -91,6 +95,14 @@ _SIGS = [
                                      ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_int32, P]),
     ("gm_mse", ctypes.c_int, [P, P, ctypes.c_int64, P, P, P]),
+    ("gm_index_to_world", ctypes.c_int, [ctypes.POINTER(GmGrid), ctypes.POINTER(ctypes.c_double)]),
+    ("gm_nrf_forward", ctypes.c_int, [ctypes.POINTER(GmNrf), ctypes.POINTER(GmGrid), P, P]),
+    ("gm_nrf_workspace", ctypes.c_int, [ctypes.POINTER(GmNrf), ctypes.c_int64,
+                                         ctypes.POINTER(ctypes.c_size_t)]),
+    ("gm_nrf_backward", ctypes.c_int, [ctypes.POINTER(GmNrf), ctypes.POINTER(GmGrid), P,
+                                        ctypes.c_int64, P, ctypes.c_float,
+                                        ctypes.POINTER(GmNrfGrads), P, ctypes.c_size_t, P]),
+    ("gm_f32_to_bf16", ctypes.c_int, [P, P, ctypes.c_int64, P]),
     ("gm_devox_init", ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(GmGrid), ctypes.c_int32,
                                       ctypes.POINTER(P), P, P, P, P, P]),
 ]
@@ -145,3 +157,11 @@ def tile_dims():
     out = (ctypes.c_int32 * 3)()
     load().gm_tile_dims(out)
     return tuple(out)
+
+
+def index_to_world(g):
+    """The library's index->world affine (3x4 float64) of a grid descriptor."""
+    import numpy as np
+    out = (ctypes.c_double * 12)()
+    check(load().gm_index_to_world(ctypes.byref(grid_struct(g)), out))
+    return np.array(list(out)).reshape(3, 4)

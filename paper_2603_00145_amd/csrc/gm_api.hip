@@ -162,6 +162,85 @@ gm_status check_ids(const gm_bins* b, const int32_t* ids, int32_t n_ids)
     return GM_OK;
 }
 
+bool index_to_world(const gm_grid& g, double* M)
+{
+    const double* A = g.world_to_index;
+    const double a = A[0], b = A[1], c = A[2], d = A[4], e = A[5], f = A[6], h = A[8], i = A[9],
+                 j = A[10];
+    const double c00 = e * j - f * i, c01 = f * h - d * j, c02 = d * i - e * h;
+    const double det = a * c00 + b * c01 + c * c02;
+    if (!(fabs(det) > 0.0) || !isfinite(det)) return false;
+    const double L[9] = {c00 / det, (c * i - b * j) / det, (b * f - c * e) / det,
+                         c01 / det, (a * j - c * h) / det, (c * d - a * f) / det,
+                         c02 / det, (b * h - a * i) / det, (a * e - b * d) / det};
+    for (int r = 0; r < 3; ++r) {
+        for (int k = 0; k < 3; ++k) M[4 * r + k] = L[3 * r + k];
+        M[4 * r + 3] = -(L[3 * r] * A[3] + L[3 * r + 1] * A[7] + L[3 * r + 2] * A[11]);
+    }
+    return true;
+}
+
+gm_status check_nrf(const gm_nrf* n)
+{
+    if (!n) return fail(GM_ERR_INVALID_ARGUMENT, "nrf is NULL");
+    if (n->width != 64) return fail(GM_ERR_UNSUPPORTED, "nrf width must be 64");
+    if (n->depth < 1 || n->depth > 4) return fail(GM_ERR_UNSUPPORTED, "nrf depth outside [1, 4]");
+    if (n->in_pad != 64 && n->in_pad != 128)
+        return fail(GM_ERR_UNSUPPORTED, "nrf in_pad must be 64 or 128");
+    if (n->n_freq < 0 || 3 + 6 * n->n_freq > n->in_pad)
+        return fail(GM_ERR_INVALID_ARGUMENT, "nrf needs 3 + 6 n_freq <= in_pad");
+    if (!isfinite(n->out_scale)) return fail(GM_ERR_INVALID_ARGUMENT, "nrf out_scale not finite");
+    if (!n->w_in || !n->b_in || !n->w_out || !n->b_out || (n->depth > 1 && (!n->w_hid || !n->b_hid)))
+        return fail(GM_ERR_INVALID_ARGUMENT, "nrf weight pointer is NULL");
+    if (((uintptr_t)n->w_in & 7u) || (n->w_hid && ((uintptr_t)n->w_hid & 7u)))
+        return fail(GM_ERR_INVALID_ARGUMENT, "nrf weights must be 8-byte aligned");
+    return GM_OK;
+}
+
+NrfArgs nrf_args(const gm_nrf* n, const gm_grid& g, const double* M)
+{
+    NrfArgs a;
+    memset(&a, 0, sizeof a);
+    a.n_freq = n->n_freq;
+    a.depth = n->depth;
+    a.in_pad = n->in_pad;
+    a.out_scale = n->out_scale;
+    a.w_in = n->w_in;
+    a.b_in = n->b_in;
+    a.w_hid = n->w_hid;
+    a.b_hid = n->b_hid;
+    a.w_out = n->w_out;
+    a.b_out = n->b_out;
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.nz = g.nz;
+    for (int k = 0; k < 12; ++k) a.m[k] = M[k];
+    return a;
+}
+
+struct NrfLayout {
+    size_t bytes;
+    size_t off_dzo, off_dz[4], off_a[5], off_part;
+    int64_t P;
+};
+
+NrfLayout nrf_layout(const gm_nrf* n, int64_t npts)
+{
+    NrfLayout L;
+    memset(&L, 0, sizeof L);
+    L.P = ((npts + 15) / 16) * 16;
+    size_t o = 0;
+    auto take = [&](size_t b) { const size_t r = o; o += align256(b); return r; };
+    L.off_dzo = take((size_t)L.P * 4);
+    for (int l = 0; l < n->depth; ++l) L.off_dz[l] = take((size_t)64 * L.P * 2);
+    L.off_a[0] = take((size_t)n->in_pad * L.P * 2);
+    for (int l = 1; l <= n->depth; ++l) L.off_a[l] = take((size_t)64 * L.P * 2);
+    const int64_t nchunk = (L.P + 1023) / 1024;
+    L.off_part = take((size_t)nchunk * 64 * (n->in_pad > 64 ? n->in_pad : 64) * 4);
+    L.bytes = o;
+    return L;
+}
+
 }  // namespace
 
 extern "C" {
@@ -365,9 +444,117 @@ gm_status gm_render_volume(const gm_bins* bins, int32_t grid_id, const gm_nrf* n
                            gm_stream stream)
 {
     g_err.clear();
-    if (nrf) return fail(GM_ERR_UNSUPPORTED, "neural residual epilogue not built into this library");
+    if (nrf) {
+        gm_status st = check_nrf(nrf);
+        if (st != GM_OK) return st;
+    }
     float* outs[1] = {out};
-    return render_impl(bins, &grid_id, 1, outs, reinterpret_cast<hipStream_t>(stream));
+    gm_status st = render_impl(bins, &grid_id, 1, outs, reinterpret_cast<hipStream_t>(stream));
+    if (st != GM_OK || !nrf) return st;
+    return gm_nrf_forward(nrf, &bins->grids[grid_id], out, stream);
+}
+
+gm_status gm_index_to_world(const gm_grid* grid, double out[12])
+{
+    g_err.clear();
+    if (!grid || !out) return fail(GM_ERR_INVALID_ARGUMENT, "NULL argument");
+    gm_status st = check_grid(*grid, 0);
+    if (st != GM_OK) return st;
+    if (!index_to_world(*grid, out)) return fail(GM_ERR_INVALID_ARGUMENT, "singular grid affine");
+    return GM_OK;
+}
+
+gm_status gm_nrf_forward(const gm_nrf* nrf, const gm_grid* grid, float* out, gm_stream stream)
+{
+    g_err.clear();
+    gm_status st = check_nrf(nrf);
+    if (st != GM_OK) return st;
+    if (!grid) return fail(GM_ERR_INVALID_ARGUMENT, "grid is NULL");
+    st = check_grid(*grid, 0);
+    if (st != GM_OK) return st;
+    REQ_PTR(out, "out");
+    double M[12];
+    if (!index_to_world(*grid, M)) return fail(GM_ERR_INVALID_ARGUMENT, "singular grid affine");
+    NrfArgs a = nrf_args(nrf, *grid, M);
+    a.n_points = (int64_t)grid->nx * grid->ny * grid->nz;
+    a.out = out;
+    GM_HIP(launch_nrf_forward(a, reinterpret_cast<hipStream_t>(stream)), "nrf forward");
+    return GM_OK;
+}
+
+gm_status gm_nrf_workspace(const gm_nrf* nrf, int64_t n_points, size_t* bytes)
+{
+    g_err.clear();
+    gm_status st = check_nrf(nrf);
+    if (st != GM_OK) return st;
+    if (n_points < 0 || n_points > 0x7fffffffLL || !bytes)
+        return fail(GM_ERR_INVALID_ARGUMENT, "n_points outside [0, 2^31) or bytes NULL");
+    *bytes = nrf_layout(nrf, n_points).bytes;
+    return GM_OK;
+}
+
+gm_status gm_nrf_backward(const gm_nrf* nrf, const gm_grid* grid, const int32_t* idx,
+                          int64_t n_points, const float* dl_dr, float scale, gm_nrf_grads* grads,
+                          void* workspace, size_t workspace_bytes, gm_stream stream)
+{
+    g_err.clear();
+    gm_status st = check_nrf(nrf);
+    if (st != GM_OK) return st;
+    if (!grid || !grads) return fail(GM_ERR_INVALID_ARGUMENT, "grid / grads is NULL");
+    st = check_grid(*grid, 0);
+    if (st != GM_OK) return st;
+    if (n_points < 0 || n_points > 0x7fffffffLL) return fail(GM_ERR_INVALID_ARGUMENT, "n_points");
+    if (!idx && n_points != (int64_t)grid->nx * grid->ny * grid->nz)
+        return fail(GM_ERR_INVALID_ARGUMENT, "idx NULL requires n_points = grid voxels");
+    if (!isfinite(scale)) return fail(GM_ERR_INVALID_ARGUMENT, "scale not finite");
+    if (n_points == 0) return GM_OK;
+    REQ_PTR(dl_dr, "dl_dr");
+    REQ_PTR(workspace, "workspace");
+    REQ_PTR(grads->w_in, "grads->w_in");
+    REQ_PTR(grads->b_in, "grads->b_in");
+    REQ_PTR(grads->w_out, "grads->w_out");
+    REQ_PTR(grads->b_out, "grads->b_out");
+    if (nrf->depth > 1) {
+        REQ_PTR(grads->w_hid, "grads->w_hid");
+        REQ_PTR(grads->b_hid, "grads->b_hid");
+    }
+    const NrfLayout L = nrf_layout(nrf, n_points);
+    if (workspace_bytes < L.bytes)
+        return fail(GM_ERR_INVALID_ARGUMENT, "workspace %zu bytes < required %zu", workspace_bytes,
+                    L.bytes);
+    double M[12];
+    if (!index_to_world(*grid, M)) return fail(GM_ERR_INVALID_ARGUMENT, "singular grid affine");
+    NrfArgs a = nrf_args(nrf, *grid, M);
+    a.n_points = n_points;
+    a.idx = idx;
+    a.dl_dr = dl_dr;
+    a.scale = scale;
+    a.g_w_in = grads->w_in;
+    a.g_b_in = grads->b_in;
+    a.g_w_hid = grads->w_hid;
+    a.g_b_hid = grads->b_hid;
+    a.g_w_out = grads->w_out;
+    a.g_b_out = grads->b_out;
+    char* base = reinterpret_cast<char*>(workspace);
+    NrfWork w;
+    memset(&w, 0, sizeof w);
+    w.P = L.P;
+    w.dzo = reinterpret_cast<float*>(base + L.off_dzo);
+    for (int l = 0; l < nrf->depth; ++l) w.dz[l] = reinterpret_cast<uint16_t*>(base + L.off_dz[l]);
+    for (int l = 0; l <= nrf->depth; ++l) w.a[l] = reinterpret_cast<uint16_t*>(base + L.off_a[l]);
+    w.part = reinterpret_cast<float*>(base + L.off_part);
+    GM_HIP(launch_nrf_backward(a, w, reinterpret_cast<hipStream_t>(stream)), "nrf backward");
+    return GM_OK;
+}
+
+gm_status gm_f32_to_bf16(const float* in, uint16_t* out, int64_t n, gm_stream stream)
+{
+    g_err.clear();
+    if (n < 0) return fail(GM_ERR_INVALID_ARGUMENT, "n < 0");
+    if (n == 0) return GM_OK;
+    if (!in || !out) return fail(GM_ERR_INVALID_ARGUMENT, "NULL pointer");
+    GM_HIP(launch_to_bf16(in, out, n, reinterpret_cast<hipStream_t>(stream)), "to bf16");
+    return GM_OK;
 }
 
 gm_status gm_backward(const gm_gaussians* g, const gm_bins* bins, const int32_t* grid_ids,

@@ -150,6 +150,40 @@ struct DevoxArgs {
 };
 hipError_t launch_devox(const DevoxArgs& a, hipStream_t s);
 
+struct NrfArgs {
+    int32_t n_freq, depth, in_pad;
+    float out_scale;
+    const uint16_t* w_in;
+    const float* b_in;
+    const uint16_t* w_hid;
+    const float* b_hid;
+    const uint16_t* w_out;
+    const float* b_out;
+    int32_t nx, ny, nz;
+    int64_t n_points;
+    const int32_t* idx;      // voxel linear indices, or NULL for every voxel in order
+    double m[12];            // index -> world affine
+    float* out;              // forward: out[v] += r
+    const float* dl_dr;      // backward: per-voxel dL/dr of the grid
+    float scale;
+    float* g_w_in;
+    float* g_b_in;
+    float* g_w_hid;
+    float* g_b_hid;
+    float* g_w_out;
+    float* g_b_out;
+};
+struct NrfWork {
+    int64_t P;               // points rounded up to 16
+    float* dzo;              // [P]
+    uint16_t* dz[4];         // [64][P] per layer
+    uint16_t* a[5];          // a[0] [in_pad][P], a[l] [64][P]
+    float* part;             // split-K partials
+};
+hipError_t launch_nrf_forward(const NrfArgs& a, hipStream_t s);
+hipError_t launch_nrf_backward(const NrfArgs& a, const NrfWork& w, hipStream_t s);
+hipError_t launch_to_bf16(const float* in, uint16_t* out, int64_t n, hipStream_t s);
+
 // ---- device helpers ---------------------------------------------------------------------
 #ifdef __HIPCC__
 // Sum of v over the 64 lanes of the wavefront, returned in every lane (DPP adds within each

@@ -1,0 +1,450 @@
+// K11: neural residual field (Sec. 3.4, Eq. 8) on MFMA: BF16 weights and activations,
+// FP32 accumulation.
+//
+// r(x) = out_scale tanh(w_out . a_D + b_out),  a_l = SiLU(W_l a_{l-1} + b_l),
+// a_0 = gamma(x) = (x, sin(2^k pi x), cos(2^k pi x), k < n_freq), zero-padded to in_pad.
+//
+// Layout trick: each layer is computed transposed, Z^T = W X^T, with the 16x16x16 BF16 MFMA
+// (A = 16 output features x 16 input features of W, B = 16 input features x 16 points).  The
+// MFMA result holds, per lane, 4 consecutive output features of one point - exactly the B
+// operand layout of the next layer - so activations never leave registers inside a layer
+// stack.  The encoding is computed directly in that layout.
+//
+// Backward (for a list of sampled voxels): recompute, then per layer dZ_l = dA_l * SiLU'(Z_l),
+// dA_{l-1} = W_l^T dZ_l (MFMA); dZ_l and A_{l-1} are written feature-major (BF16) and the
+// weight gradients dW_l = dZ_l A_{l-1}^T are formed by a split-K MFMA GEMM over the points.
+#include "gm_internal.h"
+
+namespace {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int W = 64;          // hidden width (fixed)
+constexpr int MAX_IN = 128;    // in_pad <= 128
+constexpr int MAX_DEPTH = 4;   // depth <= 4, in_pad in {64, 128}
+
+__device__ __forceinline__ uint16_t to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ v4s pack4(float a, float b, float c, float d)
+{
+    v4s r;
+    r.x = (short)to_bf16(a);
+    r.y = (short)to_bf16(b);
+    r.z = (short)to_bf16(c);
+    r.w = (short)to_bf16(d);
+    return r;
+}
+
+__device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float dsilu(float z)
+{
+    const float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+// World coordinate of voxel (vx, vy, vz): binary64 without contraction, rounded once.
+__device__ __forceinline__ float world_coord(const double* M, int vx, int vy, int vz)
+{
+    double s = __dmul_rn(M[0], (double)vx);
+    s = __dadd_rn(s, __dmul_rn(M[1], (double)vy));
+    s = __dadd_rn(s, __dmul_rn(M[2], (double)vz));
+    s = __dadd_rn(s, M[3]);
+    return (float)s;
+}
+
+// Feature f of the encoding at float coordinates x.
+__device__ __forceinline__ float feature(int f, int n_freq, const float x[3])
+{
+    if (f < 3) return x[f];
+    const int g = f - 3;
+    const int band = g / 6, r = g - band * 6;
+    if (band >= n_freq) return 0.0f;
+    const int axis = r < 3 ? r : r - 3;
+    const float phi = ldexpf(x[axis], band - 1);      // exact power-of-two scaling
+    const float frac = phi - rintf(phi);              // exact
+    // v_sin_f32 / v_cos_f32 take their argument in revolutions
+    return r < 3 ? __builtin_amdgcn_sinf(frac) : __builtin_amdgcn_cosf(frac);
+}
+
+struct Lds {
+    uint16_t w_in[W * MAX_IN];
+    uint16_t w_hid[(MAX_DEPTH - 1) * W * W];
+};
+
+__device__ void load_weights(const NrfArgs& a, Lds& s)
+{
+    const int nin = W * a.in_pad, nh = (a.depth - 1) * W * W;
+    for (int i = threadIdx.x; i < nin; i += blockDim.x) s.w_in[i] = a.w_in[i];
+    for (int i = threadIdx.x; i < nh; i += blockDim.x) s.w_hid[i] = a.w_hid[i];
+    __syncthreads();
+}
+
+__device__ __forceinline__ void point_xyz(const NrfArgs& a, int64_t p, int* vx, int* vy, int* vz)
+{
+    int64_t v = a.idx ? (int64_t)a.idx[p] : p;
+    *vx = (int)(v % a.nx);
+    v /= a.nx;
+    *vy = (int)(v % a.ny);
+    *vz = (int)(v / a.ny);
+}
+
+// Forward for the 16 points of a tile: fills B0 (encoding), Z (pre-activations) and the
+// BF16 activations A (register layout: o-tile x 4 features of point lane&15).
+template <int KT, int DEPTH>
+struct Tile {
+    v4s b0[KT];
+    v4f z[DEPTH][4];
+    v4s act[DEPTH][4];
+};
+
+// Store a register tile (4 features x point p) feature-major into dst [features][P].
+__device__ __forceinline__ void store_fm(uint16_t* dst, int f, int64_t P, int64_t p, v4s v)
+{
+    dst[(int64_t)(f + 0) * P + p] = (uint16_t)v.x;
+    dst[(int64_t)(f + 1) * P + p] = (uint16_t)v.y;
+    dst[(int64_t)(f + 2) * P + p] = (uint16_t)v.z;
+    dst[(int64_t)(f + 3) * P + p] = (uint16_t)v.w;
+}
+
+// With a workspace (w != NULL) the encoding and each layer's BF16 activations are written out
+// feature-major as soon as they are formed (the backward needs them for dW), so they need not
+// stay live in registers.
+template <int KT, int DEPTH>
+__device__ __forceinline__ void tile_forward(const NrfArgs& a, const Lds& s, const float x[3],
+                                             Tile<KT, DEPTH>& T, const NrfWork* w = nullptr,
+                                             int64_t p = 0)
+{
+    const int lane = threadIdx.x & 63, g = lane >> 4, row = lane & 15;
+    constexpr int IN = 16 * KT;
+#pragma unroll
+    for (int t = 0; t < KT; ++t) {
+        const int f0 = 16 * t + 4 * g;
+        T.b0[t] = pack4(feature(f0, a.n_freq, x), feature(f0 + 1, a.n_freq, x),
+                        feature(f0 + 2, a.n_freq, x), feature(f0 + 3, a.n_freq, x));
+        if (w) store_fm(w->a[0], f0, w->P, p, T.b0[t]);
+    }
+    // layer 1
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+        v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int t = 0; t < KT; ++t) {
+            const v4s A = *reinterpret_cast<const v4s*>(&s.w_in[(16 * o + row) * IN + 16 * t + 4 * g]);
+            acc = mfma(A, T.b0[t], acc);
+        }
+        const int f = 16 * o + 4 * g;
+        acc.x += a.b_in[f];
+        acc.y += a.b_in[f + 1];
+        acc.z += a.b_in[f + 2];
+        acc.w += a.b_in[f + 3];
+        T.z[0][o] = acc;
+        T.act[0][o] = pack4(silu(acc.x), silu(acc.y), silu(acc.z), silu(acc.w));
+        if (w) store_fm(w->a[1], f, w->P, p, T.act[0][o]);
+    }
+    // hidden layers
+#pragma unroll
+    for (int l = 1; l < DEPTH; ++l) {
+        const uint16_t* Wl = s.w_hid + (l - 1) * W * W;
+        const float* bl = a.b_hid + (l - 1) * W;
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const v4s A = *reinterpret_cast<const v4s*>(&Wl[(16 * o + row) * W + 16 * t + 4 * g]);
+                acc = mfma(A, T.act[l - 1][t], acc);
+            }
+            const int f = 16 * o + 4 * g;
+            acc.x += bl[f];
+            acc.y += bl[f + 1];
+            acc.z += bl[f + 2];
+            acc.w += bl[f + 3];
+            T.z[l][o] = acc;
+            T.act[l][o] = pack4(silu(acc.x), silu(acc.y), silu(acc.z), silu(acc.w));
+            if (w) store_fm(w->a[l + 1], f, w->P, p, T.act[l][o]);
+        }
+    }
+}
+
+// output pre-activation z_o of the tile's point (all 4 lane groups end with the total)
+template <int KT, int DEPTH>
+__device__ __forceinline__ float tile_output(const NrfArgs& a, const Tile<KT, DEPTH>& T)
+{
+    const int lane = threadIdx.x & 63, g = lane >> 4;
+    float sacc = 0.0f;
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+        const v4f zz = T.z[DEPTH - 1][o];
+        const int f = 16 * o + 4 * g;
+        sacc += from_bf16(a.w_out[f]) * silu(zz.x) + from_bf16(a.w_out[f + 1]) * silu(zz.y) +
+                from_bf16(a.w_out[f + 2]) * silu(zz.z) + from_bf16(a.w_out[f + 3]) * silu(zz.w);
+    }
+    sacc += __shfl_xor(sacc, 16, 64);
+    sacc += __shfl_xor(sacc, 32, 64);
+    return sacc + a.b_out[0];
+}
+
+template <int KT, int DEPTH>
+__global__ __launch_bounds__(256) void k_nrf_forward(const NrfArgs a)
+{
+    __shared__ Lds s;
+    load_weights(a, s);
+    const int lane = threadIdx.x & 63, g = lane >> 4, row = lane & 15;
+    const int64_t ntiles = (a.n_points + 15) / 16;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntiles;
+         tile += (int64_t)gridDim.x * 4) {
+        const int64_t p = tile * 16 + row;
+        const bool valid = p < a.n_points;
+        int vx = 0, vy = 0, vz = 0;
+        if (valid) point_xyz(a, p, &vx, &vy, &vz);
+        const float x[3] = {world_coord(a.m, vx, vy, vz), world_coord(a.m + 4, vx, vy, vz),
+                            world_coord(a.m + 8, vx, vy, vz)};
+        Tile<KT, DEPTH> T;
+        tile_forward<KT, DEPTH>(a, s, x, T);
+        const float zo = tile_output<KT, DEPTH>(a, T);
+        if (valid && g == 0) {
+            const int64_t v = ((int64_t)vz * a.ny + vy) * a.nx + vx;
+            a.out[v] += a.out_scale * tanhf(zo);
+        }
+    }
+}
+
+// Recompute a tile and write, feature-major with point stride P: DZO (f32, per point), and
+// for each layer l (1..D) dZ_l [W][P] and A_{l-1} [in_l][P] (BF16), plus A_D [W][P].
+template <int KT, int DEPTH>
+__global__ __launch_bounds__(256) void k_nrf_chain(const NrfArgs a, NrfWork w)
+{
+    __shared__ Lds s;
+    load_weights(a, s);
+    const int lane = threadIdx.x & 63, g = lane >> 4, row = lane & 15;
+    const int64_t P = w.P;
+    const int64_t ntiles = P / 16;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntiles;
+         tile += (int64_t)gridDim.x * 4) {
+        const int64_t p = tile * 16 + row;
+        const bool valid = p < a.n_points;
+        int vx = 0, vy = 0, vz = 0;
+        if (valid) point_xyz(a, p, &vx, &vy, &vz);
+        const float x[3] = {world_coord(a.m, vx, vy, vz), world_coord(a.m + 4, vx, vy, vz),
+                            world_coord(a.m + 8, vx, vy, vz)};
+        Tile<KT, DEPTH> T;
+        tile_forward<KT, DEPTH>(a, s, x, T, &w, p);
+        const float zo = tile_output<KT, DEPTH>(a, T);
+        float dl = 0.0f;
+        if (valid) dl = a.dl_dr[((int64_t)vz * a.ny + vy) * a.nx + vx];
+        const float th = tanhf(zo);
+        const float dzo = valid ? dl * a.scale * a.out_scale * (1.0f - th * th) : 0.0f;
+        if (g == 0) w.dzo[p] = dzo;
+        // dA_D = dzo w_out, then back through the layers
+        v4f da[4];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const int f = 16 * o + 4 * g;
+            da[o].x = dzo * from_bf16(a.w_out[f]);
+            da[o].y = dzo * from_bf16(a.w_out[f + 1]);
+            da[o].z = dzo * from_bf16(a.w_out[f + 2]);
+            da[o].w = dzo * from_bf16(a.w_out[f + 3]);
+        }
+#pragma unroll
+        for (int l = DEPTH - 1; l >= 0; --l) {
+            v4s dz[4];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                const v4f z = T.z[l][o];
+                const v4f d = da[o];
+                dz[o] = pack4(d.x * dsilu(z.x), d.y * dsilu(z.y), d.z * dsilu(z.z), d.w * dsilu(z.w));
+                store_fm(w.dz[l], 16 * o + 4 * g, P, p, dz[o]);
+            }
+            if (l == 0) break;
+            // dA_{l-1} = W_l^T dZ_l : A operand = 16 input x 16 output features of W_l^T
+            const uint16_t* Wl = s.w_hid + (l - 1) * W * W;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int o = 0; o < 4; ++o) {
+                    v4s A;
+                    const int oo = 16 * o + 4 * g, ii = 16 * i + row;
+                    A.x = (short)Wl[(oo + 0) * W + ii];
+                    A.y = (short)Wl[(oo + 1) * W + ii];
+                    A.z = (short)Wl[(oo + 2) * W + ii];
+                    A.w = (short)Wl[(oo + 3) * W + ii];
+                    acc = mfma(A, dz[o], acc);
+                }
+                da[i] = acc;
+            }
+        }
+    }
+}
+
+// Split-K GEMM over points: part[chunk][m][n] = sum_{p in chunk} L[m][p] R[n][p], with L
+// [M][P] and R [N][P] BF16 (M, N multiples of 16, P a multiple of 16).  One block per
+// chunk of 1024 points; its 4 wavefronts share the output tiles.
+__global__ __launch_bounds__(256) void k_gemm_nt_splitk(const uint16_t* __restrict__ L,
+                                                        const uint16_t* __restrict__ R, int M,
+                                                        int N, int64_t P, float* __restrict__ part)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, row = lane & 15;
+    const int64_t p0 = (int64_t)blockIdx.x * 1024;
+    const int64_t p1 = min(p0 + 1024, P);
+    const int mt = M / 16, nt = N / 16;
+    float* out = part + (int64_t)blockIdx.x * M * N;
+    for (int tile = wave; tile < mt * nt; tile += 4) {
+        const int tm = tile / nt, tn = tile % nt;
+        v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        const uint16_t* lp = L + (int64_t)(16 * tm + row) * P + 4 * g;
+        const uint16_t* rp = R + (int64_t)(16 * tn + row) * P + 4 * g;
+        for (int64_t q = p0; q < p1; q += 16) {
+            const v4s A = *reinterpret_cast<const v4s*>(lp + q);
+            const v4s B = *reinterpret_cast<const v4s*>(rp + q);
+            acc = mfma(A, B, acc);
+        }
+        // acc holds rows 16 tm + 4 g + j, column 16 tn + row
+        const int c = 16 * tn + row;
+        out[(16 * tm + 4 * g + 0) * N + c] = acc.x;
+        out[(16 * tm + 4 * g + 1) * N + c] = acc.y;
+        out[(16 * tm + 4 * g + 2) * N + c] = acc.z;
+        out[(16 * tm + 4 * g + 3) * N + c] = acc.w;
+    }
+}
+
+// out[e] += sum_c part[c][e]  (fixed order)
+__global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ part, int64_t nchunk,
+                                                   int64_t n, float* __restrict__ out)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    float s = 0.0f;
+    for (int64_t c = 0; c < nchunk; ++c) s += part[c * n + e];
+    out[e] += s;
+}
+
+// out[m] += sum_p L[m][p] * v[p] (v = NULL: plain row sums); BF16 rows, f32 v; block per row
+__global__ __launch_bounds__(256) void k_rowdot(const uint16_t* __restrict__ L,
+                                                const float* __restrict__ v, int64_t P,
+                                                float* __restrict__ out)
+{
+    __shared__ float sh[256];
+    const uint16_t* r = L + (int64_t)blockIdx.x * P;
+    float acc = 0.0f;
+    for (int64_t p = threadIdx.x; p < P; p += 256) acc += from_bf16(r[p]) * (v ? v[p] : 1.0f);
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] += sh[0];
+}
+
+// sum of the f32 vector v[P] into out[0]
+__global__ __launch_bounds__(256) void k_vsum(const float* __restrict__ v, int64_t P,
+                                              float* __restrict__ out)
+{
+    __shared__ float sh[256];
+    float acc = 0.0f;
+    for (int64_t p = threadIdx.x; p < P; p += 256) acc += v[p];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] += sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ in,
+                                                 uint16_t* __restrict__ out, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = to_bf16(in[i]);
+}
+
+unsigned blocks_for_tiles(int64_t ntiles)
+{
+    int64_t b = (ntiles + 3) / 4;
+    if (b < 1) b = 1;
+    if (b > 2048) b = 2048;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+template <int KT, int DEPTH>
+void launch_fwd_t(const NrfArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_nrf_forward<KT, DEPTH>), dim3(blocks_for_tiles((a.n_points + 15) / 16)),
+                       dim3(256), 0, s, a);
+}
+
+template <int KT, int DEPTH>
+void launch_chain_t(const NrfArgs& a, const NrfWork& w, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_nrf_chain<KT, DEPTH>), dim3(blocks_for_tiles(w.P / 16)), dim3(256), 0, s,
+                       a, w);
+}
+
+// supported shapes: in_pad 64 or 128 (4 or 8 K-tiles), depth 1..4
+#define GM_NRF_DISPATCH(FN, ...)                                                           \
+    switch ((a.in_pad >> 4) * 8 + a.depth) {                                               \
+    case 4 * 8 + 1: FN<4, 1>(__VA_ARGS__); break;                                          \
+    case 4 * 8 + 2: FN<4, 2>(__VA_ARGS__); break;                                          \
+    case 4 * 8 + 3: FN<4, 3>(__VA_ARGS__); break;                                          \
+    case 4 * 8 + 4: FN<4, 4>(__VA_ARGS__); break;                                          \
+    case 8 * 8 + 1: FN<8, 1>(__VA_ARGS__); break;                                          \
+    case 8 * 8 + 2: FN<8, 2>(__VA_ARGS__); break;                                          \
+    case 8 * 8 + 3: FN<8, 3>(__VA_ARGS__); break;                                          \
+    case 8 * 8 + 4: FN<8, 4>(__VA_ARGS__); break;                                          \
+    default: return hipErrorInvalidValue;                                                  \
+    }
+
+hipError_t launch_nrf_forward(const NrfArgs& a, hipStream_t s)
+{
+    if (a.n_points <= 0) return hipSuccess;
+    GM_NRF_DISPATCH(launch_fwd_t, a, s)
+    return hipGetLastError();
+}
+
+hipError_t launch_nrf_backward(const NrfArgs& a, const NrfWork& w, hipStream_t s)
+{
+    if (a.n_points <= 0) return hipSuccess;
+    GM_NRF_DISPATCH(launch_chain_t, a, w, s)
+    const int64_t nchunk = (w.P + 1023) / 1024;
+    for (int l = 0; l < a.depth; ++l) {
+        const int N = l == 0 ? a.in_pad : W;
+        float* dst = l == 0 ? a.g_w_in : a.g_w_hid + (int64_t)(l - 1) * W * W;
+        float* dbias = l == 0 ? a.g_b_in : a.g_b_hid + (int64_t)(l - 1) * W;
+        hipLaunchKernelGGL(k_gemm_nt_splitk, dim3((unsigned)nchunk), dim3(256), 0, s, w.dz[l],
+                           w.a[l], W, N, w.P, w.part);
+        const int64_t n = (int64_t)W * N;
+        hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w.part,
+                           nchunk, n, dst);
+        hipLaunchKernelGGL(k_rowdot, dim3(W), dim3(256), 0, s, w.dz[l], (const float*)nullptr, w.P,
+                           dbias);
+    }
+    hipLaunchKernelGGL(k_rowdot, dim3(W), dim3(256), 0, s, w.a[a.depth], w.dzo, w.P, a.g_w_out);
+    hipLaunchKernelGGL(k_vsum, dim3(1), dim3(256), 0, s, w.dzo, w.P, a.g_b_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(const float* in, uint16_t* out, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t b = (n + 255) / 256;
+    if (b > 4096) b = 4096;
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)b), dim3(256), 0, s, in, out, n);
+    return hipGetLastError();
+}

@@ -28,6 +28,7 @@ class TrainConfig:
     nrf: Optional[object] = None  # an nrf.NRF to train jointly (None = Gaussians only)
     nrf_start: float = 0.5        # fraction of n_iter after which the NRF is active
     lr_nrf: float = 1e-4
+    nrf_sample: int = 1 << 18     # stack voxels per stack per iteration for the NRF gradient
 
 
 class Reconstruction:
@@ -76,7 +77,7 @@ class Reconstruction:
         if self.nrf_on:
             c.nrf.zero_grad()
             for k, s in enumerate(self.stacks):
-                c.nrf.backward(s, self.dls[k])
+                c.nrf.backward(s, self.dls[k], n_sample=c.nrf_sample)
             c.nrf.adam_step(c.lr_nrf)
         for prm, gr, mm, vv, lr in zip(self.p.tensors(), self.g.tensors(), self.m.tensors(),
                                        self.v.tensors(), self.lrs()):

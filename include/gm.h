@@ -258,6 +258,52 @@ gm_status gm_devox_init(int32_t g, const gm_grid* stacks, int32_t n_stacks,
                         const float* const* stack_data, float* mean, float* quat,
                         float* log_scale, float* logit, gm_stream stream);
 
+/* ---- warm-start network ------------------------------------------------------------------
+ * Predicts, for each Gaussian of a devoxelization initialisation, residuals of its log-scale,
+ * rotation and intensity from a 3-channel 8^3 patch of the registered stacks around its centre
+ * (initialisation stage of Sec. 3.1 / Fig. 1b, learned):
+ *   conv 3->32 (3^3, stride 1, pad 1), SiLU        8^3
+ *   conv 32->32 (3^3, stride 2, pad 1), SiLU       4^3
+ *   conv 32->32 (3^3, stride 2, pad 1), SiLU       2^3
+ *   conv 32->32 (2^3, valid), SiLU                 1
+ *   linear 32->8  ->  (d log_scale 3, d quat 4, d logit 1)
+ *   log_scale = s0 + d, quat = (1,0,0,0) + d, logit = logit0 + d.
+ * Conv weights are BF16 [32][K_pad] with K = c*k^3 + (kz*k + ky)*k + kx, zero-padded to K_pad
+ * = 96, 864, 864, 256; biases FP32 [32]; head FP32 wl [8][32], bl [8].  Batches n must be
+ * multiples of 16.  Convolutions run on MFMA (BF16 x BF16 -> FP32). */
+typedef struct gm_ws_net {
+    const uint16_t* w[4];
+    const float* b[4];
+    const float* wl;
+    const float* bl;
+} gm_ws_net;
+typedef struct gm_ws_grads { /* FP32, same shapes; accumulated (+=) */
+    float* w[4];
+    float* b[4];
+    float* wl;
+    float* bl;
+} gm_ws_grads;
+
+/* patches [n][3][8][8][8] BF16: channel k = stack k (n_stacks = 3) sampled trilinearly (zero
+ * outside its index domain) at world points means[i] + ((x, y, z) - 3.5) * spacing. */
+gm_status gm_ws_gather(const gm_grid* stacks, int32_t n_stacks, const float* const* stack_data,
+                       const float* means, int64_t n, float spacing, uint16_t* patches,
+                       gm_stream stream);
+/* [host out] workspace bytes for a batch of n. */
+gm_status gm_ws_workspace(int64_t n, size_t* bytes);
+/* Inference: log_scale_out [n][3], quat_out [n][4], logit_out [n]. */
+gm_status gm_ws_forward(const gm_ws_net* net, const uint16_t* patches, int64_t n,
+                        const float* s0, const float* logit0, float* log_scale_out,
+                        float* quat_out, float* logit_out, void* workspace,
+                        size_t workspace_bytes, gm_stream stream);
+/* Training step gradients: loss = mean_i |Sigma_i - Sigma*_i|_F^2 / |Sigma*_i|_F^2
+ * + (logit_i - logit*_i)^2 with Sigma_i = R(q_i) diag(e^{2 s_i}) R(q_i)^T; sigma_target
+ * [n][6] (xx, yy, zz, xy, xz, yz), logit_target [n]; *loss (device float); grads += . */
+gm_status gm_ws_backward(const gm_ws_net* net, const uint16_t* patches, int64_t n,
+                         const float* s0, const float* logit0, const float* sigma_target,
+                         const float* logit_target, float* loss, gm_ws_grads* grads,
+                         void* workspace, size_t workspace_bytes, gm_stream stream);
+
 /* Mean squared error of vol against ref over n voxels into *mse (device float);
  * PSNR = 10 log10(1 / mse) for intensities in [0, 1] (Sec. 4.1.3). */
 gm_status gm_mse(const float* vol, const float* ref, int64_t n, float* mse, void* workspace,

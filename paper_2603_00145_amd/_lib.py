@@ -60,6 +60,14 @@ class GmNrfGrads(ctypes.Structure):
     _fields_ = [("w_in", P), ("b_in", P), ("w_hid", P), ("b_hid", P), ("w_out", P), ("b_out", P)]
 
 
+class GmWsNet(ctypes.Structure):
+    _fields_ = [("w", P * 4), ("b", P * 4), ("wl", P), ("bl", P)]
+
+
+class GmWsGrads(ctypes.Structure):
+    _fields_ = [("w", P * 4), ("b", P * 4), ("wl", P), ("bl", P)]
+
+
 class GmNrf(ctypes.Structure):
     _fields_ = [("n_freq", ctypes.c_int32), ("depth", ctypes.c_int32), ("width", ctypes.c_int32),
                 ("in_pad", ctypes.c_int32), ("out_scale", ctypes.c_float),
@@ -103,6 +111,13 @@ _SIGS = [
                                         ctypes.c_int64, P, ctypes.c_float,
                                         ctypes.POINTER(GmNrfGrads), P, ctypes.c_size_t, P]),
     ("gm_f32_to_bf16", ctypes.c_int, [P, P, ctypes.c_int64, P]),
+    ("gm_ws_gather", ctypes.c_int, [ctypes.POINTER(GmGrid), ctypes.c_int32, ctypes.POINTER(P), P,
+                                     ctypes.c_int64, ctypes.c_float, P, P]),
+    ("gm_ws_workspace", ctypes.c_int, [ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
+    ("gm_ws_forward", ctypes.c_int, [ctypes.POINTER(GmWsNet), P, ctypes.c_int64, P, P, P, P, P,
+                                      P, ctypes.c_size_t, P]),
+    ("gm_ws_backward", ctypes.c_int, [ctypes.POINTER(GmWsNet), P, ctypes.c_int64, P, P, P, P, P,
+                                       ctypes.POINTER(GmWsGrads), P, ctypes.c_size_t, P]),
     ("gm_devox_init", ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(GmGrid), ctypes.c_int32,
                                       ctypes.POINTER(P), P, P, P, P, P]),
 ]

@@ -241,6 +241,65 @@ NrfLayout nrf_layout(const gm_nrf* n, int64_t npts)
     return L;
 }
 
+struct WsLayout {
+    size_t bytes, off_z[4], off_a[4], off_dz[4], off_part, off_loss, off_dout, off_a4;
+};
+
+WsLayout ws_layout(int64_t B)
+{
+    static const int PO[4] = {512, 64, 8, 1};
+    WsLayout L;
+    memset(&L, 0, sizeof L);
+    size_t o = 0;
+    auto take = [&](size_t b) { const size_t r = o; o += align256(b); return r; };
+    for (int l = 0; l < 4; ++l) {
+        L.off_z[l] = take((size_t)B * 32 * PO[l] * 4);
+        L.off_a[l] = take((size_t)B * 32 * PO[l] * 2);
+        L.off_dz[l] = take((size_t)B * 32 * PO[l] * 2);
+    }
+    L.off_part = take(ws_part_floats(B) * 4);
+    L.off_loss = take((size_t)B * 4);
+    L.off_dout = take((size_t)B * 8 * 4);
+    L.off_a4 = take((size_t)B * 32 * 4);
+    L.bytes = o;
+    return L;
+}
+
+gm_status check_ws_net(const gm_ws_net* n)
+{
+    if (!n) return fail(GM_ERR_INVALID_ARGUMENT, "net is NULL");
+    for (int l = 0; l < 4; ++l) {
+        if (!n->w[l] || !n->b[l] || ((uintptr_t)n->w[l] & 7u))
+            return fail(GM_ERR_INVALID_ARGUMENT, "conv %d weights NULL or not 8-byte aligned", l + 1);
+    }
+    if (!n->wl || !n->bl) return fail(GM_ERR_INVALID_ARGUMENT, "head weights NULL");
+    return GM_OK;
+}
+
+WsNet ws_net(const gm_ws_net* n)
+{
+    WsNet w;
+    for (int l = 0; l < 4; ++l) {
+        w.w[l] = n->w[l];
+        w.b[l] = n->b[l];
+    }
+    w.wl = n->wl;
+    w.bl = n->bl;
+    return w;
+}
+
+WsActs ws_acts(char* base, const WsLayout& L)
+{
+    WsActs w;
+    for (int l = 0; l < 4; ++l) {
+        w.z[l] = reinterpret_cast<float*>(base + L.off_z[l]);
+        w.a[l] = reinterpret_cast<uint16_t*>(base + L.off_a[l]);
+        w.dz[l] = reinterpret_cast<uint16_t*>(base + L.off_dz[l]);
+    }
+    w.part = reinterpret_cast<float*>(base + L.off_part);
+    return w;
+}
+
 }  // namespace
 
 extern "C" {
@@ -718,6 +777,137 @@ gm_status gm_devox_init(int32_t g, const gm_grid* stacks, int32_t n_stacks,
     da.log_scale = log_scale;
     da.logit = logit;
     GM_HIP(launch_devox(da, reinterpret_cast<hipStream_t>(stream)), "devox init");
+    return GM_OK;
+}
+
+gm_status gm_ws_gather(const gm_grid* stacks, int32_t n_stacks, const float* const* stack_data,
+                       const float* means, int64_t n, float spacing, uint16_t* patches,
+                       gm_stream stream)
+{
+    g_err.clear();
+    if (n_stacks != 3 || !stacks || !stack_data)
+        return fail(GM_ERR_INVALID_ARGUMENT, "the warm-start network takes exactly 3 stacks");
+    if (n < 0 || !isfinite(spacing) || !(spacing > 0.0f))
+        return fail(GM_ERR_INVALID_ARGUMENT, "n < 0 or bad spacing");
+    if (n == 0) return GM_OK;
+    REQ_PTR(means, "means");
+    REQ_PTR(patches, "patches");
+    WsGatherArgs a;
+    memset(&a, 0, sizeof a);
+    a.n = n;
+    a.spacing = spacing;
+    a.means = means;
+    a.patches = patches;
+    for (int k = 0; k < 3; ++k) {
+        gm_status st = check_grid(stacks[k], k);
+        if (st != GM_OK) return st;
+        REQ_PTR(stack_data[k], "stack_data[k]");
+        a.data[k] = stack_data[k];
+        a.s[k] = make_const(stacks[k], 0);
+    }
+    GM_HIP(launch_ws_gather(a, reinterpret_cast<hipStream_t>(stream)), "ws gather");
+    return GM_OK;
+}
+
+gm_status gm_ws_workspace(int64_t n, size_t* bytes)
+{
+    g_err.clear();
+    if (n < 0 || n % 16 != 0 || !bytes)
+        return fail(GM_ERR_INVALID_ARGUMENT, "n must be a non-negative multiple of 16");
+    *bytes = ws_layout(n).bytes;
+    return GM_OK;
+}
+
+static gm_status ws_common(const gm_ws_net* net, const uint16_t* patches, int64_t n,
+                           const float* s0, const float* logit0, void* ws, size_t ws_bytes,
+                           WsLayout* L)
+{
+    gm_status st = check_ws_net(net);
+    if (st != GM_OK) return st;
+    if (n <= 0 || n % 16 != 0) return fail(GM_ERR_INVALID_ARGUMENT, "n must be a positive multiple of 16");
+    REQ_PTR(patches, "patches");
+    REQ_PTR(s0, "s0");
+    REQ_PTR(logit0, "logit0");
+    REQ_PTR(ws, "workspace");
+    *L = ws_layout(n);
+    if (ws_bytes < L->bytes)
+        return fail(GM_ERR_INVALID_ARGUMENT, "workspace %zu bytes < required %zu", ws_bytes, L->bytes);
+    return GM_OK;
+}
+
+gm_status gm_ws_forward(const gm_ws_net* net, const uint16_t* patches, int64_t n,
+                        const float* s0, const float* logit0, float* log_scale_out,
+                        float* quat_out, float* logit_out, void* workspace,
+                        size_t workspace_bytes, gm_stream stream)
+{
+    g_err.clear();
+    WsLayout L;
+    gm_status st = ws_common(net, patches, n, s0, logit0, workspace, workspace_bytes, &L);
+    if (st != GM_OK) return st;
+    REQ_PTR(log_scale_out, "log_scale_out");
+    REQ_PTR(quat_out, "quat_out");
+    REQ_PTR(logit_out, "logit_out");
+    char* base = reinterpret_cast<char*>(workspace);
+    WsActs w = ws_acts(base, L);
+    WsHeadArgs h;
+    memset(&h, 0, sizeof h);
+    h.n = n;
+    h.z4 = w.z[3];
+    h.wl = net->wl;
+    h.bl = net->bl;
+    h.s0 = s0;
+    h.logit0 = logit0;
+    h.s_out = log_scale_out;
+    h.q_out = quat_out;
+    h.logit_out = logit_out;
+    GM_HIP(launch_ws_forward(ws_net(net), patches, n, w, h, reinterpret_cast<hipStream_t>(stream)),
+           "ws forward");
+    return GM_OK;
+}
+
+gm_status gm_ws_backward(const gm_ws_net* net, const uint16_t* patches, int64_t n,
+                         const float* s0, const float* logit0, const float* sigma_target,
+                         const float* logit_target, float* loss, gm_ws_grads* grads,
+                         void* workspace, size_t workspace_bytes, gm_stream stream)
+{
+    g_err.clear();
+    WsLayout L;
+    gm_status st = ws_common(net, patches, n, s0, logit0, workspace, workspace_bytes, &L);
+    if (st != GM_OK) return st;
+    REQ_PTR(sigma_target, "sigma_target");
+    REQ_PTR(logit_target, "logit_target");
+    REQ_PTR(loss, "loss");
+    if (!grads) return fail(GM_ERR_INVALID_ARGUMENT, "grads is NULL");
+    WsGrads g;
+    for (int l = 0; l < 4; ++l) {
+        REQ_PTR(grads->w[l], "grads->w[l]");
+        REQ_PTR(grads->b[l], "grads->b[l]");
+        g.w[l] = grads->w[l];
+        g.b[l] = grads->b[l];
+    }
+    REQ_PTR(grads->wl, "grads->wl");
+    REQ_PTR(grads->bl, "grads->bl");
+    g.wl = grads->wl;
+    g.bl = grads->bl;
+    char* base = reinterpret_cast<char*>(workspace);
+    WsActs w = ws_acts(base, L);
+    WsHeadArgs h;
+    memset(&h, 0, sizeof h);
+    h.n = n;
+    h.z4 = w.z[3];
+    h.wl = net->wl;
+    h.bl = net->bl;
+    h.s0 = s0;
+    h.logit0 = logit0;
+    h.sig_t = sigma_target;
+    h.logit_t = logit_target;
+    h.loss_each = reinterpret_cast<float*>(base + L.off_loss);
+    h.dout = reinterpret_cast<float*>(base + L.off_dout);
+    h.a4 = reinterpret_cast<float*>(base + L.off_a4);
+    h.dz4 = w.dz[3];
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    GM_HIP(launch_ws_forward(ws_net(net), patches, n, w, h, s), "ws forward");
+    GM_HIP(launch_ws_backward(ws_net(net), patches, n, w, h, g, loss, s), "ws backward");
     return GM_OK;
 }
 

@@ -184,6 +184,57 @@ hipError_t launch_nrf_forward(const NrfArgs& a, hipStream_t s);
 hipError_t launch_nrf_backward(const NrfArgs& a, const NrfWork& w, hipStream_t s);
 hipError_t launch_to_bf16(const float* in, uint16_t* out, int64_t n, hipStream_t s);
 
+struct WsGatherArgs {
+    int64_t n;
+    float spacing;
+    const float* means;
+    uint16_t* patches;
+    const float* data[3];
+    GridConst s[3];
+};
+struct WsNet {
+    const uint16_t* w[4];
+    const float* b[4];
+    const float* wl;
+    const float* bl;
+};
+struct WsActs {
+    float* z[4];
+    uint16_t* a[4];
+    uint16_t* dz[4];
+    float* part;
+};
+struct WsHeadArgs {
+    int64_t n;
+    const float* z4;
+    const float* wl;
+    const float* bl;
+    const float* s0;
+    const float* logit0;
+    float* s_out;
+    float* q_out;
+    float* logit_out;
+    const float* sig_t;      // NULL: inference only
+    const float* logit_t;
+    float* loss_each;
+    float* dout;
+    float* a4;
+    uint16_t* dz4;
+};
+struct WsGrads {
+    float* w[4];
+    float* b[4];
+    float* wl;
+    float* bl;
+};
+int ws_kpad(int layer);
+size_t ws_part_floats(int64_t B);
+hipError_t launch_ws_gather(const WsGatherArgs& a, hipStream_t s);
+hipError_t launch_ws_forward(const WsNet& net, const uint16_t* X0, int64_t B, const WsActs& w,
+                             const WsHeadArgs& head, hipStream_t s);
+hipError_t launch_ws_backward(const WsNet& net, const uint16_t* X0, int64_t B, const WsActs& w,
+                              const WsHeadArgs& head, const WsGrads& g, float* loss, hipStream_t s);
+
 // ---- device helpers ---------------------------------------------------------------------
 #ifdef __HIPCC__
 // Sum of v over the 64 lanes of the wavefront, returned in every lane (DPP adds within each

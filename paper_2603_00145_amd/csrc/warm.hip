@@ -1,0 +1,503 @@
+// K12: warm-start network - per Gaussian a 3-channel 8^3 patch of the registered stacks
+// through four 3D convolutions (width 32, BF16 weights and activations, FP32 accumulation on
+// MFMA) and a linear head that predicts residuals (d log-scale 3, d quaternion 4, d logit 1)
+// on top of the devoxelization initialisation.  Training backward (dX and dW) on MFMA.
+//
+// Every convolution is an implicit GEMM on the 16x16x16 BF16 MFMA with one operand gathered
+// on the fly (no im2col buffer):
+//   forward      Z[o][(b,p_out)]   = sum_{(c,tap)} W[o][(c,tap)] X[b][c][p_in(p_out,tap)]
+//   backward-X   dX[c][(b,p_in)]   = sum_{(o,tap)} W[o][(c,tap)] dZ[b][o][p_out(p_in,tap)]
+//   backward-W   dW[o][(c,tap)]    = sum_{(b,p_out)} dZ[b][o][p_out] X[b][c][p_in(p_out,tap)]
+// Activations are stored [sample][channel][position] (BF16, pre-activations FP32).
+#include "gm_internal.h"
+
+namespace {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float dsilu(float z)
+{
+    const float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+__device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+constexpr int CO = 32;
+
+// layer geometry: CI input channels, K^3 taps, stride ST, padding PD, DI^3 -> DO^3
+template <int CI_, int K_, int ST_, int PD_, int DI_, int DO_>
+struct Geo {
+    static constexpr int CI = CI_, K = K_, ST = ST_, PD = PD_, DI = DI_, DO = DO_;
+    static constexpr int KV = K * K * K;
+    static constexpr int PI = DI * DI * DI, PO = DO * DO * DO;
+    static constexpr int KREAL = CI * KV;
+    static constexpr int KPAD = (KREAL + 15) / 16 * 16;
+};
+using G1 = Geo<3, 3, 1, 1, 8, 8>;
+using G2 = Geo<32, 3, 2, 1, 8, 4>;
+using G3 = Geo<32, 3, 2, 1, 4, 2>;
+using G4 = Geo<32, 2, 1, 0, 2, 1>;
+
+// ---- forward ------------------------------------------------------------------------------
+// C tile = 16 output channels x 16 columns (sample, output position); one wavefront per tile.
+template <class G>
+__global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ W,
+                                                  const float* __restrict__ bias,
+                                                  const uint16_t* __restrict__ X, int64_t B,
+                                                  float* __restrict__ Z, uint16_t* __restrict__ A)
+{
+    const int lane = threadIdx.x & 63, g = lane >> 4, row = lane & 15;
+    const int64_t ncol = B * G::PO;
+    const int64_t ntile = ncol / 16;
+    const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= ntile) return;
+    const int m0 = 16 * blockIdx.y;
+    const int64_t n = tile * 16 + row;                 // this lane's column
+    const int64_t b = n / G::PO;
+    const int p = (int)(n - b * G::PO);
+    const int oz = p / (G::DO * G::DO), oy = (p / G::DO) % G::DO, ox = p % G::DO;
+    const uint16_t* xb = X + b * G::CI * G::PI;
+    v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = 0; k0 < G::KPAD; k0 += 16) {
+        const v4s Af = *reinterpret_cast<const v4s*>(W + (m0 + row) * G::KPAD + k0 + 4 * g);
+        short bv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = k0 + 4 * g + j;
+            const int c = k / G::KV, t = k - c * G::KV;
+            const int kz = t / (G::K * G::K), ky = (t / G::K) % G::K, kx = t % G::K;
+            const int iz = G::ST * oz - G::PD + kz, iy = G::ST * oy - G::PD + ky,
+                      ix = G::ST * ox - G::PD + kx;
+            const bool ok = k < G::KREAL && iz >= 0 && iz < G::DI && iy >= 0 && iy < G::DI &&
+                            ix >= 0 && ix < G::DI;
+            bv[j] = ok ? (short)xb[c * G::PI + (iz * G::DI + iy) * G::DI + ix] : (short)0;
+        }
+        v4s Bf;
+        Bf.x = bv[0]; Bf.y = bv[1]; Bf.z = bv[2]; Bf.w = bv[3];
+        acc = mfma(Af, Bf, acc);
+    }
+    const float av[4] = {acc.x, acc.y, acc.z, acc.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int m = m0 + 4 * g + j;
+        const float z = av[j] + bias[m];
+        const int64_t o = (b * CO + m) * G::PO + p;
+        Z[o] = z;
+        A[o] = to_bf16(silu(z));
+    }
+}
+
+// ---- backward through the input: dZ_prev = (W^T dZ) * SiLU'(Z_prev) -----------------------
+// C tile = 16 input channels x 16 columns (sample, input position).
+template <class G>
+__global__ __launch_bounds__(256) void k_conv_bwd_x(const uint16_t* __restrict__ W,
+                                                    const uint16_t* __restrict__ dZ, int64_t B,
+                                                    const float* __restrict__ Zprev,
+                                                    uint16_t* __restrict__ dZprev)
+{
+    const int lane = threadIdx.x & 63, g = lane >> 4, row = lane & 15;
+    const int64_t ncol = B * G::PI;
+    const int64_t ntile = ncol / 16;
+    const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= ntile) return;
+    const int m0 = 16 * blockIdx.y;                    // input channel tile
+    const int64_t n = tile * 16 + row;
+    const int64_t b = n / G::PI;
+    const int p = (int)(n - b * G::PI);
+    const int iz = p / (G::DI * G::DI), iy = (p / G::DI) % G::DI, ix = p % G::DI;
+    const uint16_t* dzb = dZ + b * CO * G::PO;
+    constexpr int KT = CO * G::KV;                     // reduction over (o, tap)
+    v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = 0; k0 < KT; k0 += 16) {
+        short av[4], bv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            // A[c = m0 + row][k] = W[o][c * KV + tap]
+            const int ka = k0 + 4 * g + j;
+            const int oa = ka / G::KV, ta = ka - oa * G::KV;
+            av[j] = (short)W[oa * G::KPAD + (m0 + row) * G::KV + ta];
+            // B[k][n] = dZ[b][o][p_out] with p_in = ST p_out - PD + tap on each axis
+            const int o = ka / G::KV, t = ka - o * G::KV;
+            const int kz = t / (G::K * G::K), ky = (t / G::K) % G::K, kx = t % G::K;
+            const int tz = iz + G::PD - kz, ty = iy + G::PD - ky, tx = ix + G::PD - kx;
+            const bool ok = tz >= 0 && ty >= 0 && tx >= 0 && tz % G::ST == 0 && ty % G::ST == 0 &&
+                            tx % G::ST == 0 && tz / G::ST < G::DO && ty / G::ST < G::DO &&
+                            tx / G::ST < G::DO;
+            bv[j] = ok ? (short)dzb[o * G::PO + ((tz / G::ST) * G::DO + ty / G::ST) * G::DO + tx / G::ST]
+                       : (short)0;
+        }
+        v4s Af, Bf;
+        Af.x = av[0]; Af.y = av[1]; Af.z = av[2]; Af.w = av[3];
+        Bf.x = bv[0]; Bf.y = bv[1]; Bf.z = bv[2]; Bf.w = bv[3];
+        acc = mfma(Af, Bf, acc);
+    }
+    const float r[4] = {acc.x, acc.y, acc.z, acc.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int c = m0 + 4 * g + j;
+        const int64_t o = (b * G::CI + c) * G::PI + p;
+        dZprev[o] = to_bf16(r[j] * dsilu(Zprev[o]));
+    }
+}
+
+// ---- backward to the weights: split over chunks of 256 columns (sample, output position) ---
+// C tile = 16 output channels x 16 (c, tap); partial[chunk][o][k].
+template <class G>
+__global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__ dZ,
+                                                    const uint16_t* __restrict__ X, int64_t B,
+                                                    float* __restrict__ part)
+{
+    const int lane = threadIdx.x & 63, g = lane >> 4, row = lane & 15;
+    constexpr int NT = G::KPAD / 16;
+    const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= 2 * NT) return;
+    const int m0 = 16 * (tile / NT), n0 = 16 * (tile % NT);
+    const int64_t R = B * G::PO;
+    const int64_t r_begin = (int64_t)blockIdx.y * 256;
+    const int64_t r_end = r_begin + 256 < R ? r_begin + 256 : R;
+    // this lane's B column (c, tap)
+    const int kn = n0 + row;
+    const int c = kn / G::KV, t = kn - c * G::KV;
+    const int kz = t / (G::K * G::K), ky = (t / G::K) % G::K, kx = t % G::K;
+    const bool kvalid = kn < G::KREAL;
+    v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += 16) {
+        short av[4], bv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t r = r0 + 4 * g + j;
+            const int64_t b = r / G::PO;
+            const int p = (int)(r - b * G::PO);
+            av[j] = (short)dZ[(b * CO + m0 + row) * G::PO + p];
+            const int oz = p / (G::DO * G::DO), oy = (p / G::DO) % G::DO, ox = p % G::DO;
+            const int iz = G::ST * oz - G::PD + kz, iy = G::ST * oy - G::PD + ky,
+                      ix = G::ST * ox - G::PD + kx;
+            const bool ok = kvalid && iz >= 0 && iz < G::DI && iy >= 0 && iy < G::DI && ix >= 0 &&
+                            ix < G::DI;
+            bv[j] = ok ? (short)X[(b * G::CI + c) * G::PI + (iz * G::DI + iy) * G::DI + ix] : (short)0;
+        }
+        v4s Af, Bf;
+        Af.x = av[0]; Af.y = av[1]; Af.z = av[2]; Af.w = av[3];
+        Bf.x = bv[0]; Bf.y = bv[1]; Bf.z = bv[2]; Bf.w = bv[3];
+        acc = mfma(Af, Bf, acc);
+    }
+    float* out = part + (int64_t)blockIdx.y * CO * G::KPAD;
+    const float r[4] = {acc.x, acc.y, acc.z, acc.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out[(m0 + 4 * g + j) * G::KPAD + n0 + row] = r[j];
+}
+
+// out[e] += sum_c part[c][e]
+__global__ __launch_bounds__(256) void k_sum_parts_ws(const float* __restrict__ part,
+                                                      int64_t nchunk, int64_t n,
+                                                      float* __restrict__ out)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    float s = 0.0f;
+    for (int64_t c = 0; c < nchunk; ++c) s += part[c * n + e];
+    out[e] += s;
+}
+
+// db[o] += sum over (sample, position) of dZ[b][o][p]; one block per channel
+__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ dZ, int64_t B,
+                                                   int P, float* __restrict__ db)
+{
+    __shared__ float sh[256];
+    const int o = blockIdx.x;
+    float acc = 0.0f;
+    for (int64_t i = threadIdx.x; i < B * P; i += 256) {
+        const int64_t b = i / P;
+        const int p = (int)(i - b * P);
+        acc += from_bf16(dZ[(b * CO + o) * P + p]);
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[o] += sh[0];
+}
+
+// ---- patch gather -------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_ws_gather(const WsGatherArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n * 3 * 512) return;
+    const int64_t b = i / (3 * 512);
+    const int rem = (int)(i - b * 3 * 512);
+    const int k = rem / 512, v = rem % 512;
+    const int z = v / 64, y = (v / 8) % 8, x = v % 8;
+    const float wx = a.means[3 * b] + ((float)x - 3.5f) * a.spacing;
+    const float wy = a.means[3 * b + 1] + ((float)y - 3.5f) * a.spacing;
+    const float wz = a.means[3 * b + 2] + ((float)z - 3.5f) * a.spacing;
+    const GridConst& S = a.s[k];
+    const float px = (float)(S.L[0] * wx + S.L[1] * wy + S.L[2] * wz + S.t[0]);
+    const float py = (float)(S.L[3] * wx + S.L[4] * wy + S.L[5] * wz + S.t[1]);
+    const float pz = (float)(S.L[6] * wx + S.L[7] * wy + S.L[8] * wz + S.t[2]);
+    float val = 0.0f;
+    if (px >= 0.0f && py >= 0.0f && pz >= 0.0f && px <= (float)(S.nx - 1) &&
+        py <= (float)(S.ny - 1) && pz <= (float)(S.nz - 1)) {
+        const int x0 = min((int)px, max(S.nx - 2, 0)), y0 = min((int)py, max(S.ny - 2, 0)),
+                  z0 = min((int)pz, max(S.nz - 2, 0));
+        const int x1 = min(x0 + 1, S.nx - 1), y1 = min(y0 + 1, S.ny - 1), z1 = min(z0 + 1, S.nz - 1);
+        const float fx = px - (float)x0, fy = py - (float)y0, fz = pz - (float)z0;
+        const float* d = a.data[k];
+        auto at = [&](int xx, int yy, int zz) { return d[((size_t)zz * S.ny + yy) * S.nx + xx]; };
+        const float c00 = at(x0, y0, z0) * (1.0f - fx) + at(x1, y0, z0) * fx;
+        const float c10 = at(x0, y1, z0) * (1.0f - fx) + at(x1, y1, z0) * fx;
+        const float c01 = at(x0, y0, z1) * (1.0f - fx) + at(x1, y0, z1) * fx;
+        const float c11 = at(x0, y1, z1) * (1.0f - fx) + at(x1, y1, z1) * fx;
+        val = ((c00 * (1.0f - fy) + c10 * fy) * (1.0f - fz) + (c01 * (1.0f - fy) + c11 * fy) * fz);
+    }
+    a.patches[i] = to_bf16(val);
+}
+
+// ---- head: linear 32 -> 8, residual assembly, loss and its gradient -------------------------
+__device__ void rot_from_q(const double q[4], double R[9])
+{
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1.0 - 2.0 * (y * y + z * z);
+    R[1] = 2.0 * (x * y - w * z);
+    R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);
+    R[4] = 1.0 - 2.0 * (x * x + z * z);
+    R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);
+    R[7] = 2.0 * (y * z + w * x);
+    R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+__global__ __launch_bounds__(256) void k_ws_head(const WsHeadArgs a)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.n) return;
+    float a4[CO];
+#pragma unroll
+    for (int c = 0; c < CO; ++c) a4[c] = silu(a.z4[b * CO + c]);
+    float out[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        float s = a.bl[j];
+#pragma unroll
+        for (int c = 0; c < CO; ++c) s += a.wl[j * CO + c] * a4[c];
+        out[j] = s;
+    }
+    const double s_[3] = {(double)a.s0[3 * b] + out[0], (double)a.s0[3 * b + 1] + out[1],
+                          (double)a.s0[3 * b + 2] + out[2]};
+    const double q_[4] = {1.0 + out[3], (double)out[4], (double)out[5], (double)out[6]};
+    const double lg = (double)a.logit0[b] + out[7];
+    if (a.s_out) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) a.s_out[3 * b + m] = (float)s_[m];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) a.q_out[4 * b + m] = (float)q_[m];
+        a.logit_out[b] = (float)lg;
+    }
+    if (!a.sig_t) return;
+    // loss: |Sigma - Sigma*|_F^2 / |Sigma*|_F^2 + (logit - logit*)^2, mean over samples
+    const double qn = sqrt(q_[0] * q_[0] + q_[1] * q_[1] + q_[2] * q_[2] + q_[3] * q_[3]);
+    const double qh[4] = {q_[0] / qn, q_[1] / qn, q_[2] / qn, q_[3] / qn};
+    double R[9];
+    rot_from_q(qh, R);
+    const double S2[3] = {exp(2.0 * s_[0]), exp(2.0 * s_[1]), exp(2.0 * s_[2])};
+    const float* st = a.sig_t + 6 * b;  // xx yy zz xy xz yz
+    const double T[9] = {st[0], st[3], st[4], st[3], st[1], st[5], st[4], st[5], st[2]};
+    double S[9], num = 0.0, den = 0.0;
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            S[3 * p + q] = R[3 * p] * S2[0] * R[3 * q] + R[3 * p + 1] * S2[1] * R[3 * q + 1] +
+                           R[3 * p + 2] * S2[2] * R[3 * q + 2];
+            num += (S[3 * p + q] - T[3 * p + q]) * (S[3 * p + q] - T[3 * p + q]);
+            den += T[3 * p + q] * T[3 * p + q];
+        }
+    const double dlg_ = lg - (double)a.logit_t[b];
+    a.loss_each[b] = (float)(num / den + dlg_ * dlg_);
+    const double inv = 1.0 / (double)a.n;
+    double G[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) G[t] = 2.0 * (S[t] - T[t]) / den * inv;
+    // Sigma = R diag(S2) R^T
+    double GR[9], RtGR[9];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            GR[3 * p + q] = G[3 * p] * R[q] + G[3 * p + 1] * R[3 + q] + G[3 * p + 2] * R[6 + q];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            RtGR[3 * p + q] = R[p] * GR[q] + R[3 + p] * GR[3 + q] + R[6 + p] * GR[6 + q];
+    double g[9];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) g[3 * p + q] = 2.0 * GR[3 * p + q] * S2[q];
+    double dout[8];
+    dout[0] = 2.0 * S2[0] * RtGR[0];
+    dout[1] = 2.0 * S2[1] * RtGR[4];
+    dout[2] = 2.0 * S2[2] * RtGR[8];
+    const double w = qh[0], x = qh[1], y = qh[2], z = qh[3];
+    double dq[4];
+    dq[0] = 2.0 * (-z * g[1] + y * g[2] + z * g[3] - x * g[5] - y * g[6] + x * g[7]);
+    dq[1] = 2.0 * (y * g[1] + z * g[2] + y * g[3] - 2.0 * x * g[4] - w * g[5] + z * g[6] + w * g[7] -
+                   2.0 * x * g[8]);
+    dq[2] = 2.0 * (-2.0 * y * g[0] + x * g[1] + w * g[2] + x * g[3] + z * g[5] - w * g[6] + z * g[7] -
+                   2.0 * y * g[8]);
+    dq[3] = 2.0 * (-2.0 * z * g[0] - w * g[1] + x * g[2] + w * g[3] - 2.0 * z * g[4] + y * g[5] +
+                   x * g[6] + y * g[7]);
+    const double dot = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) dout[3 + m] = (dq[m] - qh[m] * dot) / qn;
+    dout[7] = 2.0 * dlg_ * inv;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a.dout[8 * b + j] = (float)dout[j];
+#pragma unroll
+    for (int c = 0; c < CO; ++c) {
+        a.a4[b * CO + c] = a4[c];
+        float da = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) da += a.wl[j * CO + c] * (float)dout[j];
+        a.dz4[b * CO + c] = to_bf16(da * dsilu(a.z4[b * CO + c]));
+    }
+}
+
+// head weight gradients: dWl[j][c] += sum_b dout[b][j] a4[b][c]; dbl[j] += sum_b dout[b][j]
+__global__ __launch_bounds__(256) void k_ws_head_grad(const float* __restrict__ dout,
+                                                      const float* __restrict__ a4, int64_t n,
+                                                      float* __restrict__ dwl, float* __restrict__ dbl)
+{
+    const int t = threadIdx.x;  // 256 = 8 x 32
+    const int j = t / CO, c = t % CO;
+    float s = 0.0f, sb = 0.0f;
+    for (int64_t b = 0; b < n; ++b) {
+        s += dout[8 * b + j] * a4[b * CO + c];
+        if (c == 0) sb += dout[8 * b + j];
+    }
+    dwl[j * CO + c] += s;
+    if (c == 0) dbl[j] += sb;
+}
+
+__global__ __launch_bounds__(256) void k_mean(const float* __restrict__ v, int64_t n,
+                                              float* __restrict__ out)
+{
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) acc += v[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = (float)(sh[0] / (double)(n > 0 ? n : 1));
+}
+
+template <class G>
+void conv_fwd(const uint16_t* W, const float* b, const uint16_t* X, int64_t B, float* Z,
+              uint16_t* A, hipStream_t s)
+{
+    const int64_t ntile = B * G::PO / 16;
+    hipLaunchKernelGGL(k_conv_fwd<G>, dim3((unsigned)((ntile + 3) / 4), 2), dim3(256), 0, s, W, b,
+                       X, B, Z, A);
+}
+
+template <class G>
+void conv_bwd_x(const uint16_t* W, const uint16_t* dZ, int64_t B, const float* Zprev,
+                uint16_t* dZprev, hipStream_t s)
+{
+    const int64_t ntile = B * G::PI / 16;
+    hipLaunchKernelGGL(k_conv_bwd_x<G>, dim3((unsigned)((ntile + 3) / 4), 2), dim3(256), 0, s, W,
+                       dZ, B, Zprev, dZprev);
+}
+
+template <class G>
+void conv_bwd_w(const uint16_t* dZ, const uint16_t* X, int64_t B, float* part, float* dW,
+                float* db, hipStream_t s)
+{
+    constexpr int NT = G::KPAD / 16;
+    const int64_t R = B * G::PO;
+    const int64_t nchunk = (R + 255) / 256;
+    hipLaunchKernelGGL(k_conv_bwd_w<G>, dim3((unsigned)((2 * NT + 3) / 4), (unsigned)nchunk),
+                       dim3(256), 0, s, dZ, X, B, part);
+    const int64_t n = (int64_t)CO * G::KPAD;
+    hipLaunchKernelGGL(k_sum_parts_ws, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part,
+                       nchunk, n, dW);
+    hipLaunchKernelGGL(k_bias_grad, dim3(CO), dim3(256), 0, s, dZ, B, G::PO, db);
+}
+
+}  // namespace
+
+int ws_kpad(int layer)
+{
+    switch (layer) {
+    case 1: return G1::KPAD;
+    case 2: return G2::KPAD;
+    case 3: return G3::KPAD;
+    default: return G4::KPAD;
+    }
+}
+
+size_t ws_part_floats(int64_t B)
+{
+    // largest split-K partial buffer over the four layers
+    const int64_t c1 = (B * G1::PO + 255) / 256 * CO * G1::KPAD;
+    const int64_t c2 = (B * G2::PO + 255) / 256 * CO * G2::KPAD;
+    const int64_t c3 = (B * G3::PO + 255) / 256 * CO * G3::KPAD;
+    const int64_t c4 = (B * G4::PO + 255) / 256 * CO * G4::KPAD;
+    int64_t m = c1 > c2 ? c1 : c2;
+    m = m > c3 ? m : c3;
+    m = m > c4 ? m : c4;
+    return (size_t)m;
+}
+
+hipError_t launch_ws_gather(const WsGatherArgs& a, hipStream_t s)
+{
+    const int64_t n = a.n * 3 * 512;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ws_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_ws_forward(const WsNet& net, const uint16_t* X0, int64_t B, const WsActs& w,
+                             const WsHeadArgs& head, hipStream_t s)
+{
+    conv_fwd<G1>(net.w[0], net.b[0], X0, B, w.z[0], w.a[0], s);
+    conv_fwd<G2>(net.w[1], net.b[1], w.a[0], B, w.z[1], w.a[1], s);
+    conv_fwd<G3>(net.w[2], net.b[2], w.a[1], B, w.z[2], w.a[2], s);
+    conv_fwd<G4>(net.w[3], net.b[3], w.a[2], B, w.z[3], w.a[3], s);
+    hipLaunchKernelGGL(k_ws_head, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, head);
+    return hipGetLastError();
+}
+
+hipError_t launch_ws_backward(const WsNet& net, const uint16_t* X0, int64_t B, const WsActs& w,
+                              const WsHeadArgs& head, const WsGrads& g, float* loss, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mean, dim3(1), dim3(256), 0, s, head.loss_each, B, loss);
+    hipLaunchKernelGGL(k_ws_head_grad, dim3(1), dim3(256), 0, s, head.dout, head.a4, B, g.wl, g.bl);
+    // layer 4 (dZ4 written by the head)
+    conv_bwd_w<G4>(w.dz[3], w.a[2], B, w.part, g.w[3], g.b[3], s);
+    conv_bwd_x<G4>(net.w[3], w.dz[3], B, w.z[2], w.dz[2], s);
+    conv_bwd_w<G3>(w.dz[2], w.a[1], B, w.part, g.w[2], g.b[2], s);
+    conv_bwd_x<G3>(net.w[2], w.dz[2], B, w.z[1], w.dz[1], s);
+    conv_bwd_w<G2>(w.dz[1], w.a[0], B, w.part, g.w[1], g.b[1], s);
+    conv_bwd_x<G2>(net.w[1], w.dz[1], B, w.z[0], w.dz[0], s);
+    conv_bwd_w<G1>(w.dz[0], X0, B, w.part, g.w[0], g.b[0], s);
+    return hipGetLastError();
+}

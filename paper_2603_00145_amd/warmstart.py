@@ -1,0 +1,273 @@
+"""Learned warm start: a small 3D convolutional network that predicts, for each Gaussian of a
+devoxelization initialisation, residuals of its log-scale, rotation and intensity from an 8^3
+patch of the registered stacks (kernels in csrc/warm.hip), its training on reconstructions
+produced by the plain method, and the iterations-to-PSNR comparison against the plain
+devoxelization initialisation.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import math
+import sys
+import time
+from typing import List, Optional
+
+import numpy as np
+import torch
+
+from . import _lib, api, inputs, recon
+from ._lib import check, load
+
+KREAL = [81, 864, 864, 256]
+KPAD = [96, 864, 864, 256]
+SHAPES = [(32, 3, 3), (32, 32, 3), (32, 32, 3), (32, 32, 2)]  # (out, in, k)
+
+
+class WarmStartNet:
+    def __init__(self, seed: int = 0, zero_head: bool = True, device="cuda"):
+        dev = torch.device(device)
+        rng = np.random.default_rng(seed)
+        p = {}
+        for l in range(4):
+            w = np.zeros((32, KPAD[l]), np.float32)
+            b = 1.0 / math.sqrt(KREAL[l])
+            w[:, :KREAL[l]] = rng.uniform(-b, b, (32, KREAL[l]))
+            p[f"w{l}"] = w
+            p[f"b{l}"] = rng.uniform(-b, b, 32).astype(np.float32)
+        b = 1.0 / math.sqrt(32)
+        p["wl"] = np.zeros((8, 32), np.float32) if zero_head else rng.uniform(-b, b, (8, 32)).astype(np.float32)
+        p["bl"] = np.zeros(8, np.float32)
+        self.p = {k: torch.from_numpy(v).to(dev).contiguous() for k, v in p.items()}
+        self.g = {k: torch.zeros_like(v) for k, v in self.p.items()}
+        self.m = {k: torch.zeros_like(v) for k, v in self.p.items()}
+        self.v = {k: torch.zeros_like(v) for k, v in self.p.items()}
+        self.bf = {f"w{l}": torch.empty((32, KPAD[l]), dtype=torch.int16, device=dev) for l in range(4)}
+        self.step_no = 0
+        self._ws = None
+        self.sync_bf16()
+
+    def sync_bf16(self):
+        for k, t in self.bf.items():
+            check(load().gm_f32_to_bf16(ctypes.c_void_p(self.p[k].data_ptr()),
+                                        ctypes.c_void_p(t.data_ptr()), t.numel(), api._stream()))
+
+    def struct(self):
+        s = _lib.GmWsNet()
+        for l in range(4):
+            s.w[l] = self.bf[f"w{l}"].data_ptr()
+            s.b[l] = self.p[f"b{l}"].data_ptr()
+        s.wl, s.bl = self.p["wl"].data_ptr(), self.p["bl"].data_ptr()
+        self._s = s
+        return s
+
+    def grads_struct(self):
+        s = _lib.GmWsGrads()
+        for l in range(4):
+            s.w[l] = self.g[f"w{l}"].data_ptr()
+            s.b[l] = self.g[f"b{l}"].data_ptr()
+        s.wl, s.bl = self.g["wl"].data_ptr(), self.g["bl"].data_ptr()
+        return s
+
+    def _workspace(self, n, dev):
+        nb = ctypes.c_size_t()
+        check(load().gm_ws_workspace(n, ctypes.byref(nb)))
+        if self._ws is None or self._ws.numel() * 4 < nb.value:
+            self._ws = torch.empty((nb.value + 3) // 4, dtype=torch.float32, device=dev)
+        return self._ws
+
+    @staticmethod
+    def gather(stacks, stack_data, means: torch.Tensor, spacing: float) -> torch.Tensor:
+        n = means.shape[0]
+        out = torch.empty((n, 3, 512), dtype=torch.int16, device=means.device)
+        cg = (_lib.GmGrid * 3)(*[_lib.grid_struct(s) for s in stacks])
+        check(load().gm_ws_gather(cg, 3, _lib.ptr_array([d.data_ptr() for d in stack_data]),
+                                  ctypes.c_void_p(means.contiguous().data_ptr()), n, float(spacing),
+                                  ctypes.c_void_p(out.data_ptr()), api._stream()))
+        return out
+
+    def forward(self, patches, s0, logit0):
+        """(log_scale, quat, logit) for a batch (n a multiple of 16)."""
+        n = patches.shape[0]
+        dev = patches.device
+        s = torch.empty((n, 3), device=dev)
+        q = torch.empty((n, 4), device=dev)
+        lg = torch.empty((n,), device=dev)
+        ws = self._workspace(n, dev)
+        P = ctypes.c_void_p
+        check(load().gm_ws_forward(ctypes.byref(self.struct()), P(patches.data_ptr()), n,
+                                   P(s0.data_ptr()), P(logit0.data_ptr()), P(s.data_ptr()),
+                                   P(q.data_ptr()), P(lg.data_ptr()), P(ws.data_ptr()),
+                                   ws.numel() * 4, api._stream()))
+        return s, q, lg
+
+    def backward(self, patches, s0, logit0, sig_t, logit_t):
+        n = patches.shape[0]
+        dev = patches.device
+        loss = torch.empty(4, device=dev)
+        ws = self._workspace(n, dev)
+        P = ctypes.c_void_p
+        gs = self.grads_struct()
+        check(load().gm_ws_backward(ctypes.byref(self.struct()), P(patches.data_ptr()), n,
+                                    P(s0.data_ptr()), P(logit0.data_ptr()), P(sig_t.data_ptr()),
+                                    P(logit_t.data_ptr()), P(loss.data_ptr()), ctypes.byref(gs),
+                                    P(ws.data_ptr()), ws.numel() * 4, api._stream()))
+        return loss[0]
+
+    def train_step(self, patches, s0, logit0, sig_t, logit_t, lr=1e-3):
+        for t in self.g.values():
+            t.zero_()
+        loss = self.backward(patches, s0, logit0, sig_t, logit_t)
+        self.step_no += 1
+        for k in self.p:
+            api.adam_step(self.p[k], self.g[k], self.m[k], self.v[k], lr, self.step_no)
+        self.sync_bf16()
+        return loss
+
+    def weights_host(self):
+        """BF16-valued conv weights [O, C, k, k, k] and FP32 head, float64 (for the oracle)."""
+        net = {}
+        for l, (o, c, k) in enumerate(SHAPES):
+            u = self.bf[f"w{l}"].cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+            w = u.view(np.float32).astype(np.float64)[:, :KREAL[l]]
+            net[f"W{l + 1}"] = w.reshape(o, c, k, k, k)
+            net[f"b{l + 1}"] = self.p[f"b{l}"].cpu().numpy().astype(np.float64)
+        net["Wl"] = self.p["wl"].cpu().numpy().astype(np.float64)
+        net["bl"] = self.p["bl"].cpu().numpy().astype(np.float64)
+        return net
+
+
+def sym6(s: torch.Tensor, q: torch.Tensor) -> torch.Tensor:
+    """Covariance (xx, yy, zz, xy, xz, yz) of log-scales s and quaternions q (float64 host
+    math on device tensors; used only to build training targets)."""
+    qn = q / q.norm(dim=1, keepdim=True)
+    w, x, y, z = qn.unbind(1)
+    R = torch.stack([
+        torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
+        torch.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
+        torch.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1)], 1)
+    S = R @ torch.diag_embed(torch.exp(2 * s)) @ R.transpose(1, 2)
+    return torch.stack([S[:, 0, 0], S[:, 1, 1], S[:, 2, 2], S[:, 0, 1], S[:, 0, 2], S[:, 1, 2]], 1)
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_case(n_vox, n_slices, seed, device, bias=True, n_ell=None):
+    """Phantom, three rigidly offset orthogonal stacks (4x thicker slices) and their data."""
+    ss = np.random.SeedSequence(seed)
+    r_ph, r_st, r_noise = [np.random.Generator(np.random.PCG64(s)) for s in ss.spawn(3)]
+    stacks = inputs.orthogonal_stacks(n_vox, n_slices, 1.0, r_st, 2.0, 1.0)
+    ph = inputs.make_phantom(n_vox, n_ell or max(12, n_vox // 3), r_ph, bias=bias, device=device)
+    data = [inputs.simulate_stack(ph, s, r_noise, 0.01) for s in stacks]
+    return stacks, data, ph, inputs.volume_grid(n_vox)
+
+
+def run_experiment(n_train=64, n_test=16, train_vox=128, test_vox=256, g_train=50, g_test=100,
+                   train_iters=200, test_iters=1000, net_steps=1500, batch=1024, lr=1e-3,
+                   psnr_every=10, device="cuda", out: Optional[str] = None):
+    """Train the warm-start network on reconstructions of n_train phantoms (plain method from
+    the devoxelization initialisation), then reconstruct n_test held-out phantoms from the
+    plain and the warm-started initialisation and compare iterations to the plain arm's final
+    PSNR."""
+    t0 = time.time()
+    dev = torch.device(device)
+    # 1. training reconstructions
+    pats, s0s, l0s, sigs, lts = [], [], [], [], []
+    h = 2.0 / g_train
+    for i in range(n_train):
+        stacks, data, ph, vol = make_case(train_vox, train_vox // 4, 4000 + i, dev)
+        p0 = api.devox_init(g_train, stacks, data)
+        init_s = p0.log_scale.clone()
+        init_l = p0.logit.clone()
+        r = recon.Reconstruction(stacks, data, p0, recon.TrainConfig(n_iter=train_iters), vol, None)
+        for _ in range(train_iters):
+            r.step()
+        pats.append(WarmStartNet.gather(stacks, data, r.p.mean, h / 4))
+        s0s.append(init_s)
+        l0s.append(init_l)
+        sigs.append(sym6(r.p.log_scale.double(), r.p.quat.double()).float().contiguous())
+        lts.append(r.p.logit.clone())
+        _say(f"# train case {i + 1}/{n_train} done ({time.time() - t0:.0f}s)")
+    P = torch.cat(pats)
+    S0 = torch.cat(s0s)
+    L0 = torch.cat(l0s)
+    SIG = torch.cat(sigs)
+    LT = torch.cat(lts)
+    # 2. train the network
+    net = WarmStartNet(seed=0)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(0)
+    losses = []
+    for it in range(net_steps):
+        idx = torch.randint(0, P.shape[0], (batch,), device=dev, generator=gen)
+        loss = net.train_step(P[idx].contiguous(), S0[idx].contiguous(), L0[idx].contiguous(),
+                              SIG[idx].contiguous(), LT[idx].contiguous(), lr)
+        if it % 100 == 0 or it == net_steps - 1:
+            losses.append((it, float(loss)))
+            _say(f"# net step {it}: loss {float(loss):.4f} ({time.time() - t0:.0f}s)")
+    del P
+    # 3. held-out comparison
+    h_t = 2.0 / g_test
+    results = []
+    for i in range(n_test):
+        stacks, data, ph, vol = make_case(test_vox, test_vox // 4, 4100 + i, dev)
+        arms = {}
+        for arm in ("plain", "warm"):
+            p0 = api.devox_init(g_test, stacks, data)
+            if arm == "warm":
+                n = p0.n
+                npad = (n + 15) // 16 * 16
+                pad = lambda t: torch.cat([t, t[:npad - n]]) if npad > n else t
+                pt = WarmStartNet.gather(stacks, data, pad(p0.mean).contiguous(), h_t / 4)
+                s, q, lg = net.forward(pt, pad(p0.log_scale).contiguous(), pad(p0.logit).contiguous())
+                p0 = api.GaussParams(p0.mean, q[:n].contiguous(), s[:n].contiguous(), lg[:n].contiguous())
+            r = recon.Reconstruction(stacks, data, p0, recon.TrainConfig(n_iter=test_iters,
+                                                                         psnr_every=psnr_every), vol, ph)
+            hist = r.run()
+            arms[arm] = hist
+            _say(f"# test case {i + 1}/{n_test} {arm}: psnr {hist[0]['psnr']:.2f} -> "
+                 f"{hist[-1]['psnr']:.2f} ({time.time() - t0:.0f}s)")
+        target = arms["plain"][-1]["psnr"]
+        results.append({
+            "case": 4100 + i, "plain_final_psnr": target,
+            "warm_final_psnr": arms["warm"][-1]["psnr"],
+            "plain_init_psnr": arms["plain"][0]["psnr"], "warm_init_psnr": arms["warm"][0]["psnr"],
+            "plain_iters_to_target": recon.iters_to_psnr(arms["plain"], target),
+            "warm_iters_to_target": recon.iters_to_psnr(arms["warm"], target),
+        })
+    reached = [r["warm_iters_to_target"] for r in results if r["warm_iters_to_target"] is not None]
+    summary = {
+        "config": dict(n_train=n_train, n_test=n_test, train_vox=train_vox, test_vox=test_vox,
+                       g_train=g_train, g_test=g_test, train_iters=train_iters,
+                       test_iters=test_iters, net_steps=net_steps, batch=batch, lr=lr),
+        "net_loss": losses, "cases": results,
+        "warm_reached": f"{len(reached)}/{len(results)}",
+        "warm_iters_mean": float(np.mean(reached)) if reached else None,
+        "warm_iters_median": float(np.median(reached)) if reached else None,
+        "plain_iters": test_iters, "seconds": time.time() - t0,
+    }
+    if out:
+        with open(out, "w") as f:
+            json.dump(summary, f, indent=1)
+    return summary
+
+
+if __name__ == "__main__":
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n-train", type=int, default=64)
+    ap.add_argument("--n-test", type=int, default=16)
+    ap.add_argument("--train-vox", type=int, default=128)
+    ap.add_argument("--test-vox", type=int, default=256)
+    ap.add_argument("--g-train", type=int, default=50)
+    ap.add_argument("--g-test", type=int, default=100)
+    ap.add_argument("--train-iters", type=int, default=200)
+    ap.add_argument("--test-iters", type=int, default=1000)
+    ap.add_argument("--net-steps", type=int, default=1500)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    s = run_experiment(a.n_train, a.n_test, a.train_vox, a.test_vox, a.g_train, a.g_test,
+                       a.train_iters, a.test_iters, a.net_steps, out=a.out)
+    print(json.dumps({k: v for k, v in s.items() if k != "cases"}))

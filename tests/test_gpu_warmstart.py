@@ -1,0 +1,110 @@
+"""Warm-start network on MFMA against the FP64 oracle (same BF16-valued weights): patch
+gather, forward outputs and every weight gradient, bar 2e-2 normwise; and a short training run
+reduces its loss."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import warm as owarm
+from paper_2603_00145_amd import inputs
+
+pytestmark = pytest.mark.gpu
+TOL_BF16 = 2e-2
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def normwise(gpu, ref):
+    ref = np.asarray(ref, np.float64)
+    return np.max(np.abs(np.asarray(gpu, np.float64) - ref)) / max(np.max(np.abs(ref)), 1e-30)
+
+
+@pytest.fixture(scope="module")
+def mods():
+    from paper_2603_00145_amd import api, warmstart
+    api.load()
+    return api, warmstart
+
+
+def bf16_to_f64(t):
+    u = t.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    return u.view(np.float32).astype(np.float64)
+
+
+def test_gather_matches_oracle(mods):
+    api, ws = mods
+    w = inputs.workload("c64")
+    rng = np.random.default_rng(0)
+    means = rng.uniform(-0.9, 0.9, (32, 3)).astype(np.float32)
+    got = ws.WarmStartNet.gather(w.stacks, [torch.from_numpy(d).cuda() for d in w.stack_data],
+                                 torch.from_numpy(means).cuda(), 2.0 / 64)
+    ref = owarm.gather(w.stacks, w.stack_data, means, 2.0 / 64).reshape(32, 3, 512)
+    assert normwise(bf16_to_f64(got), ref) <= TOL_BF16
+
+
+def test_forward_and_gradients_match_oracle(mods):
+    api, ws = mods
+    rng = np.random.default_rng(1)
+    n = 48
+    net = ws.WarmStartNet(seed=3, zero_head=False)
+    X = rng.uniform(0, 1, (n, 3, 512)).astype(np.float32)
+    Xb = torch.from_numpy(X).cuda().to(torch.bfloat16).view(torch.int16)
+    s0 = rng.normal(-3.5, 0.1, (n, 3)).astype(np.float32)
+    l0 = rng.normal(0, 0.5, n).astype(np.float32)
+    s_t = rng.normal(-3.5, 0.3, (n, 3))
+    q_t = rng.normal(size=(n, 4))
+    sig = owarm.covariance(s_t, q_t)
+    sig6 = np.stack([sig[:, 0, 0], sig[:, 1, 1], sig[:, 2, 2], sig[:, 0, 1], sig[:, 0, 2], sig[:, 1, 2]], 1)
+    lt = rng.normal(size=n)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+    s, q, lg = net.forward(Xb, T(s0), T(l0))
+    loss = net.backward(Xb, T(s0), T(l0), T(sig6), T(lt))
+    torch.cuda.synchronize()
+    W = net.weights_host()
+    X0 = bf16_to_f64(Xb).reshape(n, 3, 8, 8, 8)
+    out, _, _ = owarm.forward(W, X0)
+    rs, rq, rl = owarm.assemble(out, s0.astype(np.float64), l0.astype(np.float64))
+    for name, a, r in (("log_scale", s, rs), ("quat", q, rq), ("logit", lg, rl)):
+        err = normwise(a.cpu().numpy(), r)
+        say(f"  warm forward {name}: {err:.2e}")
+        assert err <= TOL_BF16
+    L, dout = owarm.loss_grad(out, s0.astype(np.float64), l0.astype(np.float64), sig, lt)
+    assert float(loss) == pytest.approx(L, rel=TOL_BF16)
+    g = owarm.backward(W, X0, dout)
+    got = {f"W{l + 1}": net.g[f"w{l}"].cpu().numpy()[:, :ws.KREAL[l]] for l in range(4)}
+    got.update({f"b{l + 1}": net.g[f"b{l}"].cpu().numpy() for l in range(4)})
+    got["Wl"] = net.g["wl"].cpu().numpy()
+    got["bl"] = net.g["bl"].cpu().numpy()
+    for k in got:
+        err = normwise(got[k], g[k].reshape(got[k].shape))
+        say(f"  warm gradient {k}: {err:.2e}")
+        assert err <= TOL_BF16, k
+
+
+def test_training_reduces_loss(mods):
+    api, ws = mods
+    rng = np.random.default_rng(2)
+    n = 256
+    net = ws.WarmStartNet(seed=0)
+    X = torch.from_numpy(rng.uniform(0, 1, (n, 3, 512)).astype(np.float32)).cuda()
+    Xb = X.to(torch.bfloat16).view(torch.int16)
+    s0 = torch.full((n, 3), -3.5, device="cuda")
+    l0 = torch.zeros(n, device="cuda")
+    # targets that depend on the patch mean: learnable
+    m = X.mean(dim=(1, 2))
+    s_t = (-3.5 + 0.5 * (m - 0.5)).double()[:, None].repeat(1, 3)
+    q_t = torch.zeros((n, 4), dtype=torch.float64, device="cuda")
+    q_t[:, 0] = 1
+    sig6 = ws.sym6(s_t, q_t).float().contiguous()
+    lt = (2 * (m - 0.5)).contiguous()
+    first = None
+    for it in range(200):
+        loss = float(net.train_step(Xb, s0, l0, sig6, lt, lr=3e-3))
+        first = loss if first is None else first
+    say(f"  warm training loss {first:.4f} -> {loss:.4f}")
+    assert loss < 0.5 * first

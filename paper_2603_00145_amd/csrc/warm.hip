@@ -82,7 +82,9 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ W
                       ix = G::ST * ox - G::PD + kx;
             const bool ok = k < G::KREAL && iz >= 0 && iz < G::DI && iy >= 0 && iy < G::DI &&
                             ix >= 0 && ix < G::DI;
-            bv[j] = ok ? (short)xb[c * G::PI + (iz * G::DI + iy) * G::DI + ix] : (short)0;
+            const int idx = ok ? c * G::PI + (iz * G::DI + iy) * G::DI + ix : 0;  // always valid
+            const short v = (short)xb[idx];
+            bv[j] = ok ? v : (short)0;
         }
         v4s Bf;
         Bf.x = bv[0]; Bf.y = bv[1]; Bf.z = bv[2]; Bf.w = bv[3];
@@ -135,8 +137,9 @@ __global__ __launch_bounds__(256) void k_conv_bwd_x(const uint16_t* __restrict__
             const bool ok = tz >= 0 && ty >= 0 && tx >= 0 && tz % G::ST == 0 && ty % G::ST == 0 &&
                             tx % G::ST == 0 && tz / G::ST < G::DO && ty / G::ST < G::DO &&
                             tx / G::ST < G::DO;
-            bv[j] = ok ? (short)dzb[o * G::PO + ((tz / G::ST) * G::DO + ty / G::ST) * G::DO + tx / G::ST]
-                       : (short)0;
+            const int idx = ok ? o * G::PO + ((tz / G::ST) * G::DO + ty / G::ST) * G::DO + tx / G::ST : 0;
+            const short v = (short)dzb[idx];
+            bv[j] = ok ? v : (short)0;
         }
         v4s Af, Bf;
         Af.x = av[0]; Af.y = av[1]; Af.z = av[2]; Af.w = av[3];
@@ -186,7 +189,9 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__
                       ix = G::ST * ox - G::PD + kx;
             const bool ok = kvalid && iz >= 0 && iz < G::DI && iy >= 0 && iy < G::DI && ix >= 0 &&
                             ix < G::DI;
-            bv[j] = ok ? (short)X[(b * G::CI + c) * G::PI + (iz * G::DI + iy) * G::DI + ix] : (short)0;
+            const int64_t idx = ok ? (b * G::CI + c) * G::PI + (iz * G::DI + iy) * G::DI + ix : 0;
+            const short v = (short)X[idx];
+            bv[j] = ok ? v : (short)0;
         }
         v4s Af, Bf;
         Af.x = av[0]; Af.y = av[1]; Af.z = av[2]; Af.w = av[3];

@@ -54,6 +54,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-voxels", type=int, default=4096)
     ap.add_argument("--cpu-sample-gauss", type=int, default=100000)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB before timing")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only (this build has no multi-GPU path); "
@@ -81,35 +83,45 @@ def main():
     print(f"# setup {time.time() - t0:.1f}s: {p.n} Gaussians, stacks "
           f"{[g.shape for g in stacks]}", file=sys.stderr, flush=True)
 
-    ev = {k: [] for k in ("bin", "render", "loss", "backward", "adam")}
+    if args.calib_copy_mib > 0:
+        # a plain streaming kernel of known traffic (reads N bytes, writes N bytes), for
+        # scaling the HBM byte counters of a profile; torch's copy_ would go to a DMA engine
+        src = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
+    # stage -> events; every stage is timed on the stream its kernels are launched on
+    stages = ("bin", "render", "loss", "partials", "chain", "adam")
+    ev = {k: [] for k in stages}
     step_no = [0]
+    pair_log = []
 
     def step(record):
         s = torch.cuda.current_stream()
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(6)] if record else None
-        if record:
-            e[0].record(s)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)] if record else None
+        mark = (lambda i: e[i].record(s)) if record else (lambda i: None)
+        mark(0)
         bins.bin(p)
         if record:
-            e[1].record(s)
-        api.render(bins, ids, outs)
-        if record:
-            e[2].record(s)
+            pair_log.append(sum(bins.box_pairs_host))   # reported by gm_bin, no extra sync
+        mark(1)
+        api.render(bins, ids, outs)                      # k_render
+        mark(2)
         loss, _ = api.smooth_l1(outs, targets, dls)
         for t in grads.tensors():
             t.zero_()
-        if record:
-            e[3].record(s)
-        api.backward(p, bins, ids, dls, grads, 0.1, 1.5)
-        if record:
-            e[4].record(s)
+        mark(3)
+        api.grid_partials(p, bins, ids, dls)              # k_partials
+        mark(4)
+        api.chain(p, bins, ids, grads, 0.1, 1.5)          # k_chain (+ anisotropy)
+        mark(5)
         step_no[0] += 1
         for prm, gr, mm, vv, lr in zip(p.tensors(), grads.tensors(), m.tensors(), v.tensors(), lrs):
             api.adam_step(prm, gr, mm, vv, lr, step_no[0])
-        if record:
-            e[5].record(s)
-            return e, loss
-        return None, loss
+        mark(6)
+        return e, loss
 
     for _ in range(args.warmup):
         step(False)
@@ -131,19 +143,22 @@ def main():
             ev[k].append(a.elapsed_time(b))
     stage_ms = {k: float(np.mean(x)) for k, x in ev.items()}
 
-    pairs = bins.pair_count()           # contributing (Gaussian, voxel) pairs on the stacks
+    # contributing (Gaussian, voxel) pairs on the stacks, mean over the timed steps (the
+    # Gaussians move, so the count changes from step to step)
+    pairs = float(np.mean(pair_log))
     tile_pairs = bins.n_pairs
-    value = pairs / (ms_step / 1e3)
+    value = sum(pair_log) / (total_ms / 1e3)
+    bwd_ms = stage_ms["partials"] + stage_ms["chain"]
     fwd_rate = pairs / (stage_ms["render"] / 1e3)
-    bwd_rate = pairs / (stage_ms["backward"] / 1e3)
-    # dominant kernel and its roofline
-    dom = "render" if stage_ms["render"] >= stage_ms["backward"] else "backward"
+    bwd_rate = pairs / (bwd_ms / 1e3)
+    # dominant kernel (one launch per step each) and its roofline
+    dom = "render" if stage_ms["render"] >= stage_ms["partials"] else "partials"
     if dom == "render":
         flop, instr = FLOP_FWD, FWD_VALU_INSTR + EXP_SLOTS
         kname = "k_render"
     else:
         flop, instr = FLOP_BWD, 2 * FWD_VALU_INSTR + EXP_SLOTS
-        kname = "k_partials+k_chain"
+        kname = "k_partials"
     achieved = flop * pairs / (stage_ms[dom] / 1e3) / 1e12
     peak = alu_peak_tflops(flop, instr)
 
@@ -162,7 +177,7 @@ def main():
                    "tile": list(api._lib.tile_dims())},
         "pairs_per_step": pairs, "tile_pairs": tile_pairs,
         "stage_ms": stage_ms, "fwd_evals_per_s": fwd_rate, "bwd_evals_per_s": bwd_rate,
-        "fwd_bwd_evals_per_s": pairs / ((stage_ms["render"] + stage_ms["backward"]) / 1e3),
+        "fwd_bwd_evals_per_s": pairs / ((stage_ms["render"] + bwd_ms) / 1e3),
         "final_loss": float(loss),
         "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,

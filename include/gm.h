@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define GM_ABI_VERSION 1
+#define GM_ABI_VERSION 2
 #define GM_MAX_GRIDS 8
 #define GM_RECORD_FLOATS 16       /* floats per (grid, Gaussian) record                */
 #define GM_GRID_GRAD_FLOATS 10    /* floats per (grid, Gaussian) backward partial      */
@@ -98,9 +98,11 @@ typedef struct gm_bin_opts {
  *   box_volume  [n_grids] int64: sum of box volumes = contributing (Gaussian, voxel) pairs
  *   tile_start  [total_tiles + 1] int32: CSR row starts of the per-tile lists
  *   pair_gauss  [capacity_pairs] int32: Gaussian ids grouped by tile, ascending per tile
- *   grid_grads  [n_grids][n_gauss][10] float: written by gm_backward (grid-frame partials
- *               d amp, d c(3), d K(6))
- *   scratch     scratch_bytes of device memory for sorting                              */
+ *   grid_grads  [n_grids][n_gauss][10] float: written by gm_backward / gm_grid_partials
+ *               (grid-frame partials d amp, d c(3), d K(6))
+ *   scratch     scratch_bytes of device memory: sorting workspace, and the per-grid
+ *               spatial order of the Gaussians that gm_bin writes and gm_backward /
+ *               gm_grid_partials read (leave it untouched between those calls)           */
 typedef struct gm_bins {
     int32_t n_grids;
     int32_t reserved;
@@ -117,7 +119,12 @@ typedef struct gm_bins {
     /* [host] filled by gm_bin */
     gm_grid grids[GM_MAX_GRIDS];
     int64_t tile_base[GM_MAX_GRIDS + 1]; /* global tile id of each grid's first tile */
-    int64_t n_pairs;                     /* (tile, Gaussian) pairs of the last gm_bin   */
+    int64_t n_pairs;                     /* (tile, Gaussian) pairs of the last gm_bin;
+                                            set it < 0 when allocating: gm_backward and
+                                            gm_grid_partials refuse bins gm_bin has not
+                                            filled                                       */
+    int64_t box_pairs[GM_MAX_GRIDS];     /* contributing (Gaussian, voxel) pairs per grid
+                                            of the last gm_bin (= box_volume)            */
     double cutoff_sigma;
 } gm_bins;
 
@@ -236,6 +243,24 @@ gm_status gm_aniso_reg(const gm_gaussians* g, float lambda_r, float* value, void
 gm_status gm_backward(const gm_gaussians* g, const gm_bins* bins, const int32_t* grid_ids,
                       int32_t n_ids, const float* const* dl_di, float lambda_aniso,
                       float lambda_r, gm_gaussian_grads* grad, gm_stream stream);
+
+/* First stage of gm_backward alone (Sec. 3.5): for every Gaussian and listed grid, the ten
+ * sums over its box of the derivatives of sum_v dl_di[k][v] I_k[v] with respect to the
+ * record's amplitude (1), centre (3) and the six distinct entries of its conic K as a
+ * symmetric matrix (xx yy zz xy xz yz), written (overwritten) to
+ * bins->grid_grads[grid][i][10].  These per-grid quantities are also where an update of the
+ * stacks' rigid placements would start from. */
+gm_status gm_grid_partials(const gm_gaussians* g, const gm_bins* bins,
+                           const int32_t* grid_ids, int32_t n_ids, const float* const* dl_di,
+                           gm_stream stream);
+
+/* Second stage of gm_backward alone: pulls bins->grid_grads of the listed grids (as written
+ * by gm_grid_partials for the same grid_ids) back to (mean, quat, log_scale, logit) in FP64,
+ * sums over grids, adds lambda_aniso times the anisotropy gradient (Eq. 13) and ACCUMULATES
+ * (+=) into grad.  gm_grid_partials followed by gm_chain is exactly gm_backward. */
+gm_status gm_chain(const gm_gaussians* g, const gm_bins* bins, const int32_t* grid_ids,
+                   int32_t n_ids, float lambda_aniso, float lambda_r, gm_gaussian_grads* grad,
+                   gm_stream stream);
 
 /* Adam (Sec. 4.1.4; PyTorch arrangement, no weight decay) on n float32 elements in place:
  * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;

@@ -8,6 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgm.so")
 
 GM_MAX_GRIDS = 8
+ABI_VERSION = 2          # struct layouts of include/gm.h this binding mirrors
 GM_RECORD_FLOATS = 16
 GM_GRID_GRAD_FLOATS = 10
 GM_REDUCE_WORKSPACE_BYTES = 16384
@@ -53,7 +54,8 @@ class GmBins(ctypes.Structure):
                 ("scratch_bytes", ctypes.c_size_t),
                 ("grids", GmGrid * GM_MAX_GRIDS),
                 ("tile_base", ctypes.c_int64 * (GM_MAX_GRIDS + 1)),
-                ("n_pairs", ctypes.c_int64), ("cutoff_sigma", ctypes.c_double)]
+                ("n_pairs", ctypes.c_int64), ("box_pairs", ctypes.c_int64 * GM_MAX_GRIDS),
+                ("cutoff_sigma", ctypes.c_double)]
 
 
 class GmNrfGrads(ctypes.Structure):
@@ -99,6 +101,12 @@ _SIGS = [
                                     ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
                                     ctypes.POINTER(P), ctypes.c_float, ctypes.c_float,
                                     ctypes.POINTER(GmGrads), P]),
+    ("gm_grid_partials", ctypes.c_int, [ctypes.POINTER(GmGaussians), ctypes.POINTER(GmBins),
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                         ctypes.POINTER(P), P]),
+    ("gm_chain", ctypes.c_int, [ctypes.POINTER(GmGaussians), ctypes.POINTER(GmBins),
+                                 ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_float,
+                                 ctypes.c_float, ctypes.POINTER(GmGrads), P]),
     ("gm_adam_step", ctypes.c_int, [P, P, P, P, ctypes.c_int64, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_int32, P]),
@@ -140,8 +148,8 @@ def load(path: str = LIB_PATH):
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
-    if lib.gm_abi_version() != 1:
-        raise RuntimeError("libgm ABI version mismatch")
+    if lib.gm_abi_version() != ABI_VERSION:
+        raise RuntimeError(f"libgm ABI version {lib.gm_abi_version()}, binding expects {ABI_VERSION}")
     _lib = lib
     return lib
 

@@ -120,7 +120,11 @@ class Bins:
         self.capacity = cap
 
     def struct(self) -> _lib.GmBins:
-        b = self._s if hasattr(self, "_s") else _lib.GmBins()
+        if hasattr(self, "_s"):
+            b = self._s
+        else:
+            b = _lib.GmBins()
+            b.n_pairs = -1       # not yet filled by gm_bin
         b.n_grids = len(self.grids)
         b.n_gauss = self.n
         b.capacity_pairs = self.capacity
@@ -166,8 +170,15 @@ class Bins:
         return r[:, 10:13], r[:, 13:16]
 
     def pair_count(self, k: Optional[int] = None) -> int:
+        """Contributing (Gaussian, voxel) pairs of the last bin() (read from the device)."""
         v = self.box_volume[:len(self.grids)].cpu()
         return int(v.sum()) if k is None else int(v[k])
+
+    @property
+    def box_pairs_host(self) -> List[int]:
+        """Contributing pairs per grid of the last bin(), as gm_bin reported them (no device
+        access)."""
+        return [int(self._s.box_pairs[k]) for k in range(len(self.grids))]
 
 
 def render(bins: Bins, ids: Sequence[int], outs: Optional[List[torch.Tensor]] = None):
@@ -204,6 +215,28 @@ def backward(g: GaussParams, bins: Bins, ids: Sequence[int], dl_di: Sequence[tor
     check(load().gm_backward(ctypes.byref(gs), ctypes.byref(bins.struct()), idarr, len(ids),
                              ptr_array([t.data_ptr() for t in dl_di]), float(lambda_aniso),
                              float(lambda_r), ctypes.byref(gr), _stream()))
+    return grads
+
+
+def grid_partials(g: GaussParams, bins: Bins, ids: Sequence[int], dl_di: Sequence[torch.Tensor]):
+    """gm_grid_partials: the first stage of backward(); fills bins.grid_grads for ids."""
+    for t in dl_di:
+        _need(t, torch.float32, "dl_di")
+    idarr = (ctypes.c_int32 * max(1, len(ids)))(*ids)
+    gs = g.struct()
+    check(load().gm_grid_partials(ctypes.byref(gs), ctypes.byref(bins.struct()), idarr, len(ids),
+                                  ptr_array([t.data_ptr() for t in dl_di]), _stream()))
+    return bins.grid_grads
+
+
+def chain(g: GaussParams, bins: Bins, ids: Sequence[int], grads: GaussParams,
+          lambda_aniso: float = 0.0, lambda_r: float = 1.5):
+    """gm_chain: the second stage of backward(); accumulates (+=) into grads."""
+    idarr = (ctypes.c_int32 * max(1, len(ids)))(*ids)
+    gs = g.struct()
+    gr = grads.grad_struct()
+    check(load().gm_chain(ctypes.byref(gs), ctypes.byref(bins.struct()), idarr, len(ids),
+                          float(lambda_aniso), float(lambda_r), ctypes.byref(gr), _stream()))
     return grads
 
 

@@ -1,12 +1,16 @@
 // K7 + K8: gradients of L = sum_k sum_v dL/dI_k[v] I_k[v] (+ lambda_aniso * L_aniso,
 // Eq. 12-13) with respect to every Gaussian parameter, boxes held fixed.
 //
-// K7 (grid-frame partials): half a wavefront per Gaussian gathers dL/dI over the voxels of
-// the Gaussian's box on each listed grid, recomputing w = amp 2^Q (no per-voxel
-// contributions are stored), and forms per lane the sums
-//     d amp = sum g 2^Q,   d c = -sum g w ln2 dQ/ddelta,   d K_ab = sum g w ln2 delta_a delta_b
-// which are then reduced across the half-wavefront with DPP before one store per (grid,
-// Gaussian).  No global atomics are needed: each Gaussian's sums are owned by 32 lanes.
+// K7 (grid-frame partials): half a wavefront per Gaussian gathers g = dL/dI over the voxels
+// of the Gaussian's box on each listed grid, recomputing E = 2^Q (no per-voxel
+// contributions are stored).  With delta = v - c, Q = delta^T K delta (K the record's
+// base-2 conic as a symmetric matrix) and w = amp E, the ten grid-frame partials are
+//     d amp = sum g E,   d c = -2 amp ln2 K m,   d K_ab = amp ln2 m_ab
+// with the weighted moments m = sum g E delta and m_ab = sum g E delta_a delta_b.  A lane
+// owns one (x, y) column of the box at a time and walks it along z, summing g E, g E dz and
+// g E dz^2; the column's share of the ten moments follows from those three sums and its
+// (dx, dy).  The moments are reduced across the half-wavefront with DPP and turned into the
+// partials once per (grid, Gaussian).  No global atomics are needed.
 //
 // K8 (chain rule, FP64): thread per Gaussian.  The partials of every grid are pulled back
 // through c = L mu + t, C = Sigma_g^-1, amp = alpha sqrt(det Sigma_idx / det Sigma_g),
@@ -37,21 +41,28 @@ __device__ __forceinline__ float half_sum(float v)
     return v;
 }
 
-// Two Gaussians per wavefront, one per 32-lane half.  A half maps its lanes onto chunks of
-// 32 (x, y) positions of the Gaussian's box and walks the box along z; the exponent Q and
-// its gradient t = Ks delta (Ks the symmetric base-2 conic, Q = delta^T Ks delta) change by
-// constants per z step, so each voxel costs a few adds, one exp2 and the ten sums.
-__global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
+// Two Gaussians per wavefront, one per 32-lane half, taken in the spatial order gm_bin
+// produced for the grid (neighbouring Gaussians run together, and on one XCD, so the dL/dI
+// they gather is served from the same L2 lines).  A half maps its lanes onto chunks of
+// 32 (x, y) columns of the Gaussian's box.  Each column is walked along z four steps at a
+// time: the four dL/dI values are loaded first, then each step costs two FMAs for Q, one
+// exp2 and four FMAs for the column sums.  Steps past a lane's column (or past its half's
+// box) load 0 and add exact zeros, so the arithmetic needs no per-step predication.
+__global__ __launch_bounds__(256) void k_partials(const BackwardArgs a, int blocks_per_grid)
 {
     const int lane = threadIdx.x & 63;
     const int hl = lane & 31;
-    const int64_t first = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 2;
+    const int lin = xcd_remap(blockIdx.x, gridDim.x);
+    const int kk = lin / blocks_per_grid;                  // listed grid
+    const int64_t first = ((int64_t)(lin - kk * blocks_per_grid) * 4 + (threadIdx.x >> 6)) * 2;
     if (first >= a.n) return;  // wave-uniform: both halves past the end
-    const int64_t gid = first + (lane >> 5);
-    const bool gvalid = gid < a.n;
-#pragma unroll 1
-    for (int k = 0; k < a.n_ids; ++k) {
-        const int gi = a.grid_index[k];
+    const int64_t slot = first + (lane >> 5);
+    const bool gvalid = slot < a.n;
+    {
+        const int gi = a.grid_index[kk];
+        // clamped so that even an order the caller never let gm_bin fill cannot index out
+        // of bounds
+        const int64_t gid = gvalid ? min((int64_t)a.order[(size_t)gi * a.n + slot], a.n - 1) : 0;
         float4 r0 = make_float4(0, 0, 0, 0), r1 = r0, r2 = r0, r3 = r0;
         if (gvalid) {
             const float4* rp = reinterpret_cast<const float4*>(a.records + ((size_t)gi * a.n + gid) * 16);
@@ -63,25 +74,28 @@ __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
         const int lox = __float_as_int(r2.z), loy = __float_as_int(r2.w), loz = __float_as_int(r3.x);
         const int hix = __float_as_int(r3.y), hiy = __float_as_int(r3.z), hiz = __float_as_int(r3.w);
         const bool nonempty = gvalid && lox <= hix && loy <= hiy && loz <= hiz;
+        // an empty box (including an invalid Gaussian) contributes nothing; its record's
+        // floats are replaced by zeros so that nothing non-finite enters the sums
         const int wx = nonempty ? hix - lox + 1 : 1;
         const int wy = nonempty ? hiy - loy + 1 : 0;
         const int wz = nonempty ? hiz - loz + 1 : 0;
+        const float cx = nonempty ? r0.x : 0.0f, cy = nonempty ? r0.y : 0.0f;
+        const float cz = nonempty ? r0.z : 0.0f;
+        const float kxx = nonempty ? r1.x : 0.0f, kyy = nonempty ? r1.y : 0.0f;
+        const float kzz = nonempty ? r1.z : 0.0f, kxy = nonempty ? r1.w : 0.0f;
+        const float kxz = nonempty ? r2.x : 0.0f, kyz = nonempty ? r2.y : 0.0f;
         const int fp = wx * wy;                       // (x, y) footprint of the box
         const int chunks = (fp + 31) >> 5;
         const int max_chunks = max(__builtin_amdgcn_readlane(chunks, 0),
                                    __builtin_amdgcn_readlane(chunks, 32));
         const int max_wz = max(__builtin_amdgcn_readlane(wz, 0), __builtin_amdgcn_readlane(wz, 32));
-        const float cx = r0.x, cy = r0.y, cz = r0.z;
-        const float A2 = 2.0f * r0.w * GM_LN2F;        // d(amp 2^Q)/dQ = amp ln2 2^Q; t = dQ/2
-        const float sxx = r1.x, syy = r1.y, szz = r1.z;
-        const float sxy = 0.5f * r1.w, sxz = 0.5f * r2.x, syz = 0.5f * r2.y;
         const float inv_wx = 1.0f / (float)wx;
-        const int nx = a.nx[k], ny = a.ny[k];
+        const int nx = a.nx[kk], ny = a.ny[kk];
         const int nxy = nx * ny;
-        const float* __restrict__ g = a.dl_di[k];
-        float s[10];
-#pragma unroll
-        for (int t = 0; t < 10; ++t) s[t] = 0.0f;
+        const float* __restrict__ g = a.dl_di[kk];
+        // weighted moments: m0 = sum gE, m1 = sum gE delta, m2 = sum gE delta delta^T
+        float m0 = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f;
+        float mxx = 0.0f, myy = 0.0f, mzz = 0.0f, mxy = 0.0f, mxz = 0.0f, myz = 0.0f;
 #pragma unroll 1
         for (int c = 0; c < max_chunks; ++c) {
             const int f = c * 32 + hl;
@@ -89,51 +103,68 @@ __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
             const int y = (int)(((float)f + 0.5f) * inv_wx);
             const int x = f - y * wx;
             const float dx = (float)x - cx, dy = (float)y - cy;
-            float dz = -cz;
-            float tx = sxx * dx + sxy * dy + sxz * dz;
-            float ty = sxy * dx + syy * dy + syz * dz;
-            float tz = sxz * dx + syz * dy + szz * dz;
-            float Q = dx * tx + dy * ty + dz * tz;
-            int addr = (loz * ny + (loy + y)) * nx + (lox + x);  // grids hold < 2^31 voxels
-            float gnext = (act && wz > 0) ? g[addr] : 0.0f;  // loaded one z step ahead
+            const float qxy = dx * (kxx * dx + kxy * dy) + dy * (kyy * dy);
+            const float bz = kxz * dx + kyz * dy;
+            const int nz_col = act ? wz : 0;             // z steps this lane loads
+            const int base = (loz * ny + (loy + y)) * nx + (lox + x);  // grids hold < 2^31 voxels
+            float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
 #pragma unroll 1
-            for (int z = 0; z < max_wz; ++z) {
-                const float gv = gnext;
-                addr += nxy;
-                if (act && z + 1 < wz) gnext = g[addr];
-                if (act && z < wz) {
-                    const float E = __builtin_amdgcn_exp2f(Q);
-                    const float ge = gv * E;
-                    const float gw = ge * A2;
-                    s[0] += ge;
-                    s[1] -= gw * tx;
-                    s[2] -= gw * ty;
-                    s[3] -= gw * tz;
-                    const float hx = 0.5f * gw * dx, hy = 0.5f * gw * dy, hz = 0.5f * gw * dz;
-                    s[4] += hx * dx;
-                    s[5] += hy * dy;
-                    s[6] += hz * dz;
-                    s[7] += hx * dy;
-                    s[8] += hx * dz;
-                    s[9] += hy * dz;
-                }
-                // step one voxel along z
-                Q += 2.0f * tz + szz;
-                tx += sxz;
-                ty += syz;
-                tz += szz;
-                dz += 1.0f;
-            }
-        }
+            for (int z0 = 0; z0 < max_wz; z0 += 4) {
+                float gv[4];
 #pragma unroll
-        for (int t = 0; t < 10; ++t) s[t] = half_sum(s[t]);
+                for (int u = 0; u < 4; ++u) {
+                    gv[u] = 0.0f;
+                    if (z0 + u < nz_col) gv[u] = g[base + (z0 + u) * nxy];
+                }
+                const float dz0 = (float)z0 - cz;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (z0 + u < max_wz) {
+                        const float dz = dz0 + (float)u;
+                        const float Q = qxy + dz * (bz + kzz * dz);
+                        const float ge = gv[u] * __builtin_amdgcn_exp2f(Q);
+                        const float t = ge * dz;
+                        s0 += ge;
+                        s1 += t;
+                        s2 += t * dz;
+                    }
+                }
+            }
+            const float ax = s0 * dx, ay = s0 * dy;
+            m0 += s0;
+            mx += ax;
+            my += ay;
+            mz += s1;
+            mxx += ax * dx;
+            myy += ay * dy;
+            mxy += ax * dy;
+            mxz += s1 * dx;
+            myz += s1 * dy;
+            mzz += s2;
+        }
+        m0 = half_sum(m0);
+        mx = half_sum(mx);
+        my = half_sum(my);
+        mz = half_sum(mz);
+        mxx = half_sum(mxx);
+        myy = half_sum(myy);
+        mzz = half_sum(mzz);
+        mxy = half_sum(mxy);
+        mxz = half_sum(mxz);
+        myz = half_sum(myz);
         if (hl == 31 && gvalid) {
+            // K as a full symmetric matrix has off-diagonal entries kxy/2, kxz/2, kyz/2
+            const float A = (nonempty ? r0.w : 0.0f) * GM_LN2F;   // amp ln2
+            const float hxy = 0.5f * kxy, hxz = 0.5f * kxz, hyz = 0.5f * kyz;
+            const float tx = kxx * mx + hxy * my + hxz * mz;
+            const float ty = hxy * mx + kyy * my + hyz * mz;
+            const float tz = hxz * mx + hyz * my + kzz * mz;
             float2* o = reinterpret_cast<float2*>(a.grid_grads + ((size_t)gi * a.n + gid) * 10);
-            o[0] = make_float2(s[0], s[1]);
-            o[1] = make_float2(s[2], s[3]);
-            o[2] = make_float2(s[4], s[5]);
-            o[3] = make_float2(s[6], s[7]);
-            o[4] = make_float2(s[8], s[9]);
+            o[0] = make_float2(m0, -2.0f * A * tx);
+            o[1] = make_float2(-2.0f * A * ty, -2.0f * A * tz);
+            o[2] = make_float2(A * mxx, A * myy);
+            o[3] = make_float2(A * mzz, A * mxy);
+            o[4] = make_float2(A * mxz, A * myz);
         }
     }
 }
@@ -294,8 +325,10 @@ __global__ __launch_bounds__(128) void k_chain(const ChainArgs a)
 hipError_t launch_backward_partials(const BackwardArgs& a, hipStream_t s)
 {
     if (a.n == 0 || a.n_ids == 0) return hipSuccess;
-    const int64_t blocks = (a.n + 7) / 8;  // 4 wavefronts x 2 Gaussians per block
-    hipLaunchKernelGGL(k_partials, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    const int64_t per_grid = (a.n + 7) / 8;  // 4 wavefronts x 2 Gaussians per block
+    const int64_t blocks = per_grid * a.n_ids;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_partials, dim3((unsigned)blocks), dim3(256), 0, s, a, (int)per_grid);
     return hipGetLastError();
 }
 

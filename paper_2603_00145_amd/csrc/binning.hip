@@ -126,6 +126,38 @@ __global__ __launch_bounds__(256) void k_emit(const EmitArgs a)
             }
 }
 
+// ---- spatial order of the Gaussians per grid ---------------------------------------------
+// Bucket of (grid k, Gaussian): grid k owns buckets [tile_base_k + k, tile_base_{k+1} + k],
+// one per tile plus a last one for empty boxes, so grid k's n Gaussians land in slots
+// [k n, (k + 1) n) of the order.
+__device__ __forceinline__ int64_t home_bucket(const HomeArgs& a, int k, int64_t idx)
+{
+    const GridConst& G = a.g[k];
+    const int* rec = reinterpret_cast<const int*>(a.records + idx * 16);
+    const int lx = rec[10], ly = rec[11], lz = rec[12], hx = rec[13], hy = rec[14], hz = rec[15];
+    const int64_t b0 = G.tile_base + k;
+    if (lx > hx || ly > hy || lz > hz) return b0 + (int64_t)G.ntx * G.nty * G.ntz;
+    return b0 + ((int64_t)(lz / GM_TZ) * G.nty + ly / GM_TY) * G.ntx + lx / GM_TX;
+}
+
+__global__ __launch_bounds__(256) void k_home_hist(const HomeArgs a)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)a.n_grids * a.n) return;
+    const int k = (int)(idx / a.n);
+    atomicAdd(&a.hist[home_bucket(a, k, idx)], 1u);
+}
+
+__global__ __launch_bounds__(256) void k_home_scatter(const HomeArgs a)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)a.n_grids * a.n) return;
+    const int k = (int)(idx / a.n);
+    const int64_t slot = (int64_t)atomicAdd(
+        reinterpret_cast<unsigned long long*>(&a.cursor[home_bucket(a, k, idx)]), 1ull);
+    a.order[slot] = (uint32_t)(idx - (int64_t)k * a.n);
+}
+
 // ---- radix sort --------------------------------------------------------------------------
 constexpr int RS_THREADS = 256;
 constexpr int RS_WAVES = RS_THREADS / 64;
@@ -223,6 +255,17 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* keys, int64
     start[t] = (int32_t)lo;
 }
 
+// One thread per grid: copy the box-volume totals accumulated in the scratch report block
+// to the caller's box_volume array, and the scan's grand total next to them, so that gm_bin
+// reads everything it reports back in one device-to-host copy.
+__global__ void k_bin_report(BinReport* rep, const int64_t* scan_end, int64_t* box_volume,
+                             int n_grids)
+{
+    const int k = threadIdx.x;
+    if (k < n_grids) box_volume[k] = (int64_t)rep->box_volume[k];
+    if (k == 0) rep->total = *scan_end;
+}
+
 inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
@@ -233,6 +276,13 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s
     unsigned nb = grid_for(n, 256);
     if (nb > 4096) nb = 4096;
     hipLaunchKernelGGL(k_fill_u32, dim3(nb), dim3(256), 0, s, p, value, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_report(BinReport* rep, const int64_t* scan_end, int64_t* box_volume,
+                             int n_grids, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bin_report, dim3(1), dim3(64), 0, s, rep, scan_end, box_volume, n_grids);
     return hipGetLastError();
 }
 
@@ -271,6 +321,27 @@ hipError_t launch_emit(const EmitArgs& a, hipStream_t s)
     const int64_t total = (int64_t)a.n_grids * a.n;
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_emit, dim3(grid_for(total, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+int64_t home_buckets(const GridConst* g, int32_t n_grids)
+{
+    int64_t b = 0;
+    for (int k = 0; k < n_grids; ++k) b += (int64_t)g[k].ntx * g[k].nty * g[k].ntz + 1;
+    return b;
+}
+
+hipError_t launch_home_order(const HomeArgs& a, void* scan_ws, hipStream_t s)
+{
+    const int64_t total = (int64_t)a.n_grids * a.n;
+    const int64_t nb = home_buckets(a.g, a.n_grids);
+    hipError_t e = launch_fill_u32(a.hist, 0u, nb, s);
+    if (e != hipSuccess || total == 0) return e;
+    hipLaunchKernelGGL(k_home_hist, dim3(grid_for(total, 256)), dim3(256), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = launch_scan_i32_to_i64(reinterpret_cast<const int32_t*>(a.hist), a.cursor, nb, scan_ws, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_home_scatter, dim3(grid_for(total, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -92,30 +92,39 @@ int64_t grid_tiles(const gm_grid& g)
 
 // scratch layout of gm_bins
 struct BinScratch {
+    uint32_t* order;    // [n_grids * n] backward processing order; first, so that its
+                        // address does not depend on the other sizes
+    uint32_t* home_hist;      // [n_buckets]
+    int64_t* home_cursor;     // [n_buckets + 1]
     int64_t* offsets;   // [n_grids * n + 1]
     void* scan_ws;
     uint32_t* keys0;
     uint32_t* keys1;
     uint32_t* vals0;
     void* radix_ws;
-    uint32_t* flags;
+    BinReport* report;
     size_t bytes;
 };
 
-BinScratch scratch_layout(char* base, int64_t n, int32_t n_grids, int64_t cap)
+// n_buckets = total tiles + n_grids (the spatial-order buckets, one per tile plus one per
+// grid for empty boxes).
+BinScratch scratch_layout(char* base, int64_t n, int32_t n_grids, int64_t cap, int64_t n_buckets)
 {
     BinScratch s;
     size_t o = 0;
     const int64_t m = (int64_t)n_grids * n;
     auto take = [&](size_t b) { char* p = base ? base + o : nullptr; o += align256(b); return p; };
+    s.order = reinterpret_cast<uint32_t*>(take((size_t)(m > 0 ? m : 1) * 4));
+    s.home_hist = reinterpret_cast<uint32_t*>(take((size_t)n_buckets * 4));
+    s.home_cursor = reinterpret_cast<int64_t*>(take((size_t)(n_buckets + 1) * 8));
     s.offsets = reinterpret_cast<int64_t*>(take((size_t)(m + 1) * 8));
-    s.scan_ws = take(scan_workspace_bytes(m));
+    s.scan_ws = take(scan_workspace_bytes(m > n_buckets ? m : n_buckets));
     const int64_t c = cap > 0 ? cap : 1;
     s.keys0 = reinterpret_cast<uint32_t*>(take((size_t)c * 4));
     s.keys1 = reinterpret_cast<uint32_t*>(take((size_t)c * 4));
     s.vals0 = reinterpret_cast<uint32_t*>(take((size_t)c * 4));
     s.radix_ws = take(radix_workspace_bytes(c));
-    s.flags = reinterpret_cast<uint32_t*>(take(16));
+    s.report = reinterpret_cast<BinReport*>(take(sizeof(BinReport)));
     s.bytes = o;
     return s;
 }
@@ -335,7 +344,8 @@ gm_status gm_bin_query(int64_t n, const gm_grid* grids, int32_t n_grids, int64_t
     if (T >= 0x7fffffffLL) return fail(GM_ERR_INVALID_ARGUMENT, "too many tiles");
     if (records_bytes) *records_bytes = (size_t)n_grids * (size_t)n * 16 * sizeof(float);
     if (total_tiles) *total_tiles = T;
-    if (scratch_bytes) *scratch_bytes = scratch_layout(nullptr, n, n_grids, capacity_pairs).bytes;
+    if (scratch_bytes)
+        *scratch_bytes = scratch_layout(nullptr, n, n_grids, capacity_pairs, T + n_grids).bytes;
     return GM_OK;
 }
 
@@ -386,10 +396,10 @@ gm_status gm_bin(const gm_gaussians* g, const gm_grid* grids, int32_t n_grids,
     const int64_t n = g->n;
     const int64_t m = (int64_t)n_grids * n;
     BinScratch sc = scratch_layout(reinterpret_cast<char*>(bins->scratch), n, n_grids,
-                                   bins->capacity_pairs);
-    GM_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(bins->box_volume), 0u, 2 * n_grids, s),
-           "zero box volumes");
-    GM_HIP(launch_fill_u32(sc.flags, 0u, 4, s), "zero flags");
+                                   bins->capacity_pairs, base + n_grids);
+    static_assert(sizeof(BinReport) % 4 == 0, "report block is cleared as u32 words");
+    GM_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(sc.report), 0u, sizeof(BinReport) / 4, s),
+           "clear report");
     pa.n = n;
     pa.n_grids = n_grids;
     pa.cutoff = cutoff;
@@ -399,18 +409,32 @@ gm_status gm_bin(const gm_gaussians* g, const gm_grid* grids, int32_t n_grids,
     pa.logit = g->logit;
     pa.records = bins->records;
     pa.tile_count = bins->tile_count;
-    pa.box_volume = reinterpret_cast<unsigned long long*>(bins->box_volume);
-    pa.flags = sc.flags;
+    pa.box_volume = sc.report->box_volume;
+    pa.flags = sc.report->flags;
     GM_HIP(launch_preprocess(pa, s), "preprocess");
     GM_HIP(launch_scan_i32_to_i64(bins->tile_count, sc.offsets, m, sc.scan_ws, s), "scan");
 
-    int64_t total = 0;
-    uint32_t flags = 0;
-    GM_HIP(hipMemcpyAsync(&total, sc.offsets + m, sizeof total, hipMemcpyDeviceToHost, s), "read total");
-    GM_HIP(hipMemcpyAsync(&flags, sc.flags, sizeof flags, hipMemcpyDeviceToHost, s), "read flags");
+    // the backward's spatial processing order (needs only the boxes, so it is valid even
+    // when the pair capacity below turns out to be too small)
+    HomeArgs ha;
+    memset(&ha, 0, sizeof ha);
+    ha.n = n;
+    ha.n_grids = n_grids;
+    ha.records = bins->records;
+    ha.hist = sc.home_hist;
+    ha.cursor = sc.home_cursor;
+    ha.order = sc.order;
+    for (int k = 0; k < n_grids; ++k) ha.g[k] = pa.g[k];
+    GM_HIP(launch_home_order(ha, sc.scan_ws, s), "spatial order");
+    GM_HIP(launch_bin_report(sc.report, sc.offsets + m, bins->box_volume, n_grids, s), "report");
+    BinReport rep;
+    GM_HIP(hipMemcpyAsync(&rep, sc.report, sizeof rep, hipMemcpyDeviceToHost, s), "read report");
     GM_HIP(hipStreamSynchronize(s), "synchronise");
+    const int64_t total = rep.total;
+    const uint32_t flags = rep.flags[0];
     *n_pairs = total;
     bins->n_pairs = total;
+    for (int k = 0; k < GM_MAX_GRIDS; ++k) bins->box_pairs[k] = k < n_grids ? (int64_t)rep.box_volume[k] : 0;
     if (total > bins->capacity_pairs) {
         fail(GM_ERR_CAPACITY, "%lld (tile, Gaussian) pairs exceed capacity %lld", (long long)total,
              (long long)bins->capacity_pairs);
@@ -616,12 +640,15 @@ gm_status gm_f32_to_bf16(const float* in, uint16_t* out, int64_t n, gm_stream st
     return GM_OK;
 }
 
-gm_status gm_backward(const gm_gaussians* g, const gm_bins* bins, const int32_t* grid_ids,
-                      int32_t n_ids, const float* const* dl_di, float lambda_aniso, float lambda_r,
-                      gm_gaussian_grads* grad, gm_stream stream)
+namespace {
+
+// Shared body of gm_backward (both stages), gm_grid_partials (K7 only) and gm_chain (K8
+// only).
+gm_status backward_impl(const gm_gaussians* g, const gm_bins* bins, const int32_t* grid_ids,
+                        int32_t n_ids, const float* const* dl_di, float lambda_aniso,
+                        float lambda_r, gm_gaussian_grads* grad, hipStream_t s, bool partials,
+                        bool chain)
 {
-    g_err.clear();
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     gm_status st = check_gauss(g);
     if (st != GM_OK) return st;
     st = check_bins(bins, false);
@@ -631,17 +658,27 @@ gm_status gm_backward(const gm_gaussians* g, const gm_bins* bins, const int32_t*
     if (bins->n_gauss != g->n)
         return fail(GM_ERR_INVALID_ARGUMENT, "bins were built for %lld Gaussians, got %lld",
                     (long long)bins->n_gauss, (long long)g->n);
-    if (!grad || grad->n != g->n) return fail(GM_ERR_INVALID_ARGUMENT, "grad missing or wrong n");
-    if (!isfinite(lambda_aniso) || !isfinite(lambda_r))
-        return fail(GM_ERR_INVALID_ARGUMENT, "non-finite lambda");
-    if (n_ids > 0 && !dl_di) return fail(GM_ERR_INVALID_ARGUMENT, "dl_di is NULL");
+    if (chain) {
+        if (!grad || grad->n != g->n)
+            return fail(GM_ERR_INVALID_ARGUMENT, "grad missing or wrong n");
+        if (!isfinite(lambda_aniso) || !isfinite(lambda_r))
+            return fail(GM_ERR_INVALID_ARGUMENT, "non-finite lambda");
+    }
+    if (partials && n_ids > 0 && !dl_di) return fail(GM_ERR_INVALID_ARGUMENT, "dl_di is NULL");
     if (g->n == 0) return GM_OK;
-    REQ_PTR(grad->mean, "grad->mean");
-    REQ_PTR(grad->quat, "grad->quat");
-    REQ_PTR(grad->log_scale, "grad->log_scale");
-    REQ_PTR(grad->logit, "grad->logit");
+    if (chain) {
+        REQ_PTR(grad->mean, "grad->mean");
+        REQ_PTR(grad->quat, "grad->quat");
+        REQ_PTR(grad->log_scale, "grad->log_scale");
+        REQ_PTR(grad->logit, "grad->logit");
+    }
     REQ_PTR(bins->records, "bins->records");
     if (n_ids > 0) REQ_PTR(bins->grid_grads, "bins->grid_grads");
+    if (partials) {
+        REQ_PTR(bins->scratch, "bins->scratch");
+        if (bins->n_pairs < 0)
+            return fail(GM_ERR_INVALID_ARGUMENT, "bins have not been filled by gm_bin");
+    }
     BackwardArgs ba;
     memset(&ba, 0, sizeof ba);
     ChainArgs ca;
@@ -650,18 +687,22 @@ gm_status gm_backward(const gm_gaussians* g, const gm_bins* bins, const int32_t*
     ba.n_ids = n_ids;
     ba.records = bins->records;
     ba.grid_grads = bins->grid_grads;
+    ba.order = reinterpret_cast<const uint32_t*>(bins->scratch);  // BinScratch::order
     for (int k = 0; k < n_ids; ++k) {
-        REQ_PTR(dl_di[k], "dl_di[k]");
         const gm_grid& gr = bins->grids[grid_ids[k]];
+        if (partials) {
+            REQ_PTR(dl_di[k], "dl_di[k]");
+            ba.dl_di[k] = dl_di[k];
+        }
         ba.grid_index[k] = grid_ids[k];
         ba.nx[k] = gr.nx;
         ba.ny[k] = gr.ny;
         ba.nz[k] = gr.nz;
-        ba.dl_di[k] = dl_di[k];
         ca.grid_index[k] = grid_ids[k];
         ca.g[k] = make_const(gr, bins->tile_base[grid_ids[k]]);
     }
-    GM_HIP(launch_backward_partials(ba, s), "backward partials");
+    if (partials) GM_HIP(launch_backward_partials(ba, s), "backward partials");
+    if (!chain) return GM_OK;
     ca.n = g->n;
     ca.n_ids = n_ids;
     ca.lambda_aniso = lambda_aniso;
@@ -678,6 +719,34 @@ gm_status gm_backward(const gm_gaussians* g, const gm_bins* bins, const int32_t*
     ca.g_logit = grad->logit;
     GM_HIP(launch_chain(ca, s), "chain rule");
     return GM_OK;
+}
+
+}  // namespace
+
+gm_status gm_backward(const gm_gaussians* g, const gm_bins* bins, const int32_t* grid_ids,
+                      int32_t n_ids, const float* const* dl_di, float lambda_aniso, float lambda_r,
+                      gm_gaussian_grads* grad, gm_stream stream)
+{
+    g_err.clear();
+    return backward_impl(g, bins, grid_ids, n_ids, dl_di, lambda_aniso, lambda_r, grad,
+                         reinterpret_cast<hipStream_t>(stream), true, true);
+}
+
+gm_status gm_grid_partials(const gm_gaussians* g, const gm_bins* bins, const int32_t* grid_ids,
+                           int32_t n_ids, const float* const* dl_di, gm_stream stream)
+{
+    g_err.clear();
+    return backward_impl(g, bins, grid_ids, n_ids, dl_di, 0.0f, 0.0f, nullptr,
+                         reinterpret_cast<hipStream_t>(stream), true, false);
+}
+
+gm_status gm_chain(const gm_gaussians* g, const gm_bins* bins, const int32_t* grid_ids,
+                   int32_t n_ids, float lambda_aniso, float lambda_r, gm_gaussian_grads* grad,
+                   gm_stream stream)
+{
+    g_err.clear();
+    return backward_impl(g, bins, grid_ids, n_ids, nullptr, lambda_aniso, lambda_r, grad,
+                         reinterpret_cast<hipStream_t>(stream), false, true);
 }
 
 gm_status gm_loss_smooth_l1(int32_t n_stacks, const float* const* preds,

@@ -28,6 +28,17 @@ struct GridConst {
 // ---- launchers (one per kernel family) --------------------------------------------------
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
 
+// What gm_bin reads back after its one synchronisation: device-detected conditions (bit 0:
+// a non-finite parameter or zero quaternion), per-grid contributing-pair totals (summed by
+// the preprocess kernel) and the (tile, Gaussian) pair total from the scan.
+struct BinReport {
+    uint32_t flags[4];
+    unsigned long long box_volume[GM_MAX_GRIDS];
+    int64_t total;
+};
+hipError_t launch_bin_report(BinReport* rep, const int64_t* scan_end, int64_t* box_volume,
+                             int n_grids, hipStream_t s);
+
 struct PreprocessArgs {
     int64_t n;
     int32_t n_grids;
@@ -60,6 +71,22 @@ struct EmitArgs {
     GridConst g[GM_MAX_GRIDS];
 };
 hipError_t launch_emit(const EmitArgs& a, hipStream_t s);
+
+// Spatial processing order for the backward: for every grid, the n Gaussians grouped by the
+// tile holding their box's lower corner (tiles in id order, empty boxes last).  Counting
+// sort over n_grids * (tiles + 1) buckets; the order inside a bucket is arbitrary (the
+// backward's per-Gaussian results do not depend on it).  order[k * n + slot] = Gaussian id.
+struct HomeArgs {
+    int64_t n;
+    int32_t n_grids;
+    const float* records;
+    uint32_t* hist;            // [n_buckets] (cleared by the launcher)
+    int64_t* cursor;           // [n_buckets + 1] exclusive scan of hist, then slot cursors
+    uint32_t* order;           // [n_grids * n]
+    GridConst g[GM_MAX_GRIDS];
+};
+int64_t home_buckets(const GridConst* g, int32_t n_grids);
+hipError_t launch_home_order(const HomeArgs& a, void* scan_ws, hipStream_t s);
 
 // stable LSD radix sort of (key, value) pairs on the low `bits` key bits.
 size_t radix_workspace_bytes(int64_t n);
@@ -97,6 +124,7 @@ struct BackwardArgs {
     int32_t grid_index[GM_MAX_GRIDS];
     int32_t nx[GM_MAX_GRIDS], ny[GM_MAX_GRIDS], nz[GM_MAX_GRIDS];
     const float* dl_di[GM_MAX_GRIDS];
+    const uint32_t* order;     // [grids][n] processing order from gm_bin (HomeArgs)
 };
 hipError_t launch_backward_partials(const BackwardArgs& a, hipStream_t s);
 

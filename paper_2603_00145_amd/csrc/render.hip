@@ -4,20 +4,18 @@
 //
 // One wavefront owns one GM_TX x GM_TY x GM_TZ tile and accumulates it in LDS.  It walks
 // the tile's Gaussian list (ascending id) in batches of 64: each lane loads one record and
-// prepares that Gaussian's piece (box intersect tile) in LDS; then, Gaussian after Gaussian,
-// the lanes take the piece's voxels densely, evaluate amp * 2^(delta^T K delta) and add it
-// into the tile accumulator.  Within one Gaussian every lane holds a different voxel, and
-// Gaussians are taken one after another, so each voxel's sum is formed in ascending
-// Gaussian order and the result is the same on every run.
+// prepares that Gaussian's piece (box intersect tile) in LDS.  Then the pieces are taken in
+// list order.  A lane holds one (x, y) column of a piece's footprint and walks the piece's
+// z-range, so the in-plane part of the exponent is formed once per column and each voxel
+// costs two FMAs, one exp2 and one accumulate.  Two consecutive pieces whose footprints fit
+// in 32 columns share the wave (one per half); the first half adds into the tile before the
+// second, so every voxel's sum is still formed in ascending Gaussian order and the result
+// is the same on every run.
 #include "gm_internal.h"
 
 namespace {
 
 __device__ __forceinline__ int sgpr(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ float sgprf(float v)
-{
-    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-}
 
 // Division by a per-Gaussian d in [1, 1024] of q in [0, 1024): floor(q / d) equals
 // (q * M) >> 20 with M = ceil(2^20 / d), because q * d < 2^20.
@@ -25,15 +23,87 @@ __device__ __forceinline__ uint32_t magic20(uint32_t d) { return ((1u << 20) + d
 __device__ __forceinline__ uint32_t div20(uint32_t q, uint32_t M) { return __umul24(q, M) >> 20; }
 
 // Per (Gaussian, tile) piece, prepared lane-parallel for a batch of 64 list entries:
-// centre relative to the intersection origin, amplitude, base-2 conic, intersection size,
-// magic divisors and the LDS offset of the intersection origin.
+// centre relative to the intersection origin, amplitude, base-2 conic (off-diagonals
+// doubled), footprint width and area, z extent, the magic divisor for the column unravel
+// and the LDS index of the intersection origin.
 struct Piece {
     float ux, uy, uz, amp;
     float kxx, kyy, kzz, kxy;
     float kxz, kyz;
-    int wx, wxy;
-    int V, mx, mxy, base;
+    int wx, F, wz, mx, base, pad;
 };
+
+// Keeps the compiler from moving or merging LDS accesses across this point.  The two halves
+// of a wave that hold two different Gaussians may touch the same voxel; their
+// read-add-writes must stay two separate, ordered sequences.
+__device__ __forceinline__ void lds_order() { __asm__ __volatile__("" ::: "memory"); }
+
+// Column f of piece p: its voxel values w[k] = amp 2^Q for the z-steps k < KM, and the LDS
+// index of its voxel at k = 0.
+template <int KM>
+__device__ __forceinline__ void eval_column(const Piece& p, uint32_t f, float (&w)[KM], int& idx)
+{
+    const uint32_t y = div20(f, (uint32_t)p.mx);
+    const uint32_t x = f - __umul24(y, (uint32_t)p.wx);
+    const float dx = (float)x - p.ux;
+    const float dy = (float)y - p.uy;
+    const float qxy = dx * (p.kxx * dx + p.kxy * dy) + dy * (p.kyy * dy);
+    const float bz = p.kxz * dx + p.kyz * dy;
+    static_assert(GM_TX == 16 && GM_TY == 16, "index shifts assume 16x16 tiles");
+    idx = p.base + (int)((y << 4) + x);
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        const float dz = (float)k - p.uz;
+        const float Q = qxy + dz * (bz + p.kzz * dz);
+        w[k] = p.amp * __builtin_amdgcn_exp2f(Q);
+    }
+}
+
+// acc[column voxel at z-step k] += w[k] for k < kz <= KM (kz uniform).  The z-steps are
+// distinct voxels, so all reads are issued before the writes.
+template <int KM>
+__device__ __forceinline__ void add_column(float* acc, int idx, const float (&w)[KM], int kz)
+{
+    float old[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k)
+        if (k < kz) old[k] = acc[idx + k * GM_TX * GM_TY];
+#pragma unroll
+    for (int k = 0; k < KM; ++k)
+        if (k < kz) acc[idx + k * GM_TX * GM_TY] = old[k] + w[k];
+}
+
+// One piece on the whole wave: columns f0 + lane, KM z-steps each.
+template <int KM>
+__device__ __forceinline__ void single_piece(const Piece& p, float* acc, int F, int lane)
+{
+#pragma unroll 1
+    for (int f0 = 0; f0 < F; f0 += 64) {
+        const uint32_t f = (uint32_t)(f0 + lane);
+        if (f < (uint32_t)F) {
+            float w[KM];
+            int idx;
+            eval_column<KM>(p, f, w, idx);
+            add_column<KM>(acc, idx, w, KM);
+        }
+    }
+}
+
+// Two pieces, one per half-wave (lane's piece p, column f); KM = the larger z extent.  The
+// first half's read-add-writes complete before the second half's are issued.
+template <int KM>
+__device__ __forceinline__ void paired_pieces(const Piece& p, float* acc, bool act, bool first,
+                                              uint32_t f, int wza, int wzb)
+{
+    float w[KM];
+    int idx = 0;
+    if (act) eval_column<KM>(p, f, w, idx);
+    lds_order();
+    if (act && first) add_column<KM>(acc, idx, w, wza);
+    lds_order();
+    if (act && !first) add_column<KM>(acc, idx, w, wzb);
+    lds_order();
+}
 
 __global__ __launch_bounds__(64) void k_render(const RenderArgs a)
 {
@@ -62,6 +132,7 @@ __global__ __launch_bounds__(64) void k_render(const RenderArgs a)
     for (int b0 = s; b0 < e; b0 += 64) {
         const int nb = min(64, e - b0);
         __syncthreads();
+        bool small = false;
         if (lane < nb) {
             const int gid = pg[b0 + lane];
             const float4* src = reinterpret_cast<const float4*>(recbase + (size_t)gid * 16);
@@ -82,39 +153,49 @@ __global__ __launch_bounds__(64) void k_render(const RenderArgs a)
             p.kxx = r1.x; p.kyy = r1.y; p.kzz = r1.z; p.kxy = r1.w;
             p.kxz = r2.x; p.kyz = r2.y;
             p.wx = ok ? wx : 1;
-            p.wxy = ok ? wx * wy : 1;
-            p.V = ok ? wx * wy * wz : 0;
+            p.F = ok ? wx * wy : 0;
+            p.wz = ok ? wz : 0;
             p.mx = (int)magic20((uint32_t)p.wx);
-            p.mxy = (int)magic20((uint32_t)p.wxy);
             p.base = ((iz0 - t0z) * GM_TY + (iy0 - t0y)) * GM_TX + (ix0 - t0x);
+            p.pad = 0;
             pc[lane] = p;
+            small = p.F <= 32;
         }
+        // bit j: piece j's footprint fits in half a wave
+        const uint64_t sm = __ballot(small);
         __syncthreads();
+        int j = 0;
 #pragma unroll 1
-        for (int j = 0; j < nb; ++j) {
-            const Piece p = pc[j];
-            const int V = sgpr(p.V);
-#pragma unroll 1
-            for (int q0 = 0; q0 < V; q0 += 64) {
-                const uint32_t q = (uint32_t)(q0 + lane);
-                if (q < (uint32_t)V) {
-                    const uint32_t z = div20(q, (uint32_t)p.mxy);
-                    const uint32_t rm = q - __umul24(z, (uint32_t)p.wxy);
-                    const uint32_t y = div20(rm, (uint32_t)p.mx);
-                    const uint32_t x = rm - __umul24(y, (uint32_t)p.wx);
-                    const float dx = (float)x - p.ux;
-                    const float dy = (float)y - p.uy;
-                    const float dz = (float)z - p.uz;
-                    const float Q = dx * (p.kxx * dx + p.kxy * dy + p.kxz * dz) +
-                                    dy * (p.kyy * dy + p.kyz * dz) + dz * (p.kzz * dz);
-                    const float w = p.amp * __builtin_amdgcn_exp2f(Q);
-                    // one wave owns the tile and the lanes of one Gaussian hold distinct
-                    // voxels, so a plain read-add-write is race-free (and far faster than
-                    // an LDS atomic)
-                    static_assert(GM_TX == 16 && GM_TY == 16, "index shifts assume 16x16 tiles");
-                    const int idx = p.base + (int)((z << 8) + (y << 4) + x);
-                    acc[idx] += w;
+        while (j < nb) {
+            if (((sm >> j) & 3u) == 3u) {
+                // pieces j and j+1 side by side, one per half-wave
+                const int h = lane >> 5;
+                const Piece p = pc[j + h];
+                const int wza = __builtin_amdgcn_readlane(p.wz, 0);
+                const int wzb = __builtin_amdgcn_readlane(p.wz, 32);
+                const uint32_t f = (uint32_t)(lane & 31);
+                const bool act = f < (uint32_t)p.F;
+                const bool first = h == 0;
+                static_assert(GM_TZ == 4, "z extents 1..4 are dispatched below");
+                switch (max(wza, wzb)) {
+                case 1: paired_pieces<1>(p, acc, act, first, f, wza, wzb); break;
+                case 2: paired_pieces<2>(p, acc, act, first, f, wza, wzb); break;
+                case 3: paired_pieces<3>(p, acc, act, first, f, wza, wzb); break;
+                default: paired_pieces<GM_TZ>(p, acc, act, first, f, wza, wzb); break;
                 }
+                j += 2;
+            } else {
+                const Piece p = pc[j];
+                const int F = sgpr(p.F);
+                const int wz = sgpr(p.wz);
+                switch (wz) {
+                case 0: break;
+                case 1: single_piece<1>(p, acc, F, lane); break;
+                case 2: single_piece<2>(p, acc, F, lane); break;
+                case 3: single_piece<3>(p, acc, F, lane); break;
+                default: single_piece<GM_TZ>(p, acc, F, lane); break;
+                }
+                j += 1;
             }
         }
     }

@@ -102,6 +102,29 @@ def test_bins_bit_exact_c64(api):
     b.bin(api.GaussParams.from_host(w.gauss))
     torch.cuda.synchronize()
     check_bins_exact(api, b, w.gauss, grids)
+    # the per-grid pair totals gm_bin hands back on the host equal the device array
+    assert b.box_pairs_host == [b.pair_count(k) for k in range(len(grids))]
+
+
+def test_spatial_order(api):
+    """gm_bin's per-grid processing order for the backward: a permutation of the Gaussians
+    grouped by the tile holding their box's lower corner (tiles ascending), empty boxes
+    last."""
+    g, grids, rng = ragged_problem(1, n_g=500)
+    p = api.GaussParams.from_host(g)
+    b = api.Bins(p.n, grids)
+    b.bin(p)
+    torch.cuda.synchronize()
+    order = b.scratch[:len(grids) * g.n].cpu().numpy().astype(np.int64).reshape(len(grids), g.n)
+    T = np.asarray(api._lib.tile_dims())
+    for k, grid in enumerate(grids):
+        lo, hi, ne, _ = recipe.boxes(g.mean, g.quat, g.log_scale, g.logit, grid)
+        assert np.array_equal(np.sort(order[k]), np.arange(g.n))
+        ntx, nty = -(-grid.nx // T[0]), -(-grid.ny // T[1])
+        t = lo // T
+        home = np.where(ne, (t[:, 2] * nty + t[:, 1]) * ntx + t[:, 0], np.iinfo(np.int64).max)
+        h = home[order[k]]
+        assert np.all(np.diff(h) >= 0)
 
 
 def render_ref(g, grids):
@@ -188,6 +211,26 @@ def test_grid_partials_match_oracle(api):
         dK = np.stack([G_C[:, 0, 0], G_C[:, 1, 1], G_C[:, 2, 2], G_C[:, 0, 1], G_C[:, 0, 2],
                        G_C[:, 1, 2]], 1) / kappa
         assert normwise(pg[:, 4:10], dK) <= TOL
+
+
+def test_backward_stages_equal_backward(api):
+    """gm_grid_partials followed by gm_chain gives gm_backward's result bit for bit, and the
+    partials stage alone matches the oracle's grid-frame sums."""
+    g, grids, rng = ragged_problem(5, n_g=400)
+    dl = inputs.random_dl_di(grids, rng)
+    ref, b = grads_gpu(api, g, grids, [0, 1, 2, 3], dl, 0.1, 1.5)
+    p = api.GaussParams.from_host(g)
+    b2 = api.Bins(p.n, grids)
+    b2.bin(p)
+    d_dl = [torch.from_numpy(d).cuda() for d in dl]
+    api.grid_partials(p, b2, [0, 1, 2, 3], d_dl)
+    torch.cuda.synchronize()
+    assert torch.equal(b2.grid_grads, b.grid_grads)
+    out = api.GaussParams.zeros_like(p)
+    api.chain(p, b2, [0, 1, 2, 3], out, 0.1, 1.5)
+    torch.cuda.synchronize()
+    for a_, r_ in zip(out.tensors(), ref):
+        assert np.array_equal(a_.cpu().numpy(), r_)
 
 
 def test_backward_stacks_only_c64(api):

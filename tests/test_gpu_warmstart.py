@@ -108,3 +108,19 @@ def test_training_reduces_loss(mods):
         first = loss if first is None else first
     say(f"  warm training loss {first:.4f} -> {loss:.4f}")
     assert loss < 0.5 * first
+
+
+def test_warm_start_gain_small(mods):
+    """The iterations-to-PSNR experiment at small scale: a network trained on four 128^3
+    reconstructions warm-starts a held-out 256^3 phantom, which then reaches the plain arm's
+    200-iteration PSNR in at most half the iterations."""
+    from paper_2603_00145_amd import warmstart
+    res = warmstart.run_experiment(n_train=4, n_test=1, train_iters=100, test_iters=200,
+                                   net_steps=300)
+    case = res["cases"][0]
+    say(f"  plain {case['plain_init_psnr']:.2f} -> {case['plain_final_psnr']:.2f} dB; warm "
+        f"{case['warm_init_psnr']:.2f} -> {case['warm_final_psnr']:.2f} dB, target reached at "
+        f"iteration {case['warm_iters_to_target']}")
+    assert res["net_loss"][-1][1] < res["net_loss"][0][1]
+    assert case["warm_iters_to_target"] is not None
+    assert case["warm_iters_to_target"] <= 100

@@ -97,12 +97,12 @@ typedef struct gm_bin_opts {
  *   tile_count  [n_grids][n_gauss] int32: tiles the box overlaps
  *   box_volume  [n_grids] int64: sum of box volumes = contributing (Gaussian, voxel) pairs
  *   tile_start  [total_tiles + 1] int32: CSR row starts of the per-tile lists
- *   pair_gauss  [capacity_pairs] int32: Gaussian ids grouped by tile, ascending per tile
+ *   pair_gauss  [capacity_pairs] uint32: Gaussian ids (low 31 bits) grouped by tile,
+ *               ascending per tile; bit 31 is set on the one entry of each (grid,
+ *               Gaussian) whose tile holds the box's lower corner (its "home" tile)
  *   grid_grads  [n_grids][n_gauss][10] float: written by gm_backward / gm_grid_partials
  *               (grid-frame partials d amp, d c(3), d K(6))
- *   scratch     scratch_bytes of device memory: sorting workspace, and the per-grid
- *               spatial order of the Gaussians that gm_bin writes and gm_backward /
- *               gm_grid_partials read (leave it untouched between those calls)           */
+ *   scratch     scratch_bytes of device memory for sorting                              */
 typedef struct gm_bins {
     int32_t n_grids;
     int32_t reserved;
@@ -120,9 +120,8 @@ typedef struct gm_bins {
     gm_grid grids[GM_MAX_GRIDS];
     int64_t tile_base[GM_MAX_GRIDS + 1]; /* global tile id of each grid's first tile */
     int64_t n_pairs;                     /* (tile, Gaussian) pairs of the last gm_bin;
-                                            set it < 0 when allocating: gm_backward and
-                                            gm_grid_partials refuse bins gm_bin has not
-                                            filled                                       */
+                                            set it < 0 when allocating: calls that read
+                                            the tile lists refuse bins without them      */
     int64_t box_pairs[GM_MAX_GRIDS];     /* contributing (Gaussian, voxel) pairs per grid
                                             of the last gm_bin (= box_volume)            */
     double cutoff_sigma;
@@ -239,7 +238,9 @@ gm_status gm_aniso_reg(const gm_gaussians* g, float lambda_r, float* value, void
  * Gaussian parameter, boxes held fixed (Sec. 3.5).  Recomputes each Gaussian's values
  * instead of storing per-voxel contributions.  Writes bins->grid_grads for the listed
  * grids, then ACCUMULATES (+=) into grad (caller zeroes it).  g must be the parameters
- * bins was built from.  dl_di [host] array of n_ids device pointers. */
+ * bins was built from, by a gm_bin that returned GM_OK or GM_ERR_NONFINITE (the tile lists
+ * are walked to take the Gaussians in spatial order).  dl_di [host] array of n_ids device
+ * pointers.  Bit-reproducible. */
 gm_status gm_backward(const gm_gaussians* g, const gm_bins* bins, const int32_t* grid_ids,
                       int32_t n_ids, const float* const* dl_di, float lambda_aniso,
                       float lambda_r, gm_gaussian_grads* grad, gm_stream stream);
@@ -248,8 +249,9 @@ gm_status gm_backward(const gm_gaussians* g, const gm_bins* bins, const int32_t*
  * sums over its box of the derivatives of sum_v dl_di[k][v] I_k[v] with respect to the
  * record's amplitude (1), centre (3) and the six distinct entries of its conic K as a
  * symmetric matrix (xx yy zz xy xz yz), written (overwritten) to
- * bins->grid_grads[grid][i][10].  These per-grid quantities are also where an update of the
- * stacks' rigid placements would start from. */
+ * bins->grid_grads[grid][i][10] (a Gaussian whose box is empty on a grid has zeros there,
+ * written by gm_bin).  Needs the tile lists, as gm_backward does.  These per-grid quantities
+ * are also where an update of the stacks' rigid placements would start from. */
 gm_status gm_grid_partials(const gm_gaussians* g, const gm_bins* bins,
                            const int32_t* grid_ids, int32_t n_ids, const float* const* dl_di,
                            gm_stream stream);

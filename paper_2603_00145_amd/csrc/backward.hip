@@ -21,6 +21,7 @@
 namespace {
 
 __device__ __forceinline__ int sgpr(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t sgpr64(int v) { return (int64_t)__builtin_amdgcn_readfirstlane(v); }
 
 // Sum of v over each 32-lane half of the wavefront: DPP adds within rows of 16, then row 0
 // into row 1 and row 2 into row 3.  Lane 31 ends with the first half's total, lane 63 with
@@ -41,28 +42,42 @@ __device__ __forceinline__ float half_sum(float v)
     return v;
 }
 
-// Two Gaussians per wavefront, one per 32-lane half, taken in the spatial order gm_bin
-// produced for the grid (neighbouring Gaussians run together, and on one XCD, so the dL/dI
-// they gather is served from the same L2 lines).  A half maps its lanes onto chunks of
-// 32 (x, y) columns of the Gaussian's box.  Each column is walked along z four steps at a
-// time: the four dL/dI values are loaded first, then each step costs two FMAs for Q, one
-// exp2 and four FMAs for the column sums.  Steps past a lane's column (or past its half's
-// box) load 0 and add exact zeros, so the arithmetic needs no per-step predication.
+// Each wavefront takes 64 consecutive entries of one grid's tile-sorted lists and processes
+// the Gaussians whose home entry (the tile holding the box's lower corner) is among them:
+// every Gaussian of the grid exactly once, in tile order, so neighbouring Gaussians run
+// together (and on one XCD) and the dL/dI they gather is served from the same L2 lines.
+// Two Gaussians at a time, one per 32-lane half.  A half maps its lanes onto chunks of 32
+// (x, y) columns of the Gaussian's box and walks each column along z: all of the column's
+// dL/dI values are loaded first, then step k costs two FMAs for Q_k = A + k (B + k kzz), one
+// exp2, one multiply and three adds for the column sums of g E, k g E and k^2 g E (k is a
+// compile-time constant in the unrolled loop).  In the z range both halves share, the loads
+// need no per-lane care; past the shorter box, a half's loads are clamped and zeroed.
+// Gaussians with an empty box are in no list; gm_bin wrote their zeros.
 __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a, int blocks_per_grid)
 {
     const int lane = threadIdx.x & 63;
     const int hl = lane & 31;
     const int lin = xcd_remap(blockIdx.x, gridDim.x);
     const int kk = lin / blocks_per_grid;                  // listed grid
-    const int64_t first = ((int64_t)(lin - kk * blocks_per_grid) * 4 + (threadIdx.x >> 6)) * 2;
-    if (first >= a.n) return;  // wave-uniform: both halves past the end
-    const int64_t slot = first + (lane >> 5);
-    const bool gvalid = slot < a.n;
-    {
-        const int gi = a.grid_index[kk];
-        // clamped so that even an order the caller never let gm_bin fill cannot index out
-        // of bounds
-        const int64_t gid = gvalid ? min((int64_t)a.order[(size_t)gi * a.n + slot], a.n - 1) : 0;
+    const int64_t e0 = sgpr64(a.tile_start[a.tile_lo[kk]]);
+    const int64_t e1 = sgpr64(a.tile_start[a.tile_hi[kk]]);
+    const int64_t w0 = e0 + ((int64_t)(lin - kk * blocks_per_grid) * 4 + (threadIdx.x >> 6)) * 64;
+    if (w0 >= e1) return;  // wave-uniform
+    const int64_t entry = w0 + lane;
+    const uint32_t v = entry < e1 ? a.pair_gauss[entry] : 0u;
+    uint64_t todo = __ballot(entry < e1 && (v & GM_HOME_BIT));
+    const int gi = a.grid_index[kk];
+#pragma unroll 1
+    while (todo) {
+        const int ia = __builtin_ctzll(todo);
+        todo &= todo - 1;
+        const int ib = todo ? __builtin_ctzll(todo) : ia;
+        const bool has_b = todo != 0;
+        if (has_b) todo &= todo - 1;
+        const uint32_t va = __builtin_amdgcn_readlane(v, ia);
+        const uint32_t vb = __builtin_amdgcn_readlane(v, ib);
+        const bool gvalid = lane < 32 || has_b;
+        const int64_t gid = min((int64_t)((lane < 32 ? va : vb) & GM_ID_MASK), a.n - 1);
         float4 r0 = make_float4(0, 0, 0, 0), r1 = r0, r2 = r0, r3 = r0;
         if (gvalid) {
             const float4* rp = reinterpret_cast<const float4*>(a.records + ((size_t)gi * a.n + gid) * 16);
@@ -89,10 +104,15 @@ __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a, int bloc
         const int max_chunks = max(__builtin_amdgcn_readlane(chunks, 0),
                                    __builtin_amdgcn_readlane(chunks, 32));
         const int max_wz = max(__builtin_amdgcn_readlane(wz, 0), __builtin_amdgcn_readlane(wz, 32));
-        const float inv_wx = 1.0f / (float)wx;
+        // column f -> (x, y) = (f mod wx, f div wx) as floor((f + 1/2) / wx): the fraction
+        // stays at least 1/(2 wx) away from an integer, far beyond the hardware
+        // reciprocal's error for any f < 2^20
+        const float inv_wx = __builtin_amdgcn_rcpf((float)wx);
         const int nx = a.nx[kk], ny = a.ny[kk];
         const int nxy = nx * ny;
         const float* __restrict__ g = a.dl_di[kk];
+        // z steps both halves take (no per-lane care needed) and the tail only one half takes
+        const int min_wz = min(__builtin_amdgcn_readlane(wz, 0), __builtin_amdgcn_readlane(wz, 32));
         // weighted moments: m0 = sum gE, m1 = sum gE delta, m2 = sum gE delta delta^T
         float m0 = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f;
         float mxx = 0.0f, myy = 0.0f, mzz = 0.0f, mxy = 0.0f, mxz = 0.0f, myz = 0.0f;
@@ -103,44 +123,68 @@ __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a, int bloc
             const int y = (int)(((float)f + 0.5f) * inv_wx);
             const int x = f - y * wx;
             const float dx = (float)x - cx, dy = (float)y - cy;
-            const float qxy = dx * (kxx * dx + kxy * dy) + dy * (kyy * dy);
+            // along the column, dz = dz0 + k for step k = 0, 1, ...: Q_k = A + k (B + k kzz).
+            // A lane outside the footprint reads voxel (0, 0, k) and gets A = -inf, so its
+            // every term is exactly zero.
+            const float dz0 = -cz;
             const float bz = kxz * dx + kyz * dy;
-            const int nz_col = act ? wz : 0;             // z steps this lane loads
-            const int base = (loz * ny + (loy + y)) * nx + (lox + x);  // grids hold < 2^31 voxels
+            const float qxy = dx * (kxx * dx + kxy * dy) + dy * (kyy * dy);
+            const float A = act ? qxy + dz0 * (bz + kzz * dz0) : -__builtin_inff();
+            const float B = bz + 2.0f * kzz * dz0;
+            const uint32_t off = act ? (uint32_t)((loz * ny + (loy + y)) * nx + (lox + x)) : 0u;
+            const int ncol = act ? wz : 1;             // steps whose voxel lies in the box
+            // s0 = sum ge, s1 = sum k ge, s2 = sum k^2 ge over the column (ge = g 2^Q)
             float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
-#pragma unroll 1
-            for (int z0 = 0; z0 < max_wz; z0 += 4) {
-                float gv[4];
+            float gv[8];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    gv[u] = 0.0f;
-                    if (z0 + u < nz_col) gv[u] = g[base + (z0 + u) * nxy];
-                }
-                const float dz0 = (float)z0 - cz;
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (z0 + u < max_wz) {
-                        const float dz = dz0 + (float)u;
-                        const float Q = qxy + dz * (bz + kzz * dz);
-                        const float ge = gv[u] * __builtin_amdgcn_exp2f(Q);
-                        const float t = ge * dz;
-                        s0 += ge;
-                        s1 += t;
-                        s2 += t * dz;
+            for (int k = 0; k < 8; ++k) {
+                if (k < max_wz) {
+                    if (k < min_wz) {
+                        gv[k] = (g + (size_t)k * nxy)[off];
+                    } else {
+                        const int kc = min(k, ncol - 1);
+                        const float t = (g + (size_t)kc * nxy)[off];
+                        gv[k] = k < ncol ? t : 0.0f;
                     }
                 }
             }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (k < max_wz) {
+                    const float Q = k == 0 ? A : A + (float)k * (B + (float)k * kzz);
+                    const float ge = gv[k] * __builtin_amdgcn_exp2f(Q);
+                    s0 += ge;
+                    if (k > 0) {
+                        s1 += (float)k * ge;
+                        s2 += (float)(k * k) * ge;
+                    }
+                }
+            }
+#pragma unroll 1
+            for (int k = 8; k < max_wz; ++k) {  // boxes deeper than 8 voxels
+                const int kc = min(k, ncol - 1);
+                const float t = (g + (size_t)kc * nxy)[off];
+                const float gk = k < ncol ? t : 0.0f;
+                const float fk = (float)k;
+                const float ge = gk * __builtin_amdgcn_exp2f(A + fk * (B + fk * kzz));
+                s0 += ge;
+                s1 += fk * ge;
+                s2 += fk * fk * ge;
+            }
+            // back to moments in dz = dz0 + k
+            const float S1 = s1 + dz0 * s0;
+            const float S2 = s2 + dz0 * (2.0f * s1 + dz0 * s0);
             const float ax = s0 * dx, ay = s0 * dy;
             m0 += s0;
             mx += ax;
             my += ay;
-            mz += s1;
+            mz += S1;
             mxx += ax * dx;
             myy += ay * dy;
             mxy += ax * dy;
-            mxz += s1 * dx;
-            myz += s1 * dy;
-            mzz += s2;
+            mxz += S1 * dx;
+            myz += S1 * dy;
+            mzz += S2;
         }
         m0 = half_sum(m0);
         mx = half_sum(mx);
@@ -233,9 +277,7 @@ __global__ __launch_bounds__(128) void k_chain(const ChainArgs a)
         const GridConst& G = a.g[k];
         const int gi = a.grid_index[k];
         const float* pg = a.grid_grads + ((size_t)gi * a.n + i) * 10;
-        const float* rc = a.records + ((size_t)gi * a.n + i) * 16;
-        const int* ri = reinterpret_cast<const int*>(rc);
-        if (ri[10] > ri[13] || ri[11] > ri[14] || ri[12] > ri[15]) continue;  // empty box
+        if (a.tile_count[(size_t)gi * a.n + i] == 0) continue;  // empty box
         const double damp = pg[0];
         const double dc[3] = {pg[1], pg[2], pg[3]};
         // full-matrix dL/dC from the base-2 conic partials: C-entry = K-entry * KAPPA
@@ -325,7 +367,10 @@ __global__ __launch_bounds__(128) void k_chain(const ChainArgs a)
 hipError_t launch_backward_partials(const BackwardArgs& a, hipStream_t s)
 {
     if (a.n == 0 || a.n_ids == 0) return hipSuccess;
-    const int64_t per_grid = (a.n + 7) / 8;  // 4 wavefronts x 2 Gaussians per block
+    if (a.n_pairs <= 0) return hipSuccess;
+    // 4 wavefronts x 64 entries per block; every listed grid gets enough blocks for the
+    // whole list (a grid's own share is only known on the device; surplus waves exit)
+    const int64_t per_grid = (a.n_pairs + 255) / 256;
     const int64_t blocks = per_grid * a.n_ids;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(k_partials, dim3((unsigned)blocks), dim3(256), 0, s, a, (int)per_grid);

@@ -117,45 +117,16 @@ __global__ __launch_bounds__(256) void k_emit(const EmitArgs a)
     const int* rec = reinterpret_cast<const int*>(a.records + idx * 16);
     const int lx = rec[10], ly = rec[11], lz = rec[12], hx = rec[13], hy = rec[14], hz = rec[15];
     int64_t o = a.offsets[idx];
+    // the first tile emitted holds the box's lower corner: its entry carries GM_HOME_BIT
+    uint32_t home = GM_HOME_BIT;
     for (int tz = lz / GM_TZ; tz <= hz / GM_TZ; ++tz)
         for (int ty = ly / GM_TY; ty <= hy / GM_TY; ++ty)
             for (int tx = lx / GM_TX; tx <= hx / GM_TX; ++tx) {
                 a.keys[o] = (uint32_t)(G.tile_base + ((int64_t)tz * G.nty + ty) * G.ntx + tx);
-                a.vals[o] = gid;
+                a.vals[o] = gid | home;
+                home = 0u;
                 ++o;
             }
-}
-
-// ---- spatial order of the Gaussians per grid ---------------------------------------------
-// Bucket of (grid k, Gaussian): grid k owns buckets [tile_base_k + k, tile_base_{k+1} + k],
-// one per tile plus a last one for empty boxes, so grid k's n Gaussians land in slots
-// [k n, (k + 1) n) of the order.
-__device__ __forceinline__ int64_t home_bucket(const HomeArgs& a, int k, int64_t idx)
-{
-    const GridConst& G = a.g[k];
-    const int* rec = reinterpret_cast<const int*>(a.records + idx * 16);
-    const int lx = rec[10], ly = rec[11], lz = rec[12], hx = rec[13], hy = rec[14], hz = rec[15];
-    const int64_t b0 = G.tile_base + k;
-    if (lx > hx || ly > hy || lz > hz) return b0 + (int64_t)G.ntx * G.nty * G.ntz;
-    return b0 + ((int64_t)(lz / GM_TZ) * G.nty + ly / GM_TY) * G.ntx + lx / GM_TX;
-}
-
-__global__ __launch_bounds__(256) void k_home_hist(const HomeArgs a)
-{
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)a.n_grids * a.n) return;
-    const int k = (int)(idx / a.n);
-    atomicAdd(&a.hist[home_bucket(a, k, idx)], 1u);
-}
-
-__global__ __launch_bounds__(256) void k_home_scatter(const HomeArgs a)
-{
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)a.n_grids * a.n) return;
-    const int k = (int)(idx / a.n);
-    const int64_t slot = (int64_t)atomicAdd(
-        reinterpret_cast<unsigned long long*>(&a.cursor[home_bucket(a, k, idx)]), 1ull);
-    a.order[slot] = (uint32_t)(idx - (int64_t)k * a.n);
 }
 
 // ---- radix sort --------------------------------------------------------------------------
@@ -183,7 +154,9 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t* keys, in
 
 // Stable scatter.  Wave w of the block owns keys [base + w*1024, base + (w+1)*1024) and takes
 // them in 16 rounds of 64 consecutive keys; lanes with equal digits are matched with ballots,
-// so every key learns how many equal-digit keys precede it in the block.
+// so every key learns how many equal-digit keys precede it in the block.  The block's keys are
+// first placed in LDS in digit order, then written out by consecutive threads, so that each
+// digit's run leaves the block as one contiguous stretch of stores.
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* kin,
                                                             const uint32_t* vin, uint32_t* kout,
                                                             uint32_t* vout, int64_t n, int shift,
@@ -191,12 +164,18 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* kin,
                                                             int64_t nblocks)
 {
     __shared__ uint32_t wcnt[RS_WAVES][256];
+    __shared__ uint32_t wsum[RS_WAVES];
+    __shared__ uint32_t dstart[256];
+    __shared__ int64_t obase[256];
+    __shared__ uint32_t skey[RS_BLOCK_KEYS];
+    __shared__ uint32_t sval[RS_BLOCK_KEYS];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t mask = (1u << dbits) - 1u;
     for (int d = lane; d < 256; d += 64) wcnt[wave][d] = 0;
     __syncthreads();
     const uint64_t lt = (1ull << lane) - 1ull;
-    const int64_t wbase = (int64_t)blockIdx.x * RS_BLOCK_KEYS + (int64_t)wave * RS_WAVE_KEYS;
+    const int64_t bbase = (int64_t)blockIdx.x * RS_BLOCK_KEYS;
+    const int64_t wbase = bbase + (int64_t)wave * RS_WAVE_KEYS;
     uint32_t key[RS_ROUNDS], val[RS_ROUNDS], rank[RS_ROUNDS];
 #pragma unroll
     for (int r = 0; r < RS_ROUNDS; ++r) {
@@ -218,26 +197,50 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* kin,
         if (ok && before == 0) wcnt[wave][dg] = base + (uint32_t)__popcll(peers);
     }
     __syncthreads();
-    {
-        const int d = threadIdx.x;  // RS_THREADS == 256 digits
-        uint32_t run = 0;
+    // per digit: offsets of the waves' runs, the digit's block total, and its block-local
+    // start (exclusive scan over the 256 digits: within each wave with shuffles, then across
+    // the four waves)
+    const int d = threadIdx.x;  // RS_THREADS == 256 digits
+    uint32_t run = 0;
 #pragma unroll
-        for (int w = 0; w < RS_WAVES; ++w) {
-            const uint32_t t = wcnt[w][d];
-            wcnt[w][d] = run;
-            run += t;
-        }
+    for (int w = 0; w < RS_WAVES; ++w) {
+        const uint32_t t = wcnt[w][d];
+        wcnt[w][d] = run;
+        run += t;
     }
+    uint32_t incl = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[wave] = incl;
     __syncthreads();
+    uint32_t before_w = 0;
+    for (int w = 0; w < wave; ++w) before_w += wsum[w];
+    const uint32_t ds = before_w + incl - run;
+    dstart[d] = ds;
+    obase[d] = goff[(int64_t)d * nblocks + blockIdx.x] - (int64_t)ds;
+    __syncthreads();
+    // place the keys in digit order in LDS (positions < RS_BLOCK_KEYS by construction)
 #pragma unroll
     for (int r = 0; r < RS_ROUNDS; ++r) {
         const int64_t i = wbase + r * 64 + lane;
         if (i < n) {
             const uint32_t dg = (key[r] >> shift) & mask;
-            const int64_t pos = goff[(int64_t)dg * nblocks + blockIdx.x] + wcnt[wave][dg] + rank[r];
-            kout[pos] = key[r];
-            vout[pos] = val[r];
+            const uint32_t lp = dstart[dg] + wcnt[wave][dg] + rank[r];
+            skey[lp] = key[r];
+            sval[lp] = val[r];
         }
+    }
+    __syncthreads();
+    const int64_t rem = n - bbase;
+    const int nkeys = rem < RS_BLOCK_KEYS ? (int)rem : RS_BLOCK_KEYS;
+    for (int i = threadIdx.x; i < nkeys; i += RS_THREADS) {
+        const uint32_t k = skey[i];
+        const int64_t pos = obase[(k >> shift) & mask] + i;
+        kout[pos] = k;
+        vout[pos] = sval[i];
     }
 }
 
@@ -321,27 +324,6 @@ hipError_t launch_emit(const EmitArgs& a, hipStream_t s)
     const int64_t total = (int64_t)a.n_grids * a.n;
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_emit, dim3(grid_for(total, 256)), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
-int64_t home_buckets(const GridConst* g, int32_t n_grids)
-{
-    int64_t b = 0;
-    for (int k = 0; k < n_grids; ++k) b += (int64_t)g[k].ntx * g[k].nty * g[k].ntz + 1;
-    return b;
-}
-
-hipError_t launch_home_order(const HomeArgs& a, void* scan_ws, hipStream_t s)
-{
-    const int64_t total = (int64_t)a.n_grids * a.n;
-    const int64_t nb = home_buckets(a.g, a.n_grids);
-    hipError_t e = launch_fill_u32(a.hist, 0u, nb, s);
-    if (e != hipSuccess || total == 0) return e;
-    hipLaunchKernelGGL(k_home_hist, dim3(grid_for(total, 256)), dim3(256), 0, s, a);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    e = launch_scan_i32_to_i64(reinterpret_cast<const int32_t*>(a.hist), a.cursor, nb, scan_ws, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_home_scatter, dim3(grid_for(total, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

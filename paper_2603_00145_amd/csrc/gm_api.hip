@@ -92,10 +92,6 @@ int64_t grid_tiles(const gm_grid& g)
 
 // scratch layout of gm_bins
 struct BinScratch {
-    uint32_t* order;    // [n_grids * n] backward processing order; first, so that its
-                        // address does not depend on the other sizes
-    uint32_t* home_hist;      // [n_buckets]
-    int64_t* home_cursor;     // [n_buckets + 1]
     int64_t* offsets;   // [n_grids * n + 1]
     void* scan_ws;
     uint32_t* keys0;
@@ -106,19 +102,14 @@ struct BinScratch {
     size_t bytes;
 };
 
-// n_buckets = total tiles + n_grids (the spatial-order buckets, one per tile plus one per
-// grid for empty boxes).
-BinScratch scratch_layout(char* base, int64_t n, int32_t n_grids, int64_t cap, int64_t n_buckets)
+BinScratch scratch_layout(char* base, int64_t n, int32_t n_grids, int64_t cap)
 {
     BinScratch s;
     size_t o = 0;
     const int64_t m = (int64_t)n_grids * n;
     auto take = [&](size_t b) { char* p = base ? base + o : nullptr; o += align256(b); return p; };
-    s.order = reinterpret_cast<uint32_t*>(take((size_t)(m > 0 ? m : 1) * 4));
-    s.home_hist = reinterpret_cast<uint32_t*>(take((size_t)n_buckets * 4));
-    s.home_cursor = reinterpret_cast<int64_t*>(take((size_t)(n_buckets + 1) * 8));
     s.offsets = reinterpret_cast<int64_t*>(take((size_t)(m + 1) * 8));
-    s.scan_ws = take(scan_workspace_bytes(m > n_buckets ? m : n_buckets));
+    s.scan_ws = take(scan_workspace_bytes(m));
     const int64_t c = cap > 0 ? cap : 1;
     s.keys0 = reinterpret_cast<uint32_t*>(take((size_t)c * 4));
     s.keys1 = reinterpret_cast<uint32_t*>(take((size_t)c * 4));
@@ -344,8 +335,7 @@ gm_status gm_bin_query(int64_t n, const gm_grid* grids, int32_t n_grids, int64_t
     if (T >= 0x7fffffffLL) return fail(GM_ERR_INVALID_ARGUMENT, "too many tiles");
     if (records_bytes) *records_bytes = (size_t)n_grids * (size_t)n * 16 * sizeof(float);
     if (total_tiles) *total_tiles = T;
-    if (scratch_bytes)
-        *scratch_bytes = scratch_layout(nullptr, n, n_grids, capacity_pairs, T + n_grids).bytes;
+    if (scratch_bytes) *scratch_bytes = scratch_layout(nullptr, n, n_grids, capacity_pairs).bytes;
     return GM_OK;
 }
 
@@ -396,7 +386,7 @@ gm_status gm_bin(const gm_gaussians* g, const gm_grid* grids, int32_t n_grids,
     const int64_t n = g->n;
     const int64_t m = (int64_t)n_grids * n;
     BinScratch sc = scratch_layout(reinterpret_cast<char*>(bins->scratch), n, n_grids,
-                                   bins->capacity_pairs, base + n_grids);
+                                   bins->capacity_pairs);
     static_assert(sizeof(BinReport) % 4 == 0, "report block is cleared as u32 words");
     GM_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(sc.report), 0u, sizeof(BinReport) / 4, s),
            "clear report");
@@ -411,21 +401,10 @@ gm_status gm_bin(const gm_gaussians* g, const gm_grid* grids, int32_t n_grids,
     pa.tile_count = bins->tile_count;
     pa.box_volume = sc.report->box_volume;
     pa.flags = sc.report->flags;
+    pa.grid_grads = bins->grid_grads;
     GM_HIP(launch_preprocess(pa, s), "preprocess");
     GM_HIP(launch_scan_i32_to_i64(bins->tile_count, sc.offsets, m, sc.scan_ws, s), "scan");
 
-    // the backward's spatial processing order (needs only the boxes, so it is valid even
-    // when the pair capacity below turns out to be too small)
-    HomeArgs ha;
-    memset(&ha, 0, sizeof ha);
-    ha.n = n;
-    ha.n_grids = n_grids;
-    ha.records = bins->records;
-    ha.hist = sc.home_hist;
-    ha.cursor = sc.home_cursor;
-    ha.order = sc.order;
-    for (int k = 0; k < n_grids; ++k) ha.g[k] = pa.g[k];
-    GM_HIP(launch_home_order(ha, sc.scan_ws, s), "spatial order");
     GM_HIP(launch_bin_report(sc.report, sc.offsets + m, bins->box_volume, n_grids, s), "report");
     BinReport rep;
     GM_HIP(hipMemcpyAsync(&rep, sc.report, sizeof rep, hipMemcpyDeviceToHost, s), "read report");
@@ -651,7 +630,7 @@ gm_status backward_impl(const gm_gaussians* g, const gm_bins* bins, const int32_
 {
     gm_status st = check_gauss(g);
     if (st != GM_OK) return st;
-    st = check_bins(bins, false);
+    st = check_bins(bins, partials);  // the partials walk the tile lists
     if (st != GM_OK) return st;
     st = check_ids(bins, grid_ids, n_ids);
     if (st != GM_OK) return st;
@@ -673,11 +652,11 @@ gm_status backward_impl(const gm_gaussians* g, const gm_bins* bins, const int32_
         REQ_PTR(grad->logit, "grad->logit");
     }
     REQ_PTR(bins->records, "bins->records");
+    REQ_PTR(bins->tile_count, "bins->tile_count");
     if (n_ids > 0) REQ_PTR(bins->grid_grads, "bins->grid_grads");
-    if (partials) {
-        REQ_PTR(bins->scratch, "bins->scratch");
-        if (bins->n_pairs < 0)
-            return fail(GM_ERR_INVALID_ARGUMENT, "bins have not been filled by gm_bin");
+    if (partials && bins->n_pairs > 0) {
+        REQ_PTR(bins->pair_gauss, "bins->pair_gauss");
+        REQ_PTR(bins->tile_start, "bins->tile_start");
     }
     BackwardArgs ba;
     memset(&ba, 0, sizeof ba);
@@ -687,7 +666,9 @@ gm_status backward_impl(const gm_gaussians* g, const gm_bins* bins, const int32_
     ba.n_ids = n_ids;
     ba.records = bins->records;
     ba.grid_grads = bins->grid_grads;
-    ba.order = reinterpret_cast<const uint32_t*>(bins->scratch);  // BinScratch::order
+    ba.tile_start = bins->tile_start;
+    ba.pair_gauss = reinterpret_cast<const uint32_t*>(bins->pair_gauss);
+    ba.n_pairs = bins->n_pairs;
     for (int k = 0; k < n_ids; ++k) {
         const gm_grid& gr = bins->grids[grid_ids[k]];
         if (partials) {
@@ -695,6 +676,8 @@ gm_status backward_impl(const gm_gaussians* g, const gm_bins* bins, const int32_
             ba.dl_di[k] = dl_di[k];
         }
         ba.grid_index[k] = grid_ids[k];
+        ba.tile_lo[k] = bins->tile_base[grid_ids[k]];
+        ba.tile_hi[k] = bins->tile_base[grid_ids[k] + 1];
         ba.nx[k] = gr.nx;
         ba.ny[k] = gr.ny;
         ba.nz[k] = gr.nz;
@@ -711,7 +694,7 @@ gm_status backward_impl(const gm_gaussians* g, const gm_bins* bins, const int32_
     ca.quat = g->quat;
     ca.log_scale = g->log_scale;
     ca.logit = g->logit;
-    ca.records = bins->records;
+    ca.tile_count = bins->tile_count;
     ca.grid_grads = bins->grid_grads;
     ca.g_mean = grad->mean;
     ca.g_quat = grad->quat;

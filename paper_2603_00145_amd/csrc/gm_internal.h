@@ -11,6 +11,10 @@
 #define GM_TY 16
 #define GM_TZ 4
 #define GM_TILE_VOX (GM_TX * GM_TY * GM_TZ)
+// Set on the one entry of each (grid, Gaussian) in the tile lists whose tile holds the box's
+// lower corner; the id is the low 31 bits.
+#define GM_HOME_BIT 0x80000000u
+#define GM_ID_MASK 0x7fffffffu
 
 // -1/2 log2(e): folds the Gaussian's -1/2 and the change to base 2 into the conic.
 #define GM_KAPPA (-0.72134752044448170368)
@@ -51,6 +55,7 @@ struct PreprocessArgs {
     int32_t* tile_count;     // [n_grids][n]
     unsigned long long* box_volume;  // [n_grids]
     uint32_t* flags;         // bit 0: invalid parameter seen
+    float* grid_grads;       // [n_grids][n][10] or NULL: zeroed for empty boxes
     GridConst g[GM_MAX_GRIDS];
 };
 hipError_t launch_preprocess(const PreprocessArgs& a, hipStream_t s);
@@ -71,22 +76,6 @@ struct EmitArgs {
     GridConst g[GM_MAX_GRIDS];
 };
 hipError_t launch_emit(const EmitArgs& a, hipStream_t s);
-
-// Spatial processing order for the backward: for every grid, the n Gaussians grouped by the
-// tile holding their box's lower corner (tiles in id order, empty boxes last).  Counting
-// sort over n_grids * (tiles + 1) buckets; the order inside a bucket is arbitrary (the
-// backward's per-Gaussian results do not depend on it).  order[k * n + slot] = Gaussian id.
-struct HomeArgs {
-    int64_t n;
-    int32_t n_grids;
-    const float* records;
-    uint32_t* hist;            // [n_buckets] (cleared by the launcher)
-    int64_t* cursor;           // [n_buckets + 1] exclusive scan of hist, then slot cursors
-    uint32_t* order;           // [n_grids * n]
-    GridConst g[GM_MAX_GRIDS];
-};
-int64_t home_buckets(const GridConst* g, int32_t n_grids);
-hipError_t launch_home_order(const HomeArgs& a, void* scan_ws, hipStream_t s);
 
 // stable LSD radix sort of (key, value) pairs on the low `bits` key bits.
 size_t radix_workspace_bytes(int64_t n);
@@ -124,7 +113,11 @@ struct BackwardArgs {
     int32_t grid_index[GM_MAX_GRIDS];
     int32_t nx[GM_MAX_GRIDS], ny[GM_MAX_GRIDS], nz[GM_MAX_GRIDS];
     const float* dl_di[GM_MAX_GRIDS];
-    const uint32_t* order;     // [grids][n] processing order from gm_bin (HomeArgs)
+    const int32_t* tile_start;          // the bins' CSR rows
+    const uint32_t* pair_gauss;         // tile-sorted entries, GM_HOME_BIT on home entries
+    int64_t tile_lo[GM_MAX_GRIDS];      // global tile range of each listed grid
+    int64_t tile_hi[GM_MAX_GRIDS];
+    int64_t n_pairs;                    // total entries (sizes the launch)
 };
 hipError_t launch_backward_partials(const BackwardArgs& a, hipStream_t s);
 
@@ -136,7 +129,7 @@ struct ChainArgs {
     const float* quat;
     const float* log_scale;
     const float* logit;
-    const float* records;
+    const int32_t* tile_count;  // [grids][n]: 0 exactly for an empty box
     const float* grid_grads;
     float* g_mean;
     float* g_quat;

@@ -173,6 +173,13 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a)
             }
             a.tile_count[(size_t)k * a.n + i] = cnt;
             if (vol) atomicAdd(&s_vol[k], vol);
+            // the backward visits only Gaussians listed in some tile: the grid-frame
+            // partials of an empty box are its zeros, written here
+            if (!nonempty && a.grid_grads) {
+                float2* o = reinterpret_cast<float2*>(a.grid_grads + ((size_t)k * a.n + i) * 10);
+#pragma unroll
+                for (int t = 0; t < 5; ++t) o[t] = make_float2(0.0f, 0.0f);
+            }
         }
     }
     __syncthreads();

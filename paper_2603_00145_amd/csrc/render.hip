@@ -134,7 +134,7 @@ __global__ __launch_bounds__(64) void k_render(const RenderArgs a)
         __syncthreads();
         bool small = false;
         if (lane < nb) {
-            const int gid = pg[b0 + lane];
+            const int gid = (int)((uint32_t)pg[b0 + lane] & GM_ID_MASK);
             const float4* src = reinterpret_cast<const float4*>(recbase + (size_t)gid * 16);
             const float4 r0 = src[0], r1 = src[1], r2 = src[2], r3 = src[3];
             const int lox = __float_as_int(r2.z), loy = __float_as_int(r2.w);

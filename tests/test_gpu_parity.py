@@ -79,7 +79,19 @@ def check_bins_exact(api, b, g, grids):
         assert b.pair_count(k) == vol, f"grid {k}: box volume"
     assert b.n_pairs == len(gids)
     assert np.array_equal(b.tile_start.cpu().numpy(), start)
-    assert np.array_equal(b.pair_gauss[:b.n_pairs].cpu().numpy(), gids)
+    raw = b.pair_gauss[:b.n_pairs].cpu().numpy().view(np.uint32)
+    assert np.array_equal((raw & 0x7FFFFFFF).astype(np.int64), gids)
+    # bit 31 marks exactly the entry whose tile holds the Gaussian's box lower corner
+    T = np.asarray(tile)
+    bases = np.cumsum([0] + [recipe.n_tiles(gr, tile) for gr in grids])
+    entry_tile = np.repeat(np.arange(bases[-1]), np.diff(start))
+    entry_grid = np.searchsorted(bases, entry_tile, side="right") - 1
+    home = np.zeros((len(grids), g.n), np.int64)
+    for k, ((lo, hi, ne, cnt, vol), gr) in enumerate(zip(per, grids)):
+        ntx, nty = -(-gr.nx // T[0]), -(-gr.ny // T[1])
+        t = lo // T
+        home[k] = np.where(ne, bases[k] + (t[:, 2] * nty + t[:, 1]) * ntx + t[:, 0], -1)
+    assert np.array_equal(raw >> 31 == 1, home[entry_grid, gids] == entry_tile)
 
 
 @pytest.mark.parametrize("seed", [0, 1])
@@ -104,27 +116,6 @@ def test_bins_bit_exact_c64(api):
     check_bins_exact(api, b, w.gauss, grids)
     # the per-grid pair totals gm_bin hands back on the host equal the device array
     assert b.box_pairs_host == [b.pair_count(k) for k in range(len(grids))]
-
-
-def test_spatial_order(api):
-    """gm_bin's per-grid processing order for the backward: a permutation of the Gaussians
-    grouped by the tile holding their box's lower corner (tiles ascending), empty boxes
-    last."""
-    g, grids, rng = ragged_problem(1, n_g=500)
-    p = api.GaussParams.from_host(g)
-    b = api.Bins(p.n, grids)
-    b.bin(p)
-    torch.cuda.synchronize()
-    order = b.scratch[:len(grids) * g.n].cpu().numpy().astype(np.int64).reshape(len(grids), g.n)
-    T = np.asarray(api._lib.tile_dims())
-    for k, grid in enumerate(grids):
-        lo, hi, ne, _ = recipe.boxes(g.mean, g.quat, g.log_scale, g.logit, grid)
-        assert np.array_equal(np.sort(order[k]), np.arange(g.n))
-        ntx, nty = -(-grid.nx // T[0]), -(-grid.ny // T[1])
-        t = lo // T
-        home = np.where(ne, (t[:, 2] * nty + t[:, 1]) * ntx + t[:, 0], np.iinfo(np.int64).max)
-        h = home[order[k]]
-        assert np.all(np.diff(h) >= 0)
 
 
 def render_ref(g, grids):

@@ -64,7 +64,7 @@ def test_full_size_sampled_parity(mods, name):
     torch.cuda.synchronize()
     tile = _lib.tile_dims()
     ts = b.tile_start.cpu().numpy()
-    pg = b.pair_gauss[:b.n_pairs].cpu().numpy()
+    pg = (b.pair_gauss[:b.n_pairs].cpu().numpy().view(np.uint32) & 0x7FFFFFFF).astype(np.int64)
     prep = gauss.prepare(w.gauss, w.stacks)
     for k, (grid, (gt, lo, hi, ne, _)) in enumerate(zip(w.stacks, prep)):
         glo, ghi = (t.cpu().numpy() for t in b.boxes(k))

@@ -45,6 +45,29 @@ def alu_peak_tflops(flop_per_pair, instr_per_pair):
     return LANE_OPS / instr_per_pair * flop_per_pair / 1e12
 
 
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from its committed counter summary, if that summary
+    was taken on the current source of the kernel (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic_c256.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            key, _, val = line.partition(":")
+            if key in ("traffic_bytes", "kernel", "source_sha256", "sources"):
+                fields[key] = val.strip()
+    if fields.get("kernel") != kernel or "sources" not in fields:
+        return None
+    from paper_2603_00145_amd.profile_summary import source_digest
+    try:
+        if source_digest(fields["sources"].split()) != fields.get("source_sha256"):
+            return None
+    except OSError:
+        return None
+    return float(fields["traffic_bytes"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -180,7 +203,7 @@ def main():
         "fwd_bwd_evals_per_s": pairs / ((stage_ms["render"] + bwd_ms) / 1e3),
         "final_loss": float(loss),
         "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": recorded_traffic(kname),
                      "flop_per_pair": flop, "avg_kernel_ms": stage_ms[dom]},
         "cpu_baseline": cpu,
     }

@@ -316,6 +316,11 @@ typedef struct gm_ws_grads { /* FP32, same shapes; accumulated (+=) */
 gm_status gm_ws_gather(const gm_grid* stacks, int32_t n_stacks, const float* const* stack_data,
                        const float* means, int64_t n, float spacing, uint16_t* patches,
                        gm_stream stream);
+/* Training targets from a reconstruction's parameters: sigma_target[i] = the covariance
+ * R(q_i/|q_i|) diag(e^{2 log_scale_i}) R^T (Eq. 3) as (xx, yy, zz, xy, xz, yz), FP64 inside,
+ * rounded to float.  log_scale [n][3], quat [n][4]. */
+gm_status gm_ws_targets(const float* log_scale, const float* quat, int64_t n,
+                        float* sigma_target, gm_stream stream);
 /* [host out] workspace bytes for a batch of n. */
 gm_status gm_ws_workspace(int64_t n, size_t* bytes);
 /* Inference: log_scale_out [n][3], quat_out [n][4], logit_out [n]. */

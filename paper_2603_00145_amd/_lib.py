@@ -121,6 +121,7 @@ _SIGS = [
     ("gm_f32_to_bf16", ctypes.c_int, [P, P, ctypes.c_int64, P]),
     ("gm_ws_gather", ctypes.c_int, [ctypes.POINTER(GmGrid), ctypes.c_int32, ctypes.POINTER(P), P,
                                      ctypes.c_int64, ctypes.c_float, P, P]),
+    ("gm_ws_targets", ctypes.c_int, [P, P, ctypes.c_int64, P, P]),
     ("gm_ws_workspace", ctypes.c_int, [ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
     ("gm_ws_forward", ctypes.c_int, [ctypes.POINTER(GmWsNet), P, ctypes.c_int64, P, P, P, P, P,
                                       P, ctypes.c_size_t, P]),

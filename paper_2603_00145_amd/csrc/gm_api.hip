@@ -861,6 +861,20 @@ gm_status gm_ws_gather(const gm_grid* stacks, int32_t n_stacks, const float* con
     return GM_OK;
 }
 
+gm_status gm_ws_targets(const float* log_scale, const float* quat, int64_t n,
+                        float* sigma_target, gm_stream stream)
+{
+    g_err.clear();
+    if (n < 0) return fail(GM_ERR_INVALID_ARGUMENT, "n < 0");
+    if (n == 0) return GM_OK;
+    REQ_PTR(log_scale, "log_scale");
+    REQ_PTR(quat, "quat");
+    REQ_PTR(sigma_target, "sigma_target");
+    GM_HIP(launch_ws_targets(log_scale, quat, n, sigma_target,
+                             reinterpret_cast<hipStream_t>(stream)), "ws targets");
+    return GM_OK;
+}
+
 gm_status gm_ws_workspace(int64_t n, size_t* bytes)
 {
     g_err.clear();

@@ -251,6 +251,8 @@ struct WsGrads {
 int ws_kpad(int layer);
 size_t ws_part_floats(int64_t B);
 hipError_t launch_ws_gather(const WsGatherArgs& a, hipStream_t s);
+hipError_t launch_ws_targets(const float* ls, const float* quat, int64_t n, float* sig6,
+                             hipStream_t s);
 hipError_t launch_ws_forward(const WsNet& net, const uint16_t* X0, int64_t B, const WsActs& w,
                              const WsHeadArgs& head, hipStream_t s);
 hipError_t launch_ws_backward(const WsNet& net, const uint16_t* X0, int64_t B, const WsActs& w,

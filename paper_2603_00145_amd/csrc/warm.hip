@@ -383,6 +383,34 @@ __global__ __launch_bounds__(256) void k_ws_head(const WsHeadArgs a)
     }
 }
 
+// Training targets: Sigma = R(q/|q|) diag(e^{2 s}) R^T per Gaussian in FP64, stored as
+// (xx, yy, zz, xy, xz, yz).
+__global__ __launch_bounds__(256) void k_ws_targets(const float* __restrict__ ls,
+                                                    const float* __restrict__ quat, int64_t n,
+                                                    float* __restrict__ sig6)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double q[4] = {quat[4 * i], quat[4 * i + 1], quat[4 * i + 2], quat[4 * i + 3]};
+    const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const double qh[4] = {q[0] / qn, q[1] / qn, q[2] / qn, q[3] / qn};
+    double R[9];
+    rot_from_q(qh, R);
+    const double S2[3] = {exp(2.0 * (double)ls[3 * i]), exp(2.0 * (double)ls[3 * i + 1]),
+                          exp(2.0 * (double)ls[3 * i + 2])};
+    auto sig = [&](int p, int r) {
+        return R[3 * p] * S2[0] * R[3 * r] + R[3 * p + 1] * S2[1] * R[3 * r + 1] +
+               R[3 * p + 2] * S2[2] * R[3 * r + 2];
+    };
+    float* o = sig6 + 6 * i;
+    o[0] = (float)sig(0, 0);
+    o[1] = (float)sig(1, 1);
+    o[2] = (float)sig(2, 2);
+    o[3] = (float)sig(0, 1);
+    o[4] = (float)sig(0, 2);
+    o[5] = (float)sig(1, 2);
+}
+
 // head weight gradients: dWl[j][c] += sum_b dout[b][j] a4[b][c]; dbl[j] += sum_b dout[b][j]
 __global__ __launch_bounds__(256) void k_ws_head_grad(const float* __restrict__ dout,
                                                       const float* __restrict__ a4, int64_t n,
@@ -504,5 +532,14 @@ hipError_t launch_ws_backward(const WsNet& net, const uint16_t* X0, int64_t B, c
     conv_bwd_w<G2>(w.dz[1], w.a[0], B, w.part, g.w[1], g.b[1], s);
     conv_bwd_x<G2>(net.w[1], w.dz[1], B, w.z[0], w.dz[0], s);
     conv_bwd_w<G1>(w.dz[0], X0, B, w.part, g.w[0], g.b[0], s);
+    return hipGetLastError();
+}
+
+hipError_t launch_ws_targets(const float* ls, const float* quat, int64_t n, float* sig6,
+                             hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ws_targets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ls,
+                       quat, n, sig6);
     return hipGetLastError();
 }

@@ -1,0 +1,154 @@
+"""Turn rocprofv3 outputs into the short text summaries kept under profiles/.
+
+    python -m paper_2603_00145_amd.profile_summary stats  --dir D --out F --command C
+    python -m paper_2603_00145_amd.profile_summary traffic --fetch-dir D1 --write-dir D2
+           --kernel k_render --source paper_2603_00145_amd/csrc/render.hip --calib-mib 1024
+           --out F --command C
+
+`stats` summarises a `--kernel-trace --stats` run (per-kernel calls and durations of this
+library's kernels).  `traffic` takes one `--pmc FETCH_SIZE` run and one `--pmc WRITE_SIZE`
+run of the same program (which ran a plain streaming kernel, torch.neg over calib-mib MiB,
+before its timed steps), scales the kernel's per-dispatch counters by what the counters read
+for that streaming kernel (which reads and writes exactly calib-mib MiB), and records the
+SHA-256 of the kernel's source so that a reader can tell whether the figure still applies.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import os
+import statistics
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+OUR_KERNELS = ("k_", "(anonymous namespace)::k_")
+
+
+def source_digest(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _short(name: str) -> str:
+    n = name.split("(")[0] if not name.startswith("(anonymous") else name.split("::")[1].split("(")[0]
+    return n.replace("void ", "").strip()
+
+
+def _rows(d, pattern):
+    files = glob.glob(os.path.join(d, "**", pattern), recursive=True)
+    if not files:
+        sys.exit(f"no {pattern} under {d}")
+    with open(files[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def counters(d, counter):
+    """{dispatch id: (kernel name, value)} of one counter."""
+    out = {}
+    for r in _rows(d, "*counter_collection.csv"):
+        if r["Counter_Name"] == counter:
+            out[r["Dispatch_Id"]] = (r["Kernel_Name"], float(r["Counter_Value"]))
+    return out
+
+
+def per_kernel(vals, kernel):
+    x = [v for (n, v) in vals.values() if _short(n) == kernel]
+    if not x:
+        sys.exit(f"kernel {kernel} not found")
+    return statistics.mean(x), len(x)
+
+
+def calib(vals):
+    """Counter value of the calibration kernel (the largest neg kernel dispatch)."""
+    x = [v for (n, v) in vals.values() if "neg" in n.lower()]
+    if not x:
+        sys.exit("calibration kernel (torch.neg) not found")
+    return max(x)
+
+
+def cmd_traffic(a):
+    f_vals = counters(a.fetch_dir, "FETCH_SIZE")
+    w_vals = counters(a.write_dir, "WRITE_SIZE")
+    fk, nf = per_kernel(f_vals, a.kernel)
+    wk, nw = per_kernel(w_vals, a.kernel)
+    cal_bytes = a.calib_mib * 1024.0 * 1024.0
+    cf, cw = calib(f_vals), calib(w_vals)         # KiB
+    sf, sw = cal_bytes / (cf * 1024.0), cal_bytes / (cw * 1024.0)
+    traffic = fk * 1024.0 * sf + wk * 1024.0 * sw
+    digest = source_digest(a.source)
+    txt = f"""# HBM traffic of {a.kernel} ({a.workload})
+
+Commands (from the repository root on the GPU machine, run after `cd /tmp`):
+
+    {a.command_fetch}
+    {a.command_write}
+
+| counter | {a.kernel}, KiB per dispatch (mean of {min(nf, nw)}) | calibration kernel (torch.neg, {a.calib_mib} MiB in + out), KiB | scale |
+|---|---|---|---|
+| FETCH_SIZE | {fk:.1f} | {cf:.1f} | {sf:.4f} |
+| WRITE_SIZE | {wk:.1f} | {cw:.1f} | {sw:.4f} |
+
+HBM bytes per launch = FETCH x scale + WRITE x scale:
+
+traffic_bytes: {traffic:.0f}
+kernel: {a.kernel}
+source_sha256: {digest}
+sources: {' '.join(a.source)}
+"""
+    with open(a.out, "w") as f:
+        f.write(txt)
+    print(txt)
+
+
+def cmd_stats(a):
+    rows = _rows(a.dir, "*kernel_stats.csv")
+    lines = []
+    for r in rows:
+        name = _short(r["Name"])
+        if not name.startswith("k_"):
+            continue
+        lines.append((float(r["TotalDurationNs"]), name, int(r["Calls"]),
+                      float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3))
+    lines.sort(reverse=True)
+    txt = f"# Kernel time summary: {a.workload}\n\nCommand (from the repository root on the GPU " \
+          f"machine, run after `cd /tmp`):\n\n    {a.command}\n\nLibrary kernels only.\n\n" \
+          "| kernel | calls | avg us | min us | max us |\n|---|---|---|---|---|\n"
+    for _, name, calls, avg, mn, mx in lines:
+        txt += f"| {name} | {calls} | {avg:.1f} | {mn:.1f} | {mx:.1f} |\n"
+    if a.note:
+        txt += "\n" + a.note + "\n"
+    with open(a.out, "w") as f:
+        f.write(txt)
+    print(txt)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch-dir", required=True)
+    t.add_argument("--write-dir", required=True)
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--source", nargs="+", required=True)
+    t.add_argument("--calib-mib", type=int, default=1024)
+    t.add_argument("--workload", default="training iteration, 256^3 workload")
+    t.add_argument("--command-fetch", required=True)
+    t.add_argument("--command-write", required=True)
+    t.add_argument("--out", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("--dir", required=True)
+    s.add_argument("--workload", default="training iteration, 256^3 workload")
+    s.add_argument("--command", required=True)
+    s.add_argument("--note", default="")
+    s.add_argument("--out", required=True)
+    a = ap.parse_args()
+    {"traffic": cmd_traffic, "stats": cmd_stats}[a.cmd](a)
+
+
+if __name__ == "__main__":
+    main()

@@ -138,16 +138,14 @@ class WarmStartNet:
 
 
 def sym6(s: torch.Tensor, q: torch.Tensor) -> torch.Tensor:
-    """Covariance (xx, yy, zz, xy, xz, yz) of log-scales s and quaternions q (float64 host
-    math on device tensors; used only to build training targets)."""
-    qn = q / q.norm(dim=1, keepdim=True)
-    w, x, y, z = qn.unbind(1)
-    R = torch.stack([
-        torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
-        torch.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
-        torch.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1)], 1)
-    S = R @ torch.diag_embed(torch.exp(2 * s)) @ R.transpose(1, 2)
-    return torch.stack([S[:, 0, 0], S[:, 1, 1], S[:, 2, 2], S[:, 0, 1], S[:, 0, 2], S[:, 1, 2]], 1)
+    """Covariance (xx, yy, zz, xy, xz, yz) of log-scales s [n,3] and quaternions q [n,4]
+    (gm_ws_targets): the warm-start training targets."""
+    s = s.float().contiguous()
+    q = q.float().contiguous()
+    out = torch.empty((s.shape[0], 6), dtype=torch.float32, device=s.device)
+    check(load().gm_ws_targets(ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(q.data_ptr()),
+                               s.shape[0], ctypes.c_void_p(out.data_ptr()), api._stream()))
+    return out
 
 
 def _say(*a):
@@ -187,7 +185,7 @@ def run_experiment(n_train=64, n_test=16, train_vox=128, test_vox=256, g_train=5
         pats.append(WarmStartNet.gather(stacks, data, r.p.mean, h / 4))
         s0s.append(init_s)
         l0s.append(init_l)
-        sigs.append(sym6(r.p.log_scale.double(), r.p.quat.double()).float().contiguous())
+        sigs.append(sym6(r.p.log_scale, r.p.quat))
         lts.append(r.p.logit.clone())
         _say(f"# train case {i + 1}/{n_train} done ({time.time() - t0:.0f}s)")
     P = torch.cat(pats)

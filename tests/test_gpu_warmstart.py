@@ -47,6 +47,19 @@ def test_gather_matches_oracle(mods):
     assert normwise(bf16_to_f64(got), ref) <= TOL_BF16
 
 
+def test_targets_match_oracle(mods):
+    """gm_ws_targets: training-target covariances against the oracle's FP64 covariance."""
+    api, ws = mods
+    rng = np.random.default_rng(4)
+    n = 1000
+    s = rng.normal(-3.5, 0.4, (n, 3)).astype(np.float32)
+    q = rng.normal(size=(n, 4)).astype(np.float32)
+    got = ws.sym6(torch.from_numpy(s).cuda(), torch.from_numpy(q).cuda()).cpu().numpy()
+    S = owarm.covariance(s.astype(np.float64), q.astype(np.float64))
+    ref = np.stack([S[:, 0, 0], S[:, 1, 1], S[:, 2, 2], S[:, 0, 1], S[:, 0, 2], S[:, 1, 2]], 1)
+    assert normwise(got, ref) <= 1e-6
+
+
 def test_forward_and_gradients_match_oracle(mods):
     api, ws = mods
     rng = np.random.default_rng(1)

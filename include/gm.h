@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define GM_ABI_VERSION 2
+#define GM_ABI_VERSION 3
 #define GM_MAX_GRIDS 8
 #define GM_RECORD_FLOATS 16       /* floats per (grid, Gaussian) record                */
 #define GM_GRID_GRAD_FLOATS 10    /* floats per (grid, Gaussian) backward partial      */
@@ -124,6 +124,8 @@ typedef struct gm_bins {
                                             the tile lists refuse bins without them      */
     int64_t box_pairs[GM_MAX_GRIDS];     /* contributing (Gaussian, voxel) pairs per grid
                                             of the last gm_bin (= box_volume)            */
+    int64_t list_start[GM_MAX_GRIDS + 1]; /* pair_gauss entries of grid k are
+                                            [list_start[k], list_start[k + 1])           */
     double cutoff_sigma;
 } gm_bins;
 

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgm.so")
 
 GM_MAX_GRIDS = 8
-ABI_VERSION = 2          # struct layouts of include/gm.h this binding mirrors
+ABI_VERSION = 3          # struct layouts of include/gm.h this binding mirrors
 GM_RECORD_FLOATS = 16
 GM_GRID_GRAD_FLOATS = 10
 GM_REDUCE_WORKSPACE_BYTES = 16384
@@ -55,6 +55,7 @@ class GmBins(ctypes.Structure):
                 ("grids", GmGrid * GM_MAX_GRIDS),
                 ("tile_base", ctypes.c_int64 * (GM_MAX_GRIDS + 1)),
                 ("n_pairs", ctypes.c_int64), ("box_pairs", ctypes.c_int64 * GM_MAX_GRIDS),
+                ("list_start", ctypes.c_int64 * (GM_MAX_GRIDS + 1)),
                 ("cutoff_sigma", ctypes.c_double)]
 
 

@@ -21,7 +21,6 @@
 namespace {
 
 __device__ __forceinline__ int sgpr(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ int64_t sgpr64(int v) { return (int64_t)__builtin_amdgcn_readfirstlane(v); }
 
 // Sum of v over each 32-lane half of the wavefront: DPP adds within rows of 16, then row 0
 // into row 1 and row 2 into row 3.  Lane 31 ends with the first half's total, lane 63 with
@@ -53,15 +52,16 @@ __device__ __forceinline__ float half_sum(float v)
 // compile-time constant in the unrolled loop).  In the z range both halves share, the loads
 // need no per-lane care; past the shorter box, a half's loads are clamped and zeroed.
 // Gaussians with an empty box are in no list; gm_bin wrote their zeros.
-__global__ __launch_bounds__(256) void k_partials(const BackwardArgs a, int blocks_per_grid)
+__global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
 {
     const int lane = threadIdx.x & 63;
     const int hl = lane & 31;
     const int lin = xcd_remap(blockIdx.x, gridDim.x);
-    const int kk = lin / blocks_per_grid;                  // listed grid
-    const int64_t e0 = sgpr64(a.tile_start[a.tile_lo[kk]]);
-    const int64_t e1 = sgpr64(a.tile_start[a.tile_hi[kk]]);
-    const int64_t w0 = e0 + ((int64_t)(lin - kk * blocks_per_grid) * 4 + (threadIdx.x >> 6)) * 64;
+    int kk = 0;                                            // listed grid of this block
+#pragma unroll 1
+    while (kk + 1 < a.n_ids && lin >= a.block_start[kk + 1]) ++kk;
+    const int64_t e1 = a.entry_hi[kk];
+    const int64_t w0 = a.entry_lo[kk] + ((int64_t)(lin - a.block_start[kk]) * 4 + (threadIdx.x >> 6)) * 64;
     if (w0 >= e1) return;  // wave-uniform
     const int64_t entry = w0 + lane;
     const uint32_t v = entry < e1 ? a.pair_gauss[entry] : 0u;
@@ -364,16 +364,20 @@ __global__ __launch_bounds__(128) void k_chain(const ChainArgs a)
 
 }  // namespace
 
-hipError_t launch_backward_partials(const BackwardArgs& a, hipStream_t s)
+hipError_t launch_backward_partials(const BackwardArgs& a_in, hipStream_t s)
 {
-    if (a.n == 0 || a.n_ids == 0) return hipSuccess;
-    if (a.n_pairs <= 0) return hipSuccess;
-    // 4 wavefronts x 64 entries per block; every listed grid gets enough blocks for the
-    // whole list (a grid's own share is only known on the device; surplus waves exit)
-    const int64_t per_grid = (a.n_pairs + 255) / 256;
-    const int64_t blocks = per_grid * a.n_ids;
-    if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_partials, dim3((unsigned)blocks), dim3(256), 0, s, a, (int)per_grid);
+    if (a_in.n == 0 || a_in.n_ids == 0) return hipSuccess;
+    // 4 wavefronts x 64 list entries per block, blocks laid out grid after grid
+    BackwardArgs a = a_in;
+    int64_t blocks = 0;
+    for (int k = 0; k < a.n_ids; ++k) {
+        a.block_start[k] = (int32_t)blocks;
+        blocks += (a.entry_hi[k] - a.entry_lo[k] + 255) / 256;
+        if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    }
+    a.block_start[a.n_ids] = (int32_t)blocks;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_partials, dim3((unsigned)blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -259,14 +259,15 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* keys, int64
 }
 
 // One thread per grid: copy the box-volume totals accumulated in the scratch report block
-// to the caller's box_volume array, and the scan's grand total next to them, so that gm_bin
-// reads everything it reports back in one device-to-host copy.
-__global__ void k_bin_report(BinReport* rep, const int64_t* scan_end, int64_t* box_volume,
-                             int n_grids)
+// to the caller's box_volume array, and each grid's first list entry (the scan of the tile
+// counts at the grid's first Gaussian; emission is grid-major and the sort keeps grids apart)
+// next to them, so that gm_bin reads everything it reports back in one device-to-host copy.
+__global__ void k_bin_report(BinReport* rep, const int64_t* offsets, int64_t n,
+                             int64_t* box_volume, int n_grids)
 {
     const int k = threadIdx.x;
     if (k < n_grids) box_volume[k] = (int64_t)rep->box_volume[k];
-    if (k == 0) rep->total = *scan_end;
+    if (k <= n_grids) rep->grid_start[k] = offsets[(int64_t)k * n];
 }
 
 inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -282,10 +283,11 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_bin_report(BinReport* rep, const int64_t* scan_end, int64_t* box_volume,
-                             int n_grids, hipStream_t s)
+hipError_t launch_bin_report(BinReport* rep, const int64_t* offsets, int64_t n,
+                             int64_t* box_volume, int n_grids, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bin_report, dim3(1), dim3(64), 0, s, rep, scan_end, box_volume, n_grids);
+    hipLaunchKernelGGL(k_bin_report, dim3(1), dim3(64), 0, s, rep, offsets, n, box_volume,
+                       n_grids);
     return hipGetLastError();
 }
 

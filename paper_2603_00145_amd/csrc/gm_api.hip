@@ -405,15 +405,17 @@ gm_status gm_bin(const gm_gaussians* g, const gm_grid* grids, int32_t n_grids,
     GM_HIP(launch_preprocess(pa, s), "preprocess");
     GM_HIP(launch_scan_i32_to_i64(bins->tile_count, sc.offsets, m, sc.scan_ws, s), "scan");
 
-    GM_HIP(launch_bin_report(sc.report, sc.offsets + m, bins->box_volume, n_grids, s), "report");
+    GM_HIP(launch_bin_report(sc.report, sc.offsets, n, bins->box_volume, n_grids, s), "report");
     BinReport rep;
     GM_HIP(hipMemcpyAsync(&rep, sc.report, sizeof rep, hipMemcpyDeviceToHost, s), "read report");
     GM_HIP(hipStreamSynchronize(s), "synchronise");
-    const int64_t total = rep.total;
+    const int64_t total = rep.grid_start[n_grids];
     const uint32_t flags = rep.flags[0];
     *n_pairs = total;
     bins->n_pairs = total;
     for (int k = 0; k < GM_MAX_GRIDS; ++k) bins->box_pairs[k] = k < n_grids ? (int64_t)rep.box_volume[k] : 0;
+    for (int k = 0; k <= GM_MAX_GRIDS; ++k)
+        bins->list_start[k] = rep.grid_start[k < n_grids ? k : n_grids];
     if (total > bins->capacity_pairs) {
         fail(GM_ERR_CAPACITY, "%lld (tile, Gaussian) pairs exceed capacity %lld", (long long)total,
              (long long)bins->capacity_pairs);
@@ -666,9 +668,7 @@ gm_status backward_impl(const gm_gaussians* g, const gm_bins* bins, const int32_
     ba.n_ids = n_ids;
     ba.records = bins->records;
     ba.grid_grads = bins->grid_grads;
-    ba.tile_start = bins->tile_start;
     ba.pair_gauss = reinterpret_cast<const uint32_t*>(bins->pair_gauss);
-    ba.n_pairs = bins->n_pairs;
     for (int k = 0; k < n_ids; ++k) {
         const gm_grid& gr = bins->grids[grid_ids[k]];
         if (partials) {
@@ -676,8 +676,8 @@ gm_status backward_impl(const gm_gaussians* g, const gm_bins* bins, const int32_
             ba.dl_di[k] = dl_di[k];
         }
         ba.grid_index[k] = grid_ids[k];
-        ba.tile_lo[k] = bins->tile_base[grid_ids[k]];
-        ba.tile_hi[k] = bins->tile_base[grid_ids[k] + 1];
+        ba.entry_lo[k] = bins->list_start[grid_ids[k]];
+        ba.entry_hi[k] = bins->list_start[grid_ids[k] + 1];
         ba.nx[k] = gr.nx;
         ba.ny[k] = gr.ny;
         ba.nz[k] = gr.nz;

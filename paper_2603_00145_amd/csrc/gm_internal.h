@@ -38,10 +38,10 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s
 struct BinReport {
     uint32_t flags[4];
     unsigned long long box_volume[GM_MAX_GRIDS];
-    int64_t total;
+    int64_t grid_start[GM_MAX_GRIDS + 1];  // first list entry of each grid; [n_grids] = total
 };
-hipError_t launch_bin_report(BinReport* rep, const int64_t* scan_end, int64_t* box_volume,
-                             int n_grids, hipStream_t s);
+hipError_t launch_bin_report(BinReport* rep, const int64_t* offsets, int64_t n,
+                             int64_t* box_volume, int n_grids, hipStream_t s);
 
 struct PreprocessArgs {
     int64_t n;
@@ -113,11 +113,10 @@ struct BackwardArgs {
     int32_t grid_index[GM_MAX_GRIDS];
     int32_t nx[GM_MAX_GRIDS], ny[GM_MAX_GRIDS], nz[GM_MAX_GRIDS];
     const float* dl_di[GM_MAX_GRIDS];
-    const int32_t* tile_start;          // the bins' CSR rows
     const uint32_t* pair_gauss;         // tile-sorted entries, GM_HOME_BIT on home entries
-    int64_t tile_lo[GM_MAX_GRIDS];      // global tile range of each listed grid
-    int64_t tile_hi[GM_MAX_GRIDS];
-    int64_t n_pairs;                    // total entries (sizes the launch)
+    int64_t entry_lo[GM_MAX_GRIDS];     // list entries [entry_lo, entry_hi) of each listed grid
+    int64_t entry_hi[GM_MAX_GRIDS];
+    int32_t block_start[GM_MAX_GRIDS + 1];  // first block of each listed grid; [n_ids] = total
 };
 hipError_t launch_backward_partials(const BackwardArgs& a, hipStream_t s);
 

@@ -79,6 +79,9 @@ def check_bins_exact(api, b, g, grids):
         assert b.pair_count(k) == vol, f"grid {k}: box volume"
     assert b.n_pairs == len(gids)
     assert np.array_equal(b.tile_start.cpu().numpy(), start)
+    # each grid's list range as gm_bin reports it on the host
+    per_grid = [int(cnt.sum()) for (_, _, _, cnt, _) in per]
+    assert [int(b._s.list_start[k]) for k in range(len(grids) + 1)] == list(np.cumsum([0] + per_grid))
     raw = b.pair_gauss[:b.n_pairs].cpu().numpy().view(np.uint32)
     assert np.array_equal((raw & 0x7FFFFFFF).astype(np.int64), gids)
     # bit 31 marks exactly the entry whose tile holds the Gaussian's box lower corner

@@ -22,10 +22,8 @@ namespace {
 
 __device__ __forceinline__ int sgpr(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Sum of v over each 32-lane half of the wavefront: DPP adds within rows of 16, then row 0
-// into row 1 and row 2 into row 3.  Lane 31 ends with the first half's total, lane 63 with
-// the second's.
-__device__ __forceinline__ float half_sum(float v)
+// Sum of v over each 16-lane row of the wavefront (every lane of the row ends with it).
+__device__ __forceinline__ float row_sum(float v)
 {
     int xi;
     xi = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false);  // xor 1
@@ -36,8 +34,6 @@ __device__ __forceinline__ float half_sum(float v)
     v += __int_as_float(xi);
     xi = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false); // mirror
     v += __int_as_float(xi);
-    xi = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false); // bcast15
-    v += __int_as_float(xi);
     return v;
 }
 
@@ -45,17 +41,20 @@ __device__ __forceinline__ float half_sum(float v)
 // the Gaussians whose home entry (the tile holding the box's lower corner) is among them:
 // every Gaussian of the grid exactly once, in tile order, so neighbouring Gaussians run
 // together (and on one XCD) and the dL/dI they gather is served from the same L2 lines.
-// Two Gaussians at a time, one per 32-lane half.  A half maps its lanes onto chunks of 32
-// (x, y) columns of the Gaussian's box and walks each column along z: all of the column's
-// dL/dI values are loaded first, then step k costs two FMAs for Q_k = A + k (B + k kzz), one
-// exp2, one multiply and three adds for the column sums of g E, k g E and k^2 g E (k is a
-// compile-time constant in the unrolled loop).  In the z range both halves share, the loads
-// need no per-lane care; past the shorter box, a half's loads are clamped and zeroed.
-// Gaussians with an empty box are in no list; gm_bin wrote their zeros.
+// Four Gaussians at a time, one per 16-lane row.  A row maps its lanes onto chunks of 16
+// (x, z) columns of the Gaussian's box and walks each column along y (for thick-slice
+// stacks the box is longest in-plane, so this gives the fewest chunks and the longest walks).
+// All of a column's dL/dI values are loaded first (in the y range the four boxes share, from
+// a wave-uniform base pointer per step: no per-lane address arithmetic); step k then costs
+// Q_k = A + k (B + k kyy) (two FMAs), one exp2, one multiply and three adds for the column
+// sums of g E, k g E and k^2 g E (k a compile-time constant in the unrolled loop).  Past a
+// shorter box, a row's loads are clamped and zeroed.  Gaussians with an empty box are in no
+// list; gm_bin wrote their zeros.
 __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
 {
     const int lane = threadIdx.x & 63;
-    const int hl = lane & 31;
+    const int ql = lane & 15;          // lane within the row
+    const int row = lane >> 4;
     const int lin = xcd_remap(blockIdx.x, gridDim.x);
     int kk = 0;                                            // listed grid of this block
 #pragma unroll 1
@@ -67,17 +66,26 @@ __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
     const uint32_t v = entry < e1 ? a.pair_gauss[entry] : 0u;
     uint64_t todo = __ballot(entry < e1 && (v & GM_HOME_BIT));
     const int gi = a.grid_index[kk];
+    const int nx = a.nx[kk], ny = a.ny[kk];
+    const float* __restrict__ g = a.dl_di[kk];
 #pragma unroll 1
     while (todo) {
-        const int ia = __builtin_ctzll(todo);
-        todo &= todo - 1;
-        const int ib = todo ? __builtin_ctzll(todo) : ia;
-        const bool has_b = todo != 0;
-        if (has_b) todo &= todo - 1;
-        const uint32_t va = __builtin_amdgcn_readlane(v, ia);
-        const uint32_t vb = __builtin_amdgcn_readlane(v, ib);
-        const bool gvalid = lane < 32 || has_b;
-        const int64_t gid = min((int64_t)((lane < 32 ? va : vb) & GM_ID_MASK), a.n - 1);
+        // the next (up to) four home entries, one per row
+        uint32_t mine = 0u;
+        bool gvalid = false;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (todo) {
+                const int ib = __builtin_ctzll(todo);
+                todo &= todo - 1;
+                const uint32_t vb = __builtin_amdgcn_readlane(v, ib);
+                if (row == r) {
+                    mine = vb;
+                    gvalid = true;
+                }
+            }
+        }
+        const int64_t gid = min((int64_t)(mine & GM_ID_MASK), a.n - 1);
         float4 r0 = make_float4(0, 0, 0, 0), r1 = r0, r2 = r0, r3 = r0;
         if (gvalid) {
             const float4* rp = reinterpret_cast<const float4*>(a.records + ((size_t)gi * a.n + gid) * 16);
@@ -99,59 +107,58 @@ __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
         const float kxx = nonempty ? r1.x : 0.0f, kyy = nonempty ? r1.y : 0.0f;
         const float kzz = nonempty ? r1.z : 0.0f, kxy = nonempty ? r1.w : 0.0f;
         const float kxz = nonempty ? r2.x : 0.0f, kyz = nonempty ? r2.y : 0.0f;
-        const int fp = wx * wy;                       // (x, y) footprint of the box
-        const int chunks = (fp + 31) >> 5;
-        const int max_chunks = max(__builtin_amdgcn_readlane(chunks, 0),
-                                   __builtin_amdgcn_readlane(chunks, 32));
-        const int max_wz = max(__builtin_amdgcn_readlane(wz, 0), __builtin_amdgcn_readlane(wz, 32));
-        // column f -> (x, y) = (f mod wx, f div wx) as floor((f + 1/2) / wx): the fraction
+        const int fp = wx * wz;                       // (x, z) footprint of the box
+        const int chunks = (fp + 15) >> 4;
+        const int max_chunks = max(max(__builtin_amdgcn_readlane(chunks, 0), __builtin_amdgcn_readlane(chunks, 16)),
+                                   max(__builtin_amdgcn_readlane(chunks, 32), __builtin_amdgcn_readlane(chunks, 48)));
+        const int max_wy = max(max(__builtin_amdgcn_readlane(wy, 0), __builtin_amdgcn_readlane(wy, 16)),
+                               max(__builtin_amdgcn_readlane(wy, 32), __builtin_amdgcn_readlane(wy, 48)));
+        // y steps all four rows take (no per-lane care needed); beyond, the tail
+        const int min_wy = min(min(__builtin_amdgcn_readlane(wy, 0), __builtin_amdgcn_readlane(wy, 16)),
+                               min(__builtin_amdgcn_readlane(wy, 32), __builtin_amdgcn_readlane(wy, 48)));
+        // column f -> (x, z) = (f mod wx, f div wx) as floor((f + 1/2) / wx): the fraction
         // stays at least 1/(2 wx) away from an integer, far beyond the hardware
         // reciprocal's error for any f < 2^20
         const float inv_wx = __builtin_amdgcn_rcpf((float)wx);
-        const int nx = a.nx[kk], ny = a.ny[kk];
-        const int nxy = nx * ny;
-        const float* __restrict__ g = a.dl_di[kk];
-        // z steps both halves take (no per-lane care needed) and the tail only one half takes
-        const int min_wz = min(__builtin_amdgcn_readlane(wz, 0), __builtin_amdgcn_readlane(wz, 32));
+        const float dy0 = -cy;                        // dy = dy0 + k at step k of a column
+        const float B0 = 2.0f * kyy * dy0;
         // weighted moments: m0 = sum gE, m1 = sum gE delta, m2 = sum gE delta delta^T
         float m0 = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f;
         float mxx = 0.0f, myy = 0.0f, mzz = 0.0f, mxy = 0.0f, mxz = 0.0f, myz = 0.0f;
 #pragma unroll 1
         for (int c = 0; c < max_chunks; ++c) {
-            const int f = c * 32 + hl;
+            const int f = c * 16 + ql;
             const bool act = f < fp;
-            const int y = (int)(((float)f + 0.5f) * inv_wx);
-            const int x = f - y * wx;
-            const float dx = (float)x - cx, dy = (float)y - cy;
-            // along the column, dz = dz0 + k for step k = 0, 1, ...: Q_k = A + k (B + k kzz).
-            // A lane outside the footprint reads voxel (0, 0, k) and gets A = -inf, so its
-            // every term is exactly zero.
-            const float dz0 = -cz;
-            const float bz = kxz * dx + kyz * dy;
-            const float qxy = dx * (kxx * dx + kxy * dy) + dy * (kyy * dy);
-            const float A = act ? qxy + dz0 * (bz + kzz * dz0) : -__builtin_inff();
-            const float B = bz + 2.0f * kzz * dz0;
-            const uint32_t off = act ? (uint32_t)((loz * ny + (loy + y)) * nx + (lox + x)) : 0u;
-            const int ncol = act ? wz : 1;             // steps whose voxel lies in the box
+            const int z = (int)(((float)f + 0.5f) * inv_wx);
+            const int x = f - z * wx;
+            const float dx = (float)x - cx, dz = (float)z - cz;
+            // Q along the column: Q_k = A + k (B + k kyy).  A lane outside the footprint
+            // reads voxel (0, k, 0) and gets A = -inf, so its every term is exactly zero.
+            const float b = kxy * dx + kyz * dz;
+            const float qxz = dx * (kxx * dx + kxz * dz) + dz * (kzz * dz);
+            const float A = act ? qxz + dy0 * (b + kyy * dy0) : -__builtin_inff();
+            const float B = b + B0;
+            const uint32_t off = act ? (uint32_t)(((loz + z) * ny + loy) * nx + (lox + x)) : 0u;
+            const int ncol = act ? wy : 1;             // steps whose voxel lies in the box
             // s0 = sum ge, s1 = sum k ge, s2 = sum k^2 ge over the column (ge = g 2^Q)
             float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
             float gv[8];
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                if (k < max_wz) {
-                    if (k < min_wz) {
-                        gv[k] = (g + (size_t)k * nxy)[off];
+                if (k < max_wy) {
+                    if (k < min_wy) {
+                        gv[k] = (g + (size_t)k * nx)[off];
                     } else {
                         const int kc = min(k, ncol - 1);
-                        const float t = (g + (size_t)kc * nxy)[off];
+                        const float t = (g + (size_t)kc * nx)[off];
                         gv[k] = k < ncol ? t : 0.0f;
                     }
                 }
             }
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                if (k < max_wz) {
-                    const float Q = k == 0 ? A : A + (float)k * (B + (float)k * kzz);
+                if (k < max_wy) {
+                    const float Q = k == 0 ? A : A + (float)k * (B + (float)k * kyy);
                     const float ge = gv[k] * __builtin_amdgcn_exp2f(Q);
                     s0 += ge;
                     if (k > 0) {
@@ -161,54 +168,54 @@ __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
                 }
             }
 #pragma unroll 1
-            for (int k = 8; k < max_wz; ++k) {  // boxes deeper than 8 voxels
+            for (int k = 8; k < max_wy; ++k) {  // boxes longer than 8 voxels in y
                 const int kc = min(k, ncol - 1);
-                const float t = (g + (size_t)kc * nxy)[off];
+                const float t = (g + (size_t)kc * nx)[off];
                 const float gk = k < ncol ? t : 0.0f;
                 const float fk = (float)k;
-                const float ge = gk * __builtin_amdgcn_exp2f(A + fk * (B + fk * kzz));
+                const float ge = gk * __builtin_amdgcn_exp2f(A + fk * (B + fk * kyy));
                 s0 += ge;
                 s1 += fk * ge;
                 s2 += fk * fk * ge;
             }
-            // back to moments in dz = dz0 + k
-            const float S1 = s1 + dz0 * s0;
-            const float S2 = s2 + dz0 * (2.0f * s1 + dz0 * s0);
-            const float ax = s0 * dx, ay = s0 * dy;
+            // back to moments in dy = dy0 + k
+            const float S1 = s1 + dy0 * s0;
+            const float S2 = s2 + dy0 * (2.0f * s1 + dy0 * s0);
+            const float ax = s0 * dx, az = s0 * dz;
             m0 += s0;
             mx += ax;
-            my += ay;
-            mz += S1;
+            mz += az;
+            my += S1;
             mxx += ax * dx;
-            myy += ay * dy;
-            mxy += ax * dy;
-            mxz += S1 * dx;
-            myz += S1 * dy;
-            mzz += S2;
+            mzz += az * dz;
+            mxz += ax * dz;
+            mxy += S1 * dx;
+            myz += S1 * dz;
+            myy += S2;
         }
-        m0 = half_sum(m0);
-        mx = half_sum(mx);
-        my = half_sum(my);
-        mz = half_sum(mz);
-        mxx = half_sum(mxx);
-        myy = half_sum(myy);
-        mzz = half_sum(mzz);
-        mxy = half_sum(mxy);
-        mxz = half_sum(mxz);
-        myz = half_sum(myz);
-        if (hl == 31 && gvalid) {
+        m0 = row_sum(m0);
+        mx = row_sum(mx);
+        my = row_sum(my);
+        mz = row_sum(mz);
+        mxx = row_sum(mxx);
+        myy = row_sum(myy);
+        mzz = row_sum(mzz);
+        mxy = row_sum(mxy);
+        mxz = row_sum(mxz);
+        myz = row_sum(myz);
+        if (ql == 0 && gvalid) {
             // K as a full symmetric matrix has off-diagonal entries kxy/2, kxz/2, kyz/2
-            const float A = (nonempty ? r0.w : 0.0f) * GM_LN2F;   // amp ln2
+            const float Al = (nonempty ? r0.w : 0.0f) * GM_LN2F;   // amp ln2
             const float hxy = 0.5f * kxy, hxz = 0.5f * kxz, hyz = 0.5f * kyz;
             const float tx = kxx * mx + hxy * my + hxz * mz;
             const float ty = hxy * mx + kyy * my + hyz * mz;
             const float tz = hxz * mx + hyz * my + kzz * mz;
             float2* o = reinterpret_cast<float2*>(a.grid_grads + ((size_t)gi * a.n + gid) * 10);
-            o[0] = make_float2(m0, -2.0f * A * tx);
-            o[1] = make_float2(-2.0f * A * ty, -2.0f * A * tz);
-            o[2] = make_float2(A * mxx, A * myy);
-            o[3] = make_float2(A * mzz, A * mxy);
-            o[4] = make_float2(A * mxz, A * myz);
+            o[0] = make_float2(m0, -2.0f * Al * tx);
+            o[1] = make_float2(-2.0f * Al * ty, -2.0f * Al * tz);
+            o[2] = make_float2(Al * mxx, Al * myy);
+            o[3] = make_float2(Al * mzz, Al * mxy);
+            o[4] = make_float2(Al * mxz, Al * myz);
         }
     }
 }

@@ -37,185 +37,253 @@ __device__ __forceinline__ float row_sum(float v)
     return v;
 }
 
-// Each wavefront takes 64 consecutive entries of one grid's tile-sorted lists and processes
-// the Gaussians whose home entry (the tile holding the box's lower corner) is among them:
-// every Gaussian of the grid exactly once, in tile order, so neighbouring Gaussians run
-// together (and on one XCD) and the dL/dI they gather is served from the same L2 lines.
-// Four Gaussians at a time, one per 16-lane row.  A row maps its lanes onto chunks of 16
-// (x, z) columns of the Gaussian's box and walks each column along y (for thick-slice
-// stacks the box is longest in-plane, so this gives the fewest chunks and the longest walks).
-// All of a column's dL/dI values are loaded first (in the y range the four boxes share, from
-// a wave-uniform base pointer per step: no per-lane address arithmetic); step k then costs
-// Q_k = A + k (B + k kyy) (two FMAs), one exp2, one multiply and three adds for the column
-// sums of g E, k g E and k^2 g E (k a compile-time constant in the unrolled loop).  Past a
-// shorter box, a row's loads are clamped and zeroed.  Gaussians with an empty box are in no
-// list; gm_bin wrote their zeros.
+// dL/dI region a block stages in LDS: its tile plus a halo of 8 voxels on the upper side in
+// each axis (a home Gaussian's box starts inside the tile).  The z planes are RZS floats apart,
+// RZS = 8 (mod 32), so the up-to-four z rows a lane row reads at one step sit in different
+// LDS banks.
+constexpr int RX = GM_TX + 8, RY = GM_TY + 8, RZ = GM_TZ + 8;
+constexpr int RZS = RX * RY + 8;
+static_assert(RZS % 32 == 8, "z-plane stride must be 8 mod 32 banks");
+
+// Four Gaussians of one grid at a time, one per 16-lane row: the ten moments of each, turned
+// into the grid-frame partials and stored.  A row maps its lanes onto chunks of 16 (x, z)
+// columns of its Gaussian's box and walks each column along y (for thick-slice stacks the box
+// is longest in-plane, so this gives the fewest chunks and the longest walks).  With FROM_LDS
+// every box lies inside the block's staged region and dL/dI is read from LDS; otherwise from
+// global memory.  All of a column's values are read first; step k then costs
+// Q_k = A + k (B + k kyy) (two FMAs), one exp2, one multiply and three adds for the column sums
+// of g E, k g E and k^2 g E (k a compile-time constant in the unrolled loop).  Past a shorter
+// box, a row's reads are clamped and zeroed.
+template <bool FROM_LDS>
+__device__ __forceinline__ void four_gaussians(const BackwardArgs& a, int kk, uint32_t mine,
+                                               bool gvalid, const float* __restrict__ region,
+                                               int t0x, int t0y, int t0z)
+{
+    const int ql = threadIdx.x & 15;
+    const int gi = a.grid_index[kk];
+    const int nx = a.nx[kk], ny = a.ny[kk];
+    const float* __restrict__ g = a.dl_di[kk];
+    const int64_t gid = min((int64_t)(mine & GM_ID_MASK), a.n - 1);
+    float4 r0 = make_float4(0, 0, 0, 0), r1 = r0, r2 = r0, r3 = r0;
+    if (gvalid) {
+        const float4* rp = reinterpret_cast<const float4*>(a.records + ((size_t)gi * a.n + gid) * 16);
+        r0 = rp[0];
+        r1 = rp[1];
+        r2 = rp[2];
+        r3 = rp[3];
+    }
+    const int lox = __float_as_int(r2.z), loy = __float_as_int(r2.w), loz = __float_as_int(r3.x);
+    const int hix = __float_as_int(r3.y), hiy = __float_as_int(r3.z), hiz = __float_as_int(r3.w);
+    const bool nonempty = gvalid && lox <= hix && loy <= hiy && loz <= hiz;
+    // an empty box (including an invalid Gaussian) contributes nothing; its record's
+    // floats are replaced by zeros so that nothing non-finite enters the sums
+    const int wx = nonempty ? hix - lox + 1 : 1;
+    const int wy = nonempty ? hiy - loy + 1 : 0;
+    const int wz = nonempty ? hiz - loz + 1 : 0;
+    const float cx = nonempty ? r0.x : 0.0f, cy = nonempty ? r0.y : 0.0f;
+    const float cz = nonempty ? r0.z : 0.0f;
+    const float kxx = nonempty ? r1.x : 0.0f, kyy = nonempty ? r1.y : 0.0f;
+    const float kzz = nonempty ? r1.z : 0.0f, kxy = nonempty ? r1.w : 0.0f;
+    const float kxz = nonempty ? r2.x : 0.0f, kyz = nonempty ? r2.y : 0.0f;
+    const int fp = wx * wz;                       // (x, z) footprint of the box
+    const int chunks = (fp + 15) >> 4;
+    const int max_chunks = max(max(__builtin_amdgcn_readlane(chunks, 0), __builtin_amdgcn_readlane(chunks, 16)),
+                               max(__builtin_amdgcn_readlane(chunks, 32), __builtin_amdgcn_readlane(chunks, 48)));
+    const int max_wy = max(max(__builtin_amdgcn_readlane(wy, 0), __builtin_amdgcn_readlane(wy, 16)),
+                           max(__builtin_amdgcn_readlane(wy, 32), __builtin_amdgcn_readlane(wy, 48)));
+    // y steps all four rows take (no per-lane care needed); beyond, the tail
+    const int min_wy = min(min(__builtin_amdgcn_readlane(wy, 0), __builtin_amdgcn_readlane(wy, 16)),
+                           min(__builtin_amdgcn_readlane(wy, 32), __builtin_amdgcn_readlane(wy, 48)));
+    // column f -> (x, z) = (f mod wx, f div wx) as floor((f + 1/2) / wx): the fraction stays
+    // at least 1/(2 wx) away from an integer, far beyond the hardware reciprocal's error for
+    // any f < 2^20
+    const float inv_wx = __builtin_amdgcn_rcpf((float)wx);
+    const float dy0 = -cy;                        // dy = dy0 + k at step k of a column
+    const float B0 = 2.0f * kyy * dy0;
+    const int ystride = FROM_LDS ? RX : nx;       // between consecutive y steps
+    // weighted moments: m0 = sum gE, m1 = sum gE delta, m2 = sum gE delta delta^T
+    float m0 = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f;
+    float mxx = 0.0f, myy = 0.0f, mzz = 0.0f, mxy = 0.0f, mxz = 0.0f, myz = 0.0f;
+#pragma unroll 1
+    for (int c = 0; c < max_chunks; ++c) {
+        const int f = c * 16 + ql;
+        const bool act = f < fp;
+        const int z = (int)(((float)f + 0.5f) * inv_wx);
+        const int x = f - z * wx;
+        const float dx = (float)x - cx, dz = (float)z - cz;
+        // Q along the column: Q_k = A + k (B + k kyy).  A lane outside the footprint reads
+        // the first voxel of the region (or grid) at every step and gets A = -inf, so its
+        // every term is exactly zero.
+        const float b = kxy * dx + kyz * dz;
+        const float qxz = dx * (kxx * dx + kxz * dz) + dz * (kzz * dz);
+        const float A = act ? qxz + dy0 * (b + kyy * dy0) : -__builtin_inff();
+        const float B = b + B0;
+        uint32_t off = 0u;
+        if (act) {
+            off = FROM_LDS ? (uint32_t)((loz + z - t0z) * RZS + (loy - t0y) * RX + (lox + x - t0x))
+                           : (uint32_t)(((loz + z) * ny + loy) * nx + (lox + x));
+        }
+        const int ncol = act ? wy : 1;             // steps whose voxel lies in the box
+        // s0 = sum ge, s1 = sum k ge, s2 = sum k^2 ge over the column (ge = g 2^Q)
+        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+        float gv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (k < max_wy) {
+                if (k < min_wy) {
+                    gv[k] = FROM_LDS ? region[off + k * RX] : (g + (size_t)k * nx)[off];
+                } else {
+                    const int kc = min(k, ncol - 1);
+                    const float t = FROM_LDS ? region[off + kc * RX] : (g + (size_t)kc * nx)[off];
+                    gv[k] = k < ncol ? t : 0.0f;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (k < max_wy) {
+                const float Q = k == 0 ? A : A + (float)k * (B + (float)k * kyy);
+                const float ge = gv[k] * __builtin_amdgcn_exp2f(Q);
+                s0 += ge;
+                if (k > 0) {
+                    s1 += (float)k * ge;
+                    s2 += (float)(k * k) * ge;
+                }
+            }
+        }
+#pragma unroll 1
+        for (int k = 8; k < max_wy; ++k) {  // boxes longer than 8 voxels in y
+            const int kc = min(k, ncol - 1);
+            const float t = FROM_LDS ? region[off + kc * RX] : g[(size_t)kc * ystride + off];
+            const float gk = k < ncol ? t : 0.0f;
+            const float fk = (float)k;
+            const float ge = gk * __builtin_amdgcn_exp2f(A + fk * (B + fk * kyy));
+            s0 += ge;
+            s1 += fk * ge;
+            s2 += fk * fk * ge;
+        }
+        // back to moments in dy = dy0 + k
+        const float S1 = s1 + dy0 * s0;
+        const float S2 = s2 + dy0 * (2.0f * s1 + dy0 * s0);
+        const float ax = s0 * dx, az = s0 * dz;
+        m0 += s0;
+        mx += ax;
+        mz += az;
+        my += S1;
+        mxx += ax * dx;
+        mzz += az * dz;
+        mxz += ax * dz;
+        mxy += S1 * dx;
+        myz += S1 * dz;
+        myy += S2;
+    }
+    m0 = row_sum(m0);
+    mx = row_sum(mx);
+    my = row_sum(my);
+    mz = row_sum(mz);
+    mxx = row_sum(mxx);
+    myy = row_sum(myy);
+    mzz = row_sum(mzz);
+    mxy = row_sum(mxy);
+    mxz = row_sum(mxz);
+    myz = row_sum(myz);
+    if (ql == 0 && gvalid) {
+        // K as a full symmetric matrix has off-diagonal entries kxy/2, kxz/2, kyz/2
+        const float Al = (nonempty ? r0.w : 0.0f) * GM_LN2F;   // amp ln2
+        const float hxy = 0.5f * kxy, hxz = 0.5f * kxz, hyz = 0.5f * kyz;
+        const float tx = kxx * mx + hxy * my + hxz * mz;
+        const float ty = hxy * mx + kyy * my + hyz * mz;
+        const float tz = hxz * mx + hyz * my + kzz * mz;
+        float2* o = reinterpret_cast<float2*>(a.grid_grads + ((size_t)gi * a.n + gid) * 10);
+        o[0] = make_float2(m0, -2.0f * Al * tx);
+        o[1] = make_float2(-2.0f * Al * ty, -2.0f * Al * tz);
+        o[2] = make_float2(Al * mxx, Al * myy);
+        o[3] = make_float2(Al * mzz, Al * mxy);
+        o[4] = make_float2(Al * mxz, Al * myz);
+    }
+}
+
+// Takes the next (up to) four Gaussians of `todo` (bit i = entry i of the wave's 64, whose
+// id is in v), one per row.
+__device__ __forceinline__ void take_four(uint64_t& todo, uint32_t v, uint32_t& mine, bool& valid)
+{
+    const int row = (threadIdx.x & 63) >> 4;
+    mine = 0u;
+    valid = false;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if (todo) {
+            const int ib = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const uint32_t vb = __builtin_amdgcn_readlane(v, ib);
+            if (row == r) {
+                mine = vb;
+                valid = true;
+            }
+        }
+    }
+}
+
+// One block (four wavefronts) per tile of a listed grid.  The block stages the tile's dL/dI
+// region in LDS (coalesced rows), then its wavefronts take the tile's list 64 entries at a
+// time and process the Gaussians whose home entry (the tile holding the box's lower corner) is
+// among them: every Gaussian of the grid exactly once, each from LDS when its box lies inside
+// the region (the common case) and from global memory otherwise.  Gaussians with an empty box
+// are in no list; gm_bin wrote their zeros.
 __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
 {
-    const int lane = threadIdx.x & 63;
-    const int ql = lane & 15;          // lane within the row
-    const int row = lane >> 4;
+    __shared__ float region[RZ * RZS];
     const int lin = xcd_remap(blockIdx.x, gridDim.x);
     int kk = 0;                                            // listed grid of this block
 #pragma unroll 1
     while (kk + 1 < a.n_ids && lin >= a.block_start[kk + 1]) ++kk;
-    const int64_t e1 = a.entry_hi[kk];
-    const int64_t w0 = a.entry_lo[kk] + ((int64_t)(lin - a.block_start[kk]) * 4 + (threadIdx.x >> 6)) * 64;
-    if (w0 >= e1) return;  // wave-uniform
-    const int64_t entry = w0 + lane;
-    const uint32_t v = entry < e1 ? a.pair_gauss[entry] : 0u;
-    uint64_t todo = __ballot(entry < e1 && (v & GM_HOME_BIT));
-    const int gi = a.grid_index[kk];
-    const int nx = a.nx[kk], ny = a.ny[kk];
+    const int t = lin - a.block_start[kk];
+    const int ntx = a.ntx[kk], nty = a.nty[kk];
+    const int t0x = (t % ntx) * GM_TX, t0y = ((t / ntx) % nty) * GM_TY, t0z = (t / (ntx * nty)) * GM_TZ;
+    const int64_t T = a.tile_base[kk] + t;
+    const int e0 = __builtin_amdgcn_readfirstlane(a.tile_start[T]);
+    const int e1 = __builtin_amdgcn_readfirstlane(a.tile_start[T + 1]);
+    if (e0 == e1) return;  // block-uniform
+    const int nx = a.nx[kk], ny = a.ny[kk], nz = a.nz[kk];
     const float* __restrict__ g = a.dl_di[kk];
+    for (int i = threadIdx.x; i < RX * RY * RZ; i += 256) {
+        const int z = i / (RX * RY), rem = i - z * (RX * RY);
+        const int y = rem / RX, x = rem - y * RX;
+        const int gx = t0x + x, gy = t0y + y, gz = t0z + z;
+        float val = 0.0f;
+        if (gx < nx && gy < ny && gz < nz) val = g[((size_t)gz * ny + gy) * nx + gx];
+        region[z * RZS + y * RX + x] = val;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int gi = a.grid_index[kk];
 #pragma unroll 1
-    while (todo) {
-        // the next (up to) four home entries, one per row
-        uint32_t mine = 0u;
-        bool gvalid = false;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            if (todo) {
-                const int ib = __builtin_ctzll(todo);
-                todo &= todo - 1;
-                const uint32_t vb = __builtin_amdgcn_readlane(v, ib);
-                if (row == r) {
-                    mine = vb;
-                    gvalid = true;
-                }
-            }
+    for (int w0 = e0 + (int)(threadIdx.x >> 6) * 64; w0 < e1; w0 += 256) {
+        const int entry = w0 + lane;
+        const uint32_t v = entry < e1 ? a.pair_gauss[entry] : 0u;
+        const bool home = entry < e1 && (v & GM_HOME_BIT);
+        // a home box starts inside the tile; it fits the region unless it reaches past the halo
+        bool fits = false;
+        if (home) {
+            const int* rc = reinterpret_cast<const int*>(
+                a.records + ((size_t)gi * a.n + min((int64_t)(v & GM_ID_MASK), a.n - 1)) * 16);
+            fits = rc[13] - t0x < RX && rc[14] - t0y < RY && rc[15] - t0z < RZ;
         }
-        const int64_t gid = min((int64_t)(mine & GM_ID_MASK), a.n - 1);
-        float4 r0 = make_float4(0, 0, 0, 0), r1 = r0, r2 = r0, r3 = r0;
-        if (gvalid) {
-            const float4* rp = reinterpret_cast<const float4*>(a.records + ((size_t)gi * a.n + gid) * 16);
-            r0 = rp[0];
-            r1 = rp[1];
-            r2 = rp[2];
-            r3 = rp[3];
-        }
-        const int lox = __float_as_int(r2.z), loy = __float_as_int(r2.w), loz = __float_as_int(r3.x);
-        const int hix = __float_as_int(r3.y), hiy = __float_as_int(r3.z), hiz = __float_as_int(r3.w);
-        const bool nonempty = gvalid && lox <= hix && loy <= hiy && loz <= hiz;
-        // an empty box (including an invalid Gaussian) contributes nothing; its record's
-        // floats are replaced by zeros so that nothing non-finite enters the sums
-        const int wx = nonempty ? hix - lox + 1 : 1;
-        const int wy = nonempty ? hiy - loy + 1 : 0;
-        const int wz = nonempty ? hiz - loz + 1 : 0;
-        const float cx = nonempty ? r0.x : 0.0f, cy = nonempty ? r0.y : 0.0f;
-        const float cz = nonempty ? r0.z : 0.0f;
-        const float kxx = nonempty ? r1.x : 0.0f, kyy = nonempty ? r1.y : 0.0f;
-        const float kzz = nonempty ? r1.z : 0.0f, kxy = nonempty ? r1.w : 0.0f;
-        const float kxz = nonempty ? r2.x : 0.0f, kyz = nonempty ? r2.y : 0.0f;
-        const int fp = wx * wz;                       // (x, z) footprint of the box
-        const int chunks = (fp + 15) >> 4;
-        const int max_chunks = max(max(__builtin_amdgcn_readlane(chunks, 0), __builtin_amdgcn_readlane(chunks, 16)),
-                                   max(__builtin_amdgcn_readlane(chunks, 32), __builtin_amdgcn_readlane(chunks, 48)));
-        const int max_wy = max(max(__builtin_amdgcn_readlane(wy, 0), __builtin_amdgcn_readlane(wy, 16)),
-                               max(__builtin_amdgcn_readlane(wy, 32), __builtin_amdgcn_readlane(wy, 48)));
-        // y steps all four rows take (no per-lane care needed); beyond, the tail
-        const int min_wy = min(min(__builtin_amdgcn_readlane(wy, 0), __builtin_amdgcn_readlane(wy, 16)),
-                               min(__builtin_amdgcn_readlane(wy, 32), __builtin_amdgcn_readlane(wy, 48)));
-        // column f -> (x, z) = (f mod wx, f div wx) as floor((f + 1/2) / wx): the fraction
-        // stays at least 1/(2 wx) away from an integer, far beyond the hardware
-        // reciprocal's error for any f < 2^20
-        const float inv_wx = __builtin_amdgcn_rcpf((float)wx);
-        const float dy0 = -cy;                        // dy = dy0 + k at step k of a column
-        const float B0 = 2.0f * kyy * dy0;
-        // weighted moments: m0 = sum gE, m1 = sum gE delta, m2 = sum gE delta delta^T
-        float m0 = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f;
-        float mxx = 0.0f, myy = 0.0f, mzz = 0.0f, mxy = 0.0f, mxz = 0.0f, myz = 0.0f;
+        uint64_t in_lds = __ballot(home && fits);
+        uint64_t in_global = __ballot(home && !fits);
 #pragma unroll 1
-        for (int c = 0; c < max_chunks; ++c) {
-            const int f = c * 16 + ql;
-            const bool act = f < fp;
-            const int z = (int)(((float)f + 0.5f) * inv_wx);
-            const int x = f - z * wx;
-            const float dx = (float)x - cx, dz = (float)z - cz;
-            // Q along the column: Q_k = A + k (B + k kyy).  A lane outside the footprint
-            // reads voxel (0, k, 0) and gets A = -inf, so its every term is exactly zero.
-            const float b = kxy * dx + kyz * dz;
-            const float qxz = dx * (kxx * dx + kxz * dz) + dz * (kzz * dz);
-            const float A = act ? qxz + dy0 * (b + kyy * dy0) : -__builtin_inff();
-            const float B = b + B0;
-            const uint32_t off = act ? (uint32_t)(((loz + z) * ny + loy) * nx + (lox + x)) : 0u;
-            const int ncol = act ? wy : 1;             // steps whose voxel lies in the box
-            // s0 = sum ge, s1 = sum k ge, s2 = sum k^2 ge over the column (ge = g 2^Q)
-            float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
-            float gv[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                if (k < max_wy) {
-                    if (k < min_wy) {
-                        gv[k] = (g + (size_t)k * nx)[off];
-                    } else {
-                        const int kc = min(k, ncol - 1);
-                        const float t = (g + (size_t)kc * nx)[off];
-                        gv[k] = k < ncol ? t : 0.0f;
-                    }
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                if (k < max_wy) {
-                    const float Q = k == 0 ? A : A + (float)k * (B + (float)k * kyy);
-                    const float ge = gv[k] * __builtin_amdgcn_exp2f(Q);
-                    s0 += ge;
-                    if (k > 0) {
-                        s1 += (float)k * ge;
-                        s2 += (float)(k * k) * ge;
-                    }
-                }
-            }
-#pragma unroll 1
-            for (int k = 8; k < max_wy; ++k) {  // boxes longer than 8 voxels in y
-                const int kc = min(k, ncol - 1);
-                const float t = (g + (size_t)kc * nx)[off];
-                const float gk = k < ncol ? t : 0.0f;
-                const float fk = (float)k;
-                const float ge = gk * __builtin_amdgcn_exp2f(A + fk * (B + fk * kyy));
-                s0 += ge;
-                s1 += fk * ge;
-                s2 += fk * fk * ge;
-            }
-            // back to moments in dy = dy0 + k
-            const float S1 = s1 + dy0 * s0;
-            const float S2 = s2 + dy0 * (2.0f * s1 + dy0 * s0);
-            const float ax = s0 * dx, az = s0 * dz;
-            m0 += s0;
-            mx += ax;
-            mz += az;
-            my += S1;
-            mxx += ax * dx;
-            mzz += az * dz;
-            mxz += ax * dz;
-            mxy += S1 * dx;
-            myz += S1 * dz;
-            myy += S2;
+        while (in_lds) {
+            uint32_t mine;
+            bool valid;
+            take_four(in_lds, v, mine, valid);
+            four_gaussians<true>(a, kk, mine, valid, region, t0x, t0y, t0z);
         }
-        m0 = row_sum(m0);
-        mx = row_sum(mx);
-        my = row_sum(my);
-        mz = row_sum(mz);
-        mxx = row_sum(mxx);
-        myy = row_sum(myy);
-        mzz = row_sum(mzz);
-        mxy = row_sum(mxy);
-        mxz = row_sum(mxz);
-        myz = row_sum(myz);
-        if (ql == 0 && gvalid) {
-            // K as a full symmetric matrix has off-diagonal entries kxy/2, kxz/2, kyz/2
-            const float Al = (nonempty ? r0.w : 0.0f) * GM_LN2F;   // amp ln2
-            const float hxy = 0.5f * kxy, hxz = 0.5f * kxz, hyz = 0.5f * kyz;
-            const float tx = kxx * mx + hxy * my + hxz * mz;
-            const float ty = hxy * mx + kyy * my + hyz * mz;
-            const float tz = hxz * mx + hyz * my + kzz * mz;
-            float2* o = reinterpret_cast<float2*>(a.grid_grads + ((size_t)gi * a.n + gid) * 10);
-            o[0] = make_float2(m0, -2.0f * Al * tx);
-            o[1] = make_float2(-2.0f * Al * ty, -2.0f * Al * tz);
-            o[2] = make_float2(Al * mxx, Al * myy);
-            o[3] = make_float2(Al * mzz, Al * mxy);
-            o[4] = make_float2(Al * mxz, Al * myz);
+#pragma unroll 1
+        while (in_global) {
+            uint32_t mine;
+            bool valid;
+            take_four(in_global, v, mine, valid);
+            four_gaussians<false>(a, kk, mine, valid, region, t0x, t0y, t0z);
         }
     }
 }
@@ -371,19 +439,11 @@ __global__ __launch_bounds__(128) void k_chain(const ChainArgs a)
 
 }  // namespace
 
-hipError_t launch_backward_partials(const BackwardArgs& a_in, hipStream_t s)
+hipError_t launch_backward_partials(const BackwardArgs& a, hipStream_t s)
 {
-    if (a_in.n == 0 || a_in.n_ids == 0) return hipSuccess;
-    // 4 wavefronts x 64 list entries per block, blocks laid out grid after grid
-    BackwardArgs a = a_in;
-    int64_t blocks = 0;
-    for (int k = 0; k < a.n_ids; ++k) {
-        a.block_start[k] = (int32_t)blocks;
-        blocks += (a.entry_hi[k] - a.entry_lo[k] + 255) / 256;
-        if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    }
-    a.block_start[a.n_ids] = (int32_t)blocks;
-    if (blocks == 0) return hipSuccess;
+    if (a.n == 0 || a.n_ids == 0) return hipSuccess;
+    const int32_t blocks = a.block_start[a.n_ids];   // one per tile of the listed grids
+    if (blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_partials, dim3((unsigned)blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }

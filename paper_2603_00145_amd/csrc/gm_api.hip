@@ -669,6 +669,7 @@ gm_status backward_impl(const gm_gaussians* g, const gm_bins* bins, const int32_
     ba.records = bins->records;
     ba.grid_grads = bins->grid_grads;
     ba.pair_gauss = reinterpret_cast<const uint32_t*>(bins->pair_gauss);
+    ba.tile_start = bins->tile_start;
     for (int k = 0; k < n_ids; ++k) {
         const gm_grid& gr = bins->grids[grid_ids[k]];
         if (partials) {
@@ -676,8 +677,13 @@ gm_status backward_impl(const gm_gaussians* g, const gm_bins* bins, const int32_
             ba.dl_di[k] = dl_di[k];
         }
         ba.grid_index[k] = grid_ids[k];
-        ba.entry_lo[k] = bins->list_start[grid_ids[k]];
-        ba.entry_hi[k] = bins->list_start[grid_ids[k] + 1];
+        {
+            const GridConst c = make_const(gr, bins->tile_base[grid_ids[k]]);
+            ba.tile_base[k] = c.tile_base;
+            ba.ntx[k] = c.ntx;
+            ba.nty[k] = c.nty;
+            ba.block_start[k + 1] = ba.block_start[k] + (int32_t)(grid_tiles(gr));
+        }
         ba.nx[k] = gr.nx;
         ba.ny[k] = gr.ny;
         ba.nz[k] = gr.nz;

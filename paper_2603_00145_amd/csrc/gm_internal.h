@@ -114,9 +114,10 @@ struct BackwardArgs {
     int32_t nx[GM_MAX_GRIDS], ny[GM_MAX_GRIDS], nz[GM_MAX_GRIDS];
     const float* dl_di[GM_MAX_GRIDS];
     const uint32_t* pair_gauss;         // tile-sorted entries, GM_HOME_BIT on home entries
-    int64_t entry_lo[GM_MAX_GRIDS];     // list entries [entry_lo, entry_hi) of each listed grid
-    int64_t entry_hi[GM_MAX_GRIDS];
-    int32_t block_start[GM_MAX_GRIDS + 1];  // first block of each listed grid; [n_ids] = total
+    const int32_t* tile_start;          // CSR rows of the tile lists
+    int64_t tile_base[GM_MAX_GRIDS];    // global id of each listed grid's first tile
+    int32_t ntx[GM_MAX_GRIDS], nty[GM_MAX_GRIDS];
+    int32_t block_start[GM_MAX_GRIDS + 1];  // first block (= tile) of each listed grid
 };
 hipError_t launch_backward_partials(const BackwardArgs& a, hipStream_t s);
 

@@ -246,17 +246,40 @@ __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
     if (e0 == e1) return;  // block-uniform
     const int nx = a.nx[kk], ny = a.ny[kk], nz = a.nz[kk];
     const float* __restrict__ g = a.dl_di[kk];
-    for (int i = threadIdx.x; i < RX * RY * RZ; i += 256) {
-        const int z = i / (RX * RY), rem = i - z * (RX * RY);
-        const int y = rem / RX, x = rem - y * RX;
-        const int gx = t0x + x, gy = t0y + y, gz = t0z + z;
-        float val = 0.0f;
-        if (gx < nx && gy < ny && gz < nz) val = g[((size_t)gz * ny + gy) * nx + gx];
-        region[z * RZS + y * RX + x] = val;
-    }
-    __syncthreads();
     const int lane = threadIdx.x & 63;
     const int gi = a.grid_index[kk];
+    // z planes the tile's home boxes reach (those that fit the region): staged planes only
+    __shared__ int zext;
+    if (threadIdx.x == 0) zext = 0;
+    __syncthreads();
+    {
+        int zmax = 0;
+        for (int i = e0 + (int)threadIdx.x; i < e1; i += 256) {
+            const uint32_t v = a.pair_gauss[i];
+            if (v & GM_HOME_BIT) {
+                const int* rc = reinterpret_cast<const int*>(
+                    a.records + ((size_t)gi * a.n + min((int64_t)(v & GM_ID_MASK), a.n - 1)) * 16);
+                const int ex = rc[13] - t0x, ey = rc[14] - t0y, ez = rc[15] - t0z;
+                if (ex < RX && ey < RY && ez < RZ) zmax = max(zmax, ez + 1);
+            }
+        }
+        if (zmax > 0) atomicMax(&zext, zmax);
+    }
+    __syncthreads();
+    const int nzr = min(zext, nz - t0z);
+    // rows of RX voxels along x: thread -> (x, y) of a plane, then the planes
+    for (int i = threadIdx.x; i < RX * RY; i += 256) {
+        const int y = i / RX, x = i - y * RX;
+        const int gx = t0x + x, gy = t0y + y;
+        const bool in = gx < nx && gy < ny;
+        const float* src = g + ((size_t)t0z * ny + gy) * nx + gx;
+        float* dst = region + y * RX + x;
+        for (int z = 0; z < nzr; ++z) {
+            dst[z * RZS] = in ? src[0] : 0.0f;
+            src += (size_t)nx * ny;
+        }
+    }
+    __syncthreads();
 #pragma unroll 1
     for (int w0 = e0 + (int)(threadIdx.x >> 6) * 64; w0 < e1; w0 += 256) {
         const int entry = w0 + lane;

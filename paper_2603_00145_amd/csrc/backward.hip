@@ -22,9 +22,12 @@ namespace {
 
 __device__ __forceinline__ int sgpr(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Sum of v over each 16-lane row of the wavefront (every lane of the row ends with it).
-__device__ __forceinline__ float row_sum(float v)
+// Sum of v over each aligned group of G lanes (G = 8 or 16; every lane of the group ends with
+// it): DPP adds across lane xor 1, xor 2, the half-row mirror and, for 16, the row mirror.
+template <int G>
+__device__ __forceinline__ float group_sum(float v)
 {
+    static_assert(G == 8 || G == 16, "groups of 8 or 16 lanes");
     int xi;
     xi = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false);  // xor 1
     v += __int_as_float(xi);
@@ -32,9 +35,29 @@ __device__ __forceinline__ float row_sum(float v)
     v += __int_as_float(xi);
     xi = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false); // half mirror
     v += __int_as_float(xi);
-    xi = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false); // mirror
-    v += __int_as_float(xi);
+    if (G == 16) {
+        xi = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false); // mirror
+        v += __int_as_float(xi);
+    }
     return v;
+}
+
+// Largest / smallest value of v over the lanes 0, G, 2G, ... (one per group).
+template <int G>
+__device__ __forceinline__ int group_max(int v)
+{
+    int m = __builtin_amdgcn_readlane(v, 0);
+#pragma unroll
+    for (int r = 1; r < 64 / G; ++r) m = max(m, __builtin_amdgcn_readlane(v, r * G));
+    return m;
+}
+template <int G>
+__device__ __forceinline__ int group_min(int v)
+{
+    int m = __builtin_amdgcn_readlane(v, 0);
+#pragma unroll
+    for (int r = 1; r < 64 / G; ++r) m = min(m, __builtin_amdgcn_readlane(v, r * G));
+    return m;
 }
 
 // dL/dI region a block stages in LDS: its tile plus a halo of 8 voxels on the upper side in
@@ -43,23 +66,24 @@ __device__ __forceinline__ float row_sum(float v)
 // LDS banks.
 constexpr int RX = GM_TX + 8, RY = GM_TY + 8, RZ = GM_TZ + 8;
 constexpr int RZS = RX * RY + 8;
+constexpr int BWD_G = 8;   // lanes per Gaussian in the backward
 static_assert(RZS % 32 == 8, "z-plane stride must be 8 mod 32 banks");
 
-// Four Gaussians of one grid at a time, one per 16-lane row: the ten moments of each, turned
-// into the grid-frame partials and stored.  A row maps its lanes onto chunks of 16 (x, z)
-// columns of its Gaussian's box and walks each column along y (for thick-slice stacks the box
+// 64/G Gaussians of one grid at a time, one per group of G lanes: the ten moments of each,
+// turned into the grid-frame partials and stored.  A group maps its lanes onto chunks of G
+// (x, z) columns of its Gaussian's box and walks each column along y (for thick-slice stacks the box
 // is longest in-plane, so this gives the fewest chunks and the longest walks).  With FROM_LDS
 // every box lies inside the block's staged region and dL/dI is read from LDS; otherwise from
 // global memory.  All of a column's values are read first; step k then costs
 // Q_k = A + k (B + k kyy) (two FMAs), one exp2, one multiply and three adds for the column sums
 // of g E, k g E and k^2 g E (k a compile-time constant in the unrolled loop).  Past a shorter
 // box, a row's reads are clamped and zeroed.
-template <bool FROM_LDS>
-__device__ __forceinline__ void four_gaussians(const BackwardArgs& a, int kk, uint32_t mine,
-                                               bool gvalid, const float* __restrict__ region,
-                                               int t0x, int t0y, int t0z)
+template <int G, bool FROM_LDS>
+__device__ __forceinline__ void group_of_gaussians(const BackwardArgs& a, int kk, uint32_t mine,
+                                                   bool gvalid, const float* __restrict__ region,
+                                                   int t0x, int t0y, int t0z)
 {
-    const int ql = threadIdx.x & 15;
+    const int ql = threadIdx.x & (G - 1);
     const int gi = a.grid_index[kk];
     const int nx = a.nx[kk], ny = a.ny[kk];
     const float* __restrict__ g = a.dl_di[kk];
@@ -86,14 +110,11 @@ __device__ __forceinline__ void four_gaussians(const BackwardArgs& a, int kk, ui
     const float kzz = nonempty ? r1.z : 0.0f, kxy = nonempty ? r1.w : 0.0f;
     const float kxz = nonempty ? r2.x : 0.0f, kyz = nonempty ? r2.y : 0.0f;
     const int fp = wx * wz;                       // (x, z) footprint of the box
-    const int chunks = (fp + 15) >> 4;
-    const int max_chunks = max(max(__builtin_amdgcn_readlane(chunks, 0), __builtin_amdgcn_readlane(chunks, 16)),
-                               max(__builtin_amdgcn_readlane(chunks, 32), __builtin_amdgcn_readlane(chunks, 48)));
-    const int max_wy = max(max(__builtin_amdgcn_readlane(wy, 0), __builtin_amdgcn_readlane(wy, 16)),
-                           max(__builtin_amdgcn_readlane(wy, 32), __builtin_amdgcn_readlane(wy, 48)));
-    // y steps all four rows take (no per-lane care needed); beyond, the tail
-    const int min_wy = min(min(__builtin_amdgcn_readlane(wy, 0), __builtin_amdgcn_readlane(wy, 16)),
-                           min(__builtin_amdgcn_readlane(wy, 32), __builtin_amdgcn_readlane(wy, 48)));
+    const int chunks = (fp + G - 1) / G;
+    const int max_chunks = group_max<G>(chunks);
+    const int max_wy = group_max<G>(wy);
+    // y steps all groups take (no per-lane care needed); beyond, the tail
+    const int min_wy = group_min<G>(wy);
     // column f -> (x, z) = (f mod wx, f div wx) as floor((f + 1/2) / wx): the fraction stays
     // at least 1/(2 wx) away from an integer, far beyond the hardware reciprocal's error for
     // any f < 2^20
@@ -106,7 +127,7 @@ __device__ __forceinline__ void four_gaussians(const BackwardArgs& a, int kk, ui
     float mxx = 0.0f, myy = 0.0f, mzz = 0.0f, mxy = 0.0f, mxz = 0.0f, myz = 0.0f;
 #pragma unroll 1
     for (int c = 0; c < max_chunks; ++c) {
-        const int f = c * 16 + ql;
+        const int f = c * G + ql;
         const bool act = f < fp;
         const int z = (int)(((float)f + 0.5f) * inv_wx);
         const int x = f - z * wx;
@@ -177,16 +198,16 @@ __device__ __forceinline__ void four_gaussians(const BackwardArgs& a, int kk, ui
         myz += S1 * dz;
         myy += S2;
     }
-    m0 = row_sum(m0);
-    mx = row_sum(mx);
-    my = row_sum(my);
-    mz = row_sum(mz);
-    mxx = row_sum(mxx);
-    myy = row_sum(myy);
-    mzz = row_sum(mzz);
-    mxy = row_sum(mxy);
-    mxz = row_sum(mxz);
-    myz = row_sum(myz);
+    m0 = group_sum<G>(m0);
+    mx = group_sum<G>(mx);
+    my = group_sum<G>(my);
+    mz = group_sum<G>(mz);
+    mxx = group_sum<G>(mxx);
+    myy = group_sum<G>(myy);
+    mzz = group_sum<G>(mzz);
+    mxy = group_sum<G>(mxy);
+    mxz = group_sum<G>(mxz);
+    myz = group_sum<G>(myz);
     if (ql == 0 && gvalid) {
         // K as a full symmetric matrix has off-diagonal entries kxy/2, kxz/2, kyz/2
         const float Al = (nonempty ? r0.w : 0.0f) * GM_LN2F;   // amp ln2
@@ -203,20 +224,21 @@ __device__ __forceinline__ void four_gaussians(const BackwardArgs& a, int kk, ui
     }
 }
 
-// Takes the next (up to) four Gaussians of `todo` (bit i = entry i of the wave's 64, whose
-// id is in v), one per row.
-__device__ __forceinline__ void take_four(uint64_t& todo, uint32_t v, uint32_t& mine, bool& valid)
+// Takes the next (up to) 64/G Gaussians of `todo` (bit i = entry i of the wave's 64, whose
+// id is in v), one per group of G lanes.
+template <int G>
+__device__ __forceinline__ void take_group(uint64_t& todo, uint32_t v, uint32_t& mine, bool& valid)
 {
-    const int row = (threadIdx.x & 63) >> 4;
+    const int grp = (threadIdx.x & 63) / G;
     mine = 0u;
     valid = false;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < 64 / G; ++r) {
         if (todo) {
             const int ib = __builtin_ctzll(todo);
             todo &= todo - 1;
             const uint32_t vb = __builtin_amdgcn_readlane(v, ib);
-            if (row == r) {
+            if (grp == r) {
                 mine = vb;
                 valid = true;
             }
@@ -298,15 +320,15 @@ __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
         while (in_lds) {
             uint32_t mine;
             bool valid;
-            take_four(in_lds, v, mine, valid);
-            four_gaussians<true>(a, kk, mine, valid, region, t0x, t0y, t0z);
+            take_group<BWD_G>(in_lds, v, mine, valid);
+            group_of_gaussians<BWD_G, true>(a, kk, mine, valid, region, t0x, t0y, t0z);
         }
 #pragma unroll 1
         while (in_global) {
             uint32_t mine;
             bool valid;
-            take_four(in_global, v, mine, valid);
-            four_gaussians<false>(a, kk, mine, valid, region, t0x, t0y, t0z);
+            take_group<BWD_G>(in_global, v, mine, valid);
+            group_of_gaussians<BWD_G, false>(a, kk, mine, valid, region, t0x, t0y, t0z);
         }
     }
 }

@@ -3,7 +3,7 @@
 // record's amplitude and conic).
 //
 // One wavefront owns one GM_TX x GM_TY x GM_TZ tile and accumulates it in LDS.  It walks
-// the tile's Gaussian list (ascending id) in batches of 64: each lane loads one record and
+// the tile's Gaussian list (ascending id) in batches of 32: a lane loads one record and
 // prepares that Gaussian's piece (box intersect tile) in LDS.  Then the pieces are taken in
 // list order.  A lane holds one (x, y) column of a piece's footprint and walks the piece's
 // z-range, so the in-plane part of the exponent is formed once per column and each voxel
@@ -22,7 +22,7 @@ __device__ __forceinline__ int sgpr(int v) { return __builtin_amdgcn_readfirstla
 __device__ __forceinline__ uint32_t magic20(uint32_t d) { return ((1u << 20) + d - 1u) / d; }
 __device__ __forceinline__ uint32_t div20(uint32_t q, uint32_t M) { return __umul24(q, M) >> 20; }
 
-// Per (Gaussian, tile) piece, prepared lane-parallel for a batch of 64 list entries:
+// Per (Gaussian, tile) piece, prepared lane-parallel for a batch of list entries:
 // centre relative to the intersection origin, amplitude, base-2 conic (off-diagonals
 // doubled), footprint width and area, z extent, the magic divisor for the column unravel
 // and the LDS index of the intersection origin.
@@ -105,10 +105,14 @@ __device__ __forceinline__ void paired_pieces(const Piece& p, float* acc, bool a
     lds_order();
 }
 
+// List entries prepared per batch; 32 keeps the LDS of a wavefront at 6 KB so that six
+// wavefronts fit per SIMD.
+constexpr int RB = 32;
+
 __global__ __launch_bounds__(64) void k_render(const RenderArgs a)
 {
     __shared__ float acc[GM_TILE_VOX];
-    __shared__ Piece pc[64];
+    __shared__ Piece pc[RB];
     const int lane = threadIdx.x;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     int r = 0;
@@ -129,8 +133,8 @@ __global__ __launch_bounds__(64) void k_render(const RenderArgs a)
     const int e = sgpr(a.tile_start[bt + 1]);
 
 #pragma unroll 1
-    for (int b0 = s; b0 < e; b0 += 64) {
-        const int nb = min(64, e - b0);
+    for (int b0 = s; b0 < e; b0 += RB) {
+        const int nb = min(RB, e - b0);
         __syncthreads();
         bool small = false;
         if (lane < nb) {

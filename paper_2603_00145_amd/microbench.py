@@ -1,0 +1,118 @@
+"""Throughput of the MFMA parts of the path (neural residual field, warm-start network) on
+their own, timed with HIP events on the launch stream, against the dense BF16 MFMA peak.
+
+    python -m paper_2603_00145_amd.microbench [--reps 10]
+
+Prints one JSON line per measurement.  The algorithmic FLOP counts are the multiply-adds of
+the layers as the kernels run them (inputs zero-padded to a multiple of 16 features):
+    NRF forward, per point:   2 (in_pad*64 + (D-1)*64*64 + 64)
+    NRF backward, per point:  forward recompute + dA (2 per weight of the hidden and input
+                              layers but the first) + dW (2 per weight)
+    warm-start forward, per Gaussian: 2 * sum_l (c_out * K_pad,l * positions_out,l) + head
+    warm-start training step: forward + backward-data (all but the first layer) + backward-
+                              weights, i.e. about 3x forward.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+
+import torch
+
+from . import api, inputs, nrf, warmstart
+
+BF16_PEAK = 2.5e15          # dense MFMA FLOP/s of MI355X in BF16
+
+
+def _time(fn, reps):
+    s = torch.cuda.current_stream()
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps / 1e3
+
+
+def nrf_flops(net, backward=False):
+    w = net.in_pad * 64 + (net.depth - 1) * 64 * 64 + 64
+    fwd = 2 * w
+    if not backward:
+        return fwd
+    da = 2 * ((net.depth - 1) * 64 * 64 + 64)    # dA through the hidden layers and head
+    dw = 2 * w
+    return fwd + da + dw
+
+
+def warm_flops_forward():
+    layers = [(32, 96, 512), (32, 864, 64), (32, 864, 8), (32, 256, 1)]   # c_out, K_pad, P_out
+    return 2 * sum(c * k * p for c, k, p in layers) + 2 * 8 * 32
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--reps", type=int, default=10)
+    args = ap.parse_args()
+    api.load()
+    dev = torch.device("cuda", 0)
+    out = []
+
+    # NRF forward on the 256^3 volume and backward on 2^18 samples of each of three stacks
+    w = inputs.workload("c256", with_data=False)
+    net = nrf.NRF(n_freq=16, depth=3, seed=1, zero_last=False)
+    vol = torch.zeros(w.volume.shape, dtype=torch.float32, device=dev)
+    t = _time(lambda: net.forward_add(w.volume, vol), args.reps)
+    pts = w.volume.n_voxels
+    f = nrf_flops(net) * pts
+    out.append({"what": "nrf_forward", "points": pts, "seconds": t, "points_per_s": pts / t,
+                "tflops": f / t / 1e12, "mfma_frac": f / t / BF16_PEAK,
+                "config": "L=16, in_pad 128, 3 x 64 SiLU, 256^3 voxel centres"})
+    g = torch.Generator(device=dev)
+    g.manual_seed(0)
+    dl = torch.randn(w.stacks[0].shape, device=dev, generator=g)
+    idx = torch.randint(0, w.stacks[0].n_voxels, (1 << 18,), device=dev, dtype=torch.int32,
+                        generator=g)
+
+    def nrf_bwd():
+        net.zero_grad()
+        for s in w.stacks:
+            net.backward(s, dl, idx=idx)
+    t = _time(nrf_bwd, args.reps)
+    pts = 3 * (1 << 18)
+    f = nrf_flops(net, backward=True) * pts
+    out.append({"what": "nrf_backward", "points": pts, "seconds": t, "points_per_s": pts / t,
+                "tflops": f / t / 1e12, "mfma_frac": f / t / BF16_PEAK,
+                "config": "2^18 sampled voxels on each of three 256x256x64 stacks"})
+
+    # warm-start network: inference on 256k Gaussians, one training step of batch 1024
+    ws = warmstart.WarmStartNet(seed=0, zero_head=False)
+    n = 1 << 18
+    patches = torch.rand((n, 3, 512), device=dev, generator=g)
+    patches = patches.to(torch.bfloat16).view(torch.int16).contiguous()
+    s0 = torch.full((n, 3), -4.0, device=dev)
+    l0 = torch.zeros(n, device=dev)
+    t = _time(lambda: ws.forward(patches, s0, l0), args.reps)
+    f = warm_flops_forward() * n
+    out.append({"what": "warmstart_forward", "gaussians": n, "seconds": t, "gaussians_per_s": n / t,
+                "tflops": f / t / 1e12, "mfma_frac": f / t / BF16_PEAK,
+                "config": "3 x 8^3 BF16 patches, four 3D convs of width 32 + head"})
+    b = 1024
+    sig = warmstart.sym6(s0[:b] + 0.1, torch.tensor([[1.0, 0.1, 0.0, 0.0]], device=dev).repeat(b, 1))
+    lt = torch.zeros(b, device=dev)
+    t = _time(lambda: ws.backward(patches[:b].contiguous(), s0[:b].contiguous(), l0[:b].contiguous(),
+                                  sig, lt), args.reps)
+    f = 3 * warm_flops_forward() * b
+    out.append({"what": "warmstart_train_step", "gaussians": b, "seconds": t,
+                "gaussians_per_s": b / t, "tflops": f / t / 1e12, "mfma_frac": f / t / BF16_PEAK,
+                "config": "batch 1024: forward, loss head, backward-data and backward-weights"})
+    for o in out:
+        print(json.dumps(o))
+        sys.stdout.flush()
+
+
+if __name__ == "__main__":
+    main()

@@ -86,19 +86,24 @@ class WarmStartNet:
                                   ctypes.c_void_p(out.data_ptr()), api._stream()))
         return out
 
-    def forward(self, patches, s0, logit0):
-        """(log_scale, quat, logit) for a batch (n a multiple of 16)."""
+    def forward(self, patches, s0, logit0, chunk: int = 1 << 16):
+        """(log_scale, quat, logit) for a batch (n a multiple of 16), in chunks of `chunk`
+        Gaussians so that the activation workspace stays bounded."""
         n = patches.shape[0]
         dev = patches.device
         s = torch.empty((n, 3), device=dev)
         q = torch.empty((n, 4), device=dev)
         lg = torch.empty((n,), device=dev)
-        ws = self._workspace(n, dev)
+        ws = self._workspace(min(n, chunk), dev)
         P = ctypes.c_void_p
-        check(load().gm_ws_forward(ctypes.byref(self.struct()), P(patches.data_ptr()), n,
-                                   P(s0.data_ptr()), P(logit0.data_ptr()), P(s.data_ptr()),
-                                   P(q.data_ptr()), P(lg.data_ptr()), P(ws.data_ptr()),
-                                   ws.numel() * 4, api._stream()))
+        st = self.struct()
+        for i0 in range(0, n, chunk):
+            m = min(chunk, n - i0)
+            check(load().gm_ws_forward(ctypes.byref(st), P(patches[i0].data_ptr()), m,
+                                       P(s0[i0].data_ptr()), P(logit0[i0:].data_ptr()),
+                                       P(s[i0].data_ptr()), P(q[i0].data_ptr()),
+                                       P(lg[i0:].data_ptr()), P(ws.data_ptr()), ws.numel() * 4,
+                                       api._stream()))
         return s, q, lg
 
     def backward(self, patches, s0, logit0, sig_t, logit_t):

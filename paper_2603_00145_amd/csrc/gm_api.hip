@@ -235,8 +235,7 @@ NrfLayout nrf_layout(const gm_nrf* n, int64_t npts)
     for (int l = 0; l < n->depth; ++l) L.off_dz[l] = take((size_t)64 * L.P * 2);
     L.off_a[0] = take((size_t)n->in_pad * L.P * 2);
     for (int l = 1; l <= n->depth; ++l) L.off_a[l] = take((size_t)64 * L.P * 2);
-    const int64_t nchunk = (L.P + 1023) / 1024;
-    L.off_part = take((size_t)nchunk * 64 * (n->in_pad > 64 ? n->in_pad : 64) * 4);
+    L.off_part = take(nrf_part_floats(L.P, n->in_pad) * 4);
     L.bytes = o;
     return L;
 }

@@ -202,6 +202,8 @@ struct NrfWork {
     float* part;             // split-K partials
 };
 hipError_t launch_nrf_forward(const NrfArgs& a, hipStream_t s);
+// floats of split-K / row-sum partials gm_nrf_backward needs for P points
+size_t nrf_part_floats(int64_t P, int in_pad);
 hipError_t launch_nrf_backward(const NrfArgs& a, const NrfWork& w, hipStream_t s);
 hipError_t launch_to_bf16(const float* in, uint16_t* out, int64_t n, hipStream_t s);
 

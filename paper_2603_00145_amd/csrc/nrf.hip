@@ -289,34 +289,44 @@ __global__ __launch_bounds__(256) void k_nrf_chain(const NrfArgs a, NrfWork w)
     }
 }
 
-// Split-K GEMM over points: part[chunk][m][n] = sum_{p in chunk} L[m][p] R[n][p], with L
-// [M][P] and R [N][P] BF16 (M, N multiples of 16, P a multiple of 16).  One block per
-// chunk of 1024 points; its 4 wavefronts share the output tiles.
+// Split-K GEMM over points: part[grp][m][n] = sum_{p in grp} L[m][p] R[n][p], with L [M][P]
+// and R [N][P] BF16 (M, N multiples of 16, P a multiple of 16).  One block per (16 x 16 output
+// tile, group of 4 GP points): each wavefront accumulates the tile over its GP points on MFMA,
+// then the four tiles are added in LDS in a fixed order.
+constexpr int GP = 4096;
+
 __global__ __launch_bounds__(256) void k_gemm_nt_splitk(const uint16_t* __restrict__ L,
                                                         const uint16_t* __restrict__ R, int M,
                                                         int N, int64_t P, float* __restrict__ part)
 {
+    __shared__ float sh[4][256];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, row = lane & 15;
-    const int64_t p0 = (int64_t)blockIdx.x * 1024;
-    const int64_t p1 = min(p0 + 1024, P);
-    const int mt = M / 16, nt = N / 16;
-    float* out = part + (int64_t)blockIdx.x * M * N;
-    for (int tile = wave; tile < mt * nt; tile += 4) {
-        const int tm = tile / nt, tn = tile % nt;
-        v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        const uint16_t* lp = L + (int64_t)(16 * tm + row) * P + 4 * g;
-        const uint16_t* rp = R + (int64_t)(16 * tn + row) * P + 4 * g;
-        for (int64_t q = p0; q < p1; q += 16) {
-            const v4s A = *reinterpret_cast<const v4s*>(lp + q);
-            const v4s B = *reinterpret_cast<const v4s*>(rp + q);
-            acc = mfma(A, B, acc);
-        }
-        // acc holds rows 16 tm + 4 g + j, column 16 tn + row
+    const int nt = N / 16;
+    const int tm = blockIdx.x / nt, tn = blockIdx.x % nt;
+    const int64_t p0 = ((int64_t)blockIdx.y * 4 + wave) * GP;
+    const int64_t p1 = min(p0 + GP, P);
+    v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    const uint16_t* lp = L + (int64_t)(16 * tm + row) * P + 4 * g;
+    const uint16_t* rp = R + (int64_t)(16 * tn + row) * P + 4 * g;
+    for (int64_t q = p0; q < p1; q += 16) {
+        const v4s A = *reinterpret_cast<const v4s*>(lp + q);
+        const v4s B = *reinterpret_cast<const v4s*>(rp + q);
+        acc = mfma(A, B, acc);
+    }
+    // acc holds rows 16 tm + 4 g + j, column 16 tn + row
+    sh[wave][lane * 4 + 0] = acc.x;
+    sh[wave][lane * 4 + 1] = acc.y;
+    sh[wave][lane * 4 + 2] = acc.z;
+    sh[wave][lane * 4 + 3] = acc.w;
+    __syncthreads();
+    if (wave == 0) {
+        float* out = part + (int64_t)blockIdx.y * M * N;
         const int c = 16 * tn + row;
-        out[(16 * tm + 4 * g + 0) * N + c] = acc.x;
-        out[(16 * tm + 4 * g + 1) * N + c] = acc.y;
-        out[(16 * tm + 4 * g + 2) * N + c] = acc.z;
-        out[(16 * tm + 4 * g + 3) * N + c] = acc.w;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int e = lane * 4 + j;
+            out[(16 * tm + 4 * g + j) * N + c] = ((sh[0][e] + sh[1][e]) + sh[2][e]) + sh[3][e];
+        }
     }
 }
 
@@ -331,38 +341,30 @@ __global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ par
     out[e] += s;
 }
 
-// out[m] += sum_p L[m][p] * v[p] (v = NULL: plain row sums); BF16 rows, f32 v; block per row
-__global__ __launch_bounds__(256) void k_rowdot(const uint16_t* __restrict__ L,
-                                                const float* __restrict__ v, int64_t P,
-                                                float* __restrict__ out)
-{
-    __shared__ float sh[256];
-    const uint16_t* r = L + (int64_t)blockIdx.x * P;
-    float acc = 0.0f;
-    for (int64_t p = threadIdx.x; p < P; p += 256) acc += from_bf16(r[p]) * (v ? v[p] : 1.0f);
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[blockIdx.x] += sh[0];
-}
+// Partial row sums over a chunk of points: part[chunk][m] = sum_{p in chunk} l(m, p) v(p),
+// with l = the BF16 row L[m] (or 1 if L is NULL) and v = the f32 vector (or 1 if NULL).
+// Grid (rows, chunks of RD_CHUNK points); the chunks are added in a fixed order afterwards.
+constexpr int RD_CHUNK = 8192;
 
-// sum of the f32 vector v[P] into out[0]
-__global__ __launch_bounds__(256) void k_vsum(const float* __restrict__ v, int64_t P,
-                                              float* __restrict__ out)
+__global__ __launch_bounds__(256) void k_rowdot_part(const uint16_t* __restrict__ L,
+                                                     const float* __restrict__ v, int64_t P,
+                                                     int rows, float* __restrict__ part)
 {
     __shared__ float sh[256];
+    const int m = blockIdx.x;
+    const int64_t p0 = (int64_t)blockIdx.y * RD_CHUNK;
+    const int64_t p1 = min(p0 + RD_CHUNK, P);
+    const uint16_t* r = L ? L + (int64_t)m * P : nullptr;
     float acc = 0.0f;
-    for (int64_t p = threadIdx.x; p < P; p += 256) acc += v[p];
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += 256)
+        acc += (r ? from_bf16(r[p]) : 1.0f) * (v ? v[p] : 1.0f);
     sh[threadIdx.x] = acc;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[0] += sh[0];
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.y * rows + m] = sh[0];
 }
 
 __global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ in,
@@ -418,25 +420,43 @@ hipError_t launch_nrf_forward(const NrfArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+// out[m] += sum_p l(m, p) v(p) for m < rows (see k_rowdot_part); part needs
+// rows * ceil(P / RD_CHUNK) floats.
+static void rowdot(const uint16_t* L, const float* v, int64_t P, int rows, float* part, float* out,
+                   hipStream_t s)
+{
+    const int64_t nchunk = (P + RD_CHUNK - 1) / RD_CHUNK;
+    hipLaunchKernelGGL(k_rowdot_part, dim3((unsigned)rows, (unsigned)nchunk), dim3(256), 0, s, L,
+                       v, P, rows, part);
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, part,
+                       nchunk, (int64_t)rows, out);
+}
+
+size_t nrf_part_floats(int64_t P, int in_pad)
+{
+    const int64_t gemm = ((P + 4 * GP - 1) / (4 * GP)) * W * (in_pad > W ? in_pad : W);
+    const int64_t rows = W * ((P + RD_CHUNK - 1) / RD_CHUNK);
+    return (size_t)(gemm > rows ? gemm : rows);
+}
+
 hipError_t launch_nrf_backward(const NrfArgs& a, const NrfWork& w, hipStream_t s)
 {
     if (a.n_points <= 0) return hipSuccess;
     GM_NRF_DISPATCH(launch_chain_t, a, w, s)
-    const int64_t nchunk = (w.P + 1023) / 1024;
+    const int64_t nchunk = (w.P + 4 * GP - 1) / (4 * GP);
     for (int l = 0; l < a.depth; ++l) {
         const int N = l == 0 ? a.in_pad : W;
         float* dst = l == 0 ? a.g_w_in : a.g_w_hid + (int64_t)(l - 1) * W * W;
         float* dbias = l == 0 ? a.g_b_in : a.g_b_hid + (int64_t)(l - 1) * W;
-        hipLaunchKernelGGL(k_gemm_nt_splitk, dim3((unsigned)nchunk), dim3(256), 0, s, w.dz[l],
-                           w.a[l], W, N, w.P, w.part);
+        hipLaunchKernelGGL(k_gemm_nt_splitk, dim3((unsigned)((W / 16) * (N / 16)), (unsigned)nchunk),
+                           dim3(256), 0, s, w.dz[l], w.a[l], W, N, w.P, w.part);
         const int64_t n = (int64_t)W * N;
         hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w.part,
                            nchunk, n, dst);
-        hipLaunchKernelGGL(k_rowdot, dim3(W), dim3(256), 0, s, w.dz[l], (const float*)nullptr, w.P,
-                           dbias);
+        rowdot(w.dz[l], nullptr, w.P, W, w.part, dbias, s);
     }
-    hipLaunchKernelGGL(k_rowdot, dim3(W), dim3(256), 0, s, w.a[a.depth], w.dzo, w.P, a.g_w_out);
-    hipLaunchKernelGGL(k_vsum, dim3(1), dim3(256), 0, s, w.dzo, w.P, a.g_b_out);
+    rowdot(w.a[a.depth], w.dzo, w.P, W, w.part, a.g_w_out, s);
+    rowdot(nullptr, w.dzo, w.P, 1, w.part, a.g_b_out, s);
     return hipGetLastError();
 }
 

@@ -47,10 +47,13 @@ __device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c)
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+// sigmoid with the hardware reciprocal (1 ulp; the field runs in BF16): exp(-z) overflows to
+// +inf for very negative z, whose reciprocal is 0, the right limit
+__device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu(float z) { return z * sigm(z); }
 __device__ __forceinline__ float dsilu(float z)
 {
-    const float s = 1.0f / (1.0f + __expf(-z));
+    const float s = sigm(z);
     return s * (1.0f + z * (1.0f - s));
 }
 
@@ -91,13 +94,16 @@ __device__ void load_weights(const NrfArgs& a, Lds& s)
     __syncthreads();
 }
 
+// voxel (x, y, z) of point p (grids hold < 2^31 voxels, so 32-bit division suffices)
 __device__ __forceinline__ void point_xyz(const NrfArgs& a, int64_t p, int* vx, int* vy, int* vz)
 {
-    int64_t v = a.idx ? (int64_t)a.idx[p] : p;
-    *vx = (int)(v % a.nx);
-    v /= a.nx;
-    *vy = (int)(v % a.ny);
-    *vz = (int)(v / a.ny);
+    uint32_t v = a.idx ? (uint32_t)a.idx[p] : (uint32_t)p;
+    const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny;
+    const uint32_t q = v / nx;
+    *vx = (int)(v - q * nx);
+    const uint32_t r = q / ny;
+    *vy = (int)(q - r * ny);
+    *vz = (int)r;
 }
 
 // Forward for the 16 points of a tile: fills B0 (encoding), Z (pre-activations) and the

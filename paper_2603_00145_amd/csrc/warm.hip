@@ -23,10 +23,13 @@ __device__ __forceinline__ uint16_t to_bf16(float f)
     return (uint16_t)(u >> 16);
 }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+// sigmoid with the hardware reciprocal (1 ulp; the network runs in BF16): exp(-z) overflows
+// to +inf for very negative z, whose reciprocal is 0, the right limit
+__device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu(float z) { return z * sigm(z); }
 __device__ __forceinline__ float dsilu(float z)
 {
-    const float s = 1.0f / (1.0f + __expf(-z));
+    const float s = sigm(z);
     return s * (1.0f + z * (1.0f - s));
 }
 __device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c)

@@ -164,7 +164,10 @@ gm_status gm_render_stacks(const gm_bins* bins, const int32_t* grid_ids, int32_t
 /* Neural residual field parameters for the fused volume epilogue (Eq. 8).  Weights are
  * bf16 stored as uint16 bit patterns, row-major [out][in]; biases float32.
  * n_freq frequency bands: input features (x, sin(2^k pi x), cos(2^k pi x)), k < n_freq,
- * dimension 3 + 6 n_freq, zero-padded to in_pad (64 or 128).  depth hidden layers of
+ * dimension 3 + 6 n_freq, zero-padded to in_pad: 64 (n_freq <= 8) or 128 (n_freq <= 20;
+ * the kernels group the bands in fours, which is why 9 or 10 bands need in_pad 128 although
+ * 3 + 6 n_freq <= 64).  Feature order: x_a at a, sin(2^k pi x_a) at 3 + 6 k + a, cos(2^k pi x_a)
+ * at 6 + 6 k + a (a < 3); padded columns of w_in are ignored.  depth hidden layers of
  * width (SiLU), then a linear output; r = out_scale * tanh(output). */
 typedef struct gm_nrf {
     int32_t n_freq, depth, width, in_pad;
@@ -190,8 +193,9 @@ gm_status gm_render_volume(const gm_bins* bins, int32_t grid_id, const gm_nrf* n
 gm_status gm_index_to_world(const gm_grid* grid, double out[12]);
 
 /* Neural residual field forward (Sec. 3.4, Eq. 8) on every voxel of grid: out[v] += r(x_v).
- * Requires width 64, 1 <= depth <= 4, in_pad 64 or 128 with 3 + 6 n_freq <= in_pad.  MFMA BF16 x BF16 -> FP32 for the layers; encoding, bias, SiLU, the output layer
- * and tanh in FP32. */
+ * Requires width 64, 1 <= depth <= 4, in_pad and n_freq as for gm_nrf.  MFMA BF16 x BF16 ->
+ * FP32 for the layers; encoding, bias, SiLU and tanh in FP32, activations (the last layer's
+ * too, which feeds the output layer) rounded to BF16. */
 gm_status gm_nrf_forward(const gm_nrf* nrf, const gm_grid* grid, float* out, gm_stream stream);
 
 /* Weight gradients (FP32) of the field, accumulated (+=); same shapes as gm_nrf's weights. */

@@ -187,8 +187,9 @@ gm_status check_nrf(const gm_nrf* n)
     if (n->depth < 1 || n->depth > 4) return fail(GM_ERR_UNSUPPORTED, "nrf depth outside [1, 4]");
     if (n->in_pad != 64 && n->in_pad != 128)
         return fail(GM_ERR_UNSUPPORTED, "nrf in_pad must be 64 or 128");
-    if (n->n_freq < 0 || 3 + 6 * n->n_freq > n->in_pad)
-        return fail(GM_ERR_INVALID_ARGUMENT, "nrf needs 3 + 6 n_freq <= in_pad");
+    if (n->n_freq < 0 || n->n_freq > nrf_max_bands(n->in_pad))
+        return fail(GM_ERR_INVALID_ARGUMENT,
+                    "nrf n_freq outside [0, 8] (in_pad 64) or [0, 20] (in_pad 128)");
     if (!isfinite(n->out_scale)) return fail(GM_ERR_INVALID_ARGUMENT, "nrf out_scale not finite");
     if (!n->w_in || !n->b_in || !n->w_out || !n->b_out || (n->depth > 1 && (!n->w_hid || !n->b_hid)))
         return fail(GM_ERR_INVALID_ARGUMENT, "nrf weight pointer is NULL");

@@ -201,6 +201,8 @@ struct NrfWork {
     uint16_t* a[5];          // a[0] [in_pad][P], a[l] [64][P]
     float* part;             // split-K partials
 };
+// most frequency bands the kernels encode with in_pad 64 / 128 input features
+int nrf_max_bands(int in_pad);
 hipError_t launch_nrf_forward(const NrfArgs& a, hipStream_t s);
 // floats of split-K / row-sum partials gm_nrf_backward needs for P points
 size_t nrf_part_floats(int64_t P, int in_pad);

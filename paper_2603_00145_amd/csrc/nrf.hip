@@ -24,22 +24,22 @@ constexpr int W = 64;          // hidden width (fixed)
 constexpr int MAX_IN = 128;    // in_pad <= 128
 constexpr int MAX_DEPTH = 4;   // depth <= 4, in_pad in {64, 128}
 
+// float -> bfloat16 bits, round to nearest even (gfx950's v_cvt_pk_bf16_f32)
 __device__ __forceinline__ uint16_t to_bf16(float f)
 {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+
+// four floats -> BF16 bits, round to nearest even, two per v_cvt_pk_bf16_f32
 __device__ __forceinline__ v4s pack4(float a, float b, float c, float d)
 {
-    v4s r;
-    r.x = (short)to_bf16(a);
-    r.y = (short)to_bf16(b);
-    r.z = (short)to_bf16(c);
-    r.w = (short)to_bf16(d);
-    return r;
+    const uint32_t lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(v2f{a, b}, v2bf));
+    const uint32_t hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(v2f{c, d}, v2bf));
+    return __builtin_bit_cast(v4s, (uint64_t)lo | ((uint64_t)hi << 32));
 }
 
 __device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c)
@@ -57,40 +57,111 @@ __device__ __forceinline__ float dsilu(float z)
     return s * (1.0f + z * (1.0f - s));
 }
 
-// World coordinate of voxel (vx, vy, vz): binary64 without contraction, rounded once.
+// World coordinate of voxel (vx, vy, vz): binary64 without contraction (hipcc fuses a * b + c
+// by default, the pragma stops it here), rounded once to binary32.
 __device__ __forceinline__ float world_coord(const double* M, int vx, int vy, int vz)
 {
-    double s = __dmul_rn(M[0], (double)vx);
-    s = __dadd_rn(s, __dmul_rn(M[1], (double)vy));
-    s = __dadd_rn(s, __dmul_rn(M[2], (double)vz));
-    s = __dadd_rn(s, M[3]);
+#pragma clang fp contract(off)
+    double s = M[0] * (double)vx;
+    s = s + M[1] * (double)vy;
+    s = s + M[2] * (double)vz;
+    s = s + M[3];
     return (float)s;
 }
 
-// Feature f of the encoding at float coordinates x.
-__device__ __forceinline__ float feature(int f, int n_freq, const float x[3])
+// Order of the encoding along the first layer's K dimension on the GPU.  The MFMA B operand of
+// K-tile t gives lane group g = lane / 16 the features 16 t + 4 g + j, j < 4; call c = 4 t + j
+// the column of that slot.  The last column holds the raw coordinates (x[g] for g < 3, else
+// padding); column c = 6 q + m holds frequency band 4 q + g of kind m (sin of axis m for m < 3,
+// cos of axis m - 3).  Kind, axis and band offset are compile-time constants of the unrolled
+// encoding loop and the lane group only shifts the band, so nothing per slot has to be looked
+// up or kept in registers.  The first layer's weights are permuted into this order when they
+// are staged and its weight gradient is permuted back.  Bands: up to 8 with 4 K-tiles, 20 with 8.
+template <int KT>
+__host__ __device__ constexpr int max_bands() { return 4 * ((4 * KT - 1) / 6); }
+
+// natural feature index (x_a: a; sin(2^k pi x_a): 3 + 6 k + a; cos: 6 + 6 k + a) of GPU slot
+// i = 16 t + 4 g + j, or -1 for padding
+template <int KT>
+__device__ __forceinline__ int natural_feature(int i, int n_freq)
 {
-    if (f < 3) return x[f];
-    const int g = f - 3;
-    const int band = g / 6, r = g - band * 6;
-    if (band >= n_freq) return 0.0f;
-    const int axis = r < 3 ? r : r - 3;
-    const float phi = ldexpf(x[axis], band - 1);      // exact power-of-two scaling
-    const float frac = phi - rintf(phi);              // exact
-    // v_sin_f32 / v_cos_f32 take their argument in revolutions
-    return r < 3 ? __builtin_amdgcn_sinf(frac) : __builtin_amdgcn_cosf(frac);
+    const int t = i >> 4, g = (i >> 2) & 3, j = i & 3, c = 4 * t + j;
+    if (c == 4 * KT - 1) return g < 3 ? g : -1;
+    const int q = c / 6, m = c - 6 * q, band = 4 * q + g;
+    return band < n_freq ? 3 + 6 * band + m : -1;
 }
 
+// The encoding of the lane's point, in the B operand layout of the K-tiles.
+template <int KT>
+__device__ __forceinline__ void encode(const float x[3], int n_freq, v4s b0[KT])
+{
+    const int g = (threadIdx.x >> 4) & 3;
+    const float xg = g == 0 ? x[0] : (g == 1 ? x[1] : x[2]);
+    const int nb = n_freq - g;          // band 4 q + g exists for 4 q < nb
+#pragma unroll
+    for (int t = 0; t < KT; ++t) {
+        float v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = 4 * t + j;
+            if (c == 4 * KT - 1) {
+                v[j] = g < 3 ? xg : 0.0f;
+            } else {
+                const int q = c / 6, m = c % 6;
+                const float phi = ldexpf(x[m % 3], 4 * q - 1 + g);   // exact power-of-two scaling
+                const float frac = phi - rintf(phi);                  // exact
+                // v_sin_f32 / v_cos_f32 take their argument in revolutions
+                const float sc = m < 3 ? __builtin_amdgcn_sinf(frac) : __builtin_amdgcn_cosf(frac);
+                v[j] = 4 * q < nb ? sc : 0.0f;
+            }
+        }
+        b0[t] = pack4(v[0], v[1], v[2], v[3]);
+    }
+}
+
+// Weights staged in LDS in MFMA A-operand order: operand (o, t) of a layer is 64 lanes x 4 BF16,
+// lane (g, row) holding W[16 o + row][16 t + 4 g + j], so that a wavefront reads an operand as
+// 512 contiguous bytes (one ds_read_b64 per lane, free of bank conflicts).
 struct Lds {
-    uint16_t w_in[W * MAX_IN];
-    uint16_t w_hid[(MAX_DEPTH - 1) * W * W];
+    v4s w_in[4 * (MAX_IN / 16) * 64];              // [o][t][lane], K in the GPU encoding order
+    v4s w_hid[(MAX_DEPTH - 1) * 16 * 64];          // [l][o][t][lane]
+};
+// the backward also needs W_l^T as A operand: [l][i][o][lane], lane (g, row) holding
+// W_l[16 o + 4 g + j][16 i + row]
+struct LdsChain {
+    Lds f;
+    v4s w_hid_t[(MAX_DEPTH - 1) * 16 * 64];
 };
 
-__device__ void load_weights(const NrfArgs& a, Lds& s)
+template <int KT>
+__device__ void load_weights(const NrfArgs& a, Lds& s, v4s* w_hid_t = nullptr)
 {
-    const int nin = W * a.in_pad, nh = (a.depth - 1) * W * W;
-    for (int i = threadIdx.x; i < nin; i += blockDim.x) s.w_in[i] = a.w_in[i];
-    for (int i = threadIdx.x; i < nh; i += blockDim.x) s.w_hid[i] = a.w_hid[i];
+    for (int e = threadIdx.x; e < 4 * KT * 64; e += blockDim.x) {
+        const int lane = e & 63, t = (e >> 6) % KT, o = (e >> 6) / KT;
+        const int g = lane >> 4, row = lane & 15;
+        const uint16_t* src = a.w_in + (16 * o + row) * (16 * KT);
+        short v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int nf = natural_feature<KT>(16 * t + 4 * g + j, a.n_freq);
+            v[j] = nf >= 0 ? (short)src[nf] : (short)0;
+        }
+        s.w_in[e] = v4s{v[0], v[1], v[2], v[3]};
+    }
+    const int nh = (a.depth - 1) * 16 * 64;
+    for (int e = threadIdx.x; e < nh; e += blockDim.x) {
+        const int lane = e & 63, t = (e >> 6) & 3, o = (e >> 8) & 3, l = e >> 10;
+        const int g = lane >> 4, row = lane & 15;
+        const uint16_t* Wl = a.w_hid + l * W * W;
+        short v[4], vt[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v[j] = (short)Wl[(16 * o + row) * W + 16 * t + 4 * g + j];
+            vt[j] = (short)Wl[(16 * t + 4 * g + j) * W + 16 * o + row];
+        }
+        s.w_hid[e] = v4s{v[0], v[1], v[2], v[3]};
+        if (w_hid_t) w_hid_t[e] = v4s{vt[0], vt[1], vt[2], vt[3]};
+    }
     __syncthreads();
 }
 
@@ -106,11 +177,10 @@ __device__ __forceinline__ void point_xyz(const NrfArgs& a, int64_t p, int* vx, 
     *vz = (int)r;
 }
 
-// Forward for the 16 points of a tile: fills B0 (encoding), Z (pre-activations) and the
-// BF16 activations A (register layout: o-tile x 4 features of point lane&15).
+// Forward for the 16 points of a tile: Z (pre-activations) and the BF16 activations A
+// (register layout: o-tile x 4 features of point lane&15).
 template <int KT, int DEPTH>
 struct Tile {
-    v4s b0[KT];
     v4f z[DEPTH][4];
     v4s act[DEPTH][4];
 };
@@ -124,37 +194,28 @@ __device__ __forceinline__ void store_fm(uint16_t* dst, int f, int64_t P, int64_
     dst[(int64_t)(f + 3) * P + p] = (uint16_t)v.w;
 }
 
-// With a workspace (w != NULL) the encoding and each layer's BF16 activations are written out
-// feature-major as soon as they are formed (the backward needs them for dW), so they need not
-// stay live in registers.
+// With a workspace (w != NULL) the encoding (in the GPU order) and each layer's BF16
+// activations are written out feature-major as soon as they are formed (the backward needs
+// them for dW), so they need not stay live in registers.
 template <int KT, int DEPTH>
 __device__ __forceinline__ void tile_forward(const NrfArgs& a, const Lds& s, const float x[3],
                                              Tile<KT, DEPTH>& T, const NrfWork* w = nullptr,
                                              int64_t p = 0)
 {
-    const int lane = threadIdx.x & 63, g = lane >> 4, row = lane & 15;
-    constexpr int IN = 16 * KT;
+    const int lane = threadIdx.x & 63, g = lane >> 4;
+    v4s b0[KT];
+    encode<KT>(x, a.n_freq, b0);
+    if (w) {
 #pragma unroll
-    for (int t = 0; t < KT; ++t) {
-        const int f0 = 16 * t + 4 * g;
-        T.b0[t] = pack4(feature(f0, a.n_freq, x), feature(f0 + 1, a.n_freq, x),
-                        feature(f0 + 2, a.n_freq, x), feature(f0 + 3, a.n_freq, x));
-        if (w) store_fm(w->a[0], f0, w->P, p, T.b0[t]);
+        for (int t = 0; t < KT; ++t) store_fm(w->a[0], 16 * t + 4 * g, w->P, p, b0[t]);
     }
     // layer 1
 #pragma unroll
     for (int o = 0; o < 4; ++o) {
-        v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int t = 0; t < KT; ++t) {
-            const v4s A = *reinterpret_cast<const v4s*>(&s.w_in[(16 * o + row) * IN + 16 * t + 4 * g]);
-            acc = mfma(A, T.b0[t], acc);
-        }
         const int f = 16 * o + 4 * g;
-        acc.x += a.b_in[f];
-        acc.y += a.b_in[f + 1];
-        acc.z += a.b_in[f + 2];
-        acc.w += a.b_in[f + 3];
+        v4f acc = {a.b_in[f], a.b_in[f + 1], a.b_in[f + 2], a.b_in[f + 3]};   // bias as C
+#pragma unroll
+        for (int t = 0; t < KT; ++t) acc = mfma(s.w_in[(o * KT + t) * 64 + lane], b0[t], acc);
         T.z[0][o] = acc;
         T.act[0][o] = pack4(silu(acc.x), silu(acc.y), silu(acc.z), silu(acc.w));
         if (w) store_fm(w->a[1], f, w->P, p, T.act[0][o]);
@@ -162,21 +223,14 @@ __device__ __forceinline__ void tile_forward(const NrfArgs& a, const Lds& s, con
     // hidden layers
 #pragma unroll
     for (int l = 1; l < DEPTH; ++l) {
-        const uint16_t* Wl = s.w_hid + (l - 1) * W * W;
+        const v4s* Wl = s.w_hid + (l - 1) * 16 * 64;
         const float* bl = a.b_hid + (l - 1) * W;
 #pragma unroll
         for (int o = 0; o < 4; ++o) {
-            v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const v4s A = *reinterpret_cast<const v4s*>(&Wl[(16 * o + row) * W + 16 * t + 4 * g]);
-                acc = mfma(A, T.act[l - 1][t], acc);
-            }
             const int f = 16 * o + 4 * g;
-            acc.x += bl[f];
-            acc.y += bl[f + 1];
-            acc.z += bl[f + 2];
-            acc.w += bl[f + 3];
+            v4f acc = {bl[f], bl[f + 1], bl[f + 2], bl[f + 3]};
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc = mfma(Wl[(o * 4 + t) * 64 + lane], T.act[l - 1][t], acc);
             T.z[l][o] = acc;
             T.act[l][o] = pack4(silu(acc.x), silu(acc.y), silu(acc.z), silu(acc.w));
             if (w) store_fm(w->a[l + 1], f, w->P, p, T.act[l][o]);
@@ -184,7 +238,8 @@ __device__ __forceinline__ void tile_forward(const NrfArgs& a, const Lds& s, con
     }
 }
 
-// output pre-activation z_o of the tile's point (all 4 lane groups end with the total)
+// output pre-activation z_o of the tile's point from the BF16 activations of the last layer
+// (all 4 lane groups end with the total)
 template <int KT, int DEPTH>
 __device__ __forceinline__ float tile_output(const NrfArgs& a, const Tile<KT, DEPTH>& T)
 {
@@ -192,10 +247,12 @@ __device__ __forceinline__ float tile_output(const NrfArgs& a, const Tile<KT, DE
     float sacc = 0.0f;
 #pragma unroll
     for (int o = 0; o < 4; ++o) {
-        const v4f zz = T.z[DEPTH - 1][o];
+        const v4s h = T.act[DEPTH - 1][o];
         const int f = 16 * o + 4 * g;
-        sacc += from_bf16(a.w_out[f]) * silu(zz.x) + from_bf16(a.w_out[f + 1]) * silu(zz.y) +
-                from_bf16(a.w_out[f + 2]) * silu(zz.z) + from_bf16(a.w_out[f + 3]) * silu(zz.w);
+        sacc += from_bf16(a.w_out[f]) * from_bf16((uint16_t)h.x) +
+                from_bf16(a.w_out[f + 1]) * from_bf16((uint16_t)h.y) +
+                from_bf16(a.w_out[f + 2]) * from_bf16((uint16_t)h.z) +
+                from_bf16(a.w_out[f + 3]) * from_bf16((uint16_t)h.w);
     }
     sacc += __shfl_xor(sacc, 16, 64);
     sacc += __shfl_xor(sacc, 32, 64);
@@ -206,7 +263,7 @@ template <int KT, int DEPTH>
 __global__ __launch_bounds__(256) void k_nrf_forward(const NrfArgs a)
 {
     __shared__ Lds s;
-    load_weights(a, s);
+    load_weights<KT>(a, s);
     const int lane = threadIdx.x & 63, g = lane >> 4, row = lane & 15;
     const int64_t ntiles = (a.n_points + 15) / 16;
     for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntiles;
@@ -232,8 +289,8 @@ __global__ __launch_bounds__(256) void k_nrf_forward(const NrfArgs a)
 template <int KT, int DEPTH>
 __global__ __launch_bounds__(256) void k_nrf_chain(const NrfArgs a, NrfWork w)
 {
-    __shared__ Lds s;
-    load_weights(a, s);
+    __shared__ LdsChain s;
+    load_weights<KT>(a, s.f, s.w_hid_t);
     const int lane = threadIdx.x & 63, g = lane >> 4, row = lane & 15;
     const int64_t P = w.P;
     const int64_t ntiles = P / 16;
@@ -246,7 +303,7 @@ __global__ __launch_bounds__(256) void k_nrf_chain(const NrfArgs a, NrfWork w)
         const float x[3] = {world_coord(a.m, vx, vy, vz), world_coord(a.m + 4, vx, vy, vz),
                             world_coord(a.m + 8, vx, vy, vz)};
         Tile<KT, DEPTH> T;
-        tile_forward<KT, DEPTH>(a, s, x, T, &w, p);
+        tile_forward<KT, DEPTH>(a, s.f, x, T, &w, p);
         const float zo = tile_output<KT, DEPTH>(a, T);
         float dl = 0.0f;
         if (valid) dl = a.dl_dr[((int64_t)vz * a.ny + vy) * a.nx + vx];
@@ -274,21 +331,13 @@ __global__ __launch_bounds__(256) void k_nrf_chain(const NrfArgs a, NrfWork w)
                 store_fm(w.dz[l], 16 * o + 4 * g, P, p, dz[o]);
             }
             if (l == 0) break;
-            // dA_{l-1} = W_l^T dZ_l : A operand = 16 input x 16 output features of W_l^T
-            const uint16_t* Wl = s.w_hid + (l - 1) * W * W;
+            // dA_{l-1} = W_l^T dZ_l
+            const v4s* Wt = s.w_hid_t + (l - 1) * 16 * 64;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-                for (int o = 0; o < 4; ++o) {
-                    v4s A;
-                    const int oo = 16 * o + 4 * g, ii = 16 * i + row;
-                    A.x = (short)Wl[(oo + 0) * W + ii];
-                    A.y = (short)Wl[(oo + 1) * W + ii];
-                    A.z = (short)Wl[(oo + 2) * W + ii];
-                    A.w = (short)Wl[(oo + 3) * W + ii];
-                    acc = mfma(A, dz[o], acc);
-                }
+                for (int o = 0; o < 4; ++o) acc = mfma(Wt[(i * 4 + o) * 64 + lane], dz[o], acc);
                 da[i] = acc;
             }
         }
@@ -347,6 +396,23 @@ __global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ par
     out[e] += s;
 }
 
+// The same for the first layer's weights, whose K dimension the GPU holds in its own encoding
+// order: out[m][natural_feature(i)] += sum_c part[c][m][i]; padding slots are dropped.
+template <int KT>
+__global__ __launch_bounds__(256) void k_sum_parts_in(const float* __restrict__ part,
+                                                      int64_t nchunk, int n_freq,
+                                                      float* __restrict__ out)
+{
+    constexpr int N = 16 * KT;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= W * N) return;
+    const int m = e / N, nf = natural_feature<KT>(e % N, n_freq);
+    if (nf < 0) return;
+    float s = 0.0f;
+    for (int64_t c = 0; c < nchunk; ++c) s += part[c * (W * N) + e];
+    out[m * N + nf] += s;
+}
+
 // Partial row sums over a chunk of points: part[chunk][m] = sum_{p in chunk} l(m, p) v(p),
 // with l = the BF16 row L[m] (or 1 if L is NULL) and v = the f32 vector (or 1 if NULL).
 // Grid (rows, chunks of RD_CHUNK points); the chunks are added in a fixed order afterwards.
@@ -381,11 +447,19 @@ __global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ in,
         out[i] = to_bf16(in[i]);
 }
 
-unsigned blocks_for_tiles(int64_t ntiles)
+// Grid of a tile loop: every block resident at once (the blocks then take equal shares of the
+// tiles, with no partial last wave of blocks), capped by the work.
+template <typename K>
+unsigned blocks_for_tiles(K kernel, int64_t ntiles)
 {
+    int dev = 0, cus = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0);
+    int64_t full = (int64_t)(cus > 0 ? cus : 256) * (per_cu > 0 ? per_cu : 1);
     int64_t b = (ntiles + 3) / 4;
+    if (b > full) b = full;
     if (b < 1) b = 1;
-    if (b > 2048) b = 2048;
     return (unsigned)b;
 }
 
@@ -394,18 +468,18 @@ unsigned blocks_for_tiles(int64_t ntiles)
 template <int KT, int DEPTH>
 void launch_fwd_t(const NrfArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_nrf_forward<KT, DEPTH>), dim3(blocks_for_tiles((a.n_points + 15) / 16)),
-                       dim3(256), 0, s, a);
+    const unsigned nb = blocks_for_tiles(k_nrf_forward<KT, DEPTH>, (a.n_points + 15) / 16);
+    hipLaunchKernelGGL((k_nrf_forward<KT, DEPTH>), dim3(nb), dim3(256), 0, s, a);
 }
 
 template <int KT, int DEPTH>
 void launch_chain_t(const NrfArgs& a, const NrfWork& w, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_nrf_chain<KT, DEPTH>), dim3(blocks_for_tiles(w.P / 16)), dim3(256), 0, s,
-                       a, w);
+    const unsigned nb = blocks_for_tiles(k_nrf_chain<KT, DEPTH>, w.P / 16);
+    hipLaunchKernelGGL((k_nrf_chain<KT, DEPTH>), dim3(nb), dim3(256), 0, s, a, w);
 }
 
-// supported shapes: in_pad 64 or 128 (4 or 8 K-tiles), depth 1..4
+// supported shapes: in_pad 64 or 128 (4 or 8 K-tiles; at most max_bands<KT>() bands), depth 1..4
 #define GM_NRF_DISPATCH(FN, ...)                                                           \
     switch ((a.in_pad >> 4) * 8 + a.depth) {                                               \
     case 4 * 8 + 1: FN<4, 1>(__VA_ARGS__); break;                                          \
@@ -418,6 +492,8 @@ void launch_chain_t(const NrfArgs& a, const NrfWork& w, hipStream_t s)
     case 8 * 8 + 4: FN<8, 4>(__VA_ARGS__); break;                                          \
     default: return hipErrorInvalidValue;                                                  \
     }
+
+int nrf_max_bands(int in_pad) { return in_pad == 64 ? max_bands<4>() : max_bands<8>(); }
 
 hipError_t launch_nrf_forward(const NrfArgs& a, hipStream_t s)
 {
@@ -457,8 +533,13 @@ hipError_t launch_nrf_backward(const NrfArgs& a, const NrfWork& w, hipStream_t s
         hipLaunchKernelGGL(k_gemm_nt_splitk, dim3((unsigned)((W / 16) * (N / 16)), (unsigned)nchunk),
                            dim3(256), 0, s, w.dz[l], w.a[l], W, N, w.P, w.part);
         const int64_t n = (int64_t)W * N;
-        hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w.part,
-                           nchunk, n, dst);
+        const dim3 grid((unsigned)((n + 255) / 256));
+        if (l > 0)
+            hipLaunchKernelGGL(k_sum_parts, grid, dim3(256), 0, s, w.part, nchunk, n, dst);
+        else if (N == 64)
+            hipLaunchKernelGGL(k_sum_parts_in<4>, grid, dim3(256), 0, s, w.part, nchunk, a.n_freq, dst);
+        else
+            hipLaunchKernelGGL(k_sum_parts_in<8>, grid, dim3(256), 0, s, w.part, nchunk, a.n_freq, dst);
         rowdot(w.dz[l], nullptr, w.P, W, w.part, dbias, s);
     }
     rowdot(w.a[a.depth], w.dzo, w.P, W, w.part, a.g_w_out, s);

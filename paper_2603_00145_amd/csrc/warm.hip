@@ -16,11 +16,10 @@ namespace {
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+// float -> bfloat16 bits, round to nearest even (gfx950's v_cvt_pk_bf16_f32)
 __device__ __forceinline__ uint16_t to_bf16(float f)
 {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 // sigmoid with the hardware reciprocal (1 ulp; the network runs in BF16): exp(-z) overflows

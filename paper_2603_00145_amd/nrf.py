@@ -21,9 +21,10 @@ class NRF:
                  zero_last: bool = True, device="cuda"):
         self.n_freq, self.depth, self.width, self.out_scale = n_freq, depth, 64, out_scale
         self.in_dim = 3 + 6 * n_freq
-        self.in_pad = 64 if self.in_dim <= 64 else 128
-        if self.in_dim > 128:
-            raise ValueError("n_freq too large (3 + 6 n_freq must be <= 128)")
+        # the kernels encode bands in groups of four: 64 inputs hold 8 bands, 128 hold 20
+        self.in_pad = 64 if n_freq <= 8 else 128
+        if not 0 <= n_freq <= 20:
+            raise ValueError("n_freq must lie in [0, 20]")
         dev = torch.device(device)
         rng = np.random.default_rng(seed)
         Wd = self.width

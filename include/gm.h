@@ -235,6 +235,23 @@ gm_status gm_loss_smooth_l1(int32_t n_stacks, const float* const* preds,
                             float* const* dl_di, float* loss, void* workspace,
                             gm_stream stream);
 
+/* SSIM term of the reconstruction loss (Sec. 3.5.2, Eq. 10: L_recon = L_L1 + lambda_SSIM L_SSIM;
+ * lambda_SSIM = 0.5 in Sec. 4.1.4).  The paper names the term without window or constants; read
+ * as textbook SSIM on whole slices: every z-slice of stack k is a 2D image of nx x ny pixels,
+ * 11 x 11 Gaussian window (sigma 1.5, normalised), zero padding outside the slice,
+ * C1 = 0.01^2, C2 = 0.03^2 (intensities in [0, 1]).
+ *   *loss (device float) = L_SSIM = 1 - mean of the SSIM map over every voxel of the listed
+ *                          stacks (0 when they hold no voxel);
+ *   dl_di[k][v] += lambda * dL_SSIM / d pred_k[v]  (accumulated, so that it adds onto the
+ *                          smooth-L1 gradient written by gm_loss_smooth_l1).
+ * preds/targets/dl_di: [host] arrays of device pointers to [nz][ny][nx] float32 stacks;
+ * dims: [host] n_stacks x (nx, ny, nz), each >= 0.  Statistics and derivatives in FP64.
+ * workspace: GM_REDUCE_WORKSPACE_BYTES device bytes.  Bit-reproducible run to run.  A stack
+ * must not alias another's dl_di. */
+gm_status gm_loss_ssim(int32_t n_stacks, const float* const* preds, const float* const* targets,
+                       const int32_t* dims, float lambda, float* const* dl_di, float* loss,
+                       void* workspace, gm_stream stream);
+
 /* Anisotropy regulariser (Eq. 13, reading the ratio as exp(max s - min s), the ratio of the
  * actual scales): *value (device float) = mean_i max(0, exp(max s_i - min s_i) - lambda_r). */
 gm_status gm_aniso_reg(const gm_gaussians* g, float lambda_r, float* value, void* workspace,

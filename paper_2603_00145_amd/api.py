@@ -256,6 +256,25 @@ def smooth_l1(preds: Sequence[torch.Tensor], targets: Sequence[torch.Tensor],
     return loss[0], dl_di
 
 
+def ssim_loss(preds: Sequence[torch.Tensor], targets: Sequence[torch.Tensor],
+              dl_di: Sequence[torch.Tensor], lam: float = 0.5):
+    """gm_loss_ssim: L_SSIM = 1 - mean SSIM over every slice of every [nz, ny, nx] stack
+    (device scalar); dl_di[k] += lam * dL_SSIM/dpred_k."""
+    for t in list(preds) + list(targets) + list(dl_di):
+        _need(t, torch.float32, "loss operand")
+    for p, t, d in zip(preds, targets, dl_di):
+        if p.dim() != 3 or t.shape != p.shape or d.shape != p.shape:
+            raise ValueError("SSIM operands must be [nz, ny, nx] stacks of equal shape")
+    loss = torch.empty(4, dtype=torch.float32, device=preds[0].device)
+    dims = (ctypes.c_int32 * (3 * len(preds)))(
+        *[v for p in preds for v in (p.shape[2], p.shape[1], p.shape[0])])
+    check(load().gm_loss_ssim(len(preds), ptr_array([p.data_ptr() for p in preds]),
+                              ptr_array([t.data_ptr() for t in targets]), dims, float(lam),
+                              ptr_array([d.data_ptr() for d in dl_di]), _p(loss),
+                              _p(workspace()), _stream()))
+    return loss[0]
+
+
 def aniso(g: GaussParams, lambda_r: float = 1.5):
     val = torch.empty(4, dtype=torch.float32, device=g.mean.device)
     gs = g.struct()

@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgm.so")
 
 SOURCES = ["gm_api.hip", "preprocess.hip", "binning.hip", "render.hip", "backward.hip",
-           "optim.hip", "init.hip", "nrf.hip", "warm.hip"]
+           "optim.hip", "init.hip", "nrf.hip", "warm.hip", "ssim.hip"]
 NO_CONTRACT = {"preprocess.hip"}
 
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

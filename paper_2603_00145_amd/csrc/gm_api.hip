@@ -772,6 +772,55 @@ gm_status gm_loss_smooth_l1(int32_t n_stacks, const float* const* preds,
     return GM_OK;
 }
 
+gm_status gm_loss_ssim(int32_t n_stacks, const float* const* preds, const float* const* targets,
+                       const int32_t* dims, float lambda, float* const* dl_di, float* loss,
+                       void* workspace, gm_stream stream)
+{
+    g_err.clear();
+    if (n_stacks < 1 || n_stacks > GM_MAX_GRIDS)
+        return fail(GM_ERR_INVALID_ARGUMENT, "n_stacks outside [1, %d]", GM_MAX_GRIDS);
+    if (!preds || !targets || !dims || !dl_di)
+        return fail(GM_ERR_INVALID_ARGUMENT, "NULL array argument");
+    REQ_PTR(loss, "loss");
+    REQ_PTR(workspace, "workspace");
+    if (!isfinite(lambda)) return fail(GM_ERR_INVALID_ARGUMENT, "lambda not finite");
+    SsimArgs sa;
+    memset(&sa, 0, sizeof sa);
+    sa.n_stacks = n_stacks;
+    int64_t tiles = 0, vox = 0;
+    for (int k = 0; k < n_stacks; ++k) {
+        const int32_t nx = dims[3 * k], ny = dims[3 * k + 1], nz = dims[3 * k + 2];
+        if (nx < 0 || ny < 0 || nz < 0) return fail(GM_ERR_INVALID_ARGUMENT, "negative dims");
+        const int64_t n = (int64_t)nx * ny * nz;
+        if (n > 0) {
+            REQ_PTR(preds[k], "preds[k]");
+            REQ_PTR(targets[k], "targets[k]");
+            REQ_PTR(dl_di[k], "dl_di[k]");
+        }
+        sa.nx[k] = nx;
+        sa.ny[k] = ny;
+        ssim_tiles(nx, ny, &sa.tiles_x[k], &sa.tiles_y[k]);
+        sa.tile_begin[k] = tiles;
+        if (n > 0) tiles += (int64_t)nz * sa.tiles_x[k] * sa.tiles_y[k];
+        sa.pred[k] = preds[k];
+        sa.target[k] = targets[k];
+        sa.dl[k] = dl_di[k];
+        vox += n;
+    }
+    sa.tile_begin[n_stacks] = tiles;
+    // 1D Gaussian taps, sigma 1.5, normalised
+    double gs = 0.0;
+    for (int i = 0; i < 11; ++i) {
+        const double d = (double)(i - 5);
+        sa.g[i] = exp(-d * d / (2.0 * 1.5 * 1.5));
+        gs += sa.g[i];
+    }
+    for (int i = 0; i < 11; ++i) sa.g[i] /= gs;
+    sa.grad_scale = vox > 0 ? -(double)lambda / (double)vox : 0.0;
+    GM_HIP(launch_ssim(sa, vox, loss, workspace, reinterpret_cast<hipStream_t>(stream)), "SSIM");
+    return GM_OK;
+}
+
 gm_status gm_aniso_reg(const gm_gaussians* g, float lambda_r, float* value, void* workspace,
                        gm_stream stream)
 {

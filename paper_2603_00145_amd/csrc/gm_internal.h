@@ -149,6 +149,22 @@ struct LossArgs {
     float* dl[GM_MAX_GRIDS];
 };
 hipError_t launch_smooth_l1(const LossArgs& a, float* loss, void* ws, hipStream_t s);
+
+// SSIM term on whole stack slices (Eq. 10): every z-slice is a 2D image; 16 x 32 pixel tiles
+constexpr double GM_SSIM_C1 = 0.01 * 0.01, GM_SSIM_C2 = 0.03 * 0.03;
+struct SsimArgs {
+    int32_t n_stacks;
+    int32_t nx[GM_MAX_GRIDS], ny[GM_MAX_GRIDS];
+    int32_t tiles_x[GM_MAX_GRIDS], tiles_y[GM_MAX_GRIDS];
+    int64_t tile_begin[GM_MAX_GRIDS + 1];   // prefix of nz * tiles_y * tiles_x
+    const float* pred[GM_MAX_GRIDS];
+    const float* target[GM_MAX_GRIDS];
+    float* dl[GM_MAX_GRIDS];
+    double g[11];                           // 1D window taps, sum 1
+    double grad_scale;                      // -lambda / N
+};
+void ssim_tiles(int nx, int ny, int* tiles_x, int* tiles_y);
+hipError_t launch_ssim(const SsimArgs& a, int64_t n_voxels, float* loss, void* ws, hipStream_t s);
 hipError_t launch_aniso(const float* log_scale, int64_t n, float lambda_r, float* value,
                         void* ws, hipStream_t s);
 hipError_t launch_mse(const float* a, const float* b, int64_t n, float* mse, void* ws,

@@ -357,3 +357,23 @@ def workload(name: str, with_data: bool = True, seed: Optional[int] = None,
 def random_dl_di(grids: Sequence[Grid], rng: np.random.Generator, scale: float = 1.0):
     """Seeded per-voxel upstream gradients dL/dI for each grid (float32)."""
     return [(rng.normal(size=g.shape) * scale).astype(np.float32) for g in grids]
+
+
+def slice_pair(shape, rng: np.random.Generator):
+    """Seeded (prediction, target) float32 stacks [nz, ny, nx] for the SSIM term.  Each target
+    slice holds 6 random ellipses, piecewise constant with values U(0.2, 1) over a zero
+    background, plus noise N(0, 0.01^2); the prediction is the target averaged over 3 x 3
+    in-plane neighbours (edge-replicated), scaled by 0.95, plus noise N(0, 0.005^2)."""
+    nz, ny, nx = shape
+    yy, xx = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    tgt = np.zeros(shape)
+    for z in range(nz):
+        for _ in range(6):
+            cy, cx = rng.uniform(0, ny), rng.uniform(0, nx)
+            ry, rx = rng.uniform(0.1, 0.5) * ny + 1, rng.uniform(0.1, 0.5) * nx + 1
+            tgt[z][((yy - cy) / ry) ** 2 + ((xx - cx) / rx) ** 2 <= 1.0] = rng.uniform(0.2, 1.0)
+    tgt += rng.normal(0.0, 0.01, size=shape)
+    pad = np.pad(tgt, ((0, 0), (1, 1), (1, 1)), mode="edge")
+    avg = sum(pad[:, i:i + ny, j:j + nx] for i in range(3) for j in range(3)) / 9.0
+    pred = 0.95 * avg + rng.normal(0.0, 0.005, size=shape)
+    return pred.astype(np.float32), tgt.astype(np.float32)

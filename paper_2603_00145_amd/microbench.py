@@ -1,5 +1,6 @@
-"""Throughput of the MFMA parts of the path (neural residual field, warm-start network) on
-their own, timed with HIP events on the launch stream, against the dense BF16 MFMA peak.
+"""Throughput of the parts of the path outside the benchmark's iteration (neural residual field
+and warm-start network against the dense BF16 MFMA peak; the SSIM loss term against the FP64
+vector peak), each on its own, timed with HIP events on the launch stream.
 
     python -m paper_2603_00145_amd.microbench [--reps 10]
 
@@ -8,6 +9,7 @@ the layers as the kernels run them (inputs zero-padded to a multiple of 16 featu
     NRF forward, per point:   2 (in_pad*64 + (D-1)*64*64 + 64)
     NRF backward, per point:  forward recompute + dA (2 per weight of the hidden and input
                               layers but the first) + dW (2 per weight)
+    SSIM value + gradient, per pixel: SSIM_FLOP_PER_PIXEL (FP64, against the FP64 peak)
     warm-start forward, per Gaussian: 2 * sum_l (c_out * K_pad,l * positions_out,l) + head
     warm-start training step: forward + backward-data (all but the first layer) + backward-
                               weights, i.e. about 3x forward.
@@ -18,11 +20,17 @@ import argparse
 import json
 import sys
 
+import numpy as np
 import torch
 
 from . import api, inputs, nrf, warmstart
 
 BF16_PEAK = 2.5e15          # dense MFMA FLOP/s of MI355X in BF16
+FP64_PEAK = 78.6e12         # FP64 vector FLOP/s of MI355X (an FMA counts 2)
+# SSIM value + gradient per pixel, separable 11-tap window: five window sums (2 x 11 FMA each)
+# and three products, ~35 FLOP for the statistics and partials (plus two divisions), three
+# adjoint window sums (2 x 11 FMA each) and 5 FLOP to assemble the gradient
+SSIM_FLOP_PER_PIXEL = 2 * 5 * 22 + 3 + 35 + 2 * 3 * 22 + 5
 
 
 def _time(fn, reps):
@@ -87,6 +95,19 @@ def main():
     out.append({"what": "nrf_backward", "points": pts, "seconds": t, "points_per_s": pts / t,
                 "tflops": f / t / 1e12, "mfma_frac": f / t / BF16_PEAK,
                 "config": "2^18 sampled voxels on each of three 256x256x64 stacks"})
+
+    # SSIM term (value + gradient) on three 256x256x64 stacks
+    rng = np.random.default_rng(0)
+    pairs = [inputs.slice_pair((64, 256, 256), rng) for _ in range(3)]
+    sp = [torch.from_numpy(p).to(dev) for p, _ in pairs]
+    st = [torch.from_numpy(q).to(dev) for _, q in pairs]
+    sd = [torch.zeros_like(p) for p in sp]
+    t = _time(lambda: api.ssim_loss(sp, st, sd, 0.5), args.reps)
+    pix = sum(p.numel() for p in sp)
+    f = SSIM_FLOP_PER_PIXEL * pix
+    out.append({"what": "ssim_loss", "pixels": pix, "seconds": t, "pixels_per_s": pix / t,
+                "tflops_fp64": f / t / 1e12, "fp64_frac": f / t / FP64_PEAK,
+                "config": "three 256x256x64 stacks, 11x11 window, value + gradient, FP64"})
 
     # warm-start network: inference on 256k Gaussians, one training step of batch 1024
     ws = warmstart.WarmStartNet(seed=0, zero_head=False)

@@ -1,7 +1,8 @@
 """Reconstruction driver: the paper's training loop (Sec. 3.5; settings of Sec. 4.1.4) run on
 the HIP path.  Each iteration bins the Gaussians onto the stacks, renders them, forms the
-smooth-L1 data term and its per-voxel gradient, backpropagates to every Gaussian parameter
-(with the anisotropy regulariser), and takes one Adam step per parameter group.  Optionally a
+smooth-L1 data term and its per-voxel gradient (plus, with lambda_ssim > 0, the SSIM term of
+Eq. 10 on whole slices), backpropagates to every Gaussian parameter (with the anisotropy
+regulariser), and takes one Adam step per parameter group.  Optionally a
 neural residual field (Sec. 3.4) is switched on part-way through (delayed activation).
 """
 from __future__ import annotations
@@ -24,6 +25,7 @@ class TrainConfig:
     lr_logit: float = 5e-2       # intensity
     lambda_aniso: float = 0.1
     lambda_r: float = 1.5
+    lambda_ssim: float = 0.0     # 0.5 is the paper's full loss; 0 the plain smooth-L1 method
     psnr_every: int = 10
     nrf: Optional[object] = None  # an nrf.NRF to train jointly (None = Gaussians only)
     nrf_start: float = 0.5        # fraction of n_iter after which the NRF is active
@@ -71,6 +73,9 @@ class Reconstruction:
             for k, s in enumerate(self.stacks):
                 c.nrf.forward_add(s, self.outs[k])
         loss, _ = api.smooth_l1(self.outs, self.targets, self.dls)
+        if c.lambda_ssim > 0:
+            loss = loss + c.lambda_ssim * api.ssim_loss(self.outs, self.targets, self.dls,
+                                                        c.lambda_ssim)
         for t in self.g.tensors():
             t.zero_()
         api.backward(self.p, self.bins, self.ids, self.dls, self.g, c.lambda_aniso, c.lambda_r)

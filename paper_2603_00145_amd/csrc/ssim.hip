@@ -1,5 +1,5 @@
 // SSIM term of the reconstruction loss (Sec. 3.5.2, Eq. 10) on whole stack slices, with its
-// gradient, fused in one kernel over 16 x 32 pixel tiles of the slices.
+// gradient, fused in one kernel over 32 x 32 pixel tiles of the slices.
 //
 // Every z-slice of a stack is a 2D image.  The SSIM map uses an 11 x 11 Gaussian window (the
 // outer product of 11 taps g, sigma 1.5), zero padding outside the slice, C1 = 0.01^2 and
@@ -27,17 +27,17 @@
 namespace {
 
 constexpr int R = 5, WN = 2 * R + 1;
-constexpr int TY = 16, TX = 32;
-constexpr int IR = TY + 4 * R, IC = TX + 4 * R;   // staged input region 36 x 52
-constexpr int VR = TY + 2 * R;                    // rows after the vertical pass: 26
+constexpr int TY = 32, TX = 32;
+constexpr int IR = TY + 4 * R, IC = TX + 4 * R;   // staged input region 52 x 52
+constexpr int VR = TY + 2 * R;                    // rows after the vertical pass: 42
 constexpr int MC = TX + 2 * R;                    // map columns: 42
-constexpr int NT = 512;
+constexpr int NT = 1024;
 constexpr int SSIM_BLOCKS = 1024;                 // block partials fit the reduction workspace
 
 // stage 2: (column, run of V_SEG rows); stage 3: (row, run of H_SEG columns)
-constexpr int V_SEG = 3, V_RUNS = (VR + V_SEG - 1) / V_SEG;     // 9 runs x 52 columns
-constexpr int H_SEG = 3, H_RUNS = MC / H_SEG;                   // 14 runs x 26 rows
-constexpr int A_SEG = 4, A_RUNS = TY / A_SEG;                   // 4 runs x 42 columns x 3 maps
+constexpr int V_SEG = 3, V_RUNS = (VR + V_SEG - 1) / V_SEG;     // 14 runs x 52 columns
+constexpr int H_SEG = 3, H_RUNS = MC / H_SEG;                   // 14 runs x 42 rows
+constexpr int A_SEG = 4, A_RUNS = TY / A_SEG;                   // 8 runs x 42 columns x 3 maps
 static_assert(V_RUNS * IC <= NT, "stage 2 runs exceed the block");
 static_assert(MC % H_SEG == 0, "stage 3 runs must tile the map row");
 static_assert(VR * H_RUNS <= NT, "stage 3 runs exceed the block");
@@ -56,6 +56,15 @@ struct Lds {
     double red[NT / 64];
 };
 
+// 1/d from the hardware reciprocal refined by two Newton steps (error ~1 ulp); here
+// d = b1 b2 lies in [C1 C2, 4.1]
+__device__ __forceinline__ double recip(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return fma(r, fma(-d, r, 1.0), r);
+}
+
 __device__ double block_sum(double v, double* red)
 {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -68,36 +77,80 @@ __device__ double block_sum(double v, double* red)
     return s;
 }
 
-// four waves per SIMD: two 512-thread blocks per CU (128 VGPRs, 68 KB of LDS each)
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_ssim(const SsimArgs a, double* part)
+struct TileGeom {
+    int k, nx, ny, y0, x0;
+    int64_t slice;     // offset of the tile's slice in its stack
+};
+
+__device__ TileGeom tile_geom(const SsimArgs& a, int64_t t)
+{
+    TileGeom g;
+    int k = 0;
+    while (t >= a.tile_begin[k + 1]) ++k;
+    g.k = k;
+    g.nx = a.nx[k];
+    g.ny = a.ny[k];
+    const int64_t local = t - a.tile_begin[k];
+    const int64_t per_slice = (int64_t)a.tiles_x[k] * a.tiles_y[k];
+    const int z = (int)(local / per_slice);
+    const int rem = (int)(local - (int64_t)z * per_slice);
+    g.y0 = (rem / a.tiles_x[k]) * TY;
+    g.x0 = (rem % a.tiles_x[k]) * TX;
+    g.slice = (int64_t)z * g.ny * g.nx;
+    return g;
+}
+
+constexpr int LOAD_ITERS = (IR * IC + NT - 1) / NT;   // input elements per thread
+
+// the thread's share of a tile's input region (zero outside the slice), into registers
+__device__ __forceinline__ void load_region(const SsimArgs& a, const TileGeom& g, int tid,
+                                            float (&vx)[LOAD_ITERS], float (&vy)[LOAD_ITERS])
+{
+    const float* px = a.pred[g.k] + g.slice;
+    const float* py = a.target[g.k] + g.slice;
+#pragma unroll
+    for (int i = 0; i < LOAD_ITERS; ++i) {
+        const int e = tid + i * NT;
+        const int r = e / IC, c = e - r * IC;
+        const int Y = g.y0 - 2 * R + r, X = g.x0 - 2 * R + c;
+        const bool in = e < IR * IC && Y >= 0 && Y < g.ny && X >= 0 && X < g.nx;
+        const int64_t o = (int64_t)Y * g.nx + X;
+        vx[i] = in ? px[o] : 0.0f;
+        vy[i] = in ? py[o] : 0.0f;
+    }
+}
+
+// one 1024-thread block per CU (107 KB of LDS): four waves per SIMD
+__global__ __launch_bounds__(NT) void k_ssim(const SsimArgs a, double* part)
 {
     __shared__ Lds s;
-    const int tid = threadIdx.x;
     const int64_t total = a.tile_begin[a.n_stacks];
     double ssum = 0.0;
+    // the next tile's input region is fetched into registers while the current one is
+    // processed, so its latency is hidden behind the window passes
+    float nxv[LOAD_ITERS], nyv[LOAD_ITERS];
+    if ((int64_t)blockIdx.x < total) load_region(a, tile_geom(a, blockIdx.x), threadIdx.x, nxv, nyv);
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int k = 0;
-        while (t >= a.tile_begin[k + 1]) ++k;
-        const int nx = a.nx[k], ny = a.ny[k];
-        const int64_t local = t - a.tile_begin[k];
-        const int64_t per_slice = (int64_t)a.tiles_x[k] * a.tiles_y[k];
-        const int z = (int)(local / per_slice);
-        const int rem = (int)(local - (int64_t)z * per_slice);
-        const int y0 = (rem / a.tiles_x[k]) * TY, x0 = (rem % a.tiles_x[k]) * TX;
-        const int64_t slice = (int64_t)z * ny * nx;
-        const float* px = a.pred[k] + slice;
-        const float* py = a.target[k] + slice;
+        // the thread's roles are recomputed per tile: kept out of the loop they would hold
+        // dozens of registers for the whole kernel
+        int tid = threadIdx.x;
+        __asm__ __volatile__("" : "+v"(tid));
+        const TileGeom geo = tile_geom(a, t);
+        const int k = geo.k, nx = geo.nx, ny = geo.ny, y0 = geo.y0, x0 = geo.x0;
+        const int64_t slice = geo.slice;
 
-        // 1. input region, zero outside the slice
-        for (int e = tid; e < IR * IC; e += NT) {
-            const int r = e / IC, c = e - r * IC;
-            const int Y = y0 - 2 * R + r, X = x0 - 2 * R + c;
-            const bool in = Y >= 0 && Y < ny && X >= 0 && X < nx;
-            const int64_t o = (int64_t)Y * nx + X;
-            s.x[r][c] = in ? px[o] : 0.0f;
-            s.y[r][c] = in ? py[o] : 0.0f;
+        // 1. input region (prefetched), then the fetch of the next tile's
+#pragma unroll
+        for (int i = 0; i < LOAD_ITERS; ++i) {
+            const int e = tid + i * NT;
+            if (e < IR * IC) {
+                const int r = e / IC, c = e - r * IC;
+                s.x[r][c] = nxv[i];
+                s.y[r][c] = nyv[i];
+            }
         }
         __syncthreads();
+        if (t + gridDim.x < total) load_region(a, tile_geom(a, t + gridDim.x), tid, nxv, nyv);
 
         // 2. vertical pass: V[q][r][c] = sum_i g_i f_q(in[r + i][c])
         if (tid < V_RUNS * IC) {
@@ -164,14 +217,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 const double cxy = m[j][4] - mx * my;
                 const double a1 = 2.0 * mx * my + GM_SSIM_C1, a2 = 2.0 * cxy + GM_SSIM_C2;
                 const double b1 = mx * mx + my * my + GM_SSIM_C1, b2 = vx + vy + GM_SSIM_C2;
-                const double r1 = 1.0 / b1, r2 = 1.0 / b2;
-                const double sv = a1 * a2 * r1 * r2;
+                const double rb = recip(b1 * b2), r1 = b2 * rb, r2 = b1 * rb;   // 1/b1, 1/b2
+                const double sv = a1 * a2 * rb;
                 const bool in = Y >= 0 && Y < ny && X >= 0 && X < nx;
                 const bool own = in && hr >= R && hr < R + TY && c >= R && c < R + TX;
                 if (own) ssum += sv;
-                pd[j][0] = in ? 2.0 * my * (a2 - a1) * r1 * r2 + 2.0 * mx * sv * (r2 - r1) : 0.0;
+                pd[j][0] = in ? 2.0 * my * (a2 - a1) * rb + 2.0 * mx * sv * (r2 - r1) : 0.0;
                 pd[j][1] = in ? -sv * r2 : 0.0;
-                pd[j][2] = in ? 2.0 * a1 * r1 * r2 : 0.0;
+                pd[j][2] = in ? 2.0 * a1 * rb : 0.0;
             }
         }
         __syncthreads();   // the partials overwrite the vertical sums

@@ -64,72 +64,78 @@ def warm_flops_forward():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--only", choices=["nrf", "ssim", "warm"], default=None,
+                    help="run one group of measurements")
     args = ap.parse_args()
+    run = (lambda grp: args.only is None or args.only == grp)
     api.load()
     dev = torch.device("cuda", 0)
     out = []
 
-    # NRF forward on the 256^3 volume and backward on 2^18 samples of each of three stacks
-    w = inputs.workload("c256", with_data=False)
-    net = nrf.NRF(n_freq=16, depth=3, seed=1, zero_last=False)
-    vol = torch.zeros(w.volume.shape, dtype=torch.float32, device=dev)
-    t = _time(lambda: net.forward_add(w.volume, vol), args.reps)
-    pts = w.volume.n_voxels
-    f = nrf_flops(net) * pts
-    out.append({"what": "nrf_forward", "points": pts, "seconds": t, "points_per_s": pts / t,
-                "tflops": f / t / 1e12, "mfma_frac": f / t / BF16_PEAK,
-                "config": "L=16, in_pad 128, 3 x 64 SiLU, 256^3 voxel centres"})
     g = torch.Generator(device=dev)
     g.manual_seed(0)
-    dl = torch.randn(w.stacks[0].shape, device=dev, generator=g)
-    idx = torch.randint(0, w.stacks[0].n_voxels, (1 << 18,), device=dev, dtype=torch.int32,
-                        generator=g)
+    if run("nrf"):
+        # NRF forward on the 256^3 volume and backward on 2^18 samples of each of three stacks
+        w = inputs.workload("c256", with_data=False)
+        net = nrf.NRF(n_freq=16, depth=3, seed=1, zero_last=False)
+        vol = torch.zeros(w.volume.shape, dtype=torch.float32, device=dev)
+        t = _time(lambda: net.forward_add(w.volume, vol), args.reps)
+        pts = w.volume.n_voxels
+        f = nrf_flops(net) * pts
+        out.append({"what": "nrf_forward", "points": pts, "seconds": t, "points_per_s": pts / t,
+                    "tflops": f / t / 1e12, "mfma_frac": f / t / BF16_PEAK,
+                    "config": "L=16, in_pad 128, 3 x 64 SiLU, 256^3 voxel centres"})
+        dl = torch.randn(w.stacks[0].shape, device=dev, generator=g)
+        idx = torch.randint(0, w.stacks[0].n_voxels, (1 << 18,), device=dev, dtype=torch.int32,
+                            generator=g)
 
-    def nrf_bwd():
-        net.zero_grad()
-        for s in w.stacks:
-            net.backward(s, dl, idx=idx)
-    t = _time(nrf_bwd, args.reps)
-    pts = 3 * (1 << 18)
-    f = nrf_flops(net, backward=True) * pts
-    out.append({"what": "nrf_backward", "points": pts, "seconds": t, "points_per_s": pts / t,
-                "tflops": f / t / 1e12, "mfma_frac": f / t / BF16_PEAK,
-                "config": "2^18 sampled voxels on each of three 256x256x64 stacks"})
+        def nrf_bwd():
+            net.zero_grad()
+            for s in w.stacks:
+                net.backward(s, dl, idx=idx)
+        t = _time(nrf_bwd, args.reps)
+        pts = 3 * (1 << 18)
+        f = nrf_flops(net, backward=True) * pts
+        out.append({"what": "nrf_backward", "points": pts, "seconds": t, "points_per_s": pts / t,
+                    "tflops": f / t / 1e12, "mfma_frac": f / t / BF16_PEAK,
+                    "config": "2^18 sampled voxels on each of three 256x256x64 stacks"})
 
-    # SSIM term (value + gradient) on three 256x256x64 stacks
-    rng = np.random.default_rng(0)
-    pairs = [inputs.slice_pair((64, 256, 256), rng) for _ in range(3)]
-    sp = [torch.from_numpy(p).to(dev) for p, _ in pairs]
-    st = [torch.from_numpy(q).to(dev) for _, q in pairs]
-    sd = [torch.zeros_like(p) for p in sp]
-    t = _time(lambda: api.ssim_loss(sp, st, sd, 0.5), args.reps)
-    pix = sum(p.numel() for p in sp)
-    f = SSIM_FLOP_PER_PIXEL * pix
-    out.append({"what": "ssim_loss", "pixels": pix, "seconds": t, "pixels_per_s": pix / t,
-                "tflops_fp64": f / t / 1e12, "fp64_frac": f / t / FP64_PEAK,
-                "config": "three 256x256x64 stacks, 11x11 window, value + gradient, FP64"})
+    if run("ssim"):
+        # SSIM term (value + gradient) on three 256x256x64 stacks
+        rng = np.random.default_rng(0)
+        pairs = [inputs.slice_pair((64, 256, 256), rng) for _ in range(3)]
+        sp = [torch.from_numpy(p).to(dev) for p, _ in pairs]
+        st = [torch.from_numpy(q).to(dev) for _, q in pairs]
+        sd = [torch.zeros_like(p) for p in sp]
+        t = _time(lambda: api.ssim_loss(sp, st, sd, 0.5), args.reps)
+        pix = sum(p.numel() for p in sp)
+        f = SSIM_FLOP_PER_PIXEL * pix
+        out.append({"what": "ssim_loss", "pixels": pix, "seconds": t, "pixels_per_s": pix / t,
+                    "tflops_fp64": f / t / 1e12, "fp64_frac": f / t / FP64_PEAK,
+                    "config": "three 256x256x64 stacks, 11x11 window, value + gradient, FP64"})
 
-    # warm-start network: inference on 256k Gaussians, one training step of batch 1024
-    ws = warmstart.WarmStartNet(seed=0, zero_head=False)
-    n = 1 << 18
-    patches = torch.rand((n, 3, 512), device=dev, generator=g)
-    patches = patches.to(torch.bfloat16).view(torch.int16).contiguous()
-    s0 = torch.full((n, 3), -4.0, device=dev)
-    l0 = torch.zeros(n, device=dev)
-    t = _time(lambda: ws.forward(patches, s0, l0), args.reps)
-    f = warm_flops_forward() * n
-    out.append({"what": "warmstart_forward", "gaussians": n, "seconds": t, "gaussians_per_s": n / t,
-                "tflops": f / t / 1e12, "mfma_frac": f / t / BF16_PEAK,
-                "config": "3 x 8^3 BF16 patches, four 3D convs of width 32 + head"})
-    b = 1024
-    sig = warmstart.sym6(s0[:b] + 0.1, torch.tensor([[1.0, 0.1, 0.0, 0.0]], device=dev).repeat(b, 1))
-    lt = torch.zeros(b, device=dev)
-    t = _time(lambda: ws.backward(patches[:b].contiguous(), s0[:b].contiguous(), l0[:b].contiguous(),
-                                  sig, lt), args.reps)
-    f = 3 * warm_flops_forward() * b
-    out.append({"what": "warmstart_train_step", "gaussians": b, "seconds": t,
-                "gaussians_per_s": b / t, "tflops": f / t / 1e12, "mfma_frac": f / t / BF16_PEAK,
-                "config": "batch 1024: forward, loss head, backward-data and backward-weights"})
+    if run("warm"):
+        # warm-start network: inference on 256k Gaussians, one training step of batch 1024
+        ws = warmstart.WarmStartNet(seed=0, zero_head=False)
+        n = 1 << 18
+        patches = torch.rand((n, 3, 512), device=dev, generator=g)
+        patches = patches.to(torch.bfloat16).view(torch.int16).contiguous()
+        s0 = torch.full((n, 3), -4.0, device=dev)
+        l0 = torch.zeros(n, device=dev)
+        t = _time(lambda: ws.forward(patches, s0, l0), args.reps)
+        f = warm_flops_forward() * n
+        out.append({"what": "warmstart_forward", "gaussians": n, "seconds": t, "gaussians_per_s": n / t,
+                    "tflops": f / t / 1e12, "mfma_frac": f / t / BF16_PEAK,
+                    "config": "3 x 8^3 BF16 patches, four 3D convs of width 32 + head"})
+        b = 1024
+        sig = warmstart.sym6(s0[:b] + 0.1, torch.tensor([[1.0, 0.1, 0.0, 0.0]], device=dev).repeat(b, 1))
+        lt = torch.zeros(b, device=dev)
+        t = _time(lambda: ws.backward(patches[:b].contiguous(), s0[:b].contiguous(), l0[:b].contiguous(),
+                                      sig, lt), args.reps)
+        f = 3 * warm_flops_forward() * b
+        out.append({"what": "warmstart_train_step", "gaussians": b, "seconds": t,
+                    "gaussians_per_s": b / t, "tflops": f / t / 1e12, "mfma_frac": f / t / BF16_PEAK,
+                    "config": "batch 1024: forward, loss head, backward-data and backward-weights"})
     for o in out:
         print(json.dumps(o))
         sys.stdout.flush()

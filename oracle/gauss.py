@@ -111,7 +111,8 @@ def grid_terms(mean, quat, log_scale, logit, grid, wt=None):
     Sigma_g^-1 and amplitude amp (slice-profile convolution in closed form)."""
     if wt is None:
         wt = world_terms(mean, quat, log_scale, logit)
-    A = np.asarray(grid.world_to_index, np.float64)
+    A = np.asarray(grid.world_to_index)
+    A = A if np.iscomplexobj(A) else A.astype(np.float64)   # complex for complex-step checks
     L, t = A[:, :3], A[:, 3]
     c = mean @ L.T + t
     Sig_idx = np.einsum("ij,njk,lk->nil", L, wt["Sigma"], L)
@@ -198,6 +199,33 @@ def grid_partials(grid, gt, lo, hi, nonempty, dl_di):
     return d_amp, d_c, G_C
 
 
+def sigma_idx_grad(gt, d_amp, G_C):
+    """dL/dSigma_idx per Gaussian from the grid-frame partials: the conic C = Sigma_g^-1 gives
+    dL/dSigma_g = -C G_C C, and amp = alpha sqrt(det Sigma_idx / det Sigma_g) adds
+    -1/2 d_amp amp C (through Sigma_g) and +1/2 d_amp amp Sigma_idx^-1; Sigma_g = Sigma_idx
+    + sig^2 e_z e_z^T, so dSigma_g = dSigma_idx."""
+    C = gt["C"]
+    ha = 0.5 * (d_amp * gt["amp"])[:, None, None]
+    G_g = -np.einsum("nij,njk,nkl->nil", C, G_C, C) - ha * C
+    return G_g + ha * np.linalg.inv(gt["Sig_idx"])
+
+
+def pose_grad(mean, quat, log_scale, logit, grid, partial):
+    """Gradient of the objective behind one grid's partials (d_amp, d_c, G_C) with respect to
+    the grid's world->index affine A = [L | t] (row-major 3x4), boxes held fixed: the
+    quantity a joint optimisation of the stacks' rigid transforms T_k (Sec. 3.3.2) chains
+    through.  c = L mu + t gives dL/dL = sum_i d_c,i mu_i^T and dL/dt = sum_i d_c,i;
+    Sigma_idx = L Sigma L^T gives dL/dL += sum_i 2 G_idx,i L Sigma_i (G_idx symmetric)."""
+    d_amp, d_c, G_C = partial
+    wt = world_terms(mean, quat, log_scale, logit)
+    gt = grid_terms(mean, quat, log_scale, logit, grid, wt)
+    G_idx = sigma_idx_grad(gt, d_amp, G_C)
+    G_L = np.einsum("ni,nj->ij", d_c, mean) + \
+        2 * np.einsum("nij,jk,nkl->il", G_idx, gt["L"], wt["Sigma"])
+    G_t = d_c.sum(0)
+    return np.concatenate([G_L, G_t[:, None]], axis=1)
+
+
 def chain(mean, quat, log_scale, logit, grids, partials):
     """Raw-parameter gradients from the grid-frame partials of every grid.
 
@@ -218,9 +246,7 @@ def chain(mean, quat, log_scale, logit, grids, partials):
         gt = grid_terms(mean, quat, log_scale, logit, grid, wt)
         L = gt["L"]
         d_mu += d_c @ L
-        C = gt["C"]
-        G_g = -np.einsum("nij,njk,nkl->nil", C, G_C, C) - 0.5 * (d_amp * gt["amp"])[:, None, None] * C
-        G_idx = G_g + 0.5 * (d_amp * gt["amp"])[:, None, None] * np.linalg.inv(gt["Sig_idx"])
+        G_idx = sigma_idx_grad(gt, d_amp, G_C)
         G_S += np.einsum("ji,njk,kl->nil", L, G_idx, L)
         d_alpha += d_amp * gt["amp"] / wt["alpha"]
     R, S2 = wt["R"], wt["S2"]

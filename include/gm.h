@@ -287,6 +287,23 @@ gm_status gm_chain(const gm_gaussians* g, const gm_bins* bins, const int32_t* gr
                    int32_t n_ids, float lambda_aniso, float lambda_r, gm_gaussian_grads* grad,
                    gm_stream stream);
 
+/* Workspace gm_grid_pose_grads needs: GM_POSE_WORKSPACE_BYTES(n_ids) device bytes. */
+#define GM_POSE_WORKSPACE_BYTES(n_ids) ((size_t)256 * (size_t)(n_ids) * 12 * sizeof(double))
+
+/* Gradient with respect to each listed grid's world->index affine A = [L | t] (row-major
+ * 3x4), boxes held fixed, of the objective whose per-voxel derivatives produced the grid-frame
+ * partials in bins->grid_grads (a gm_backward or gm_grid_partials call on the same bins and
+ * parameters): out[k][12] (device, binary64, overwritten) = dL/dA of grid grid_ids[k].
+ * This is what the joint optimisation of the stacks' rigid transforms T_k (Sec. 3.3.2)
+ * chains through: with A = A0 o T_k^-1, a rigid increment of T_k changes A linearly.
+ *   c = L mu + t          -> dL/dL += d_c mu^T,  dL/dt += d_c
+ *   Sigma_idx = L Sigma L^T -> dL/dL += 2 (dL/dSigma_idx) L Sigma
+ * summed over the Gaussians with non-empty boxes, in FP64 and a fixed order (reproducible).
+ * workspace: GM_POSE_WORKSPACE_BYTES(n_ids) device bytes. */
+gm_status gm_grid_pose_grads(const gm_gaussians* g, const gm_bins* bins, const int32_t* grid_ids,
+                             int32_t n_ids, double* out, void* workspace, size_t workspace_bytes,
+                             gm_stream stream);
+
 /* Adam (Sec. 4.1.4; PyTorch arrangement, no weight decay) on n float32 elements in place:
  * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
  * p -= (lr / (1 - b1^step)) m / (sqrt(v) / sqrt(1 - b2^step) + eps).  step >= 1.

@@ -159,6 +159,19 @@ class Bins:
         self.n_pairs = int(npairs.value)
         return self.n_pairs
 
+    def set_grids(self, grids: Sequence):
+        """Replace the grids' affines (and slice profiles) for the next bin(); the dimensions
+        must stay those the buffers were sized for."""
+        grids = list(grids)
+        if len(grids) != len(self.grids) or any(
+                (a.nx, a.ny, a.nz) != (b.nx, b.ny, b.nz) for a, b in zip(grids, self.grids)):
+            raise ValueError("set_grids keeps the number and dimensions of the grids")
+        self.grids = grids
+        self._cgrids = (_lib.GmGrid * len(grids))(*[_lib.grid_struct(g) for g in grids])
+        self.n_pairs = -1
+        if hasattr(self, "_s"):
+            self._s.n_pairs = -1
+
     @property
     def tile_base_host(self):
         """Global id of each grid's first tile (filled by gm_bin)."""
@@ -254,6 +267,19 @@ def smooth_l1(preds: Sequence[torch.Tensor], targets: Sequence[torch.Tensor],
                                    ptr_array([d.data_ptr() for d in dl_di]), _p(loss),
                                    _p(workspace()), _stream()))
     return loss[0], dl_di
+
+
+def pose_grads(g: GaussParams, bins: Bins, ids: Sequence[int]) -> torch.Tensor:
+    """gm_grid_pose_grads: dL/d(world->index affine) [len(ids), 3, 4] (float64, device) of the
+    objective whose partials the last backward / grid_partials call on these bins left."""
+    out = torch.empty((max(1, len(ids)), 12), dtype=torch.float64, device=bins.device)
+    nbytes = 256 * max(1, len(ids)) * 12 * 8
+    ws = torch.empty(nbytes // 8, dtype=torch.float64, device=bins.device)
+    idarr = (ctypes.c_int32 * max(1, len(ids)))(*ids)
+    gs = g.struct()
+    check(load().gm_grid_pose_grads(ctypes.byref(gs), ctypes.byref(bins.struct()), idarr,
+                                    len(ids), _p(out), _p(ws), nbytes, _stream()))
+    return out[:len(ids)].view(-1, 3, 4)
 
 
 def ssim_loss(preds: Sequence[torch.Tensor], targets: Sequence[torch.Tensor],

@@ -362,15 +362,57 @@ __device__ __forceinline__ double inv3(const double* A, double* Ai)
     return det;
 }
 
-__global__ __launch_bounds__(128) void k_chain(const ChainArgs a)
+// One Gaussian on one grid: from its grid-frame partials pg (d amp, d c, d K) and its world
+// covariance Sig, the derivative Gi = dL/dSigma_idx (C = Sigma_g^-1 gives dL/dSigma_g =
+// -C G_C C; amp = alpha sqrt(det Sigma_idx / det Sigma_g) adds -1/2 d_amp amp C and
+// +1/2 d_amp amp Sigma_idx^-1), the centre partial dc, and amp.
+__device__ __forceinline__ double sigma_idx_grad(const GridConst& G, const double* Sig,
+                                                 double alpha, const float* pg, double* dc,
+                                                 double* Gi)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
-    const double qw = a.quat[4 * i], qx = a.quat[4 * i + 1], qy = a.quat[4 * i + 2],
-                 qz = a.quat[4 * i + 3];
-    const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-    const double w = qw / qn, x = qx / qn, y = qy / qn, z = qz / qn;
-    double R[9];
+    const double damp = pg[0];
+    dc[0] = pg[1];
+    dc[1] = pg[2];
+    dc[2] = pg[3];
+    // full-matrix dL/dC from the base-2 conic partials: C-entry = K-entry * KAPPA
+    const double GC[9] = {GM_KAPPA * pg[4], GM_KAPPA * pg[7], GM_KAPPA * pg[8],
+                          GM_KAPPA * pg[7], GM_KAPPA * pg[5], GM_KAPPA * pg[9],
+                          GM_KAPPA * pg[8], GM_KAPPA * pg[9], GM_KAPPA * pg[6]};
+    const double* L = G.L;
+    double T[9], SI[9];
+    mm3(L, Sig, T);
+    const double Lt[9] = {L[0], L[3], L[6], L[1], L[4], L[7], L[2], L[5], L[8]};
+    mm3(T, Lt, SI);  // Sigma_idx
+    double SG[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) SG[t] = SI[t];
+    SG[8] += G.sig * G.sig;
+    double C[9], SIi[9];
+    const double detG = inv3(SG, C);
+    const double detI = inv3(SI, SIi);
+    const double amp = alpha * sqrt(detI / detG);
+    double CG[9], CGC[9];
+    mm3(C, GC, CG);
+    mm3(CG, C, CGC);
+    const double ha = 0.5 * damp * amp;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) Gi[t] = -CGC[t] - ha * C[t] + ha * SIi[t];
+    return amp;
+}
+
+// Normalised quaternion (w, x, y, z), its rotation R (Hamilton) and Sigma = R diag(S2) R^T.
+__device__ __forceinline__ void world_covariance(const float* quat, const float* log_scale,
+                                                 int64_t i, double* qh, double* qn, double* R,
+                                                 double* S2, double* Sig)
+{
+    const double qw = quat[4 * i], qx = quat[4 * i + 1], qy = quat[4 * i + 2],
+                 qz = quat[4 * i + 3];
+    *qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    const double w = qw / *qn, x = qx / *qn, y = qy / *qn, z = qz / *qn;
+    qh[0] = w;
+    qh[1] = x;
+    qh[2] = y;
+    qh[3] = z;
     R[0] = 1.0 - 2.0 * (y * y + z * z);
     R[1] = 2.0 * (x * y - w * z);
     R[2] = 2.0 * (x * z + w * y);
@@ -380,15 +422,24 @@ __global__ __launch_bounds__(128) void k_chain(const ChainArgs a)
     R[6] = 2.0 * (x * z - w * y);
     R[7] = 2.0 * (y * z + w * x);
     R[8] = 1.0 - 2.0 * (x * x + y * y);
-    const double ls[3] = {a.log_scale[3 * i], a.log_scale[3 * i + 1], a.log_scale[3 * i + 2]};
-    const double S2[3] = {exp(2.0 * ls[0]), exp(2.0 * ls[1]), exp(2.0 * ls[2])};
-    double Sig[9];  // R diag(S2) R^T
+#pragma unroll
+    for (int m = 0; m < 3; ++m) S2[m] = exp(2.0 * (double)log_scale[3 * i + m]);
 #pragma unroll
     for (int p = 0; p < 3; ++p)
 #pragma unroll
         for (int q = 0; q < 3; ++q)
             Sig[3 * p + q] = R[3 * p] * S2[0] * R[3 * q] + R[3 * p + 1] * S2[1] * R[3 * q + 1] +
                              R[3 * p + 2] * S2[2] * R[3 * q + 2];
+}
+
+__global__ __launch_bounds__(128) void k_chain(const ChainArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    double qh[4], qn, R[9], S2[3], Sig[9];
+    world_covariance(a.quat, a.log_scale, i, qh, &qn, R, S2, Sig);
+    const double w = qh[0], x = qh[1], y = qh[2], z = qh[3];
+    const double ls[3] = {a.log_scale[3 * i], a.log_scale[3 * i + 1], a.log_scale[3 * i + 2]};
     const double alpha = 1.0 / (1.0 + exp(-(double)a.logit[i]));
 
     double dmu[3] = {0, 0, 0}, GS[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, dalpha = 0.0;
@@ -398,43 +449,20 @@ __global__ __launch_bounds__(128) void k_chain(const ChainArgs a)
         const int gi = a.grid_index[k];
         const float* pg = a.grid_grads + ((size_t)gi * a.n + i) * 10;
         if (a.tile_count[(size_t)gi * a.n + i] == 0) continue;  // empty box
-        const double damp = pg[0];
-        const double dc[3] = {pg[1], pg[2], pg[3]};
-        // full-matrix dL/dC from the base-2 conic partials: C-entry = K-entry * KAPPA
-        const double GC[9] = {GM_KAPPA * pg[4], GM_KAPPA * pg[7], GM_KAPPA * pg[8],
-                              GM_KAPPA * pg[7], GM_KAPPA * pg[5], GM_KAPPA * pg[9],
-                              GM_KAPPA * pg[8], GM_KAPPA * pg[9], GM_KAPPA * pg[6]};
+        double dc[3], Gi[9];
+        const double amp = sigma_idx_grad(G, Sig, alpha, pg, dc, Gi);
         const double* L = G.L;
-        double T[9], SI[9];
-        mm3(L, Sig, T);
-        double Lt[9] = {L[0], L[3], L[6], L[1], L[4], L[7], L[2], L[5], L[8]};
-        mm3(T, Lt, SI);  // Sigma_idx
-        double SG[9];
-#pragma unroll
-        for (int t = 0; t < 9; ++t) SG[t] = SI[t];
-        SG[8] += G.sig * G.sig;
-        double C[9], SIi[9];
-        const double detG = inv3(SG, C);
-        const double detI = inv3(SI, SIi);
-        const double amp = alpha * sqrt(detI / detG);
         // mu
 #pragma unroll
         for (int m = 0; m < 3; ++m) dmu[m] += L[m] * dc[0] + L[3 + m] * dc[1] + L[6 + m] * dc[2];
-        // Sigma_g then Sigma_idx
-        double CG[9], CGC[9];
-        mm3(C, GC, CG);
-        mm3(CG, C, CGC);
-        const double ha = 0.5 * damp * amp;
-        double Gi[9];
-#pragma unroll
-        for (int t = 0; t < 9; ++t) Gi[t] = -CGC[t] - ha * C[t] + ha * SIi[t];
         // Sigma = L^T Gi L
+        const double Lt[9] = {L[0], L[3], L[6], L[1], L[4], L[7], L[2], L[5], L[8]};
         double U[9], V9[9];
         mm3(Lt, Gi, U);
         mm3(U, L, V9);
 #pragma unroll
         for (int t = 0; t < 9; ++t) GS[t] += V9[t];
-        dalpha += damp * amp / alpha;
+        dalpha += (double)pg[0] * amp / alpha;
     }
     // Sigma = R diag(S2) R^T
     double GR[9], RtGR[9], GRR[9];
@@ -456,7 +484,6 @@ __global__ __launch_bounds__(128) void k_chain(const ChainArgs a)
     dq[3] = 2.0 * (-2.0 * z * g[0] - w * g[1] + x * g[2] + w * g[3] - 2.0 * z * g[4] + y * g[5] +
                    x * g[6] + y * g[7]);
     const double dot = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
-    const double qh[4] = {w, x, y, z};
     // anisotropy regulariser (Eq. 13 on the actual scales)
     if (a.lambda_aniso != 0.0f) {
         int im = 0, in = 0;
@@ -482,6 +509,69 @@ __global__ __launch_bounds__(128) void k_chain(const ChainArgs a)
     a.g_logit[i] += (float)(dalpha * alpha * (1.0 - alpha));
 }
 
+// Gradient with respect to each listed grid's world->index affine [L | t] (boxes fixed): per
+// Gaussian, c = L mu + t contributes dc mu^T to dL/dL and dc to dL/dt, and Sigma_idx =
+// L Sigma L^T contributes 2 Gi L Sigma.  One pass over the Gaussians per grid; FP64 block sums
+// part[block][grid][12] (row-major 3x4), added in a fixed order by k_pose_sum.
+constexpr int POSE_BLOCKS = 256, POSE_THREADS = 256;
+static_assert(GM_POSE_WORKSPACE_BYTES(1) == (size_t)POSE_BLOCKS * 12 * sizeof(double),
+              "the header's workspace size follows the block count");
+
+__global__ __launch_bounds__(POSE_THREADS) void k_pose(const ChainArgs a, double* part)
+{
+    __shared__ double red[POSE_THREADS / 64][12];
+    for (int k = 0; k < a.n_ids; ++k) {
+        const GridConst& G = a.g[k];
+        const int gi = a.grid_index[k];
+        double acc[12];
+#pragma unroll
+        for (int j = 0; j < 12; ++j) acc[j] = 0.0;
+        for (int64_t i = (int64_t)blockIdx.x * POSE_THREADS + threadIdx.x; i < a.n;
+             i += (int64_t)gridDim.x * POSE_THREADS) {
+            if (a.tile_count[(size_t)gi * a.n + i] == 0) continue;  // empty box
+            double qh[4], qn, R[9], S2[3], Sig[9];
+            world_covariance(a.quat, a.log_scale, i, qh, &qn, R, S2, Sig);
+            const double alpha = 1.0 / (1.0 + exp(-(double)a.logit[i]));
+            const float* pg = a.grid_grads + ((size_t)gi * a.n + i) * 10;
+            double dc[3], Gi[9];
+            sigma_idx_grad(G, Sig, alpha, pg, dc, Gi);
+            double GL[9], GLS[9];
+            mm3(Gi, G.L, GL);
+            mm3(GL, Sig, GLS);
+            const double mu[3] = {a.mean[3 * i], a.mean[3 * i + 1], a.mean[3 * i + 2]};
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc[4 * r + c] += dc[r] * mu[c] + 2.0 * GLS[3 * r + c];
+                acc[4 * r + 3] += dc[r];
+            }
+        }
+        // block sum: wavefront butterflies, then the four wavefronts in order
+#pragma unroll
+        for (int j = 0; j < 12; ++j)
+            for (int o = 32; o > 0; o >>= 1) acc[j] += __shfl_xor(acc[j], o, 64);
+        if ((threadIdx.x & 63) == 0)
+#pragma unroll
+            for (int j = 0; j < 12; ++j) red[threadIdx.x >> 6][j] = acc[j];
+        __syncthreads();
+        if (threadIdx.x < 12) {
+            double v = 0.0;
+            for (int w = 0; w < POSE_THREADS / 64; ++w) v += red[w][threadIdx.x];
+            part[((size_t)blockIdx.x * a.n_ids + k) * 12 + threadIdx.x] = v;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_pose_sum(const double* part, int nb, int n_ids, double* out)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;   // (grid, entry)
+    if (e >= n_ids * 12) return;
+    double v = 0.0;
+    for (int b = 0; b < nb; ++b) v += part[(size_t)b * n_ids * 12 + e];
+    out[e] = v;
+}
+
 }  // namespace
 
 hipError_t launch_backward_partials(const BackwardArgs& a, hipStream_t s)
@@ -497,5 +587,19 @@ hipError_t launch_chain(const ChainArgs& a, hipStream_t s)
 {
     if (a.n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_chain, dim3((unsigned)((a.n + 127) / 128)), dim3(128), 0, s, a);
+    return hipGetLastError();
+}
+
+size_t pose_workspace_bytes(int n_ids) { return (size_t)POSE_BLOCKS * n_ids * 12 * sizeof(double); }
+
+hipError_t launch_pose(const ChainArgs& a, double* out, void* ws, hipStream_t s)
+{
+    if (a.n_ids == 0) return hipSuccess;
+    int64_t nb = (a.n + POSE_THREADS - 1) / POSE_THREADS;
+    if (nb > POSE_BLOCKS) nb = POSE_BLOCKS;
+    if (nb < 1) nb = 1;
+    double* part = reinterpret_cast<double*>(ws);
+    hipLaunchKernelGGL(k_pose, dim3((unsigned)nb), dim3(POSE_THREADS), 0, s, a, part);
+    hipLaunchKernelGGL(k_pose_sum, dim3(1), dim3(128), 0, s, part, (int)nb, a.n_ids, out);
     return hipGetLastError();
 }

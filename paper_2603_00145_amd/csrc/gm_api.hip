@@ -729,6 +729,48 @@ gm_status gm_grid_partials(const gm_gaussians* g, const gm_bins* bins, const int
                          reinterpret_cast<hipStream_t>(stream), true, false);
 }
 
+gm_status gm_grid_pose_grads(const gm_gaussians* g, const gm_bins* bins, const int32_t* grid_ids,
+                             int32_t n_ids, double* out, void* workspace, size_t workspace_bytes,
+                             gm_stream stream)
+{
+    g_err.clear();
+    gm_status st = check_gauss(g);
+    if (st != GM_OK) return st;
+    st = check_bins(bins, false);
+    if (st != GM_OK) return st;
+    st = check_ids(bins, grid_ids, n_ids);
+    if (st != GM_OK) return st;
+    if (bins->n_gauss != g->n)
+        return fail(GM_ERR_INVALID_ARGUMENT, "bins were built for %lld Gaussians, got %lld",
+                    (long long)bins->n_gauss, (long long)g->n);
+    if (n_ids == 0) return GM_OK;
+    REQ_PTR(out, "out");
+    REQ_PTR(workspace, "workspace");
+    if (workspace_bytes < pose_workspace_bytes(n_ids))
+        return fail(GM_ERR_INVALID_ARGUMENT, "workspace needs %zu bytes",
+                    pose_workspace_bytes(n_ids));
+    if (g->n > 0) {
+        REQ_PTR(bins->tile_count, "bins->tile_count");
+        REQ_PTR(bins->grid_grads, "bins->grid_grads");
+    }
+    ChainArgs ca;
+    memset(&ca, 0, sizeof ca);
+    ca.n = g->n;
+    ca.n_ids = n_ids;
+    ca.mean = g->mean;
+    ca.quat = g->quat;
+    ca.log_scale = g->log_scale;
+    ca.logit = g->logit;
+    ca.tile_count = bins->tile_count;
+    ca.grid_grads = bins->grid_grads;
+    for (int k = 0; k < n_ids; ++k) {
+        ca.grid_index[k] = grid_ids[k];
+        ca.g[k] = make_const(bins->grids[grid_ids[k]], bins->tile_base[grid_ids[k]]);
+    }
+    GM_HIP(launch_pose(ca, out, workspace, reinterpret_cast<hipStream_t>(stream)), "pose gradient");
+    return GM_OK;
+}
+
 gm_status gm_chain(const gm_gaussians* g, const gm_bins* bins, const int32_t* grid_ids,
                    int32_t n_ids, float lambda_aniso, float lambda_r, gm_gaussian_grads* grad,
                    gm_stream stream)

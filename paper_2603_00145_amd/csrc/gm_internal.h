@@ -139,6 +139,9 @@ struct ChainArgs {
     GridConst g[GM_MAX_GRIDS];
 };
 hipError_t launch_chain(const ChainArgs& a, hipStream_t s);
+// gradient with respect to the listed grids' affines: out [n_ids][12] doubles
+size_t pose_workspace_bytes(int n_ids);
+hipError_t launch_pose(const ChainArgs& a, double* out, void* ws, hipStream_t s);
 
 struct LossArgs {
     int32_t n_stacks;

@@ -2,7 +2,9 @@
 the HIP path.  Each iteration bins the Gaussians onto the stacks, renders them, forms the
 smooth-L1 data term and its per-voxel gradient (plus, with lambda_ssim > 0, the SSIM term of
 Eq. 10 on whole slices), backpropagates to every Gaussian parameter (with the anisotropy
-regulariser), and takes one Adam step per parameter group.  Optionally a
+regulariser), and takes one Adam step per parameter group.  Optionally the stacks' rigid
+transforms T_k are optimised jointly (Sec. 3.3.2): the library returns the gradient with respect
+to each stack's world->index affine and rigid.PoseAdam moves the poses.  Optionally a
 neural residual field (Sec. 3.4) is switched on part-way through (delayed activation).
 """
 from __future__ import annotations
@@ -13,7 +15,7 @@ from typing import List, Optional, Sequence
 
 import torch
 
-from . import api
+from . import api, rigid
 
 
 @dataclasses.dataclass
@@ -31,6 +33,10 @@ class TrainConfig:
     nrf_start: float = 0.5        # fraction of n_iter after which the NRF is active
     lr_nrf: float = 1e-4
     nrf_sample: int = 1 << 18     # stack voxels per stack per iteration for the NRF gradient
+    optimize_pose: bool = False   # joint optimisation of the stacks' rigid transforms
+    lr_pose_rot: float = 1e-3     # radians
+    lr_pose_trans: float = 1e-3   # world units ([-1, 1]^3)
+    pose_frozen: tuple = (0,)     # stacks whose pose stays fixed (the gauge reference)
 
 
 class Reconstruction:
@@ -57,6 +63,11 @@ class Reconstruction:
             if volume_grid is not None else None
         self.it = 0
         self.nrf_on = False
+        self.poses = None
+        if cfg.optimize_pose:
+            self.poses = [rigid.StackPose(s) for s in self.stacks]
+            self.pose_opt = rigid.PoseAdam(self.poses, cfg.lr_pose_rot, cfg.lr_pose_trans,
+                                           frozen=cfg.pose_frozen)
 
     def lrs(self):
         c = self.cfg
@@ -67,6 +78,8 @@ class Reconstruction:
         self.it += 1
         if c.nrf is not None and not self.nrf_on and self.it > int(c.nrf_start * c.n_iter):
             self.nrf_on = True
+        if self.poses is not None:
+            self.bins.set_grids([q.grid() for q in self.poses])
         self.bins.bin(self.p)
         api.render(self.bins, self.ids, self.outs)
         if self.nrf_on:
@@ -79,6 +92,9 @@ class Reconstruction:
         for t in self.g.tensors():
             t.zero_()
         api.backward(self.p, self.bins, self.ids, self.dls, self.g, c.lambda_aniso, c.lambda_r)
+        if self.poses is not None:
+            G = api.pose_grads(self.p, self.bins, self.ids).cpu().numpy()
+            self.pose_opt.step(list(G))
         if self.nrf_on:
             c.nrf.zero_grad()
             for k, s in enumerate(self.stacks):

@@ -12,6 +12,7 @@ Contents
   nrf.py     the neural residual field in FP64
   warm.py    the warm-start network in FP64
   ssim.py    the SSIM term of the reconstruction loss on whole stack slices, FP64
+  progressive.py  the lattice resolution transition of progressive training, FP64
 
 Parity unpinned: nothing in this package is pinned against the paper's own outputs (the
 paper prints no worked example, and its datasets are not available); every function is

@@ -325,6 +325,22 @@ gm_status gm_devox_init(int32_t g, const gm_grid* stacks, int32_t n_stacks,
                         const float* const* stack_data, float* mean, float* quat,
                         float* log_scale, float* logit, gm_stream stream);
 
+/* Resolution transition of multi-resolution progressive training (Sec. 4.1.3): the Gaussians
+ * of a g_old^3 lattice (Gaussian (ix, iy, iz) at index (iz g + iy) g + ix, as gm_devox_init lays
+ * them out) are replaced by a g_new^3 lattice interpolated from them.  The paper names
+ * trilinear interpolation for intensity and scale and normalised linear interpolation for the
+ * rotation; readings: new Gaussians at the new cell centres; the old lattice sampled there in
+ * its cell-index units, clamped to its centres; alpha = sigmoid(logit) and exp(log_scale)
+ * interpolated, the scale multiplied by g_old / g_new (one cell per Gaussian, which keeps the
+ * rendered intensity), alpha clipped to [1e-6, 1 - 1e-6]; quaternions normalised, aligned to
+ * the hemisphere of the heaviest corner (the first of equal weights in (z, y, x) corner
+ * order), summed with the weights and normalised.  Binary64 arithmetic.
+ * old: device parameters of g_old^3 Gaussians (mean unused); outputs: device arrays for g_new^3
+ * Gaussians ([n][3], [n][4], [n][3], [n]), overwritten, not aliasing the inputs. */
+gm_status gm_upsample_lattice(int32_t g_old, const gm_gaussians* old, int32_t g_new,
+                              float* mean, float* quat, float* log_scale, float* logit,
+                              gm_stream stream);
+
 /* ---- warm-start network ------------------------------------------------------------------
  * Predicts, for each Gaussian of a devoxelization initialisation, residuals of its log-scale,
  * rotation and intensity from a 3-channel 8^3 patch of the registered stacks around its centre

@@ -100,6 +100,8 @@ _SIGS = [
     ("gm_grid_pose_grads", ctypes.c_int, [ctypes.POINTER(GmGaussians), ctypes.POINTER(GmBins),
                                            ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, P, P,
                                            ctypes.c_size_t, P]),
+    ("gm_upsample_lattice", ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(GmGaussians),
+                                            ctypes.c_int32, P, P, P, P, P]),
     ("gm_loss_ssim", ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(P),
                                      ctypes.POINTER(ctypes.c_int32), ctypes.c_float,
                                      ctypes.POINTER(P), P, P, P]),

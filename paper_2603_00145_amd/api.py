@@ -269,6 +269,18 @@ def smooth_l1(preds: Sequence[torch.Tensor], targets: Sequence[torch.Tensor],
     return loss[0], dl_di
 
 
+def upsample_lattice(g: GaussParams, g_old: int, g_new: int) -> GaussParams:
+    """gm_upsample_lattice: the g_new^3 lattice interpolated from the g_old^3 one."""
+    n = g_new ** 3
+    dev = g.mean.device
+    out = GaussParams(torch.empty((n, 3), device=dev), torch.empty((n, 4), device=dev),
+                      torch.empty((n, 3), device=dev), torch.empty(n, device=dev))
+    gs = g.struct()
+    check(load().gm_upsample_lattice(int(g_old), ctypes.byref(gs), int(g_new), _p(out.mean),
+                                     _p(out.quat), _p(out.log_scale), _p(out.logit), _stream()))
+    return out
+
+
 def pose_grads(g: GaussParams, bins: Bins, ids: Sequence[int]) -> torch.Tensor:
     """gm_grid_pose_grads: dL/d(world->index affine) [len(ids), 3, 4] (float64, device) of the
     objective whose partials the last backward / grid_partials call on these bins left."""

@@ -898,6 +898,36 @@ gm_status gm_adam_step(float* param, const float* grad, float* m, float* v, int6
     return GM_OK;
 }
 
+gm_status gm_upsample_lattice(int32_t g_old, const gm_gaussians* old, int32_t g_new,
+                              float* mean, float* quat, float* log_scale, float* logit,
+                              gm_stream stream)
+{
+    g_err.clear();
+    if (g_old < 1 || g_new < 1 || g_old > 2048 || g_new > 2048)
+        return fail(GM_ERR_INVALID_ARGUMENT, "lattice sizes outside [1, 2048]");
+    gm_status st = check_gauss(old);
+    if (st != GM_OK) return st;
+    if (old->n != (int64_t)g_old * g_old * g_old)
+        return fail(GM_ERR_INVALID_ARGUMENT, "old holds %lld Gaussians, not g_old^3",
+                    (long long)old->n);
+    REQ_PTR(mean, "mean");
+    REQ_PTR(quat, "quat");
+    REQ_PTR(log_scale, "log_scale");
+    REQ_PTR(logit, "logit");
+    UpsampleArgs ua;
+    ua.g_old = g_old;
+    ua.g_new = g_new;
+    ua.quat = old->quat;
+    ua.log_scale = old->log_scale;
+    ua.logit = old->logit;
+    ua.out_mean = mean;
+    ua.out_quat = quat;
+    ua.out_log_scale = log_scale;
+    ua.out_logit = logit;
+    GM_HIP(launch_upsample(ua, reinterpret_cast<hipStream_t>(stream)), "lattice upsample");
+    return GM_OK;
+}
+
 gm_status gm_devox_init(int32_t g, const gm_grid* stacks, int32_t n_stacks,
                         const float* const* stack_data, float* mean, float* quat,
                         float* log_scale, float* logit, gm_stream stream)

@@ -190,6 +190,18 @@ struct DevoxArgs {
 };
 hipError_t launch_devox(const DevoxArgs& a, hipStream_t s);
 
+struct UpsampleArgs {
+    int32_t g_old, g_new;
+    const float* quat;         // old lattice [g_old^3][4]
+    const float* log_scale;    // [g_old^3][3]
+    const float* logit;        // [g_old^3]
+    float* out_mean;           // new lattice [g_new^3][3]
+    float* out_quat;
+    float* out_log_scale;
+    float* out_logit;
+};
+hipError_t launch_upsample(const UpsampleArgs& a, hipStream_t s);
+
 struct NrfArgs {
     int32_t n_freq, depth, in_pad;
     float out_scale;

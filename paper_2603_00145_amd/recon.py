@@ -4,7 +4,9 @@ smooth-L1 data term and its per-voxel gradient (plus, with lambda_ssim > 0, the 
 Eq. 10 on whole slices), backpropagates to every Gaussian parameter (with the anisotropy
 regulariser), and takes one Adam step per parameter group.  Optionally the stacks' rigid
 transforms T_k are optimised jointly (Sec. 3.3.2): the library returns the gradient with respect
-to each stack's world->index affine and rigid.PoseAdam moves the poses.  Optionally a
+to each stack's world->index affine and rigid.PoseAdam moves the poses.  With a progressive
+schedule (Sec. 4.1.3) the Gaussian lattice is refined at the milestones: the library
+interpolates the new lattice from the old one and the optimiser state starts afresh.  Optionally a
 neural residual field (Sec. 3.4) is switched on part-way through (delayed activation).
 """
 from __future__ import annotations
@@ -37,6 +39,8 @@ class TrainConfig:
     lr_pose_rot: float = 1e-3     # radians
     lr_pose_trans: float = 1e-3   # world units ([-1, 1]^3)
     pose_frozen: tuple = (0,)     # stacks whose pose stays fixed (the gauge reference)
+    lattice: int = 0              # the Gaussians form a lattice^3 (devoxelization layout)
+    progressive: tuple = ()       # ((completed iterations, new lattice size), ...) milestones
 
 
 class Reconstruction:
@@ -62,7 +66,11 @@ class Reconstruction:
         self.vbins = api.Bins(params.n, [volume_grid], capacity=int(12 * params.n) + 4096) \
             if volume_grid is not None else None
         self.it = 0
+        self.adam_t0 = 0              # Adam's step count restarts at a lattice refinement
         self.nrf_on = False
+        self.lattice = cfg.lattice
+        if cfg.progressive and self.lattice ** 3 != params.n:
+            raise ValueError("a progressive schedule needs the Gaussians of a lattice^3 grid")
         self.poses = None
         if cfg.optimize_pose:
             self.poses = [rigid.StackPose(s) for s in self.stacks]
@@ -73,8 +81,24 @@ class Reconstruction:
         c = self.cfg
         return (c.lr_mean, c.lr_quat, c.lr_scale, c.lr_logit)
 
+    def refine(self, g_new: int):
+        """Replace the lattice by the g_new^3 lattice interpolated from it."""
+        self.p = api.upsample_lattice(self.p, self.lattice, g_new)
+        self.lattice = g_new
+        self.g = api.GaussParams.zeros_like(self.p)
+        self.m = api.GaussParams.zeros_like(self.p)
+        self.v = api.GaussParams.zeros_like(self.p)
+        self.bins = api.Bins(self.p.n, self.bins.grids,
+                             capacity=int(10 * self.p.n * len(self.stacks)) + 4096)
+        if self.vbins is not None:
+            self.vbins = api.Bins(self.p.n, [self.volume_grid], capacity=int(12 * self.p.n) + 4096)
+        self.adam_t0 = self.it
+
     def step(self) -> torch.Tensor:
         c = self.cfg
+        for done, g_new in c.progressive:
+            if done == self.it:
+                self.refine(g_new)
         self.it += 1
         if c.nrf is not None and not self.nrf_on and self.it > int(c.nrf_start * c.n_iter):
             self.nrf_on = True
@@ -102,7 +126,7 @@ class Reconstruction:
             c.nrf.adam_step(c.lr_nrf)
         for prm, gr, mm, vv, lr in zip(self.p.tensors(), self.g.tensors(), self.m.tensors(),
                                        self.v.tensors(), self.lrs()):
-            api.adam_step(prm, gr, mm, vv, lr, self.it)
+            api.adam_step(prm, gr, mm, vv, lr, self.it - self.adam_t0)
         return loss
 
     def render_volume(self) -> torch.Tensor:

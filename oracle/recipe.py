@@ -28,6 +28,9 @@ Recipe, per (Gaussian, grid) with world->index affine [L | t] and slice sigma si
      axis or the input was invalid.
   8. Tiles touched: [lo_j // T_j, hi_j // T_j] for tile edge T_j.
 
+block_boxes() is the paper's own rule instead (Eqs. 4-6, cells of [-1, 1]^3 within a block
+radius of the Gaussian's cell), for grids whose world->index map is axis-aligned.
+
 exp_recipe(s) is Cody-Waite range reduction with a two-part ln 2 followed by the Taylor
 series of e^r (coefficients 1/n!, n = 0..13) in Horner form, then an exact power-of-two
 scaling:  k = rint(s * INV_LN2);  r = (s - k*LN2_HI) - k*LN2_LO;  p = sum c_n r^n;
@@ -120,6 +123,60 @@ def boxes(mean, quat, log_scale, logit, grid, cutoff: float = 3.0):
     lo = np.maximum(lo, 0)
     hi = np.minimum(hi, dims[None, :] - 1)
     nonempty = valid & (lo <= hi).all(1)
+    return lo, hi, nonempty, valid
+
+
+def world_axes(grid):
+    """For an axis-aligned grid (each row of L has one non-zero entry, in distinct columns):
+    the world axis of each index axis; None otherwise."""
+    L = np.asarray(grid.world_to_index, np.float64)[:, :3]
+    nz = [np.flatnonzero(L[j]) for j in range(3)]
+    if any(len(k) != 1 for k in nz):
+        return None
+    axes = [int(k[0]) for k in nz]
+    return axes if len(set(axes)) == 3 else None
+
+
+def cell_of(x, resolution):
+    """Eq. 4: cell index floor((x + 1) res / 2) along one axis, binary64, that association."""
+    return np.floor(((np.asarray(x, np.float64) + 1.0) * float(resolution)) / 2.0)
+
+
+def block_boxes(mean, quat, log_scale, logit, grid, resolution: int, radius: int):
+    """The paper's cell-neighbourhood query (Sec. 3.3.1, Eqs. 4-6) as voxel boxes.
+
+    [-1, 1]^3 is cut into resolution^3 cells; voxel v of the grid takes Gaussian i when, on
+    every world axis a, |cell_a(x(v)) - cell_a(mu_i)| <= radius (Eqs. 5-6).  On an axis-aligned
+    grid the world coordinate of v along world axis a depends on one index axis j only:
+    x_a = (v_j - t_j) / L[j, a] (binary64), so the voxels form a box.  Gaussians whose
+    parameters are invalid (as in boxes()) get none.  Returns (lo, hi, nonempty, valid) like
+    boxes()."""
+    axes = world_axes(grid)
+    if axes is None:
+        raise ValueError("the block query needs an axis-aligned grid")
+    _, _, _, valid = boxes(mean, quat, log_scale, logit, grid)
+    mu = np.asarray(mean, np.float32).astype(np.float64)
+    A = np.asarray(grid.world_to_index, np.float64)
+    dims = [grid.nx, grid.ny, grid.nz]
+    n = mu.shape[0]
+    lo = np.zeros((n, 3), np.int64)
+    hi = np.zeros((n, 3), np.int64)
+    nonempty = valid.copy()
+    for j in range(3):
+        a = axes[j]
+        v = np.arange(dims[j], dtype=np.float64)
+        cells = cell_of((v - A[j, 3]) / A[j, a], resolution)     # monotone in v
+        with np.errstate(invalid="ignore"):
+            cm = cell_of(np.where(valid, mu[:, a], 0.0), resolution)
+        if A[j, a] > 0:
+            first = np.searchsorted(cells, cm - radius, side="left")
+            last = np.searchsorted(cells, cm + radius, side="right") - 1
+        else:
+            rc = cells[::-1]
+            first = dims[j] - np.searchsorted(rc, cm + radius, side="right")
+            last = dims[j] - 1 - np.searchsorted(rc, cm - radius, side="left")
+        lo[:, j], hi[:, j] = first, last
+        nonempty &= first <= last
     return lo, hi, nonempty, valid
 
 

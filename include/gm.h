@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define GM_ABI_VERSION 3
+#define GM_ABI_VERSION 4
 #define GM_MAX_GRIDS 8
 #define GM_RECORD_FLOATS 16       /* floats per (grid, Gaussian) record                */
 #define GM_GRID_GRAD_FLOATS 10    /* floats per (grid, Gaussian) backward partial      */
@@ -86,6 +86,15 @@ typedef struct gm_grid {
  * query (Sec. 3.3.1, Eq. 4-6). */
 typedef struct gm_bin_opts {
     double cutoff_sigma;
+    /* > 0: the paper's own query (Sec. 3.3.1, Eqs. 4-6) instead of the sigma box: [-1, 1]^3
+     * is cut into cell_resolution^3 cells (Eq. 4, cell = floor((x + 1) res / 2) per axis, in
+     * binary64) and voxel v takes Gaussian i when on every world axis the cell of v's world
+     * position lies within block_radius of the cell of mu_i.  A voxel's world coordinate along
+     * world axis a is (v_j - t_j) / L[j][a] for the index axis j mapped to it, so every grid
+     * must be axis-aligned (each row of L one non-zero entry, in distinct columns; rotated
+     * stacks are GM_ERR_UNSUPPORTED) and the voxels form a box.  0: the sigma box. */
+    int32_t block_radius;
+    int32_t cell_resolution;
 } gm_bin_opts;
 
 /* Binning state: caller-allocated device buffers (sizes from gm_bin_query) plus host fields

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgm.so")
 
 GM_MAX_GRIDS = 8
-ABI_VERSION = 3          # struct layouts of include/gm.h this binding mirrors
+ABI_VERSION = 4          # struct layouts of include/gm.h this binding mirrors
 GM_RECORD_FLOATS = 16
 GM_GRID_GRAD_FLOATS = 10
 GM_REDUCE_WORKSPACE_BYTES = 16384
@@ -43,7 +43,8 @@ class GmGrid(ctypes.Structure):
 
 
 class GmBinOpts(ctypes.Structure):
-    _fields_ = [("cutoff_sigma", ctypes.c_double)]
+    _fields_ = [("cutoff_sigma", ctypes.c_double), ("block_radius", ctypes.c_int32),
+                ("cell_resolution", ctypes.c_int32)]
 
 
 class GmBins(ctypes.Structure):

@@ -85,11 +85,15 @@ class Bins:
     torch tensors owned by this object; the pair capacity grows on demand."""
 
     def __init__(self, n: int, grids: Sequence, capacity: Optional[int] = None,
-                 cutoff: float = 3.0, device="cuda"):
+                 cutoff: float = 3.0, device="cuda", block_radius: int = 0,
+                 cell_resolution: int = 0):
         load()
         self.grids = list(grids)
         self.n = int(n)
         self.cutoff = float(cutoff)
+        # block_radius > 0: the paper's cell-neighbourhood query (Eqs. 4-6) instead of the box
+        self.block_radius = int(block_radius)
+        self.cell_resolution = int(cell_resolution)
         self.device = torch.device(device)
         self._cgrids = (_lib.GmGrid * len(self.grids))(*[_lib.grid_struct(g) for g in self.grids])
         rb = ctypes.c_size_t()
@@ -143,7 +147,7 @@ class Bins:
         if g.n != self.n:
             raise ValueError(f"bins built for {self.n} Gaussians, got {g.n}")
         gs = g.struct()
-        opts = _lib.GmBinOpts(self.cutoff)
+        opts = _lib.GmBinOpts(self.cutoff, self.block_radius, self.cell_resolution)
         npairs = ctypes.c_int64()
         for _ in range(2):
             b = self.struct()

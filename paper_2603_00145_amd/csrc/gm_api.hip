@@ -82,6 +82,20 @@ GridConst make_const(const gm_grid& g, int64_t tile_base)
         c.t[r] = g.world_to_index[4 * r + 3];
     }
     c.sig = g.psf_sigma_z;
+    // world axis of each index axis when [L] is a scaled permutation
+    bool aligned = true;
+    for (int r = 0; r < 3; ++r) {
+        int nzc = 0, col = -1;
+        for (int j = 0; j < 3; ++j)
+            if (c.L[3 * r + j] != 0.0) {
+                ++nzc;
+                col = j;
+            }
+        c.waxis[r] = nzc == 1 ? col : -1;
+        aligned = aligned && nzc == 1;
+    }
+    if (!aligned || c.waxis[0] == c.waxis[1] || c.waxis[0] == c.waxis[2] || c.waxis[1] == c.waxis[2])
+        c.waxis[0] = c.waxis[1] = c.waxis[2] = -1;
     return c;
 }
 
@@ -357,6 +371,11 @@ gm_status gm_bin(const gm_gaussians* g, const gm_grid* grids, int32_t n_grids,
     const double cutoff = opts ? opts->cutoff_sigma : 3.0;
     if (!(cutoff > 0.0) || !isfinite(cutoff))
         return fail(GM_ERR_INVALID_ARGUMENT, "cutoff_sigma must be finite and > 0");
+    const int32_t block_radius = opts ? opts->block_radius : 0;
+    const int32_t cell_res = opts ? opts->cell_resolution : 0;
+    if (block_radius < 0 || (block_radius > 0 && (cell_res < 1 || cell_res > (1 << 20))))
+        return fail(GM_ERR_INVALID_ARGUMENT, "block query needs block_radius >= 0 and "
+                                             "cell_resolution in [1, 2^20]");
     REQ_PTR(bins->tile_start, "bins->tile_start");
     REQ_PTR(bins->box_volume, "bins->box_volume");
     REQ_PTR(bins->scratch, "bins->scratch");
@@ -368,6 +387,12 @@ gm_status gm_bin(const gm_gaussians* g, const gm_grid* grids, int32_t n_grids,
     if (bins->scratch_bytes < need_scratch)
         return fail(GM_ERR_INVALID_ARGUMENT, "scratch_bytes %zu < required %zu",
                     bins->scratch_bytes, need_scratch);
+
+    if (block_radius > 0)
+        for (int k = 0; k < n_grids; ++k)
+            if (make_const(grids[k], 0).waxis[0] < 0)
+                return fail(GM_ERR_UNSUPPORTED, "the block query needs axis-aligned grids (grid %d "
+                                                "is rotated)", k);
 
     // host fields
     int64_t base = 0;
@@ -393,6 +418,8 @@ gm_status gm_bin(const gm_gaussians* g, const gm_grid* grids, int32_t n_grids,
     pa.n = n;
     pa.n_grids = n_grids;
     pa.cutoff = cutoff;
+    pa.block_radius = block_radius;
+    pa.cell_res = cell_res;
     pa.mean = g->mean;
     pa.quat = g->quat;
     pa.log_scale = g->log_scale;
@@ -453,6 +480,8 @@ gm_status gm_bin(const gm_gaussians* g, const gm_grid* grids, int32_t n_grids,
     if (flags & 1u)
         return fail(GM_ERR_NONFINITE,
                     "non-finite parameter, zero quaternion or overflowing scale (empty boxes)");
+    if (flags & 2u)
+        return fail(GM_ERR_UNSUPPORTED, "a block-query box did not settle (grid scale too extreme)");
     return GM_OK;
 }
 

@@ -27,6 +27,7 @@ struct GridConst {
     double L[9];             // world -> index linear part, row-major
     double t[3];
     double sig;              // slice-profile sigma along index z
+    int32_t waxis[3];        // world axis of each index axis (axis-aligned grids), else -1
 };
 
 // ---- launchers (one per kernel family) --------------------------------------------------
@@ -47,6 +48,8 @@ struct PreprocessArgs {
     int64_t n;
     int32_t n_grids;
     double cutoff;
+    int32_t block_radius;    // > 0: the cell-neighbourhood query of Eqs. 4-6 instead
+    int32_t cell_res;
     const float* mean;
     const float* quat;
     const float* log_scale;
@@ -54,7 +57,7 @@ struct PreprocessArgs {
     float* records;          // [n_grids][n][16]
     int32_t* tile_count;     // [n_grids][n]
     unsigned long long* box_volume;  // [n_grids]
-    uint32_t* flags;         // bit 0: invalid parameter seen
+    uint32_t* flags;         // bit 0: invalid parameter seen; bit 1: block box not settled
     float* grid_grads;       // [n_grids][n][10] or NULL: zeroed for empty boxes
     GridConst g[GM_MAX_GRIDS];
 };

@@ -10,7 +10,8 @@
 //   c = L mu + t,  Sigma_idx = B B^T with B = L R diag(e^s),
 //   Sigma_g = Sigma_idx + sig^2 e_z e_z^T,  C = Sigma_g^-1,
 //   amp = alpha sqrt(det Sigma_idx / det Sigma_g)       (Gaussian (x) normalised profile).
-// The box is +-cutoff marginal standard deviations sqrt((Sigma_g)_jj) around c.
+// The box is +-cutoff marginal standard deviations sqrt((Sigma_g)_jj) around c, or, with a
+// block radius, the paper's cell-neighbourhood query (Eqs. 4-6) on axis-aligned grids.
 #include "gm_internal.h"
 
 namespace {
@@ -37,6 +38,42 @@ __device__ double exp_cw(double s)
 }
 
 __device__ __forceinline__ bool finite_d(double x) { return __builtin_isfinite(x); }
+
+// Eq. 4 along one axis: floor((x + 1) res / 2), binary64, that association
+__device__ __forceinline__ double cell_of(double x, double res) { return floor(((x + 1.0) * res) / 2.0); }
+
+// The paper's block query (Eqs. 4-6) on index axis j of an axis-aligned grid: the voxels v with
+// |cell(x(v)) - cm| <= r, x(v) = (v - t) / l the world coordinate along the mapped axis.  A
+// candidate range from the real-number inverse, widened by two voxels, is narrowed by the
+// exact predicate at both ends (the set is an interval: x(v) and the cell are monotone).
+// Returns false when a bounded walk did not settle (never for finite grid scales).
+__device__ bool block_interval(double l, double t, double cm, double r, double res, int dim,
+                               int* lo, int* hi)
+{
+    const double CL = 1073741824.0;
+    const double x0 = ((cm - r) * 2.0) / res - 1.0, x1 = ((cm + r + 1.0) * 2.0) / res - 1.0;
+    const double va = x0 * l + t, vb = x1 * l + t;
+    double a = floor(fmin(va, vb)) - 2.0, b = ceil(fmax(va, vb)) + 2.0;
+    a = (a != a) ? CL : fmin(fmax(a, -CL), CL);
+    b = (b != b) ? -CL : fmin(fmax(b, -CL), CL);
+    int v0 = (int)a, v1 = (int)b;
+    v0 = v0 < 0 ? 0 : v0;
+    v1 = v1 > dim - 1 ? dim - 1 : v1;
+    auto in = [&](int v) { return fabs(cell_of(((double)v - t) / l, res) - cm) <= r; };
+    int steps = 0;
+    while (v0 <= v1 && !in(v0) && steps < 16) {
+        ++v0;
+        ++steps;
+    }
+    steps = 0;
+    while (v1 >= v0 && !in(v1) && steps < 16) {
+        --v1;
+        ++steps;
+    }
+    *lo = v0;
+    *hi = v1;
+    return v0 > v1 || (in(v0) && in(v1));
+}
 
 __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a)
 {
@@ -106,6 +143,18 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a)
             int lo[3], hi[3];
             bool nonempty = valid;
             const double CL = 1073741824.0;
+            if (a.block_radius > 0) {
+                const double mus[3] = {mu0, mu1, mu2};
+                const double res = (double)a.cell_res, r = (double)a.block_radius;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const int wa = G.waxis[j];
+                    const double cm = cell_of(valid ? mus[wa] : 0.0, res);
+                    if (!block_interval(G.L[3 * j + wa], G.t[j], cm, r, res, dims[j], &lo[j], &hi[j]))
+                        atomicOr(a.flags, 2u);
+                    nonempty = nonempty && (lo[j] <= hi[j]);
+                }
+            } else {
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 const double rho = a.cutoff * sqrt(D[j]);
@@ -118,6 +167,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a)
                 lo[j] = li;
                 hi[j] = hj;
                 nonempty = nonempty && (li <= hj);
+            }
             }
             // record: c - lo, amp, base-2 conic, box
             double Si[6];  // Sigma_idx = B B^T: xx yy zz xy xz yz

@@ -39,6 +39,8 @@ class TrainConfig:
     lr_pose_rot: float = 1e-3     # radians
     lr_pose_trans: float = 1e-3   # world units ([-1, 1]^3)
     pose_frozen: tuple = (0,)     # stacks whose pose stays fixed (the gauge reference)
+    block_radius: int = 0         # > 0: the paper's cell-neighbourhood query (Eqs. 4-6)
+    cell_resolution: int = 0      # its grid_resolution (cells per axis of [-1, 1]^3)
     lattice: int = 0              # the Gaussians form a lattice^3 (devoxelization layout)
     progressive: tuple = ()       # ((completed iterations, new lattice size), ...) milestones
 
@@ -57,14 +59,13 @@ class Reconstruction:
         self.m = api.GaussParams.zeros_like(params)
         self.v = api.GaussParams.zeros_like(params)
         dev = params.mean.device
-        self.bins = api.Bins(params.n, self.stacks, capacity=int(10 * params.n * len(self.stacks)) + 4096)
+        self.bins = self._bins(params.n, self.stacks, 10)
         self.ids = list(range(len(self.stacks)))
         self.outs = [torch.empty(s.shape, dtype=torch.float32, device=dev) for s in self.stacks]
         self.dls = [torch.empty(s.shape, dtype=torch.float32, device=dev) for s in self.stacks]
         self.volume_grid = volume_grid
         self.phantom = phantom
-        self.vbins = api.Bins(params.n, [volume_grid], capacity=int(12 * params.n) + 4096) \
-            if volume_grid is not None else None
+        self.vbins = self._bins(params.n, [volume_grid], 12) if volume_grid is not None else None
         self.it = 0
         self.adam_t0 = 0              # Adam's step count restarts at a lattice refinement
         self.nrf_on = False
@@ -77,6 +78,11 @@ class Reconstruction:
             self.pose_opt = rigid.PoseAdam(self.poses, cfg.lr_pose_rot, cfg.lr_pose_trans,
                                            frozen=cfg.pose_frozen)
 
+    def _bins(self, n, grids, per):
+        c = self.cfg
+        return api.Bins(n, grids, capacity=int(per * n * len(grids)) + 4096,
+                        block_radius=c.block_radius, cell_resolution=c.cell_resolution)
+
     def lrs(self):
         c = self.cfg
         return (c.lr_mean, c.lr_quat, c.lr_scale, c.lr_logit)
@@ -88,10 +94,9 @@ class Reconstruction:
         self.g = api.GaussParams.zeros_like(self.p)
         self.m = api.GaussParams.zeros_like(self.p)
         self.v = api.GaussParams.zeros_like(self.p)
-        self.bins = api.Bins(self.p.n, self.bins.grids,
-                             capacity=int(10 * self.p.n * len(self.stacks)) + 4096)
+        self.bins = self._bins(self.p.n, self.bins.grids, 10)
         if self.vbins is not None:
-            self.vbins = api.Bins(self.p.n, [self.volume_grid], capacity=int(12 * self.p.n) + 4096)
+            self.vbins = self._bins(self.p.n, [self.volume_grid], 12)
         self.adam_t0 = self.it
 
     def step(self) -> torch.Tensor:

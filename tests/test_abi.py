@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 def test_host_only_calls():
     from paper_2603_00145_amd import _lib
     lib = _lib.load()
-    assert lib.gm_abi_version() == 3
+    assert lib.gm_abi_version() == 4
     assert _lib.tile_dims() == (16, 16, 4)
     # host-side validation needs no device
     g = _lib.GmGrid()

@@ -47,7 +47,7 @@ def alu_peak_tflops(flop_per_pair, instr_per_pair):
 
 def recorded_traffic(kernel):
     """HBM bytes per launch of `kernel` from its committed counter summary, if that summary
-    was taken on the current source of the kernel (else None)."""
+    was taken on the kernel as it is built now (the same gfx950 assembly digest), else None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_traffic_c256.md")
     if not os.path.exists(path):
         return None
@@ -55,15 +55,13 @@ def recorded_traffic(kernel):
     with open(path) as f:
         for line in f:
             key, _, val = line.partition(":")
-            if key in ("traffic_bytes", "kernel", "source_sha256", "sources"):
+            if key in ("traffic_bytes", "kernel", "kernel_asm_sha256"):
                 fields[key] = val.strip()
-    if fields.get("kernel") != kernel or "sources" not in fields:
+    if fields.get("kernel") != kernel:
         return None
-    from paper_2603_00145_amd.profile_summary import source_digest
-    try:
-        if source_digest(fields["sources"].split()) != fields.get("source_sha256"):
-            return None
-    except OSError:
+    from paper_2603_00145_amd.profile_summary import kernel_digest
+    now = kernel_digest(kernel)
+    if now is None or now != fields.get("kernel_asm_sha256"):
         return None
     return float(fields["traffic_bytes"])
 

@@ -3,10 +3,16 @@
 Every source is compiled with hipcc for gfx950 only.  Packed FP32 instruction selection is
 disabled on every device pass.  The box/record kernel is compiled without floating-point
 contraction (its integer boxes follow one exact IEEE binary64 recipe).
+
+The build also records, in kernel_digests.json beside the library, the SHA-256 of the gfx950
+assembly of the kernels whose hardware counters are kept as summaries: a summary applies to a
+build exactly when the digest it was taken with is still the one recorded here.
 """
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
+import json
 import os
 import shutil
 import subprocess
@@ -46,6 +52,39 @@ def _compile(src: str) -> str:
     return obj
 
 
+# kernels with counter summaries (profiles/<kernel>_traffic_*.md) and their source files
+DIGESTED = {"k_partials": "backward.hip", "k_render": "render.hip"}
+DIGESTS = os.path.join(HERE, "kernel_digests.json")
+
+
+def _kernel_asm_digest(src: str, kernels) -> dict:
+    """SHA-256 of each kernel's gfx950 assembly (its function body, labels included)."""
+    flags = list(COMMON)
+    if src in NO_CONTRACT:
+        flags.append("-ffp-contract=off")
+    out = os.path.join(BUILD, os.path.splitext(src)[0] + ".s")
+    cmd = [hipcc()] + flags + ["--cuda-device-only", "-S", os.path.join(CSRC, src), "-o", out]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"assembly of {src} failed:\n{r.stderr}")
+    with open(out) as f:
+        lines = f.read().splitlines()
+    res = {}
+    for k in kernels:
+        body, inside = [], False
+        for ln in lines:
+            head = ln.split(";")[0].strip()
+            if not inside and head.endswith(":") and k in head and not head.startswith("."):
+                inside = True
+            if inside:
+                body.append(ln)
+                if ln.startswith(".Lfunc_end"):
+                    break
+        if body:
+            res[k] = hashlib.sha256("\n".join(body).encode()).hexdigest()
+    return res
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
@@ -56,6 +95,14 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    by_src = {}
+    for k, src in DIGESTED.items():
+        by_src.setdefault(src, []).append(k)
+    with cf.ThreadPoolExecutor(max_workers=len(by_src)) as ex:
+        parts = list(ex.map(lambda kv: _kernel_asm_digest(*kv), by_src.items()))
+    digests = {k: v for d in parts for k, v in d.items()}
+    with open(DIGESTS, "w") as f:
+        json.dump(digests, f, indent=1, sort_keys=True)
     if verbose:
         print(LIB)
     return LIB

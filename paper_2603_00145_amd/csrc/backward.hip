@@ -432,7 +432,8 @@ __device__ __forceinline__ void world_covariance(const float* quat, const float*
                              R[3 * p + 2] * S2[2] * R[3 * q + 2];
 }
 
-__global__ __launch_bounds__(128) void k_chain(const ChainArgs a)
+// three waves per SIMD (at most 168 VGPRs): a few registers more drop it to two, 25% slower
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k_chain(const ChainArgs a)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
@@ -563,13 +564,19 @@ __global__ __launch_bounds__(POSE_THREADS) void k_pose(const ChainArgs a, double
     }
 }
 
-__global__ void k_pose_sum(const double* part, int nb, int n_ids, double* out)
+// one block per (grid, entry): the block partials added by a fixed tree in LDS
+__global__ __launch_bounds__(POSE_BLOCKS) void k_pose_sum(const double* part, int nb, int n_ids,
+                                                          double* out)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;   // (grid, entry)
-    if (e >= n_ids * 12) return;
-    double v = 0.0;
-    for (int b = 0; b < nb; ++b) v += part[(size_t)b * n_ids * 12 + e];
-    out[e] = v;
+    __shared__ double sh[POSE_BLOCKS];
+    const int e = blockIdx.x;   // (grid, entry)
+    sh[threadIdx.x] = (int)threadIdx.x < nb ? part[(size_t)threadIdx.x * n_ids * 12 + e] : 0.0;
+    __syncthreads();
+    for (int o = POSE_BLOCKS / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[e] = sh[0];
 }
 
 }  // namespace
@@ -600,6 +607,7 @@ hipError_t launch_pose(const ChainArgs& a, double* out, void* ws, hipStream_t s)
     if (nb < 1) nb = 1;
     double* part = reinterpret_cast<double*>(ws);
     hipLaunchKernelGGL(k_pose, dim3((unsigned)nb), dim3(POSE_THREADS), 0, s, a, part);
-    hipLaunchKernelGGL(k_pose_sum, dim3(1), dim3(128), 0, s, part, (int)nb, a.n_ids, out);
+    hipLaunchKernelGGL(k_pose_sum, dim3((unsigned)(a.n_ids * 12)), dim3(POSE_BLOCKS), 0, s, part,
+                       (int)nb, a.n_ids, out);
     return hipGetLastError();
 }

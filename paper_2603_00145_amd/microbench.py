@@ -27,6 +27,7 @@ from . import api, inputs, nrf, warmstart
 
 BF16_PEAK = 2.5e15          # dense MFMA FLOP/s of MI355X in BF16
 FP64_PEAK = 78.6e12         # FP64 vector FLOP/s of MI355X (an FMA counts 2)
+HBM_PEAK = 8.0e12           # bytes/s
 # SSIM value + gradient per pixel, separable 11-tap window: five window sums (2 x 11 FMA each)
 # and three products, ~35 FLOP for the statistics and partials (plus two divisions), three
 # adjoint window sums (2 x 11 FMA each) and 5 FLOP to assemble the gradient
@@ -64,7 +65,7 @@ def warm_flops_forward():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--reps", type=int, default=10)
-    ap.add_argument("--only", choices=["nrf", "ssim", "warm"], default=None,
+    ap.add_argument("--only", choices=["nrf", "ssim", "warm", "pose", "lattice"], default=None,
                     help="run one group of measurements")
     args = ap.parse_args()
     run = (lambda grp: args.only is None or args.only == grp)
@@ -136,6 +137,38 @@ def main():
         out.append({"what": "warmstart_train_step", "gaussians": b, "seconds": t,
                     "gaussians_per_s": b / t, "tflops": f / t / 1e12, "mfma_frac": f / t / BF16_PEAK,
                     "config": "batch 1024: forward, loss head, backward-data and backward-weights"})
+    if run("pose"):
+        # stack-pose gradient of the 256^3 workload (1M Gaussians, three stacks), after the
+        # grid-frame partials of a random dL/dI
+        w = inputs.workload("c256", with_data=False)
+        p = api.GaussParams.from_host(w.gauss)
+        ids = list(range(len(w.stacks)))
+        b = api.Bins(p.n, w.stacks, capacity=int(12 * p.n * len(ids)))
+        b.bin(p)
+        dl = [torch.randn(s.shape, device=dev, generator=g) for s in w.stacks]
+        api.grid_partials(p, b, ids, dl)
+        t = _time(lambda: api.pose_grads(p, b, ids), args.reps)
+        # per (Gaussian, grid): 44 B of parameters, 40 B of partials, 4 B tile count
+        byt = p.n * len(ids) * (44 + 40 + 4)
+        out.append({"what": "pose_grads", "gaussians": p.n, "grids": len(ids), "seconds": t,
+                    "gb_per_s": byt / t / 1e9, "hbm_frac": byt / t / HBM_PEAK,
+                    "config": "1M Gaussians x 3 stacks of 256x256x64, FP64 reduction"})
+
+    if run("lattice"):
+        # progressive-training transition 100^3 -> 126^3 lattices (1M -> 2M Gaussians)
+        n0, n1 = 100, 126
+        c = torch.linspace(-1 + 1 / n0, 1 - 1 / n0, n0, device=dev)
+        Z, Y, X = torch.meshgrid(c, c, c, indexing="ij")
+        m = torch.stack([X, Y, Z], -1).reshape(-1, 3).contiguous()
+        p = api.GaussParams(m, torch.randn((n0 ** 3, 4), device=dev, generator=g),
+                            torch.full((n0 ** 3, 3), -4.0, device=dev),
+                            torch.randn(n0 ** 3, device=dev, generator=g))
+        t = _time(lambda: api.upsample_lattice(p, n0, n1), args.reps)
+        byt = n0 ** 3 * 32 + n1 ** 3 * 44      # old quat, scale, logit read; new lattice written
+        out.append({"what": "upsample_lattice", "gaussians_out": n1 ** 3, "seconds": t,
+                    "gb_per_s": byt / t / 1e9, "hbm_frac": byt / t / HBM_PEAK,
+                    "config": "100^3 -> 126^3 lattice, binary64 interpolation"})
+
     for o in out:
         print(json.dumps(o))
         sys.stdout.flush()

@@ -3,21 +3,22 @@
     python -m paper_2603_00145_amd.profile_summary stats  --dir D --out F --command C
     python -m paper_2603_00145_amd.profile_summary traffic --fetch-dir D1 --write-dir D2
            --kernel k_render --source paper_2603_00145_amd/csrc/render.hip --calib-mib 1024
-           --out F --command C
+           --out F --command-fetch C1 --command-write C2
 
 `stats` summarises a `--kernel-trace --stats` run (per-kernel calls and durations of this
 library's kernels).  `traffic` takes one `--pmc FETCH_SIZE` run and one `--pmc WRITE_SIZE`
 run of the same program (which ran a plain streaming kernel, torch.neg over calib-mib MiB,
 before its timed steps), scales the kernel's per-dispatch counters by what the counters read
 for that streaming kernel (which reads and writes exactly calib-mib MiB), and records the
-SHA-256 of the kernel's source so that a reader can tell whether the figure still applies.
+SHA-256 of the kernel's gfx950 assembly in the build that was profiled (kernel_digests.json,
+written by the build), so that a reader can tell whether the figure still applies.
 """
 from __future__ import annotations
 
 import argparse
 import csv
 import glob
-import hashlib
+import json
 import os
 import statistics
 import sys
@@ -26,12 +27,16 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 OUR_KERNELS = ("k_", "(anonymous namespace)::k_")
 
 
-def source_digest(paths):
-    h = hashlib.sha256()
-    for p in paths:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()
+DIGESTS = os.path.join(ROOT, "paper_2603_00145_amd", "kernel_digests.json")
+
+
+def kernel_digest(kernel):
+    """SHA-256 of the kernel's assembly in the current build (None without a build)."""
+    try:
+        with open(DIGESTS) as f:
+            return json.load(f).get(kernel)
+    except (OSError, ValueError):
+        return None
 
 
 def _short(name: str) -> str:
@@ -80,7 +85,9 @@ def cmd_traffic(a):
     cf, cw = calib(f_vals), calib(w_vals)         # KiB
     sf, sw = cal_bytes / (cf * 1024.0), cal_bytes / (cw * 1024.0)
     traffic = fk * 1024.0 * sf + wk * 1024.0 * sw
-    digest = source_digest(a.source)
+    digest = kernel_digest(a.kernel)
+    if digest is None:
+        sys.exit("no kernel_digests.json entry: build first")
     txt = f"""# HBM traffic of {a.kernel} ({a.workload})
 
 Commands (from the repository root on the GPU machine, run after `cd /tmp`):
@@ -97,8 +104,8 @@ HBM bytes per launch = FETCH x scale + WRITE x scale:
 
 traffic_bytes: {traffic:.0f}
 kernel: {a.kernel}
-source_sha256: {digest}
-sources: {' '.join(a.source)}
+kernel_asm_sha256: {digest}
+source: {a.source}
 """
     with open(a.out, "w") as f:
         f.write(txt)
@@ -134,7 +141,7 @@ def main():
     t.add_argument("--fetch-dir", required=True)
     t.add_argument("--write-dir", required=True)
     t.add_argument("--kernel", required=True)
-    t.add_argument("--source", nargs="+", required=True)
+    t.add_argument("--source", required=True, help="the kernel's source file (for the reader)")
     t.add_argument("--calib-mib", type=int, default=1024)
     t.add_argument("--workload", default="training iteration, 256^3 workload")
     t.add_argument("--command-fetch", required=True)

@@ -69,6 +69,33 @@ constexpr int RZS = RX * RY + 8;
 constexpr int BWD_G = 8;   // lanes per Gaussian in the backward
 static_assert(RZS % 32 == 8, "z-plane stride must be 8 mod 32 banks");
 
+// Column sums s0 = sum ge, s1 = sum k ge, s2 = sum k^2 ge (ge = g 2^Q_k) over the first NK
+// rows of a column whose rows are RX floats apart in the staged region.  Rows 0..7 of a home
+// box lie inside the region (the box starts in the tile, the region reaches 8 rows past it),
+// so all NK reads are issued at immediate offsets before the first use; rows past the column
+// (k >= ncol) are masked where they are used.  NK is the wavefront's longest column (up to 8),
+// a compile-time constant, so the steps carry no branches.
+template <int NK>
+__device__ __forceinline__ void lds_column(const float* __restrict__ region, uint32_t off,
+                                           int ncol, float A, float B, float kyy, float& s0,
+                                           float& s1, float& s2)
+{
+    float gv[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) gv[k] = region[off + k * RX];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+        const float Q = k == 0 ? A : A + (float)k * (B + (float)k * kyy);
+        const float gk = k == 0 ? gv[0] : (k < ncol ? gv[k] : 0.0f);
+        const float ge = gk * __builtin_amdgcn_exp2f(Q);
+        s0 += ge;
+        if (k > 0) {
+            s1 += (float)k * ge;
+            s2 += (float)(k * k) * ge;
+        }
+    }
+}
+
 // 64/G Gaussians of one grid at a time, one per group of G lanes: the ten moments of each,
 // turned into the grid-frame partials and stored.  A group maps its lanes onto chunks of G
 // (x, z) columns of its Gaussian's box and walks each column along y (for thick-slice stacks the box
@@ -147,28 +174,41 @@ __device__ __forceinline__ void group_of_gaussians(const BackwardArgs& a, int kk
         const int ncol = act ? wy : 1;             // steps whose voxel lies in the box
         // s0 = sum ge, s1 = sum k ge, s2 = sum k^2 ge over the column (ge = g 2^Q)
         float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
-        float gv[8];
+        if (FROM_LDS) {
+            switch (max_wy < 8 ? max_wy : 8) {
+            case 1: lds_column<1>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+            case 2: lds_column<2>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+            case 3: lds_column<3>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+            case 4: lds_column<4>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+            case 5: lds_column<5>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+            case 6: lds_column<6>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+            case 7: lds_column<7>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+            default: lds_column<8>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+            }
+        } else {
+            float gv[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (k < max_wy) {
-                if (k < min_wy) {
-                    gv[k] = FROM_LDS ? region[off + k * RX] : (g + (size_t)k * nx)[off];
-                } else {
-                    const int kc = min(k, ncol - 1);
-                    const float t = FROM_LDS ? region[off + kc * RX] : (g + (size_t)kc * nx)[off];
-                    gv[k] = k < ncol ? t : 0.0f;
+            for (int k = 0; k < 8; ++k) {
+                if (k < max_wy) {
+                    if (k < min_wy) {
+                        gv[k] = (g + (size_t)k * nx)[off];
+                    } else {
+                        const int kc = min(k, ncol - 1);
+                        const float t = (g + (size_t)kc * nx)[off];
+                        gv[k] = k < ncol ? t : 0.0f;
+                    }
                 }
             }
-        }
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (k < max_wy) {
-                const float Q = k == 0 ? A : A + (float)k * (B + (float)k * kyy);
-                const float ge = gv[k] * __builtin_amdgcn_exp2f(Q);
-                s0 += ge;
-                if (k > 0) {
-                    s1 += (float)k * ge;
-                    s2 += (float)(k * k) * ge;
+            for (int k = 0; k < 8; ++k) {
+                if (k < max_wy) {
+                    const float Q = k == 0 ? A : A + (float)k * (B + (float)k * kyy);
+                    const float ge = gv[k] * __builtin_amdgcn_exp2f(Q);
+                    s0 += ge;
+                    if (k > 0) {
+                        s1 += (float)k * ge;
+                        s2 += (float)(k * k) * ge;
+                    }
                 }
             }
         }

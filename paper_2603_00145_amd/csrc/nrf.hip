@@ -344,56 +344,111 @@ __global__ __launch_bounds__(256) void k_nrf_chain(const NrfArgs a, NrfWork w)
     }
 }
 
-// Split-K GEMM over points: part[grp][m][n] = sum_{p in grp} L[m][p] R[n][p], with L [M][P]
-// and R [N][P] BF16 (M, N multiples of 16, P a multiple of 16).  One block per (16 x 16 output
-// tile, group of 4 GP points): each wavefront accumulates the tile over its GP points on MFMA,
-// then the four tiles are added in LDS in a fixed order.
-constexpr int GP = 4096;
+// Split-K GEMM over points: part[blk][m][n] = sum over block blk's points p of L[m][p] R[n][p],
+// L [64][P] and R [N][P] BF16 (N = 16 NT, P a multiple of 16), FP32 accumulation on MFMA.  Each
+// block owns a contiguous range of GPB points and every output tile: per round it stages 64
+// points of all 64 + N rows in LDS (each row's 128 bytes read as one coalesced segment), laid
+// out so that every MFMA operand is 512 contiguous bytes, and wavefront w multiplies output
+// rows 16 w .. 16 w + 15 against all N columns, its A operand loaded once per 16 points.  With
+// rowpart the block also writes the row sums of L over its points (rowpart[blk][64]).
+constexpr int GPB = 1024;   // points per block
+constexpr int GK = 64;      // points per LDS round
 
-__global__ __launch_bounds__(256) void k_gemm_nt_splitk(const uint16_t* __restrict__ L,
-                                                        const uint16_t* __restrict__ R, int M,
-                                                        int N, int64_t P, float* __restrict__ part)
+template <int NT>
+__global__ __launch_bounds__(256) void k_gemm_nt_rows(const uint16_t* __restrict__ L,
+                                                      const uint16_t* __restrict__ R, int64_t P,
+                                                      float* __restrict__ part,
+                                                      float* __restrict__ rowpart)
 {
-    __shared__ float sh[4][256];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, row = lane & 15;
-    const int nt = N / 16;
-    const int tm = blockIdx.x / nt, tn = blockIdx.x % nt;
-    const int64_t p0 = ((int64_t)blockIdx.y * 4 + wave) * GP;
-    const int64_t p1 = min(p0 + GP, P);
-    v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    const uint16_t* lp = L + (int64_t)(16 * tm + row) * P + 4 * g;
-    const uint16_t* rp = R + (int64_t)(16 * tn + row) * P + 4 * g;
-    for (int64_t q = p0; q < p1; q += 16) {
-        const v4s A = *reinterpret_cast<const v4s*>(lp + q);
-        const v4s B = *reinterpret_cast<const v4s*>(rp + q);
-        acc = mfma(A, B, acc);
-    }
-    // acc holds rows 16 tm + 4 g + j, column 16 tn + row
-    sh[wave][lane * 4 + 0] = acc.x;
-    sh[wave][lane * 4 + 1] = acc.y;
-    sh[wave][lane * 4 + 2] = acc.z;
-    sh[wave][lane * 4 + 3] = acc.w;
-    __syncthreads();
-    if (wave == 0) {
-        float* out = part + (int64_t)blockIdx.y * M * N;
-        const int c = 16 * tn + row;
+    constexpr int ROWS = 64 + 16 * NT;
+    constexpr int PER = ROWS * 16 / 256;   // 8-byte segments each thread stages per round
+    static_assert(ROWS * 16 % 256 == 0, "rounds split evenly over the block");
+    __shared__ v4s sl[4 * 4 * 64];     // [row block][16-point step][lane]
+    __shared__ v4s sr[NT * 4 * 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    v4f acc[NT];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int e = lane * 4 + j;
-            out[(16 * tm + 4 * g + j) * N + c] = ((sh[0][e] + sh[1][e]) + sh[2][e]) + sh[3][e];
+    for (int t = 0; t < NT; ++t) acc[t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    const int64_t p0 = (int64_t)blockIdx.x * GPB;
+    const int64_t p1 = min(p0 + (int64_t)GPB, P);
+    // the next round's segments are fetched into registers while this round multiplies
+    v4s nxt[PER];
+    auto fetch = [&](int64_t q0) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = (int)threadIdx.x + i * 256;
+            const int r = e >> 4, c = e & 15;
+            const int64_t q = q0 + 4 * c;
+            const bool isl = r < 64;
+            const uint16_t* src = (isl ? L : R) + (int64_t)(isl ? r : r - 64) * P;
+            nxt[i] = q < p1 ? *reinterpret_cast<const v4s*>(src + q) : v4s{0, 0, 0, 0};
         }
+    };
+    if (p0 < p1) fetch(p0);
+    float rsum = 0.0f;
+    for (int64_t q0 = p0; q0 < p1; q0 += GK) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = (int)threadIdx.x + i * 256;
+            const int r = e >> 4, c = e & 15;
+            const bool isl = r < 64;
+            const int rr = isl ? r : r - 64;
+            const int slot = ((rr >> 4) * 4 + (c >> 2)) * 64 + (rr & 15) + 16 * (c & 3);
+            if (isl)
+                sl[slot] = nxt[i];
+            else
+                sr[slot] = nxt[i];
+        }
+        __syncthreads();
+        if (q0 + GK < p1) fetch(q0 + GK);
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            const v4s a = sl[(w * 4 + st) * 64 + lane];
+            rsum += (from_bf16((uint16_t)a.x) + from_bf16((uint16_t)a.y)) +
+                    (from_bf16((uint16_t)a.z) + from_bf16((uint16_t)a.w));
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[t] = mfma(a, sr[(t * 4 + st) * 64 + lane], acc[t]);
+        }
+    }
+    // row sums of L (the bias gradient when L = dZ): lane (row, g) holds a quarter of row
+    // 16 w + row; the four quarters are added across g
+    rsum += __shfl_xor(rsum, 16, 64);
+    rsum += __shfl_xor(rsum, 32, 64);
+    if (rowpart && lane < 16) rowpart[(int64_t)blockIdx.x * 64 + 16 * w + lane] = rsum;
+    // acc[t] holds output rows 16 w + 4 g + j, column 16 t + (lane & 15)
+    const int g = lane >> 4, col = lane & 15;
+    float* out = part + (int64_t)blockIdx.x * 64 * (16 * NT);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        out[(16 * w + 4 * g + 0) * (16 * NT) + 16 * t + col] = acc[t].x;
+        out[(16 * w + 4 * g + 1) * (16 * NT) + 16 * t + col] = acc[t].y;
+        out[(16 * w + 4 * g + 2) * (16 * NT) + 16 * t + col] = acc[t].z;
+        out[(16 * w + 4 * g + 3) * (16 * NT) + 16 * t + col] = acc[t].w;
     }
 }
 
-// out[e] += sum_c part[c][e]  (fixed order)
+// out[e] += sum_c part[c][e] in a fixed order: 64 elements per block, wavefront w summing
+// chunks w, w + 4, ..., then the four sums added in order
+__device__ __forceinline__ float sum_chunks(const float* __restrict__ part, int64_t nchunk,
+                                            int64_t n, int64_t e)
+{
+    __shared__ float sh[4][64];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    float s = 0.0f;
+    if (e < n)
+        for (int64_t c = w; c < nchunk; c += 4) s += part[c * n + e];
+    sh[w][l] = s;
+    __syncthreads();
+    return ((sh[0][l] + sh[1][l]) + sh[2][l]) + sh[3][l];
+}
+
 __global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ part, int64_t nchunk,
                                                    int64_t n, float* __restrict__ out)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
-    float s = 0.0f;
-    for (int64_t c = 0; c < nchunk; ++c) s += part[c * n + e];
-    out[e] += s;
+    const int64_t e = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+    const float s = sum_chunks(part, nchunk, n, e);
+    if (threadIdx.x < 64 && e < n) out[e] += s;
 }
 
 // The same for the first layer's weights, whose K dimension the GPU holds in its own encoding
@@ -404,12 +459,11 @@ __global__ __launch_bounds__(256) void k_sum_parts_in(const float* __restrict__ 
                                                       float* __restrict__ out)
 {
     constexpr int N = 16 * KT;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= W * N) return;
+    const int e = blockIdx.x * 64 + (threadIdx.x & 63);
+    const float s = sum_chunks(part, nchunk, W * N, e);
+    if (threadIdx.x >= 64 || e >= W * N) return;
     const int m = e / N, nf = natural_feature<KT>(e % N, n_freq);
     if (nf < 0) return;
-    float s = 0.0f;
-    for (int64_t c = 0; c < nchunk; ++c) s += part[c * (W * N) + e];
     out[m * N + nf] += s;
 }
 
@@ -510,13 +564,13 @@ static void rowdot(const uint16_t* L, const float* v, int64_t P, int rows, float
     const int64_t nchunk = (P + RD_CHUNK - 1) / RD_CHUNK;
     hipLaunchKernelGGL(k_rowdot_part, dim3((unsigned)rows, (unsigned)nchunk), dim3(256), 0, s, L,
                        v, P, rows, part);
-    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, part,
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((rows + 63) / 64)), dim3(256), 0, s, part,
                        nchunk, (int64_t)rows, out);
 }
 
 size_t nrf_part_floats(int64_t P, int in_pad)
 {
-    const int64_t gemm = ((P + 4 * GP - 1) / (4 * GP)) * W * (in_pad > W ? in_pad : W);
+    const int64_t gemm = ((P + GPB - 1) / GPB) * W * ((in_pad > W ? in_pad : W) + 1);
     const int64_t rows = W * ((P + RD_CHUNK - 1) / RD_CHUNK);
     return (size_t)(gemm > rows ? gemm : rows);
 }
@@ -525,22 +579,29 @@ hipError_t launch_nrf_backward(const NrfArgs& a, const NrfWork& w, hipStream_t s
 {
     if (a.n_points <= 0) return hipSuccess;
     GM_NRF_DISPATCH(launch_chain_t, a, w, s)
-    const int64_t nchunk = (w.P + 4 * GP - 1) / (4 * GP);
+    const int64_t nchunk = (w.P + GPB - 1) / GPB;
     for (int l = 0; l < a.depth; ++l) {
         const int N = l == 0 ? a.in_pad : W;
         float* dst = l == 0 ? a.g_w_in : a.g_w_hid + (int64_t)(l - 1) * W * W;
         float* dbias = l == 0 ? a.g_b_in : a.g_b_hid + (int64_t)(l - 1) * W;
-        hipLaunchKernelGGL(k_gemm_nt_splitk, dim3((unsigned)((W / 16) * (N / 16)), (unsigned)nchunk),
-                           dim3(256), 0, s, w.dz[l], w.a[l], W, N, w.P, w.part);
+        // block row sums of dZ_l (the bias gradient) after the GEMM partials
+        float* rowpart = w.part + nchunk * W * N;
+        if (N == 128)
+            hipLaunchKernelGGL(k_gemm_nt_rows<8>, dim3((unsigned)nchunk), dim3(256), 0, s, w.dz[l],
+                               w.a[l], w.P, w.part, rowpart);
+        else
+            hipLaunchKernelGGL(k_gemm_nt_rows<4>, dim3((unsigned)nchunk), dim3(256), 0, s, w.dz[l],
+                               w.a[l], w.P, w.part, rowpart);
         const int64_t n = (int64_t)W * N;
-        const dim3 grid((unsigned)((n + 255) / 256));
+        const dim3 grid((unsigned)((n + 63) / 64));
         if (l > 0)
             hipLaunchKernelGGL(k_sum_parts, grid, dim3(256), 0, s, w.part, nchunk, n, dst);
         else if (N == 64)
             hipLaunchKernelGGL(k_sum_parts_in<4>, grid, dim3(256), 0, s, w.part, nchunk, a.n_freq, dst);
         else
             hipLaunchKernelGGL(k_sum_parts_in<8>, grid, dim3(256), 0, s, w.part, nchunk, a.n_freq, dst);
-        rowdot(w.dz[l], nullptr, w.P, W, w.part, dbias, s);
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, rowpart, nchunk, (int64_t)W,
+                           dbias);
     }
     rowdot(w.a[a.depth], w.dzo, w.P, W, w.part, a.g_w_out, s);
     rowdot(nullptr, w.dzo, w.P, 1, w.part, a.g_b_out, s);

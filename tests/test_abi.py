@@ -51,3 +51,53 @@ def test_host_only_calls():
     assert tt.value == 1 and sb.value > 0
     assert lib.gm_adam_step(None, None, None, None, 4, 1e-3, 0.9, 0.999, 1e-8, 0, None) == \
         _lib.GM_ERR_INVALID_ARGUMENT
+
+
+def test_host_validation_of_the_extension_entry_points():
+    """Host-side checks of the SSIM, pose, lattice and block-query entry points (they return
+    before anything is launched, so no device is needed)."""
+    from paper_2603_00145_amd import _lib
+    lib = _lib.load()
+    P = ctypes.c_void_p
+    fake = P(0x1000)           # never dereferenced on the host
+    arr = (P * 2)(fake, fake)
+    dims = (ctypes.c_int32 * 6)(8, 8, 2, 8, 8, 2)
+    # SSIM: stack count, lambda, negative dims
+    assert lib.gm_loss_ssim(0, arr, arr, dims, 0.5, arr, fake, fake, None) == _lib.GM_ERR_INVALID_ARGUMENT
+    assert lib.gm_loss_ssim(2, arr, arr, dims, float("nan"), arr, fake, fake, None) == \
+        _lib.GM_ERR_INVALID_ARGUMENT
+    bad = (ctypes.c_int32 * 6)(8, -1, 2, 8, 8, 2)
+    assert lib.gm_loss_ssim(2, arr, arr, bad, 0.5, arr, fake, fake, None) == _lib.GM_ERR_INVALID_ARGUMENT
+    assert b"dims" in lib.gm_last_error()
+    # lattice refinement: sizes and the old lattice's count
+    g = _lib.GmGaussians(27, fake, fake, fake, fake)
+    assert lib.gm_upsample_lattice(0, ctypes.byref(g), 4, fake, fake, fake, fake, None) == \
+        _lib.GM_ERR_INVALID_ARGUMENT
+    assert lib.gm_upsample_lattice(4, ctypes.byref(g), 4, fake, fake, fake, fake, None) == \
+        _lib.GM_ERR_INVALID_ARGUMENT
+    assert b"g_old^3" in lib.gm_last_error()
+    # pose gradient: NULL Gaussians
+    assert lib.gm_grid_pose_grads(None, None, None, 0, fake, fake, 0, None) == \
+        _lib.GM_ERR_INVALID_ARGUMENT
+    # block query: a rotated grid is refused before any launch
+    grid = _lib.GmGrid()
+    grid.nx, grid.ny, grid.nz = 16, 16, 4
+    c, s_ = 0.8, 0.6
+    grid.world_to_index[0], grid.world_to_index[1] = 8 * c, -8 * s_
+    grid.world_to_index[4], grid.world_to_index[5] = 8 * s_, 8 * c
+    grid.world_to_index[10] = 2.0
+    b = _lib.GmBins()
+    b.n_grids, b.n_gauss, b.capacity_pairs = 1, 27, 1000
+    for f in ("records", "tile_count", "box_volume", "tile_start", "pair_gauss", "scratch"):
+        setattr(b, f, 0x1000)
+    b.scratch_bytes = 1 << 30
+    opts = _lib.GmBinOpts(3.0, 2, 8)
+    npairs = ctypes.c_int64()
+    st = lib.gm_bin(ctypes.byref(g), ctypes.byref(grid), 1, ctypes.byref(opts), ctypes.byref(b),
+                    ctypes.byref(npairs), None)
+    assert st == _lib.GM_ERR_UNSUPPORTED
+    assert b"axis-aligned" in lib.gm_last_error()
+    opts = _lib.GmBinOpts(3.0, 2, 0)
+    st = lib.gm_bin(ctypes.byref(g), ctypes.byref(grid), 1, ctypes.byref(opts), ctypes.byref(b),
+                    ctypes.byref(npairs), None)
+    assert st == _lib.GM_ERR_INVALID_ARGUMENT

@@ -66,6 +66,23 @@ def recorded_traffic(kernel):
     return float(fields["traffic_bytes"])
 
 
+def recorded_iters_to_psnr():
+    """The committed warm-start experiment's iterations-to-PSNR on the held-out 256^3
+    phantoms (a separate, longer run; reported beside the throughput, not re-measured)."""
+    import re
+    path = os.path.join(ROOT, "profiles", "warmstart_iters_to_psnr_256.md")
+    if not os.path.exists(path):
+        return None
+    txt = " ".join(open(path).read().split())
+    m = re.search(r"reached the target on (\d+)/(\d+) phantoms; iterations to target: mean "
+                  r"([0-9.]+), median ([0-9.]+) \(plain arm: (\d+)\)", txt)
+    if not m:
+        return None
+    return {"warm_mean": float(m.group(3)), "warm_median": float(m.group(4)),
+            "plain": int(m.group(5)), "reached": f"{m.group(1)}/{m.group(2)}",
+            "source": "profiles/warmstart_iters_to_psnr_256.md"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,6 +221,7 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": recorded_traffic(kname),
                      "flop_per_pair": flop, "avg_kernel_ms": stage_ms[dom]},
         "cpu_baseline": cpu,
+        "iters_to_psnr": recorded_iters_to_psnr(),
     }
     print(json.dumps(out))
 

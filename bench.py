@@ -180,6 +180,7 @@ def main():
         for k, (a, b) in zip(ev, zip(e[:-1], e[1:])):
             ev[k].append(a.elapsed_time(b))
     stage_ms = {k: float(np.mean(x)) for k, x in ev.items()}
+    step_ms = np.array([e[0].elapsed_time(e[-1]) for e in recs])
 
     # contributing (Gaussian, voxel) pairs on the stacks, mean over the timed steps (the
     # Gaussians move, so the count changes from step to step)
@@ -213,6 +214,7 @@ def main():
                    "Gaussians, plain method (smooth-L1 + anisotropy, Adam)",
                    "n_gauss": p.n, "stacks": [list(g.shape) for g in stacks],
                    "tile": list(api._lib.tile_dims())},
+        "ms_per_step_p10_p50_p90": [float(np.percentile(step_ms, q)) for q in (10, 50, 90)],
         "pairs_per_step": pairs, "tile_pairs": tile_pairs,
         "stage_ms": stage_ms, "fwd_evals_per_s": fwd_rate, "bwd_evals_per_s": bwd_rate,
         "fwd_bwd_evals_per_s": pairs / ((stage_ms["render"] + bwd_ms) / 1e3),

@@ -170,6 +170,21 @@ gm_status gm_bin(const gm_gaussians* g, const gm_grid* grids, int32_t n_grids,
 gm_status gm_render_stacks(const gm_bins* bins, const int32_t* grid_ids, int32_t n_ids,
                            float* const* outs, gm_stream stream);
 
+/* Forward rendering fused with the smooth-L1 data term (Eq. 7 and Eq. 11, beta = 1): the
+ * listed grids are rendered as by gm_render_stacks and, while each tile is still on chip,
+ *   dl_di[k][v] = clamp(I_k[v] - targets[k][v], -1, 1) / N   (overwritten),
+ *   *loss (device float) = (1/N) sum over every voxel of smoothL1(I_k[v] - targets[k][v]),
+ * N = voxels of the listed grids; dl_di is bit-identical to gm_render_stacks followed by
+ * gm_loss_smooth_l1, the loss equal up to the order of its FP64 sum.  outs may be NULL (the
+ * rendered stacks are then not stored) or an array whose entries are NULL or [nz][ny][nx]
+ * device buffers that receive the rendering.  targets / dl_di: [host] arrays of n_ids (>= 1)
+ * device pointers to [nz][ny][nx] float32.  workspace: device bytes >= 8 x the tiles of the
+ * listed grids (one FP64 partial per tile).  Bit-deterministic run to run. */
+gm_status gm_render_loss_smooth_l1(const gm_bins* bins, const int32_t* grid_ids, int32_t n_ids,
+                                   const float* const* targets, float* const* outs,
+                                   float* const* dl_di, float* loss, void* workspace,
+                                   size_t workspace_bytes, gm_stream stream);
+
 /* Neural residual field parameters for the fused volume epilogue (Eq. 8).  Weights are
  * bf16 stored as uint16 bit patterns, row-major [out][in]; biases float32.
  * n_freq frequency bands: input features (x, sin(2^k pi x), cos(2^k pi x)), k < n_freq,

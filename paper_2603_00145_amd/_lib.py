@@ -93,6 +93,9 @@ _SIGS = [
                                ctypes.POINTER(GmBins), ctypes.POINTER(ctypes.c_int64), P]),
     ("gm_render_stacks", ctypes.c_int, [ctypes.POINTER(GmBins), ctypes.POINTER(ctypes.c_int32),
                                          ctypes.c_int32, ctypes.POINTER(P), P]),
+    ("gm_render_loss_smooth_l1", ctypes.c_int,
+     [ctypes.POINTER(GmBins), ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.POINTER(P),
+      ctypes.POINTER(P), ctypes.POINTER(P), P, P, ctypes.c_size_t, P]),
     ("gm_render_volume", ctypes.c_int, [ctypes.POINTER(GmBins), ctypes.c_int32,
                                          ctypes.POINTER(GmNrf), P, P]),
     ("gm_loss_smooth_l1", ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(P),

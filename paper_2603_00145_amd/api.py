@@ -49,9 +49,31 @@ class GaussParams:
         return GaussParams(*(torch.from_numpy(np.ascontiguousarray(getattr(g, k), np.float32))
                              .to(device) for k in ("mean", "quat", "log_scale", "logit")))
 
+    # set by zeros_like: the one buffer the four tensors are views of
+    flat: Optional[torch.Tensor] = dataclasses.field(default=None, repr=False, compare=False)
+
     @staticmethod
     def zeros_like(p: "GaussParams") -> "GaussParams":
-        return GaussParams(*(torch.zeros_like(t) for t in p.tensors()))
+        """Zeroed tensors of p's shapes, laid out back to back in one buffer so that
+        zero_() clears them with a single fill."""
+        # each tensor starts on a 256-byte boundary (the kernels read quaternions as float4)
+        sizes = [t.numel() for t in p.tensors()]
+        starts = []
+        o = 0
+        for k in sizes:
+            starts.append(o)
+            o += -(-k // 64) * 64
+        flat = torch.zeros(max(o, 1), dtype=torch.float32, device=p.mean.device)
+        views = [flat[a:a + k].view(t.shape) for a, k, t in zip(starts, sizes, p.tensors())]
+        return GaussParams(*views, flat=flat)
+
+    def zero_(self):
+        if self.flat is not None:
+            self.flat.zero_()
+        else:
+            for t in self.tensors():
+                t.zero_()
+        return self
 
     def tensors(self):
         return (self.mean, self.quat, self.log_scale, self.logit)
@@ -108,6 +130,8 @@ class Bins:
         self.box_volume = torch.zeros(max(G, 2), dtype=torch.int64, device=dev)
         self.tile_start = torch.empty(self.total_tiles + 1, dtype=torch.int32, device=dev)
         self.grid_grads = torch.empty((G, max(self.n, 1), 10), dtype=torch.float32, device=dev)
+        # one FP64 loss partial per tile for the fused render + loss
+        self.loss_part = torch.empty(max(self.total_tiles, 1), dtype=torch.float64, device=dev)
         self.capacity = 0
         self.pair_gauss = None
         self.scratch = None
@@ -209,6 +233,32 @@ def render(bins: Bins, ids: Sequence[int], outs: Optional[List[torch.Tensor]] = 
     check(load().gm_render_stacks(ctypes.byref(bins.struct()), idarr, len(ids),
                                   ptr_array([t.data_ptr() for t in outs]), _stream()))
     return outs
+
+
+def render_loss(bins: Bins, ids: Sequence[int], targets: Sequence[torch.Tensor],
+                dl_di: Optional[List[torch.Tensor]] = None,
+                outs: Optional[List[torch.Tensor]] = None):
+    """gm_render_loss_smooth_l1: renders the listed grids and forms the smooth-L1 term in the
+    same pass; returns (loss device scalar, dL/dI per stack).  The renderings are stored only
+    when outs is given."""
+    if dl_di is None:
+        dl_di = [torch.empty_like(t) for t in targets]
+    for t in list(targets) + list(dl_di) + list(outs or []):
+        _need(t, torch.float32, "render-loss operand")
+    for i, t, d in zip(ids, targets, dl_di):
+        shp = tuple(bins.grids[i].shape)
+        if tuple(t.shape) != shp or tuple(d.shape) != shp:
+            raise ValueError(f"grid {i}: target / dl_di shape differs from {shp}")
+    if outs is not None and len(outs) != len(ids):
+        raise ValueError("outs must hold one tensor per listed grid")
+    loss = torch.empty(4, dtype=torch.float32, device=bins.device)
+    idarr = (ctypes.c_int32 * max(1, len(ids)))(*ids)
+    out_arr = None if outs is None else ptr_array([t.data_ptr() for t in outs])
+    check(load().gm_render_loss_smooth_l1(
+        ctypes.byref(bins.struct()), idarr, len(ids), ptr_array([t.data_ptr() for t in targets]),
+        out_arr, ptr_array([d.data_ptr() for d in dl_di]), _p(loss), _p(bins.loss_part),
+        bins.loss_part.numel() * 8, _stream()))
+    return loss[0], dl_di
 
 
 def render_volume(bins: Bins, grid_id: int, out: Optional[torch.Tensor] = None, nrf=None):

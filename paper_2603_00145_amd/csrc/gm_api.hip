@@ -485,20 +485,45 @@ gm_status gm_bin(const gm_gaussians* g, const gm_grid* grids, int32_t n_grids,
     return GM_OK;
 }
 
+// The loss fields (targets, dl, loss) are NULL for a plain render; with them the render also
+// writes the smooth-L1 gradient and loss, and outs (the array or an entry) may be NULL.
+struct RenderLoss {
+    const float* const* targets;
+    float* const* dl;
+    float* loss;
+    void* ws;
+    size_t ws_bytes;
+};
+
 static gm_status render_impl(const gm_bins* bins, const int32_t* ids, int32_t n_ids,
-                             float* const* outs, hipStream_t s)
+                             float* const* outs, const RenderLoss* lo, hipStream_t s)
 {
     gm_status st = check_bins(bins, true);
     if (st != GM_OK) return st;
     st = check_ids(bins, ids, n_ids);
     if (st != GM_OK) return st;
-    if (n_ids > 0 && !outs) return fail(GM_ERR_INVALID_ARGUMENT, "outs is NULL");
+    if (n_ids > 0 && !outs && !lo) return fail(GM_ERR_INVALID_ARGUMENT, "outs is NULL");
+    if (lo) {
+        if (n_ids < 1) return fail(GM_ERR_INVALID_ARGUMENT, "n_ids must be >= 1");
+        if (!lo->targets || !lo->dl) return fail(GM_ERR_INVALID_ARGUMENT, "NULL array argument");
+        REQ_PTR(lo->loss, "loss");
+    }
     RenderArgs ra;
     memset(&ra, 0, sizeof ra);
-    int64_t blocks = 0;
+    int64_t blocks = 0, voxels = 0;
     for (int k = 0; k < n_ids; ++k) {
-        REQ_PTR(outs[k], "outs[k]");
         const gm_grid& g = bins->grids[ids[k]];
+        if (lo) {
+            if (grid_tiles(g) > 0) {
+                REQ_PTR(lo->targets[k], "targets[k]");
+                REQ_PTR(lo->dl[k], "dl_di[k]");
+            }
+            ra.rg[k].target = lo->targets[k];
+            ra.rg[k].dl = lo->dl[k];
+            voxels += (int64_t)g.nx * g.ny * g.nz;
+        } else {
+            REQ_PTR(outs[k], "outs[k]");
+        }
         RenderGrid& r = ra.rg[k];
         r.nx = g.nx;
         r.ny = g.ny;
@@ -509,10 +534,23 @@ static gm_status render_impl(const gm_bins* bins, const int32_t* ids, int32_t n_
         r.grid_index = ids[k];
         r.first_block = (int32_t)blocks;
         r.bin_tile_base = bins->tile_base[ids[k]];
-        r.out = outs[k];
+        r.out = outs ? outs[k] : nullptr;
         blocks += grid_tiles(g);
     }
     if (blocks >= 0x7fffffffLL) return fail(GM_ERR_INVALID_ARGUMENT, "too many tiles");
+    if (lo) {
+        if (lo->ws_bytes < (size_t)blocks * sizeof(double))
+            return fail(GM_ERR_INVALID_ARGUMENT, "workspace_bytes %zu < %lld (8 per tile)",
+                        lo->ws_bytes, (long long)blocks * (long long)sizeof(double));
+        if (blocks > 0) REQ_PTR(lo->ws, "workspace");
+        ra.loss_part = reinterpret_cast<double*>(lo->ws);
+        ra.loss = lo->loss;
+        ra.inv_n = voxels > 0 ? 1.0 / (double)voxels : 0.0;
+        if (blocks == 0) {
+            GM_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(lo->loss), 0u, 1, s), "zero loss");
+            return GM_OK;
+        }
+    }
     if (blocks == 0) return GM_OK;
     if (bins->n_gauss > 0) REQ_PTR(bins->records, "bins->records");
     REQ_PTR(bins->tile_start, "bins->tile_start");
@@ -530,7 +568,17 @@ gm_status gm_render_stacks(const gm_bins* bins, const int32_t* grid_ids, int32_t
                            float* const* outs, gm_stream stream)
 {
     g_err.clear();
-    return render_impl(bins, grid_ids, n_ids, outs, reinterpret_cast<hipStream_t>(stream));
+    return render_impl(bins, grid_ids, n_ids, outs, nullptr, reinterpret_cast<hipStream_t>(stream));
+}
+
+gm_status gm_render_loss_smooth_l1(const gm_bins* bins, const int32_t* grid_ids, int32_t n_ids,
+                                   const float* const* targets, float* const* outs,
+                                   float* const* dl_di, float* loss, void* workspace,
+                                   size_t workspace_bytes, gm_stream stream)
+{
+    g_err.clear();
+    const RenderLoss lo{targets, dl_di, loss, workspace, workspace_bytes};
+    return render_impl(bins, grid_ids, n_ids, outs, &lo, reinterpret_cast<hipStream_t>(stream));
 }
 
 gm_status gm_render_volume(const gm_bins* bins, int32_t grid_id, const gm_nrf* nrf, float* out,
@@ -542,7 +590,8 @@ gm_status gm_render_volume(const gm_bins* bins, int32_t grid_id, const gm_nrf* n
         if (st != GM_OK) return st;
     }
     float* outs[1] = {out};
-    gm_status st = render_impl(bins, &grid_id, 1, outs, reinterpret_cast<hipStream_t>(stream));
+    gm_status st = render_impl(bins, &grid_id, 1, outs, nullptr,
+                               reinterpret_cast<hipStream_t>(stream));
     if (st != GM_OK || !nrf) return st;
     return gm_nrf_forward(nrf, &bins->grids[grid_id], out, stream);
 }

@@ -95,7 +95,9 @@ struct RenderGrid {
     int32_t grid_index;      // index into the binned grids (records)
     int32_t first_block;     // first flattened tile of this grid in the launch
     int64_t bin_tile_base;   // global tile id of the grid's first tile in the binning
-    float* out;
+    float* out;              // rendered values, or NULL (loss mode only)
+    const float* target;     // loss mode: the stack's data
+    float* dl;               // loss mode: dL/dI of the smooth-L1 term
 };
 struct RenderArgs {
     int32_t n_render;
@@ -104,6 +106,9 @@ struct RenderArgs {
     const float* records;
     const int32_t* tile_start;
     const int32_t* pair_gauss;
+    double* loss_part;       // loss mode (non-NULL): per-block smooth-L1 sums [total_blocks]
+    float* loss;             // loss mode: the mean, written by the finishing kernel
+    double inv_n;            // loss mode: 1 / voxels of the listed grids
     RenderGrid rg[GM_MAX_GRIDS];
 };
 hipError_t launch_render(const RenderArgs& a, hipStream_t s);

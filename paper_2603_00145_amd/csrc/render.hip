@@ -126,7 +126,24 @@ __global__ __launch_bounds__(64) void k_render(const RenderArgs a)
     const int* __restrict__ pg = a.pair_gauss;
 
 #pragma unroll
-    for (int i = lane; i < GM_TILE_VOX; i += 64) acc[i] = 0.0f;
+    for (int j = 0; j < GM_TILE_VOX / 64; ++j) acc[j * 64 + lane] = 0.0f;
+
+    // loss mode: the tile's data values are loaded now, so that their latency is hidden
+    // behind the accumulation
+    constexpr int VPL = GM_TILE_VOX / 64;
+    float tv[VPL];
+    if (a.loss_part) {
+#pragma unroll
+        for (int j = 0; j < VPL; ++j) {
+            const int i = j * 64 + lane;
+            const int x = i % GM_TX, y = (i / GM_TX) % GM_TY, z = i / (GM_TX * GM_TY);
+            const int gx = t0x + x, gy = t0y + y, gz = t0z + z;
+            // outside the grid: a valid address (voxel 0) whose value goes unused
+            const bool in = (gx < G.nx) & (gy < G.ny) & (gz < G.nz);
+            const size_t v = in ? ((size_t)gz * G.ny + gy) * G.nx + gx : 0;
+            tv[j] = __builtin_nontemporal_load(G.target + v);
+        }
+    }
 
     const int64_t bt = G.bin_tile_base + lt;
     const int s = sgpr(a.tile_start[bt]);
@@ -205,13 +222,66 @@ __global__ __launch_bounds__(64) void k_render(const RenderArgs a)
     }
     __syncthreads();
     float* out = G.out;
+    if (!a.loss_part) {
 #pragma unroll
-    for (int i = lane; i < GM_TILE_VOX; i += 64) {
+        for (int j = 0; j < GM_TILE_VOX / 64; ++j) {
+            const int i = j * 64 + lane;
+            const int x = i % GM_TX, y = (i / GM_TX) % GM_TY, z = i / (GM_TX * GM_TY);
+            const int gx = t0x + x, gy = t0y + y, gz = t0z + z;
+            if ((gx < G.nx) & (gy < G.ny) & (gz < G.nz))
+                out[((size_t)gz * G.ny + gy) * G.nx + gx] = acc[i];
+        }
+        return;
+    }
+    // the smooth-L1 data term (Eq. 11, beta = 1) on the tile: dL/dI = clamp(I - y, -1, 1) / N
+    // and the tile's sum of smoothL1(I - y), FP64
+    const float g_scale = (float)a.inv_n;
+    double lsum = 0.0;
+#pragma unroll
+    for (int j = 0; j < GM_TILE_VOX / 64; ++j) {
+        const int i = j * 64 + lane;
         const int x = i % GM_TX, y = (i / GM_TX) % GM_TY, z = i / (GM_TX * GM_TY);
         const int gx = t0x + x, gy = t0y + y, gz = t0z + z;
-        if (gx < G.nx && gy < G.ny && gz < G.nz)
-            out[((size_t)gz * G.ny + gy) * G.nx + gx] = acc[i];
+        if ((gx < G.nx) & (gy < G.ny) & (gz < G.nz)) {
+            const size_t v = ((size_t)gz * G.ny + gy) * G.nx + gx;
+            const float val = acc[i];
+            if (out) out[v] = val;
+            const float d = val - tv[j];
+            const float ad = fabsf(d);
+            lsum += ad < 1.0f ? 0.5 * (double)d * (double)d : (double)ad - 0.5;
+            G.dl[v] = fminf(fmaxf(d, -1.0f), 1.0f) * g_scale;
+        }
     }
+    for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
+    if (lane == 0) a.loss_part[blk] = lsum;
+}
+
+// loss = inv_n * sum of the per-block sums, in a fixed order.  Each thread takes four
+// partials per round (all four loads in flight), then a tree over the block.
+constexpr int FIN_THREADS = 1024;
+
+__global__ __launch_bounds__(FIN_THREADS) void k_render_loss_finish(const double* part, int nb,
+                                                                    double inv_n, float* loss)
+{
+    __shared__ double sh[FIN_THREADS];
+    const int t = threadIdx.x;
+    double v = 0.0;
+    for (int i = t; i < nb; i += 4 * FIN_THREADS) {
+        double q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = i + u * FIN_THREADS;
+            q[u] = k < nb ? part[k] : 0.0;
+        }
+        v += (q[0] + q[1]) + (q[2] + q[3]);
+    }
+    sh[t] = v;
+    __syncthreads();
+    for (int o = FIN_THREADS / 2; o > 0; o >>= 1) {
+        if (t < o) sh[t] += sh[t + o];
+        __syncthreads();
+    }
+    if (t == 0) *loss = (float)(sh[0] * inv_n);
 }
 
 }  // namespace
@@ -220,5 +290,8 @@ hipError_t launch_render(const RenderArgs& a, hipStream_t s)
 {
     if (a.total_blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_render, dim3((unsigned)a.total_blocks), dim3(64), 0, s, a);
+    if (a.loss_part)
+        hipLaunchKernelGGL(k_render_loss_finish, dim3(1), dim3(FIN_THREADS), 0, s, a.loss_part,
+                           a.total_blocks, a.inv_n, a.loss);
     return hipGetLastError();
 }

@@ -110,16 +110,20 @@ class Reconstruction:
         if self.poses is not None:
             self.bins.set_grids([q.grid() for q in self.poses])
         self.bins.bin(self.p)
-        api.render(self.bins, self.ids, self.outs)
         if self.nrf_on:
+            api.render(self.bins, self.ids, self.outs)
             for k, s in enumerate(self.stacks):
                 c.nrf.forward_add(s, self.outs[k])
-        loss, _ = api.smooth_l1(self.outs, self.targets, self.dls)
+            loss, _ = api.smooth_l1(self.outs, self.targets, self.dls)
+        else:
+            # the loss is formed in the render's epilogue; the renderings are stored only
+            # when the SSIM term reads them
+            loss, _ = api.render_loss(self.bins, self.ids, self.targets, self.dls,
+                                      outs=self.outs if c.lambda_ssim > 0 else None)
         if c.lambda_ssim > 0:
             loss = loss + c.lambda_ssim * api.ssim_loss(self.outs, self.targets, self.dls,
                                                         c.lambda_ssim)
-        for t in self.g.tensors():
-            t.zero_()
+        self.g.zero_()
         api.backward(self.p, self.bins, self.ids, self.dls, self.g, c.lambda_aniso, c.lambda_r)
         if self.poses is not None:
             G = api.pose_grads(self.p, self.bins, self.ids).cpu().numpy()

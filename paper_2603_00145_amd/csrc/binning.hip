@@ -82,23 +82,44 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(const int32_t* in, 
                                                               const int64_t* part,
                                                               int64_t* out)
 {
-    // each thread owns SCAN_ITEMS consecutive elements of the block's chunk
+    // each thread owns SCAN_ITEMS consecutive elements of the block's chunk, moved with
+    // 16-byte loads and stores where the chunk is whole and the buffers are aligned
+    static_assert(SCAN_ITEMS == 8, "vector path moves 8 elements per thread");
     const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_ITEMS;
+    const bool vec = base + SCAN_ITEMS <= n && ((uintptr_t)in & 31u) == 0 &&
+                     ((uintptr_t)out & 15u) == 0;
     int32_t v[SCAN_ITEMS];
+    if (vec) {
+        const int4 a = *reinterpret_cast<const int4*>(in + base);
+        const int4 b = *reinterpret_cast<const int4*>(in + base + 4);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k) {
+            const int64_t i = base + k;
+            v[k] = i < n ? in[i] : 0;
+        }
+    }
     int64_t s = 0;
 #pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        const int64_t i = base + k;
-        v[k] = i < n ? in[i] : 0;
-        s += v[k];
-    }
+    for (int k = 0; k < SCAN_ITEMS; ++k) s += v[k];
     int64_t tot;
     int64_t run = block_exclusive_scan(s, &tot) + part[blockIdx.x];
+    int64_t r[SCAN_ITEMS];
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) {
-        const int64_t i = base + k;
-        if (i < n) out[i] = run;
+        r[k] = run;
         run += v[k];
+    }
+    if (vec) {
+        longlong2* o = reinterpret_cast<longlong2*>(out + base);
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS / 2; ++k) o[k] = make_longlong2(r[2 * k], r[2 * k + 1]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k)
+            if (base + k < n) out[base + k] = r[k];
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_THREADS - 1) out[n] = run;
 }
@@ -109,19 +130,20 @@ __global__ __launch_bounds__(256) void k_emit(const EmitArgs a)
     const int64_t total = (int64_t)a.n_grids * a.n;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
-    const int cnt = a.tile_count[idx];
-    if (cnt == 0) return;
+    const uint32_t* tb = a.tile_box + idx * 3;
+    const uint32_t b0 = tb[0], b1 = tb[1], b2 = tb[2];
+    const int lx = (int)(b0 & 0xffffu), ly = (int)(b0 >> 16), lz = (int)(b1 & 0xffffu);
+    const int hx = (int)(b1 >> 16), hy = (int)(b2 & 0xffffu), hz = (int)(b2 >> 16);
+    if (hx < lx || hy < ly || hz < lz) return;  // empty box: no tile
     const int k = (int)(idx / a.n);
     const uint32_t gid = (uint32_t)(idx - (int64_t)k * a.n);
     const GridConst& G = a.g[k];
-    const int* rec = reinterpret_cast<const int*>(a.records + idx * 16);
-    const int lx = rec[10], ly = rec[11], lz = rec[12], hx = rec[13], hy = rec[14], hz = rec[15];
     int64_t o = a.offsets[idx];
     // the first tile emitted holds the box's lower corner: its entry carries GM_HOME_BIT
     uint32_t home = GM_HOME_BIT;
-    for (int tz = lz / GM_TZ; tz <= hz / GM_TZ; ++tz)
-        for (int ty = ly / GM_TY; ty <= hy / GM_TY; ++ty)
-            for (int tx = lx / GM_TX; tx <= hx / GM_TX; ++tx) {
+    for (int tz = lz; tz <= hz; ++tz)
+        for (int ty = ly; ty <= hy; ++ty)
+            for (int tx = lx; tx <= hx; ++tx) {
                 a.keys[o] = (uint32_t)(G.tile_base + ((int64_t)tz * G.nty + ty) * G.ntx + tx);
                 a.vals[o] = gid | home;
                 home = 0u;

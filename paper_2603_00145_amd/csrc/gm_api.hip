@@ -113,6 +113,7 @@ struct BinScratch {
     uint32_t* vals0;
     void* radix_ws;
     BinReport* report;
+    uint32_t* tile_box;  // [n_grids * n][3]
     size_t bytes;
 };
 
@@ -130,6 +131,7 @@ BinScratch scratch_layout(char* base, int64_t n, int32_t n_grids, int64_t cap)
     s.vals0 = reinterpret_cast<uint32_t*>(take((size_t)c * 4));
     s.radix_ws = take(radix_workspace_bytes(c));
     s.report = reinterpret_cast<BinReport*>(take(sizeof(BinReport)));
+    s.tile_box = reinterpret_cast<uint32_t*>(take((size_t)(m > 0 ? m : 1) * 12));
     s.bytes = o;
     return s;
 }
@@ -429,6 +431,7 @@ gm_status gm_bin(const gm_gaussians* g, const gm_grid* grids, int32_t n_grids,
     pa.box_volume = sc.report->box_volume;
     pa.flags = sc.report->flags;
     pa.grid_grads = bins->grid_grads;
+    pa.tile_box = sc.tile_box;
     GM_HIP(launch_preprocess(pa, s), "preprocess");
     GM_HIP(launch_scan_i32_to_i64(bins->tile_count, sc.offsets, m, sc.scan_ws, s), "scan");
 
@@ -461,8 +464,7 @@ gm_status gm_bin(const gm_gaussians* g, const gm_grid* grids, int32_t n_grids,
         memset(&ea, 0, sizeof ea);
         ea.n = n;
         ea.n_grids = n_grids;
-        ea.records = bins->records;
-        ea.tile_count = bins->tile_count;
+        ea.tile_box = sc.tile_box;
         ea.offsets = sc.offsets;
         ea.keys = k_in;
         ea.vals = v_in;

@@ -59,6 +59,8 @@ struct PreprocessArgs {
     unsigned long long* box_volume;  // [n_grids]
     uint32_t* flags;         // bit 0: invalid parameter seen; bit 1: block box not settled
     float* grid_grads;       // [n_grids][n][10] or NULL: zeroed for empty boxes
+    uint32_t* tile_box;      // [n_grids][n][3]: the box's tile range (lo, hi) as 16-bit
+                             // fields x | y << 16, z | X << 16, Y | Z << 16 (lo > hi: empty)
     GridConst g[GM_MAX_GRIDS];
 };
 hipError_t launch_preprocess(const PreprocessArgs& a, hipStream_t s);
@@ -71,8 +73,7 @@ hipError_t launch_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, vo
 struct EmitArgs {
     int64_t n;
     int32_t n_grids;
-    const float* records;
-    const int32_t* tile_count;
+    const uint32_t* tile_box;  // [n_grids * n][3], as written by the preprocess
     const int64_t* offsets;  // [n_grids * n + 1]
     uint32_t* keys;
     uint32_t* vals;

@@ -222,6 +222,20 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a)
                       (unsigned long long)(hi[2] - lo[2] + 1);
             }
             a.tile_count[(size_t)k * a.n + i] = cnt;
+            {
+                // the tile range alone, for the pair emission (which then need not read
+                // the 64-byte records); tile indices fit 16 bits for grids of <= 32768
+                uint32_t* tb = a.tile_box + ((size_t)k * a.n + i) * 3;
+                const uint32_t tlx = nonempty ? (uint32_t)(lo[0] / GM_TX) : 1u;
+                const uint32_t tly = nonempty ? (uint32_t)(lo[1] / GM_TY) : 1u;
+                const uint32_t tlz = nonempty ? (uint32_t)(lo[2] / GM_TZ) : 1u;
+                const uint32_t thx = nonempty ? (uint32_t)(hi[0] / GM_TX) : 0u;
+                const uint32_t thy = nonempty ? (uint32_t)(hi[1] / GM_TY) : 0u;
+                const uint32_t thz = nonempty ? (uint32_t)(hi[2] / GM_TZ) : 0u;
+                tb[0] = tlx | (tly << 16);
+                tb[1] = tlz | (thx << 16);
+                tb[2] = thy | (thz << 16);
+            }
             if (vol) atomicAdd(&s_vol[k], vol);
             // the backward visits only Gaussians listed in some tile: the grid-frame
             // partials of an empty box are its zeros, written here

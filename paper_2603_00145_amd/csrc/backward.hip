@@ -67,6 +67,7 @@ __device__ __forceinline__ int group_min(int v)
 constexpr int RX = GM_TX + 8, RY = GM_TY + 8, RZ = GM_TZ + 8;
 constexpr int RZS = RX * RY + 8;
 constexpr int BWD_G = 8;   // lanes per Gaussian in the backward
+constexpr int NCLS = 8;    // size classes the backward groups Gaussians by
 static_assert(RZS % 32 == 8, "z-plane stride must be 8 mod 32 banks");
 
 // Column sums s0 = sum ge, s1 = sum k ge, s2 = sum k^2 ge (ge = g 2^Q_k) over the first NK
@@ -342,25 +343,46 @@ __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
         }
     }
     __syncthreads();
+    // per wavefront: its window's Gaussians served from LDS, in size-class order
+    __shared__ uint32_t order[4][64];
+    const int wv = threadIdx.x >> 6;
+    const int grp = lane / BWD_G;
 #pragma unroll 1
-    for (int w0 = e0 + (int)(threadIdx.x >> 6) * 64; w0 < e1; w0 += 256) {
+    for (int w0 = e0 + wv * 64; w0 < e1; w0 += 256) {
         const int entry = w0 + lane;
         const uint32_t v = entry < e1 ? a.pair_gauss[entry] : 0u;
         const bool home = entry < e1 && (v & GM_HOME_BIT);
         // a home box starts inside the tile; it fits the region unless it reaches past the halo
         bool fits = false;
+        int cls = NCLS;
         if (home) {
             const int* rc = reinterpret_cast<const int*>(
                 a.records + ((size_t)gi * a.n + min((int64_t)(v & GM_ID_MASK), a.n - 1)) * 16);
-            fits = rc[13] - t0x < RX && rc[14] - t0y < RY && rc[15] - t0z < RZ;
+            const int lx = rc[10], ly = rc[11], lz = rc[12], hx = rc[13], hy = rc[14], hz = rc[15];
+            fits = hx - t0x < RX && hy - t0y < RY && hz - t0z < RZ;
+            // size class: column chunks (1, 2, 3, 4+) x (y length above 6), so that the eight
+            // Gaussians a wavefront takes at once have similar loop trips
+            const int chunks = ((hx - lx + 1) * (hz - lz + 1) + BWD_G - 1) / BWD_G;
+            if (fits) cls = (min(chunks, 4) - 1) * 2 + (hy - ly + 1 > 6 ? 1 : 0);
         }
-        uint64_t in_lds = __ballot(home && fits);
+        // rank of each such Gaussian in (class, list) order; the result of a Gaussian does not
+        // depend on when it is taken
+        int rank = 0, n_lds = 0;
+#pragma unroll
+        for (int c = 0; c < NCLS; ++c) {
+            const uint64_t mc = __ballot(cls == c);
+            if (cls == c)
+                rank = n_lds + (int)__builtin_amdgcn_mbcnt_hi(
+                                   (uint32_t)(mc >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mc, 0u));
+            n_lds += __popcll(mc);
+        }
+        if (cls < NCLS) order[wv][rank] = v;
         uint64_t in_global = __ballot(home && !fits);
 #pragma unroll 1
-        while (in_lds) {
-            uint32_t mine;
-            bool valid;
-            take_group<BWD_G>(in_lds, v, mine, valid);
+        for (int r0 = 0; r0 < n_lds; r0 += 64 / BWD_G) {
+            const int ix = r0 + grp;
+            const bool valid = ix < n_lds;
+            const uint32_t mine = valid ? order[wv][ix] : 0u;
             group_of_gaussians<BWD_G, true>(a, kk, mine, valid, region, t0x, t0y, t0z);
         }
 #pragma unroll 1

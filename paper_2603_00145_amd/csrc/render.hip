@@ -80,12 +80,10 @@ __device__ __forceinline__ void single_piece(const Piece& p, float* acc, int F, 
 #pragma unroll 1
     for (int f0 = 0; f0 < F; f0 += 64) {
         const uint32_t f = (uint32_t)(f0 + lane);
-        if (f < (uint32_t)F) {
-            float w[KM];
-            int idx;
-            eval_column<KM>(p, f, w, idx);
-            add_column<KM>(acc, idx, w, KM);
-        }
+        float w[KM];
+        int idx;
+        eval_column<KM>(p, f, w, idx);
+        if (f < (uint32_t)F) add_column<KM>(acc, idx, w, KM);
     }
 }
 
@@ -95,9 +93,11 @@ template <int KM>
 __device__ __forceinline__ void paired_pieces(const Piece& p, float* acc, bool act, bool first,
                                               uint32_t f, int wza, int wzb)
 {
+    // every lane evaluates (a lane past its piece's footprint computes values it never
+    // stores), so no lane mask is needed around the evaluation
     float w[KM];
-    int idx = 0;
-    if (act) eval_column<KM>(p, f, w, idx);
+    int idx;
+    eval_column<KM>(p, f, w, idx);
     lds_order();
     if (act && first) add_column<KM>(acc, idx, w, wza);
     lds_order();

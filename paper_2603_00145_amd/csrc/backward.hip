@@ -67,7 +67,9 @@ __device__ __forceinline__ int group_min(int v)
 constexpr int RX = GM_TX + 8, RY = GM_TY + 8, RZ = GM_TZ + 8;
 constexpr int RZS = RX * RY + 8;
 constexpr int BWD_G = 8;   // lanes per Gaussian in the backward
-constexpr int NCLS = 8;    // size classes the backward groups Gaussians by
+constexpr int NCLS = 8;    // size classes of boxes inside the staged region
+constexpr int NSLOT = NCLS + 1;  // ... and one class for boxes reaching past it
+constexpr int WIN = 128;   // list entries a wavefront sorts and takes at a time
 static_assert(RZS % 32 == 8, "z-plane stride must be 8 mod 32 banks");
 
 // Column sums s0 = sum ge, s1 = sum k ge, s2 = sum k^2 ge (ge = g 2^Q_k) over the first NK
@@ -265,30 +267,8 @@ __device__ __forceinline__ void group_of_gaussians(const BackwardArgs& a, int kk
     }
 }
 
-// Takes the next (up to) 64/G Gaussians of `todo` (bit i = entry i of the wave's 64, whose
-// id is in v), one per group of G lanes.
-template <int G>
-__device__ __forceinline__ void take_group(uint64_t& todo, uint32_t v, uint32_t& mine, bool& valid)
-{
-    const int grp = (threadIdx.x & 63) / G;
-    mine = 0u;
-    valid = false;
-#pragma unroll
-    for (int r = 0; r < 64 / G; ++r) {
-        if (todo) {
-            const int ib = __builtin_ctzll(todo);
-            todo &= todo - 1;
-            const uint32_t vb = __builtin_amdgcn_readlane(v, ib);
-            if (grp == r) {
-                mine = vb;
-                valid = true;
-            }
-        }
-    }
-}
-
 // One block (four wavefronts) per tile of a listed grid.  The block stages the tile's dL/dI
-// region in LDS (coalesced rows), then its wavefronts take the tile's list 64 entries at a
+// region in LDS (coalesced rows), then its wavefronts take the tile's list WIN entries at a
 // time and process the Gaussians whose home entry (the tile holding the box's lower corner) is
 // among them: every Gaussian of the grid exactly once, each from LDS when its box lies inside
 // the region (the common case) and from global memory otherwise.  Gaussians with an empty box
@@ -343,53 +323,64 @@ __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
         }
     }
     __syncthreads();
-    // per wavefront: its window's Gaussians served from LDS, in size-class order
-    __shared__ uint32_t order[4][64];
+    // Each wavefront takes windows of WIN list entries (two per lane) and sorts the windows'
+    // home Gaussians by size class in LDS with ballots (stable: (class, list position)), then
+    // takes them eight at a time, so that the eight Gaussians of a wavefront have similar
+    // loop trips.  A Gaussian's result does not depend on which others share its wavefront.
+    __shared__ uint32_t order[4][WIN];
     const int wv = threadIdx.x >> 6;
     const int grp = lane / BWD_G;
+    // class of a list entry: 0..NCLS-1 a home box inside the staged region (column chunks 1,
+    // 2, 3, 4+ x y length above 6), NCLS a home box reaching past it, NSLOT not a home entry
+    auto entry_class = [&](int entry, uint32_t& v) -> int {
+        v = entry < e1 ? a.pair_gauss[entry] : 0u;
+        if (entry >= e1 || !(v & GM_HOME_BIT)) return NSLOT;
+        const int* rc = reinterpret_cast<const int*>(
+            a.records + ((size_t)gi * a.n + min((int64_t)(v & GM_ID_MASK), a.n - 1)) * 16);
+        const int lx = rc[10], ly = rc[11], lz = rc[12], hx = rc[13], hy = rc[14], hz = rc[15];
+        if (!(hx - t0x < RX && hy - t0y < RY && hz - t0z < RZ)) return NCLS;
+        const int chunks = ((hx - lx + 1) * (hz - lz + 1) + BWD_G - 1) / BWD_G;
+        return (min(chunks, 4) - 1) * 2 + (hy - ly + 1 > 6 ? 1 : 0);
+    };
+    constexpr int EPL = WIN / 64;  // entries per lane
 #pragma unroll 1
-    for (int w0 = e0 + wv * 64; w0 < e1; w0 += 256) {
-        const int entry = w0 + lane;
-        const uint32_t v = entry < e1 ? a.pair_gauss[entry] : 0u;
-        const bool home = entry < e1 && (v & GM_HOME_BIT);
-        // a home box starts inside the tile; it fits the region unless it reaches past the halo
-        bool fits = false;
-        int cls = NCLS;
-        if (home) {
-            const int* rc = reinterpret_cast<const int*>(
-                a.records + ((size_t)gi * a.n + min((int64_t)(v & GM_ID_MASK), a.n - 1)) * 16);
-            const int lx = rc[10], ly = rc[11], lz = rc[12], hx = rc[13], hy = rc[14], hz = rc[15];
-            fits = hx - t0x < RX && hy - t0y < RY && hz - t0z < RZ;
-            // size class: column chunks (1, 2, 3, 4+) x (y length above 6), so that the eight
-            // Gaussians a wavefront takes at once have similar loop trips
-            const int chunks = ((hx - lx + 1) * (hz - lz + 1) + BWD_G - 1) / BWD_G;
-            if (fits) cls = (min(chunks, 4) - 1) * 2 + (hy - ly + 1 > 6 ? 1 : 0);
-        }
-        // rank of each such Gaussian in (class, list) order; the result of a Gaussian does not
-        // depend on when it is taken
-        int rank = 0, n_lds = 0;
+    for (int w0 = e0 + wv * WIN; w0 < e1; w0 += 4 * WIN) {
+        uint32_t v[EPL];
+        int cl[EPL], pos[EPL];
 #pragma unroll
-        for (int c = 0; c < NCLS; ++c) {
-            const uint64_t mc = __ballot(cls == c);
-            if (cls == c)
-                rank = n_lds + (int)__builtin_amdgcn_mbcnt_hi(
-                                   (uint32_t)(mc >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mc, 0u));
-            n_lds += __popcll(mc);
+        for (int h = 0; h < EPL; ++h) {
+            cl[h] = entry_class(w0 + h * 64 + lane, v[h]);
+            pos[h] = 0;
         }
-        if (cls < NCLS) order[wv][rank] = v;
-        uint64_t in_global = __ballot(home && !fits);
+        int n_lds = 0, base = 0;
+#pragma unroll
+        for (int c = 0; c < NSLOT; ++c) {
+#pragma unroll
+            for (int h = 0; h < EPL; ++h) {
+                const uint64_t m = __ballot(cl[h] == c);
+                const int r = (int)__builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                if (cl[h] == c) pos[h] = base + r;
+                base += __popcll(m);
+            }
+            if (c == NCLS - 1) n_lds = base;
+        }
+#pragma unroll
+        for (int h = 0; h < EPL; ++h)
+            if (cl[h] < NSLOT) order[wv][pos[h]] = v[h];
+        constexpr int PER_ROUND = 64 / BWD_G;
 #pragma unroll 1
-        for (int r0 = 0; r0 < n_lds; r0 += 64 / BWD_G) {
+        for (int r0 = 0; r0 < n_lds; r0 += PER_ROUND) {
             const int ix = r0 + grp;
             const bool valid = ix < n_lds;
             const uint32_t mine = valid ? order[wv][ix] : 0u;
             group_of_gaussians<BWD_G, true>(a, kk, mine, valid, region, t0x, t0y, t0z);
         }
 #pragma unroll 1
-        while (in_global) {
-            uint32_t mine;
-            bool valid;
-            take_group<BWD_G>(in_global, v, mine, valid);
+        for (int r0 = n_lds; r0 < base; r0 += PER_ROUND) {
+            const int ix = r0 + grp;
+            const bool valid = ix < base;
+            const uint32_t mine = valid ? order[wv][ix] : 0u;
             group_of_gaussians<BWD_G, false>(a, kk, mine, valid, region, t0x, t0y, t0z);
         }
     }

@@ -40,6 +40,48 @@ FWD_VALU_INSTR = 16
 EXP_SLOTS = 4.0
 
 
+class TimingEvent:
+    """A HIP event created with hipEventDisableSystemFence, on the HIP runtime torch loaded.
+    Recording a default event ends with a system-scope cache writeback and invalidation (about
+    5 us of idle GPU per record on this part); an event used only for timing does not need it,
+    and its timestamps are the same."""
+    FLAG = 0x20000000
+    _hip = None
+
+    @classmethod
+    def runtime(cls):
+        if cls._hip is None:
+            import ctypes
+            with open("/proc/self/maps") as f:
+                path = next(ln.split()[-1] for ln in f if "libamdhip64" in ln)
+            cls._hip = ctypes.CDLL(path)
+        return cls._hip
+
+    def __init__(self):
+        import ctypes
+        self._ct = ctypes
+        self.ev = ctypes.c_void_p()
+        rc = self.runtime().hipEventCreateWithFlags(ctypes.byref(self.ev), ctypes.c_uint(self.FLAG))
+        if rc != 0:
+            raise RuntimeError(f"hipEventCreateWithFlags failed ({rc})")
+
+    def record(self, stream):
+        rc = self._hip.hipEventRecord(self.ev, self._ct.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise RuntimeError(f"hipEventRecord failed ({rc})")
+
+    def elapsed_time(self, end) -> float:
+        ms = self._ct.c_float()
+        rc = self._hip.hipEventElapsedTime(self._ct.byref(ms), self.ev, end.ev)
+        if rc != 0:
+            raise RuntimeError(f"hipEventElapsedTime failed ({rc})")
+        return float(ms.value)
+
+    def __del__(self):
+        if self._hip is not None and self.ev:
+            self._hip.hipEventDestroy(self.ev)
+
+
 def alu_peak_tflops(flop_per_pair, instr_per_pair):
     """FLOP/s ceiling of a kernel whose every pair costs instr_per_pair VALU issue slots."""
     return LANE_OPS / instr_per_pair * flop_per_pair / 1e12
@@ -140,9 +182,10 @@ def main():
     step_no = [0]
     pair_log = []
 
-    def step(record):
+    def step(e):
+        # e: the step's events (created beforehand), or None for an untimed step
         s = torch.cuda.current_stream()
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)] if record else None
+        record = e is not None
         mark = (lambda i: e[i].record(s)) if record else (lambda i: None)
         mark(0)
         bins.bin(p)
@@ -169,17 +212,16 @@ def main():
         return e, loss
 
     for _ in range(args.warmup):
-        step(False)
+        step(None)
     torch.cuda.synchronize()
-    recs = []
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
+    recs = [[TimingEvent() for _ in range(len(stages) + 1)] for _ in range(args.steps)]
+    start, stop = TimingEvent(), TimingEvent()
+    stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
-    start.record()
-    for _ in range(args.steps):
-        e, loss = step(True)
-        recs.append(e)
-    stop.record()
+    start.record(stream)
+    for e in recs:
+        _, loss = step(e)
+    stop.record(stream)
     torch.cuda.synchronize()
     total_ms = start.elapsed_time(stop)
     ms_step = total_ms / args.steps

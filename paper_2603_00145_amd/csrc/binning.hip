@@ -284,12 +284,20 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* keys, int64
 // to the caller's box_volume array, and each grid's first list entry (the scan of the tile
 // counts at the grid's first Gaussian; emission is grid-major and the sort keeps grids apart)
 // next to them, so that gm_bin reads everything it reports back in one device-to-host copy.
+// With `host` (pinned host memory) the whole report is also written there, so that the host
+// reads it after a stream synchronisation without a copy.
 __global__ void k_bin_report(BinReport* rep, const int64_t* offsets, int64_t n,
-                             int64_t* box_volume, int n_grids)
+                             int64_t* box_volume, int n_grids, BinReport* host)
 {
     const int k = threadIdx.x;
     if (k < n_grids) box_volume[k] = (int64_t)rep->box_volume[k];
-    if (k <= n_grids) rep->grid_start[k] = offsets[(int64_t)k * n];
+    const int64_t gs = k <= n_grids ? offsets[(int64_t)k * n] : 0;
+    if (k <= n_grids) rep->grid_start[k] = gs;
+    if (host) {
+        if (k <= GM_MAX_GRIDS) host->grid_start[k] = gs;
+        if (k < GM_MAX_GRIDS) host->box_volume[k] = k < n_grids ? rep->box_volume[k] : 0ull;
+        if (k < 4) host->flags[k] = rep->flags[k];
+    }
 }
 
 inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -306,10 +314,11 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s
 }
 
 hipError_t launch_bin_report(BinReport* rep, const int64_t* offsets, int64_t n,
-                             int64_t* box_volume, int n_grids, hipStream_t s)
+                             int64_t* box_volume, int n_grids, BinReport* host, hipStream_t s)
 {
+    static_assert(GM_MAX_GRIDS < 64, "one thread per grid");
     hipLaunchKernelGGL(k_bin_report, dim3(1), dim3(64), 0, s, rep, offsets, n, box_volume,
-                       n_grids);
+                       n_grids, host);
     return hipGetLastError();
 }
 

@@ -435,10 +435,18 @@ gm_status gm_bin(const gm_gaussians* g, const gm_grid* grids, int32_t n_grids,
     GM_HIP(launch_preprocess(pa, s), "preprocess");
     GM_HIP(launch_scan_i32_to_i64(bins->tile_count, sc.offsets, m, sc.scan_ws, s), "scan");
 
-    GM_HIP(launch_bin_report(sc.report, sc.offsets, n, bins->box_volume, n_grids, s), "report");
-    BinReport rep;
-    GM_HIP(hipMemcpyAsync(&rep, sc.report, sizeof rep, hipMemcpyDeviceToHost, s), "read report");
+    // the report lands in a pinned host block of this thread (allocated once, kept for the
+    // life of the process), written by the report kernel itself
+    static thread_local BinReport* t_report = nullptr;
+    if (!t_report) {
+        void* hp = nullptr;
+        GM_HIP(hipHostMalloc(&hp, sizeof(BinReport), hipHostMallocDefault), "pinned report block");
+        t_report = static_cast<BinReport*>(hp);
+    }
+    GM_HIP(launch_bin_report(sc.report, sc.offsets, n, bins->box_volume, n_grids, t_report, s),
+           "report");
     GM_HIP(hipStreamSynchronize(s), "synchronise");
+    const BinReport rep = *t_report;
     const int64_t total = rep.grid_start[n_grids];
     const uint32_t flags = rep.flags[0];
     *n_pairs = total;

@@ -42,7 +42,7 @@ struct BinReport {
     int64_t grid_start[GM_MAX_GRIDS + 1];  // first list entry of each grid; [n_grids] = total
 };
 hipError_t launch_bin_report(BinReport* rep, const int64_t* offsets, int64_t n,
-                             int64_t* box_volume, int n_grids, hipStream_t s);
+                             int64_t* box_volume, int n_grids, BinReport* host, hipStream_t s);
 
 struct PreprocessArgs {
     int64_t n;

@@ -64,20 +64,6 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const int32_t* in,
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-// single block: exclusive scan of the block partials in place
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_partials(int64_t* part, int64_t nb)
-{
-    int64_t carry = 0;
-    for (int64_t b0 = 0; b0 < nb; b0 += SCAN_THREADS) {
-        const int64_t i = b0 + threadIdx.x;
-        const int64_t v = i < nb ? part[i] : 0;
-        int64_t tot;
-        const int64_t ex = block_exclusive_scan(v, &tot);
-        if (i < nb) part[i] = carry + ex;
-        carry += tot;
-    }
-}
-
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(const int32_t* in, int64_t n,
                                                               const int64_t* part,
                                                               int64_t* out)
@@ -104,8 +90,14 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(const int32_t* in, 
     int64_t s = 0;
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) s += v[k];
+    // this block's offset: the sum of the chunk totals before it (read from L2; integer,
+    // so the order of the sum does not matter)
+    int64_t pre = 0;
+    for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += SCAN_THREADS) pre += part[b];
+    int64_t before;
+    block_exclusive_scan(pre, &before);
     int64_t tot;
-    int64_t run = block_exclusive_scan(s, &tot) + part[blockIdx.x];
+    int64_t run = block_exclusive_scan(s, &tot) + before;
     int64_t r[SCAN_ITEMS];
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) {
@@ -347,7 +339,6 @@ hipError_t launch_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, vo
     const unsigned nb = grid_for(n, SCAN_CHUNK);
     int64_t* part = reinterpret_cast<int64_t*>(ws);
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(SCAN_THREADS), 0, s, in, n, part);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, part, (int64_t)nb);
     hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(SCAN_THREADS), 0, s, in, n, part, out);
     return hipGetLastError();
 }

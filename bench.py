@@ -134,6 +134,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--unfused-loss", action="store_true",
                     help="render and smooth-L1 as two calls (the renderings go through HBM)")
+    ap.add_argument("--unfused-adam", action="store_true",
+                    help="chain rule into a gradient buffer, then Adam per group (four calls)")
     ap.add_argument("--cpu-sample-voxels", type=int, default=4096)
     ap.add_argument("--cpu-sample-gauss", type=int, default=100000)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -176,8 +178,15 @@ def main():
 
     # stage -> events; every stage is timed on the stream its kernels are launched on.  By
     # default "render" is the fused render + smooth-L1 call (the loss and dL/dI are formed in
-    # the render's epilogue) and "loss" only clears the gradient buffers.
+    # the render's epilogue) and "chain" the fused chain rule + Adam call; with the unfused
+    # options the separate calls get stages of their own ("loss": the smooth-L1 pass and/or the
+    # gradient clear, "adam": the four Adam steps).
+    fused_adam = not args.unfused_adam
     stages = ("bin", "render", "loss", "partials", "chain", "adam")
+    if fused_adam and not args.unfused_loss:
+        stages = ("bin", "render", "partials", "chain")
+    elif fused_adam:
+        stages = ("bin", "render", "loss", "partials", "chain")
     ev = {k: [] for k in stages}
     step_no = [0]
     pair_log = []
@@ -186,29 +195,43 @@ def main():
         # e: the step's events (created beforehand), or None for an untimed step
         s = torch.cuda.current_stream()
         record = e is not None
-        mark = (lambda i: e[i].record(s)) if record else (lambda i: None)
-        mark(0)
+        k = [0]
+
+        def mark(name):
+            # closes the stage before `name` (or the step, for None) and opens `name`
+            if record:
+                e[k[0]].record(s)
+                k[0] += 1
+
+        mark("bin")
         bins.bin(p)
         if record:
             pair_log.append(sum(bins.box_pairs_host))   # reported by gm_bin, no extra sync
-        mark(1)
+        mark("render")
         if args.unfused_loss:
             api.render(bins, ids, outs)                  # k_render
-            mark(2)
+            mark("loss")
             loss, _ = api.smooth_l1(outs, targets, dls)
         else:
             loss, _ = api.render_loss(bins, ids, targets, dls)   # k_render, loss epilogue
-            mark(2)
-        grads.zero_()
-        mark(3)
+            if not fused_adam:
+                mark("loss")
+        if not fused_adam:
+            grads.zero_()
+        mark("partials")
         api.grid_partials(p, bins, ids, dls)              # k_partials
-        mark(4)
-        api.chain(p, bins, ids, grads, 0.1, 1.5)          # k_chain (+ anisotropy)
-        mark(5)
+        mark("chain")
         step_no[0] += 1
-        for prm, gr, mm, vv, lr in zip(p.tensors(), grads.tensors(), m.tensors(), v.tensors(), lrs):
-            api.adam_step(prm, gr, mm, vv, lr, step_no[0])
-        mark(6)
+        if fused_adam:
+            # k_chain (+ anisotropy) with Adam on the four groups in its epilogue
+            api.chain_adam(p, bins, ids, m, v, lrs, step_no[0], 0.1, 1.5)
+        else:
+            api.chain(p, bins, ids, grads, 0.1, 1.5)      # k_chain (+ anisotropy)
+            mark("adam")
+            for prm, gr, mm, vv, lr in zip(p.tensors(), grads.tensors(), m.tensors(),
+                                           v.tensors(), lrs):
+                api.adam_step(prm, gr, mm, vv, lr, step_no[0])
+        mark(None)
         return e, loss
 
     for _ in range(args.warmup):
@@ -269,6 +292,8 @@ def main():
         "fwd_bwd_evals_per_s": pairs / ((stage_ms["render"] + bwd_ms) / 1e3),
         "final_loss": float(loss),
         "loss_path": "two calls" if args.unfused_loss else "fused into the render",
+        "adam_path": "four calls after the chain rule" if args.unfused_adam
+                     else "fused into the chain rule (the chain stage includes Adam)",
         "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": recorded_traffic(kname),
                      "flop_per_pair": flop, "avg_kernel_ms": stage_ms[dom]},

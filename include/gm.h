@@ -328,6 +328,27 @@ gm_status gm_grid_pose_grads(const gm_gaussians* g, const gm_bins* bins, const i
                              int32_t n_ids, double* out, void* workspace, size_t workspace_bytes,
                              gm_stream stream);
 
+/* Hyperparameters of the fused chain-rule + Adam step: one learning rate per parameter group
+ * (Sec. 4.1.4; groups mean, quat, log_scale, logit in that order), shared betas and eps. */
+typedef struct gm_adam_opts {
+    double lr[4];
+    double beta1, beta2, eps;
+    int32_t step;  /* >= 1 */
+} gm_adam_opts;
+
+/* gm_chain into a zeroed gradient followed by gm_adam_step on each of the four parameter groups
+ * (with opts->lr[0..3]), in one pass: each Gaussian's gradient is formed in FP64, rounded to
+ * float as gm_chain stores it, and applied at once, so it never goes to memory.  The result is
+ * bit-identical to that three-step sequence.  g's four parameter arrays are updated IN PLACE
+ * (they must be writable device memory, whatever the const of gm_gaussians says) and must be
+ * the parameters bins->grid_grads was computed for by gm_grid_partials with the same grid_ids;
+ * m and v are the first and second moments, laid out as the parameters (device, updated in
+ * place).  The Adam scalars are formed as gm_adam_step forms them. */
+gm_status gm_chain_adam(const gm_gaussians* g, const gm_bins* bins, const int32_t* grid_ids,
+                        int32_t n_ids, float lambda_aniso, float lambda_r,
+                        const gm_adam_opts* opts, gm_gaussian_grads* m, gm_gaussian_grads* v,
+                        gm_stream stream);
+
 /* Adam (Sec. 4.1.4; PyTorch arrangement, no weight decay) on n float32 elements in place:
  * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
  * p -= (lr / (1 - b1^step)) m / (sqrt(v) / sqrt(1 - b2^step) + eps).  step >= 1.

@@ -47,6 +47,11 @@ class GmBinOpts(ctypes.Structure):
                 ("cell_resolution", ctypes.c_int32)]
 
 
+class GmAdamOpts(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_double * 4), ("beta1", ctypes.c_double),
+                ("beta2", ctypes.c_double), ("eps", ctypes.c_double), ("step", ctypes.c_int32)]
+
+
 class GmBins(ctypes.Structure):
     _fields_ = [("n_grids", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("n_gauss", ctypes.c_int64), ("capacity_pairs", ctypes.c_int64),
@@ -120,6 +125,10 @@ _SIGS = [
     ("gm_chain", ctypes.c_int, [ctypes.POINTER(GmGaussians), ctypes.POINTER(GmBins),
                                  ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_float,
                                  ctypes.c_float, ctypes.POINTER(GmGrads), P]),
+    ("gm_chain_adam", ctypes.c_int, [ctypes.POINTER(GmGaussians), ctypes.POINTER(GmBins),
+                                      ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                      ctypes.c_float, ctypes.c_float, ctypes.POINTER(GmAdamOpts),
+                                      ctypes.POINTER(GmGrads), ctypes.POINTER(GmGrads), P]),
     ("gm_adam_step", ctypes.c_int, [P, P, P, P, ctypes.c_int64, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_int32, P]),

@@ -307,6 +307,25 @@ def chain(g: GaussParams, bins: Bins, ids: Sequence[int], grads: GaussParams,
     return grads
 
 
+def chain_adam(g: GaussParams, bins: Bins, ids: Sequence[int], m: GaussParams, v: GaussParams,
+               lrs: Sequence[float], step: int, lambda_aniso: float = 0.0,
+               lambda_r: float = 1.5, beta1: float = 0.9, beta2: float = 0.999,
+               eps: float = 1e-8):
+    """gm_chain_adam: chain rule and Adam in one pass; g, m and v are updated in place.
+    lrs: learning rates of the mean, quat, log_scale and logit groups."""
+    if len(lrs) != 4:
+        raise ValueError("four learning rates: mean, quat, log_scale, logit")
+    idarr = (ctypes.c_int32 * max(1, len(ids)))(*ids)
+    gs = g.struct()
+    ms, vs = m.grad_struct(), v.grad_struct()
+    opts = _lib.GmAdamOpts((ctypes.c_double * 4)(*[float(x) for x in lrs]), float(beta1),
+                           float(beta2), float(eps), int(step))
+    check(load().gm_chain_adam(ctypes.byref(gs), ctypes.byref(bins.struct()), idarr, len(ids),
+                               float(lambda_aniso), float(lambda_r), ctypes.byref(opts),
+                               ctypes.byref(ms), ctypes.byref(vs), _stream()))
+    return g
+
+
 def smooth_l1(preds: Sequence[torch.Tensor], targets: Sequence[torch.Tensor],
               dl_di: Optional[List[torch.Tensor]] = None):
     """gm_loss_smooth_l1: returns (loss device scalar, dL/dI per stack)."""

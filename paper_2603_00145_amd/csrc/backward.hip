@@ -553,14 +553,41 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k
             ds[in] -= gr;
         }
     }
+    float gr[11];  // the gradient as float: mean (3), quat (4), log_scale (3), logit (1)
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        a.g_mean[3 * i + m] += (float)dmu[m];
-        a.g_log_scale[3 * i + m] += (float)ds[m];
+        gr[m] = (float)dmu[m];
+        gr[7 + m] = (float)ds[m];
     }
 #pragma unroll
-    for (int m = 0; m < 4; ++m) a.g_quat[4 * i + m] += (float)((dq[m] - qh[m] * dot) / qn);
-    a.g_logit[i] += (float)(dalpha * alpha * (1.0 - alpha));
+    for (int m = 0; m < 4; ++m) gr[3 + m] = (float)((dq[m] - qh[m] * dot) / qn);
+    gr[10] = (float)(dalpha * alpha * (1.0 - alpha));
+    if (!a.adam) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            a.g_mean[3 * i + m] += gr[m];
+            a.g_log_scale[3 * i + m] += gr[7 + m];
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) a.g_quat[4 * i + m] += gr[3 + m];
+        a.g_logit[i] += gr[10];
+        return;
+    }
+    // fused Adam: the value a zeroed gradient buffer would hold (0 + g), applied at once to
+    // the parameter and its moments, group by group
+    constexpr int width[4] = {3, 4, 3, 1}, first[4] = {0, 3, 7, 10};
+#pragma unroll
+    for (int grp = 0; grp < 4; ++grp) {
+#pragma unroll
+        for (int m = 0; m < width[grp]; ++m) {
+            const int64_t e = width[grp] * i + m;
+            float pv = a.prm[grp][e], mv = a.m1[grp][e], vv = a.m2[grp][e];
+            adam_elem(pv, mv, vv, 0.0f + gr[first[grp] + m], a.adam_s[grp]);
+            a.m1[grp][e] = mv;
+            a.m2[grp][e] = vv;
+            a.prm[grp][e] = pv;
+        }
+    }
 }
 
 // Gradient with respect to each listed grid's world->index affine [L | t] (boxes fixed): per

@@ -713,10 +713,17 @@ namespace {
 
 // Shared body of gm_backward (both stages), gm_grid_partials (K7 only) and gm_chain (K8
 // only).
+// the fused chain + Adam step: moments and per-group scalars
+struct AdamFuse {
+    gm_gaussian_grads* m;
+    gm_gaussian_grads* v;
+    AdamScalars c[4];
+};
+
 gm_status backward_impl(const gm_gaussians* g, const gm_bins* bins, const int32_t* grid_ids,
                         int32_t n_ids, const float* const* dl_di, float lambda_aniso,
                         float lambda_r, gm_gaussian_grads* grad, hipStream_t s, bool partials,
-                        bool chain)
+                        bool chain, const AdamFuse* fuse = nullptr)
 {
     gm_status st = check_gauss(g);
     if (st != GM_OK) return st;
@@ -728,18 +735,30 @@ gm_status backward_impl(const gm_gaussians* g, const gm_bins* bins, const int32_
         return fail(GM_ERR_INVALID_ARGUMENT, "bins were built for %lld Gaussians, got %lld",
                     (long long)bins->n_gauss, (long long)g->n);
     if (chain) {
-        if (!grad || grad->n != g->n)
+        if (fuse) {
+            if (!fuse->m || !fuse->v || fuse->m->n != g->n || fuse->v->n != g->n)
+                return fail(GM_ERR_INVALID_ARGUMENT, "Adam moments missing or wrong n");
+        } else if (!grad || grad->n != g->n) {
             return fail(GM_ERR_INVALID_ARGUMENT, "grad missing or wrong n");
+        }
         if (!isfinite(lambda_aniso) || !isfinite(lambda_r))
             return fail(GM_ERR_INVALID_ARGUMENT, "non-finite lambda");
     }
     if (partials && n_ids > 0 && !dl_di) return fail(GM_ERR_INVALID_ARGUMENT, "dl_di is NULL");
     if (g->n == 0) return GM_OK;
-    if (chain) {
+    if (chain && !fuse) {
         REQ_PTR(grad->mean, "grad->mean");
         REQ_PTR(grad->quat, "grad->quat");
         REQ_PTR(grad->log_scale, "grad->log_scale");
         REQ_PTR(grad->logit, "grad->logit");
+    }
+    if (fuse) {
+        for (const gm_gaussian_grads* t : {fuse->m, fuse->v}) {
+            REQ_PTR(t->mean, "moment mean");
+            REQ_PTR(t->quat, "moment quat");
+            REQ_PTR(t->log_scale, "moment log_scale");
+            REQ_PTR(t->logit, "moment logit");
+        }
     }
     REQ_PTR(bins->records, "bins->records");
     REQ_PTR(bins->tile_count, "bins->tile_count");
@@ -790,10 +809,28 @@ gm_status backward_impl(const gm_gaussians* g, const gm_bins* bins, const int32_
     ca.logit = g->logit;
     ca.tile_count = bins->tile_count;
     ca.grid_grads = bins->grid_grads;
-    ca.g_mean = grad->mean;
-    ca.g_quat = grad->quat;
-    ca.g_log_scale = grad->log_scale;
-    ca.g_logit = grad->logit;
+    if (fuse) {
+        // the parameters are updated in place
+        ca.adam = 1;
+        ca.prm[0] = const_cast<float*>(g->mean);
+        ca.prm[1] = const_cast<float*>(g->quat);
+        ca.prm[2] = const_cast<float*>(g->log_scale);
+        ca.prm[3] = const_cast<float*>(g->logit);
+        const gm_gaussian_grads* mv[2] = {fuse->m, fuse->v};
+        float** dst[2] = {ca.m1, ca.m2};
+        for (int t = 0; t < 2; ++t) {
+            dst[t][0] = mv[t]->mean;
+            dst[t][1] = mv[t]->quat;
+            dst[t][2] = mv[t]->log_scale;
+            dst[t][3] = mv[t]->logit;
+        }
+        for (int k = 0; k < 4; ++k) ca.adam_s[k] = fuse->c[k];
+    } else {
+        ca.g_mean = grad->mean;
+        ca.g_quat = grad->quat;
+        ca.g_log_scale = grad->log_scale;
+        ca.g_logit = grad->logit;
+    }
     GM_HIP(launch_chain(ca, s), "chain rule");
     return GM_OK;
 }
@@ -866,6 +903,29 @@ gm_status gm_chain(const gm_gaussians* g, const gm_bins* bins, const int32_t* gr
     g_err.clear();
     return backward_impl(g, bins, grid_ids, n_ids, nullptr, lambda_aniso, lambda_r, grad,
                          reinterpret_cast<hipStream_t>(stream), false, true);
+}
+
+gm_status gm_chain_adam(const gm_gaussians* g, const gm_bins* bins, const int32_t* grid_ids,
+                        int32_t n_ids, float lambda_aniso, float lambda_r,
+                        const gm_adam_opts* opts, gm_gaussian_grads* m, gm_gaussian_grads* v,
+                        gm_stream stream)
+{
+    g_err.clear();
+    if (!opts) return fail(GM_ERR_INVALID_ARGUMENT, "opts is NULL");
+    if (opts->step < 1) return fail(GM_ERR_INVALID_ARGUMENT, "step must be >= 1");
+    if (!(opts->beta1 >= 0.0 && opts->beta1 < 1.0 && opts->beta2 >= 0.0 && opts->beta2 < 1.0) ||
+        !(opts->eps >= 0.0) || !isfinite(opts->eps))
+        return fail(GM_ERR_INVALID_ARGUMENT, "bad Adam hyperparameters");
+    AdamFuse fuse;
+    fuse.m = m;
+    fuse.v = v;
+    for (int k = 0; k < 4; ++k) {
+        if (!isfinite(opts->lr[k])) return fail(GM_ERR_INVALID_ARGUMENT, "non-finite learning rate");
+        fuse.c[k] = adam_scalars(opts->lr[k], opts->beta1, opts->beta2, opts->eps, opts->step);
+    }
+    if (!m || !v) return fail(GM_ERR_INVALID_ARGUMENT, "Adam moments missing");
+    return backward_impl(g, bins, grid_ids, n_ids, nullptr, lambda_aniso, lambda_r, nullptr,
+                         reinterpret_cast<hipStream_t>(stream), false, true, &fuse);
 }
 
 gm_status gm_loss_smooth_l1(int32_t n_stacks, const float* const* preds,
@@ -978,10 +1038,7 @@ gm_status gm_adam_step(float* param, const float* grad, float* m, float* v, int6
     REQ_PTR(grad, "grad");
     REQ_PTR(m, "m");
     REQ_PTR(v, "v");
-    const double bc1 = 1.0 - pow(beta1, (double)step);
-    const double bc2 = 1.0 - pow(beta2, (double)step);
-    GM_HIP(launch_adam(param, grad, m, v, n, (float)beta1, (float)(1.0 - beta1), (float)beta2,
-                       (float)(1.0 - beta2), (float)eps, (float)(lr / bc1), (float)sqrt(bc2),
+    GM_HIP(launch_adam(param, grad, m, v, n, adam_scalars(lr, beta1, beta2, eps, step),
                        reinterpret_cast<hipStream_t>(stream)), "adam");
     return GM_OK;
 }

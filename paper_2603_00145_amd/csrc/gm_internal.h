@@ -130,6 +130,26 @@ struct BackwardArgs {
 };
 hipError_t launch_backward_partials(const BackwardArgs& a, hipStream_t s);
 
+// Adam's per-group scalars, rounded once to float from double hyperparameters
+struct AdamScalars {
+    float b1, omb1, b2, omb2, eps, step_size, bc2_sqrt;
+};
+AdamScalars adam_scalars(double lr, double beta1, double beta2, double eps, int32_t step);
+
+// One Adam element update (PyTorch arrangement).  No multiply-add is contracted here (division
+// and square root are correctly rounded), so that each kernel that calls it (the plain step and
+// the fused chain step) gives the same bits.
+__device__ __forceinline__ void adam_elem(float& p, float& m, float& v, float g,
+                                          const AdamScalars& c)
+{
+#pragma clang fp contract(off)
+    const float mi = c.b1 * m + c.omb1 * g;
+    const float vi = c.b2 * v + c.omb2 * g * g;
+    m = mi;
+    v = vi;
+    p = p - c.step_size * mi / (sqrtf(vi) / c.bc2_sqrt + c.eps);
+}
+
 struct ChainArgs {
     int64_t n;
     int32_t n_ids;
@@ -144,6 +164,14 @@ struct ChainArgs {
     float* g_quat;
     float* g_log_scale;
     float* g_logit;
+    // fused Adam (adam != 0): the gradient is applied to the parameters (prm, the same arrays
+    // as mean..logit) and the moments m1, m2 of groups mean, quat, log_scale, logit instead of
+    // being added to g_*
+    int32_t adam;
+    float* prm[4];
+    float* m1[4];
+    float* m2[4];
+    AdamScalars adam_s[4];
     int32_t grid_index[GM_MAX_GRIDS];
     GridConst g[GM_MAX_GRIDS];
 };
@@ -183,9 +211,8 @@ hipError_t launch_mse(const float* a, const float* b, int64_t n, float* mse, voi
                       hipStream_t s);
 // scalars formed in double on the host and rounded once: 1 - beta, lr / (1 - beta1^t),
 // sqrt(1 - beta2^t)
-hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float b1,
-                       float omb1, float b2, float omb2, float eps, float step_size,
-                       float bc2_sqrt, hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n,
+                       const AdamScalars& c, hipStream_t s);
 
 struct DevoxArgs {
     int32_t g;

@@ -84,18 +84,15 @@ __global__ __launch_bounds__(RED_THREADS) void k_sqdiff(const float* a, const fl
 
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
                                                float* __restrict__ m, float* __restrict__ v,
-                                               int64_t n, float b1, float omb1, float b2,
-                                               float omb2, float eps, float step_size,
-                                               float bc2_sqrt)
+                                               int64_t n, const AdamScalars c)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const float gi = g[i];
-        const float mi = b1 * m[i] + omb1 * gi;
-        const float vi = b2 * v[i] + omb2 * gi * gi;
+        float pi = p[i], mi = m[i], vi = v[i];
+        adam_elem(pi, mi, vi, g[i], c);
         m[i] = mi;
         v[i] = vi;
-        p[i] -= step_size * mi / (sqrtf(vi) / bc2_sqrt + eps);
+        p[i] = pi;
     }
 }
 
@@ -141,14 +138,27 @@ hipError_t launch_mse(const float* a, const float* b, int64_t n, float* mse, voi
     return hipGetLastError();
 }
 
-hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float b1,
-                       float omb1, float b2, float omb2, float eps, float step_size,
-                       float bc2_sqrt, hipStream_t s)
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n,
+                       const AdamScalars& c, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     int64_t nb = (n + 255) / 256;
     if (nb > 8192) nb = 8192;
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)nb), dim3(256), 0, s, p, g, m, v, n, b1, omb1, b2,
-                       omb2, eps, step_size, bc2_sqrt);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)nb), dim3(256), 0, s, p, g, m, v, n, c);
     return hipGetLastError();
+}
+
+AdamScalars adam_scalars(double lr, double beta1, double beta2, double eps, int32_t step)
+{
+    const double bc1 = 1.0 - pow(beta1, (double)step);
+    const double bc2 = 1.0 - pow(beta2, (double)step);
+    AdamScalars c;
+    c.b1 = (float)beta1;
+    c.omb1 = (float)(1.0 - beta1);
+    c.b2 = (float)beta2;
+    c.omb2 = (float)(1.0 - beta2);
+    c.eps = (float)eps;
+    c.step_size = (float)(lr / bc1);
+    c.bc2_sqrt = (float)sqrt(bc2);
+    return c;
 }

@@ -55,7 +55,6 @@ class Reconstruction:
         self.stacks = list(stacks)
         self.targets = [t.contiguous() for t in targets]
         self.p = params
-        self.g = api.GaussParams.zeros_like(params)
         self.m = api.GaussParams.zeros_like(params)
         self.v = api.GaussParams.zeros_like(params)
         dev = params.mean.device
@@ -91,7 +90,6 @@ class Reconstruction:
         """Replace the lattice by the g_new^3 lattice interpolated from it."""
         self.p = api.upsample_lattice(self.p, self.lattice, g_new)
         self.lattice = g_new
-        self.g = api.GaussParams.zeros_like(self.p)
         self.m = api.GaussParams.zeros_like(self.p)
         self.v = api.GaussParams.zeros_like(self.p)
         self.bins = self._bins(self.p.n, self.bins.grids, 10)
@@ -123,8 +121,7 @@ class Reconstruction:
         if c.lambda_ssim > 0:
             loss = loss + c.lambda_ssim * api.ssim_loss(self.outs, self.targets, self.dls,
                                                         c.lambda_ssim)
-        self.g.zero_()
-        api.backward(self.p, self.bins, self.ids, self.dls, self.g, c.lambda_aniso, c.lambda_r)
+        api.grid_partials(self.p, self.bins, self.ids, self.dls)
         if self.poses is not None:
             G = api.pose_grads(self.p, self.bins, self.ids).cpu().numpy()
             self.pose_opt.step(list(G))
@@ -133,9 +130,10 @@ class Reconstruction:
             for k, s in enumerate(self.stacks):
                 c.nrf.backward(s, self.dls[k], n_sample=c.nrf_sample)
             c.nrf.adam_step(c.lr_nrf)
-        for prm, gr, mm, vv, lr in zip(self.p.tensors(), self.g.tensors(), self.m.tensors(),
-                                       self.v.tensors(), self.lrs()):
-            api.adam_step(prm, gr, mm, vv, lr, self.it - self.adam_t0)
+        # chain rule and Adam on the four groups in one pass: the parameters change only here,
+        # after everything above has read them
+        api.chain_adam(self.p, self.bins, self.ids, self.m, self.v, self.lrs(),
+                       self.it - self.adam_t0, c.lambda_aniso, c.lambda_r)
         return loss
 
     def render_volume(self) -> torch.Tensor:

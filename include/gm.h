@@ -154,7 +154,8 @@ gm_status gm_bin_query(int64_t n, const gm_grid* grids, int32_t n_grids,
 /* Spatial query (stands in for Sec. 3.3.1): per (grid, Gaussian) compute the record and
  * the box, then list for every tile of every grid the Gaussians whose box overlaps it, in
  * ascending Gaussian id (a stable device radix sort of (tile, Gaussian) keys).
- * Synchronises `stream` once to read the pair total; *n_pairs [host] receives it.
+ * Waits once on the host for the pair total (an event recorded after the count; the pair
+ * emission is already enqueued behind it); *n_pairs [host] receives it.
  * GM_ERR_CAPACITY if it exceeds bins->capacity_pairs (records, counts and box volumes are
  * still valid; lists are not).  GM_ERR_NONFINITE if any parameter is non-finite, a
  * quaternion is zero or exp(log_scale) overflows (those Gaussians get empty boxes; the

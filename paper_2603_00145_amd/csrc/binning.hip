@@ -131,6 +131,8 @@ __global__ __launch_bounds__(256) void k_emit(const EmitArgs a)
     const uint32_t gid = (uint32_t)(idx - (int64_t)k * a.n);
     const GridConst& G = a.g[k];
     int64_t o = a.offsets[idx];
+    // the emission runs before the host has checked the total against the capacity
+    if (o + (int64_t)(hx - lx + 1) * (hy - ly + 1) * (hz - lz + 1) > a.capacity) return;
     // the first tile emitted holds the box's lower corner: its entry carries GM_HOME_BIT
     uint32_t home = GM_HOME_BIT;
     for (int tz = lz; tz <= hz; ++tz)

@@ -445,7 +445,38 @@ gm_status gm_bin(const gm_gaussians* g, const gm_grid* grids, int32_t n_grids,
     }
     GM_HIP(launch_bin_report(sc.report, sc.offsets, n, bins->box_volume, n_grids, t_report, s),
            "report");
-    GM_HIP(hipStreamSynchronize(s), "synchronise");
+    // The host waits for the report only (an event after it, one per device and thread); the
+    // pair emission is enqueued first, sized by the Gaussians and guarded by the capacity on
+    // the device, so that the GPU emits while the host wakes up.
+    static thread_local hipEvent_t t_done[64] = {};
+    int dev = 0;
+    GM_HIP(hipGetDevice(&dev), "current device");
+    if (dev < 0 || dev >= 64) return fail(GM_ERR_UNSUPPORTED, "device index %d >= 64", dev);
+    if (!t_done[dev])
+        GM_HIP(hipEventCreateWithFlags(&t_done[dev], hipEventDisableTiming), "report event");
+    GM_HIP(hipEventRecord(t_done[dev], s), "record report event");
+
+    int bits = 0;
+    while ((int64_t(1) << bits) < T) ++bits;
+    const int passes = (bits + 7) / 8;
+    uint32_t* pg = reinterpret_cast<uint32_t*>(bins->pair_gauss);
+    // arrange the ping-pong buffers so the last pass lands in pair_gauss
+    uint32_t *k_in = sc.keys0, *k_alt = sc.keys1;
+    uint32_t *v_in = (passes & 1) ? sc.vals0 : pg, *v_alt = (passes & 1) ? pg : sc.vals0;
+    {
+        EmitArgs ea;
+        memset(&ea, 0, sizeof ea);
+        ea.n = n;
+        ea.n_grids = n_grids;
+        ea.tile_box = sc.tile_box;
+        ea.offsets = sc.offsets;
+        ea.capacity = bins->capacity_pairs;
+        ea.keys = k_in;
+        ea.vals = v_in;
+        for (int k = 0; k < n_grids; ++k) ea.g[k] = pa.g[k];
+        GM_HIP(launch_emit(ea, s), "emit");
+    }
+    GM_HIP(hipEventSynchronize(t_done[dev]), "synchronise");
     const BinReport rep = *t_report;
     const int64_t total = rep.grid_start[n_grids];
     const uint32_t flags = rep.flags[0];
@@ -460,24 +491,7 @@ gm_status gm_bin(const gm_gaussians* g, const gm_grid* grids, int32_t n_grids,
         return GM_ERR_CAPACITY;
     }
 
-    int bits = 0;
-    while ((int64_t(1) << bits) < T) ++bits;
-    const int passes = (bits + 7) / 8;
-    uint32_t* pg = reinterpret_cast<uint32_t*>(bins->pair_gauss);
-    // arrange the ping-pong buffers so the last pass lands in pair_gauss
-    uint32_t *k_in = sc.keys0, *k_alt = sc.keys1;
-    uint32_t *v_in = (passes & 1) ? sc.vals0 : pg, *v_alt = (passes & 1) ? pg : sc.vals0;
     if (total > 0) {
-        EmitArgs ea;
-        memset(&ea, 0, sizeof ea);
-        ea.n = n;
-        ea.n_grids = n_grids;
-        ea.tile_box = sc.tile_box;
-        ea.offsets = sc.offsets;
-        ea.keys = k_in;
-        ea.vals = v_in;
-        for (int k = 0; k < n_grids; ++k) ea.g[k] = pa.g[k];
-        GM_HIP(launch_emit(ea, s), "emit");
         int in_alt = 0;
         GM_HIP(launch_radix_sort(k_in, v_in, k_alt, v_alt, total, bits, sc.radix_ws, &in_alt, s),
                "radix sort");

@@ -75,6 +75,7 @@ struct EmitArgs {
     int32_t n_grids;
     const uint32_t* tile_box;  // [n_grids * n][3], as written by the preprocess
     const int64_t* offsets;  // [n_grids * n + 1]
+    int64_t capacity;        // pairs the key/value buffers hold: a Gaussian past it emits none
     uint32_t* keys;
     uint32_t* vals;
     GridConst g[GM_MAX_GRIDS];

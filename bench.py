@@ -128,8 +128,8 @@ def recorded_iters_to_psnr():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--unfused-loss", action="store_true",

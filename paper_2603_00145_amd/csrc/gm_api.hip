@@ -450,10 +450,23 @@ gm_status gm_bin(const gm_gaussians* g, const gm_grid* grids, int32_t n_grids,
     // the device, so that the GPU emits while the host wakes up.
     static thread_local hipEvent_t t_done[64] = {};
     int dev = 0;
-    GM_HIP(hipGetDevice(&dev), "current device");
+    if (s) {
+        hipDevice_t sd = 0;
+        GM_HIP(hipStreamGetDevice(s, &sd), "stream device");
+        dev = (int)sd;
+    } else {
+        GM_HIP(hipGetDevice(&dev), "current device");
+    }
     if (dev < 0 || dev >= 64) return fail(GM_ERR_UNSUPPORTED, "device index %d >= 64", dev);
-    if (!t_done[dev])
-        GM_HIP(hipEventCreateWithFlags(&t_done[dev], hipEventDisableTiming), "report event");
+    if (!t_done[dev]) {
+        // the event belongs to the stream's device: create it with that device current
+        int cur = 0;
+        GM_HIP(hipGetDevice(&cur), "current device");
+        if (cur != dev) GM_HIP(hipSetDevice(dev), "select stream device");
+        const hipError_t ce = hipEventCreateWithFlags(&t_done[dev], hipEventDisableTiming);
+        if (cur != dev) GM_HIP(hipSetDevice(cur), "restore device");
+        GM_HIP(ce, "report event");
+    }
     GM_HIP(hipEventRecord(t_done[dev], s), "record report event");
 
     int bits = 0;

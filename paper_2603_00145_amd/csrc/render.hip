@@ -22,15 +22,15 @@ __device__ __forceinline__ int sgpr(int v) { return __builtin_amdgcn_readfirstla
 __device__ __forceinline__ uint32_t magic20(uint32_t d) { return ((1u << 20) + d - 1u) / d; }
 __device__ __forceinline__ uint32_t div20(uint32_t q, uint32_t M) { return __umul24(q, M) >> 20; }
 
-// Per (Gaussian, tile) piece, prepared lane-parallel for a batch of list entries:
-// centre relative to the intersection origin, amplitude, base-2 conic (off-diagonals
-// doubled), footprint width and area, z extent, the magic divisor for the column unravel
-// and the LDS index of the intersection origin.
+// Per (Gaussian, tile) piece, prepared lane-parallel for a batch of list entries: in-plane
+// centre relative to the intersection origin, the base-2 conic (off-diagonals doubled) and
+// the z-walk constants of the column formula below, footprint width and area, z extent, the
+// magic divisor for the column unravel and the LDS index of the intersection origin.
 struct Piece {
-    float ux, uy, uz, amp;
+    float ux, uy, d0, F0;
     float kxx, kyy, kzz, kxy;
-    float kxz, kyz;
-    int wx, F, wz, mx, base, pad;
+    float kxz, kyz, E;
+    int wx, F, wz, mx, base;
 };
 
 // Keeps the compiler from moving or merging LDS accesses across this point.  The two halves
@@ -38,8 +38,11 @@ struct Piece {
 // read-add-writes must stay two separate, ordered sequences.
 __device__ __forceinline__ void lds_order() { __asm__ __volatile__("" ::: "memory"); }
 
-// Column f of piece p: its voxel values w[k] = amp 2^Q for the z-steps k < KM, and the LDS
-// index of its voxel at k = 0.
+// Column f of piece p: its voxel values w[k] = amp 2^Q_k for the z-steps k < KM, and the LDS
+// index of its voxel at k = 0.  With dz = k + d0 (d0 = minus the centre's z offset) and
+// bz = kxz dx + kyz dy, Q_k = qxy + dz (bz + kzz dz) is expanded in k as
+// A + k (B + k kzz), A = qxy + d0 bz + kzz d0^2 + log2 amp, B = bz + 2 kzz d0: the per-piece
+// parts of A and B (F0 and E) are formed once, and amp enters as log2 amp in the exponent.
 template <int KM>
 __device__ __forceinline__ void eval_column(const Piece& p, uint32_t f, float (&w)[KM], int& idx)
 {
@@ -47,30 +50,43 @@ __device__ __forceinline__ void eval_column(const Piece& p, uint32_t f, float (&
     const uint32_t x = f - __umul24(y, (uint32_t)p.wx);
     const float dx = (float)x - p.ux;
     const float dy = (float)y - p.uy;
-    const float qxy = dx * (p.kxx * dx + p.kxy * dy) + dy * (p.kyy * dy);
+    const float qxy = dx * (p.kxx * dx + p.kxy * dy) + (dy * (p.kyy * dy) + p.F0);
     const float bz = p.kxz * dx + p.kyz * dy;
+    const float A = p.d0 * bz + qxy;
     static_assert(GM_TX == 16 && GM_TY == 16, "index shifts assume 16x16 tiles");
     idx = p.base + (int)((y << 4) + x);
+    w[0] = __builtin_amdgcn_exp2f(A);
+    if (KM > 1) {
+        const float B = bz + p.E;
 #pragma unroll
-    for (int k = 0; k < KM; ++k) {
-        const float dz = (float)k - p.uz;
-        const float Q = qxy + dz * (bz + p.kzz * dz);
-        w[k] = p.amp * __builtin_amdgcn_exp2f(Q);
+        for (int k = 1; k < KM; ++k)
+            w[k] = __builtin_amdgcn_exp2f(A + (float)k * (B + (float)k * p.kzz));
     }
 }
 
-// acc[column voxel at z-step k] += w[k] for k < kz <= KM (kz uniform).  The z-steps are
-// distinct voxels, so all reads are issued before the writes.
-template <int KM>
-__device__ __forceinline__ void add_column(float* acc, int idx, const float (&w)[KM], int kz)
+// acc[column voxel at z-step k] += w[k] for k < KZ (the piece's exact z extent; KZ <= the
+// length of w).  The z-steps are distinct voxels, so all reads are issued before the writes.
+template <int KZ, int KM>
+__device__ __forceinline__ void add_column(float* acc, int idx, const float (&w)[KM])
 {
-    float old[KM];
+    static_assert(KZ <= KM, "z extent within the evaluated steps");
+    float old[KZ];
 #pragma unroll
-    for (int k = 0; k < KM; ++k)
-        if (k < kz) old[k] = acc[idx + k * GM_TX * GM_TY];
+    for (int k = 0; k < KZ; ++k) old[k] = acc[idx + k * GM_TX * GM_TY];
 #pragma unroll
-    for (int k = 0; k < KM; ++k)
-        if (k < kz) acc[idx + k * GM_TX * GM_TY] = old[k] + w[k];
+    for (int k = 0; k < KZ; ++k) acc[idx + k * GM_TX * GM_TY] = old[k] + w[k];
+}
+
+// add_column for a uniform z extent kz in [1, KM]
+template <int KM>
+__device__ __forceinline__ void add_column_kz(float* acc, int idx, const float (&w)[KM], int kz)
+{
+    switch (kz) {
+    case 1: add_column<1, KM>(acc, idx, w); break;
+    case 2: if constexpr (KM >= 2) add_column<2, KM>(acc, idx, w); break;
+    case 3: if constexpr (KM >= 3) add_column<3, KM>(acc, idx, w); break;
+    default: if constexpr (KM >= 4) add_column<4, KM>(acc, idx, w); break;
+    }
 }
 
 // One piece on the whole wave: columns f0 + lane, KM z-steps each.
@@ -83,7 +99,7 @@ __device__ __forceinline__ void single_piece(const Piece& p, float* acc, int F, 
         float w[KM];
         int idx;
         eval_column<KM>(p, f, w, idx);
-        if (f < (uint32_t)F) add_column<KM>(acc, idx, w, KM);
+        if (f < (uint32_t)F) add_column<KM, KM>(acc, idx, w);
     }
 }
 
@@ -99,9 +115,9 @@ __device__ __forceinline__ void paired_pieces(const Piece& p, float* acc, bool a
     int idx;
     eval_column<KM>(p, f, w, idx);
     lds_order();
-    if (act && first) add_column<KM>(acc, idx, w, wza);
+    if (act && first) add_column_kz<KM>(acc, idx, w, wza);
     lds_order();
-    if (act && !first) add_column<KM>(acc, idx, w, wzb);
+    if (act && !first) add_column_kz<KM>(acc, idx, w, wzb);
     lds_order();
 }
 
@@ -169,16 +185,17 @@ __global__ __launch_bounds__(64) void k_render(const RenderArgs a)
             Piece p;
             p.ux = r0.x - (float)(ix0 - lox);
             p.uy = r0.y - (float)(iy0 - loy);
-            p.uz = r0.z - (float)(iz0 - loz);
-            p.amp = r0.w;
+            p.d0 = (float)(iz0 - loz) - r0.z;
             p.kxx = r1.x; p.kyy = r1.y; p.kzz = r1.z; p.kxy = r1.w;
             p.kxz = r2.x; p.kyz = r2.y;
+            // amp >= 0 (0 for an empty box, never listed): log2 0 = -inf gives zeros
+            p.F0 = log2f(r0.w) + p.kzz * p.d0 * p.d0;
+            p.E = 2.0f * p.kzz * p.d0;
             p.wx = ok ? wx : 1;
             p.F = ok ? wx * wy : 0;
             p.wz = ok ? wz : 0;
             p.mx = (int)magic20((uint32_t)p.wx);
             p.base = ((iz0 - t0z) * GM_TY + (iy0 - t0y)) * GM_TX + (ix0 - t0x);
-            p.pad = 0;
             pc[lane] = p;
             small = p.F <= 32;
         }

@@ -430,21 +430,39 @@ __global__ __launch_bounds__(256) void k_gemm_nt_rows(const uint16_t* __restrict
 
 // out[e] += sum_c part[c][e] in a fixed order: 64 elements per block, wavefront w summing
 // chunks w, w + 4, ..., then the four sums added in order
+// Sum over the nchunk partials of element e: SUM_WAVES wavefronts of the block share the
+// chunks (chunk c to wavefront c mod SUM_WAVES), each with four independent accumulators so
+// that its loads are in flight together, then the wavefronts' sums are added in a fixed order.
+constexpr int SUM_WAVES = 16;
+constexpr int SUM_THREADS = 64 * SUM_WAVES;
+
 __device__ __forceinline__ float sum_chunks(const float* __restrict__ part, int64_t nchunk,
                                             int64_t n, int64_t e)
 {
-    __shared__ float sh[4][64];
+    __shared__ float sh[SUM_WAVES][64];
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    float s = 0.0f;
-    if (e < n)
-        for (int64_t c = w; c < nchunk; c += 4) s += part[c * n + e];
-    sh[w][l] = s;
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+    if (e < n) {
+        int64_t c = w;
+        for (; c + 3 * SUM_WAVES < nchunk; c += 4 * SUM_WAVES) {
+            a0 += part[c * n + e];
+            a1 += part[(c + SUM_WAVES) * n + e];
+            a2 += part[(c + 2 * SUM_WAVES) * n + e];
+            a3 += part[(c + 3 * SUM_WAVES) * n + e];
+        }
+        for (; c < nchunk; c += SUM_WAVES) a0 += part[c * n + e];
+    }
+    sh[w][l] = (a0 + a1) + (a2 + a3);
     __syncthreads();
-    return ((sh[0][l] + sh[1][l]) + sh[2][l]) + sh[3][l];
+    float t = 0.0f;
+#pragma unroll
+    for (int i = 0; i < SUM_WAVES; ++i) t += sh[i][l];
+    return t;
 }
 
-__global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ part, int64_t nchunk,
-                                                   int64_t n, float* __restrict__ out)
+__global__ __launch_bounds__(SUM_THREADS) void k_sum_parts(const float* __restrict__ part,
+                                                           int64_t nchunk, int64_t n,
+                                                           float* __restrict__ out)
 {
     const int64_t e = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
     const float s = sum_chunks(part, nchunk, n, e);
@@ -454,7 +472,7 @@ __global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ par
 // The same for the first layer's weights, whose K dimension the GPU holds in its own encoding
 // order: out[m][natural_feature(i)] += sum_c part[c][m][i]; padding slots are dropped.
 template <int KT>
-__global__ __launch_bounds__(256) void k_sum_parts_in(const float* __restrict__ part,
+__global__ __launch_bounds__(SUM_THREADS) void k_sum_parts_in(const float* __restrict__ part,
                                                       int64_t nchunk, int n_freq,
                                                       float* __restrict__ out)
 {
@@ -564,7 +582,7 @@ static void rowdot(const uint16_t* L, const float* v, int64_t P, int rows, float
     const int64_t nchunk = (P + RD_CHUNK - 1) / RD_CHUNK;
     hipLaunchKernelGGL(k_rowdot_part, dim3((unsigned)rows, (unsigned)nchunk), dim3(256), 0, s, L,
                        v, P, rows, part);
-    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((rows + 63) / 64)), dim3(256), 0, s, part,
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((rows + 63) / 64)), dim3(SUM_THREADS), 0, s, part,
                        nchunk, (int64_t)rows, out);
 }
 
@@ -595,12 +613,14 @@ hipError_t launch_nrf_backward(const NrfArgs& a, const NrfWork& w, hipStream_t s
         const int64_t n = (int64_t)W * N;
         const dim3 grid((unsigned)((n + 63) / 64));
         if (l > 0)
-            hipLaunchKernelGGL(k_sum_parts, grid, dim3(256), 0, s, w.part, nchunk, n, dst);
+            hipLaunchKernelGGL(k_sum_parts, grid, dim3(SUM_THREADS), 0, s, w.part, nchunk, n, dst);
         else if (N == 64)
-            hipLaunchKernelGGL(k_sum_parts_in<4>, grid, dim3(256), 0, s, w.part, nchunk, a.n_freq, dst);
+            hipLaunchKernelGGL(k_sum_parts_in<4>, grid, dim3(SUM_THREADS), 0, s, w.part, nchunk,
+                               a.n_freq, dst);
         else
-            hipLaunchKernelGGL(k_sum_parts_in<8>, grid, dim3(256), 0, s, w.part, nchunk, a.n_freq, dst);
-        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, rowpart, nchunk, (int64_t)W,
+            hipLaunchKernelGGL(k_sum_parts_in<8>, grid, dim3(SUM_THREADS), 0, s, w.part, nchunk,
+                               a.n_freq, dst);
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(SUM_THREADS), 0, s, rowpart, nchunk, (int64_t)W,
                            dbias);
     }
     rowdot(w.a[a.depth], w.dzo, w.P, W, w.part, a.g_w_out, s);

@@ -1214,6 +1214,8 @@ gm_status gm_ws_forward(const gm_ws_net* net, const uint16_t* patches, int64_t n
     REQ_PTR(logit_out, "logit_out");
     char* base = reinterpret_cast<char*>(workspace);
     WsActs w = ws_acts(base, L);
+    // inference: only the last layer's pre-activation (read by the head) is stored
+    for (int l = 0; l < 3; ++l) w.z[l] = nullptr;
     WsHeadArgs h;
     memset(&h, 0, sizeof h);
     h.n = n;

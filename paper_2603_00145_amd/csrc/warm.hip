@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ W
         const int m = m0 + 4 * g + j;
         const float z = av[j] + bias[m];
         const int64_t o = (b * CO + m) * G::PO + p;
-        Z[o] = z;
+        if (Z) Z[o] = z;  // the pre-activation is kept for the backward only
         A[o] = to_bf16(silu(z));
     }
 }
@@ -207,25 +207,54 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__
 }
 
 // out[e] += sum_c part[c][e]
-__global__ __launch_bounds__(256) void k_sum_parts_ws(const float* __restrict__ part,
-                                                      int64_t nchunk, int64_t n,
-                                                      float* __restrict__ out)
+// out[e] += sum over the nchunk partials part[c][e]: SUM_WAVES wavefronts share the chunks
+// (chunk c to wavefront c mod SUM_WAVES), four independent accumulators each so that the loads
+// are in flight together; the wavefronts' sums are added in a fixed order.
+constexpr int SUM_WAVES = 16;
+constexpr int SUM_THREADS = 64 * SUM_WAVES;
+
+__global__ __launch_bounds__(SUM_THREADS) void k_sum_parts_ws(const float* __restrict__ part,
+                                                              int64_t nchunk, int64_t n,
+                                                              float* __restrict__ out)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
-    float s = 0.0f;
-    for (int64_t c = 0; c < nchunk; ++c) s += part[c * n + e];
-    out[e] += s;
+    __shared__ float sh[SUM_WAVES][64];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int64_t e = (int64_t)blockIdx.x * 64 + l;
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+    if (e < n) {
+        int64_t c = w;
+        for (; c + 3 * SUM_WAVES < nchunk; c += 4 * SUM_WAVES) {
+            a0 += part[c * n + e];
+            a1 += part[(c + SUM_WAVES) * n + e];
+            a2 += part[(c + 2 * SUM_WAVES) * n + e];
+            a3 += part[(c + 3 * SUM_WAVES) * n + e];
+        }
+        for (; c < nchunk; c += SUM_WAVES) a0 += part[c * n + e];
+    }
+    sh[w][l] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (w != 0 || e >= n) return;
+    float t = 0.0f;
+#pragma unroll
+    for (int i = 0; i < SUM_WAVES; ++i) t += sh[i][l];
+    out[e] += t;
 }
 
-// db[o] += sum over (sample, position) of dZ[b][o][p]; one block per channel
+// Bias gradient partials: part[split][o] = sum over the split's share of the (sample,
+// position) pairs of dZ[b][o][p]; grid (CO, BIAS_SPLIT), added in a fixed order afterwards.
+constexpr int BIAS_SPLIT = 64;
+static_assert(BIAS_SPLIT <= 256, "the bias partials fit the smallest weight-partial buffer");
+
 __global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ dZ, int64_t B,
-                                                   int P, float* __restrict__ db)
+                                                   int P, float* __restrict__ part)
 {
     __shared__ float sh[256];
     const int o = blockIdx.x;
+    const int64_t total = B * P;
+    const int64_t per = (total + BIAS_SPLIT - 1) / BIAS_SPLIT;
+    const int64_t i0 = (int64_t)blockIdx.y * per, i1 = min(i0 + per, total);
     float acc = 0.0f;
-    for (int64_t i = threadIdx.x; i < B * P; i += 256) {
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
         const int64_t b = i / P;
         const int p = (int)(i - b * P);
         acc += from_bf16(dZ[(b * CO + o) * P + p]);
@@ -236,7 +265,7 @@ __global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ 
         if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) db[o] += sh[0];
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.y * CO + o] = sh[0];
 }
 
 // ---- patch gather -------------------------------------------------------------------------
@@ -472,9 +501,12 @@ void conv_bwd_w(const uint16_t* dZ, const uint16_t* X, int64_t B, float* part, f
     hipLaunchKernelGGL(k_conv_bwd_w<G>, dim3((unsigned)((2 * NT + 3) / 4), (unsigned)nchunk),
                        dim3(256), 0, s, dZ, X, B, part);
     const int64_t n = (int64_t)CO * G::KPAD;
-    hipLaunchKernelGGL(k_sum_parts_ws, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part,
-                       nchunk, n, dW);
-    hipLaunchKernelGGL(k_bias_grad, dim3(CO), dim3(256), 0, s, dZ, B, G::PO, db);
+    hipLaunchKernelGGL(k_sum_parts_ws, dim3((unsigned)((n + 63) / 64)), dim3(SUM_THREADS), 0, s,
+                       part, nchunk, n, dW);
+    // the weight partials have been consumed: their buffer takes the bias partials
+    hipLaunchKernelGGL(k_bias_grad, dim3(CO, BIAS_SPLIT), dim3(256), 0, s, dZ, B, G::PO, part);
+    hipLaunchKernelGGL(k_sum_parts_ws, dim3((CO + 63) / 64), dim3(SUM_THREADS), 0, s, part,
+                       (int64_t)BIAS_SPLIT, (int64_t)CO, db);
 }
 
 }  // namespace

@@ -103,6 +103,86 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ W
     }
 }
 
+// Forward for the layers whose sample has a multiple of 16 output positions: one block per
+// sample.  The sample's input is staged in LDS, zero-padded as far as the windows reach past
+// it (PD below, up to PD above), with a table
+// of each K index's offset in it (channel, kz, ky, kx), so that a B-fragment element costs a
+// table entry (four per 16-byte read) and one LDS read, with no index arithmetic or bounds
+// check; K indices past the real taps read as zero.  The wavefronts share the sample's
+// (output-channel tile, column tile) pairs.
+template <class G>
+__global__ __launch_bounds__(256) void k_conv_fwd_lds(const uint16_t* __restrict__ W,
+                                                      const float* __restrict__ bias,
+                                                      const uint16_t* __restrict__ X,
+                                                      float* __restrict__ Z,
+                                                      uint16_t* __restrict__ A)
+{
+    static_assert(G::PO % 16 == 0, "whole column tiles per sample");
+    // padding: PD below; above, only as far as the last window reaches past the input
+    constexpr int REACH = G::ST * (G::DO - 1) - G::PD + G::K;   // one past the last index read
+    constexpr int PH = REACH > G::DI ? REACH - G::DI : 0;
+    constexpr int DP = G::PD + G::DI + PH, PP = DP * DP * DP;
+    static_assert(G::CI * PP * 2 + G::KPAD * 4 <= 65536, "staged input and table fit 64 KB");
+    constexpr int NCT = G::PO / 16;            // column tiles per sample
+    __shared__ uint16_t xin[G::CI * PP];
+    __shared__ __align__(16) int koff[G::KPAD];
+    const int64_t b = blockIdx.x;
+    for (int k = threadIdx.x; k < G::KPAD; k += 256) {
+        int o = -1;
+        if (k < G::KREAL) {
+            const int c = k / G::KV, t = k - c * G::KV;
+            const int kz = t / (G::K * G::K), ky = (t / G::K) % G::K, kx = t % G::K;
+            o = c * PP + (kz * DP + ky) * DP + kx;
+        }
+        koff[k] = o;
+    }
+    for (int i = threadIdx.x; i < G::CI * PP; i += 256) xin[i] = 0;
+    __syncthreads();
+    const uint16_t* xb = X + b * G::CI * G::PI;
+    for (int i = threadIdx.x; i < G::CI * G::PI; i += 256) {
+        const int c = i / G::PI, r = i - c * G::PI;
+        const int z = r / (G::DI * G::DI), y = (r / G::DI) % G::DI, x = r % G::DI;
+        xin[c * PP + ((z + G::PD) * DP + (y + G::PD)) * DP + (x + G::PD)] = xb[i];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, g = lane >> 4, row = lane & 15;
+    for (int tI = threadIdx.x >> 6; tI < 2 * NCT; tI += 4) {
+        const int m0 = 16 * (tI / NCT);
+        const int p = (tI % NCT) * 16 + row;  // this lane's output position
+        const int oz = p / (G::DO * G::DO), oy = (p / G::DO) % G::DO, ox = p % G::DO;
+        const int base = ((G::ST * oz) * DP + G::ST * oy) * DP + G::ST * ox;
+        v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 3
+        for (int k0 = 0; k0 < G::KPAD; k0 += 16) {
+            const v4s Af = *reinterpret_cast<const v4s*>(W + (m0 + row) * G::KPAD + k0 + 4 * g);
+            const int4 ko = *reinterpret_cast<const int4*>(koff + k0 + 4 * g);
+            short bv[4];
+            const int kk[4] = {ko.x, ko.y, ko.z, ko.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if constexpr (G::KPAD != G::KREAL) {
+                    const short v = (short)xin[base + max(kk[j], 0)];
+                    bv[j] = kk[j] < 0 ? (short)0 : v;
+                } else {
+                    bv[j] = (short)xin[base + kk[j]];
+                }
+            }
+            v4s Bf;
+            Bf.x = bv[0]; Bf.y = bv[1]; Bf.z = bv[2]; Bf.w = bv[3];
+            acc = mfma(Af, Bf, acc);
+        }
+        const float av[4] = {acc.x, acc.y, acc.z, acc.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int m = m0 + 4 * g + j;
+            const float z = av[j] + bias[m];
+            const int64_t o = (b * CO + m) * G::PO + p;
+            if (Z) Z[o] = z;
+            A[o] = to_bf16(silu(z));
+        }
+    }
+}
+
 // ---- backward through the input: dZ_prev = (W^T dZ) * SiLU'(Z_prev) -----------------------
 // C tile = 16 input channels x 16 columns (sample, input position).
 template <class G>
@@ -478,6 +558,10 @@ void conv_fwd(const uint16_t* W, const float* b, const uint16_t* X, int64_t B, f
               uint16_t* A, hipStream_t s)
 {
     const int64_t ntile = B * G::PO / 16;
+    if constexpr (G::PO % 16 == 0 && G::PD > 0) {
+        hipLaunchKernelGGL(k_conv_fwd_lds<G>, dim3((unsigned)B), dim3(256), 0, s, W, b, X, Z, A);
+        return;
+    }
     hipLaunchKernelGGL(k_conv_fwd<G>, dim3((unsigned)((ntile + 3) / 4), 2), dim3(256), 0, s, W, b,
                        X, B, Z, A);
 }

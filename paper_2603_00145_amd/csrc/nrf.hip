@@ -218,7 +218,7 @@ __device__ __forceinline__ void tile_forward(const NrfArgs& a, const Lds& s, con
         for (int t = 0; t < KT; ++t) acc = mfma(s.w_in[(o * KT + t) * 64 + lane], b0[t], acc);
         T.z[0][o] = acc;
         T.act[0][o] = pack4(silu(acc.x), silu(acc.y), silu(acc.z), silu(acc.w));
-        if (w) store_fm(w->a[1], f, w->P, p, T.act[0][o]);
+        if (w && DEPTH > 1) store_fm(w->a[1], f, w->P, p, T.act[0][o]);
     }
     // hidden layers
 #pragma unroll
@@ -233,7 +233,7 @@ __device__ __forceinline__ void tile_forward(const NrfArgs& a, const Lds& s, con
             for (int t = 0; t < 4; ++t) acc = mfma(Wl[(o * 4 + t) * 64 + lane], T.act[l - 1][t], acc);
             T.z[l][o] = acc;
             T.act[l][o] = pack4(silu(acc.x), silu(acc.y), silu(acc.z), silu(acc.w));
-            if (w) store_fm(w->a[l + 1], f, w->P, p, T.act[l][o]);
+            if (w && l + 1 < DEPTH) store_fm(w->a[l + 1], f, w->P, p, T.act[l][o]);
         }
     }
 }
@@ -294,6 +294,11 @@ __global__ __launch_bounds__(256) void k_nrf_chain(const NrfArgs a, NrfWork w)
     const int lane = threadIdx.x & 63, g = lane >> 4, row = lane & 15;
     const int64_t P = w.P;
     const int64_t ntiles = P / 16;
+    // the output layer's gradient over this wavefront's points: gwo[4 o + j] for feature
+    // 16 o + 4 g + j (sum of dzo a_D), gbo the sum of dzo (lanes of group 0)
+    float gwo[16], gbo = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) gwo[i] = 0.0f;
     for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntiles;
          tile += (int64_t)gridDim.x * 4) {
         const int64_t p = tile * 16 + row;
@@ -309,7 +314,15 @@ __global__ __launch_bounds__(256) void k_nrf_chain(const NrfArgs a, NrfWork w)
         if (valid) dl = a.dl_dr[((int64_t)vz * a.ny + vy) * a.nx + vx];
         const float th = tanhf(zo);
         const float dzo = valid ? dl * a.scale * a.out_scale * (1.0f - th * th) : 0.0f;
-        if (g == 0) w.dzo[p] = dzo;
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const v4s h = T.act[DEPTH - 1][o];
+            gwo[4 * o + 0] += dzo * from_bf16((uint16_t)h.x);
+            gwo[4 * o + 1] += dzo * from_bf16((uint16_t)h.y);
+            gwo[4 * o + 2] += dzo * from_bf16((uint16_t)h.z);
+            gwo[4 * o + 3] += dzo * from_bf16((uint16_t)h.w);
+        }
+        if (g == 0) gbo += dzo;
         // dA_D = dzo w_out, then back through the layers
         v4f da[4];
 #pragma unroll
@@ -341,6 +354,21 @@ __global__ __launch_bounds__(256) void k_nrf_chain(const NrfArgs a, NrfWork w)
                 da[i] = acc;
             }
         }
+    }
+    // sum over the 16 points of each lane group, then one partial per wavefront:
+    // part[wave][64] for w_out, then part[nwaves * 64 + wave] for b_out
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        for (int o = 1; o < 16; o <<= 1) gwo[i] += __shfl_xor(gwo[i], o, 64);
+    for (int o = 1; o < 16; o <<= 1) gbo += __shfl_xor(gbo, o, 64);
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row == 0) {
+#pragma unroll
+        for (int o = 0; o < 4; ++o)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) w.part[wid * W + 16 * o + 4 * g + j] = gwo[4 * o + j];
+        if (g == 0) w.part[nwaves * W + wid] = gbo;
     }
 }
 
@@ -485,32 +513,6 @@ __global__ __launch_bounds__(SUM_THREADS) void k_sum_parts_in(const float* __res
     out[m * N + nf] += s;
 }
 
-// Partial row sums over a chunk of points: part[chunk][m] = sum_{p in chunk} l(m, p) v(p),
-// with l = the BF16 row L[m] (or 1 if L is NULL) and v = the f32 vector (or 1 if NULL).
-// Grid (rows, chunks of RD_CHUNK points); the chunks are added in a fixed order afterwards.
-constexpr int RD_CHUNK = 8192;
-
-__global__ __launch_bounds__(256) void k_rowdot_part(const uint16_t* __restrict__ L,
-                                                     const float* __restrict__ v, int64_t P,
-                                                     int rows, float* __restrict__ part)
-{
-    __shared__ float sh[256];
-    const int m = blockIdx.x;
-    const int64_t p0 = (int64_t)blockIdx.y * RD_CHUNK;
-    const int64_t p1 = min(p0 + RD_CHUNK, P);
-    const uint16_t* r = L ? L + (int64_t)m * P : nullptr;
-    float acc = 0.0f;
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += 256)
-        acc += (r ? from_bf16(r[p]) : 1.0f) * (v ? v[p] : 1.0f);
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.y * rows + m] = sh[0];
-}
-
 __global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ in,
                                                  uint16_t* __restrict__ out, int64_t n)
 {
@@ -545,9 +547,10 @@ void launch_fwd_t(const NrfArgs& a, hipStream_t s)
 }
 
 template <int KT, int DEPTH>
-void launch_chain_t(const NrfArgs& a, const NrfWork& w, hipStream_t s)
+void launch_chain_t(const NrfArgs& a, const NrfWork& w, hipStream_t s, int64_t* nwaves)
 {
     const unsigned nb = blocks_for_tiles(k_nrf_chain<KT, DEPTH>, w.P / 16);
+    *nwaves = (int64_t)nb * 4;
     hipLaunchKernelGGL((k_nrf_chain<KT, DEPTH>), dim3(nb), dim3(256), 0, s, a, w);
 }
 
@@ -574,29 +577,25 @@ hipError_t launch_nrf_forward(const NrfArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-// out[m] += sum_p l(m, p) v(p) for m < rows (see k_rowdot_part); part needs
-// rows * ceil(P / RD_CHUNK) floats.
-static void rowdot(const uint16_t* L, const float* v, int64_t P, int rows, float* part, float* out,
-                   hipStream_t s)
-{
-    const int64_t nchunk = (P + RD_CHUNK - 1) / RD_CHUNK;
-    hipLaunchKernelGGL(k_rowdot_part, dim3((unsigned)rows, (unsigned)nchunk), dim3(256), 0, s, L,
-                       v, P, rows, part);
-    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((rows + 63) / 64)), dim3(SUM_THREADS), 0, s, part,
-                       nchunk, (int64_t)rows, out);
-}
-
 size_t nrf_part_floats(int64_t P, int in_pad)
 {
     const int64_t gemm = ((P + GPB - 1) / GPB) * W * ((in_pad > W ? in_pad : W) + 1);
-    const int64_t rows = W * ((P + RD_CHUNK - 1) / RD_CHUNK);
+    // the chain kernel's output-layer partials: W + 1 per wavefront, at most P/16 + 3 of them
+    const int64_t rows = (int64_t)(W + 1) * (P / 16 + 4);
     return (size_t)(gemm > rows ? gemm : rows);
 }
 
 hipError_t launch_nrf_backward(const NrfArgs& a, const NrfWork& w, hipStream_t s)
 {
     if (a.n_points <= 0) return hipSuccess;
-    GM_NRF_DISPATCH(launch_chain_t, a, w, s)
+    int64_t nwaves = 0;
+    GM_NRF_DISPATCH(launch_chain_t, a, w, s, &nwaves)
+    // the output layer's gradient from the chain kernel's per-wavefront partials (the layer
+    // GEMMs below reuse the partial buffer after these sums)
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(SUM_THREADS), 0, s, w.part, nwaves, (int64_t)W,
+                       a.g_w_out);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(SUM_THREADS), 0, s, w.part + nwaves * W, nwaves,
+                       (int64_t)1, a.g_b_out);
     const int64_t nchunk = (w.P + GPB - 1) / GPB;
     for (int l = 0; l < a.depth; ++l) {
         const int N = l == 0 ? a.in_pad : W;
@@ -623,8 +622,6 @@ hipError_t launch_nrf_backward(const NrfArgs& a, const NrfWork& w, hipStream_t s
         hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(SUM_THREADS), 0, s, rowpart, nchunk, (int64_t)W,
                            dbias);
     }
-    rowdot(w.a[a.depth], w.dzo, w.P, W, w.part, a.g_w_out, s);
-    rowdot(nullptr, w.dzo, w.P, 1, w.part, a.g_b_out, s);
     return hipGetLastError();
 }
 

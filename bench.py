@@ -263,15 +263,20 @@ def main():
     fwd_rate = pairs / (stage_ms["render"] / 1e3)
     bwd_rate = pairs / (bwd_ms / 1e3)
     # dominant kernel (one launch per step each) and its roofline
+    # the two pair kernels' rooflines (one launch per step each); the dominant one is `roofline`
+    def kernel_roofline(stage):
+        if stage == "render":
+            flop, instr, kname = FLOP_FWD, FWD_VALU_INSTR + EXP_SLOTS, "k_render"
+        else:
+            flop, instr, kname = FLOP_BWD, 2 * FWD_VALU_INSTR + EXP_SLOTS, "k_partials"
+        achieved = flop * pairs / (stage_ms[stage] / 1e3) / 1e12
+        peak = alu_peak_tflops(flop, instr)
+        return {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": recorded_traffic(kname),
+                "flop_per_pair": flop, "avg_kernel_ms": stage_ms[stage]}
+
     dom = "render" if stage_ms["render"] >= stage_ms["partials"] else "partials"
-    if dom == "render":
-        flop, instr = FLOP_FWD, FWD_VALU_INSTR + EXP_SLOTS
-        kname = "k_render"
-    else:
-        flop, instr = FLOP_BWD, 2 * FWD_VALU_INSTR + EXP_SLOTS
-        kname = "k_partials"
-    achieved = flop * pairs / (stage_ms[dom] / 1e3) / 1e12
-    peak = alu_peak_tflops(flop, instr)
+    rooflines = {s: kernel_roofline(s) for s in ("render", "partials")}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -294,9 +299,8 @@ def main():
         "loss_path": "two calls" if args.unfused_loss else "fused into the render",
         "adam_path": "four calls after the chain rule" if args.unfused_adam
                      else "fused into the chain rule (the chain stage includes Adam)",
-        "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": recorded_traffic(kname),
-                     "flop_per_pair": flop, "avg_kernel_ms": stage_ms[dom]},
+        "roofline": rooflines[dom],
+        "roofline_pair_kernels": {r["kernel"]: r for r in rooflines.values()},
         "cpu_baseline": cpu,
         "iters_to_psnr": recorded_iters_to_psnr(),
     }

@@ -7,10 +7,10 @@
 // prepares that Gaussian's piece (box intersect tile) in LDS.  Then the pieces are taken in
 // list order.  A lane holds one (x, y) column of a piece's footprint and walks the piece's
 // z-range, so the in-plane part of the exponent is formed once per column and each voxel
-// costs two FMAs, one exp2 and one accumulate.  Two consecutive pieces whose footprints fit
-// in 32 columns share the wave (one per half); the first half adds into the tile before the
-// second, so every voxel's sum is still formed in ascending Gaussian order and the result
-// is the same on every run.
+// costs two FMAs, one exp2 and one accumulate.  Two consecutive pieces whose footprints sum to
+// at most 64 columns share the wave (the first piece's columns on the low lanes); the first
+// piece's lanes add into the tile before the second's, so every voxel's sum is still formed
+// in ascending Gaussian order and the result is the same on every run.
 #include "gm_internal.h"
 
 namespace {
@@ -103,8 +103,8 @@ __device__ __forceinline__ void single_piece(const Piece& p, float* acc, int F, 
     }
 }
 
-// Two pieces, one per half-wave (lane's piece p, column f); KM = the larger z extent.  The
-// first half's read-add-writes complete before the second half's are issued.
+// Two pieces side by side in the wave (lane's piece p, column f); KM = the larger z extent.
+// The first piece's read-add-writes complete before the second piece's are issued.
 template <int KM>
 __device__ __forceinline__ void paired_pieces(const Piece& p, float* acc, bool act, bool first,
                                               uint32_t f, int wza, int wzb)
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(64) void k_render(const RenderArgs a)
     for (int b0 = s; b0 < e; b0 += RB) {
         const int nb = min(RB, e - b0);
         __syncthreads();
-        bool small = false;
+        int myF = 0, myWz = 0;  // this lane's piece: footprint area and z extent
         if (lane < nb) {
             const int gid = (int)((uint32_t)pg[b0 + lane] & GM_ID_MASK);
             const float4* src = reinterpret_cast<const float4*>(recbase + (size_t)gid * 16);
@@ -197,21 +197,24 @@ __global__ __launch_bounds__(64) void k_render(const RenderArgs a)
             p.mx = (int)magic20((uint32_t)p.wx);
             p.base = ((iz0 - t0z) * GM_TY + (iy0 - t0y)) * GM_TX + (ix0 - t0x);
             pc[lane] = p;
-            small = p.F <= 32;
+            myF = p.F;
+            myWz = p.wz;
         }
-        // bit j: piece j's footprint fits in half a wave
-        const uint64_t sm = __ballot(small);
+        // bit j: pieces j and j + 1 fit side by side in the wave (footprints summing to <= 64)
+        const int nextF = __shfl_down(myF, 1, 64);
+        const uint64_t pm = __ballot(lane + 1 < nb && myF + nextF <= 64);
         __syncthreads();
         int j = 0;
 #pragma unroll 1
         while (j < nb) {
-            if (((sm >> j) & 3u) == 3u) {
-                // pieces j and j+1 side by side, one per half-wave
-                const int h = lane >> 5;
+            if ((pm >> j) & 1u) {
+                // pieces j and j+1 side by side: lanes [0, Fa) take piece j, the next Fb piece j+1
+                const int Fa = __builtin_amdgcn_readlane(myF, j);
+                const int wza = __builtin_amdgcn_readlane(myWz, j);
+                const int wzb = __builtin_amdgcn_readlane(myWz, j + 1);
+                const int h = lane >= Fa ? 1 : 0;
                 const Piece p = pc[j + h];
-                const int wza = __builtin_amdgcn_readlane(p.wz, 0);
-                const int wzb = __builtin_amdgcn_readlane(p.wz, 32);
-                const uint32_t f = (uint32_t)(lane & 31);
+                const uint32_t f = (uint32_t)(h ? lane - Fa : lane);
                 const bool act = f < (uint32_t)p.F;
                 const bool first = h == 0;
                 static_assert(GM_TZ == 4, "z extents 1..4 are dispatched below");

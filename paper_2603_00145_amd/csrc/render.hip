@@ -33,8 +33,8 @@ struct Piece {
     int wx, F, wz, mx, base;
 };
 
-// Keeps the compiler from moving or merging LDS accesses across this point.  The two halves
-// of a wave that hold two different Gaussians may touch the same voxel; their
+// Keeps the compiler from moving or merging LDS accesses across this point.  The two groups of
+// lanes of a wave that hold two different Gaussians may touch the same voxel; their
 // read-add-writes must stay two separate, ordered sequences.
 __device__ __forceinline__ void lds_order() { __asm__ __volatile__("" ::: "memory"); }
 

@@ -91,3 +91,27 @@ def test_chain_adam_rejects_bad_arguments(api):
     short = api.GaussParams(*(t[:-1] for t in m.tensors()))
     with pytest.raises(_lib.GmError, match="moments"):
         api.chain_adam(p, b, [0, 1, 2], short, v, LRS, 1)
+
+
+def test_chain_adam_edges(api):
+    """No listed grid (only the anisotropy term moves the scales) and no Gaussian at all."""
+    p, b, rng = problem(api, 4, n_g=80, n=17)
+    m0, v0 = moments(api, p, rng, True)
+    pa, ma, va = clone(api, p), clone(api, m0), clone(api, v0)
+    grads = api.GaussParams.zeros_like(p)
+    api.chain(pa, b, [], grads, 0.5, 1.0)
+    for prm, gr, mm, vv, lr in zip(pa.tensors(), grads.tensors(), ma.tensors(), va.tensors(), LRS):
+        api.adam_step(prm, gr, mm, vv, lr, 1)
+    pb, mb, vb = clone(api, p), clone(api, m0), clone(api, v0)
+    api.chain_adam(pb, b, [], mb, vb, LRS, 1, 0.5, 1.0)
+    torch.cuda.synchronize()
+    for x, y in zip(pa.tensors() + ma.tensors() + va.tensors(),
+                    pb.tensors() + mb.tensors() + vb.tensors()):
+        assert torch.equal(x, y)
+    g0 = inputs.init_anisotropic(17, 1, rng).subset(slice(0, 0))
+    p0 = api.GaussParams.from_host(g0)
+    b0 = api.Bins(0, [inputs.volume_grid(17)])
+    b0.bin(p0)
+    m, v = moments(api, p0, rng, True)
+    api.chain_adam(p0, b0, [0], m, v, LRS, 1)     # nothing to do, no error
+    torch.cuda.synchronize()

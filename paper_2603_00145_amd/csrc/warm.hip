@@ -237,6 +237,102 @@ __global__ __launch_bounds__(256) void k_conv_bwd_x(const uint16_t* __restrict__
     }
 }
 
+// Backward through the input of a stride-2, 3-tap, pad-1 layer by parity class.  Along an axis,
+// input position i = 2a + p receives tap 1 from output a when p = 0, and taps 0 and 2 from
+// outputs a + 1 and a when p = 1 (output DO counts as zero).  The 8 classes of positions by
+// (z, y, x) parity are then dense GEMMs over their own taps only (2^popcount(class) per
+// channel, 1/8 of the 27) instead of over all taps with zeros.  One block per sample: dZ staged
+// in LDS with a zero plane past the last output on each axis, and tables of each class's K
+// entries (output channel o major, then the taps): their offsets in the staged dZ and in W.
+template <class G>
+__global__ __launch_bounds__(256) void k_conv_bwd_x_par(const uint16_t* __restrict__ W,
+                                                        const uint16_t* __restrict__ dZ,
+                                                        const float* __restrict__ Zprev,
+                                                        uint16_t* __restrict__ dZprev)
+{
+    static_assert(G::ST == 2 && G::K == 3 && G::PD == 1 && G::DI == 2 * G::DO,
+                  "stride-2, 3-tap, pad-1 layer");
+    constexpr int H = G::DO;                  // positions per axis within a class
+    constexpr int NPC = H * H * H;            // positions per class
+    static_assert(NPC % 16 == 0, "whole column tiles per class");
+    constexpr int NCT = NPC / 16;
+    constexpr int DQ = G::DO + 1, QQ = DQ * DQ * DQ;
+    constexpr int KTOT = CO * 27;             // the classes' K entries together
+    __shared__ uint16_t dzs[CO * QQ];
+    __shared__ int boff[KTOT];
+    __shared__ int aoff[KTOT];
+    const int64_t b = blockIdx.x;
+    // tables; class c = pz << 2 | py << 1 | px, entry k of class c at kbase(c) + k
+    for (int e = threadIdx.x; e < KTOT; e += 256) {
+        int c = 0, base = 0;
+        while (base + CO * (1 << __popc(c)) <= e) {
+            base += CO * (1 << __popc(c));
+            ++c;
+        }
+        const int nc = 1 << __popc(c);
+        const int k = e - base, o = k / nc;
+        int bits = k % nc, tap = 0, d = 0;
+        // axes x, y, z; an odd-parity axis takes one bit of the tap number
+        const int wt[3] = {1, G::K, G::K * G::K}, wd[3] = {1, DQ, DQ * DQ};
+        for (int ax = 0; ax < 3; ++ax) {
+            int kx = 1, dx = 0;
+            if ((c >> ax) & 1) {
+                const int pick = bits & 1;
+                bits >>= 1;
+                kx = pick ? 2 : 0;
+                dx = pick ? 0 : 1;
+            }
+            tap += kx * wt[ax];
+            d += dx * wd[ax];
+        }
+        boff[e] = o * QQ + d;
+        aoff[e] = o * G::KPAD + tap;
+    }
+    for (int i = threadIdx.x; i < CO * QQ; i += 256) dzs[i] = 0;
+    __syncthreads();
+    const uint16_t* dzb = dZ + b * CO * G::PO;
+    for (int i = threadIdx.x; i < CO * G::PO; i += 256) {
+        const int o = i / G::PO, r = i - o * G::PO;
+        const int z = r / (G::DO * G::DO), y = (r / G::DO) % G::DO, x = r % G::DO;
+        dzs[o * QQ + (z * DQ + y) * DQ + x] = dzb[i];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, g = lane >> 4, row = lane & 15;
+    for (int tI = threadIdx.x >> 6; tI < 8 * 2 * NCT; tI += 4) {
+        const int c = tI / (2 * NCT), rem = tI - c * 2 * NCT;
+        const int m0 = 16 * (rem / NCT), ct = rem % NCT;
+        int kb = 0;
+        for (int d = 0; d < c; ++d) kb += CO * (1 << __popc(d));
+        const int kc = CO * (1 << __popc(c));
+        const int q = ct * 16 + row;         // this lane's position within the class
+        const int az = q / (H * H), ay = (q / H) % H, ax = q % H;
+        const int colbase = (az * DQ + ay) * DQ + ax;
+        v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int k0 = 0; k0 < kc; k0 += 16) {
+            const int e0 = kb + k0 + 4 * g;
+            short av[4], bv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                av[j] = (short)W[aoff[e0 + j] + (m0 + row) * G::KV];
+                bv[j] = (short)dzs[colbase + boff[e0 + j]];
+            }
+            v4s Af, Bf;
+            Af.x = av[0]; Af.y = av[1]; Af.z = av[2]; Af.w = av[3];
+            Bf.x = bv[0]; Bf.y = bv[1]; Bf.z = bv[2]; Bf.w = bv[3];
+            acc = mfma(Af, Bf, acc);
+        }
+        const int iz = 2 * az + ((c >> 2) & 1), iy = 2 * ay + ((c >> 1) & 1), ix = 2 * ax + (c & 1);
+        const int pin = (iz * G::DI + iy) * G::DI + ix;
+        const float r[4] = {acc.x, acc.y, acc.z, acc.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int cc = m0 + 4 * g + j;
+            const int64_t o = (b * G::CI + cc) * G::PI + pin;
+            dZprev[o] = to_bf16(r[j] * dsilu(Zprev[o]));
+        }
+    }
+}
+
 // ---- backward to the weights: split over chunks of 256 columns (sample, output position) ---
 // C tile = 16 output channels x 16 (c, tap); partial[chunk][o][k].
 template <class G>
@@ -570,6 +666,12 @@ template <class G>
 void conv_bwd_x(const uint16_t* W, const uint16_t* dZ, int64_t B, const float* Zprev,
                 uint16_t* dZprev, hipStream_t s)
 {
+    if constexpr (G::ST == 2 && G::K == 3 && G::PD == 1 && G::DI == 2 * G::DO &&
+                  (G::DO * G::DO * G::DO) % 16 == 0 && G::CI == 32) {
+        hipLaunchKernelGGL(k_conv_bwd_x_par<G>, dim3((unsigned)B), dim3(256), 0, s, W, dZ, Zprev,
+                           dZprev);
+        return;
+    }
     const int64_t ntile = B * G::PI / 16;
     hipLaunchKernelGGL(k_conv_bwd_x<G>, dim3((unsigned)((ntile + 3) / 4), 2), dim3(256), 0, s, W,
                        dZ, B, Zprev, dZprev);

@@ -619,19 +619,27 @@ __global__ __launch_bounds__(256) void k_ws_targets(const float* __restrict__ ls
 }
 
 // head weight gradients: dWl[j][c] += sum_b dout[b][j] a4[b][c]; dbl[j] += sum_b dout[b][j]
+// Head weight/bias gradient partials over HG_SPLIT ranges of samples: part[split][j][c] =
+// sum of dout[b][j] a4[b][c], then part[HG_SPLIT * 256 + split * 8 + j] = sum of dout[b][j];
+// the ranges are added in a fixed order afterwards.
+constexpr int HG_SPLIT = 64;
+static_assert(8 * CO == 256, "one thread per head weight");
+
 __global__ __launch_bounds__(256) void k_ws_head_grad(const float* __restrict__ dout,
                                                       const float* __restrict__ a4, int64_t n,
-                                                      float* __restrict__ dwl, float* __restrict__ dbl)
+                                                      float* __restrict__ part)
 {
     const int t = threadIdx.x;  // 256 = 8 x 32
     const int j = t / CO, c = t % CO;
+    const int64_t per = (n + HG_SPLIT - 1) / HG_SPLIT;
+    const int64_t b0 = (int64_t)blockIdx.x * per, b1 = min(b0 + per, n);
     float s = 0.0f, sb = 0.0f;
-    for (int64_t b = 0; b < n; ++b) {
+    for (int64_t b = b0; b < b1; ++b) {
         s += dout[8 * b + j] * a4[b * CO + c];
         if (c == 0) sb += dout[8 * b + j];
     }
-    dwl[j * CO + c] += s;
-    if (c == 0) dbl[j] += sb;
+    part[(int64_t)blockIdx.x * 256 + t] = s;
+    if (c == 0) part[(int64_t)HG_SPLIT * 256 + blockIdx.x * 8 + j] = sb;
 }
 
 __global__ __launch_bounds__(256) void k_mean(const float* __restrict__ v, int64_t n,
@@ -743,7 +751,12 @@ hipError_t launch_ws_backward(const WsNet& net, const uint16_t* X0, int64_t B, c
                               const WsHeadArgs& head, const WsGrads& g, float* loss, hipStream_t s)
 {
     hipLaunchKernelGGL(k_mean, dim3(1), dim3(256), 0, s, head.loss_each, B, loss);
-    hipLaunchKernelGGL(k_ws_head_grad, dim3(1), dim3(256), 0, s, head.dout, head.a4, B, g.wl, g.bl);
+    hipLaunchKernelGGL(k_ws_head_grad, dim3(HG_SPLIT), dim3(256), 0, s, head.dout, head.a4, B,
+                       w.part);
+    hipLaunchKernelGGL(k_sum_parts_ws, dim3(4), dim3(SUM_THREADS), 0, s, w.part,
+                       (int64_t)HG_SPLIT, (int64_t)256, g.wl);
+    hipLaunchKernelGGL(k_sum_parts_ws, dim3(1), dim3(SUM_THREADS), 0, s,
+                       w.part + (int64_t)HG_SPLIT * 256, (int64_t)HG_SPLIT, (int64_t)8, g.bl);
     // layer 4 (dZ4 written by the head)
     conv_bwd_w<G4>(w.dz[3], w.a[2], B, w.part, g.w[3], g.b[3], s);
     conv_bwd_x<G4>(net.w[3], w.dz[3], B, w.z[2], w.dz[2], s);

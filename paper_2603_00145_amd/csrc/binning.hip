@@ -146,21 +146,25 @@ __global__ __launch_bounds__(256) void k_emit(const EmitArgs a)
 }
 
 // ---- radix sort --------------------------------------------------------------------------
-constexpr int RS_THREADS = 256;
+// The scatter's block holds 4096 keys (32 KB of LDS for keys and values): eight waves of
+// eight 64-key rounds, so that a CU keeps 32 waves in flight through the load and store bursts.
+constexpr int RS_THREADS = 512;
 constexpr int RS_WAVES = RS_THREADS / 64;
-constexpr int RS_ROUNDS = 16;
+constexpr int RS_ROUNDS = 8;
 constexpr int RS_WAVE_KEYS = 64 * RS_ROUNDS;
 constexpr int RS_BLOCK_KEYS = RS_WAVE_KEYS * RS_WAVES;
+constexpr int RS_HIST_THREADS = 256;  // one per digit
+static_assert(RS_THREADS >= 256 && RS_THREADS % 256 == 0, "the digit phase uses the first 256 threads");
 
-__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t* keys, int64_t n,
-                                                         int shift, uint32_t mask,
-                                                         int32_t* ghist, int64_t nblocks)
+__global__ __launch_bounds__(RS_HIST_THREADS) void k_rs_hist(const uint32_t* keys, int64_t n,
+                                                              int shift, uint32_t mask,
+                                                              int32_t* ghist, int64_t nblocks)
 {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RS_BLOCK_KEYS;
-    for (int k = threadIdx.x; k < RS_BLOCK_KEYS; k += RS_THREADS) {
+    for (int k = threadIdx.x; k < RS_BLOCK_KEYS; k += RS_HIST_THREADS) {
         const int64_t i = base + k;
         if (i < n) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
     }
@@ -168,8 +172,8 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t* keys, in
     ghist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = (int32_t)h[threadIdx.x];
 }
 
-// Stable scatter.  Wave w of the block owns keys [base + w*1024, base + (w+1)*1024) and takes
-// them in 16 rounds of 64 consecutive keys; lanes with equal digits are matched with ballots,
+// Stable scatter.  Wave w of the block owns keys [base + w*512, base + (w+1)*512) and takes
+// them in 8 rounds of 64 consecutive keys; lanes with equal digits are matched with ballots,
 // so every key learns how many equal-digit keys precede it in the block.  The block's keys are
 // first placed in LDS in digit order, then written out by consecutive threads, so that each
 // digit's run leaves the block as one contiguous stretch of stores.
@@ -216,27 +220,33 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* kin,
     // per digit: offsets of the waves' runs, the digit's block total, and its block-local
     // start (exclusive scan over the 256 digits: within each wave with shuffles, then across
     // the four waves)
-    const int d = threadIdx.x;  // RS_THREADS == 256 digits
-    uint32_t run = 0;
+    // (thread d < 256 takes digit d; waves 0-3 are whole, so the shuffles see full waves)
+    const int d = threadIdx.x;
+    const bool dig = d < 256;
+    uint32_t run = 0, incl = 0;
+    if (dig) {
 #pragma unroll
-    for (int w = 0; w < RS_WAVES; ++w) {
-        const uint32_t t = wcnt[w][d];
-        wcnt[w][d] = run;
-        run += t;
-    }
-    uint32_t incl = run;
+        for (int w = 0; w < RS_WAVES; ++w) {
+            const uint32_t t = wcnt[w][d];
+            wcnt[w][d] = run;
+            run += t;
+        }
+        incl = run;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(incl, o);
-        if (lane >= o) incl += y;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o);
+            if (lane >= o) incl += y;
+        }
+        if (lane == 63) wsum[wave] = incl;
     }
-    if (lane == 63) wsum[wave] = incl;
     __syncthreads();
-    uint32_t before_w = 0;
-    for (int w = 0; w < wave; ++w) before_w += wsum[w];
-    const uint32_t ds = before_w + incl - run;
-    dstart[d] = ds;
-    obase[d] = goff[(int64_t)d * nblocks + blockIdx.x] - (int64_t)ds;
+    if (dig) {
+        uint32_t before_w = 0;
+        for (int w = 0; w < wave; ++w) before_w += wsum[w];
+        const uint32_t ds = before_w + incl - run;
+        dstart[d] = ds;
+        obase[d] = goff[(int64_t)d * nblocks + blockIdx.x] - (int64_t)ds;
+    }
     __syncthreads();
     // place the keys in digit order in LDS (positions < RS_BLOCK_KEYS by construction)
 #pragma unroll
@@ -383,7 +393,7 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
         const int shift = p * dbits;
         const int db = (bits - shift) < dbits ? (bits - shift) : dbits;
         const uint32_t mask = (1u << db) - 1u;
-        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(RS_THREADS), 0, s, ki, n, shift,
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(RS_HIST_THREADS), 0, s, ki, n, shift,
                            mask, ghist, nb);
         err = launch_scan_i32_to_i64(ghist, goff, hn, sws, s);
         if (err != hipSuccess) return err;

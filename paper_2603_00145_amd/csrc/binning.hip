@@ -147,29 +147,56 @@ __global__ __launch_bounds__(256) void k_emit(const EmitArgs a)
 
 // ---- radix sort --------------------------------------------------------------------------
 // The scatter's block holds 4096 keys (32 KB of LDS for keys and values): eight waves of
-// eight 64-key rounds, so that a CU keeps 32 waves in flight through the load and store bursts.
+// eight 64-key rounds, so that a CU keeps 24 waves (three blocks) in flight through the load
+// and store bursts.
 constexpr int RS_THREADS = 512;
 constexpr int RS_WAVES = RS_THREADS / 64;
 constexpr int RS_ROUNDS = 8;
 constexpr int RS_WAVE_KEYS = 64 * RS_ROUNDS;
 constexpr int RS_BLOCK_KEYS = RS_WAVE_KEYS * RS_WAVES;
 constexpr int RS_HIST_THREADS = 256;  // one per digit
+static_assert(RS_BLOCK_KEYS % (4 * RS_HIST_THREADS) == 0, "whole 16-byte loads per thread");
 static_assert(RS_THREADS >= 256 && RS_THREADS % 256 == 0, "the digit phase uses the first 256 threads");
 
+// Digit counts of one scatter block's keys.  Each wave counts into its own LDS histogram
+// (fewer colliding atomics), full blocks read four keys per 16-byte load, and the four
+// histograms are summed per digit at the end.
 __global__ __launch_bounds__(RS_HIST_THREADS) void k_rs_hist(const uint32_t* keys, int64_t n,
                                                               int shift, uint32_t mask,
                                                               int32_t* ghist, int64_t nblocks)
 {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    constexpr int HW = RS_HIST_THREADS / 64;
+    __shared__ uint32_t h[HW][256];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int d = lane; d < 256; d += 64) h[wave][d] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RS_BLOCK_KEYS;
-    for (int k = threadIdx.x; k < RS_BLOCK_KEYS; k += RS_HIST_THREADS) {
-        const int64_t i = base + k;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
+    const int64_t rem = n - base;
+    const int nk = rem < RS_BLOCK_KEYS ? (int)rem : RS_BLOCK_KEYS;
+    uint32_t* hw = h[wave];
+    if (nk == RS_BLOCK_KEYS && (reinterpret_cast<uintptr_t>(keys) & 15u) == 0) {
+        const uint4* k4 = reinterpret_cast<const uint4*>(keys + base);
+        uint4 v[RS_BLOCK_KEYS / 4 / RS_HIST_THREADS];
+#pragma unroll
+        for (int j = 0; j < RS_BLOCK_KEYS / 4 / RS_HIST_THREADS; ++j)
+            v[j] = k4[threadIdx.x + j * RS_HIST_THREADS];
+#pragma unroll
+        for (int j = 0; j < RS_BLOCK_KEYS / 4 / RS_HIST_THREADS; ++j) {
+            atomicAdd(&hw[(v[j].x >> shift) & mask], 1u);
+            atomicAdd(&hw[(v[j].y >> shift) & mask], 1u);
+            atomicAdd(&hw[(v[j].z >> shift) & mask], 1u);
+            atomicAdd(&hw[(v[j].w >> shift) & mask], 1u);
+        }
+    } else {
+        for (int k = threadIdx.x; k < nk; k += RS_HIST_THREADS)
+            atomicAdd(&hw[(keys[base + k] >> shift) & mask], 1u);
     }
     __syncthreads();
-    ghist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = (int32_t)h[threadIdx.x];
+    const int d = threadIdx.x;
+    uint32_t t = 0;
+#pragma unroll
+    for (int w = 0; w < HW; ++w) t += h[w][d];
+    ghist[(int64_t)d * nblocks + blockIdx.x] = (int32_t)t;
 }
 
 // Stable scatter.  Wave w of the block owns keys [base + w*512, base + (w+1)*512) and takes

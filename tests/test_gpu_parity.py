@@ -318,6 +318,25 @@ def test_edge_outside_face_and_one_tile(api):
         assert normwise(o.cpu().numpy(), r) <= TOL
 
 
+def test_edge_crowded_tile_many_sort_blocks(api):
+    """Twenty thousand Gaussians crowded into the tiles at one corner: tens of thousands of
+    entries share a handful of keys, so one digit holds whole sort blocks (4096 keys) and the
+    equal keys must keep ascending Gaussian order across blocks, in both passes (320 tiles:
+    9-bit keys)."""
+    n = 64
+    rng = np.random.default_rng(21)
+    g = inputs.init_anisotropic(n, 20500, rng)
+    g.mean[:20000] = (np.float32(-0.9) + rng.uniform(-0.01, 0.01, size=(20000, 3))).astype(np.float32)
+    g.log_scale[:20000] = np.float32(math.log(0.5 * 2 / n))
+    grids = [inputs.volume_grid(n), inputs.stack_grid("axial", n, 16, 1.0)]
+    say("crowded tile, sort blocks")
+    b = api.Bins(g.n, grids)
+    b.bin(api.GaussParams.from_host(g))
+    torch.cuda.synchronize()
+    assert b.n_pairs > 4 * 4096
+    check_bins_exact(api, b, g, grids)
+
+
 def test_edge_huge_gaussian_and_capacity_growth(api):
     n = 24
     g = inputs.init_anisotropic(n, 50, np.random.default_rng(2))

@@ -193,10 +193,12 @@ __global__ __launch_bounds__(RS_HIST_THREADS) void k_rs_hist(const uint32_t* key
     }
     __syncthreads();
     const int d = threadIdx.x;
-    uint32_t t = 0;
+    if (d <= (int)mask) {  // the pass's digits only: rows of the digit-major histogram
+        uint32_t t = 0;
 #pragma unroll
-    for (int w = 0; w < HW; ++w) t += h[w][d];
-    ghist[(int64_t)d * nblocks + blockIdx.x] = (int32_t)t;
+        for (int w = 0; w < HW; ++w) t += h[w][d];
+        ghist[(int64_t)d * nblocks + blockIdx.x] = (int32_t)t;
+    }
 }
 
 // Stable scatter.  Wave w of the block owns keys [base + w*512, base + (w+1)*512) and takes
@@ -272,7 +274,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* kin,
         for (int w = 0; w < wave; ++w) before_w += wsum[w];
         const uint32_t ds = before_w + incl - run;
         dstart[d] = ds;
-        obase[d] = goff[(int64_t)d * nblocks + blockIdx.x] - (int64_t)ds;
+        obase[d] = d <= (int)mask ? goff[(int64_t)d * nblocks + blockIdx.x] - (int64_t)ds : 0;
     }
     __syncthreads();
     // place the keys in digit order in LDS (positions < RS_BLOCK_KEYS by construction)
@@ -420,9 +422,11 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
         const int shift = p * dbits;
         const int db = (bits - shift) < dbits ? (bits - shift) : dbits;
         const uint32_t mask = (1u << db) - 1u;
+        // the histogram holds the pass's 2^db digit rows of nb block counts each
+        const int64_t hrows = (int64_t)nb << db;
         hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(RS_HIST_THREADS), 0, s, ki, n, shift,
                            mask, ghist, nb);
-        err = launch_scan_i32_to_i64(ghist, goff, hn, sws, s);
+        err = launch_scan_i32_to_i64(ghist, goff, hrows, sws, s);
         if (err != hipSuccess) return err;
         hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(RS_THREADS), 0, s, ki, vi, ko,
                            vo, n, shift, db, goff, nb);

@@ -31,13 +31,21 @@ UNIT = "Gaussian·voxel evals/s"
 # one exp2.
 FLOP_FWD = 25
 FLOP_BWD = 52
-# VALU issue model of MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 39.3e12 lane-ops/s
-# (78.6 TFLOP/s counting an FMA as 2; packed FP32 is not used).  Instructions per pair of
-# the direct forward formula: 16 non-transcendental + one v_exp_f32 whose issue cost, in
-# FMA slots, is measured by the probe and stated in the design doc.
+# Published MI355X peaks: FP32 vector 157.3 TFLOP/s (an FMA counts 2; the figure assumes
+# packed FP32, which this build never issues, so 78.6 TFLOP/s is the unpacked ceiling) and
+# HBM3E 8 TB/s.
+FP32_PEAK = 157.3e12
+FP32_PEAK_UNPACKED = 78.6e12
+# Transcendental rate (every pair takes one v_exp_f32): measured on this part with a scratch
+# probe of independent v_exp_f32 chains at full occupancy.
+EXP_RATE_MEASURED = 13.9e12
+# VALU issue model (secondary): 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 39.3e12 lane-slots/s;
+# the direct forward formula issues 16 non-transcendental instructions per pair, the backward
+# 32, and one v_exp_f32 costs EXP_SLOTS issue slots: the lane-slot rate over the measured exp
+# rate, 39.3e12 / 13.9e12 = 2.8.
 LANE_OPS = 256 * 4 * 16 * 2.4e9
 FWD_VALU_INSTR = 16
-EXP_SLOTS = 4.0
+EXP_SLOTS = LANE_OPS / EXP_RATE_MEASURED
 
 
 class TimingEvent:
@@ -83,8 +91,39 @@ class TimingEvent:
 
 
 def alu_peak_tflops(flop_per_pair, instr_per_pair):
-    """FLOP/s ceiling of a kernel whose every pair costs instr_per_pair VALU issue slots."""
+    """Issue-model FLOP/s ceiling of a kernel whose every pair costs instr_per_pair VALU slots."""
     return LANE_OPS / instr_per_pair * flop_per_pair / 1e12
+
+
+def pair_roof(flop_per_pair, exps_per_pair, p_f=FP32_PEAK, p_e=EXP_RATE_MEASURED):
+    """Pairs/s ceiling when the FLOP run at p_f and the exps at p_e, one after the other on the
+    same vector unit: R = 1 / (flop / p_f + exps / p_e)."""
+    return 1.0 / (flop_per_pair / p_f + exps_per_pair / p_e)
+
+
+def recorded_counters(kernel):
+    """Per-launch VALU instruction counts of `kernel` from its committed counter summary
+    (profiles/<kernel>_valu_c256.md), if taken on the kernel as built now, else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_valu_c256.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            key, _, val = line.partition(":")
+            fields[key.strip()] = val.strip()
+    if fields.get("kernel") != kernel:
+        return None
+    from bench_profile import kernel_digest
+    now = kernel_digest(kernel)
+    if now is None or now != fields.get("kernel_asm_sha256"):
+        return None
+    out = {}
+    for k, v in fields.items():
+        if k.startswith("SQ_"):
+            out[k] = float(v)
+    out["pairs_per_launch"] = float(fields.get("pairs_per_launch", "nan"))
+    return out
 
 
 def recorded_traffic(kernel):
@@ -101,7 +140,7 @@ def recorded_traffic(kernel):
                 fields[key] = val.strip()
     if fields.get("kernel") != kernel:
         return None
-    from paper_2603_00145_amd.profile_summary import kernel_digest
+    from bench_profile import kernel_digest
     now = kernel_digest(kernel)
     if now is None or now != fields.get("kernel_asm_sha256"):
         return None
@@ -138,6 +177,8 @@ def main():
                     help="chain rule into a gradient buffer, then Adam per group (four calls)")
     ap.add_argument("--cpu-sample-voxels", type=int, default=4096)
     ap.add_argument("--cpu-sample-gauss", type=int, default=100000)
+    ap.add_argument("--pairs-log", default="",
+                    help="write the contributing pairs of every step (warm-up included) here")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB before timing")
     args = ap.parse_args()
@@ -190,6 +231,7 @@ def main():
     ev = {k: [] for k in stages}
     step_no = [0]
     pair_log = []
+    all_pairs = []
 
     def step(e):
         # e: the step's events (created beforehand), or None for an untimed step
@@ -205,6 +247,7 @@ def main():
 
         mark("bin")
         bins.bin(p)
+        all_pairs.append(sum(bins.box_pairs_host))
         if record:
             pair_log.append(sum(bins.box_pairs_host))   # reported by gm_bin, no extra sync
         mark("render")
@@ -262,21 +305,64 @@ def main():
     bwd_ms = stage_ms["partials"] + stage_ms["chain"]
     fwd_rate = pairs / (stage_ms["render"] / 1e3)
     bwd_rate = pairs / (bwd_ms / 1e3)
-    # dominant kernel (one launch per step each) and its roofline
-    # the two pair kernels' rooflines (one launch per step each); the dominant one is `roofline`
+    # The pair kernels' rooflines (one launch per step each; `roofline` is the dominant one):
+    # algorithmic FLOP per launch (FLOP per contributing pair x the pairs gm_bin reported for
+    # the step) over the stage's HIP-event time on the launch stream, against the published
+    # FP32 peak.  The render stage also holds the 4-5 us one-block sum of the loss partials.
     def kernel_roofline(stage):
         if stage == "render":
             flop, instr, kname = FLOP_FWD, FWD_VALU_INSTR + EXP_SLOTS, "k_render"
         else:
             flop, instr, kname = FLOP_BWD, 2 * FWD_VALU_INSTR + EXP_SLOTS, "k_partials"
-        achieved = flop * pairs / (stage_ms[stage] / 1e3) / 1e12
-        peak = alu_peak_tflops(flop, instr)
-        return {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": peak,
-                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": recorded_traffic(kname),
-                "flop_per_pair": flop, "avg_kernel_ms": stage_ms[stage]}
+        sec = stage_ms[stage] / 1e3
+        achieved = flop * pairs / sec / 1e12
+        peak = FP32_PEAK / 1e12
+        r = {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": peak,
+             "unit": "TFLOP/s", "frac": achieved / peak, "traffic": recorded_traffic(kname),
+             "flop_per_pair": flop, "avg_kernel_ms": stage_ms[stage],
+             "frac_of_unpacked_fp32": achieved * 1e12 / FP32_PEAK_UNPACKED,
+             "issue_model": {"peak": alu_peak_tflops(flop, instr), "slots_per_pair": instr,
+                             "frac": achieved / alu_peak_tflops(flop, instr)}}
+        cnt = recorded_counters(kname)
+        if cnt is not None:
+            # every evaluated (Gaussian, voxel) lane takes one v_exp_f32; a wave instruction
+            # covers 64 lanes, so contributing pairs / (64 x exp instructions) is the fraction of
+            # evaluated lane-pairs that contribute (the per-piece log2 of the setup counts too,
+            # so this slightly understates it)
+            trans = cnt.get("SQ_INSTS_VALU_TRANS_F32")
+            if trans:
+                r["lane_efficiency"] = cnt["pairs_per_launch"] / (64.0 * trans)
+                r["exp_lane_rate_per_s"] = 64.0 * trans / sec
+                r["exp_lane_rate_frac_of_measured_peak"] = 64.0 * trans / sec / EXP_RATE_MEASURED
+            fma = cnt.get("SQ_INSTS_VALU_FMA_F32")
+            if fma is not None:
+                r["fma_flop_rate_tflops"] = 2 * 64.0 * fma / sec / 1e12
+            r["counters_per_launch"] = cnt
+        return r
 
     dom = "render" if stage_ms["render"] >= stage_ms["partials"] else "partials"
     rooflines = {s: kernel_roofline(s) for s in ("render", "partials")}
+    pair_ms = stage_ms["render"] + stage_ms["partials"]
+    fb_rate = pairs / (pair_ms / 1e3)
+    fwd_bwd_roof = {
+        "what": "forward + backward pair rate (k_render + k_partials time) against "
+                "R = 1/(77/P_F + 2/P_E): 77 FLOP and 2 exp per contributing pair",
+        "achieved_pairs_per_s": fb_rate,
+        "R_pairs_per_s": pair_roof(FLOP_FWD + FLOP_BWD, 2),
+        "frac": fb_rate / pair_roof(FLOP_FWD + FLOP_BWD, 2),
+        "R_unpacked_pairs_per_s": pair_roof(FLOP_FWD + FLOP_BWD, 2, FP32_PEAK_UNPACKED),
+        "frac_unpacked": fb_rate / pair_roof(FLOP_FWD + FLOP_BWD, 2, FP32_PEAK_UNPACKED),
+        "P_F": FP32_PEAK, "P_E": EXP_RATE_MEASURED,
+        "achieved_tflops": (FLOP_FWD + FLOP_BWD) * fb_rate / 1e12,
+        "frac_of_fp32_peak": (FLOP_FWD + FLOP_BWD) * fb_rate / FP32_PEAK,
+        "whole_iteration_frac_of_fp32_peak":
+            (FLOP_FWD + FLOP_BWD) * pairs / (ms_step / 1e3) / FP32_PEAK,
+        "target": 0.5, "target_met": bool(fb_rate / pair_roof(FLOP_FWD + FLOP_BWD, 2) >= 0.5),
+    }
+
+    if args.pairs_log:
+        with open(args.pairs_log, "w") as f:
+            json.dump(all_pairs, f)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -301,6 +387,7 @@ def main():
                      else "fused into the chain rule (the chain stage includes Adam)",
         "roofline": rooflines[dom],
         "roofline_pair_kernels": {r["kernel"]: r for r in rooflines.values()},
+        "roofline_fwd_bwd": fwd_bwd_roof,
         "cpu_baseline": cpu,
         "iters_to_psnr": recorded_iters_to_psnr(),
     }

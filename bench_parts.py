@@ -2,7 +2,7 @@
 and warm-start network against the dense BF16 MFMA peak; the SSIM loss term against the FP64
 vector peak), each on its own, timed with HIP events on the launch stream.
 
-    python -m paper_2603_00145_amd.microbench [--reps 10]
+    python bench_parts.py [--reps 10]
 
 Prints one JSON line per measurement.  The algorithmic FLOP counts are the multiply-adds of
 the layers as the kernels run them (inputs zero-padded to a multiple of 16 features):
@@ -18,12 +18,15 @@ from __future__ import annotations
 
 import argparse
 import json
+import os
 import sys
 
 import numpy as np
 import torch
 
-from . import api, inputs, nrf, warmstart
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+
+from paper_2603_00145_amd import api, inputs, nrf, warmstart  # noqa: E402
 
 BF16_PEAK = 2.5e15          # dense MFMA FLOP/s of MI355X in BF16
 FP64_PEAK = 78.6e12         # FP64 vector FLOP/s of MI355X (an FMA counts 2)

@@ -1,9 +1,14 @@
 """Turn rocprofv3 outputs into the short text summaries kept under profiles/.
 
-    python -m paper_2603_00145_amd.profile_summary stats  --dir D --out F --command C
-    python -m paper_2603_00145_amd.profile_summary traffic --fetch-dir D1 --write-dir D2
+    python bench_profile.py stats  --dir D --out F --command C
+    python bench_profile.py valu --dir D --kernel k_render --pairs-log P --out F --command C
+    python bench_profile.py traffic --fetch-dir D1 --write-dir D2
            --kernel k_render --source paper_2603_00145_amd/csrc/render.hip --calib-mib 1024
            --out F --command-fetch C1 --command-write C2
+
+`valu` takes one `--pmc` run of VALU instruction counters (SQ_INSTS_VALU_*) of bench.py with
+`--pairs-log`, and records their mean per dispatch of one kernel with the mean contributing
+pairs per dispatch and the kernel's assembly digest.
 
 `stats` summarises a `--kernel-trace --stats` run (per-kernel calls and durations of this
 library's kernels).  `traffic` takes one `--pmc FETCH_SIZE` run and one `--pmc WRITE_SIZE`
@@ -23,7 +28,7 @@ import os
 import statistics
 import sys
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ROOT = os.path.dirname(os.path.abspath(__file__))
 OUR_KERNELS = ("k_", "(anonymous namespace)::k_")
 
 
@@ -112,6 +117,55 @@ source: {a.source}
     print(txt)
 
 
+def cmd_valu(a):
+    rows = _rows(a.dir, "*counter_collection.csv")
+    per = {}
+    names = {}
+    for r in rows:
+        if _short(r["Kernel_Name"]) != a.kernel:
+            continue
+        d = int(r["Dispatch_Id"])
+        per.setdefault(d, {})[r["Counter_Name"]] = \
+            per.get(d, {}).get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        names[r["Counter_Name"]] = 1
+    if not per:
+        sys.exit(f"kernel {a.kernel} not found")
+    with open(a.pairs_log) as f:
+        pairs = json.load(f)
+    disp = sorted(per)
+    if len(disp) != len(pairs):
+        sys.exit(f"{len(disp)} dispatches of {a.kernel} but {len(pairs)} logged steps")
+    digest = kernel_digest(a.kernel)
+    if digest is None:
+        sys.exit("no kernel_digests.json entry: build first")
+    means = {c: statistics.mean(per[d].get(c, 0.0) for d in disp) for c in sorted(names)}
+    mp = statistics.mean(pairs)
+    txt = f"""# VALU instruction mix of {a.kernel} ({a.workload})
+
+Command (from the repository root on the GPU machine, run after `cd /tmp`):
+
+    {a.command}
+
+Wave-level instruction counts per dispatch (mean of {len(disp)} dispatches, one per training
+iteration; each covers up to 64 lanes), and the contributing (Gaussian, voxel) pairs gm_bin
+reported for the same iterations.
+
+| counter | per dispatch | per contributing pair |
+|---|---|---|
+"""
+    for c, v in means.items():
+        txt += f"| {c} | {v:.4g} | {v / mp:.4f} |\n"
+    txt += f"\npairs_per_launch: {mp:.0f}\n"
+    for c, v in means.items():
+        txt += f"{c}: {v:.0f}\n"
+    txt += f"kernel: {a.kernel}\nkernel_asm_sha256: {digest}\nsource: {a.source}\n"
+    if a.note:
+        txt += "\n" + a.note + "\n"
+    with open(a.out, "w") as f:
+        f.write(txt)
+    print(txt)
+
+
 def cmd_stats(a):
     rows = _rows(a.dir, "*kernel_stats.csv")
     lines = []
@@ -147,6 +201,15 @@ def main():
     t.add_argument("--command-fetch", required=True)
     t.add_argument("--command-write", required=True)
     t.add_argument("--out", required=True)
+    v = sub.add_parser("valu")
+    v.add_argument("--dir", required=True)
+    v.add_argument("--kernel", required=True)
+    v.add_argument("--source", required=True)
+    v.add_argument("--pairs-log", required=True)
+    v.add_argument("--workload", default="training iteration, 256^3 workload")
+    v.add_argument("--command", required=True)
+    v.add_argument("--note", default="")
+    v.add_argument("--out", required=True)
     s = sub.add_parser("stats")
     s.add_argument("--dir", required=True)
     s.add_argument("--workload", default="training iteration, 256^3 workload")
@@ -154,7 +217,7 @@ def main():
     s.add_argument("--note", default="")
     s.add_argument("--out", required=True)
     a = ap.parse_args()
-    {"traffic": cmd_traffic, "stats": cmd_stats}[a.cmd](a)
+    {"traffic": cmd_traffic, "stats": cmd_stats, "valu": cmd_valu}[a.cmd](a)
 
 
 if __name__ == "__main__":

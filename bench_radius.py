@@ -3,7 +3,7 @@ with the cell-neighbourhood query (Eqs. 4-6) at block radii 3..7 (cells = the Ga
 against the 3-sigma box, reporting final PSNR, milliseconds per iteration (HIP events) and the
 contributing (Gaussian, voxel) pairs each query evaluates.
 
-    python -m paper_2603_00145_amd.radius_sweep [--iters 150] [--lattice 32]
+    python bench_radius.py [--iters 150] [--lattice 32]
 
 One JSON line per configuration.  The 64^3 workload's stacks are axis-aligned (no rigid
 offsets), which the block query needs.
@@ -12,11 +12,14 @@ from __future__ import annotations
 
 import argparse
 import json
+import os
 import sys
 
 import torch
 
-from . import api, inputs, recon
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+
+from paper_2603_00145_amd import api, inputs, recon  # noqa: E402
 
 
 def run(rule, radius, lattice, iters, w, data):

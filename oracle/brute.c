@@ -65,6 +65,27 @@ void oracle_render_points(int64_t npts, const int64_t* pts, int64_t n, const dou
     }
 }
 
+/* The same sum as oracle_render, visiting each Gaussian's box instead of testing every
+ * Gaussian at every voxel: plane z collects, in ascending i, the box rows of the Gaussians
+ * whose box holds z.  Each voxel receives exactly the terms, and in exactly the order, of
+ * oracle_render (starting from 0.0), so the results are identical; it costs the box volumes
+ * instead of voxels x Gaussians.  out must be zeroed by the caller. */
+void oracle_scatter_render(int64_t nx, int64_t ny, int64_t nz, int64_t n, const double* c,
+                           const double* C, const double* amp, const int64_t* lo,
+                           const int64_t* hi, const uint8_t* nonempty, double* out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t z = 0; z < nz; ++z) {
+        for (int64_t i = 0; i < n; ++i) {
+            if (!nonempty[i] || z < lo[3 * i + 2] || z > hi[3 * i + 2]) continue;
+            for (int64_t y = lo[3 * i + 1]; y <= hi[3 * i + 1]; ++y)
+                for (int64_t x = lo[3 * i]; x <= hi[3 * i]; ++x)
+                    out[(z * ny + y) * nx + x] += gauss_value(c + 3 * i, C + 9 * i, amp[i],
+                                                              (double)x, (double)y, (double)z);
+        }
+    }
+}
+
 /* For L = sum_v g[v] I[v]: per Gaussian, over the voxels of its box,
  *   d_amp[i]  = sum g * e            (e = exp(-q/2), w = amp * e)
  *   d_c[i]    = sum g * w * C (v - c)
@@ -114,5 +135,15 @@ int oracle_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* Set the thread count of the loops above (k <= 0 leaves it unchanged). */
+void oracle_set_threads(int k)
+{
+#ifdef _OPENMP
+    if (k > 0) omp_set_num_threads(k);
+#else
+    (void)k;
 #endif
 }

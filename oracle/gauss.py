@@ -49,8 +49,12 @@ def _lib():
         lib.oracle_render.restype = None
         lib.oracle_render_points.restype = None
         lib.oracle_partials.restype = None
+        lib.oracle_scatter_render.argtypes = [I, I, I, I, P, P, P, P, P, P, P]
+        lib.oracle_scatter_render.restype = None
         lib.oracle_threads.restype = ctypes.c_int
         lib.oracle_threads.argtypes = []
+        lib.oracle_set_threads.restype = None
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
         _LIB = lib
     return _LIB
 
@@ -58,6 +62,11 @@ def _lib():
 def threads() -> int:
     """OpenMP threads the brute-force sums run on."""
     return int(_lib().oracle_threads())
+
+
+def set_threads(k: int) -> None:
+    """Thread count of the brute-force sums (k <= 0: unchanged)."""
+    _lib().oracle_set_threads(int(k))
 
 
 def _ptr(a):
@@ -145,6 +154,19 @@ def render(grid, gt, lo, hi, nonempty):
     lo, hi, ne = _boxes_c(lo, hi, nonempty)
     lib.oracle_render(grid.nx, grid.ny, grid.nz, n, _ptr(c), _ptr(C), _ptr(amp), _ptr(lo),
                       _ptr(hi), _ptr(ne), _ptr(out))
+    return out
+
+
+def render_scatter(grid, gt, lo, hi, nonempty):
+    """The same sums as render(), each Gaussian visiting its own box (ascending i per voxel, so
+    the result is identical); its cost is the box volumes, so it serves full-size grids."""
+    lib = _lib()
+    n = gt["c"].shape[0]
+    out = np.zeros(grid.shape, np.float64)
+    c, C, amp = _f64c(gt["c"]), _f64c(gt["C"]), _f64c(gt["amp"])
+    lo, hi, ne = _boxes_c(lo, hi, nonempty)
+    lib.oracle_scatter_render(grid.nx, grid.ny, grid.nz, n, _ptr(c), _ptr(C), _ptr(amp),
+                              _ptr(lo), _ptr(hi), _ptr(ne), _ptr(out))
     return out
 
 
@@ -405,3 +427,89 @@ def devox_init(g, stacks, stack_data):
     quat[:, 0] = 1
     log_scale = np.full((n, 3), np.log(sigma))
     return mean, quat, log_scale, logit
+
+
+# ----------------------------------------------------------------------------------------
+# sensitivity of the gradients to the per-voxel upstream gradient
+# ----------------------------------------------------------------------------------------
+
+def abs_jacobian_sums(g, grids, cutoff=3.0, chunk=1 << 20):
+    """For every raw parameter component theta of every Gaussian i: sum over the grids and over
+    the voxels v of Box_g(i) of |d w_i(v) / d theta|, where w_i(v) is the Gaussian's value at v
+    (the term of I_g[v], Eq. 7 with the slice profile).  The gradient of sum_v dl[v] I[v]
+    changes by at most max_v |delta dl[v]| times this sum when dl changes by delta dl.
+
+    Per pair: d w / d amp = w / amp, d w / d c = w C delta, d w / d C_aa = -1/2 w delta_a^2,
+    d w / d C_ab = -w delta_a delta_b (a < b, both symmetric entries), delta = v - c; the
+    derivatives of (amp, c, C) with respect to the raw parameters come from complex-step
+    differentiation of grid_terms.  Returns (mean [N,3], quat [N,4], log_scale [N,3],
+    logit [N])."""
+    n = g.mean.shape[0]
+    p64 = params64(g)
+    sizes = (3, 4, 3, 1)
+    out = [np.zeros((n, k)) for k in sizes]
+    h = 1e-30
+    for grid in grids:
+        lo, hi, ne, _ = recipe.boxes(g.mean, g.quat, g.log_scale, g.logit, grid, cutoff)
+        gt = grid_terms(*p64, grid)
+        # Jacobian of (amp, c0..2, C00 C11 C22 C01 C02 C12) with respect to the 11 raw components
+        J = np.zeros((n, 10, 11))
+        col = 0
+        for grp, k in enumerate(sizes):
+            for comp in range(k):
+                pc = [np.asarray(a, np.complex128).copy() for a in p64]
+                if pc[grp].ndim == 1:
+                    pc[grp] = pc[grp] + 1j * h
+                else:
+                    pc[grp][:, comp] = pc[grp][:, comp] + 1j * h
+                t = grid_terms(*pc, grid)
+                C = t["C"]
+                J[:, 0, col] = t["amp"].imag / h
+                J[:, 1:4, col] = t["c"].imag / h
+                J[:, 4:10, col] = np.stack([C[:, 0, 0], C[:, 1, 1], C[:, 2, 2], C[:, 0, 1],
+                                            C[:, 0, 2], C[:, 1, 2]], 1).imag / h
+                col += 1
+        idx = np.nonzero(ne)[0]
+        dims = (hi[idx] - lo[idx] + 1).astype(np.int64)
+        cnt = np.prod(dims, axis=1)
+        acc = np.zeros((n, 11))
+        # enumerate the box voxels of the nonempty Gaussians in chunks of whole Gaussians
+        starts = np.concatenate([[0], np.cumsum(cnt)])
+        a = 0
+        while a < idx.size:
+            b = int(np.searchsorted(starts, starts[a] + chunk, side="right")) - 1
+            b = max(b, a + 1)
+            sel = idx[a:b]
+            c_sel = cnt[a:b]
+            gi = np.repeat(sel, c_sel)
+            k = np.arange(int(c_sel.sum())) - np.repeat(starts[a:b] - starts[a], c_sel)
+            d = dims[a:b]
+            dx, dy = np.repeat(d[:, 0], c_sel), np.repeat(d[:, 1], c_sel)
+            vx = lo[gi, 0] + k % dx
+            vy = lo[gi, 1] + (k // dx) % dy
+            vz = lo[gi, 2] + k // (dx * dy)
+            delta = np.stack([vx, vy, vz], 1).astype(np.float64) - gt["c"][gi]
+            Cg = gt["C"][gi]
+            Cd = np.einsum("pij,pj->pi", Cg, delta)
+            q = (delta * Cd).sum(1)
+            e = np.exp(-0.5 * q)
+            w = gt["amp"][gi] * e
+            dw = np.empty((gi.size, 10))
+            dw[:, 0] = e
+            dw[:, 1:4] = w[:, None] * Cd
+            dw[:, 4] = -0.5 * w * delta[:, 0] ** 2
+            dw[:, 5] = -0.5 * w * delta[:, 1] ** 2
+            dw[:, 6] = -0.5 * w * delta[:, 2] ** 2
+            dw[:, 7] = -w * delta[:, 0] * delta[:, 1]
+            dw[:, 8] = -w * delta[:, 0] * delta[:, 2]
+            dw[:, 9] = -w * delta[:, 1] * delta[:, 2]
+            jt = np.abs(np.einsum("pk,pkl->pl", dw, J[gi]))
+            for col in range(11):
+                acc[:, col] += np.bincount(gi, weights=jt[:, col], minlength=n)
+            a = b
+        col = 0
+        for grp, k in enumerate(sizes):
+            out[grp] += acc[:, col:col + k]
+            col += k
+    out[3] = out[3][:, 0]
+    return tuple(out)

@@ -30,6 +30,31 @@ def bf16_bits(a):
     return (bf16_round(a).view(np.uint32) >> 16).astype(np.uint16)
 
 
+def index_to_world(world_to_index):
+    """Inverse of a grid's world->index affine A = [L | t] (row-major 3x4, binary64) by the
+    adjugate: with cofactors c00 = e j - f i, c01 = f h - d j, c02 = d i - e h of
+    L = [[a b c] [d e f] [h i j]] and det = a c00 + b c01 + c c02, L^-1 row by row =
+    [c00, c i - b j, b f - c e] / det, [c01, a j - c h, c d - a f] / det,
+    [c02, b h - a i, a e - b d] / det; the translation column is -(L^-1 t), each row summed in
+    column order.  Every product and sum is one binary64 operation in the written order (the
+    residual field's coordinates depend on the last bit of this matrix, so the boundary fixes
+    the recipe)."""
+    A = np.asarray(world_to_index, np.float64).reshape(3, 4)
+    a, b, c = float(A[0, 0]), float(A[0, 1]), float(A[0, 2])
+    d, e, f = float(A[1, 0]), float(A[1, 1]), float(A[1, 2])
+    h, i, j = float(A[2, 0]), float(A[2, 1]), float(A[2, 2])
+    c00, c01, c02 = e * j - f * i, f * h - d * j, d * i - e * h
+    det = a * c00 + b * c01 + c * c02
+    Li = [[c00 / det, (c * i - b * j) / det, (b * f - c * e) / det],
+          [c01 / det, (a * j - c * h) / det, (c * d - a * f) / det],
+          [c02 / det, (b * h - a * i) / det, (a * e - b * d) / det]]
+    M = np.zeros((3, 4))
+    for r in range(3):
+        M[r, :3] = Li[r]
+        M[r, 3] = -((Li[r][0] * float(A[0, 3]) + Li[r][1] * float(A[1, 3])) + Li[r][2] * float(A[2, 3]))
+    return M
+
+
 def world_coords(vox, index_to_world):
     """vox [P,3] integer (x, y, z) -> float32 world coordinates by the stated recipe."""
     M = np.asarray(index_to_world, np.float64).reshape(3, 4)

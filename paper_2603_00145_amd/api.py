@@ -137,6 +137,9 @@ class Bins:
         self.scratch = None
         self._reserve(capacity if capacity is not None else max(1024, 8 * self.n * G))
         self.n_pairs = -1
+        # bumped by every bin(): records, lists and partials describe the parameters of the
+        # last bin() only, so a saved generation tells whether they still hold
+        self.generation = 0
 
     def _reserve(self, cap: int):
         cap = int(min(cap, 2 ** 31 - 1))
@@ -171,6 +174,7 @@ class Bins:
         if g.n != self.n:
             raise ValueError(f"bins built for {self.n} Gaussians, got {g.n}")
         gs = g.struct()
+        self.generation += 1
         opts = _lib.GmBinOpts(self.cutoff, self.block_radius, self.cell_resolution)
         npairs = ctypes.c_int64()
         for _ in range(2):
@@ -196,6 +200,7 @@ class Bins:
             raise ValueError("set_grids keeps the number and dimensions of the grids")
         self.grids = grids
         self._cgrids = (_lib.GmGrid * len(grids))(*[_lib.grid_struct(g) for g in grids])
+        self.generation += 1
         self.n_pairs = -1
         if hasattr(self, "_s"):
             self._s.n_pairs = -1

@@ -101,3 +101,19 @@ def test_host_validation_of_the_extension_entry_points():
     st = lib.gm_bin(ctypes.byref(g), ctypes.byref(grid), 1, ctypes.byref(opts), ctypes.byref(b),
                     ctypes.byref(npairs), None)
     assert st == _lib.GM_ERR_INVALID_ARGUMENT
+
+
+def test_index_to_world_follows_the_stated_recipe():
+    """gm_index_to_world (a host call) gives, bit for bit, the adjugate recipe its header
+    states, which the oracle writes out on its own (the residual field's coordinates depend on
+    the last bit of this matrix)."""
+    import numpy as np
+    from oracle import nrf as onrf
+    from paper_2603_00145_amd import _lib, inputs
+    rng = np.random.default_rng(4)
+    grids = [inputs.volume_grid(64)] + inputs.orthogonal_stacks(96, 24, 1.0, rng, 2.0, 1.0) + \
+        inputs.oblique_stacks(80, 20, 1.25)
+    for g in grids:
+        got = _lib.index_to_world(g)
+        ref = onrf.index_to_world(g.world_to_index)
+        assert np.array_equal(got, ref), g.name

@@ -105,6 +105,37 @@ def test_gradcheck_c256_crop_subset(mods):
     assert normwise(gpu, fd) <= TOL
 
 
+def test_two_forwards_before_backward(mods):
+    """Two forwards on the same bins (the second with other parameters re-bins them) before
+    the first forward's backward: the first backward still differentiates its own parameters."""
+    api, autograd = mods
+    rng = np.random.default_rng(31)
+    n = 30
+    g1 = inputs.init_anisotropic(n, 400, rng)
+    g2 = inputs.init_anisotropic(n, 400, rng)
+    grids = [inputs.stack_grid("axial", n, 8, 1.0, *inputs.random_rigid(rng, 2, 1, n)),
+             inputs.volume_grid(n)]
+    dl = inputs.random_dl_di(grids, rng)
+    b = api.Bins(g1.n, grids)
+
+    def leaf(g):
+        return [torch.from_numpy(np.ascontiguousarray(getattr(g, k))).cuda().requires_grad_(True)
+                for k in ("mean", "quat", "log_scale", "logit")]
+
+    p1, p2 = leaf(g1), leaf(g2)
+    o1 = autograd.render(p1, b, [0, 1])
+    o2 = autograd.render(p2, b, [0, 1])          # re-bins b for g2
+    L1 = sum((o * torch.from_numpy(d).cuda()).sum() for o, d in zip(o1, dl))
+    L2 = sum((o * torch.from_numpy(d).cuda()).sum() for o, d in zip(o2, dl))
+    L1.backward()
+    L2.backward()
+    for g, p in ((g1, p1), (g2, p2)):
+        ref = gauss.gradients(g, grids, dl)
+        for name, t, r in zip(("mean", "quat", "log_scale", "logit"), p, ref):
+            err = normwise(t.grad.cpu().numpy(), r)
+            assert err <= TOL, (name, err)
+
+
 def test_devox_matches_oracle(mods):
     api, _ = mods
     w = inputs.workload("c64")

@@ -46,7 +46,7 @@ def test_nrf_forward_parity(mods, n_freq, depth):
     net.forward_add(grid, out)
     torch.cuda.synchronize()
     r_gpu = (out - base).cpu().numpy().reshape(-1)
-    x = onrf.world_coords(all_voxels(grid), _lib.index_to_world(grid))
+    x = onrf.world_coords(all_voxels(grid), onrf.index_to_world(grid.world_to_index))
     r_ref, *_ = onrf.forward(net.weights_host(), onrf.encode(x, n_freq, net.in_pad), net.out_scale)
     err = normwise(r_gpu, r_ref)
     say(f"  nrf forward L={n_freq} D={depth}: normwise {err:.2e}, max|r| {np.abs(r_ref).max():.3f}")
@@ -65,7 +65,7 @@ def test_nrf_backward_parity(mods, n_freq, depth):
     _, scale = net.backward(grid, torch.from_numpy(dl).cuda(), idx=torch.from_numpy(idx).cuda())
     torch.cuda.synchronize()
     vox = all_voxels(grid)[idx]
-    x = onrf.world_coords(vox, _lib.index_to_world(grid))
+    x = onrf.world_coords(vox, onrf.index_to_world(grid.world_to_index))
     feats = onrf.encode(x, n_freq, net.in_pad)
     g = onrf.backward(net.weights_host(), feats, dl.reshape(-1)[idx].astype(np.float64) * scale,
                       net.out_scale)
@@ -77,6 +77,40 @@ def test_nrf_backward_parity(mods, n_freq, depth):
     for name, a, r in checks:
         err = normwise(a, r)
         say(f"  nrf backward L={n_freq} D={depth} {name}: {err:.2e}")
+        assert err <= TOL_BF16, name
+
+
+def test_nrf_backward_parity_training_size(mods):
+    """The field's gradient as training takes it on the 256^3 workload: 2^18 sampled voxels of
+    a rigidly offset 256x256x64 stack, 16 bands, three 64-wide layers (the split-K weight
+    gradients then sum 256 partials per element)."""
+    _lib, api, nrf = mods
+    rng = np.random.default_rng(12)
+    grid = inputs.stack_grid("coronal", 256, 64, 1.0, *inputs.random_rigid(rng, 2, 1, 256))
+    net = nrf.NRF(n_freq=16, depth=3, seed=9, zero_last=False)
+    dl = (rng.normal(size=grid.shape) * 1e-6).astype(np.float32)
+    npts = 1 << 18
+    idx = rng.choice(grid.n_voxels, size=npts, replace=False).astype(np.int32)
+    net.zero_grad()
+    _, scale = net.backward(grid, torch.from_numpy(dl).cuda(), idx=torch.from_numpy(idx).cuda())
+    torch.cuda.synchronize()
+    assert scale == grid.n_voxels / npts
+    z, rem = np.divmod(idx.astype(np.int64), grid.nx * grid.ny)
+    y, x = np.divmod(rem, grid.nx)
+    vox = np.stack([x, y, z], 1)
+    xw = onrf.world_coords(vox, onrf.index_to_world(grid.world_to_index))
+    feats = onrf.encode(xw, 16, net.in_pad)
+    g = onrf.backward(net.weights_host(), feats, dl.reshape(-1)[idx].astype(np.float64) * scale,
+                      net.out_scale)
+    got = {k: v.cpu().numpy() for k, v in net.g.items()}
+    checks = [("w_in", got["w_in"], g["W"][0]), ("b_in", got["b_in"], g["b"][0]),
+              ("w_out", got["w_out"], g["w_out"]), ("b_out", got["b_out"][0], g["b_out"])]
+    for l in range(2):
+        checks += [(f"w_hid{l}", got["w_hid"][l], g["W"][l + 1]),
+                   (f"b_hid{l}", got["b_hid"][l], g["b"][l + 1])]
+    for name, a, r in checks:
+        err = normwise(a, r)
+        say(f"  nrf backward 2^18 points {name}: {err:.2e}")
         assert err <= TOL_BF16, name
 
 

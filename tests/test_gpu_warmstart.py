@@ -60,10 +60,12 @@ def test_targets_match_oracle(mods):
     assert normwise(got, ref) <= 1e-6
 
 
-def test_forward_and_gradients_match_oracle(mods):
+@pytest.mark.parametrize("n", [48, 1024])
+def test_forward_and_gradients_match_oracle(mods, n):
+    """n = 1024 is the training batch: the head's weight gradient is then split over 64
+    sample ranges and the convolution weight gradients over many sample partials."""
     api, ws = mods
     rng = np.random.default_rng(1)
-    n = 48
     net = ws.WarmStartNet(seed=3, zero_head=False)
     X = rng.uniform(0, 1, (n, 3, 512)).astype(np.float32)
     Xb = torch.from_numpy(X).cuda().to(torch.bfloat16).view(torch.int16)
@@ -97,6 +99,34 @@ def test_forward_and_gradients_match_oracle(mods):
         err = normwise(got[k], g[k].reshape(got[k].shape))
         say(f"  warm gradient {k}: {err:.2e}")
         assert err <= TOL_BF16, k
+
+
+def test_chunked_inference_sampled(mods):
+    """Inference as the warm start runs it, in chunks of 65536 Gaussians (two chunks, the second
+    ragged): outputs at samples spread over both chunks and their edges against the oracle's
+    forward of those samples (each sample's output depends on its own patch only)."""
+    api, ws = mods
+    rng = np.random.default_rng(6)
+    n = (1 << 16) + 16 * 37
+    net = ws.WarmStartNet(seed=5, zero_head=False)
+    X = torch.rand((n, 3, 512), device="cuda", generator=torch.Generator("cuda").manual_seed(3))
+    Xb = X.to(torch.bfloat16).view(torch.int16)
+    s0 = torch.from_numpy(rng.normal(-3.5, 0.1, (n, 3)).astype(np.float32)).cuda()
+    l0 = torch.from_numpy(rng.normal(0, 0.5, n).astype(np.float32)).cuda()
+    s, q, lg = net.forward(Xb, s0, l0)
+    torch.cuda.synchronize()
+    c = 1 << 16
+    pick = np.unique(np.concatenate([np.arange(8), np.arange(c - 8, c + 8), np.arange(n - 8, n),
+                                     rng.integers(0, n, 40)]))
+    W = net.weights_host()
+    X0 = bf16_to_f64(Xb[torch.from_numpy(pick).cuda()]).reshape(pick.size, 3, 8, 8, 8)
+    out, _, _ = owarm.forward(W, X0)
+    rs, rq, rl = owarm.assemble(out, s0.cpu().numpy()[pick].astype(np.float64),
+                                l0.cpu().numpy()[pick].astype(np.float64))
+    for name, a, r in (("log_scale", s, rs), ("quat", q, rq), ("logit", lg, rl)):
+        err = normwise(a.cpu().numpy()[pick], r)
+        say(f"  warm inference (chunked, {n}) {name}: {err:.2e} on {pick.size} samples")
+        assert err <= TOL_BF16
 
 
 def test_training_reduces_loss(mods):

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 import torch
 
+from adam_bounds import adam_range, check_range
 from oracle import gauss, recipe
 from oracle import nrf as onrf
 from paper_2603_00145_amd import inputs
@@ -125,7 +126,7 @@ def test_c320_volume_crop_fp32_and_bf16(mods):
     sel = ne & np.all(lo <= c0 + size - 1, 1) & np.all(hi >= c0, 1)
     gs = {k: gt[k][sel] for k in ("c", "C", "amp")}
     ref_g = gauss.render_points(pts, gs, lo[sel], hi[sel], ne[sel])
-    xw = onrf.world_coords(pts, _lib.index_to_world(w.volume))
+    xw = onrf.world_coords(pts, onrf.index_to_world(w.volume.world_to_index))
     r_ref, *_ = onrf.forward(net.weights_host(), onrf.encode(xw, 16, net.in_pad), net.out_scale)
     e32 = normwise(g_plain, ref_g)
     e_r = normwise(g_full - g_plain, r_ref)
@@ -137,3 +138,59 @@ def test_c320_volume_crop_fp32_and_bf16(mods):
     assert e32 <= TOL
     assert e_r <= TOL_BF16
     assert e_all <= TOL_BF16
+
+
+def test_c256_training_step_every_voxel_and_gaussian(mods):
+    """The benchmark's training iteration on the 256^3 workload (1M Gaussians, three
+    256x256x64 stacks: gm_bin, the render with the smooth-L1 epilogue over 12k tiles, the grid
+    partials, the chain rule with Adam fused) against the oracle's FP64 iteration: every stack
+    voxel, the loss, every dL/dI, and every Gaussian's new parameters and moments (Adam range
+    of the gradient bar, as in test_gpu_train_step)."""
+    from oracle import train
+    _lib, api, _ = mods
+    w = inputs.workload("c256", with_data=True)
+    stacks = w.stacks
+    targets = [np.asarray(d, np.float32) for d in w.stack_data]
+    p = api.GaussParams.from_host(w.gauss)
+    m = api.GaussParams.zeros_like(p)
+    v = api.GaussParams.zeros_like(p)
+    ids = list(range(len(stacks)))
+    b = api.Bins(p.n, stacks, capacity=int(12 * p.n * len(stacks)))
+    b.bin(p)
+    tg = [torch.from_numpy(t).cuda() for t in targets]
+    outs = [torch.empty(s.shape, device="cuda") for s in stacks]
+    dls = [torch.empty(s.shape, device="cuda") for s in stacks]
+    loss, _ = api.render_loss(b, ids, tg, dls, outs=outs)
+    api.grid_partials(p, b, ids, dls)
+    lrs = (1e-3, 1e-3, 5e-3, 5e-2)
+    api.chain_adam(p, b, ids, m, v, lrs, 1, 0.1, 1.5)
+    torch.cuda.synchronize()
+    say(f"  c256 step: {b.n_pairs} (tile, Gaussian) pairs, {sum(b.box_pairs_host)} voxel pairs, "
+        f"{b.total_tiles} tiles")
+    params0 = [np.asarray(getattr(w.gauss, k), np.float32) for k in ("mean", "quat", "log_scale",
+                                                                     "logit")]
+    z = [np.zeros(a.shape, np.float32) for a in params0]
+    ref = train.step(params0, z, z, 1, stacks, targets, lrs, 0.1, 1.5)
+    for k, (o, r) in enumerate(zip(outs, ref["renders"])):
+        o = o.cpu().numpy()
+        e = normwise(o, r)
+        say(f"  stack {k}: every voxel normwise {e:.2e}, per-element {elementwise(o, r):.2e}")
+        assert e <= TOL
+    say(f"  loss gpu {float(loss):.9g} oracle {ref['loss']:.9g}")
+    assert abs(float(loss) - ref["loss"]) <= TOL * ref["loss"]
+    for k, (d, r) in enumerate(zip(dls, ref["dl"])):
+        e = normwise(d.cpu().numpy(), r)
+        say(f"  dL/dI stack {k}: normwise {e:.2e}")
+        assert e <= TOL
+    gmax_s = np.max(np.abs(ref["grads"][2]))
+    for k, (name, got_p, got_m, got_v) in enumerate(zip(("mean", "quat", "log_scale", "logit"),
+                                                        p.tensors(), m.tensors(), v.tensors())):
+        gref = ref["grads"][k]
+        gmax = max(np.max(np.abs(gref)), gmax_s if name == "quat" else 0.0)
+        delta = np.full(gref.shape, TOL * gmax)
+        p_in = params0[k].astype(np.float64)
+        rp, rm, rv = adam_range(p_in, gref, delta, z[k], z[k], 1, lrs[k])
+        e_p = check_range(f"{name} p", got_p.cpu().numpy(), rp, ref["p"][k], p_in)
+        e_m = check_range(f"{name} m", got_m.cpu().numpy(), rm, ref["m"][k], None)
+        e_v = check_range(f"{name} v", got_v.cpu().numpy(), rv, ref["v"][k], None)
+        say(f"  {name}: p {e_p:.2e} m {e_m:.2e} v {e_v:.2e} (normwise to the oracle)")

@@ -175,10 +175,13 @@ def main():
                     help="render and smooth-L1 as two calls (the renderings go through HBM)")
     ap.add_argument("--unfused-adam", action="store_true",
                     help="chain rule into a gradient buffer, then Adam per group (four calls)")
-    ap.add_argument("--cpu-sample-voxels", type=int, default=4096)
-    ap.add_argument("--cpu-sample-gauss", type=int, default=100000)
+    ap.add_argument("--cpu-sample-gauss", type=int, default=200000)
+    ap.add_argument("--cpu-sample-gauss-1core", type=int, default=15000)
     ap.add_argument("--pairs-log", default="",
                     help="write the contributing pairs of every step (warm-up included) here")
+    ap.add_argument("--nrf-steps", type=int, default=10,
+                    help="also time this many iterations with the neural residual field on "
+                         "(0: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB before timing")
     args = ap.parse_args()
@@ -364,9 +367,14 @@ def main():
         with open(args.pairs_log, "w") as f:
             json.dump(all_pairs, f)
 
+    nrf_on = None
+    if args.nrf_steps > 0:
+        nrf_on = time_nrf_on(args, bins, p, m, v, ids, stacks, targets, dls, lrs,
+                             step_no[0])
+
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, args.cpu_sample_voxels, args.cpu_sample_gauss)
+        cpu = cpu_baseline(w, args.cpu_sample_gauss, args.cpu_sample_gauss_1core)
 
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
@@ -390,57 +398,122 @@ def main():
         "roofline_fwd_bwd": fwd_bwd_roof,
         "cpu_baseline": cpu,
         "iters_to_psnr": recorded_iters_to_psnr(),
+        "nrf_on": nrf_on,
     }
     print(json.dumps(out))
 
 
-def cpu_baseline(w, n_vox, n_gauss):
-    """The FP64 oracle, untuned, on a bounded sample of the same workload: forward values
-    at n_vox random stack voxels (brute force over every Gaussian) and the backward partials
-    + chain rule of n_gauss random Gaussians over their boxes on the three stacks."""
+def time_nrf_on(args, bins, p, m, v, ids, stacks, targets, dls, lrs, step0):
+    """ms per iteration of the same workload with the neural residual field on (the second
+    half of a reconstruction): bin, render + field + smooth-L1 in one pass, backward partials,
+    the field's backward on 2^18 uniformly drawn voxels per stack (drawn beforehand: they are
+    inputs), the field's Adam step, chain rule + Adam on the Gaussians."""
+    import torch
+    from paper_2603_00145_amd import api, nrf as nrfmod
+    dev = p.mean.device
+    net = nrfmod.NRF(n_freq=16, depth=3, seed=0, zero_last=False)
+    n_sample = 1 << 18
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(2603)
+    total = args.nrf_steps + 2
+    draws = [[torch.randint(0, g.n_voxels, (n_sample,), device=dev, dtype=torch.int32,
+                            generator=gen) for g in stacks] for _ in range(total)]
+    stages = ("bin", "render_field_loss", "partials", "field_backward", "chain")
+    k_step = [step0]
+
+    def step(i, e):
+        s = torch.cuda.current_stream()
+        k = [0]
+
+        def mark():
+            if e is not None:
+                e[k[0]].record(s)
+                k[0] += 1
+
+        mark()
+        bins.bin(p)
+        mark()
+        api.render_loss(bins, ids, targets, dls, nrf=net)
+        mark()
+        api.grid_partials(p, bins, ids, dls)
+        mark()
+        net.zero_grad()
+        for kk, g in enumerate(stacks):
+            net.backward(g, dls[kk], idx=draws[i][kk])
+        net.adam_step(1e-4)
+        mark()
+        k_step[0] += 1
+        api.chain_adam(p, bins, ids, m, v, lrs, k_step[0], 0.1, 1.5)
+        mark()
+
+    for i in range(2):
+        step(i, None)
+    torch.cuda.synchronize()
+    recs = [[TimingEvent() for _ in range(len(stages) + 1)] for _ in range(args.nrf_steps)]
+    for i, e in enumerate(recs):
+        step(i + 2, e)
+    torch.cuda.synchronize()
+    step_ms = np.array([e[0].elapsed_time(e[-1]) for e in recs])
+    stage_ms = {st: float(np.mean([e[j].elapsed_time(e[j + 1]) for e in recs]))
+                for j, st in enumerate(stages)}
+    return {"what": "iteration with the residual field on (n_freq 16, 3 x 64, BF16 MFMA): "
+                    "render + field + smooth-L1 fused, field backward on 2^18 sampled voxels "
+                    "per stack, field and Gaussian Adam",
+            "steps": args.nrf_steps, "ms_per_step": float(step_ms.mean()),
+            "ms_per_step_p10_p50_p90": [float(np.percentile(step_ms, q)) for q in (10, 50, 90)],
+            "stage_ms": stage_ms}
+
+
+def cpu_baseline(w, n_gauss, n_gauss_1core):
+    """The FP64 oracle, untuned, as a CPU reconstruction would run the same iteration: every
+    Gaussian of a random sample scatters its values over its box on each stack (forward), then
+    walks its box again for the ten partial sums and is pulled back through the chain rule
+    (backward); contributing pairs per second, on every host core (OpenMP) and on one core (a
+    smaller sample).  The FP64 per-Gaussian set-up (conic, amplitude, box) is excluded."""
     from oracle import gauss
     rng = np.random.default_rng(123)
     g = w.gauss
-    sub = np.sort(rng.choice(g.n, size=min(n_gauss, g.n), replace=False))
+    dl = [np.asarray(d.cpu().numpy() if hasattr(d, "cpu") else d, np.float64) * 1e-6
+          for d in w.stack_data]
     t_prep = time.time()
     prep = gauss.prepare(g, w.stacks)
     t_prep = time.time() - t_prep
-    # forward sample
-    t_f = 0.0
-    p_f = 0
-    per = max(1, n_vox // len(w.stacks))
-    for grid, (gt, lo, hi, ne, _) in zip(w.stacks, prep):
-        pts = np.stack([rng.integers(0, grid.nx, per), rng.integers(0, grid.ny, per),
-                        rng.integers(0, grid.nz, per)], 1)
+
+    def run(n_sample):
+        sub = np.sort(rng.choice(g.n, size=min(n_sample, g.n), replace=False))
+        mean, quat, ls, logit = gauss.params64(g.subset(sub))
+        pairs, t_f, t_b = 0, 0.0, 0.0
+        parts = []
+        for grid, (gt, lo, hi, ne, _), d in zip(w.stacks, prep, dl):
+            gs = {k: (v[sub] if isinstance(v, np.ndarray) and v.shape[:1] == (g.n,) else v)
+                  for k, v in gt.items() if k != "wt"}
+            t = time.time()
+            gauss.render_scatter(grid, gs, lo[sub], hi[sub], ne[sub])
+            t_f += time.time() - t
+            t = time.time()
+            parts.append(gauss.grid_partials(grid, gs, lo[sub], hi[sub], ne[sub], d))
+            t_b += time.time() - t
+            pairs += int(np.where(ne[sub], np.prod(hi[sub] - lo[sub] + 1, axis=1), 0).sum())
         t = time.time()
-        gauss.render_points(pts, gt, lo, hi, ne)
-        t_f += time.time() - t
-        inside = ((pts[:, None, :] >= lo[None]) & (pts[:, None, :] <= hi[None])).all(2) & ne[None]
-        p_f += int(inside.sum())
-    # backward sample
-    t_b = 0.0
-    p_b = 0
-    dl = [np.asarray(d.cpu().numpy() if hasattr(d, "cpu") else d, np.float64) * 1e-6
-          for d in w.stack_data]
-    mean, quat, ls, logit = gauss.params64(g.subset(sub))
-    parts = []
-    for grid, (gt, lo, hi, ne, _), d in zip(w.stacks, prep, dl):
-        gs = {k: (v[sub] if isinstance(v, np.ndarray) and v.shape[:1] == (g.n,) else v)
-              for k, v in gt.items() if k != "wt"}
-        t = time.time()
-        parts.append(gauss.grid_partials(grid, gs, lo[sub], hi[sub], ne[sub], d))
+        gauss.chain(mean, quat, ls, logit, w.stacks, parts)
         t_b += time.time() - t
-        p_b += int(np.where(ne[sub], np.prod(hi[sub] - lo[sub] + 1, axis=1), 0).sum())
-    t = time.time()
-    gauss.chain(mean, quat, ls, logit, w.stacks, parts)
-    t_b += time.time() - t
-    rate = 1.0 / (t_f / max(p_f, 1) + t_b / max(p_b, 1))
-    return {"value": rate, "unit": UNIT, "cores": gauss.threads(), "kind": "oracle",
-            "sample": f"forward at {per * len(w.stacks)} random stack voxels (brute force over "
-                      f"all {g.n} Gaussians: {p_f} contributing pairs, {t_f:.2f}s) + backward "
-                      f"of {len(sub)} random Gaussians over their boxes on 3 stacks "
-                      f"({p_b} pairs, {t_b:.2f}s); FP64 per-Gaussian setup {t_prep:.1f}s "
-                      "excluded"}
+        return pairs / (t_f + t_b), len(sub), pairs, t_f, t_b
+
+    cores = gauss.threads()
+    rate, n_all, p_all, tf_all, tb_all = run(n_gauss)
+    gauss.set_threads(1)
+    try:
+        rate1, n_one, p_one, tf_one, tb_one = run(n_gauss_1core)
+    finally:
+        gauss.set_threads(cores)
+    return {"value": rate, "unit": UNIT, "cores": cores, "kind": "oracle",
+            "sample": f"FP64 box-scatter forward + box-walk backward + chain rule of {n_all} "
+                      f"random Gaussians on the 3 stacks ({p_all} contributing pairs: forward "
+                      f"{tf_all:.2f}s, backward {tb_all:.2f}s, {cores} threads); FP64 "
+                      f"per-Gaussian set-up {t_prep:.1f}s excluded",
+            "single_core": {"value": rate1, "cores": 1,
+                            "sample": f"{n_one} random Gaussians ({p_one} pairs: forward "
+                                      f"{tf_one:.2f}s, backward {tb_one:.2f}s)"}}
 
 
 if __name__ == "__main__":

@@ -207,9 +207,24 @@ typedef struct gm_nrf {
 } gm_nrf;
 
 /* Inference (Sec. 3.1): render binned grid grid_id into out [nz][ny][nx]; when nrf is not
- * NULL add the residual r(x) at each voxel's world coordinate (Eq. 8, I_final = I + r). */
+ * NULL add the residual r(x) at each voxel's world coordinate (Eq. 8, I_final = I + r) in the
+ * same pass: each tile is rendered in LDS, the field is evaluated on its voxels with the
+ * weights staged once per block, and the sum is stored once.  Bit-identical to the render
+ * without the field followed by gm_nrf_forward on the same grid. */
 gm_status gm_render_volume(const gm_bins* bins, int32_t grid_id, const gm_nrf* nrf,
                            float* out, gm_stream stream);
+
+/* gm_render_loss_smooth_l1 with the residual field (Sec. 3.4, Eq. 8) added to every voxel of
+ * the listed stacks before the data term (Eq. 11) is formed, all in one pass: the prediction is
+ * I_k[v] + r(x_v) at the voxel's world coordinate x_v.  dl_di and the stored renderings (outs,
+ * as there; they hold I + r) are bit-identical to gm_render_stacks, gm_nrf_forward on each
+ * stack and gm_loss_smooth_l1, the loss equal up to the order of its FP64 sum.  dl_di is also dL/dr, the input gm_nrf_backward takes.  nrf must not be NULL;
+ * other arguments as for gm_render_loss_smooth_l1. */
+gm_status gm_render_nrf_loss_smooth_l1(const gm_bins* bins, const int32_t* grid_ids,
+                                       int32_t n_ids, const gm_nrf* nrf,
+                                       const float* const* targets, float* const* outs,
+                                       float* const* dl_di, float* loss, void* workspace,
+                                       size_t workspace_bytes, gm_stream stream);
 
 /* [host out] The index->world affine (row-major 3x4, binary64) of a grid: the inverse of its
  * world_to_index.  The residual field encodes the world coordinate of voxel v as, per row a,

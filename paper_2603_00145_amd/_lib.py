@@ -103,6 +103,10 @@ _SIGS = [
       ctypes.POINTER(P), ctypes.POINTER(P), P, P, ctypes.c_size_t, P]),
     ("gm_render_volume", ctypes.c_int, [ctypes.POINTER(GmBins), ctypes.c_int32,
                                          ctypes.POINTER(GmNrf), P, P]),
+    ("gm_render_nrf_loss_smooth_l1", ctypes.c_int,
+     [ctypes.POINTER(GmBins), ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+      ctypes.POINTER(GmNrf), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), P, P,
+      ctypes.c_size_t, P]),
     ("gm_loss_smooth_l1", ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(P),
                                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(P), P,
                                           P, P]),

@@ -242,10 +242,11 @@ def render(bins: Bins, ids: Sequence[int], outs: Optional[List[torch.Tensor]] = 
 
 def render_loss(bins: Bins, ids: Sequence[int], targets: Sequence[torch.Tensor],
                 dl_di: Optional[List[torch.Tensor]] = None,
-                outs: Optional[List[torch.Tensor]] = None):
+                outs: Optional[List[torch.Tensor]] = None, nrf=None):
     """gm_render_loss_smooth_l1: renders the listed grids and forms the smooth-L1 term in the
     same pass; returns (loss device scalar, dL/dI per stack).  The renderings are stored only
-    when outs is given."""
+    when outs is given.  With nrf (an nrf.NRF), gm_render_nrf_loss_smooth_l1: the residual
+    field is added to every voxel in the same pass before the loss."""
     if dl_di is None:
         dl_di = [torch.empty_like(t) for t in targets]
     for t in list(targets) + list(dl_di) + list(outs or []):
@@ -259,10 +260,18 @@ def render_loss(bins: Bins, ids: Sequence[int], targets: Sequence[torch.Tensor],
     loss = torch.empty(4, dtype=torch.float32, device=bins.device)
     idarr = (ctypes.c_int32 * max(1, len(ids)))(*ids)
     out_arr = None if outs is None else ptr_array([t.data_ptr() for t in outs])
-    check(load().gm_render_loss_smooth_l1(
-        ctypes.byref(bins.struct()), idarr, len(ids), ptr_array([t.data_ptr() for t in targets]),
-        out_arr, ptr_array([d.data_ptr() for d in dl_di]), _p(loss), _p(bins.loss_part),
-        bins.loss_part.numel() * 8, _stream()))
+    if nrf is None:
+        check(load().gm_render_loss_smooth_l1(
+            ctypes.byref(bins.struct()), idarr, len(ids),
+            ptr_array([t.data_ptr() for t in targets]), out_arr,
+            ptr_array([d.data_ptr() for d in dl_di]), _p(loss), _p(bins.loss_part),
+            bins.loss_part.numel() * 8, _stream()))
+    else:
+        check(load().gm_render_nrf_loss_smooth_l1(
+            ctypes.byref(bins.struct()), idarr, len(ids), ctypes.byref(nrf.struct()),
+            ptr_array([t.data_ptr() for t in targets]), out_arr,
+            ptr_array([d.data_ptr() for d in dl_di]), _p(loss), _p(bins.loss_part),
+            bins.loss_part.numel() * 8, _stream()))
     return loss[0], dl_di
 
 

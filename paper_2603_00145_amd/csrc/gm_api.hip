@@ -532,9 +532,15 @@ struct RenderLoss {
     size_t ws_bytes;
 };
 
+// nrf (optional): add the residual field to every rendered voxel in the same pass.
 static gm_status render_impl(const gm_bins* bins, const int32_t* ids, int32_t n_ids,
-                             float* const* outs, const RenderLoss* lo, hipStream_t s)
+                             float* const* outs, const RenderLoss* lo, hipStream_t s,
+                             const gm_nrf* nrf = nullptr)
 {
+    if (nrf) {
+        gm_status sn = check_nrf(nrf);
+        if (sn != GM_OK) return sn;
+    }
     gm_status st = check_bins(bins, true);
     if (st != GM_OK) return st;
     st = check_ids(bins, ids, n_ids);
@@ -572,6 +578,8 @@ static gm_status render_impl(const gm_bins* bins, const int32_t* ids, int32_t n_
         r.first_block = (int32_t)blocks;
         r.bin_tile_base = bins->tile_base[ids[k]];
         r.out = outs ? outs[k] : nullptr;
+        if (nrf && !index_to_world(g, r.index_to_world))
+            return fail(GM_ERR_INVALID_ARGUMENT, "grid %d: singular affine", ids[k]);
         blocks += grid_tiles(g);
     }
     if (blocks >= 0x7fffffffLL) return fail(GM_ERR_INVALID_ARGUMENT, "too many tiles");
@@ -597,7 +605,12 @@ static gm_status render_impl(const gm_bins* bins, const int32_t* ids, int32_t n_
     ra.records = bins->records;
     ra.tile_start = bins->tile_start;
     ra.pair_gauss = bins->pair_gauss;
-    GM_HIP(launch_render(ra, s), "render");
+    if (nrf) {
+        const NrfArgs f = nrf_args(nrf, bins->grids[ids[0]], ra.rg[0].index_to_world);
+        GM_HIP(launch_render_field(ra, f, s), "render + field");
+    } else {
+        GM_HIP(launch_render(ra, s), "render");
+    }
     return GM_OK;
 }
 
@@ -622,15 +635,22 @@ gm_status gm_render_volume(const gm_bins* bins, int32_t grid_id, const gm_nrf* n
                            gm_stream stream)
 {
     g_err.clear();
-    if (nrf) {
-        gm_status st = check_nrf(nrf);
-        if (st != GM_OK) return st;
-    }
     float* outs[1] = {out};
-    gm_status st = render_impl(bins, &grid_id, 1, outs, nullptr,
-                               reinterpret_cast<hipStream_t>(stream));
-    if (st != GM_OK || !nrf) return st;
-    return gm_nrf_forward(nrf, &bins->grids[grid_id], out, stream);
+    return render_impl(bins, &grid_id, 1, outs, nullptr, reinterpret_cast<hipStream_t>(stream),
+                       nrf);
+}
+
+gm_status gm_render_nrf_loss_smooth_l1(const gm_bins* bins, const int32_t* grid_ids,
+                                       int32_t n_ids, const gm_nrf* nrf,
+                                       const float* const* targets, float* const* outs,
+                                       float* const* dl_di, float* loss, void* workspace,
+                                       size_t workspace_bytes, gm_stream stream)
+{
+    g_err.clear();
+    if (!nrf) return fail(GM_ERR_INVALID_ARGUMENT, "nrf is NULL");
+    const RenderLoss lo{targets, dl_di, loss, workspace, workspace_bytes};
+    return render_impl(bins, grid_ids, n_ids, outs, &lo, reinterpret_cast<hipStream_t>(stream),
+                       nrf);
 }
 
 gm_status gm_index_to_world(const gm_grid* grid, double out[12])

@@ -100,6 +100,7 @@ struct RenderGrid {
     float* out;              // rendered values, or NULL (loss mode only)
     const float* target;     // loss mode: the stack's data
     float* dl;               // loss mode: dL/dI of the smooth-L1 term
+    double index_to_world[12]; // with a residual field: the grid's index -> world affine
 };
 struct RenderArgs {
     int32_t n_render;
@@ -114,6 +115,10 @@ struct RenderArgs {
     RenderGrid rg[GM_MAX_GRIDS];
 };
 hipError_t launch_render(const RenderArgs& a, hipStream_t s);
+struct NrfArgs;
+// the render with the residual field added to every voxel in the same pass (f's grid fields
+// unused: each grid's index -> world affine comes from its RenderGrid)
+hipError_t launch_render_field(const RenderArgs& a, const NrfArgs& f, hipStream_t s);
 
 struct BackwardArgs {
     int64_t n;

@@ -11,7 +11,7 @@
 // at most 64 columns share the wave (the first piece's columns on the low lanes); the first
 // piece's lanes add into the tile before the second's, so every voxel's sum is still formed
 // in ascending Gaussian order and the result is the same on every run.
-#include "gm_internal.h"
+#include "nrf_core.h"
 
 namespace {
 
@@ -125,50 +125,85 @@ __device__ __forceinline__ void paired_pieces(const Piece& p, float* acc, bool a
 // wavefronts fit per SIMD.
 constexpr int RB = 32;
 
-__global__ __launch_bounds__(64) void k_render(const RenderArgs a)
+// Barrier before LDS written by some lanes is read by others.  BLOCK: the workgroup is this
+// one wavefront (a block barrier); otherwise the other wavefronts of the block run their own
+// tiles, so only this wavefront's LDS accesses are ordered (a workgroup-scope fence waits for
+// them; the wavefront's lanes run in lockstep).
+template <bool BLOCK>
+__device__ __forceinline__ void tile_sync()
 {
-    __shared__ float acc[GM_TILE_VOX];
-    __shared__ Piece pc[RB];
-    const int lane = threadIdx.x;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    if constexpr (BLOCK) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Origin and grid of flattened tile t of a launch (t < a.total_blocks).
+struct TilePos {
+    const RenderGrid* G;
+    int lt;                 // tile within its grid
+    int t0x, t0y, t0z;      // first voxel
+};
+
+__device__ __forceinline__ TilePos tile_pos(const RenderArgs& a, int t)
+{
     int r = 0;
 #pragma unroll 1
-    while (r + 1 < a.n_render && blk >= a.rg[r + 1].first_block) ++r;
-    const RenderGrid& G = a.rg[r];
-    const int lt = blk - G.first_block;
-    const int tx = lt % G.ntx, ty = (lt / G.ntx) % G.nty, tz = lt / (G.ntx * G.nty);
-    const int t0x = tx * GM_TX, t0y = ty * GM_TY, t0z = tz * GM_TZ;
+    while (r + 1 < a.n_render && t >= a.rg[r + 1].first_block) ++r;
+    TilePos p;
+    p.G = &a.rg[r];
+    p.lt = t - p.G->first_block;
+    const int tx = p.lt % p.G->ntx, ty = (p.lt / p.G->ntx) % p.G->nty;
+    const int tz = p.lt / (p.G->ntx * p.G->nty);
+    p.t0x = tx * GM_TX;
+    p.t0y = ty * GM_TY;
+    p.t0z = tz * GM_TZ;
+    return p;
+}
+
+constexpr int VPL = GM_TILE_VOX / 64;   // tile voxels per lane in the epilogues
+
+// loss mode: the tile's data values, loaded before the Gaussian list is walked so that their
+// latency is hidden behind the accumulation
+__device__ __forceinline__ void load_targets(const TilePos& P, int lane, float (&tv)[VPL])
+{
+    const RenderGrid& G = *P.G;
+#pragma unroll
+    for (int j = 0; j < VPL; ++j) {
+        const int i = j * 64 + lane;
+        const int x = i % GM_TX, y = (i / GM_TX) % GM_TY, z = i / (GM_TX * GM_TY);
+        const int gx = P.t0x + x, gy = P.t0y + y, gz = P.t0z + z;
+        // outside the grid: a valid address (voxel 0) whose value goes unused
+        const bool in = (gx < G.nx) & (gy < G.ny) & (gz < G.nz);
+        const size_t v = in ? ((size_t)gz * G.ny + gy) * G.nx + gx : 0;
+        tv[j] = __builtin_nontemporal_load(G.target + v);
+    }
+}
+
+// acc (the tile's voxels, LDS) = the sum over the tile's list of Gaussians, in list order.
+// Ends with a tile_sync, so every lane may read any voxel afterwards.
+template <bool BLOCK>
+__device__ __forceinline__ void accumulate_tile(const RenderArgs& a, const TilePos& P, float* acc,
+                                                Piece* pc, int lane)
+{
+    const RenderGrid& G = *P.G;
+    const int t0x = P.t0x, t0y = P.t0y, t0z = P.t0z;
     const float* __restrict__ recbase = a.records + (size_t)G.grid_index * a.n_gauss * 16;
     const int* __restrict__ pg = a.pair_gauss;
 
 #pragma unroll
     for (int j = 0; j < GM_TILE_VOX / 64; ++j) acc[j * 64 + lane] = 0.0f;
 
-    // loss mode: the tile's data values are loaded now, so that their latency is hidden
-    // behind the accumulation
-    constexpr int VPL = GM_TILE_VOX / 64;
-    float tv[VPL];
-    if (a.loss_part) {
-#pragma unroll
-        for (int j = 0; j < VPL; ++j) {
-            const int i = j * 64 + lane;
-            const int x = i % GM_TX, y = (i / GM_TX) % GM_TY, z = i / (GM_TX * GM_TY);
-            const int gx = t0x + x, gy = t0y + y, gz = t0z + z;
-            // outside the grid: a valid address (voxel 0) whose value goes unused
-            const bool in = (gx < G.nx) & (gy < G.ny) & (gz < G.nz);
-            const size_t v = in ? ((size_t)gz * G.ny + gy) * G.nx + gx : 0;
-            tv[j] = __builtin_nontemporal_load(G.target + v);
-        }
-    }
-
-    const int64_t bt = G.bin_tile_base + lt;
+    const int64_t bt = G.bin_tile_base + P.lt;
     const int s = sgpr(a.tile_start[bt]);
     const int e = sgpr(a.tile_start[bt + 1]);
 
 #pragma unroll 1
     for (int b0 = s; b0 < e; b0 += RB) {
         const int nb = min(RB, e - b0);
-        __syncthreads();
+        tile_sync<BLOCK>();
         int myF = 0, myWz = 0;  // this lane's piece: footprint area and z extent
         if (lane < nb) {
             const int gid = (int)((uint32_t)pg[b0 + lane] & GM_ID_MASK);
@@ -203,7 +238,7 @@ __global__ __launch_bounds__(64) void k_render(const RenderArgs a)
         // bit j: pieces j and j + 1 fit side by side in the wave (footprints summing to <= 64)
         const int nextF = __shfl_down(myF, 1, 64);
         const uint64_t pm = __ballot(lane + 1 < nb && myF + nextF <= 64);
-        __syncthreads();
+        tile_sync<BLOCK>();
         int j = 0;
 #pragma unroll 1
         while (j < nb) {
@@ -240,28 +275,36 @@ __global__ __launch_bounds__(64) void k_render(const RenderArgs a)
             }
         }
     }
-    __syncthreads();
+    tile_sync<BLOCK>();
+}
+
+// Writes the finished tile (plain mode), or (loss mode) the smooth-L1 data term on it (Eq. 11,
+// beta = 1): dL/dI = clamp(I - y, -1, 1) / N, the rendering when G.out is set, and the tile's
+// FP64 sum of smoothL1(I - y) to a.loss_part[part].
+__device__ __forceinline__ void finish_tile(const RenderArgs& a, const TilePos& P,
+                                            const float* acc, const float (&tv)[VPL], int lane,
+                                            int part)
+{
+    const RenderGrid& G = *P.G;
     float* out = G.out;
     if (!a.loss_part) {
 #pragma unroll
         for (int j = 0; j < GM_TILE_VOX / 64; ++j) {
             const int i = j * 64 + lane;
             const int x = i % GM_TX, y = (i / GM_TX) % GM_TY, z = i / (GM_TX * GM_TY);
-            const int gx = t0x + x, gy = t0y + y, gz = t0z + z;
+            const int gx = P.t0x + x, gy = P.t0y + y, gz = P.t0z + z;
             if ((gx < G.nx) & (gy < G.ny) & (gz < G.nz))
                 out[((size_t)gz * G.ny + gy) * G.nx + gx] = acc[i];
         }
         return;
     }
-    // the smooth-L1 data term (Eq. 11, beta = 1) on the tile: dL/dI = clamp(I - y, -1, 1) / N
-    // and the tile's sum of smoothL1(I - y), FP64
     const float g_scale = (float)a.inv_n;
     double lsum = 0.0;
 #pragma unroll
     for (int j = 0; j < GM_TILE_VOX / 64; ++j) {
         const int i = j * 64 + lane;
         const int x = i % GM_TX, y = (i / GM_TX) % GM_TY, z = i / (GM_TX * GM_TY);
-        const int gx = t0x + x, gy = t0y + y, gz = t0z + z;
+        const int gx = P.t0x + x, gy = P.t0y + y, gz = P.t0z + z;
         if ((gx < G.nx) & (gy < G.ny) & (gz < G.nz)) {
             const size_t v = ((size_t)gz * G.ny + gy) * G.nx + gx;
             const float val = acc[i];
@@ -273,7 +316,69 @@ __global__ __launch_bounds__(64) void k_render(const RenderArgs a)
         }
     }
     for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
-    if (lane == 0) a.loss_part[blk] = lsum;
+    if (lane == 0) a.loss_part[part] = lsum;
+}
+
+__global__ __launch_bounds__(64) void k_render(const RenderArgs a)
+{
+    __shared__ float acc[GM_TILE_VOX];
+    __shared__ Piece pc[RB];
+    const int lane = threadIdx.x;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const TilePos P = tile_pos(a, blk);
+    float tv[VPL];
+    if (a.loss_part) load_targets(P, lane, tv);
+    accumulate_tile<true>(a, P, acc, pc, lane);
+    finish_tile(a, P, acc, tv, lane, blk);
+}
+
+// Render + residual field (Sec. 3.4, Eq. 8: I_final = I + r) in one pass.  Blocks of FW
+// wavefronts share the field's weights, staged once in LDS; each wavefront takes whole tiles
+// (the tiles of the launch are split into eight contiguous ranges, one per XCD, whose blocks
+// deal them to their wavefronts), renders a tile into its LDS accumulator exactly as k_render
+// does, then evaluates the field on the tile's voxels in 64 groups of 16 (one x row each) and
+// adds out_scale tanh(z_out) to each voxel before the store or loss epilogue.  Each point's
+// field value is the same arithmetic as the field's own forward kernel, so the result is bit
+// for bit the render followed by gm_nrf_forward (and the loss the same terms).
+constexpr int FW = 8;
+
+template <int KT, int DEPTH>
+__global__ __launch_bounds__(64 * FW) void k_render_field(const RenderArgs a, const NrfArgs f)
+{
+    __shared__ nrfcore::Lds<KT, DEPTH> sw;
+    __shared__ float accs[FW][GM_TILE_VOX];
+    __shared__ Piece pcs[FW][RB];
+    nrfcore::load_weights<KT, DEPTH>(f, sw);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, row = lane & 15;
+    float* acc = accs[w];
+    Piece* pc = pcs[w];
+    const int xcd = blockIdx.x & 7;
+    const int nbx = (int)(gridDim.x >> 3);     // the launch has a multiple of 8 blocks
+    const int T = a.total_blocks;
+    const int lo = (int)((int64_t)T * xcd / 8), hi = (int)((int64_t)T * (xcd + 1) / 8);
+#pragma unroll 1
+    for (int t = lo + (int)(blockIdx.x >> 3) * FW + w; t < hi; t += nbx * FW) {
+        const TilePos P = tile_pos(a, t);
+        const RenderGrid& G = *P.G;
+        float tv[VPL];
+        if (a.loss_part) load_targets(P, lane, tv);
+        accumulate_tile<false>(a, P, acc, pc, lane);
+#pragma unroll 1
+        for (int q = 0; q < GM_TILE_VOX / 16; ++q) {
+            const int vy = P.t0y + (q % GM_TY), vz = P.t0z + q / GM_TY, vx = P.t0x + row;
+            if (vy >= G.ny || vz >= G.nz) continue;     // uniform over the wavefront
+            const float x[3] = {nrfcore::world_coord(G.index_to_world, vx, vy, vz),
+                                nrfcore::world_coord(G.index_to_world + 4, vx, vy, vz),
+                                nrfcore::world_coord(G.index_to_world + 8, vx, vy, vz)};
+            nrfcore::Tile<KT, DEPTH> Tl;
+            nrfcore::tile_forward<KT, DEPTH>(f, sw, x, Tl);
+            const float zo = nrfcore::tile_output<KT, DEPTH>(f, Tl);
+            if (g == 0 && vx < G.nx) acc[q * 16 + row] += f.out_scale * tanhf(zo);
+        }
+        tile_sync<false>();
+        finish_tile(a, P, acc, tv, lane, t);
+        tile_sync<false>();
+    }
 }
 
 // loss = inv_n * sum of the per-block sums, in a fixed order.  Each thread takes four
@@ -310,6 +415,41 @@ hipError_t launch_render(const RenderArgs& a, hipStream_t s)
 {
     if (a.total_blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_render, dim3((unsigned)a.total_blocks), dim3(64), 0, s, a);
+    if (a.loss_part)
+        hipLaunchKernelGGL(k_render_loss_finish, dim3(1), dim3(FIN_THREADS), 0, s, a.loss_part,
+                           a.total_blocks, a.inv_n, a.loss);
+    return hipGetLastError();
+}
+
+template <int KT, int DEPTH>
+static void launch_field_t(const RenderArgs& a, const NrfArgs& f, hipStream_t s)
+{
+    // every block resident at once, a multiple of 8 (one share per XCD), capped by the tiles
+    int dev = 0, cus = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_render_field<KT, DEPTH>, 64 * FW, 0);
+    int64_t full = (int64_t)(cus > 0 ? cus : 256) * (per_cu > 0 ? per_cu : 1);
+    int64_t need = ((int64_t)a.total_blocks + FW - 1) / FW;
+    int64_t nb = need < full ? need : full;
+    nb = (nb + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_render_field<KT, DEPTH>), dim3((unsigned)nb), dim3(64 * FW), 0, s, a, f);
+}
+
+hipError_t launch_render_field(const RenderArgs& a, const NrfArgs& f, hipStream_t s)
+{
+    if (a.total_blocks == 0) return hipSuccess;
+    switch ((f.in_pad >> 4) * 8 + f.depth) {
+    case 4 * 8 + 1: launch_field_t<4, 1>(a, f, s); break;
+    case 4 * 8 + 2: launch_field_t<4, 2>(a, f, s); break;
+    case 4 * 8 + 3: launch_field_t<4, 3>(a, f, s); break;
+    case 4 * 8 + 4: launch_field_t<4, 4>(a, f, s); break;
+    case 8 * 8 + 1: launch_field_t<8, 1>(a, f, s); break;
+    case 8 * 8 + 2: launch_field_t<8, 2>(a, f, s); break;
+    case 8 * 8 + 3: launch_field_t<8, 3>(a, f, s); break;
+    case 8 * 8 + 4: launch_field_t<8, 4>(a, f, s); break;
+    default: return hipErrorInvalidValue;
+    }
     if (a.loss_part)
         hipLaunchKernelGGL(k_render_loss_finish, dim3(1), dim3(FIN_THREADS), 0, s, a.loss_part,
                            a.total_blocks, a.inv_n, a.loss);

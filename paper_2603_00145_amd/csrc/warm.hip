@@ -31,9 +31,17 @@ __device__ __forceinline__ float dsilu(float z)
     const float s = sigm(z);
     return s * (1.0f + z * (1.0f - s));
 }
-__device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c)
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// gfx950's 16x16x32 BF16 MFMA over two 16-wide K halves: lane group g supplies, in A and in B
+// alike, slots 4 g + j of the first half (a0, b0) and of the second (a1, b1), so the product
+// sums all 32 slots whatever order the hardware gives them.  The result has the 16x16x16
+// layout (lane group g: rows 4 g + j of column lane & 15).
+__device__ __forceinline__ v4f mfma2(v4s a0, v4s a1, v4s b0, v4s b1, v4f c)
 {
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    const v8bf a = __builtin_bit_cast(v8bf, __builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7));
+    const v8bf b = __builtin_bit_cast(v8bf, __builtin_shufflevector(b0, b1, 0, 1, 2, 3, 4, 5, 6, 7));
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
 constexpr int CO = 32;
@@ -71,9 +79,10 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ W
     const int p = (int)(n - b * G::PO);
     const int oz = p / (G::DO * G::DO), oy = (p / G::DO) % G::DO, ox = p % G::DO;
     const uint16_t* xb = X + b * G::CI * G::PI;
-    v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int k0 = 0; k0 < G::KPAD; k0 += 16) {
-        const v4s Af = *reinterpret_cast<const v4s*>(W + (m0 + row) * G::KPAD + k0 + 4 * g);
+    static_assert(G::KPAD % 32 == 0, "whole 32-wide K steps");
+    // the A and B fragments of the 16-wide K block at k0
+    auto frag = [&](int k0, v4s& Af, v4s& Bf) {
+        Af = *reinterpret_cast<const v4s*>(W + (m0 + row) * G::KPAD + k0 + 4 * g);
         short bv[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -88,9 +97,14 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ W
             const short v = (short)xb[idx];
             bv[j] = ok ? v : (short)0;
         }
-        v4s Bf;
-        Bf.x = bv[0]; Bf.y = bv[1]; Bf.z = bv[2]; Bf.w = bv[3];
-        acc = mfma(Af, Bf, acc);
+        Bf = v4s{bv[0], bv[1], bv[2], bv[3]};
+    };
+    v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = 0; k0 < G::KPAD; k0 += 32) {
+        v4s A0, B0, A1, B1;
+        frag(k0, A0, B0);
+        frag(k0 + 16, A1, B1);
+        acc = mfma2(A0, A1, B0, B1, acc);
     }
     const float av[4] = {acc.x, acc.y, acc.z, acc.w};
 #pragma unroll
@@ -151,10 +165,8 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(const uint16_t* __restrict
         const int p = (tI % NCT) * 16 + row;  // this lane's output position
         const int oz = p / (G::DO * G::DO), oy = (p / G::DO) % G::DO, ox = p % G::DO;
         const int base = ((G::ST * oz) * DP + G::ST * oy) * DP + G::ST * ox;
-        v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 3
-        for (int k0 = 0; k0 < G::KPAD; k0 += 16) {
-            const v4s Af = *reinterpret_cast<const v4s*>(W + (m0 + row) * G::KPAD + k0 + 4 * g);
+        auto frag = [&](int k0, v4s& Af, v4s& Bf) {
+            Af = *reinterpret_cast<const v4s*>(W + (m0 + row) * G::KPAD + k0 + 4 * g);
             const int4 ko = *reinterpret_cast<const int4*>(koff + k0 + 4 * g);
             short bv[4];
             const int kk[4] = {ko.x, ko.y, ko.z, ko.w};
@@ -167,9 +179,16 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(const uint16_t* __restrict
                     bv[j] = (short)xin[base + kk[j]];
                 }
             }
-            v4s Bf;
-            Bf.x = bv[0]; Bf.y = bv[1]; Bf.z = bv[2]; Bf.w = bv[3];
-            acc = mfma(Af, Bf, acc);
+            Bf = v4s{bv[0], bv[1], bv[2], bv[3]};
+        };
+        static_assert(G::KPAD % 32 == 0, "whole 32-wide K steps");
+        v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 3
+        for (int k0 = 0; k0 < G::KPAD; k0 += 32) {
+            v4s A0, B0, A1, B1;
+            frag(k0, A0, B0);
+            frag(k0 + 16, A1, B1);
+            acc = mfma2(A0, A1, B0, B1, acc);
         }
         const float av[4] = {acc.x, acc.y, acc.z, acc.w};
 #pragma unroll
@@ -203,8 +222,8 @@ __global__ __launch_bounds__(256) void k_conv_bwd_x(const uint16_t* __restrict__
     const int iz = p / (G::DI * G::DI), iy = (p / G::DI) % G::DI, ix = p % G::DI;
     const uint16_t* dzb = dZ + b * CO * G::PO;
     constexpr int KT = CO * G::KV;                     // reduction over (o, tap)
-    v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int k0 = 0; k0 < KT; k0 += 16) {
+    static_assert(KT % 32 == 0, "whole 32-wide K steps");
+    auto frag = [&](int k0, v4s& Af, v4s& Bf) {
         short av[4], bv[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -223,10 +242,15 @@ __global__ __launch_bounds__(256) void k_conv_bwd_x(const uint16_t* __restrict__
             const short v = (short)dzb[idx];
             bv[j] = ok ? v : (short)0;
         }
-        v4s Af, Bf;
-        Af.x = av[0]; Af.y = av[1]; Af.z = av[2]; Af.w = av[3];
-        Bf.x = bv[0]; Bf.y = bv[1]; Bf.z = bv[2]; Bf.w = bv[3];
-        acc = mfma(Af, Bf, acc);
+        Af = v4s{av[0], av[1], av[2], av[3]};
+        Bf = v4s{bv[0], bv[1], bv[2], bv[3]};
+    };
+    v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = 0; k0 < KT; k0 += 32) {
+        v4s A0, B0, A1, B1;
+        frag(k0, A0, B0);
+        frag(k0 + 16, A1, B1);
+        acc = mfma2(A0, A1, B0, B1, acc);
     }
     const float r[4] = {acc.x, acc.y, acc.z, acc.w};
 #pragma unroll
@@ -307,8 +331,8 @@ __global__ __launch_bounds__(256) void k_conv_bwd_x_par(const uint16_t* __restri
         const int q = ct * 16 + row;         // this lane's position within the class
         const int az = q / (H * H), ay = (q / H) % H, ax = q % H;
         const int colbase = (az * DQ + ay) * DQ + ax;
-        v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        for (int k0 = 0; k0 < kc; k0 += 16) {
+        // kc = CO 2^popcount(class) is a multiple of 32
+        auto frag = [&](int k0, v4s& Af, v4s& Bf) {
             const int e0 = kb + k0 + 4 * g;
             short av[4], bv[4];
 #pragma unroll
@@ -316,10 +340,16 @@ __global__ __launch_bounds__(256) void k_conv_bwd_x_par(const uint16_t* __restri
                 av[j] = (short)W[aoff[e0 + j] + (m0 + row) * G::KV];
                 bv[j] = (short)dzs[colbase + boff[e0 + j]];
             }
-            v4s Af, Bf;
-            Af.x = av[0]; Af.y = av[1]; Af.z = av[2]; Af.w = av[3];
-            Bf.x = bv[0]; Bf.y = bv[1]; Bf.z = bv[2]; Bf.w = bv[3];
-            acc = mfma(Af, Bf, acc);
+            Af = v4s{av[0], av[1], av[2], av[3]};
+            Bf = v4s{bv[0], bv[1], bv[2], bv[3]};
+        };
+        static_assert(CO % 32 == 0, "whole 32-wide K steps per class");
+        v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int k0 = 0; k0 < kc; k0 += 32) {
+            v4s A0, B0, A1, B1;
+            frag(k0, A0, B0);
+            frag(k0 + 16, A1, B1);
+            acc = mfma2(A0, A1, B0, B1, acc);
         }
         const int iz = 2 * az + ((c >> 2) & 1), iy = 2 * ay + ((c >> 1) & 1), ix = 2 * ax + (c & 1);
         const int pin = (iz * G::DI + iy) * G::DI + ix;
@@ -353,8 +383,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__
     const int c = kn / G::KV, t = kn - c * G::KV;
     const int kz = t / (G::K * G::K), ky = (t / G::K) % G::K, kx = t % G::K;
     const bool kvalid = kn < G::KREAL;
-    v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int64_t r0 = r_begin; r0 < r_end; r0 += 16) {
+    auto frag = [&](int64_t r0, v4s& Af, v4s& Bf) {
         short av[4], bv[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -371,10 +400,17 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__
             const short v = (short)X[idx];
             bv[j] = ok ? v : (short)0;
         }
-        v4s Af, Bf;
-        Af.x = av[0]; Af.y = av[1]; Af.z = av[2]; Af.w = av[3];
-        Bf.x = bv[0]; Bf.y = bv[1]; Bf.z = bv[2]; Bf.w = bv[3];
-        acc = mfma(Af, Bf, acc);
+        Af = v4s{av[0], av[1], av[2], av[3]};
+        Bf = v4s{bv[0], bv[1], bv[2], bv[3]};
+    };
+    // the chunk holds a multiple of 16 rows (B is); an odd 16-row block at its end pairs with
+    // zeros
+    v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += 32) {
+        v4s A0, B0, A1 = v4s{0, 0, 0, 0}, B1 = v4s{0, 0, 0, 0};
+        frag(r0, A0, B0);
+        if (r0 + 16 < r_end) frag(r0 + 16, A1, B1);
+        acc = mfma2(A0, A1, B0, B1, acc);
     }
     float* out = part + (int64_t)blockIdx.y * CO * G::KPAD;
     const float r[4] = {acc.x, acc.y, acc.z, acc.w};

@@ -108,16 +108,12 @@ class Reconstruction:
         if self.poses is not None:
             self.bins.set_grids([q.grid() for q in self.poses])
         self.bins.bin(self.p)
-        if self.nrf_on:
-            api.render(self.bins, self.ids, self.outs)
-            for k, s in enumerate(self.stacks):
-                c.nrf.forward_add(s, self.outs[k])
-            loss, _ = api.smooth_l1(self.outs, self.targets, self.dls)
-        else:
-            # the loss is formed in the render's epilogue; the renderings are stored only
-            # when the SSIM term reads them
-            loss, _ = api.render_loss(self.bins, self.ids, self.targets, self.dls,
-                                      outs=self.outs if c.lambda_ssim > 0 else None)
+        # the loss is formed in the render's epilogue (with the residual field added to every
+        # voxel first once it is on); the renderings are stored only when the SSIM term reads
+        # them
+        loss, _ = api.render_loss(self.bins, self.ids, self.targets, self.dls,
+                                  outs=self.outs if c.lambda_ssim > 0 else None,
+                                  nrf=c.nrf if self.nrf_on else None)
         if c.lambda_ssim > 0:
             loss = loss + c.lambda_ssim * api.ssim_loss(self.outs, self.targets, self.dls,
                                                         c.lambda_ssim)
@@ -138,10 +134,7 @@ class Reconstruction:
 
     def render_volume(self) -> torch.Tensor:
         self.vbins.bin(self.p)
-        vol = api.render_volume(self.vbins, 0)
-        if self.nrf_on:
-            self.cfg.nrf.forward_add(self.volume_grid, vol)
-        return vol
+        return api.render_volume(self.vbins, 0, nrf=self.cfg.nrf if self.nrf_on else None)
 
     def psnr(self) -> float:
         vol = self.render_volume()

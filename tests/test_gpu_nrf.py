@@ -7,6 +7,7 @@ import pytest
 import torch
 
 from oracle import nrf as onrf
+from precision_report import row as report
 from paper_2603_00145_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -49,6 +50,8 @@ def test_nrf_forward_parity(mods, n_freq, depth):
     x = onrf.world_coords(all_voxels(grid), onrf.index_to_world(grid.world_to_index))
     r_ref, *_ = onrf.forward(net.weights_host(), onrf.encode(x, n_freq, net.in_pad), net.out_scale)
     err = normwise(r_gpu, r_ref)
+    report(f"33x33x9 stack, L={n_freq} D={depth}", "field r, every voxel", "BF16 MFMA, FP32 acc.",
+           r_gpu, r_ref)
     say(f"  nrf forward L={n_freq} D={depth}: normwise {err:.2e}, max|r| {np.abs(r_ref).max():.3f}")
     assert err <= TOL_BF16
 
@@ -110,6 +113,8 @@ def test_nrf_backward_parity_training_size(mods):
                    (f"b_hid{l}", got["b_hid"][l], g["b"][l + 1])]
     for name, a, r in checks:
         err = normwise(a, r)
+        report("256x256x64 stack, 2^18 sampled voxels", f"field dL/d{name}",
+               "BF16 MFMA, FP32 acc.", a, r)
         say(f"  nrf backward 2^18 points {name}: {err:.2e}")
         assert err <= TOL_BF16, name
 
@@ -129,6 +134,46 @@ def test_render_volume_with_nrf(mods):
     torch.cuda.synchronize()
     assert torch.equal(with_r, extra)
     assert float((with_r - plain).abs().max()) > 1e-4
+
+
+@pytest.mark.parametrize("n_freq,depth", [(16, 3), (6, 2)])
+def test_fused_render_field_loss(mods, n_freq, depth):
+    """gm_render_nrf_loss_smooth_l1 (render + field + smooth-L1 in one pass) against the three
+    calls it fuses, on ragged rotated stacks and a ragged volume: renderings and dL/dI bit for
+    bit, the loss to 1e-6 (the order of its FP64 sum differs)."""
+    _lib, api, nrf = mods
+    rng = np.random.default_rng(7 + depth)
+    n = 41
+    g = inputs.init_anisotropic(n, 900, rng)
+    grids = [inputs.stack_grid("axial", n, 11, 1.0, *inputs.random_rigid(rng, 2, 1, n)),
+             inputs.stack_grid("coronal", n, 9, 1.0, *inputs.random_rigid(rng, 2, 1, n)),
+             inputs.stack_grid("sagittal", n, 13, 1.0),
+             inputs.volume_grid(n)]
+    ids = [0, 1, 2, 3]
+    say(f"fused render + field + loss: n_freq {n_freq} depth {depth}")
+    targ = [torch.from_numpy(rng.normal(0.3, 1.0, size=gr.shape).astype(np.float32)).cuda()
+            for gr in grids]
+    b = api.Bins(g.n, grids)
+    b.bin(api.GaussParams.from_host(g))
+    net = nrf.NRF(n_freq=n_freq, depth=depth, seed=3, zero_last=False)
+    outs = api.render(b, ids)
+    for k in ids:
+        net.forward_add(grids[k], outs[k])
+    ref_loss, ref_dl = api.smooth_l1(outs, targ)
+    stored = [torch.full(gr.shape, float("nan"), device="cuda") for gr in grids]
+    loss, dl = api.render_loss(b, ids, targ, outs=stored, nrf=net)
+    loss2, dl2 = api.render_loss(b, ids, targ, nrf=net)
+    vol = api.render_volume(b, 3, nrf=net)
+    torch.cuda.synchronize()
+    for k in ids:
+        assert torch.equal(stored[k], outs[k]), f"grid {k}: rendering + field differs"
+        assert torch.equal(dl[k], ref_dl[k]), f"grid {k}: dL/dI differs"
+        assert torch.equal(dl2[k], dl[k])
+    assert torch.equal(vol, outs[3])
+    assert float(loss2) == float(loss)
+    assert float(loss) == pytest.approx(float(ref_loss), rel=1e-6)
+    plain = api.render(b, ids)
+    assert max(float((o - q).abs().max()) for o, q in zip(outs, plain)) > 1e-4  # field is on
 
 
 def test_reconstruction_with_nrf_runs(mods):

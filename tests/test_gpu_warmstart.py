@@ -8,6 +8,7 @@ import pytest
 import torch
 
 from oracle import warm as owarm
+from precision_report import row as report
 from paper_2603_00145_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -86,6 +87,8 @@ def test_forward_and_gradients_match_oracle(mods, n):
     rs, rq, rl = owarm.assemble(out, s0.astype(np.float64), l0.astype(np.float64))
     for name, a, r in (("log_scale", s, rs), ("quat", q, rq), ("logit", lg, rl)):
         err = normwise(a.cpu().numpy(), r)
+        report(f"warm-start batch {n}", f"network output {name}", "BF16 MFMA, FP32 acc.",
+               a.cpu().numpy(), r)
         say(f"  warm forward {name}: {err:.2e}")
         assert err <= TOL_BF16
     L, dout = owarm.loss_grad(out, s0.astype(np.float64), l0.astype(np.float64), sig, lt)
@@ -97,6 +100,8 @@ def test_forward_and_gradients_match_oracle(mods, n):
     got["bl"] = net.g["bl"].cpu().numpy()
     for k in got:
         err = normwise(got[k], g[k].reshape(got[k].shape))
+        report(f"warm-start batch {n}", f"weight gradient {k}", "BF16 MFMA, FP32 acc.", got[k],
+               g[k].reshape(got[k].shape))
         say(f"  warm gradient {k}: {err:.2e}")
         assert err <= TOL_BF16, k
 

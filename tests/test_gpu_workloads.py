@@ -9,6 +9,7 @@ import pytest
 import torch
 
 from adam_bounds import adam_range, check_range
+from precision_report import row as report
 from oracle import gauss, recipe
 from oracle import nrf as onrf
 from paper_2603_00145_amd import inputs
@@ -87,6 +88,7 @@ def test_full_size_sampled_parity(mods, name):
         ref = gauss.render_points(pts, gt, lo, hi, ne)
         got = outs[k].cpu().numpy()[pts[:, 2], pts[:, 1], pts[:, 0]]
         err = normwise(got, ref)
+        report(name, f"stack {k} ({grid.name}) I, 600 sampled voxels", "FP32", got, ref)
         say(f"  {name} grid {k} ({grid.name}): {b.pair_count(k)} pairs, sampled voxel error {err:.2e}")
         assert err <= TOL
     sub = np.sort(rng.choice(p.n, 3000, replace=False))
@@ -99,6 +101,8 @@ def test_full_size_sampled_parity(mods, name):
     ref[2] = ref[2] + 0.1 * gauss.aniso(w.gauss.log_scale, 1.5)[1][sub]
     for pname, t, r in zip(("mean", "quat", "log_scale", "logit"), grads.tensors(), ref):
         err = normwise(t.cpu().numpy()[sub], r)
+        report(name, f"dL/d{pname}, 3000 sampled Gaussians (random dL/dI)", "FP32",
+               t.cpu().numpy()[sub], r)
         say(f"  {name} sampled gradient {pname}: {err:.2e}")
         assert err <= TOL
 
@@ -131,6 +135,10 @@ def test_c320_volume_crop_fp32_and_bf16(mods):
     e32 = normwise(g_plain, ref_g)
     e_r = normwise(g_full - g_plain, r_ref)
     e_all = normwise(g_full, ref_g + r_ref)
+    report("c320 crop [128,192)^3", "volume I (Gaussians)", "FP32", g_plain, ref_g)
+    report("c320 crop [128,192)^3", "residual field r", "BF16 MFMA, FP32 acc.", g_full - g_plain,
+           r_ref)
+    report("c320 crop [128,192)^3", "I + r", "FP32 + BF16", g_full, ref_g + r_ref)
     say(f"  c320 crop: {int(sel.sum())} Gaussians meet it")
     say(f"  FP32 Gaussians: normwise {e32:.2e}, per-element {elementwise(g_plain, ref_g):.2e}")
     say(f"  BF16 field r: normwise {e_r:.2e}, per-element {elementwise(g_full - g_plain, r_ref):.2e}")
@@ -174,12 +182,15 @@ def test_c256_training_step_every_voxel_and_gaussian(mods):
     for k, (o, r) in enumerate(zip(outs, ref["renders"])):
         o = o.cpu().numpy()
         e = normwise(o, r)
+        report("c256 step", f"stack {k} I, every voxel", "FP32", o, r)
         say(f"  stack {k}: every voxel normwise {e:.2e}, per-element {elementwise(o, r):.2e}")
         assert e <= TOL
+    report("c256 step", "smooth-L1 loss", "FP32 (FP64 sums)", [float(loss)], [ref["loss"]])
     say(f"  loss gpu {float(loss):.9g} oracle {ref['loss']:.9g}")
     assert abs(float(loss) - ref["loss"]) <= TOL * ref["loss"]
     for k, (d, r) in enumerate(zip(dls, ref["dl"])):
         e = normwise(d.cpu().numpy(), r)
+        report("c256 step", f"dL/dI stack {k}", "FP32", d.cpu().numpy(), r)
         say(f"  dL/dI stack {k}: normwise {e:.2e}")
         assert e <= TOL
     gmax_s = np.max(np.abs(ref["grads"][2]))
@@ -193,4 +204,8 @@ def test_c256_training_step_every_voxel_and_gaussian(mods):
         e_p = check_range(f"{name} p", got_p.cpu().numpy(), rp, ref["p"][k], p_in)
         e_m = check_range(f"{name} m", got_m.cpu().numpy(), rm, ref["m"][k], None)
         e_v = check_range(f"{name} v", got_v.cpu().numpy(), rv, ref["v"][k], None)
+        # after Adam's first step m = (1 - beta1) g: the raw gradient of every Gaussian
+        report("c256 step", f"dL/d{name} (Adam m / 0.1), every Gaussian", "FP32 (FP64 chain)",
+               got_m.cpu().numpy() / 0.1, np.asarray(ref["grads"][k]))
+        report("c256 step", f"{name} after Adam", "FP32", got_p.cpu().numpy(), ref["p"][k])
         say(f"  {name}: p {e_p:.2e} m {e_m:.2e} v {e_v:.2e} (normwise to the oracle)")

@@ -9,7 +9,9 @@
  * Conventions shared by every entry point
  *   - Pointers are DEVICE pointers unless marked [host].  The caller allocates and frees
  *     every buffer; the library allocates no device memory and keeps no pointer after a
- *     call returns.  Buffers must be 16-byte aligned (PyTorch allocations are).
+ *     call returns (the one exception, a static per-device array loaded with the library,
+ *     serves gm_render_loss_smooth_l1_noalloc).  Buffers must be 16-byte aligned (PyTorch
+ *     allocations are).
  *   - Every call enqueues its kernels on `stream` (a hipStream_t; NULL = default stream)
  *     and returns without synchronising, except gm_bin (one synchronisation, see there).
  *   - Every call returns a gm_status.  Arguments are validated on the host before anything
@@ -23,7 +25,9 @@
  *       logit[n]         intensity alpha = 1 / (1 + exp(-logit)), so alpha is in [0, 1]
  *   - Voxel arrays are float32 [nz][ny][nx] (x fastest).  Voxel v of a grid sits at the
  *     integer index v of that grid's index frame.
- *   - Reentrant.  The only global state is the thread-local error string.
+ *   - Reentrant.  The only global state is the thread-local error string, and the static
+ *     scratch array of gm_render_loss_smooth_l1_noalloc (see there: its calls race when
+ *     they overlap on one GPU).
  */
 #ifndef GM_H
 #define GM_H
@@ -40,6 +44,7 @@ extern "C" {
 #define GM_RECORD_FLOATS 16       /* floats per (grid, Gaussian) record                */
 #define GM_GRID_GRAD_FLOATS 10    /* floats per (grid, Gaussian) backward partial      */
 #define GM_REDUCE_WORKSPACE_BYTES 16384 /* workspace for the reductions below           */
+#define GM_NOALLOC_MAX_TILES 131072     /* tiles gm_render_loss_smooth_l1_noalloc takes    */
 
 typedef void* gm_stream; /* hipStream_t */
 
@@ -185,6 +190,23 @@ gm_status gm_render_loss_smooth_l1(const gm_bins* bins, const int32_t* grid_ids,
                                    const float* const* targets, float* const* outs,
                                    float* const* dl_di, float* loss, void* workspace,
                                    size_t workspace_bytes, gm_stream stream);
+
+/* gm_render_loss_smooth_l1 for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the per-tile FP64
+ * partials go to a static array of the library, GM_NOALLOC_MAX_TILES doubles (1 MiB) on each
+ * GPU the library runs on, held until the process ends, instead of a workspace argument.  Same
+ * kernels, so the same results bit for bit.  The listed grids may hold at most
+ * GM_NOALLOC_MAX_TILES tiles of the size gm_tile_dims reports (the three 256x256x64 stacks of a
+ * 256^3 reconstruction hold 12288, five 320x320x80 stacks 40000); more is GM_ERR_CAPACITY and
+ * nothing is enqueued.  The call allocates nothing; its first call on a device looks the
+ * array's device address up (hipGetSymbolAddress) with that device current.  Every call on one
+ * GPU shares that GPU's array: calls that may overlap on one GPU (two streams, two host
+ * threads) race and must be ordered by the caller.  The array needs no clearing: every tile of
+ * a call writes its partial before the final sum reads it. */
+gm_status gm_render_loss_smooth_l1_noalloc(const gm_bins* bins, const int32_t* grid_ids,
+                                           int32_t n_ids, const float* const* targets,
+                                           float* const* outs, float* const* dl_di, float* loss,
+                                           gm_stream stream);
 
 /* Neural residual field parameters for the fused volume epilogue (Eq. 8).  Weights are
  * bf16 stored as uint16 bit patterns, row-major [out][in]; biases float32.

@@ -12,6 +12,7 @@ ABI_VERSION = 4          # struct layouts of include/gm.h this binding mirrors
 GM_RECORD_FLOATS = 16
 GM_GRID_GRAD_FLOATS = 10
 GM_REDUCE_WORKSPACE_BYTES = 16384
+GM_NOALLOC_MAX_TILES = 131072
 
 STATUS = {0: "GM_OK", 1: "GM_ERR_INVALID_ARGUMENT", 2: "GM_ERR_CAPACITY",
           3: "GM_ERR_NONFINITE", 4: "GM_ERR_HIP", 5: "GM_ERR_UNSUPPORTED"}
@@ -101,6 +102,9 @@ _SIGS = [
     ("gm_render_loss_smooth_l1", ctypes.c_int,
      [ctypes.POINTER(GmBins), ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.POINTER(P),
       ctypes.POINTER(P), ctypes.POINTER(P), P, P, ctypes.c_size_t, P]),
+    ("gm_render_loss_smooth_l1_noalloc", ctypes.c_int,
+     [ctypes.POINTER(GmBins), ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.POINTER(P),
+      ctypes.POINTER(P), ctypes.POINTER(P), P, P]),
     ("gm_render_volume", ctypes.c_int, [ctypes.POINTER(GmBins), ctypes.c_int32,
                                          ctypes.POINTER(GmNrf), P, P]),
     ("gm_render_nrf_loss_smooth_l1", ctypes.c_int,

@@ -1,10 +1,12 @@
 // Host side of the C ABI declared in include/gm.h: argument validation, workspace layout,
-// launch configuration and status codes.  Nothing here allocates device memory.
+// launch configuration and status codes.  Nothing here allocates device memory; the one
+// library-held buffer is the static array behind gm_render_loss_smooth_l1_noalloc.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 
 #include "gm_internal.h"
@@ -628,6 +630,60 @@ gm_status gm_render_loss_smooth_l1(const gm_bins* bins, const int32_t* grid_ids,
 {
     g_err.clear();
     const RenderLoss lo{targets, dl_di, loss, workspace, workspace_bytes};
+    return render_impl(bins, grid_ids, n_ids, outs, &lo, reinterpret_cast<hipStream_t>(stream));
+}
+
+// Per-tile FP64 loss partials of gm_render_loss_smooth_l1_noalloc.  Each GPU the library runs
+// on holds its own copy until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device (the array's name is not a device address
+// in host code).
+static __device__ __align__(256) double scratch[GM_NOALLOC_MAX_TILES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+}  // namespace
+
+// The scratch array's address on the current device, looked up once per device.
+static gm_status scratch_for_current_device(void** ptr)
+{
+    int dev = -1;
+    GM_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(GM_ERR_UNSUPPORTED, "device ordinal %d beyond %d", dev, kMaxDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        GM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(GM_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return GM_OK;
+}
+
+gm_status gm_render_loss_smooth_l1_noalloc(const gm_bins* bins, const int32_t* grid_ids,
+                                           int32_t n_ids, const float* const* targets,
+                                           float* const* outs, float* const* dl_di, float* loss,
+                                           gm_stream stream)
+{
+    g_err.clear();
+    // the tile count is checked here, before the lookup, so that an oversized call fails with
+    // a clear message; render_impl checks the buffer size again against the same figure
+    gm_status st = check_bins(bins, true);
+    if (st != GM_OK) return st;
+    st = check_ids(bins, grid_ids, n_ids);
+    if (st != GM_OK) return st;
+    int64_t tiles = 0;
+    for (int k = 0; k < n_ids; ++k) tiles += grid_tiles(bins->grids[grid_ids[k]]);
+    if (tiles > GM_NOALLOC_MAX_TILES)
+        return fail(GM_ERR_CAPACITY, "%lld tiles exceed the %d the static scratch holds",
+                    (long long)tiles, GM_NOALLOC_MAX_TILES);
+    void* ws = nullptr;
+    st = scratch_for_current_device(&ws);
+    if (st != GM_OK) return st;
+    const RenderLoss lo{targets, dl_di, loss, ws, (size_t)GM_NOALLOC_MAX_TILES * sizeof(double)};
     return render_impl(bins, grid_ids, n_ids, outs, &lo, reinterpret_cast<hipStream_t>(stream));
 }
 

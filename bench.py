@@ -380,9 +380,10 @@ def main():
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{args.workload}: 256^3 phantom, 3 orthogonal stacks "
-                   f"256x256x64 (slice FWHM 4 voxels, rigid offsets), {p.n} anisotropic "
-                   "Gaussians, plain method (smooth-L1 + anisotropy, Adam)",
+        "config": {"workload": f"{args.workload}: {w.n_vox}^3 phantom, {len(stacks)} stacks "
+                   f"{'/'.join(f'{g.nx}x{g.ny}x{g.nz}' for g in stacks)} (thick slices, "
+                   f"rigid offsets or oblique), {p.n} anisotropic Gaussians, plain method "
+                   "(smooth-L1 + anisotropy, Adam)",
                    "n_gauss": p.n, "stacks": [list(g.shape) for g in stacks],
                    "tile": list(api._lib.tile_dims())},
         "ms_per_step_p10_p50_p90": [float(np.percentile(step_ms, q)) for q in (10, 50, 90)],

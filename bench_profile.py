@@ -45,8 +45,12 @@ def kernel_digest(kernel):
 
 
 def _short(name: str) -> str:
-    n = name.split("(")[0] if not name.startswith("(anonymous") else name.split("::")[1].split("(")[0]
-    return n.replace("void ", "").strip()
+    """Kernel name without return type, namespace and argument list (template arguments
+    kept)."""
+    n = name[5:] if name.startswith("void ") else name
+    if n.startswith("(anonymous namespace)::"):
+        n = n[len("(anonymous namespace)::"):]
+    return n.split("(")[0].strip()
 
 
 def _rows(d, pattern):

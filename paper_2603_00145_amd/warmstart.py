@@ -167,13 +167,36 @@ def make_case(n_vox, n_slices, seed, device, bias=True, n_ell=None):
     return stacks, data, ph, inputs.volume_grid(n_vox)
 
 
+def constant_offsets(s0: torch.Tensor, l0: torch.Tensor, sig_t: torch.Tensor,
+                     logit_t: torch.Tensor):
+    """The control arm's fix: one log-scale offset d (added to all three log-scales) and one
+    logit offset e, fitted on the training set in the network's own loss.  The devoxelization
+    Gaussians are isotropic, Sigma0 = u0 I, so with u = u0 e^{2 d} the covariance term
+    sum_i |u I - Sigma*_i|_F^2 / |Sigma*_i|_F^2 is a quadratic in u, least at
+    u = sum_i tr(Sigma*_i) / |Sigma*_i|^2 / (3 sum_i 1 / |Sigma*_i|^2); the logit term is least at
+    e = mean(logit* - logit0).  Returns (d, e) relative to each Gaussian's own initial values,
+    so they transfer to a finer lattice as a ratio of scales."""
+    S = sig_t.double().cpu().numpy()
+    tr = S[:, 0] + S[:, 1] + S[:, 2]
+    nrm = (S[:, :3] ** 2).sum(1) + 2.0 * (S[:, 3:] ** 2).sum(1)
+    u = float(np.sum(tr / nrm) / (3.0 * np.sum(1.0 / nrm)))
+    s0h = s0.double().cpu().numpy()
+    u0 = np.exp(2.0 * s0h[:, 0])          # isotropic: the three log-scales are equal
+    if not np.allclose(s0h, s0h[:, :1]) or not np.allclose(u0, u0[0]):
+        raise ValueError("the constant-offset arm expects one isotropic initial scale")
+    d = 0.5 * np.log(u / u0[0])
+    e = float(np.mean(logit_t.double().cpu().numpy() - l0.double().cpu().numpy()))
+    return float(d), e
+
+
 def run_experiment(n_train=64, n_test=16, train_vox=128, test_vox=256, g_train=50, g_test=100,
                    train_iters=200, test_iters=1000, net_steps=1500, batch=1024, lr=1e-3,
                    psnr_every=10, device="cuda", out: Optional[str] = None):
     """Train the warm-start network on reconstructions of n_train phantoms (plain method from
-    the devoxelization initialisation), then reconstruct n_test held-out phantoms from the
-    plain and the warm-started initialisation and compare iterations to the plain arm's final
-    PSNR."""
+    the devoxelization initialisation), then reconstruct n_test held-out phantoms from three
+    initialisations - plain devoxelization, devoxelization with the best constant log-scale and
+    logit offsets on the same training set (the control arm: what a one-number fix gains), and
+    the network's - and compare iterations to the plain arm's final PSNR."""
     t0 = time.time()
     dev = torch.device(device)
     # 1. training reconstructions
@@ -211,14 +234,19 @@ def run_experiment(n_train=64, n_test=16, train_vox=128, test_vox=256, g_train=5
             losses.append((it, float(loss)))
             _say(f"# net step {it}: loss {float(loss):.4f} ({time.time() - t0:.0f}s)")
     del P
+    d_off, e_off = constant_offsets(S0, L0, SIG, LT)
+    _say(f"# constant offsets: log-scale {d_off:+.4f}, logit {e_off:+.4f}")
     # 3. held-out comparison
     h_t = 2.0 / g_test
     results = []
     for i in range(n_test):
         stacks, data, ph, vol = make_case(test_vox, test_vox // 4, 4100 + i, dev)
         arms = {}
-        for arm in ("plain", "warm"):
+        for arm in ("plain", "offset", "warm"):
             p0 = api.devox_init(g_test, stacks, data)
+            if arm == "offset":
+                p0 = api.GaussParams(p0.mean, p0.quat, (p0.log_scale + d_off).contiguous(),
+                                     (p0.logit + e_off).contiguous())
             if arm == "warm":
                 n = p0.n
                 npad = (n + 15) // 16 * 16
@@ -235,22 +263,29 @@ def run_experiment(n_train=64, n_test=16, train_vox=128, test_vox=256, g_train=5
         target = arms["plain"][-1]["psnr"]
         results.append({
             "case": 4100 + i, "plain_final_psnr": target,
+            "offset_final_psnr": arms["offset"][-1]["psnr"],
             "warm_final_psnr": arms["warm"][-1]["psnr"],
-            "plain_init_psnr": arms["plain"][0]["psnr"], "warm_init_psnr": arms["warm"][0]["psnr"],
+            "plain_init_psnr": arms["plain"][0]["psnr"],
+            "offset_init_psnr": arms["offset"][0]["psnr"],
+            "warm_init_psnr": arms["warm"][0]["psnr"],
             "plain_iters_to_target": recon.iters_to_psnr(arms["plain"], target),
+            "offset_iters_to_target": recon.iters_to_psnr(arms["offset"], target),
             "warm_iters_to_target": recon.iters_to_psnr(arms["warm"], target),
         })
-    reached = [r["warm_iters_to_target"] for r in results if r["warm_iters_to_target"] is not None]
     summary = {
         "config": dict(n_train=n_train, n_test=n_test, train_vox=train_vox, test_vox=test_vox,
                        g_train=g_train, g_test=g_test, train_iters=train_iters,
                        test_iters=test_iters, net_steps=net_steps, batch=batch, lr=lr),
         "net_loss": losses, "cases": results,
-        "warm_reached": f"{len(reached)}/{len(results)}",
-        "warm_iters_mean": float(np.mean(reached)) if reached else None,
-        "warm_iters_median": float(np.median(reached)) if reached else None,
+        "constant_offsets": {"log_scale": d_off, "logit": e_off},
         "plain_iters": test_iters, "seconds": time.time() - t0,
     }
+    for arm in ("offset", "warm"):
+        reached = [r[f"{arm}_iters_to_target"] for r in results
+                   if r[f"{arm}_iters_to_target"] is not None]
+        summary[f"{arm}_reached"] = f"{len(reached)}/{len(results)}"
+        summary[f"{arm}_iters_mean"] = float(np.mean(reached)) if reached else None
+        summary[f"{arm}_iters_median"] = float(np.median(reached)) if reached else None
     if out:
         with open(out, "w") as f:
             json.dump(summary, f, indent=1)
@@ -270,7 +305,21 @@ if __name__ == "__main__":
     ap.add_argument("--test-iters", type=int, default=1000)
     ap.add_argument("--net-steps", type=int, default=1500)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--md", default=None, help="also write the per-phantom table here")
     a = ap.parse_args()
     s = run_experiment(a.n_train, a.n_test, a.train_vox, a.test_vox, a.g_train, a.g_test,
                        a.train_iters, a.test_iters, a.net_steps, out=a.out)
     print(json.dumps({k: v for k, v in s.items() if k != "cases"}))
+    if a.md:
+        def it(v):
+            return "not reached" if v is None else str(v)
+        rows = ["| phantom seed | plain init dB | plain final dB | offset init dB | offset final dB "
+                "| offset iterations to target | warm init dB | warm final dB | warm iterations to "
+                "target |", "|---|---|---|---|---|---|---|---|---|"]
+        for c in s["cases"]:
+            rows.append(f"| {c['case']} | {c['plain_init_psnr']:.2f} | {c['plain_final_psnr']:.2f} "
+                        f"| {c['offset_init_psnr']:.2f} | {c['offset_final_psnr']:.2f} | "
+                        f"{it(c['offset_iters_to_target'])} | {c['warm_init_psnr']:.2f} | "
+                        f"{c['warm_final_psnr']:.2f} | {it(c['warm_iters_to_target'])} |")
+        with open(a.md, "w") as f:
+            f.write("\n".join(rows) + "\n")

@@ -78,7 +78,7 @@ static_assert(RZS % 32 == 8, "z-plane stride must be 8 mod 32 banks");
 // so all NK reads are issued at immediate offsets before the first use; rows past the column
 // (k >= ncol) are masked where they are used.  NK is the wavefront's longest column (up to 8),
 // a compile-time constant, so the steps carry no branches.
-template <int NK>
+template <int NK, bool MASK>
 __device__ __forceinline__ void lds_column(const float* __restrict__ region, uint32_t off,
                                            int ncol, float A, float B, float kyy, float& s0,
                                            float& s1, float& s2)
@@ -88,13 +88,14 @@ __device__ __forceinline__ void lds_column(const float* __restrict__ region, uin
     for (int k = 0; k < NK; ++k) gv[k] = region[off + k * RX];
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
-        const float Q = k == 0 ? A : A + (float)k * (B + (float)k * kyy);
-        const float gk = k == 0 ? gv[0] : (k < ncol ? gv[k] : 0.0f);
+        const float Q = k == 0 ? A : fmaf((float)k, fmaf((float)k, kyy, B), A);
+        // without MASK every active column of the wavefront is at least NK long
+        const float gk = (k == 0 || !MASK) ? gv[k] : (k < ncol ? gv[k] : 0.0f);
         const float ge = gk * __builtin_amdgcn_exp2f(Q);
         s0 += ge;
         if (k > 0) {
-            s1 += (float)k * ge;
-            s2 += (float)(k * k) * ge;
+            s1 = fmaf((float)k, ge, s1);
+            s2 = fmaf((float)(k * k), ge, s2);
         }
     }
 }
@@ -143,50 +144,72 @@ __device__ __forceinline__ void group_of_gaussians(const BackwardArgs& a, int kk
     const int chunks = (fp + G - 1) / G;
     const int max_chunks = group_max<G>(chunks);
     const int max_wy = group_max<G>(wy);
-    // y steps all groups take (no per-lane care needed); beyond, the tail
-    const int min_wy = group_min<G>(wy);
-    // column f -> (x, z) = (f mod wx, f div wx) as floor((f + 1/2) / wx): the fraction stays
-    // at least 1/(2 wx) away from an integer, far beyond the hardware reciprocal's error for
-    // any f < 2^20
-    const float inv_wx = __builtin_amdgcn_rcpf((float)wx);
+    // y steps every active column of the wavefront takes (no mask needed below it)
+    const int min_wy = group_min<G>(nonempty ? wy : 64);
+    // column f -> (x, z) = (f mod wx, f div wx), with fh = f + 1/2: z = floor(fh / wx) (the
+    // fraction stays at least 1/(2 wx) away from an integer, far beyond the hardware
+    // reciprocal's error for any f < 2^20) and x + 1/2 = fh - z wx, exact in float
+    const float wxf = (float)wx;
+    const float inv_wx = __builtin_amdgcn_rcpf(wxf);
     const float dy0 = -cy;                        // dy = dy0 + k at step k of a column
     const float B0 = 2.0f * kyy * dy0;
+    // Q along a column at (dx, dz): A = qxz + dy0 (kxy dx + kyz dz + kyy dy0) regrouped as
+    // dx (kxx dx + kxz dz + dy0 kxy) + dz (kzz dz + dy0 kyz) + kyy dy0^2
+    const float g1 = dy0 * kxy, g2 = dy0 * kyz, A0 = kyy * dy0 * dy0;
+    const float cxh = cx + 0.5f;
+    // staged-region index of the box's voxel (x, 0, z) minus 1/2, as a float: zf RZS + (x + 1/2)
+    // + obase, exact (the region holds fewer than 2^13 floats); in the grid, integer arithmetic
     const int ystride = FROM_LDS ? RX : nx;       // between consecutive y steps
+    const float obase = (float)((loz - t0z) * RZS + (loy - t0y) * RX + (lox - t0x)) - 0.5f;
+    const float qlh = (float)ql + 0.5f;
     // weighted moments: m0 = sum gE, m1 = sum gE delta, m2 = sum gE delta delta^T
     float m0 = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f;
     float mxx = 0.0f, myy = 0.0f, mzz = 0.0f, mxy = 0.0f, mxz = 0.0f, myz = 0.0f;
 #pragma unroll 1
     for (int c = 0; c < max_chunks; ++c) {
-        const int f = c * G + ql;
-        const bool act = f < fp;
-        const int z = (int)(((float)f + 0.5f) * inv_wx);
-        const int x = f - z * wx;
-        const float dx = (float)x - cx, dz = (float)z - cz;
+        const float fh = fmaf((float)c, (float)G, qlh);
+        const bool act = fh < (float)fp;
+        const float zf = floorf(fh * inv_wx);
+        const float xh = fmaf(-zf, wxf, fh);
+        const float dx = xh - cxh, dz = zf - cz;
         // Q along the column: Q_k = A + k (B + k kyy).  A lane outside the footprint reads
         // the first voxel of the region (or grid) at every step and gets A = -inf, so its
         // every term is exactly zero.
-        const float b = kxy * dx + kyz * dz;
-        const float qxz = dx * (kxx * dx + kxz * dz) + dz * (kzz * dz);
-        const float A = act ? qxz + dy0 * (b + kyy * dy0) : -__builtin_inff();
-        const float B = b + B0;
+        const float Aq = fmaf(dx, fmaf(kxx, dx, fmaf(kxz, dz, g1)), fmaf(dz, fmaf(kzz, dz, g2), A0));
+        const float A = act ? Aq : -__builtin_inff();
+        const float B = fmaf(kxy, dx, fmaf(kyz, dz, B0));
         uint32_t off = 0u;
         if (act) {
-            off = FROM_LDS ? (uint32_t)((loz + z - t0z) * RZS + (loy - t0y) * RX + (lox + x - t0x))
-                           : (uint32_t)(((loz + z) * ny + loy) * nx + (lox + x));
+            off = FROM_LDS ? (uint32_t)fmaf(zf, (float)RZS, xh + obase)
+                           : (uint32_t)(((loz + (int)zf) * ny + loy) * nx + (lox + (int)xh));
         }
         const int ncol = act ? wy : 1;             // steps whose voxel lies in the box
         // s0 = sum ge, s1 = sum k ge, s2 = sum k^2 ge over the column (ge = g 2^Q)
         float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
         if (FROM_LDS) {
-            switch (max_wy < 8 ? max_wy : 8) {
-            case 1: lds_column<1>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
-            case 2: lds_column<2>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
-            case 3: lds_column<3>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
-            case 4: lds_column<4>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
-            case 5: lds_column<5>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
-            case 6: lds_column<6>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
-            case 7: lds_column<7>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
-            default: lds_column<8>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+            const int nk = max_wy < 8 ? max_wy : 8;
+            if (min_wy >= nk) {
+                switch (nk) {
+                case 1: lds_column<1, false>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+                case 2: lds_column<2, false>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+                case 3: lds_column<3, false>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+                case 4: lds_column<4, false>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+                case 5: lds_column<5, false>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+                case 6: lds_column<6, false>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+                case 7: lds_column<7, false>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+                default: lds_column<8, false>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+                }
+            } else {
+                switch (nk) {
+                case 1: lds_column<1, true>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+                case 2: lds_column<2, true>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+                case 3: lds_column<3, true>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+                case 4: lds_column<4, true>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+                case 5: lds_column<5, true>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+                case 6: lds_column<6, true>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+                case 7: lds_column<7, true>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+                default: lds_column<8, true>(region, off, ncol, A, B, kyy, s0, s1, s2); break;
+                }
             }
         } else {
             float gv[8];

@@ -17,20 +17,16 @@ namespace {
 
 __device__ __forceinline__ int sgpr(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Division by a per-Gaussian d in [1, 1024] of q in [0, 1024): floor(q / d) equals
-// (q * M) >> 20 with M = ceil(2^20 / d), because q * d < 2^20.
-__device__ __forceinline__ uint32_t magic20(uint32_t d) { return ((1u << 20) + d - 1u) / d; }
-__device__ __forceinline__ uint32_t div20(uint32_t q, uint32_t M) { return __umul24(q, M) >> 20; }
-
-// Per (Gaussian, tile) piece, prepared lane-parallel for a batch of list entries: in-plane
-// centre relative to the intersection origin, the base-2 conic (off-diagonals doubled) and
-// the z-walk constants of the column formula below, footprint width and area, z extent, the
-// magic divisor for the column unravel and the LDS index of the intersection origin.
+// Per (Gaussian, tile) piece, prepared lane-parallel for a batch of list entries, in the
+// frame of the piece's intersection origin (the box clipped to the tile): the centre's x offset
+// plus 1/2 and its y offset, the base-2 conic (off-diagonals doubled), the z-walk constants of
+// the column formula below (F0, E, g1 = d0 kxz, g2 = d0 kyz), the footprint width (as a float
+// and its reciprocal) and area, and the LDS index of the origin minus 1/2.
 struct Piece {
-    float ux, uy, d0, F0;
+    float uxh, uy, F0, E;
     float kxx, kyy, kzz, kxy;
-    float kxz, kyz, E;
-    int wx, F, wz, mx, base;
+    float kxz, kyz, g1, g2;
+    float inv_wx, wxf, Ff, basef;
 };
 
 // Keeps the compiler from moving or merging LDS accesses across this point.  The two groups of
@@ -38,29 +34,32 @@ struct Piece {
 // read-add-writes must stay two separate, ordered sequences.
 __device__ __forceinline__ void lds_order() { __asm__ __volatile__("" ::: "memory"); }
 
-// Column f of piece p: its voxel values w[k] = amp 2^Q_k for the z-steps k < KM, and the LDS
-// index of its voxel at k = 0.  With dz = k + d0 (d0 = minus the centre's z offset) and
-// bz = kxz dx + kyz dy, Q_k = qxy + dz (bz + kzz dz) is expanded in k as
-// A + k (B + k kzz), A = qxy + d0 bz + kzz d0^2 + log2 amp, B = bz + 2 kzz d0: the per-piece
-// parts of A and B (F0 and E) are formed once, and amp enters as log2 amp in the exponent.
+// Column f of piece p, passed as fh = f + 1/2: its voxel values w[k] = amp 2^Q_k for the
+// z-steps k < KM, and the LDS index of its voxel at k = 0.  The column is (x, y) = (f mod wx,
+// f div wx), found as y = floor(fh / wx) (the fraction (x + 1/2) / wx stays at least 1/(2 wx)
+// from an integer, far beyond the reciprocal's error) and x + 1/2 = fh - y wx, all exact in
+// float.  With dz = k + d0 (d0 = minus the centre's z offset), Q_k = qxy + dz (bz + kzz dz),
+// qxy = dx (kxx dx + kxy dy) + kyy dy^2 and bz = kxz dx + kyz dy, is expanded in k as
+// A + k (B + k kzz) with A = dx (kxx dx + kxy dy + d0 kxz) + dy (kyy dy + d0 kyz) + F0 and
+// B = bz + E: the per-piece parts (F0 = log2 amp + kzz d0^2, E = 2 kzz d0, d0 kxz, d0 kyz) are
+// formed once, and amp enters as log2 amp in the exponent.
 template <int KM>
-__device__ __forceinline__ void eval_column(const Piece& p, uint32_t f, float (&w)[KM], int& idx)
+__device__ __forceinline__ void eval_column(const Piece& p, float fh, float (&w)[KM], int& idx)
 {
-    const uint32_t y = div20(f, (uint32_t)p.mx);
-    const uint32_t x = f - __umul24(y, (uint32_t)p.wx);
-    const float dx = (float)x - p.ux;
-    const float dy = (float)y - p.uy;
-    const float qxy = dx * (p.kxx * dx + p.kxy * dy) + (dy * (p.kyy * dy) + p.F0);
-    const float bz = p.kxz * dx + p.kyz * dy;
-    const float A = p.d0 * bz + qxy;
-    static_assert(GM_TX == 16 && GM_TY == 16, "index shifts assume 16x16 tiles");
-    idx = p.base + (int)((y << 4) + x);
+    const float yf = floorf(fh * p.inv_wx);
+    const float xh = fmaf(-yf, p.wxf, fh);
+    const float dx = xh - p.uxh;
+    const float dy = yf - p.uy;
+    const float A = fmaf(dx, fmaf(p.kxx, dx, fmaf(p.kxy, dy, p.g1)),
+                         fmaf(dy, fmaf(p.kyy, dy, p.g2), p.F0));
+    static_assert(GM_TX == 16 && GM_TY == 16, "index arithmetic assumes 16x16 tiles");
+    idx = (int)fmaf(yf, (float)GM_TX, xh + p.basef);     // an exact small integer
     w[0] = __builtin_amdgcn_exp2f(A);
     if (KM > 1) {
-        const float B = bz + p.E;
+        const float B = fmaf(p.kxz, dx, fmaf(p.kyz, dy, p.E));
 #pragma unroll
         for (int k = 1; k < KM; ++k)
-            w[k] = __builtin_amdgcn_exp2f(A + (float)k * (B + (float)k * p.kzz));
+            w[k] = __builtin_amdgcn_exp2f(fmaf((float)k, fmaf((float)k, p.kzz, B), A));
     }
 }
 
@@ -89,31 +88,32 @@ __device__ __forceinline__ void add_column_kz(float* acc, int idx, const float (
     }
 }
 
-// One piece on the whole wave: columns f0 + lane, KM z-steps each.
+// One piece on the whole wave: columns f0 + lane, KM z-steps each (lane_fh = lane + 1/2).
 template <int KM>
-__device__ __forceinline__ void single_piece(const Piece& p, float* acc, int F, int lane)
+__device__ __forceinline__ void single_piece(const Piece& p, float* acc, int F, float lane_fh)
 {
+    float fh = lane_fh;
 #pragma unroll 1
     for (int f0 = 0; f0 < F; f0 += 64) {
-        const uint32_t f = (uint32_t)(f0 + lane);
         float w[KM];
         int idx;
-        eval_column<KM>(p, f, w, idx);
-        if (f < (uint32_t)F) add_column<KM, KM>(acc, idx, w);
+        eval_column<KM>(p, fh, w, idx);
+        if (fh < p.Ff) add_column<KM, KM>(acc, idx, w);
+        fh += 64.0f;
     }
 }
 
-// Two pieces side by side in the wave (lane's piece p, column f); KM = the larger z extent.
-// The first piece's read-add-writes complete before the second piece's are issued.
+// Two pieces side by side in the wave (lane's piece p, column fh - 1/2); KM = the larger z
+// extent.  The first piece's read-add-writes complete before the second piece's are issued.
 template <int KM>
 __device__ __forceinline__ void paired_pieces(const Piece& p, float* acc, bool act, bool first,
-                                              uint32_t f, int wza, int wzb)
+                                              float fh, int wza, int wzb)
 {
     // every lane evaluates (a lane past its piece's footprint computes values it never
     // stores), so no lane mask is needed around the evaluation
     float w[KM];
     int idx;
-    eval_column<KM>(p, f, w, idx);
+    eval_column<KM>(p, fh, w, idx);
     lds_order();
     if (act && first) add_column_kz<KM>(acc, idx, w, wza);
     lds_order();
@@ -192,6 +192,7 @@ __device__ __forceinline__ void accumulate_tile(const RenderArgs& a, const TileP
     const int t0x = P.t0x, t0y = P.t0y, t0z = P.t0z;
     const float* __restrict__ recbase = a.records + (size_t)G.grid_index * a.n_gauss * 16;
     const int* __restrict__ pg = a.pair_gauss;
+    const float lane_fh = (float)lane + 0.5f;
 
 #pragma unroll
     for (int j = 0; j < GM_TILE_VOX / 64; ++j) acc[j * 64 + lane] = 0.0f;
@@ -217,23 +218,25 @@ __device__ __forceinline__ void accumulate_tile(const RenderArgs& a, const TileP
             const int wy = min(hiy, t0y + GM_TY - 1) - iy0 + 1;
             const int wz = min(hiz, t0z + GM_TZ - 1) - iz0 + 1;
             const bool ok = wx > 0 && wy > 0 && wz > 0;  // always true for a listed tile
+            const float d0 = (float)(iz0 - loz) - r0.z;
+            const int wxe = ok ? wx : 1;
             Piece p;
-            p.ux = r0.x - (float)(ix0 - lox);
+            p.uxh = (r0.x - (float)(ix0 - lox)) + 0.5f;
             p.uy = r0.y - (float)(iy0 - loy);
-            p.d0 = (float)(iz0 - loz) - r0.z;
             p.kxx = r1.x; p.kyy = r1.y; p.kzz = r1.z; p.kxy = r1.w;
             p.kxz = r2.x; p.kyz = r2.y;
             // amp >= 0 (0 for an empty box, never listed): log2 0 = -inf gives zeros
-            p.F0 = log2f(r0.w) + p.kzz * p.d0 * p.d0;
-            p.E = 2.0f * p.kzz * p.d0;
-            p.wx = ok ? wx : 1;
-            p.F = ok ? wx * wy : 0;
-            p.wz = ok ? wz : 0;
-            p.mx = (int)magic20((uint32_t)p.wx);
-            p.base = ((iz0 - t0z) * GM_TY + (iy0 - t0y)) * GM_TX + (ix0 - t0x);
+            p.F0 = log2f(r0.w) + p.kzz * d0 * d0;
+            p.E = 2.0f * p.kzz * d0;
+            p.g1 = d0 * p.kxz;
+            p.g2 = d0 * p.kyz;
+            p.wxf = (float)wxe;
+            p.inv_wx = __builtin_amdgcn_rcpf(p.wxf);
+            myF = ok ? wx * wy : 0;
+            myWz = ok ? wz : 0;
+            p.Ff = (float)myF;
+            p.basef = (float)(((iz0 - t0z) * GM_TY + (iy0 - t0y)) * GM_TX + (ix0 - t0x)) - 0.5f;
             pc[lane] = p;
-            myF = p.F;
-            myWz = p.wz;
         }
         // bit j: pieces j and j + 1 fit side by side in the wave (footprints summing to <= 64)
         const int nextF = __shfl_down(myF, 1, 64);
@@ -247,29 +250,28 @@ __device__ __forceinline__ void accumulate_tile(const RenderArgs& a, const TileP
                 const int Fa = __builtin_amdgcn_readlane(myF, j);
                 const int wza = __builtin_amdgcn_readlane(myWz, j);
                 const int wzb = __builtin_amdgcn_readlane(myWz, j + 1);
-                const int h = lane >= Fa ? 1 : 0;
-                const Piece p = pc[j + h];
-                const uint32_t f = (uint32_t)(h ? lane - Fa : lane);
-                const bool act = f < (uint32_t)p.F;
-                const bool first = h == 0;
+                const bool first = lane < Fa;
+                const Piece p = pc[first ? j : j + 1];
+                const float fh = first ? lane_fh : lane_fh - (float)Fa;
+                const bool act = fh < p.Ff;
                 static_assert(GM_TZ == 4, "z extents 1..4 are dispatched below");
                 switch (max(wza, wzb)) {
-                case 1: paired_pieces<1>(p, acc, act, first, f, wza, wzb); break;
-                case 2: paired_pieces<2>(p, acc, act, first, f, wza, wzb); break;
-                case 3: paired_pieces<3>(p, acc, act, first, f, wza, wzb); break;
-                default: paired_pieces<GM_TZ>(p, acc, act, first, f, wza, wzb); break;
+                case 1: paired_pieces<1>(p, acc, act, first, fh, wza, wzb); break;
+                case 2: paired_pieces<2>(p, acc, act, first, fh, wza, wzb); break;
+                case 3: paired_pieces<3>(p, acc, act, first, fh, wza, wzb); break;
+                default: paired_pieces<GM_TZ>(p, acc, act, first, fh, wza, wzb); break;
                 }
                 j += 2;
             } else {
                 const Piece p = pc[j];
-                const int F = sgpr(p.F);
-                const int wz = sgpr(p.wz);
+                const int F = __builtin_amdgcn_readlane(myF, j);
+                const int wz = __builtin_amdgcn_readlane(myWz, j);
                 switch (wz) {
                 case 0: break;
-                case 1: single_piece<1>(p, acc, F, lane); break;
-                case 2: single_piece<2>(p, acc, F, lane); break;
-                case 3: single_piece<3>(p, acc, F, lane); break;
-                default: single_piece<GM_TZ>(p, acc, F, lane); break;
+                case 1: single_piece<1>(p, acc, F, lane_fh); break;
+                case 2: single_piece<2>(p, acc, F, lane_fh); break;
+                case 3: single_piece<3>(p, acc, F, lane_fh); break;
+                default: single_piece<GM_TZ>(p, acc, F, lane_fh); break;
                 }
                 j += 1;
             }

@@ -195,6 +195,20 @@ def make_phantom(n: int, n_ellipsoids: int, rng: np.random.Generator, bias: bool
     return vol.contiguous()
 
 
+def slice_grids(stack: Grid) -> List[Grid]:
+    """The stack's slices as one-slice grids: slice k keeps the stack's in-plane indexing and
+    slice profile, and its index z is the stack's minus k (so the slice sits at z = 0).  With
+    the stack's placement they give the stack's values slice by slice; each can then carry its
+    own rigid transform T_k (Sec. 3.3.2: every slice is moved by its own T_k)."""
+    out = []
+    A = np.asarray(stack.world_to_index, np.float64)
+    for k in range(stack.nz):
+        Ak = A.copy()
+        Ak[2, 3] -= k
+        out.append(Grid(stack.nx, stack.ny, 1, Ak, stack.psf_sigma_z, f"{stack.name}[{k}]"))
+    return out
+
+
 def simulate_stack(vol, grid: Grid, rng: np.random.Generator, noise: float = 0.01,
                    samples_per_slice: int = 8):
     """Acquire a thick-slice stack of the cell-centred volume ``vol`` (torch [n,n,n]).

@@ -15,9 +15,10 @@ import dataclasses
 import math
 from typing import List, Optional, Sequence
 
+import numpy as np
 import torch
 
-from . import api, rigid
+from . import api, inputs, rigid
 
 
 @dataclasses.dataclass
@@ -36,9 +37,10 @@ class TrainConfig:
     lr_nrf: float = 1e-4
     nrf_sample: int = 1 << 18     # stack voxels per stack per iteration for the NRF gradient
     optimize_pose: bool = False   # joint optimisation of the stacks' rigid transforms
+    pose_mode: str = "stack"      # "stack": one T_k per stack; "slice": one per slice
     lr_pose_rot: float = 1e-3     # radians
     lr_pose_trans: float = 1e-3   # world units ([-1, 1]^3)
-    pose_frozen: tuple = (0,)     # stacks whose pose stays fixed (the gauge reference)
+    pose_frozen: tuple = (0,)     # stacks whose pose (every slice's, per slice) stays fixed
     block_radius: int = 0         # > 0: the paper's cell-neighbourhood query (Eqs. 4-6)
     cell_resolution: int = 0      # its grid_resolution (cells per axis of [-1, 1]^3)
     lattice: int = 0              # the Gaussians form a lattice^3 (devoxelization layout)
@@ -50,7 +52,8 @@ class Reconstruction:
 
     def __init__(self, stacks: Sequence, targets: Sequence[torch.Tensor], params: api.GaussParams,
                  cfg: TrainConfig = TrainConfig(), volume_grid=None,
-                 phantom: Optional[torch.Tensor] = None):
+                 phantom: Optional[torch.Tensor] = None,
+                 slice_poses: Optional[Sequence] = None):
         self.cfg = cfg
         self.stacks = list(stacks)
         self.targets = [t.contiguous() for t in targets]
@@ -72,10 +75,79 @@ class Reconstruction:
         if cfg.progressive and self.lattice ** 3 != params.n:
             raise ValueError("a progressive schedule needs the Gaussians of a lattice^3 grid")
         self.poses = None
-        if cfg.optimize_pose:
+        self.slices = None
+        if cfg.pose_mode not in ("stack", "slice"):
+            raise ValueError("pose_mode is 'stack' or 'slice'")
+        if cfg.optimize_pose and cfg.pose_mode == "slice":
+            self._init_slices(slice_poses)
+        elif cfg.optimize_pose:
             self.poses = [rigid.StackPose(s) for s in self.stacks]
             self.pose_opt = rigid.PoseAdam(self.poses, cfg.lr_pose_rot, cfg.lr_pose_trans,
                                            frozen=cfg.pose_frozen)
+
+    # slices per Bins (the library bins at most 8 grids at once)
+    SLICE_GROUP = 8
+
+    def _init_slices(self, slice_poses):
+        """Per-slice rigid transforms (Sec. 3.3.2): every slice of every stack is a one-slice
+        grid (inputs.slice_grids) with its own pose, a rotation R about the slice's centre and a
+        translation tau; slice_poses optionally gives the starting (R, tau) of each, stacks in
+        order, slices in order.  The slices are binned in groups of
+        SLICE_GROUP grids, each group rendering into its slices' rows of the stack tensors."""
+        c = self.cfg
+        if c.nrf is not None or c.lambda_ssim > 0 or c.progressive or c.block_radius:
+            raise ValueError("per-slice poses run the plain smooth-L1 method only")
+        self.slices = []          # (stack, slice) of every slice grid, in order
+        nominal = []
+        for k, st in enumerate(self.stacks):
+            for z, g in enumerate(inputs.slice_grids(st)):
+                self.slices.append((k, z))
+                nominal.append(g)
+        # each slice rotates about its own centre, where rotation and translation decouple
+        self.poses = [rigid.StackPose(g, centre=rigid.grid_centre(g)) for g in nominal]
+        if slice_poses is not None:
+            if len(slice_poses) != len(self.poses):
+                raise ValueError("one (R, tau) per slice")
+            for q, (R, tau) in zip(self.poses, slice_poses):
+                q.R = np.asarray(R, np.float64).copy()
+                q.tau = np.asarray(tau, np.float64).copy()
+        frozen = [i for i, (k, _) in enumerate(self.slices) if k in set(c.pose_frozen)]
+        self.pose_opt = rigid.PoseAdam(self.poses, c.lr_pose_rot, c.lr_pose_trans, frozen=frozen)
+        n = self.p.n
+        self.groups = []
+        for i0 in range(0, len(nominal), self.SLICE_GROUP):
+            idx = list(range(i0, min(i0 + self.SLICE_GROUP, len(nominal))))
+            self.groups.append((self._bins(n, [nominal[i] for i in idx], 10), idx))
+        self.bins = None
+        self.slice_out = [self.outs[k][z:z + 1] for k, z in self.slices]
+        self.slice_dl = [self.dls[k][z:z + 1] for k, z in self.slices]
+        self.grads = api.GaussParams.zeros_like(self.p)
+
+    def _step_slices(self):
+        """One iteration with per-slice poses: each group of slice grids is binned and
+        rendered, the smooth-L1 term is formed over the whole stacks, then each group's
+        backward partials give its slices' affine gradients and accumulate the chain rule (the
+        anisotropy term once), and Adam steps the Gaussians and the slice poses."""
+        c = self.cfg
+        grids = [q.grid() for q in self.poses]
+        for b, idx in self.groups:
+            b.set_grids([grids[i] for i in idx])
+            b.bin(self.p)
+            api.render(b, list(range(len(idx))), [self.slice_out[i] for i in idx])
+        loss, _ = api.smooth_l1(self.outs, self.targets, self.dls)
+        for t in self.grads.tensors():
+            t.zero_()
+        G = []
+        for gi, (b, idx) in enumerate(self.groups):
+            ids = list(range(len(idx)))
+            api.grid_partials(self.p, b, ids, [self.slice_dl[i] for i in idx])
+            G.append(api.pose_grads(self.p, b, ids))
+            api.chain(self.p, b, ids, self.grads, c.lambda_aniso if gi == 0 else 0.0, c.lambda_r)
+        self.pose_opt.step(list(torch.cat(G).cpu().numpy().reshape(-1, 3, 4)))
+        for prm, gr, mm, vv, lr in zip(self.p.tensors(), self.grads.tensors(), self.m.tensors(),
+                                       self.v.tensors(), self.lrs()):
+            api.adam_step(prm, gr, mm, vv, lr, self.it - self.adam_t0)
+        return loss
 
     def _bins(self, n, grids, per):
         c = self.cfg
@@ -103,6 +175,8 @@ class Reconstruction:
             if done == self.it:
                 self.refine(g_new)
         self.it += 1
+        if self.slices is not None:
+            return self._step_slices()
         if c.nrf is not None and not self.nrf_on and self.it > int(c.nrf_start * c.n_iter):
             self.nrf_on = True
         if self.poses is not None:

@@ -11,13 +11,17 @@ the increment (d_omega, d_tau) at zero is
     d_tau:   -R L0^T G_t
     d_omega: vee of the skew part of Q = -R L0^T (G_L - G_t tau^T), i.e.
              (Q32 - Q23, Q13 - Q31, Q21 - Q12)   (1-based indices)
-since dA = [-L0 R^T [d_omega]x | L0 R^T [d_omega]x tau - L0 R^T d_tau].  This module is 6
-numbers per stack of host arithmetic; every voxel-level step runs in the library.
+since dA = [-L0 R^T [d_omega]x | L0 R^T [d_omega]x tau - L0 R^T d_tau].  A pose may instead
+rotate about its own centre c (a slice's centre, where its rotation and translation decouple):
+T(x_s) = R (x_s - c) + c + tau is the origin form with tau' = tau + c - R c, and under the same
+increment tau' moves by d_tau - [d_omega]x R c, so d_omega's gradient gains - (R c) x g_tau'.
+This module is 6 numbers per stack (or slice) of host arithmetic; every voxel-level step runs
+in the library.
 """
 from __future__ import annotations
 
 import dataclasses
-from typing import List, Sequence
+from typing import List, Optional, Sequence
 
 import numpy as np
 
@@ -39,18 +43,35 @@ def rotvec_to_matrix(w) -> np.ndarray:
     return np.eye(3) + (np.sin(th) / th) * K + ((1.0 - np.cos(th)) / (th * th)) * K @ K
 
 
+def grid_centre(grid: inputs.Grid) -> np.ndarray:
+    """World coordinates of the centre of a grid's voxel lattice (index ((n - 1) / 2) per
+    axis)."""
+    M = grid.index_to_world()
+    v = np.array([(grid.nx - 1) / 2.0, (grid.ny - 1) / 2.0, (grid.nz - 1) / 2.0])
+    return M[:, :3] @ v + M[:, 3]
+
+
 @dataclasses.dataclass
 class StackPose:
-    """Pose of one stack: nominal grid (T = identity) and the current rigid motion."""
+    """Pose of one stack (or slice): nominal grid (T = identity) and the current rigid motion,
+    rotating about the world origin, or about `centre` (world coordinates) when it is given."""
     nominal: inputs.Grid
     R: np.ndarray = dataclasses.field(default_factory=lambda: np.eye(3))
     tau: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(3))
+    centre: Optional[np.ndarray] = None
+
+    def tau_origin(self) -> np.ndarray:
+        """The translation of the same motion written as a rotation about the origin."""
+        if self.centre is None:
+            return self.tau
+        c = np.asarray(self.centre, np.float64)
+        return self.tau + c - self.R @ c
 
     def affine(self) -> np.ndarray:
         A0 = np.asarray(self.nominal.world_to_index, np.float64)
         L0, t0 = A0[:, :3], A0[:, 3]
         L = L0 @ self.R.T
-        return np.concatenate([L, (t0 - L @ self.tau)[:, None]], axis=1)
+        return np.concatenate([L, (t0 - L @ self.tau_origin())[:, None]], axis=1)
 
     def grid(self) -> inputs.Grid:
         g = self.nominal
@@ -61,9 +82,11 @@ class StackPose:
         G = np.asarray(G, np.float64)
         G_L, G_t = G[:, :3], G[:, 3]
         L0 = np.asarray(self.nominal.world_to_index, np.float64)[:, :3]
-        Q = -self.R @ L0.T @ (G_L - np.outer(G_t, self.tau))
+        Q = -self.R @ L0.T @ (G_L - np.outer(G_t, self.tau_origin()))
         g_w = np.array([Q[2, 1] - Q[1, 2], Q[0, 2] - Q[2, 0], Q[1, 0] - Q[0, 1]])
         g_t = -self.R @ L0.T @ G_t
+        if self.centre is not None:
+            g_w = g_w - np.cross(self.R @ np.asarray(self.centre, np.float64), g_t)
         return np.concatenate([g_w, g_t])
 
     def apply(self, d) -> None:

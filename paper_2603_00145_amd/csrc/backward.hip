@@ -109,9 +109,33 @@ __device__ __forceinline__ void lds_column(const float* __restrict__ region, uin
 // Q_k = A + k (B + k kyy) (two FMAs), one exp2, one multiply and three adds for the column sums
 // of g E, k g E and k^2 g E (k a compile-time constant in the unrolled loop).  Past a shorter
 // box, a row's reads are clamped and zeroed.
+// A Gaussian's 64-byte render record on one grid, as the group loads it (zeros when invalid).
+struct Rec {
+    float4 r0, r1, r2, r3;
+};
+
+__device__ __forceinline__ Rec load_record(const BackwardArgs& a, int gi, uint32_t mine, bool valid)
+{
+    Rec r;
+    r.r0 = make_float4(0, 0, 0, 0);
+    r.r1 = r.r0;
+    r.r2 = r.r0;
+    r.r3 = r.r0;
+    if (valid) {
+        const int64_t gid = min((int64_t)(mine & GM_ID_MASK), a.n - 1);
+        const float4* rp = reinterpret_cast<const float4*>(a.records + ((size_t)gi * a.n + gid) * 16);
+        r.r0 = rp[0];
+        r.r1 = rp[1];
+        r.r2 = rp[2];
+        r.r3 = rp[3];
+    }
+    return r;
+}
+
 template <int G, bool FROM_LDS>
 __device__ __forceinline__ void group_of_gaussians(const BackwardArgs& a, int kk, uint32_t mine,
-                                                   bool gvalid, const float* __restrict__ region,
+                                                   bool gvalid, const Rec& rec,
+                                                   const float* __restrict__ region,
                                                    int t0x, int t0y, int t0z)
 {
     const int ql = threadIdx.x & (G - 1);
@@ -119,14 +143,7 @@ __device__ __forceinline__ void group_of_gaussians(const BackwardArgs& a, int kk
     const int nx = a.nx[kk], ny = a.ny[kk];
     const float* __restrict__ g = a.dl_di[kk];
     const int64_t gid = min((int64_t)(mine & GM_ID_MASK), a.n - 1);
-    float4 r0 = make_float4(0, 0, 0, 0), r1 = r0, r2 = r0, r3 = r0;
-    if (gvalid) {
-        const float4* rp = reinterpret_cast<const float4*>(a.records + ((size_t)gi * a.n + gid) * 16);
-        r0 = rp[0];
-        r1 = rp[1];
-        r2 = rp[2];
-        r3 = rp[3];
-    }
+    const float4 r0 = rec.r0, r1 = rec.r1, r2 = rec.r2, r3 = rec.r3;
     const int lox = __float_as_int(r2.z), loy = __float_as_int(r2.w), loz = __float_as_int(r3.x);
     const int hix = __float_as_int(r3.y), hiy = __float_as_int(r3.z), hiz = __float_as_int(r3.w);
     const bool nonempty = gvalid && lox <= hix && loy <= hiy && loz <= hiz;
@@ -392,19 +409,32 @@ __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
         for (int h = 0; h < EPL; ++h)
             if (cl[h] < NSLOT) order[wv][pos[h]] = v[h];
         constexpr int PER_ROUND = 64 / BWD_G;
+        // the next round's records are in flight while a round is processed
+        uint32_t mine_n = 0u;
+        bool valid_n = false;
+        Rec rec_n;
+        auto fetch = [&](int r0, int lim) {
+            const int ix = r0 + grp;
+            valid_n = ix < lim;
+            mine_n = valid_n ? order[wv][ix] : 0u;
+            rec_n = load_record(a, gi, mine_n, valid_n);
+        };
+        if (n_lds > 0) fetch(0, n_lds);
 #pragma unroll 1
         for (int r0 = 0; r0 < n_lds; r0 += PER_ROUND) {
-            const int ix = r0 + grp;
-            const bool valid = ix < n_lds;
-            const uint32_t mine = valid ? order[wv][ix] : 0u;
-            group_of_gaussians<BWD_G, true>(a, kk, mine, valid, region, t0x, t0y, t0z);
+            const Rec rec = rec_n;
+            const uint32_t mine = mine_n;
+            const bool valid = valid_n;
+            if (r0 + PER_ROUND < n_lds) fetch(r0 + PER_ROUND, n_lds);
+            group_of_gaussians<BWD_G, true>(a, kk, mine, valid, rec, region, t0x, t0y, t0z);
         }
 #pragma unroll 1
         for (int r0 = n_lds; r0 < base; r0 += PER_ROUND) {
             const int ix = r0 + grp;
             const bool valid = ix < base;
             const uint32_t mine = valid ? order[wv][ix] : 0u;
-            group_of_gaussians<BWD_G, false>(a, kk, mine, valid, region, t0x, t0y, t0z);
+            const Rec rec = load_record(a, gi, mine, valid);
+            group_of_gaussians<BWD_G, false>(a, kk, mine, valid, rec, region, t0x, t0y, t0z);
         }
     }
 }

@@ -201,15 +201,37 @@ __device__ __forceinline__ void accumulate_tile(const RenderArgs& a, const TileP
     const int s = sgpr(a.tile_start[bt]);
     const int e = sgpr(a.tile_start[bt + 1]);
 
+    // Software pipeline over batches: while a batch's pieces are evaluated, the next batch's
+    // records and the list entries of the batch after it are in flight (lane i of a batch
+    // holds entry b0 + i).  Out-of-range lanes load nothing and keep zeros.
+    // (the id's home bit is cleared only when the record is loaded, so that no wait for the
+    // entry is placed right after its load)
+    auto load_id = [&](int b) -> int {
+        return (lane < RB && b + lane < e) ? pg[b + lane] : -1;
+    };
+    float4 n0 = make_float4(0, 0, 0, 0), n1 = n0, n2 = n0, n3 = n0;   // next batch's records
+    auto load_rec = [&](int entry) {
+        if (entry != -1) {
+            const uint32_t gid = (uint32_t)entry & GM_ID_MASK;
+            const float4* src = reinterpret_cast<const float4*>(recbase + (size_t)gid * 16);
+            n0 = src[0];
+            n1 = src[1];
+            n2 = src[2];
+            n3 = src[3];
+        }
+    };
+    load_rec(load_id(s));
+    int id_next = load_id(s + RB);
+
 #pragma unroll 1
     for (int b0 = s; b0 < e; b0 += RB) {
         const int nb = min(RB, e - b0);
+        const float4 r0 = n0, r1 = n1, r2 = n2, r3 = n3;
+        load_rec(id_next);
+        id_next = load_id(b0 + 2 * RB);
         tile_sync<BLOCK>();
         int myF = 0, myWz = 0;  // this lane's piece: footprint area and z extent
         if (lane < nb) {
-            const int gid = (int)((uint32_t)pg[b0 + lane] & GM_ID_MASK);
-            const float4* src = reinterpret_cast<const float4*>(recbase + (size_t)gid * 16);
-            const float4 r0 = src[0], r1 = src[1], r2 = src[2], r3 = src[3];
             const int lox = __float_as_int(r2.z), loy = __float_as_int(r2.w);
             const int loz = __float_as_int(r3.x), hix = __float_as_int(r3.y);
             const int hiy = __float_as_int(r3.z), hiz = __float_as_int(r3.w);

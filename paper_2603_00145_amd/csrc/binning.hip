@@ -9,6 +9,7 @@ namespace {
 constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_CHUNK = SCAN_THREADS * SCAN_ITEMS;
+constexpr unsigned SCAN_PREFIX_BLOCKS = 2048;   // final-pass blocks that sum their own prefix
 
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, uint32_t v, int64_t n)
 {
@@ -64,9 +65,37 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const int32_t* in,
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
+// The chunk totals part[0..nb) replaced by their exclusive prefix sums, in place: one block
+// walks them SCAN_CHUNK at a time with a running offset (used when the final pass has too many
+// blocks to sum the totals before it one by one).
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_parts(int64_t* part, int64_t nb)
+{
+    int64_t running = 0;
+    for (int64_t c0 = 0; c0 < nb; c0 += SCAN_CHUNK) {
+        const int64_t base = c0 + (int64_t)threadIdx.x * SCAN_ITEMS;
+        int64_t v[SCAN_ITEMS];
+        int64_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k) {
+            v[k] = base + k < nb ? part[base + k] : 0;
+            sum += v[k];
+        }
+        int64_t tot;
+        int64_t run = block_exclusive_scan(sum, &tot) + running;
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k) {
+            if (base + k < nb) part[base + k] = run;
+            run += v[k];
+        }
+        running += tot;
+    }
+}
+
+// prefixed: part holds the exclusive prefix sums of the chunk totals (k_scan_parts ran);
+// otherwise each block sums the totals before it.
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(const int32_t* in, int64_t n,
                                                               const int64_t* part,
-                                                              int64_t* out)
+                                                              int64_t* out, int prefixed)
 {
     // each thread owns SCAN_ITEMS consecutive elements of the block's chunk, moved with
     // 16-byte loads and stores where the chunk is whole and the buffers are aligned
@@ -91,11 +120,15 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(const int32_t* in, 
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) s += v[k];
     // this block's offset: the sum of the chunk totals before it (read from L2; integer,
-    // so the order of the sum does not matter)
-    int64_t pre = 0;
-    for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += SCAN_THREADS) pre += part[b];
+    // so the order of the sum does not matter), or its prefix when the totals were scanned
     int64_t before;
-    block_exclusive_scan(pre, &before);
+    if (prefixed) {
+        before = part[blockIdx.x];
+    } else {
+        int64_t pre = 0;
+        for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += SCAN_THREADS) pre += part[b];
+        block_exclusive_scan(pre, &before);
+    }
     int64_t tot;
     int64_t run = block_exclusive_scan(s, &tot) + before;
     int64_t r[SCAN_ITEMS];
@@ -380,7 +413,13 @@ hipError_t launch_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, vo
     const unsigned nb = grid_for(n, SCAN_CHUNK);
     int64_t* part = reinterpret_cast<int64_t*>(ws);
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(SCAN_THREADS), 0, s, in, n, part);
-    hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(SCAN_THREADS), 0, s, in, n, part, out);
+    // up to SCAN_PREFIX_BLOCKS blocks each sum the totals before them (a few L2 reads per
+    // thread); beyond, one more pass scans the totals so that the final pass stays linear
+    const int prefixed = nb > SCAN_PREFIX_BLOCKS ? 1 : 0;
+    if (prefixed)
+        hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(SCAN_THREADS), 0, s, part, (int64_t)nb);
+    hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(SCAN_THREADS), 0, s, in, n, part, out,
+                       prefixed);
     return hipGetLastError();
 }
 

@@ -1,15 +1,15 @@
 // K7 + K8: gradients of L = sum_k sum_v dL/dI_k[v] I_k[v] (+ lambda_aniso * L_aniso,
 // Eq. 12-13) with respect to every Gaussian parameter, boxes held fixed.
 //
-// K7 (grid-frame partials): half a wavefront per Gaussian gathers g = dL/dI over the voxels
-// of the Gaussian's box on each listed grid, recomputing E = 2^Q (no per-voxel
-// contributions are stored).  With delta = v - c, Q = delta^T K delta (K the record's
-// base-2 conic as a symmetric matrix) and w = amp E, the ten grid-frame partials are
+// K7 (grid-frame partials): eight lanes per Gaussian gather g = dL/dI over the voxels of the
+// Gaussian's box on each listed grid, recomputing E = 2^Q (no per-voxel contributions are
+// stored).  With delta = v - c, Q = delta^T K delta (K the record's base-2 conic as a
+// symmetric matrix) and w = amp E, the ten grid-frame partials are
 //     d amp = sum g E,   d c = -2 amp ln2 K m,   d K_ab = amp ln2 m_ab
 // with the weighted moments m = sum g E delta and m_ab = sum g E delta_a delta_b.  A lane
-// owns one (x, y) column of the box at a time and walks it along z, summing g E, g E dz and
-// g E dz^2; the column's share of the ten moments follows from those three sums and its
-// (dx, dy).  The moments are reduced across the half-wavefront with DPP and turned into the
+// owns one (x, z) column of the box at a time and walks it along y, summing g E, g E dy and
+// g E dy^2; the column's share of the ten moments follows from those three sums and its
+// (dx, dz).  The moments are reduced across the eight lanes with DPP and turned into the
 // partials once per (grid, Gaussian).  No global atomics are needed.
 //
 // K8 (chain rule, FP64): thread per Gaussian.  The partials of every grid are pulled back
@@ -60,16 +60,18 @@ __device__ __forceinline__ int group_min(int v)
     return m;
 }
 
-// dL/dI region a block stages in LDS: its tile plus a halo of 8 voxels on the upper side in
-// each axis (a home Gaussian's box starts inside the tile).  The z planes are RZS floats apart,
-// RZS = 8 (mod 32), so the up-to-four z rows a lane row reads at one step sit in different
-// LDS banks.
-constexpr int RX = GM_TX + 8, RY = GM_TY + 8, RZ = GM_TZ + 8;
+// dL/dI region a block stages in LDS: its tile plus a halo of 8 voxels on the upper side in x
+// and y and 6 in z (a home Gaussian's box starts inside the tile; thick-slice boxes are short
+// in z).  The z planes are RZS floats apart, RZS = 8 (mod 32), so the up-to-four z rows a lane
+// row reads at one step sit in different LDS banks.
+constexpr int RX = GM_TX + 8, RY = GM_TY + 8, RZ = GM_TZ + 6;
 constexpr int RZS = RX * RY + 8;
 constexpr int BWD_G = 8;   // lanes per Gaussian in the backward
-constexpr int NCLS = 8;    // size classes of boxes inside the staged region
-constexpr int NSLOT = NCLS + 1;  // ... and one class for boxes reaching past it
-constexpr int WIN = 128;   // list entries a wavefront sorts and takes at a time
+constexpr int WINB = 1024; // list entries a block sorts at a time
+constexpr int EPT = WINB / 256;  // ... per thread
+// sort keys of home entries: boxes inside the staged region by (column chunks, y length), both
+// capped, 8 x 16 keys; then one key for boxes reaching past the region
+constexpr int NKEY = 8 * 16 + 1;
 static_assert(RZS % 32 == 8, "z-plane stride must be 8 mod 32 banks");
 
 // Column sums s0 = sum ge, s1 = sum k ge, s2 = sum k^2 ge (ge = g 2^Q_k) over the first NK
@@ -307,15 +309,51 @@ __device__ __forceinline__ void group_of_gaussians(const BackwardArgs& a, int kk
     }
 }
 
+// Exclusive prefix sums of hist[0..NKEY) in place and the total in hist[NKEY], by one
+// wavefront (three keys per lane).
+__device__ __forceinline__ void scan_keys(int* hist, int lane)
+{
+    static_assert(NKEY <= 3 * 64, "three keys per lane");
+    int c[3], sum = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int k = 3 * lane + i;
+        c[i] = k < NKEY ? hist[k] : 0;
+        sum += c[i];
+    }
+    int incl = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += t;
+    }
+    int off = incl - sum;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int k = 3 * lane + i;
+        if (k < NKEY) hist[k] = off;
+        off += c[i];
+    }
+    if (lane == 63) hist[NKEY] = incl;
+}
+
 // One block (four wavefronts) per tile of a listed grid.  The block stages the tile's dL/dI
-// region in LDS (coalesced rows), then its wavefronts take the tile's list WIN entries at a
-// time and process the Gaussians whose home entry (the tile holding the box's lower corner) is
-// among them: every Gaussian of the grid exactly once, each from LDS when its box lies inside
-// the region (the common case) and from global memory otherwise.  Gaussians with an empty box
-// are in no list; gm_bin wrote their zeros.
+// region in LDS (coalesced rows), then sorts the home Gaussians of the tile's list (the tile
+// holding the box's lower corner: every Gaussian of the grid exactly once), WINB list entries
+// at a time, by the loop trips of their boxes: a counting sort over (column chunks, y length)
+// with LDS atomics.  The sorted Gaussians are taken eight at a time (a round), rounds dealt to
+// the wavefronts in turn, so that the eight Gaussians of a wavefront have similar loop trips
+// and the wavefronts of the block similar work.  Each Gaussian is read from LDS when its box
+// lies inside the region (the common case) and from global memory otherwise.  A Gaussian's
+// partials come from its own eight lanes only and do not depend on which others share its
+// round, so the order the atomics give within a key does not change any result bit.
+// Gaussians with an empty box are in no list; gm_bin wrote their zeros.
 __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
 {
     __shared__ float region[RZ * RZS];
+    __shared__ uint32_t order[WINB];
+    __shared__ int hist[NKEY + 1];
+    __shared__ int zext;
     const int lin = xcd_remap(blockIdx.x, gridDim.x);
     int kk = 0;                                            // listed grid of this block
 #pragma unroll 1
@@ -329,29 +367,97 @@ __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
     if (e0 == e1) return;  // block-uniform
     const int nx = a.nx[kk], ny = a.ny[kk], nz = a.nz[kk];
     const float* __restrict__ g = a.dl_di[kk];
-    const int lane = threadIdx.x & 63;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int gi = a.grid_index[kk];
-    // z planes the tile's home boxes reach (those that fit the region): staged planes only
-    __shared__ int zext;
-    if (threadIdx.x == 0) zext = 0;
-    __syncthreads();
-    {
-        int zmax = 0;
-        for (int i = e0 + (int)threadIdx.x; i < e1; i += 256) {
-            const uint32_t v = a.pair_gauss[i];
-            if (v & GM_HOME_BIT) {
-                const int* rc = reinterpret_cast<const int*>(
-                    a.records + ((size_t)gi * a.n + min((int64_t)(v & GM_ID_MASK), a.n - 1)) * 16);
-                const int ex = rc[13] - t0x, ey = rc[14] - t0y, ez = rc[15] - t0z;
-                if (ex < RX && ey < RY && ez < RZ) zmax = max(zmax, ez + 1);
-            }
+
+    // list entry -> its sort key (-1: not a home entry) and the z planes its box reaches in
+    // the region (0 when it reaches past the region)
+    auto classify = [&](int entry, uint32_t& v, int& zreach) -> int {
+        zreach = 0;
+        v = entry < e1 ? a.pair_gauss[entry] : 0u;
+        if (entry >= e1 || !(v & GM_HOME_BIT)) return -1;
+        const int4* rc = reinterpret_cast<const int4*>(
+            a.records + ((size_t)gi * a.n + min((int64_t)(v & GM_ID_MASK), a.n - 1)) * 16);
+        const int4 r2 = rc[2], r3 = rc[3];     // (kxz, kyz, lox, loy), (loz, hix, hiy, hiz)
+        const int lx = r2.z, ly = r2.w, lz = r3.x, hx = r3.y, hy = r3.z, hz = r3.w;
+        if (!(hx - t0x < RX && hy - t0y < RY && hz - t0z < RZ)) return NKEY - 1;
+        zreach = hz - t0z + 1;
+        const int chunks = ((hx - lx + 1) * (hz - lz + 1) + BWD_G - 1) / BWD_G;
+        return (min(chunks, 8) - 1) * 16 + (min(hy - ly + 1, 16) - 1);
+    };
+    uint32_t v[EPT];
+    int key[EPT], rank[EPT];
+    // counts the keys of entries [w0, w0 + WINB) into hist (zeroed before); a thread's rank
+    // within its key is the count the atomic returns
+    auto count_keys = [&](int w0, int& zmax) {
+#pragma unroll
+        for (int h = 0; h < EPT; ++h) {
+            int zr;
+            key[h] = classify(w0 + h * 256 + tid, v[h], zr);
+            zmax = max(zmax, zr);
+            rank[h] = key[h] >= 0 ? atomicAdd(&hist[key[h]], 1) : 0;
         }
-        if (zmax > 0) atomicMax(&zext, zmax);
-    }
+    };
+    auto scatter = [&]() {
+#pragma unroll
+        for (int h = 0; h < EPT; ++h)
+            if (key[h] >= 0) order[hist[key[h]] + rank[h]] = v[h];
+    };
+    // the rounds of one sorted window: n_lds Gaussians from LDS, then the rest from global
+    // memory; round r (order entries 8 r .. 8 r + 7) goes to wavefront r mod 4, and the next
+    // round's records are in flight while a round is processed
+    constexpr int PER_ROUND = 64 / BWD_G;
+    const int grp = lane / BWD_G;
+    auto rounds = [&](int n_lds, int n_all) {
+        const int nr = (n_lds + PER_ROUND - 1) / PER_ROUND;
+        uint32_t mine_n = 0u;
+        bool valid_n = false;
+        Rec rec_n;
+        auto fetch = [&](int r) {
+            const int ix = r * PER_ROUND + grp;
+            valid_n = ix < n_lds;
+            mine_n = valid_n ? order[ix] : 0u;
+            rec_n = load_record(a, gi, mine_n, valid_n);
+        };
+        if (wv < nr) fetch(wv);
+#pragma unroll 1
+        for (int r = wv; r < nr; r += 4) {
+            const Rec rec = rec_n;
+            const uint32_t mine = mine_n;
+            const bool valid = valid_n;
+            if (r + 4 < nr) fetch(r + 4);
+            group_of_gaussians<BWD_G, true>(a, kk, mine, valid, rec, region, t0x, t0y, t0z);
+        }
+        const int ng = (n_all - n_lds + PER_ROUND - 1) / PER_ROUND;
+#pragma unroll 1
+        for (int r = wv; r < ng; r += 4) {
+            const int ix = n_lds + r * PER_ROUND + grp;
+            const bool valid = ix < n_all;
+            const uint32_t mine = valid ? order[ix] : 0u;
+            const Rec rec = load_record(a, gi, mine, valid);
+            group_of_gaussians<BWD_G, false>(a, kk, mine, valid, rec, region, t0x, t0y, t0z);
+        }
+    };
+
+    // first window: keys counted while the z planes the home boxes reach (those that fit
+    // the region) are found over the whole list; only those planes are staged
+    if (tid == 0) zext = 0;
+    for (int i = tid; i < NKEY; i += 256) hist[i] = 0;
     __syncthreads();
+    int zmax = 0;
+    count_keys(e0, zmax);
+    for (int i = e0 + WINB + tid; i < e1; i += 256) {
+        uint32_t vi;
+        int zr;
+        classify(i, vi, zr);
+        zmax = max(zmax, zr);
+    }
+    if (zmax > 0) atomicMax(&zext, zmax);
+    __syncthreads();
+    if (wv == 0) scan_keys(hist, lane);
     const int nzr = min(zext, nz - t0z);
     // rows of RX voxels along x: thread -> (x, y) of a plane, then the planes
-    for (int i = threadIdx.x; i < RX * RY; i += 256) {
+    for (int i = tid; i < RX * RY; i += 256) {
         const int y = i / RX, x = i - y * RX;
         const int gx = t0x + x, gy = t0y + y;
         const bool in = gx < nx && gy < ny;
@@ -363,79 +469,23 @@ __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
         }
     }
     __syncthreads();
-    // Each wavefront takes windows of WIN list entries (two per lane) and sorts the windows'
-    // home Gaussians by size class in LDS with ballots (stable: (class, list position)), then
-    // takes them eight at a time, so that the eight Gaussians of a wavefront have similar
-    // loop trips.  A Gaussian's result does not depend on which others share its wavefront.
-    __shared__ uint32_t order[4][WIN];
-    const int wv = threadIdx.x >> 6;
-    const int grp = lane / BWD_G;
-    // class of a list entry: 0..NCLS-1 a home box inside the staged region (column chunks 1,
-    // 2, 3, 4+ x y length above 6), NCLS a home box reaching past it, NSLOT not a home entry
-    auto entry_class = [&](int entry, uint32_t& v) -> int {
-        v = entry < e1 ? a.pair_gauss[entry] : 0u;
-        if (entry >= e1 || !(v & GM_HOME_BIT)) return NSLOT;
-        const int* rc = reinterpret_cast<const int*>(
-            a.records + ((size_t)gi * a.n + min((int64_t)(v & GM_ID_MASK), a.n - 1)) * 16);
-        const int lx = rc[10], ly = rc[11], lz = rc[12], hx = rc[13], hy = rc[14], hz = rc[15];
-        if (!(hx - t0x < RX && hy - t0y < RY && hz - t0z < RZ)) return NCLS;
-        const int chunks = ((hx - lx + 1) * (hz - lz + 1) + BWD_G - 1) / BWD_G;
-        return (min(chunks, 4) - 1) * 2 + (hy - ly + 1 > 6 ? 1 : 0);
-    };
-    constexpr int EPL = WIN / 64;  // entries per lane
+    scatter();
+    __syncthreads();
+    rounds(hist[NKEY - 1], hist[NKEY]);
+    // further windows (lists longer than WINB entries)
 #pragma unroll 1
-    for (int w0 = e0 + wv * WIN; w0 < e1; w0 += 4 * WIN) {
-        uint32_t v[EPL];
-        int cl[EPL], pos[EPL];
-#pragma unroll
-        for (int h = 0; h < EPL; ++h) {
-            cl[h] = entry_class(w0 + h * 64 + lane, v[h]);
-            pos[h] = 0;
-        }
-        int n_lds = 0, base = 0;
-#pragma unroll
-        for (int c = 0; c < NSLOT; ++c) {
-#pragma unroll
-            for (int h = 0; h < EPL; ++h) {
-                const uint64_t m = __ballot(cl[h] == c);
-                const int r = (int)__builtin_amdgcn_mbcnt_hi(
-                    (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                if (cl[h] == c) pos[h] = base + r;
-                base += __popcll(m);
-            }
-            if (c == NCLS - 1) n_lds = base;
-        }
-#pragma unroll
-        for (int h = 0; h < EPL; ++h)
-            if (cl[h] < NSLOT) order[wv][pos[h]] = v[h];
-        constexpr int PER_ROUND = 64 / BWD_G;
-        // the next round's records are in flight while a round is processed
-        uint32_t mine_n = 0u;
-        bool valid_n = false;
-        Rec rec_n;
-        auto fetch = [&](int r0, int lim) {
-            const int ix = r0 + grp;
-            valid_n = ix < lim;
-            mine_n = valid_n ? order[wv][ix] : 0u;
-            rec_n = load_record(a, gi, mine_n, valid_n);
-        };
-        if (n_lds > 0) fetch(0, n_lds);
-#pragma unroll 1
-        for (int r0 = 0; r0 < n_lds; r0 += PER_ROUND) {
-            const Rec rec = rec_n;
-            const uint32_t mine = mine_n;
-            const bool valid = valid_n;
-            if (r0 + PER_ROUND < n_lds) fetch(r0 + PER_ROUND, n_lds);
-            group_of_gaussians<BWD_G, true>(a, kk, mine, valid, rec, region, t0x, t0y, t0z);
-        }
-#pragma unroll 1
-        for (int r0 = n_lds; r0 < base; r0 += PER_ROUND) {
-            const int ix = r0 + grp;
-            const bool valid = ix < base;
-            const uint32_t mine = valid ? order[wv][ix] : 0u;
-            const Rec rec = load_record(a, gi, mine, valid);
-            group_of_gaussians<BWD_G, false>(a, kk, mine, valid, rec, region, t0x, t0y, t0z);
-        }
+    for (int w0 = e0 + WINB; w0 < e1; w0 += WINB) {
+        __syncthreads();                       // order and hist are free again
+        for (int i = tid; i < NKEY; i += 256) hist[i] = 0;
+        __syncthreads();
+        int zr = 0;
+        count_keys(w0, zr);
+        __syncthreads();
+        if (wv == 0) scan_keys(hist, lane);
+        __syncthreads();
+        scatter();
+        __syncthreads();
+        rounds(hist[NKEY - 1], hist[NKEY]);
     }
 }
 

@@ -76,18 +76,6 @@ __device__ __forceinline__ void add_column(float* acc, int idx, const float (&w)
     for (int k = 0; k < KZ; ++k) acc[idx + k * GM_TX * GM_TY] = old[k] + w[k];
 }
 
-// add_column for a uniform z extent kz in [1, KM]
-template <int KM>
-__device__ __forceinline__ void add_column_kz(float* acc, int idx, const float (&w)[KM], int kz)
-{
-    switch (kz) {
-    case 1: add_column<1, KM>(acc, idx, w); break;
-    case 2: if constexpr (KM >= 2) add_column<2, KM>(acc, idx, w); break;
-    case 3: if constexpr (KM >= 3) add_column<3, KM>(acc, idx, w); break;
-    default: if constexpr (KM >= 4) add_column<4, KM>(acc, idx, w); break;
-    }
-}
-
 // One piece on the whole wave: columns f0 + lane, KM z-steps each (lane_fh = lane + 1/2).
 template <int KM>
 __device__ __forceinline__ void single_piece(const Piece& p, float* acc, int F, float lane_fh)
@@ -103,22 +91,42 @@ __device__ __forceinline__ void single_piece(const Piece& p, float* acc, int F, 
     }
 }
 
-// Two pieces side by side in the wave (lane's piece p, column fh - 1/2); KM = the larger z
-// extent.  The first piece's read-add-writes complete before the second piece's are issued.
-template <int KM>
+// Two pieces side by side in the wave (lane's piece p, column fh - 1/2) with z extents ZA
+// and ZB, evaluated over the larger of the two.  The first piece's read-add-writes complete
+// before the second piece's are issued.  Both extents are template parameters, so a pass
+// dispatches once on the pair and its two add phases carry no branches of their own.
+template <int ZA, int ZB>
 __device__ __forceinline__ void paired_pieces(const Piece& p, float* acc, bool act, bool first,
-                                              float fh, int wza, int wzb)
+                                              float fh)
 {
+    constexpr int KM = ZA > ZB ? ZA : ZB;
     // every lane evaluates (a lane past its piece's footprint computes values it never
     // stores), so no lane mask is needed around the evaluation
     float w[KM];
     int idx;
     eval_column<KM>(p, fh, w, idx);
     lds_order();
-    if (act && first) add_column_kz<KM>(acc, idx, w, wza);
+    if (act && first) add_column<ZA, KM>(acc, idx, w);
     lds_order();
-    if (act && !first) add_column_kz<KM>(acc, idx, w, wzb);
+    if (act && !first) add_column<ZB, KM>(acc, idx, w);
     lds_order();
+}
+
+// paired_pieces for uniform z extents wza, wzb in [1, GM_TZ]
+__device__ __forceinline__ void paired_pieces_kz(const Piece& p, float* acc, bool act,
+                                                 bool first, float fh, int wza, int wzb)
+{
+    static_assert(GM_TZ == 4, "z extents 1..4 are dispatched below");
+#define GM_PAIR_CASE(A, B) \
+    case (A - 1) * 4 + (B - 1): paired_pieces<A, B>(p, acc, act, first, fh); break;
+    switch ((wza - 1) * 4 + (wzb - 1)) {
+    GM_PAIR_CASE(1, 1) GM_PAIR_CASE(1, 2) GM_PAIR_CASE(1, 3) GM_PAIR_CASE(1, 4)
+    GM_PAIR_CASE(2, 1) GM_PAIR_CASE(2, 2) GM_PAIR_CASE(2, 3) GM_PAIR_CASE(2, 4)
+    GM_PAIR_CASE(3, 1) GM_PAIR_CASE(3, 2) GM_PAIR_CASE(3, 3) GM_PAIR_CASE(3, 4)
+    GM_PAIR_CASE(4, 1) GM_PAIR_CASE(4, 2) GM_PAIR_CASE(4, 3)
+    default: paired_pieces<4, 4>(p, acc, act, first, fh); break;
+    }
+#undef GM_PAIR_CASE
 }
 
 // List entries prepared per batch; 32 keeps the LDS of a wavefront at 6 KB so that six
@@ -276,13 +284,7 @@ __device__ __forceinline__ void accumulate_tile(const RenderArgs& a, const TileP
                 const Piece p = pc[first ? j : j + 1];
                 const float fh = first ? lane_fh : lane_fh - (float)Fa;
                 const bool act = fh < p.Ff;
-                static_assert(GM_TZ == 4, "z extents 1..4 are dispatched below");
-                switch (max(wza, wzb)) {
-                case 1: paired_pieces<1>(p, acc, act, first, fh, wza, wzb); break;
-                case 2: paired_pieces<2>(p, acc, act, first, fh, wza, wzb); break;
-                case 3: paired_pieces<3>(p, acc, act, first, fh, wza, wzb); break;
-                default: paired_pieces<GM_TZ>(p, acc, act, first, fh, wza, wzb); break;
-                }
+                paired_pieces_kz(p, acc, act, first, fh, wza, wzb);
                 j += 2;
             } else {
                 const Piece p = pc[j];

@@ -148,17 +148,16 @@ __device__ __forceinline__ void group_of_gaussians(const BackwardArgs& a, int kk
     const float4 r0 = rec.r0, r1 = rec.r1, r2 = rec.r2, r3 = rec.r3;
     const int lox = __float_as_int(r2.z), loy = __float_as_int(r2.w), loz = __float_as_int(r3.x);
     const int hix = __float_as_int(r3.y), hiy = __float_as_int(r3.z), hiz = __float_as_int(r3.w);
+    // a listed Gaussian's box is never empty; an invalid lane group (past the round's end)
+    // holds the all-zero record load_record gives it, so its floats are finite and its box
+    // takes no steps
     const bool nonempty = gvalid && lox <= hix && loy <= hiy && loz <= hiz;
-    // an empty box (including an invalid Gaussian) contributes nothing; its record's
-    // floats are replaced by zeros so that nothing non-finite enters the sums
     const int wx = nonempty ? hix - lox + 1 : 1;
     const int wy = nonempty ? hiy - loy + 1 : 0;
     const int wz = nonempty ? hiz - loz + 1 : 0;
-    const float cx = nonempty ? r0.x : 0.0f, cy = nonempty ? r0.y : 0.0f;
-    const float cz = nonempty ? r0.z : 0.0f;
-    const float kxx = nonempty ? r1.x : 0.0f, kyy = nonempty ? r1.y : 0.0f;
-    const float kzz = nonempty ? r1.z : 0.0f, kxy = nonempty ? r1.w : 0.0f;
-    const float kxz = nonempty ? r2.x : 0.0f, kyz = nonempty ? r2.y : 0.0f;
+    const float cx = r0.x, cy = r0.y, cz = r0.z;
+    const float kxx = r1.x, kyy = r1.y, kzz = r1.z, kxy = r1.w;
+    const float kxz = r2.x, kyz = r2.y;
     const int fp = wx * wz;                       // (x, z) footprint of the box
     const int chunks = (fp + G - 1) / G;
     const int max_chunks = group_max<G>(chunks);
@@ -182,8 +181,10 @@ __device__ __forceinline__ void group_of_gaussians(const BackwardArgs& a, int kk
     const float obase = (float)((loz - t0z) * RZS + (loy - t0y) * RX + (lox - t0x)) - 0.5f;
     const float qlh = (float)ql + 0.5f;
     // weighted moments: m0 = sum gE, m1 = sum gE delta, m2 = sum gE delta delta^T
-    float m0 = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f;
-    float mxx = 0.0f, myy = 0.0f, mzz = 0.0f, mxy = 0.0f, mxz = 0.0f, myz = 0.0f;
+    float m0 = 0.0f, mx = 0.0f, mz = 0.0f, mxx = 0.0f, mzz = 0.0f, mxz = 0.0f;
+    // ... and in the column step index k: k1 = sum k gE, k2 = sum k^2 gE, k1x = sum k gE dx,
+    // k1z = sum k gE dz
+    float k1 = 0.0f, k2 = 0.0f, k1x = 0.0f, k1z = 0.0f;
 #pragma unroll 1
     for (int c = 0; c < max_chunks; ++c) {
         const float fh = fmaf((float)c, (float)G, qlh);
@@ -268,21 +269,26 @@ __device__ __forceinline__ void group_of_gaussians(const BackwardArgs& a, int kk
             s1 += fk * ge;
             s2 += fk * fk * ge;
         }
-        // back to moments in dy = dy0 + k
-        const float S1 = s1 + dy0 * s0;
-        const float S2 = s2 + dy0 * (2.0f * s1 + dy0 * s0);
+        // the column's share in the step index k (moments in dy = dy0 + k follow below)
         const float ax = s0 * dx, az = s0 * dz;
         m0 += s0;
         mx += ax;
         mz += az;
-        my += S1;
-        mxx += ax * dx;
-        mzz += az * dz;
-        mxz += ax * dz;
-        mxy += S1 * dx;
-        myz += S1 * dz;
-        myy += S2;
+        mxx = fmaf(ax, dx, mxx);
+        mzz = fmaf(az, dz, mzz);
+        mxz = fmaf(ax, dz, mxz);
+        k1 += s1;
+        k2 += s2;
+        k1x = fmaf(s1, dx, k1x);
+        k1z = fmaf(s1, dz, k1z);
     }
+    // from sums over the step index k to moments in dy = dy0 + k (dy0 is the Gaussian's):
+    // sum (dy0 + k) gE = k1 + dy0 m0, sum (dy0 + k)^2 gE = k2 + dy0 (2 k1 + dy0 m0), and
+    // the products with dx and dz likewise
+    float my = fmaf(dy0, m0, k1);
+    float myy = fmaf(dy0, fmaf(2.0f, k1, dy0 * m0), k2);
+    float mxy = fmaf(dy0, mx, k1x);
+    float myz = fmaf(dy0, mz, k1z);
     m0 = group_sum<G>(m0);
     mx = group_sum<G>(mx);
     my = group_sum<G>(my);
@@ -295,7 +301,7 @@ __device__ __forceinline__ void group_of_gaussians(const BackwardArgs& a, int kk
     myz = group_sum<G>(myz);
     if (ql == 0 && gvalid) {
         // K as a full symmetric matrix has off-diagonal entries kxy/2, kxz/2, kyz/2
-        const float Al = (nonempty ? r0.w : 0.0f) * GM_LN2F;   // amp ln2
+        const float Al = r0.w * GM_LN2F;   // amp ln2
         const float hxy = 0.5f * kxy, hxz = 0.5f * kxz, hyz = 0.5f * kyz;
         const float tx = kxx * mx + hxy * my + hxz * mz;
         const float ty = hxy * mx + kyy * my + hyz * mz;

@@ -271,25 +271,27 @@ __device__ __forceinline__ void accumulate_tile(const RenderArgs& a, const TileP
         // bit j: pieces j and j + 1 fit side by side in the wave (footprints summing to <= 64)
         const int nextF = __shfl_down(myF, 1, 64);
         const uint64_t pm = __ballot(lane + 1 < nb && myF + nextF <= 64);
+        // lane j: (F_j << 6) | (wz_{j+1} << 3) | wz_j, so that one read gives a pass its
+        // footprint and both z extents (F <= 256, wz <= 4)
+        const int pk = (myF << 6) | (__shfl_down(myWz, 1, 64) << 3) | myWz;
         tile_sync<BLOCK>();
         int j = 0;
 #pragma unroll 1
         while (j < nb) {
+            const int k = __builtin_amdgcn_readlane(pk, j);
             if ((pm >> j) & 1u) {
                 // pieces j and j+1 side by side: lanes [0, Fa) take piece j, the next Fb piece j+1
-                const int Fa = __builtin_amdgcn_readlane(myF, j);
-                const int wza = __builtin_amdgcn_readlane(myWz, j);
-                const int wzb = __builtin_amdgcn_readlane(myWz, j + 1);
+                const int Fa = k >> 6, wza = k & 7, wzb = (k >> 3) & 7;
                 const bool first = lane < Fa;
-                const Piece p = pc[first ? j : j + 1];
-                const float fh = first ? lane_fh : lane_fh - (float)Fa;
+                const Piece p = *reinterpret_cast<const Piece*>(
+                    reinterpret_cast<const char*>(pc + j) + (first ? 0 : (int)sizeof(Piece)));
+                const float fh = lane_fh - (first ? 0.0f : (float)Fa);
                 const bool act = fh < p.Ff;
                 paired_pieces_kz(p, acc, act, first, fh, wza, wzb);
                 j += 2;
             } else {
                 const Piece p = pc[j];
-                const int F = __builtin_amdgcn_readlane(myF, j);
-                const int wz = __builtin_amdgcn_readlane(myWz, j);
+                const int F = k >> 6, wz = k & 7;
                 switch (wz) {
                 case 0: break;
                 case 1: single_piece<1>(p, acc, F, lane_fh); break;

@@ -2,6 +2,7 @@
 
     python bench_profile.py stats  --dir D --out F --command C
     python bench_profile.py valu --dir D --kernel k_render --pairs-log P --out F --command C
+    python bench_profile.py util --dir D --kernel k_render --out F --command C
     python bench_profile.py traffic --fetch-dir D1 --write-dir D2
            --kernel k_render --source paper_2603_00145_amd/csrc/render.hip --calib-mib 1024
            --out F --command-fetch C1 --command-write C2
@@ -9,6 +10,10 @@
 `valu` takes one `--pmc` run of VALU instruction counters (SQ_INSTS_VALU_*) of bench.py with
 `--pairs-log`, and records their mean per dispatch of one kernel with the mean contributing
 pairs per dispatch and the kernel's assembly digest.
+
+`util` takes one `--pmc` run of LDS and issue counters (SQ_LDS_IDX_ACTIVE, SQ_LDS_BANK_CONFLICT,
+SQ_ACTIVE_INST_VALU, SQ_ACTIVE_INST_SCA, SQ_WAIT_INST_LDS, SQ_WAIT_INST_ANY, GRBM_GUI_ACTIVE) and
+records the busy fractions rocprofv3's derived metrics define (LdsUtil, VALUBusy) for one kernel.
 
 `stats` summarises a `--kernel-trace --stats` run (per-kernel calls and durations of this
 library's kernels).  `traffic` takes one `--pmc FETCH_SIZE` run and one `--pmc WRITE_SIZE`
@@ -170,6 +175,64 @@ reported for the same iterations.
     print(txt)
 
 
+def cmd_util(a):
+    rows = _rows(a.dir, "*counter_collection.csv")
+    per = {}
+    for r in rows:
+        if _short(r["Kernel_Name"]) != a.kernel:
+            continue
+        d = per.setdefault(int(r["Dispatch_Id"]), {})
+        d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    if not per:
+        sys.exit(f"kernel {a.kernel} not found")
+    names = sorted({c for d in per.values() for c in d})
+    m = {c: statistics.mean(d.get(c, 0.0) for d in per.values()) for c in names}
+    need = ("GRBM_GUI_ACTIVE", "SQ_LDS_IDX_ACTIVE", "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_VALU",
+            "SQ_ACTIVE_INST_SCA", "SQ_WAIT_INST_LDS", "SQ_WAIT_INST_ANY")
+    for c in need:
+        if c not in m:
+            sys.exit(f"counter {c} missing")
+    digest = kernel_digest(a.kernel)
+    if digest is None:
+        sys.exit("no kernel_digests.json entry: build first")
+    # GRBM_GUI_ACTIVE comes summed over the XCDs: per XCD it is the dispatch's GPU clocks
+    clocks = m["GRBM_GUI_ACTIVE"] / a.xcds
+    cu_clocks = clocks * a.cus
+    rows_out = [
+        ("LDS busy (LdsUtil: SQ_LDS_IDX_ACTIVE / (clocks x CUs))", m["SQ_LDS_IDX_ACTIVE"] / cu_clocks),
+        ("LDS stalled on bank conflicts (SQ_LDS_BANK_CONFLICT / (clocks x CUs))",
+         m["SQ_LDS_BANK_CONFLICT"] / cu_clocks),
+        ("vector issue busy (VALUBusy: SQ_ACTIVE_INST_VALU / (clocks x CUs))",
+         m["SQ_ACTIVE_INST_VALU"] / cu_clocks),
+        ("scalar issue busy (SQ_ACTIVE_INST_SCA / (clocks x CUs))", m["SQ_ACTIVE_INST_SCA"] / cu_clocks),
+        ("share of issue waits that wait on LDS (SQ_WAIT_INST_LDS / SQ_WAIT_INST_ANY)",
+         m["SQ_WAIT_INST_LDS"] / m["SQ_WAIT_INST_ANY"]),
+    ]
+    txt = f"""# LDS and issue utilisation of {a.kernel} ({a.workload})
+
+Command (from the repository root on the GPU machine, run after `cd /tmp`):
+
+    {a.command}
+
+Counters per dispatch (mean of {len(per)} dispatches), summed over the chip; clocks =
+GRBM_GUI_ACTIVE / {a.xcds} XCDs = {clocks:.0f}, CUs = {a.cus}.
+
+| fraction | value |
+|---|---|
+"""
+    for k, v in rows_out:
+        txt += f"| {k} | {v:.3f} |\n"
+    txt += "\n"
+    for c in names:
+        txt += f"{c}: {m[c]:.0f}\n"
+    txt += f"kernel: {a.kernel}\nkernel_asm_sha256: {digest}\nsource: {a.source}\n"
+    if a.note:
+        txt += "\n" + a.note + "\n"
+    with open(a.out, "w") as f:
+        f.write(txt)
+    print(txt)
+
+
 def cmd_stats(a):
     rows = _rows(a.dir, "*kernel_stats.csv")
     lines = []
@@ -214,6 +277,16 @@ def main():
     v.add_argument("--command", required=True)
     v.add_argument("--note", default="")
     v.add_argument("--out", required=True)
+    u = sub.add_parser("util")
+    u.add_argument("--dir", required=True)
+    u.add_argument("--kernel", required=True)
+    u.add_argument("--source", required=True)
+    u.add_argument("--xcds", type=int, default=8)
+    u.add_argument("--cus", type=int, default=256)
+    u.add_argument("--workload", default="training iteration, 256^3 workload")
+    u.add_argument("--command", required=True)
+    u.add_argument("--note", default="")
+    u.add_argument("--out", required=True)
     s = sub.add_parser("stats")
     s.add_argument("--dir", required=True)
     s.add_argument("--workload", default="training iteration, 256^3 workload")
@@ -221,7 +294,7 @@ def main():
     s.add_argument("--note", default="")
     s.add_argument("--out", required=True)
     a = ap.parse_args()
-    {"traffic": cmd_traffic, "stats": cmd_stats, "valu": cmd_valu}[a.cmd](a)
+    {"traffic": cmd_traffic, "stats": cmd_stats, "valu": cmd_valu, "util": cmd_util}[a.cmd](a)
 
 
 if __name__ == "__main__":

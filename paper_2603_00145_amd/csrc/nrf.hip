@@ -26,6 +26,8 @@ __global__ __launch_bounds__(256) void k_nrf_forward(const NrfArgs a)
     __shared__ Lds<KT, DEPTH> s;
     load_weights<KT, DEPTH>(a, s);
     const int lane = threadIdx.x & 63, g = lane >> 4, row = lane & 15;
+    v4s wo[4];
+    load_wout(a, wo);
     const int64_t ntiles = (a.n_points + 15) / 16;
     for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntiles;
          tile += (int64_t)gridDim.x * 4) {
@@ -37,7 +39,7 @@ __global__ __launch_bounds__(256) void k_nrf_forward(const NrfArgs a)
                             world_coord(a.m + 8, vx, vy, vz)};
         Tile<KT, DEPTH> T;
         tile_forward<KT, DEPTH>(a, s, x, T);
-        const float zo = tile_output<KT, DEPTH>(a, T);
+        const float zo = tile_output<KT, DEPTH>(a, T, wo);     // lane group 0
         if (valid && g == 0) {
             const int64_t v = ((int64_t)vz * a.ny + vy) * a.nx + vx;
             a.out[v] += a.out_scale * tanhf(zo);
@@ -53,6 +55,8 @@ __global__ __launch_bounds__(256) void k_nrf_chain(const NrfArgs a, NrfWork w)
     __shared__ LdsChain<KT, DEPTH> s;
     load_weights<KT, DEPTH>(a, s.f, s.w_hid_t);
     const int lane = threadIdx.x & 63, g = lane >> 4, row = lane & 15;
+    v4s wo[4];
+    load_wout(a, wo);
     const int64_t P = w.P;
     const int64_t ntiles = P / 16;
     // the output layer's gradient over this wavefront's points: gwo[4 o + j] for feature
@@ -70,7 +74,8 @@ __global__ __launch_bounds__(256) void k_nrf_chain(const NrfArgs a, NrfWork w)
                             world_coord(a.m + 8, vx, vy, vz)};
         Tile<KT, DEPTH> T;
         tile_forward<KT, DEPTH>(a, s.f, x, T, &w, p);
-        const float zo = tile_output<KT, DEPTH>(a, T);
+        // z_o of the lane's point, from lane group 0 to all four
+        const float zo = __shfl(tile_output<KT, DEPTH>(a, T, wo), row, 64);
         float dl = 0.0f;
         if (valid) dl = a.dl_dr[((int64_t)vz * a.ny + vy) * a.nx + vx];
         const float th = tanhf(zo);

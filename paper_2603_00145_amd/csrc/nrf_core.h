@@ -243,25 +243,29 @@ __device__ __forceinline__ void tile_forward(const NrfArgs& a, const Lds<KT, DEP
     }
 }
 
-// output pre-activation z_o of the tile's point from the BF16 activations of the last layer
-// (all 4 lane groups end with the total)
-template <int KT, int DEPTH>
-__device__ __forceinline__ float tile_output(const NrfArgs& a, const Tile<KT, DEPTH>& T)
+// The output layer as a 16-row MFMA A operand whose row 0 is w_out and the other rows zero:
+// lane (g, 0) holds w_out[16 t + 4 g + j] of K-tile t.  Loaded once per wavefront.
+__device__ __forceinline__ void load_wout(const NrfArgs& a, v4s (&wo)[4])
 {
-    const int lane = threadIdx.x & 63, g = lane >> 4;
-    float sacc = 0.0f;
+    const int lane = threadIdx.x & 63, g = lane >> 4, row = lane & 15;
 #pragma unroll
-    for (int o = 0; o < 4; ++o) {
-        const v4s h = T.act[DEPTH - 1][o];
-        const int f = 16 * o + 4 * g;
-        sacc += from_bf16(a.w_out[f]) * from_bf16((uint16_t)h.x) +
-                from_bf16(a.w_out[f + 1]) * from_bf16((uint16_t)h.y) +
-                from_bf16(a.w_out[f + 2]) * from_bf16((uint16_t)h.z) +
-                from_bf16(a.w_out[f + 3]) * from_bf16((uint16_t)h.w);
+    for (int t = 0; t < 4; ++t) {
+        const v4s v = *reinterpret_cast<const v4s*>(a.w_out + 16 * t + 4 * g);
+        wo[t] = row == 0 ? v : v4s{0, 0, 0, 0};
     }
-    sacc += __shfl_xor(sacc, 16, 64);
-    sacc += __shfl_xor(sacc, 32, 64);
-    return sacc + a.b_out[0];
+}
+
+// output pre-activation z_o of the tile's point from the BF16 activations of the last layer,
+// on the matrix cores (wo from load_wout): row 0 of the product, held by lane group 0, is
+// w_out . a_D for the lane's point.  Valid in lane group 0 only (the other groups get b_out).
+template <int KT, int DEPTH>
+__device__ __forceinline__ float tile_output(const NrfArgs& a, const Tile<KT, DEPTH>& T,
+                                             const v4s (&wo)[4])
+{
+    v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    acc = mfma2(wo[0], wo[1], T.act[DEPTH - 1][0], T.act[DEPTH - 1][1], acc);
+    acc = mfma2(wo[2], wo[3], T.act[DEPTH - 1][2], T.act[DEPTH - 1][3], acc);
+    return acc.x + a.b_out[0];
 }
 
 }  // namespace nrfcore

@@ -378,6 +378,8 @@ __global__ __launch_bounds__(64 * FW) void k_render_field(const RenderArgs a, co
     __shared__ Piece pcs[FW][RB];
     nrfcore::load_weights<KT, DEPTH>(f, sw);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, row = lane & 15;
+    nrfcore::v4s wo[4];
+    nrfcore::load_wout(f, wo);
     float* acc = accs[w];
     Piece* pc = pcs[w];
     const int xcd = blockIdx.x & 7;
@@ -400,7 +402,7 @@ __global__ __launch_bounds__(64 * FW) void k_render_field(const RenderArgs a, co
                                 nrfcore::world_coord(G.index_to_world + 8, vx, vy, vz)};
             nrfcore::Tile<KT, DEPTH> Tl;
             nrfcore::tile_forward<KT, DEPTH>(f, sw, x, Tl);
-            const float zo = nrfcore::tile_output<KT, DEPTH>(f, Tl);
+            const float zo = nrfcore::tile_output<KT, DEPTH>(f, Tl, wo);   // lane group 0
             if (g == 0 && vx < G.nx) acc[q * 16 + row] += f.out_scale * tanhf(zo);
         }
         tile_sync<false>();

@@ -25,8 +25,12 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgm.so")
 
 SOURCES = ["gm_api.hip", "preprocess.hip", "binning.hip", "render.hip", "backward.hip",
-           "optim.hip", "init.hip", "nrf.hip", "warm.hip", "ssim.hip"]
+           "optim.hip", "init.hip", "nrf.hip", "nrf_fwd.hip", "warm.hip", "ssim.hip"]
 NO_CONTRACT = {"preprocess.hip"}
+# MFMA results in ordinary VGPRs rather than AGPRs: the field's forward reads every accumulator
+# back for the activation, which AGPRs would cost one v_accvgpr_read each (the field's chain
+# kernel, in nrf.hip, holds more live registers and runs 3% slower so built)
+MFMA_VGPR = {"nrf_fwd.hip"}
 
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
           "-Wno-unused-function", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -40,11 +44,18 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+def _flags(src: str) -> list:
     flags = list(COMMON)
     if src in NO_CONTRACT:
         flags.append("-ffp-contract=off")
+    if src in MFMA_VGPR:
+        flags += ["-mllvm", "-amdgpu-mfma-vgpr-form"]
+    return flags
+
+
+def _compile(src: str) -> str:
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    flags = _flags(src)
     cmd = [hipcc()] + flags + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -59,9 +70,7 @@ DIGESTS = os.path.join(HERE, "kernel_digests.json")
 
 def _kernel_asm_digest(src: str, kernels) -> dict:
     """SHA-256 of each kernel's gfx950 assembly (its function body, labels included)."""
-    flags = list(COMMON)
-    if src in NO_CONTRACT:
-        flags.append("-ffp-contract=off")
+    flags = _flags(src)
     out = os.path.join(BUILD, os.path.splitext(src)[0] + ".s")
     cmd = [hipcc()] + flags + ["--cuda-device-only", "-S", os.path.join(CSRC, src), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -14,38 +14,12 @@
 // Backward (for a list of sampled voxels): recompute, then per layer dZ_l = dA_l * SiLU'(Z_l),
 // dA_{l-1} = W_l^T dZ_l (MFMA); dZ_l and A_{l-1} are written feature-major (BF16) and the
 // weight gradients dW_l = dZ_l A_{l-1}^T are formed by a split-K MFMA GEMM over the points.
+// The forward alone (k_nrf_forward) is in nrf_fwd.hip.
 #include "nrf_core.h"
 
 namespace {
 
 using namespace nrfcore;
-
-template <int KT, int DEPTH>
-__global__ __launch_bounds__(256) void k_nrf_forward(const NrfArgs a)
-{
-    __shared__ Lds<KT, DEPTH> s;
-    load_weights<KT, DEPTH>(a, s);
-    const int lane = threadIdx.x & 63, g = lane >> 4, row = lane & 15;
-    v4s wo[4];
-    load_wout(a, wo);
-    const int64_t ntiles = (a.n_points + 15) / 16;
-    for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntiles;
-         tile += (int64_t)gridDim.x * 4) {
-        const int64_t p = tile * 16 + row;
-        const bool valid = p < a.n_points;
-        int vx = 0, vy = 0, vz = 0;
-        if (valid) point_xyz(a, p, &vx, &vy, &vz);
-        const float x[3] = {world_coord(a.m, vx, vy, vz), world_coord(a.m + 4, vx, vy, vz),
-                            world_coord(a.m + 8, vx, vy, vz)};
-        Tile<KT, DEPTH> T;
-        tile_forward<KT, DEPTH>(a, s, x, T);
-        const float zo = tile_output<KT, DEPTH>(a, T, wo);     // lane group 0
-        if (valid && g == 0) {
-            const int64_t v = ((int64_t)vz * a.ny + vy) * a.nx + vx;
-            a.out[v] += a.out_scale * tanhf(zo);
-        }
-    }
-}
 
 // Recompute a tile and write, feature-major with point stride P: DZO (f32, per point), and
 // for each layer l (1..D) dZ_l [W][P] and A_{l-1} [in_l][P] (BF16), plus A_D [W][P].
@@ -294,61 +268,17 @@ __global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ in,
         out[i] = to_bf16(in[i]);
 }
 
-// Grid of a tile loop: every block resident at once (the blocks then take equal shares of the
-// tiles, with no partial last wave of blocks), capped by the work.
-template <typename K>
-unsigned blocks_for_tiles(K kernel, int64_t ntiles)
-{
-    int dev = 0, cus = 0, per_cu = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0);
-    int64_t full = (int64_t)(cus > 0 ? cus : 256) * (per_cu > 0 ? per_cu : 1);
-    int64_t b = (ntiles + 3) / 4;
-    if (b > full) b = full;
-    if (b < 1) b = 1;
-    return (unsigned)b;
-}
-
 }  // namespace
-
-template <int KT, int DEPTH>
-void launch_fwd_t(const NrfArgs& a, hipStream_t s)
-{
-    const unsigned nb = blocks_for_tiles(k_nrf_forward<KT, DEPTH>, (a.n_points + 15) / 16);
-    hipLaunchKernelGGL((k_nrf_forward<KT, DEPTH>), dim3(nb), dim3(256), 0, s, a);
-}
 
 template <int KT, int DEPTH>
 void launch_chain_t(const NrfArgs& a, const NrfWork& w, hipStream_t s, int64_t* nwaves)
 {
-    const unsigned nb = blocks_for_tiles(k_nrf_chain<KT, DEPTH>, w.P / 16);
+    const unsigned nb = nrfcore::blocks_for_tiles(k_nrf_chain<KT, DEPTH>, w.P / 16);
     *nwaves = (int64_t)nb * 4;
     hipLaunchKernelGGL((k_nrf_chain<KT, DEPTH>), dim3(nb), dim3(256), 0, s, a, w);
 }
 
-// supported shapes: in_pad 64 or 128 (4 or 8 K-tiles; at most max_bands<KT>() bands), depth 1..4
-#define GM_NRF_DISPATCH(FN, ...)                                                           \
-    switch ((a.in_pad >> 4) * 8 + a.depth) {                                               \
-    case 4 * 8 + 1: FN<4, 1>(__VA_ARGS__); break;                                          \
-    case 4 * 8 + 2: FN<4, 2>(__VA_ARGS__); break;                                          \
-    case 4 * 8 + 3: FN<4, 3>(__VA_ARGS__); break;                                          \
-    case 4 * 8 + 4: FN<4, 4>(__VA_ARGS__); break;                                          \
-    case 8 * 8 + 1: FN<8, 1>(__VA_ARGS__); break;                                          \
-    case 8 * 8 + 2: FN<8, 2>(__VA_ARGS__); break;                                          \
-    case 8 * 8 + 3: FN<8, 3>(__VA_ARGS__); break;                                          \
-    case 8 * 8 + 4: FN<8, 4>(__VA_ARGS__); break;                                          \
-    default: return hipErrorInvalidValue;                                                  \
-    }
-
 int nrf_max_bands(int in_pad) { return in_pad == 64 ? max_bands<4>() : max_bands<8>(); }
-
-hipError_t launch_nrf_forward(const NrfArgs& a, hipStream_t s)
-{
-    if (a.n_points <= 0) return hipSuccess;
-    GM_NRF_DISPATCH(launch_fwd_t, a, s)
-    return hipGetLastError();
-}
 
 size_t nrf_part_floats(int64_t P, int in_pad)
 {

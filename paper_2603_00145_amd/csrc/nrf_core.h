@@ -195,13 +195,42 @@ __device__ __forceinline__ void store_fm(uint16_t* dst, int f, int64_t P, int64_
     dst[(int64_t)(f + 3) * P + p] = (uint16_t)v.w;
 }
 
+// Where tile_forward takes the layers' MFMA A operands from: the LDS stage, read at each use,
+// or the wavefront's registers (each lane its quad of every operand, 4 KT + 16 (DEPTH - 1)
+// quads, copied once from the stage; the per-tile LDS reads of the weights, 512 bytes per lane,
+// then disappear).
+template <int KT, int DEPTH>
+struct WeightsLds {
+    const Lds<KT, DEPTH>& s;
+    int lane;
+    __device__ v4s in(int o, int t) const { return s.w_in[(o * KT + t) * 64 + lane]; }
+    __device__ v4s hid(int l, int o, int t) const
+    {
+        return s.w_hid[((l - 1) * 16 + o * 4 + t) * 64 + lane];
+    }
+};
+template <int KT, int DEPTH>
+struct WeightsReg {
+    v4s w_in[4 * KT];
+    v4s w_hid[(DEPTH > 1 ? DEPTH - 1 : 1) * 16];
+    __device__ void load(const Lds<KT, DEPTH>& s, int lane)
+    {
+#pragma unroll
+        for (int i = 0; i < 4 * KT; ++i) w_in[i] = s.w_in[i * 64 + lane];
+#pragma unroll
+        for (int i = 0; i < (DEPTH - 1) * 16; ++i) w_hid[i] = s.w_hid[i * 64 + lane];
+    }
+    __device__ v4s in(int o, int t) const { return w_in[o * KT + t]; }
+    __device__ v4s hid(int l, int o, int t) const { return w_hid[(l - 1) * 16 + o * 4 + t]; }
+};
+
 // With a workspace (w != NULL) the encoding (in the GPU order) and each layer's BF16
 // activations are written out feature-major as soon as they are formed (the backward needs
 // them for dW), so they need not stay live in registers.
-template <int KT, int DEPTH>
-__device__ __forceinline__ void tile_forward(const NrfArgs& a, const Lds<KT, DEPTH>& s, const float x[3],
-                                             Tile<KT, DEPTH>& T, const NrfWork* w = nullptr,
-                                             int64_t p = 0)
+template <int KT, int DEPTH, typename WS>
+__device__ __forceinline__ void tile_forward_w(const NrfArgs& a, const WS& ws, const float x[3],
+                                               Tile<KT, DEPTH>& T, const NrfWork* w = nullptr,
+                                               int64_t p = 0)
 {
     const int lane = threadIdx.x & 63, g = lane >> 4;
     v4s b0[KT];
@@ -217,8 +246,7 @@ __device__ __forceinline__ void tile_forward(const NrfArgs& a, const Lds<KT, DEP
         v4f acc = {a.b_in[f], a.b_in[f + 1], a.b_in[f + 2], a.b_in[f + 3]};   // bias as C
 #pragma unroll
         for (int t = 0; t < KT; t += 2)
-            acc = mfma2(s.w_in[(o * KT + t) * 64 + lane], s.w_in[(o * KT + t + 1) * 64 + lane],
-                        b0[t], b0[t + 1], acc);
+            acc = mfma2(ws.in(o, t), ws.in(o, t + 1), b0[t], b0[t + 1], acc);
         T.z[0][o] = acc;
         T.act[0][o] = pack4(silu(acc.x), silu(acc.y), silu(acc.z), silu(acc.w));
         if (w && DEPTH > 1) store_fm(w->a[1], f, w->P, p, T.act[0][o]);
@@ -226,7 +254,6 @@ __device__ __forceinline__ void tile_forward(const NrfArgs& a, const Lds<KT, DEP
     // hidden layers
 #pragma unroll
     for (int l = 1; l < DEPTH; ++l) {
-        const v4s* Wl = s.w_hid + (l - 1) * 16 * 64;
         const float* bl = a.b_hid + (l - 1) * W;
 #pragma unroll
         for (int o = 0; o < 4; ++o) {
@@ -234,13 +261,23 @@ __device__ __forceinline__ void tile_forward(const NrfArgs& a, const Lds<KT, DEP
             v4f acc = {bl[f], bl[f + 1], bl[f + 2], bl[f + 3]};
 #pragma unroll
             for (int t = 0; t < 4; t += 2)
-                acc = mfma2(Wl[(o * 4 + t) * 64 + lane], Wl[(o * 4 + t + 1) * 64 + lane],
-                            T.act[l - 1][t], T.act[l - 1][t + 1], acc);
+                acc = mfma2(ws.hid(l, o, t), ws.hid(l, o, t + 1), T.act[l - 1][t],
+                            T.act[l - 1][t + 1], acc);
             T.z[l][o] = acc;
             T.act[l][o] = pack4(silu(acc.x), silu(acc.y), silu(acc.z), silu(acc.w));
             if (w && l + 1 < DEPTH) store_fm(w->a[l + 1], f, w->P, p, T.act[l][o]);
         }
     }
+}
+
+// tile_forward_w with the weights read from the LDS stage at each use
+template <int KT, int DEPTH>
+__device__ __forceinline__ void tile_forward(const NrfArgs& a, const Lds<KT, DEPTH>& s, const float x[3],
+                                             Tile<KT, DEPTH>& T, const NrfWork* w = nullptr,
+                                             int64_t p = 0)
+{
+    const WeightsLds<KT, DEPTH> ws{s, (int)(threadIdx.x & 63)};
+    tile_forward_w<KT, DEPTH>(a, ws, x, T, w, p);
 }
 
 // The output layer as a 16-row MFMA A operand whose row 0 is w_out and the other rows zero:
@@ -268,5 +305,36 @@ __device__ __forceinline__ float tile_output(const NrfArgs& a, const Tile<KT, DE
     return acc.x + a.b_out[0];
 }
 
+// Grid of a tile loop: every block resident at once (the blocks then take equal shares of the
+// tiles, with no partial last wave of blocks), capped by the work.
+template <typename K>
+inline unsigned blocks_for_tiles(K kernel, int64_t ntiles)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0);
+    int64_t full = (int64_t)(cus > 0 ? cus : 256) * (per_cu > 0 ? per_cu : 1);
+    int64_t b = (ntiles + 3) / 4;
+    if (b > full) b = full;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
 }  // namespace nrfcore
+
+// supported shapes: in_pad 64 or 128 (4 or 8 K-tiles; at most max_bands<KT>() bands), depth 1..4
+#define GM_NRF_DISPATCH(FN, ...)                                                           \
+    switch ((a.in_pad >> 4) * 8 + a.depth) {                                               \
+    case 4 * 8 + 1: FN<4, 1>(__VA_ARGS__); break;                                          \
+    case 4 * 8 + 2: FN<4, 2>(__VA_ARGS__); break;                                          \
+    case 4 * 8 + 3: FN<4, 3>(__VA_ARGS__); break;                                          \
+    case 4 * 8 + 4: FN<4, 4>(__VA_ARGS__); break;                                          \
+    case 8 * 8 + 1: FN<8, 1>(__VA_ARGS__); break;                                          \
+    case 8 * 8 + 2: FN<8, 2>(__VA_ARGS__); break;                                          \
+    case 8 * 8 + 3: FN<8, 3>(__VA_ARGS__); break;                                          \
+    case 8 * 8 + 4: FN<8, 4>(__VA_ARGS__); break;                                          \
+    default: return hipErrorInvalidValue;                                                  \
+    }
+
 #endif

@@ -116,21 +116,17 @@ struct Rec {
     float4 r0, r1, r2, r3;
 };
 
-__device__ __forceinline__ Rec load_record(const BackwardArgs& a, int gi, uint32_t mine, bool valid)
+// (an invalid lane group passes mine = 0 and gets Gaussian 0's record: finite values whose
+// box group_of_gaussians never walks)
+__device__ __forceinline__ Rec load_record(const BackwardArgs& a, int gi, uint32_t mine)
 {
+    const int64_t gid = min((int64_t)(mine & GM_ID_MASK), a.n - 1);
+    const float4* rp = reinterpret_cast<const float4*>(a.records + ((size_t)gi * a.n + gid) * 16);
     Rec r;
-    r.r0 = make_float4(0, 0, 0, 0);
-    r.r1 = r.r0;
-    r.r2 = r.r0;
-    r.r3 = r.r0;
-    if (valid) {
-        const int64_t gid = min((int64_t)(mine & GM_ID_MASK), a.n - 1);
-        const float4* rp = reinterpret_cast<const float4*>(a.records + ((size_t)gi * a.n + gid) * 16);
-        r.r0 = rp[0];
-        r.r1 = rp[1];
-        r.r2 = rp[2];
-        r.r3 = rp[3];
-    }
+    r.r0 = rp[0];
+    r.r1 = rp[1];
+    r.r2 = rp[2];
+    r.r3 = rp[3];
     return r;
 }
 
@@ -149,8 +145,7 @@ __device__ __forceinline__ void group_of_gaussians(const BackwardArgs& a, int kk
     const int lox = __float_as_int(r2.z), loy = __float_as_int(r2.w), loz = __float_as_int(r3.x);
     const int hix = __float_as_int(r3.y), hiy = __float_as_int(r3.z), hiz = __float_as_int(r3.w);
     // a listed Gaussian's box is never empty; an invalid lane group (past the round's end)
-    // holds the all-zero record load_record gives it, so its floats are finite and its box
-    // takes no steps
+    // holds a finite record (Gaussian 0's) and takes no steps: its box counts as empty
     const bool nonempty = gvalid && lox <= hix && loy <= hiy && loz <= hiz;
     const int wx = nonempty ? hix - lox + 1 : 1;
     const int wy = nonempty ? hiy - loy + 1 : 0;
@@ -416,23 +411,24 @@ __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
     const int grp = lane / BWD_G;
     auto rounds = [&](int n_lds, int n_all) {
         const int nr = (n_lds + PER_ROUND - 1) / PER_ROUND;
-        uint32_t mine_n = 0u;
-        bool valid_n = false;
-        Rec rec_n;
-        auto fetch = [&](int r) {
+        // two record buffers used in turn (no copy between rounds)
+        uint32_t ma = 0u, mb = 0u;
+        bool va = false, vb = false;
+        Rec ra, rb;
+        auto fetch = [&](int r, Rec& rec, uint32_t& m, bool& v) {
             const int ix = r * PER_ROUND + grp;
-            valid_n = ix < n_lds;
-            mine_n = valid_n ? order[ix] : 0u;
-            rec_n = load_record(a, gi, mine_n, valid_n);
+            v = ix < n_lds;
+            m = v ? order[ix] : 0u;
+            rec = load_record(a, gi, m);
         };
-        if (wv < nr) fetch(wv);
+        if (wv < nr) fetch(wv, ra, ma, va);
 #pragma unroll 1
-        for (int r = wv; r < nr; r += 4) {
-            const Rec rec = rec_n;
-            const uint32_t mine = mine_n;
-            const bool valid = valid_n;
-            if (r + 4 < nr) fetch(r + 4);
-            group_of_gaussians<BWD_G, true>(a, kk, mine, valid, rec, region, t0x, t0y, t0z);
+        for (int r = wv; r < nr; r += 8) {
+            if (r + 4 < nr) fetch(r + 4, rb, mb, vb);
+            group_of_gaussians<BWD_G, true>(a, kk, ma, va, ra, region, t0x, t0y, t0z);
+            if (r + 4 >= nr) break;
+            if (r + 8 < nr) fetch(r + 8, ra, ma, va);
+            group_of_gaussians<BWD_G, true>(a, kk, mb, vb, rb, region, t0x, t0y, t0z);
         }
         const int ng = (n_all - n_lds + PER_ROUND - 1) / PER_ROUND;
 #pragma unroll 1
@@ -440,7 +436,7 @@ __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
             const int ix = n_lds + r * PER_ROUND + grp;
             const bool valid = ix < n_all;
             const uint32_t mine = valid ? order[ix] : 0u;
-            const Rec rec = load_record(a, gi, mine, valid);
+            const Rec rec = load_record(a, gi, mine);
             group_of_gaussians<BWD_G, false>(a, kk, mine, valid, rec, region, t0x, t0y, t0z);
         }
     };

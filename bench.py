@@ -469,8 +469,7 @@ def time_nrf_on(args, bins, p, m, v, ids, stacks, targets, dls, lrs, step0):
         api.grid_partials(p, bins, ids, dls)
         mark()
         net.zero_grad()
-        for kk, g in enumerate(stacks):
-            net.backward(g, dls[kk], idx=draws[i][kk])
+        net.backward_grids(stacks, dls, idxs=draws[i])
         net.adam_step(1e-4)
         mark()
         k_step[0] += 1

@@ -95,8 +95,7 @@ def main():
 
         def nrf_bwd():
             net.zero_grad()
-            for s in w.stacks:
-                net.backward(s, dl, idx=idx)
+            net.backward_grids(w.stacks, [dl] * len(w.stacks), idxs=[idx] * len(w.stacks))
         t = _time(nrf_bwd, args.reps)
         pts = 3 * (1 << 18)
         f = nrf_flops(net, backward=True) * pts

@@ -285,6 +285,26 @@ gm_status gm_nrf_backward(const gm_nrf* nrf, const gm_grid* grid, const int32_t*
                           gm_nrf_grads* grads, void* workspace, size_t workspace_bytes,
                           gm_stream stream);
 
+/* [host out] device workspace bytes gm_nrf_backward_grids needs for n_grids point lists of
+ * n_points[k] points (each rounded up to a multiple of 16 in the workspace). */
+gm_status gm_nrf_workspace_grids(const gm_nrf* nrf, int32_t n_grids, const int64_t* n_points,
+                                 size_t* bytes);
+
+/* The backward of gm_nrf_backward summed over several grids in one pass: the gradient of
+ * sum_k scales[k] sum_{j < n_points[k]} dl_dr[k][v_kj] r(x_{v_kj}), v_kj = idx[k][j] (idx[k]
+ * NULL = every voxel of grids[k]), accumulated into grads.  Equal to the n_grids calls of
+ * gm_nrf_backward up to the order of the FP32 sums: the chain kernel runs once per grid into
+ * one workspace, then the weight-gradient GEMMs and their sums run once over all the points
+ * (the paper's sampled training points of every stack, Sec. 3.4).  grids, idx, n_points,
+ * dl_dr, scales: [host] arrays of n_grids (1 <= n_grids <= GM_MAX_GRIDS); idx[k] and dl_dr[k]
+ * device pointers; other arguments and errors as for gm_nrf_backward, with workspace_bytes at
+ * least what gm_nrf_workspace_grids gives. */
+gm_status gm_nrf_backward_grids(const gm_nrf* nrf, int32_t n_grids, const gm_grid* grids,
+                                const int32_t* const* idx, const int64_t* n_points,
+                                const float* const* dl_dr, const float* scales,
+                                gm_nrf_grads* grads, void* workspace, size_t workspace_bytes,
+                                gm_stream stream);
+
 /* out[i] = bfloat16(in[i]) (round to nearest even), as uint16 bit patterns. */
 gm_status gm_f32_to_bf16(const float* in, uint16_t* out, int64_t n, gm_stream stream);
 

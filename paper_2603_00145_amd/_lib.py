@@ -148,6 +148,14 @@ _SIGS = [
     ("gm_nrf_backward", ctypes.c_int, [ctypes.POINTER(GmNrf), ctypes.POINTER(GmGrid), P,
                                         ctypes.c_int64, P, ctypes.c_float,
                                         ctypes.POINTER(GmNrfGrads), P, ctypes.c_size_t, P]),
+    ("gm_nrf_workspace_grids", ctypes.c_int, [ctypes.POINTER(GmNrf), ctypes.c_int32,
+                                               ctypes.POINTER(ctypes.c_int64),
+                                               ctypes.POINTER(ctypes.c_size_t)]),
+    ("gm_nrf_backward_grids", ctypes.c_int, [ctypes.POINTER(GmNrf), ctypes.c_int32,
+                                              ctypes.POINTER(GmGrid), ctypes.POINTER(P),
+                                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(P),
+                                              ctypes.POINTER(ctypes.c_float),
+                                              ctypes.POINTER(GmNrfGrads), P, ctypes.c_size_t, P]),
     ("gm_f32_to_bf16", ctypes.c_int, [P, P, ctypes.c_int64, P]),
     ("gm_ws_gather", ctypes.c_int, [ctypes.POINTER(GmGrid), ctypes.c_int32, ctypes.POINTER(P), P,
                                      ctypes.c_int64, ctypes.c_float, P, P]),

@@ -748,23 +748,25 @@ gm_status gm_nrf_workspace(const gm_nrf* nrf, int64_t n_points, size_t* bytes)
     return GM_OK;
 }
 
-gm_status gm_nrf_backward(const gm_nrf* nrf, const gm_grid* grid, const int32_t* idx,
-                          int64_t n_points, const float* dl_dr, float scale, gm_nrf_grads* grads,
-                          void* workspace, size_t workspace_bytes, gm_stream stream)
+namespace {
+
+// the workspace views of a layout over P points
+NrfWork nrf_work(const gm_nrf* nrf, const NrfLayout& L, void* workspace)
 {
-    g_err.clear();
-    gm_status st = check_nrf(nrf);
-    if (st != GM_OK) return st;
-    if (!grid || !grads) return fail(GM_ERR_INVALID_ARGUMENT, "grid / grads is NULL");
-    st = check_grid(*grid, 0);
-    if (st != GM_OK) return st;
-    if (n_points < 0 || n_points > 0x7fffffffLL) return fail(GM_ERR_INVALID_ARGUMENT, "n_points");
-    if (!idx && n_points != (int64_t)grid->nx * grid->ny * grid->nz)
-        return fail(GM_ERR_INVALID_ARGUMENT, "idx NULL requires n_points = grid voxels");
-    if (!isfinite(scale)) return fail(GM_ERR_INVALID_ARGUMENT, "scale not finite");
-    if (n_points == 0) return GM_OK;
-    REQ_PTR(dl_dr, "dl_dr");
-    REQ_PTR(workspace, "workspace");
+    char* base = reinterpret_cast<char*>(workspace);
+    NrfWork w;
+    memset(&w, 0, sizeof w);
+    w.P = L.P;
+    w.dzo = reinterpret_cast<float*>(base + L.off_dzo);
+    for (int l = 0; l < nrf->depth; ++l) w.dz[l] = reinterpret_cast<uint16_t*>(base + L.off_dz[l]);
+    for (int l = 0; l <= nrf->depth; ++l) w.a[l] = reinterpret_cast<uint16_t*>(base + L.off_a[l]);
+    w.part = reinterpret_cast<float*>(base + L.off_part);
+    return w;
+}
+
+gm_status check_nrf_grads(const gm_nrf* nrf, const gm_nrf_grads* grads)
+{
+    if (!grads) return fail(GM_ERR_INVALID_ARGUMENT, "grads is NULL");
     REQ_PTR(grads->w_in, "grads->w_in");
     REQ_PTR(grads->b_in, "grads->b_in");
     REQ_PTR(grads->w_out, "grads->w_out");
@@ -773,13 +775,27 @@ gm_status gm_nrf_backward(const gm_nrf* nrf, const gm_grid* grid, const int32_t*
         REQ_PTR(grads->w_hid, "grads->w_hid");
         REQ_PTR(grads->b_hid, "grads->b_hid");
     }
-    const NrfLayout L = nrf_layout(nrf, n_points);
-    if (workspace_bytes < L.bytes)
-        return fail(GM_ERR_INVALID_ARGUMENT, "workspace %zu bytes < required %zu", workspace_bytes,
-                    L.bytes);
+    return GM_OK;
+}
+
+// one grid's point list of a backward call, checked
+gm_status nrf_backward_grid(const gm_nrf* nrf, int k, const gm_grid& grid, const int32_t* idx,
+                            int64_t n_points, const float* dl_dr, float scale,
+                            const gm_nrf_grads* grads, NrfArgs* out)
+{
+    gm_status st = check_grid(grid, k);
+    if (st != GM_OK) return st;
+    if (n_points < 0 || n_points > 0x7fffffffLL)
+        return fail(GM_ERR_INVALID_ARGUMENT, "grid %d: n_points outside [0, 2^31)", k);
+    if (!idx && n_points != (int64_t)grid.nx * grid.ny * grid.nz)
+        return fail(GM_ERR_INVALID_ARGUMENT, "grid %d: idx NULL requires n_points = grid voxels",
+                    k);
+    if (!isfinite(scale)) return fail(GM_ERR_INVALID_ARGUMENT, "grid %d: scale not finite", k);
+    if (n_points > 0) REQ_PTR(dl_dr, "dl_dr");
     double M[12];
-    if (!index_to_world(*grid, M)) return fail(GM_ERR_INVALID_ARGUMENT, "singular grid affine");
-    NrfArgs a = nrf_args(nrf, *grid, M);
+    if (!index_to_world(grid, M))
+        return fail(GM_ERR_INVALID_ARGUMENT, "grid %d: singular grid affine", k);
+    NrfArgs a = nrf_args(nrf, grid, M);
     a.n_points = n_points;
     a.idx = idx;
     a.dl_dr = dl_dr;
@@ -790,15 +806,93 @@ gm_status gm_nrf_backward(const gm_nrf* nrf, const gm_grid* grid, const int32_t*
     a.g_b_hid = grads->b_hid;
     a.g_w_out = grads->w_out;
     a.g_b_out = grads->b_out;
-    char* base = reinterpret_cast<char*>(workspace);
-    NrfWork w;
-    memset(&w, 0, sizeof w);
-    w.P = L.P;
-    w.dzo = reinterpret_cast<float*>(base + L.off_dzo);
-    for (int l = 0; l < nrf->depth; ++l) w.dz[l] = reinterpret_cast<uint16_t*>(base + L.off_dz[l]);
-    for (int l = 0; l <= nrf->depth; ++l) w.a[l] = reinterpret_cast<uint16_t*>(base + L.off_a[l]);
-    w.part = reinterpret_cast<float*>(base + L.off_part);
+    *out = a;
+    return GM_OK;
+}
+
+int64_t rounded_points(int32_t n_grids, const int64_t* n_points)
+{
+    int64_t P = 0;
+    for (int k = 0; k < n_grids; ++k) P += ((n_points[k] + 15) / 16) * 16;
+    return P;
+}
+
+}  // namespace
+
+gm_status gm_nrf_backward(const gm_nrf* nrf, const gm_grid* grid, const int32_t* idx,
+                          int64_t n_points, const float* dl_dr, float scale, gm_nrf_grads* grads,
+                          void* workspace, size_t workspace_bytes, gm_stream stream)
+{
+    g_err.clear();
+    gm_status st = check_nrf(nrf);
+    if (st != GM_OK) return st;
+    if (!grid || !grads) return fail(GM_ERR_INVALID_ARGUMENT, "grid / grads is NULL");
+    NrfArgs a;
+    st = nrf_backward_grid(nrf, 0, *grid, idx, n_points, dl_dr, scale, grads, &a);
+    if (st != GM_OK) return st;
+    if (n_points == 0) return GM_OK;
+    REQ_PTR(workspace, "workspace");
+    st = check_nrf_grads(nrf, grads);
+    if (st != GM_OK) return st;
+    const NrfLayout L = nrf_layout(nrf, n_points);
+    if (workspace_bytes < L.bytes)
+        return fail(GM_ERR_INVALID_ARGUMENT, "workspace %zu bytes < required %zu", workspace_bytes,
+                    L.bytes);
+    const NrfWork w = nrf_work(nrf, L, workspace);
     GM_HIP(launch_nrf_backward(a, w, reinterpret_cast<hipStream_t>(stream)), "nrf backward");
+    return GM_OK;
+}
+
+gm_status gm_nrf_workspace_grids(const gm_nrf* nrf, int32_t n_grids, const int64_t* n_points,
+                                 size_t* bytes)
+{
+    g_err.clear();
+    gm_status st = check_nrf(nrf);
+    if (st != GM_OK) return st;
+    if (n_grids < 1 || n_grids > GM_MAX_GRIDS || !n_points || !bytes)
+        return fail(GM_ERR_INVALID_ARGUMENT, "n_grids outside [1, %d], or n_points / bytes NULL",
+                    GM_MAX_GRIDS);
+    for (int k = 0; k < n_grids; ++k)
+        if (n_points[k] < 0 || n_points[k] > 0x7fffffffLL)
+            return fail(GM_ERR_INVALID_ARGUMENT, "n_points[%d] outside [0, 2^31)", k);
+    const int64_t P = rounded_points(n_grids, n_points);
+    if (P > 0x7fffffffLL) return fail(GM_ERR_INVALID_ARGUMENT, "more than 2^31 points in all");
+    *bytes = nrf_layout(nrf, P).bytes;
+    return GM_OK;
+}
+
+gm_status gm_nrf_backward_grids(const gm_nrf* nrf, int32_t n_grids, const gm_grid* grids,
+                                const int32_t* const* idx, const int64_t* n_points,
+                                const float* const* dl_dr, const float* scales,
+                                gm_nrf_grads* grads, void* workspace, size_t workspace_bytes,
+                                gm_stream stream)
+{
+    g_err.clear();
+    gm_status st = check_nrf(nrf);
+    if (st != GM_OK) return st;
+    if (n_grids < 1 || n_grids > GM_MAX_GRIDS)
+        return fail(GM_ERR_INVALID_ARGUMENT, "n_grids outside [1, %d]", GM_MAX_GRIDS);
+    if (!grids || !idx || !n_points || !dl_dr || !scales || !grads)
+        return fail(GM_ERR_INVALID_ARGUMENT, "grids / idx / n_points / dl_dr / scales / grads NULL");
+    NrfArgs as[GM_MAX_GRIDS];
+    for (int k = 0; k < n_grids; ++k) {
+        st = nrf_backward_grid(nrf, k, grids[k], idx[k], n_points[k], dl_dr[k], scales[k], grads,
+                               &as[k]);
+        if (st != GM_OK) return st;
+    }
+    const int64_t P = rounded_points(n_grids, n_points);
+    if (P == 0) return GM_OK;
+    if (P > 0x7fffffffLL) return fail(GM_ERR_INVALID_ARGUMENT, "more than 2^31 points in all");
+    REQ_PTR(workspace, "workspace");
+    st = check_nrf_grads(nrf, grads);
+    if (st != GM_OK) return st;
+    const NrfLayout L = nrf_layout(nrf, P);
+    if (workspace_bytes < L.bytes)
+        return fail(GM_ERR_INVALID_ARGUMENT, "workspace %zu bytes < required %zu", workspace_bytes,
+                    L.bytes);
+    const NrfWork w = nrf_work(nrf, L, workspace);
+    GM_HIP(launch_nrf_backward_grids(as, n_grids, w, reinterpret_cast<hipStream_t>(stream)),
+           "nrf backward over grids");
     return GM_OK;
 }
 

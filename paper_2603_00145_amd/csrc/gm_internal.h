@@ -268,11 +268,15 @@ struct NrfArgs {
     float* g_b_out;
 };
 struct NrfWork {
-    int64_t P;               // points rounded up to 16
+    int64_t P;               // workspace points (every grid's, each rounded up to 16)
     float* dzo;              // [P]
     uint16_t* dz[4];         // [64][P] per layer
     uint16_t* a[5];          // a[0] [in_pad][P], a[l] [64][P]
     float* part;             // split-K partials
+    // the chain kernel's grid: its points sit at workspace columns p0 .. p0 + np (np its point
+    // count rounded up to 16), its wavefronts' output-layer partials at rows wave0 .. of
+    // nwaves_total
+    int64_t p0, np, wave0, nwaves_total;
 };
 // most frequency bands the kernels encode with in_pad 64 / 128 input features
 int nrf_max_bands(int in_pad);
@@ -280,6 +284,11 @@ hipError_t launch_nrf_forward(const NrfArgs& a, hipStream_t s);
 // floats of split-K / row-sum partials gm_nrf_backward needs for P points
 size_t nrf_part_floats(int64_t P, int in_pad);
 hipError_t launch_nrf_backward(const NrfArgs& a, const NrfWork& w, hipStream_t s);
+// the backward summed over n grids' point lists (a[k]: grid k's arguments, the weights and
+// gradients the same in all), into one workspace of w.P = sum of the rounded point counts
+hipError_t launch_nrf_backward_grids(const NrfArgs* a, int n, const NrfWork& w, hipStream_t s);
+// chain kernel blocks (4 wavefronts each) for np points
+unsigned nrf_chain_blocks(const NrfArgs& a, int64_t np);
 hipError_t launch_to_bf16(const float* in, uint16_t* out, int64_t n, hipStream_t s);
 
 struct WsGatherArgs {

@@ -32,7 +32,7 @@ __global__ __launch_bounds__(256) void k_nrf_chain(const NrfArgs a, NrfWork w)
     v4s wo[4];
     load_wout(a, wo);
     const int64_t P = w.P;
-    const int64_t ntiles = P / 16;
+    const int64_t ntiles = w.np / 16;
     // the output layer's gradient over this wavefront's points: gwo[4 o + j] for feature
     // 16 o + 4 g + j (sum of dzo a_D), gbo the sum of dzo (lanes of group 0)
     float gwo[16], gbo = 0.0f;
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(256) void k_nrf_chain(const NrfArgs a, NrfWork w)
         const float x[3] = {world_coord(a.m, vx, vy, vz), world_coord(a.m + 4, vx, vy, vz),
                             world_coord(a.m + 8, vx, vy, vz)};
         Tile<KT, DEPTH> T;
-        tile_forward<KT, DEPTH>(a, s.f, x, T, &w, p);
+        tile_forward<KT, DEPTH>(a, s.f, x, T, &w, w.p0 + p);
         // z_o of the lane's point, from lane group 0 to all four
         const float zo = __shfl(tile_output<KT, DEPTH>(a, T, wo), row, 64);
         float dl = 0.0f;
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void k_nrf_chain(const NrfArgs a, NrfWork w)
                 const v4f z = T.z[l][o];
                 const v4f d = da[o];
                 dz[o] = pack4(d.x * dsilu(z.x), d.y * dsilu(z.y), d.z * dsilu(z.z), d.w * dsilu(z.w));
-                store_fm(w.dz[l], 16 * o + 4 * g, P, p, dz[o]);
+                store_fm(w.dz[l], 16 * o + 4 * g, P, w.p0 + p, dz[o]);
             }
             if (l == 0) break;
             // dA_{l-1} = W_l^T dZ_l
@@ -98,13 +98,14 @@ __global__ __launch_bounds__(256) void k_nrf_chain(const NrfArgs a, NrfWork w)
         }
     }
     // sum over the 16 points of each lane group, then one partial per wavefront:
-    // part[wave][64] for w_out, then part[nwaves * 64 + wave] for b_out
+    // part[wave][64] for w_out, then part[nwaves * 64 + wave] for b_out (waves counted over
+    // every grid of the call)
 #pragma unroll
     for (int i = 0; i < 16; ++i)
         for (int o = 1; o < 16; o <<= 1) gwo[i] += __shfl_xor(gwo[i], o, 64);
     for (int o = 1; o < 16; o <<= 1) gbo += __shfl_xor(gbo, o, 64);
-    const int64_t nwaves = (int64_t)gridDim.x * 4;
-    const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t nwaves = w.nwaves_total;
+    const int64_t wid = w.wave0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row == 0) {
 #pragma unroll
         for (int o = 0; o < 4; ++o)
@@ -271,10 +272,15 @@ __global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ in,
 }  // namespace
 
 template <int KT, int DEPTH>
-void launch_chain_t(const NrfArgs& a, const NrfWork& w, hipStream_t s, int64_t* nwaves)
+void chain_blocks_t(const NrfArgs& a, int64_t np, unsigned* nb)
 {
-    const unsigned nb = nrfcore::blocks_for_tiles(k_nrf_chain<KT, DEPTH>, w.P / 16);
-    *nwaves = (int64_t)nb * 4;
+    (void)a;
+    *nb = nrfcore::blocks_for_tiles(k_nrf_chain<KT, DEPTH>, np / 16);
+}
+
+template <int KT, int DEPTH>
+void launch_chain_t(const NrfArgs& a, const NrfWork& w, unsigned nb, hipStream_t s)
+{
     hipLaunchKernelGGL((k_nrf_chain<KT, DEPTH>), dim3(nb), dim3(256), 0, s, a, w);
 }
 
@@ -283,21 +289,62 @@ int nrf_max_bands(int in_pad) { return in_pad == 64 ? max_bands<4>() : max_bands
 size_t nrf_part_floats(int64_t P, int in_pad)
 {
     const int64_t gemm = ((P + GPB - 1) / GPB) * W * ((in_pad > W ? in_pad : W) + 1);
-    // the chain kernel's output-layer partials: W + 1 per wavefront, at most P/16 + 3 of them
-    const int64_t rows = (int64_t)(W + 1) * (P / 16 + 4);
+    // the chain kernel's output-layer partials: W + 1 per wavefront, at most np/16 + 3 of them
+    // for each grid of a call
+    const int64_t rows = (int64_t)(W + 1) * (P / 16 + 4 * GM_MAX_GRIDS);
     return (size_t)(gemm > rows ? gemm : rows);
 }
 
-hipError_t launch_nrf_backward(const NrfArgs& a, const NrfWork& w, hipStream_t s)
+unsigned nrf_chain_blocks(const NrfArgs& a, int64_t np)
 {
-    if (a.n_points <= 0) return hipSuccess;
-    int64_t nwaves = 0;
-    GM_NRF_DISPATCH(launch_chain_t, a, w, s, &nwaves)
-    // the output layer's gradient from the chain kernel's per-wavefront partials (the layer
+    unsigned nb = 0;
+    switch ((a.in_pad >> 4) * 8 + a.depth) {
+    case 4 * 8 + 1: chain_blocks_t<4, 1>(a, np, &nb); break;
+    case 4 * 8 + 2: chain_blocks_t<4, 2>(a, np, &nb); break;
+    case 4 * 8 + 3: chain_blocks_t<4, 3>(a, np, &nb); break;
+    case 4 * 8 + 4: chain_blocks_t<4, 4>(a, np, &nb); break;
+    case 8 * 8 + 1: chain_blocks_t<8, 1>(a, np, &nb); break;
+    case 8 * 8 + 2: chain_blocks_t<8, 2>(a, np, &nb); break;
+    case 8 * 8 + 3: chain_blocks_t<8, 3>(a, np, &nb); break;
+    case 8 * 8 + 4: chain_blocks_t<8, 4>(a, np, &nb); break;
+    default: break;
+    }
+    return nb;
+}
+
+// One chain launch per grid, each writing its points' columns of the shared workspace and its
+// wavefronts' output-layer partials; then the output layer's sums and, once over all the
+// points, the layers' weight-gradient GEMMs and sums.
+hipError_t launch_nrf_backward_grids(const NrfArgs* as, int n, const NrfWork& w, hipStream_t s)
+{
+    const NrfArgs& a = as[0];
+    unsigned nb[GM_MAX_GRIDS];
+    int64_t np[GM_MAX_GRIDS], totw = 0;
+    for (int k = 0; k < n; ++k) {
+        np[k] = ((as[k].n_points + 15) / 16) * 16;
+        nb[k] = np[k] > 0 ? nrf_chain_blocks(as[k], np[k]) : 0;
+        if (np[k] > 0 && nb[k] == 0) return hipErrorInvalidValue;
+        totw += (int64_t)nb[k] * 4;
+    }
+    if (totw == 0) return hipSuccess;
+    int64_t p0 = 0, wave0 = 0;
+    for (int k = 0; k < n; ++k) {
+        if (np[k] == 0) continue;
+        NrfWork wk = w;
+        wk.p0 = p0;
+        wk.np = np[k];
+        wk.wave0 = wave0;
+        wk.nwaves_total = totw;
+        const NrfArgs& ak = as[k];
+        GM_NRF_DISPATCH(launch_chain_t, ak, wk, nb[k], s)
+        p0 += np[k];
+        wave0 += (int64_t)nb[k] * 4;
+    }
+    // the output layer's gradient from the chain kernels' per-wavefront partials (the layer
     // GEMMs below reuse the partial buffer after these sums)
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(SUM_THREADS), 0, s, w.part, nwaves, (int64_t)W,
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(SUM_THREADS), 0, s, w.part, totw, (int64_t)W,
                        a.g_w_out);
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(SUM_THREADS), 0, s, w.part + nwaves * W, nwaves,
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(SUM_THREADS), 0, s, w.part + totw * W, totw,
                        (int64_t)1, a.g_b_out);
     const int64_t nchunk = (w.P + GPB - 1) / GPB;
     for (int l = 0; l < a.depth; ++l) {
@@ -312,10 +359,10 @@ hipError_t launch_nrf_backward(const NrfArgs& a, const NrfWork& w, hipStream_t s
         else
             hipLaunchKernelGGL(k_gemm_nt_rows<4>, dim3((unsigned)nchunk), dim3(256), 0, s, w.dz[l],
                                w.a[l], w.P, w.part, rowpart);
-        const int64_t n = (int64_t)W * N;
-        const dim3 grid((unsigned)((n + 63) / 64));
+        const int64_t ne = (int64_t)W * N;
+        const dim3 grid((unsigned)((ne + 63) / 64));
         if (l > 0)
-            hipLaunchKernelGGL(k_sum_parts, grid, dim3(SUM_THREADS), 0, s, w.part, nchunk, n, dst);
+            hipLaunchKernelGGL(k_sum_parts, grid, dim3(SUM_THREADS), 0, s, w.part, nchunk, ne, dst);
         else if (N == 64)
             hipLaunchKernelGGL(k_sum_parts_in<4>, grid, dim3(SUM_THREADS), 0, s, w.part, nchunk,
                                a.n_freq, dst);
@@ -326,6 +373,12 @@ hipError_t launch_nrf_backward(const NrfArgs& a, const NrfWork& w, hipStream_t s
                            dbias);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_nrf_backward(const NrfArgs& a, const NrfWork& w, hipStream_t s)
+{
+    if (a.n_points <= 0) return hipSuccess;
+    return launch_nrf_backward_grids(&a, 1, w, s);
 }
 
 hipError_t launch_to_bf16(const float* in, uint16_t* out, int64_t n, hipStream_t s)

@@ -107,6 +107,42 @@ class NRF:
                                      self._ws.numel() * 4, api._stream()))
         return idx, scale
 
+    def backward_grids(self, grids, dls, idxs=None, n_sample: Optional[int] = None,
+                       generator: Optional[torch.Generator] = None):
+        """backward over several grids in one call (one chain pass per grid, the weight
+        gradients over all the points at once): the gradient of sum over grids k of
+        scale_k * sum_j dls[k][v_kj] r(x_{v_kj}), point lists as for backward."""
+        n = len(grids)
+        if n != len(dls) or (idxs is not None and len(idxs) != n):
+            raise ValueError("grids, dls and idxs differ in length")
+        idx_l, npts, scales = [], [], []
+        for k, (grid, dl) in enumerate(zip(grids, dls)):
+            api._need(dl, torch.float32, "dl_dr")
+            nvox = grid.n_voxels
+            idx = None if idxs is None else idxs[k]
+            if idx is None and n_sample is not None and n_sample < nvox:
+                idx = torch.randint(0, nvox, (n_sample,), device=dl.device, dtype=torch.int32,
+                                    generator=generator)
+            idx_l.append(idx)
+            npts.append(nvox if idx is None else int(idx.numel()))
+            scales.append(nvox / npts[-1] if idx is not None else 1.0)
+        s = self.struct()
+        n_pts = (ctypes.c_int64 * n)(*npts)
+        nb = ctypes.c_size_t()
+        check(load().gm_nrf_workspace_grids(ctypes.byref(s), n, n_pts, ctypes.byref(nb)))
+        if self._ws is None or self._ws.numel() * 4 < nb.value:
+            self._ws = torch.empty((nb.value + 3) // 4, dtype=torch.float32, device=dls[0].device)
+        gs = self.grads_struct()
+        structs = (_lib.GmGrid * n)(*[_lib.grid_struct(g) for g in grids])
+        ptr = ctypes.c_void_p
+        idx_p = (ptr * n)(*[ptr(0 if i is None else i.data_ptr()) for i in idx_l])
+        dl_p = (ptr * n)(*[ptr(d.data_ptr()) for d in dls])
+        sc = (ctypes.c_float * n)(*scales)
+        check(load().gm_nrf_backward_grids(ctypes.byref(s), n, structs, idx_p, n_pts, dl_p, sc,
+                                           ctypes.byref(gs), ptr(self._ws.data_ptr()),
+                                           self._ws.numel() * 4, api._stream()))
+        return idx_l, scales
+
     def adam_step(self, lr: float = 1e-4):
         self.step_no += 1
         for k in self.p:

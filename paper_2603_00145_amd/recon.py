@@ -197,8 +197,7 @@ class Reconstruction:
             self.pose_opt.step(list(G))
         if self.nrf_on:
             c.nrf.zero_grad()
-            for k, s in enumerate(self.stacks):
-                c.nrf.backward(s, self.dls[k], n_sample=c.nrf_sample)
+            c.nrf.backward_grids(self.stacks, self.dls, n_sample=c.nrf_sample)
             c.nrf.adam_step(c.lr_nrf)
         # chain rule and Adam on the four groups in one pass: the parameters change only here,
         # after everything above has read them

@@ -103,6 +103,50 @@ def test_host_validation_of_the_extension_entry_points():
     assert st == _lib.GM_ERR_INVALID_ARGUMENT
 
 
+def test_host_validation_of_the_multi_grid_field_backward():
+    """The multi-grid field backward sizes its workspace for every grid's points rounded up
+    to 16, refuses grid counts outside [1, GM_MAX_GRIDS] and returns before any launch when
+    no grid has a point."""
+    from paper_2603_00145_amd import _lib
+    lib = _lib.load()
+    P = ctypes.c_void_p
+    fake = 0x1000
+    nrf = _lib.GmNrf(16, 3, 64, 128, 0.1, 0, fake, fake, fake, fake, fake, fake)
+    npts = (ctypes.c_int64 * 3)(3001, 17, 0)
+    got, one = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.gm_nrf_workspace_grids(ctypes.byref(nrf), 3, npts, ctypes.byref(got)) == 0
+    assert lib.gm_nrf_workspace(ctypes.byref(nrf), 3008 + 32, ctypes.byref(one)) == 0
+    assert got.value == one.value
+    assert lib.gm_nrf_workspace_grids(ctypes.byref(nrf), 0, npts, ctypes.byref(got)) == \
+        _lib.GM_ERR_INVALID_ARGUMENT
+    assert lib.gm_nrf_workspace_grids(ctypes.byref(nrf), _lib.GM_MAX_GRIDS + 1, npts,
+                                      ctypes.byref(got)) == _lib.GM_ERR_INVALID_ARGUMENT
+    grids = (_lib.GmGrid * 2)()
+    for g in grids:
+        g.nx, g.ny, g.nz = 8, 8, 2
+        for i in range(3):
+            g.world_to_index[4 * i + i] = 1.0
+    idx = (P * 2)(P(fake), P(fake))
+    dl = (P * 2)(P(fake), P(fake))
+    sc = (ctypes.c_float * 2)(1.0, 1.0)
+    zero = (ctypes.c_int64 * 2)(0, 0)
+    gr = _lib.GmNrfGrads(fake, fake, fake, fake, fake, fake)
+    assert lib.gm_nrf_backward_grids(ctypes.byref(nrf), 2, grids, idx, zero, dl, sc,
+                                     ctypes.byref(gr), None, 0, None) == 0
+    # a grid with no idx must name every voxel; errors name the grid
+    idx[1] = P(0)
+    bad = (ctypes.c_int64 * 2)(5, 7)
+    assert lib.gm_nrf_backward_grids(ctypes.byref(nrf), 2, grids, idx, bad, dl, sc,
+                                     ctypes.byref(gr), None, 0, None) == \
+        _lib.GM_ERR_INVALID_ARGUMENT
+    assert b"grid 1" in lib.gm_last_error()
+    sc[0] = float("inf")
+    assert lib.gm_nrf_backward_grids(ctypes.byref(nrf), 1, grids, idx, bad, dl, sc,
+                                     ctypes.byref(gr), None, 0, None) == \
+        _lib.GM_ERR_INVALID_ARGUMENT
+    assert b"scale" in lib.gm_last_error()
+
+
 def test_index_to_world_follows_the_stated_recipe():
     """gm_index_to_world (a host call) gives, bit for bit, the adjugate recipe its header
     states, which the oracle writes out on its own (the residual field's coordinates depend on

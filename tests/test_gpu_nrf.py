@@ -119,6 +119,65 @@ def test_nrf_backward_parity_training_size(mods):
         assert err <= TOL_BF16, name
 
 
+def test_nrf_backward_over_several_grids(mods):
+    """One backward call over three grids (3001 and 17 sampled voxels, and every voxel of a
+    third grid): the oracle's gradient summed over the grids, and the three single-grid calls
+    up to the order of the FP32 sums.  Every gradient is a sum over points of per-point terms
+    that BF16 storage perturbs by a few units of 2^-8 each; with random-sign dl_dr a bias sum
+    can cancel far below its terms, so the oracle bar is taken relative to the sum of the
+    terms' magnitudes (the oracle's gradient at each point alone), the usual bound of a
+    rounded sum."""
+    _lib, api, nrf = mods
+    rng = np.random.default_rng(21)
+    grids = [inputs.stack_grid("axial", 40, 10, 1.0, *inputs.random_rigid(rng, 2, 1, 40)),
+             inputs.stack_grid("coronal", 24, 6, 1.0, *inputs.random_rigid(rng, 2, 1, 24)),
+             inputs.stack_grid("sagittal", 20, 3, 1.5, *inputs.random_rigid(rng, 2, 1, 20))]
+    net = nrf.NRF(n_freq=16, depth=3, seed=6, zero_last=False)
+    dls = [rng.normal(size=g.shape).astype(np.float32) for g in grids]
+    idxs = [rng.choice(grids[0].n_voxels, size=3001, replace=False).astype(np.int32),
+            rng.choice(grids[1].n_voxels, size=17, replace=False).astype(np.int32), None]
+    dls_d = [torch.from_numpy(d).cuda() for d in dls]
+    idx_d = [None if i is None else torch.from_numpy(i).cuda() for i in idxs]
+    net.zero_grad()
+    say("  nrf backward over 3 grids: one call")
+    _, scales = net.backward_grids(grids, dls_d, idxs=idx_d)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy().astype(np.float64) for k, v in net.g.items()}
+    net.zero_grad()
+    for g, d, i in zip(grids, dls_d, idx_d):
+        net.backward(g, d, idx=i)
+    torch.cuda.synchronize()
+    one = {k: v.cpu().numpy().astype(np.float64) for k, v in net.g.items()}
+    def flat(g):
+        return {"w_in": g["W"][0], "b_in": g["b"][0], "w_out": g["w_out"], "b_out": g["b_out"],
+                "w_hid0": g["W"][1], "b_hid0": g["b"][1], "w_hid1": g["W"][2], "b_hid1": g["b"][2]}
+
+    wts = net.weights_host()
+    ref, mag = {}, {}
+    for g, d, i, sc in zip(grids, dls, idxs, scales):
+        vox = all_voxels(g) if i is None else all_voxels(g)[i]
+        x = onrf.world_coords(vox, onrf.index_to_world(g.world_to_index))
+        dsel = (d.reshape(-1) if i is None else d.reshape(-1)[i]).astype(np.float64) * sc
+        feats = onrf.encode(x, 16, net.in_pad)
+        for k, v in flat(onrf.backward(wts, feats, dsel, net.out_scale)).items():
+            ref[k] = ref.get(k, 0.0) + np.asarray(v)
+        for p in range(len(dsel)):
+            for k, v in flat(onrf.backward(wts, feats[p:p + 1], dsel[p:p + 1], net.out_scale)).items():
+                mag[k] = mag.get(k, 0.0) + np.abs(np.asarray(v))
+    where = {"w_in": ("w_in", None), "b_in": ("b_in", None), "w_out": ("w_out", None),
+             "b_out": ("b_out", 0), "w_hid0": ("w_hid", 0), "b_hid0": ("b_hid", 0),
+             "w_hid1": ("w_hid", 1), "b_hid1": ("b_hid", 1)}
+    for name, (key, sel) in where.items():
+        a = got[key] if sel is None else got[key][sel]
+        b = one[key] if sel is None else one[key][sel]
+        e_ref = np.max(np.abs(a - ref[name])) / np.max(mag[name])
+        e_one = normwise(a, b)
+        say(f"  nrf backward 3 grids {name}: oracle {e_ref:.2e} (of the terms' magnitudes), "
+            f"normwise {normwise(a, ref[name]):.2e}; single-grid calls {e_one:.2e}")
+        assert e_ref <= TOL_BF16, name
+        assert e_one <= 1e-5, name
+
+
 def test_render_volume_with_nrf(mods):
     _lib, api, nrf = mods
     g = inputs.init_anisotropic(20, 200, np.random.default_rng(1))

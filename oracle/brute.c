@@ -125,6 +125,74 @@ void oracle_partials(int64_t nx, int64_t ny, int64_t nz, int64_t n, const double
     }
 }
 
+/* The paper's cell-neighbourhood query (Sec. 3.3.1, Eqs. 4-6) on any grid: voxel v takes
+ * Gaussian i when valid[i] != 0 and, on every world axis a, the cell of v's world position
+ * vcell[v][a] lies within radius of the cell of the Gaussian's mean gcell[i][a].  No box. */
+static int in_block(const int64_t* vc, const int64_t* gc, int64_t radius)
+{
+    for (int a = 0; a < 3; ++a) {
+        const int64_t d = vc[a] - gc[a];
+        if (d < -radius || d > radius) return 0;
+    }
+    return 1;
+}
+
+/* oracle_render with the block test in place of the box test. */
+void oracle_render_cells(int64_t nx, int64_t ny, int64_t nz, int64_t n, const double* c,
+                         const double* C, const double* amp, const int64_t* vcell,
+                         const int64_t* gcell, const uint8_t* valid, int64_t radius,
+                         double* out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t z = 0; z < nz; ++z) {
+        for (int64_t y = 0; y < ny; ++y) {
+            for (int64_t x = 0; x < nx; ++x) {
+                const int64_t v = (z * ny + y) * nx + x;
+                double acc = 0.0;
+                for (int64_t i = 0; i < n; ++i) {
+                    if (!valid[i] || !in_block(vcell + 3 * v, gcell + 3 * i, radius)) continue;
+                    acc += gauss_value(c + 3 * i, C + 9 * i, amp[i], (double)x, (double)y,
+                                       (double)z);
+                }
+                out[v] = acc;
+            }
+        }
+    }
+}
+
+/* oracle_partials over the voxels the block test gives each Gaussian. */
+void oracle_partials_cells(int64_t nx, int64_t ny, int64_t nz, int64_t n, const double* c,
+                           const double* C, const double* amp, const int64_t* vcell,
+                           const int64_t* gcell, const uint8_t* valid, int64_t radius,
+                           const double* g, double* d_amp, double* d_c, double* G_C)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        double s_amp = 0.0, s_c[3] = {0, 0, 0}, s_C[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        const double* ci = c + 3 * i;
+        const double* Ci = C + 9 * i;
+        for (int64_t z = 0; valid[i] && z < nz; ++z)
+            for (int64_t y = 0; y < ny; ++y)
+                for (int64_t x = 0; x < nx; ++x) {
+                    const int64_t v = (z * ny + y) * nx + x;
+                    if (!in_block(vcell + 3 * v, gcell + 3 * i, radius)) continue;
+                    const double gv = g[v];
+                    const double d[3] = {(double)x - ci[0], (double)y - ci[1], (double)z - ci[2]};
+                    const double e = gauss_value(ci, Ci, 1.0, (double)x, (double)y, (double)z);
+                    const double gw = gv * amp[i] * e;
+                    s_amp += gv * e;
+                    for (int a = 0; a < 3; ++a) {
+                        s_c[a] += gw * (Ci[3 * a] * d[0] + Ci[3 * a + 1] * d[1]
+                                        + Ci[3 * a + 2] * d[2]);
+                        for (int b = 0; b < 3; ++b) s_C[3 * a + b] += -0.5 * gw * d[a] * d[b];
+                    }
+                }
+        d_amp[i] = s_amp;
+        for (int a = 0; a < 3; ++a) d_c[3 * i + a] = s_c[a];
+        for (int a = 0; a < 9; ++a) G_C[9 * i + a] = s_C[a];
+    }
+}
+
 #ifdef _OPENMP
 #include <omp.h>
 #endif

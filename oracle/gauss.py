@@ -51,6 +51,10 @@ def _lib():
         lib.oracle_partials.restype = None
         lib.oracle_scatter_render.argtypes = [I, I, I, I, P, P, P, P, P, P, P]
         lib.oracle_scatter_render.restype = None
+        lib.oracle_render_cells.argtypes = [I, I, I, I, P, P, P, P, P, P, I, P]
+        lib.oracle_render_cells.restype = None
+        lib.oracle_partials_cells.argtypes = [I, I, I, I, P, P, P, P, P, P, I, P, P, P, P]
+        lib.oracle_partials_cells.restype = None
         lib.oracle_threads.restype = ctypes.c_int
         lib.oracle_threads.argtypes = []
         lib.oracle_set_threads.restype = None
@@ -200,6 +204,24 @@ def render_numpy(grid, gt, lo, hi, nonempty):
     return out.reshape(grid.shape)
 
 
+def render_cells(grid, gt, vcell, gcell, valid, radius):
+    """render() with the paper's block query (Sec. 3.3.1, Eqs. 4-6) in place of the box:
+    voxel v takes Gaussian i when valid[i] and |vcell[v] - gcell[i]| <= radius on every world
+    axis (vcell from recipe.voxel_cells, gcell from recipe.mean_cells).  Brute force over
+    every voxel and every Gaussian, ascending i."""
+    lib = _lib()
+    n = gt["c"].shape[0]
+    out = np.zeros(grid.shape, np.float64)
+    c, C, amp = _f64c(gt["c"]), _f64c(gt["C"]), _f64c(gt["amp"])
+    vc = np.ascontiguousarray(vcell, np.int64).reshape(-1, 3)
+    gc = np.ascontiguousarray(gcell, np.int64).reshape(-1, 3)
+    va = np.ascontiguousarray(valid, np.uint8)
+    assert vc.shape[0] == grid.n_voxels and gc.shape[0] == n and va.shape[0] == n
+    lib.oracle_render_cells(grid.nx, grid.ny, grid.nz, n, _ptr(c), _ptr(C), _ptr(amp), _ptr(vc),
+                            _ptr(gc), _ptr(va), int(radius), _ptr(out))
+    return out
+
+
 # ----------------------------------------------------------------------------------------
 # gradients
 # ----------------------------------------------------------------------------------------
@@ -218,6 +240,25 @@ def grid_partials(grid, gt, lo, hi, nonempty, dl_di):
     G_C = np.zeros((n, 3, 3))
     lib.oracle_partials(grid.nx, grid.ny, grid.nz, n, _ptr(c), _ptr(C), _ptr(amp), _ptr(lo),
                         _ptr(hi), _ptr(ne), _ptr(g), _ptr(d_amp), _ptr(d_c), _ptr(G_C))
+    return d_amp, d_c, G_C
+
+
+def grid_partials_cells(grid, gt, vcell, gcell, valid, radius, dl_di):
+    """grid_partials() over the voxels the block query gives each Gaussian (render_cells)."""
+    lib = _lib()
+    n = gt["c"].shape[0]
+    c, C, amp = _f64c(gt["c"]), _f64c(gt["C"]), _f64c(gt["amp"])
+    vc = np.ascontiguousarray(vcell, np.int64).reshape(-1, 3)
+    gc = np.ascontiguousarray(gcell, np.int64).reshape(-1, 3)
+    va = np.ascontiguousarray(valid, np.uint8)
+    assert vc.shape[0] == grid.n_voxels and gc.shape[0] == n and va.shape[0] == n
+    g = _f64c(dl_di)
+    d_amp = np.zeros(n)
+    d_c = np.zeros((n, 3))
+    G_C = np.zeros((n, 3, 3))
+    lib.oracle_partials_cells(grid.nx, grid.ny, grid.nz, n, _ptr(c), _ptr(C), _ptr(amp),
+                              _ptr(vc), _ptr(gc), _ptr(va), int(radius), _ptr(g), _ptr(d_amp),
+                              _ptr(d_c), _ptr(G_C))
     return d_amp, d_c, G_C
 
 

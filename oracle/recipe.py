@@ -29,7 +29,11 @@ Recipe, per (Gaussian, grid) with world->index affine [L | t] and slice sigma si
   8. Tiles touched: [lo_j // T_j, hi_j // T_j] for tile edge T_j.
 
 block_boxes() is the paper's own rule instead (Eqs. 4-6, cells of [-1, 1]^3 within a block
-radius of the Gaussian's cell), for grids whose world->index map is axis-aligned.
+radius of the Gaussian's cell), for grids whose world->index map is axis-aligned.  On any
+grid, rotated stacks included, voxel_cells() and mean_cells() give the cells the rule
+compares: a voxel's world position comes from the grid's index->world affine (the adjugate
+recipe of nrf.index_to_world), each coordinate ((m_a0 x + m_a1 y) + m_a2 z) + m_a3 in
+binary64; the voxel sets are then not boxes (gauss.render_cells tests every voxel).
 
 exp_recipe(s) is Cody-Waite range reduction with a two-part ln 2 followed by the Taylor
 series of e^r (coefficients 1/n!, n = 0..13) in Horner form, then an exact power-of-two
@@ -178,6 +182,35 @@ def block_boxes(mean, quat, log_scale, logit, grid, resolution: int, radius: int
         lo[:, j], hi[:, j] = first, last
         nonempty &= first <= last
     return lo, hi, nonempty, valid
+
+
+def voxel_cells(grid, resolution: int):
+    """Eq. 4 cell, per world axis, of every voxel's world position: [n_voxels, 3] int64 in
+    storage order ([z][y][x]).  x_a = ((M_a0 x + M_a1 y) + M_a2 z) + M_a3 (binary64) with
+    M = the grid's index->world affine by the adjugate recipe."""
+    from .nrf import index_to_world
+    M = index_to_world(grid.world_to_index)
+    z, y, x = np.meshgrid(np.arange(grid.nz, dtype=np.float64),
+                          np.arange(grid.ny, dtype=np.float64),
+                          np.arange(grid.nx, dtype=np.float64), indexing="ij")
+    x, y, z = x.reshape(-1), y.reshape(-1), z.reshape(-1)
+    out = np.empty((x.shape[0], 3), np.int64)
+    for a in range(3):
+        w = ((M[a, 0] * x + M[a, 1] * y) + M[a, 2] * z) + M[a, 3]
+        out[:, a] = cell_of(w, resolution).astype(np.int64)
+    return out
+
+
+def mean_cells(mean, resolution: int):
+    """Eq. 4 cell of each Gaussian's mean (float32 inputs in binary64), clamped to
+    [-2^30, 2^30] (no voxel of a grid of at most 32768 voxels a side within world
+    coordinates of magnitude 1000 has a cell beyond 2^30 - 2^21 at resolutions up to 2^20, so
+    the clamp changes no comparison); 0 where not finite (such Gaussians are invalid and take
+    no voxel)."""
+    mu = np.asarray(mean, np.float32).astype(np.float64)
+    with np.errstate(invalid="ignore", over="ignore"):
+        c = cell_of(np.where(np.isfinite(mu), mu, 0.0), resolution)
+    return np.clip(c, -2.0 ** 30, 2.0 ** 30).astype(np.int64)
 
 
 def box_volume(lo, hi, nonempty):

@@ -81,3 +81,76 @@ def test_rotated_grid_rejected():
     g = inputs.stack_grid("axial", 16, 4, 1.0, *inputs.random_rigid(rng, 2.0, 1.0, 16))
     with pytest.raises(ValueError):
         recipe.block_boxes(mean, quat, ls, logit, g, 8, 2)
+
+
+def cell_sets(vcell, gcell, valid, r):
+    """Per Gaussian: the voxels (storage-order indices) the block query gives it."""
+    return [np.flatnonzero((np.abs(vcell - gcell[i]) <= r).all(1)) if valid[i] else
+            np.zeros(0, np.int64) for i in range(gcell.shape[0])]
+
+
+@pytest.mark.parametrize("res,r", [(16, 1), (10, 2)])
+def test_cell_sets_are_the_boxes_on_exact_axis_aligned_grids(res, r):
+    """On unrotated grids with power-of-two sizes both routes to a voxel's world position
+    (the per-axis division of block_boxes, the index->world affine of voxel_cells) are exact,
+    so the cell test must select exactly block_boxes' boxes, and the brute-force sums over
+    those sets must equal the box sums bit for bit."""
+    from oracle import gauss
+    rng = np.random.default_rng(40 + r)
+    mean, quat, ls, logit = gaussians(40, rng, spread=1.05)
+    grids = [inputs.volume_grid(16), inputs.stack_grid("coronal", 32, 8, 1.0),
+             inputs.stack_grid("sagittal", 16, 4, 1.0)]
+    for grid in grids:
+        lo, hi, ne, valid = recipe.block_boxes(mean, quat, ls, logit, grid, res, r)
+        vcell = recipe.voxel_cells(grid, res)
+        gcell = recipe.mean_cells(mean, res)
+        sets = cell_sets(vcell, gcell, valid, r)
+        z, y, x = np.meshgrid(np.arange(grid.nz), np.arange(grid.ny), np.arange(grid.nx),
+                              indexing="ij")
+        vox = np.stack([x, y, z], -1).reshape(-1, 3)
+        for i in range(len(sets)):
+            inbox = ((vox >= lo[i]) & (vox <= hi[i])).all(1) & bool(ne[i])
+            np.testing.assert_array_equal(sets[i], np.flatnonzero(inbox), err_msg=f"{grid.name} {i}")
+        g = inputs.Gaussians(mean, quat, ls, logit)
+        (gt, _, _, _, _), = gauss.prepare(g, [grid])
+        a = gauss.render_cells(grid, gt, vcell, gcell, valid, r)
+        b = gauss.render(grid, gt, lo, hi, ne)
+        np.testing.assert_array_equal(a, b)
+        dl = rng.normal(size=grid.shape)
+        pa = gauss.grid_partials_cells(grid, gt, vcell, gcell, valid, r, dl)
+        pb = gauss.grid_partials(grid, gt, lo, hi, ne, dl)
+        for u, w in zip(pa, pb):
+            np.testing.assert_array_equal(u, w)
+
+
+def test_voxel_cells_on_a_rotated_grid_follow_the_world_position():
+    """On a rotated, shifted stack the cell of every voxel is that of its world position
+    found another way (solving L x = v - t by LU), except within 1e-9 of a cell boundary; and
+    the cell test is the world interval [2 (c - r) / res - 1, 2 (c + r + 1) / res - 1) of
+    each axis (Eqs. 4-5 solved for x)."""
+    rng = np.random.default_rng(7)
+    res, r = 12, 1
+    grid = inputs.stack_grid("axial", 24, 6, 1.0, *inputs.random_rigid(rng, 25.0, 2.0, 24))
+    vcell = recipe.voxel_cells(grid, res)
+    A = np.asarray(grid.world_to_index, np.float64)
+    z, y, x = np.meshgrid(np.arange(grid.nz), np.arange(grid.ny), np.arange(grid.nx),
+                          indexing="ij")
+    vox = np.stack([x, y, z], -1).reshape(-1, 3).astype(np.float64)
+    xw = np.linalg.solve(A[:, :3], (vox - A[:, 3]).T).T
+    u = (xw + 1.0) * res / 2.0
+    near = np.abs(u - np.rint(u)) < 1e-9
+    ok = (vcell == np.floor(u)) | near
+    assert ok.all()
+    assert (~near).mean() > 0.99
+    mean = rng.uniform(-0.9, 0.9, (30, 3)).astype(np.float32)
+    gcell = recipe.mean_cells(mean, res)
+    sets = cell_sets(vcell, gcell, np.ones(30, bool), r)
+    for i in range(30):
+        lo_w = 2.0 * (gcell[i] - r) / res - 1.0
+        hi_w = 2.0 * (gcell[i] + r + 1) / res - 1.0
+        inside = ((xw >= lo_w - 1e-9) & (xw < hi_w + 1e-9)).all(1)
+        strict = ((xw >= lo_w + 1e-9) & (xw < hi_w - 1e-9)).all(1)
+        member = np.zeros(len(vox), bool)
+        member[sets[i]] = True
+        assert (member <= inside).all() and (strict <= member).all()
+        assert member.any()

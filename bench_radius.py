@@ -3,10 +3,11 @@ with the cell-neighbourhood query (Eqs. 4-6) at block radii 3..7 (cells = the Ga
 against the 3-sigma box, reporting final PSNR, milliseconds per iteration (HIP events) and the
 contributing (Gaussian, voxel) pairs each query evaluates.
 
-    python bench_radius.py [--iters 150] [--lattice 32]
+    python bench_radius.py [--iters 150] [--lattice 32] [--workload c64] [--radii 3,4,5,6,7]
 
 One JSON line per configuration.  The 64^3 workload's stacks are axis-aligned (no rigid
-offsets), which the block query needs.
+offsets): the query's voxel sets are boxes.  The 128^3 workload's stacks are rigidly rotated,
+where every voxel of a Gaussian's bounding box is tested against its cell block.
 """
 from __future__ import annotations
 
@@ -39,7 +40,8 @@ def run(rule, radius, lattice, iters, w, data):
     e1.record(s)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / (iters - 5)
-    return {"rule": rule, "block_radius": radius, "lattice": lattice, "iters": iters,
+    return {"workload": w.name, "rule": rule, "block_radius": radius, "lattice": lattice,
+            "iters": iters,
             "psnr_start": start, "psnr": r.psnr(), "ms_per_iter": ms,
             "pairs_per_iter": sum(r.bins.box_pairs_host)}
 
@@ -48,12 +50,14 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--iters", type=int, default=150)
     ap.add_argument("--lattice", type=int, default=32)
+    ap.add_argument("--workload", default="c64")
+    ap.add_argument("--radii", default="3,4,5,6,7")
     args = ap.parse_args()
     api.load()
-    w = inputs.workload("c64", device="cuda")
+    w = inputs.workload(args.workload, device="cuda")
     data = [torch.as_tensor(d) for d in w.stack_data]
     rows = [run("3-sigma box", 0, args.lattice, args.iters, w, data)]
-    for radius in range(3, 8):
+    for radius in (int(x) for x in args.radii.split(",")):
         rows.append(run("block", radius, args.lattice, args.iters, w, data))
     for row in rows:
         print(json.dumps(row))

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define GM_ABI_VERSION 4
+#define GM_ABI_VERSION 5
 #define GM_MAX_GRIDS 8
 #define GM_RECORD_FLOATS 16       /* floats per (grid, Gaussian) record                */
 #define GM_GRID_GRAD_FLOATS 10    /* floats per (grid, Gaussian) backward partial      */
@@ -94,10 +94,15 @@ typedef struct gm_bin_opts {
     /* > 0: the paper's own query (Sec. 3.3.1, Eqs. 4-6) instead of the sigma box: [-1, 1]^3
      * is cut into cell_resolution^3 cells (Eq. 4, cell = floor((x + 1) res / 2) per axis, in
      * binary64) and voxel v takes Gaussian i when on every world axis the cell of v's world
-     * position lies within block_radius of the cell of mu_i.  A voxel's world coordinate along
-     * world axis a is (v_j - t_j) / L[j][a] for the index axis j mapped to it, so every grid
-     * must be axis-aligned (each row of L one non-zero entry, in distinct columns; rotated
-     * stacks are GM_ERR_UNSUPPORTED) and the voxels form a box.  0: the sigma box. */
+     * position lies within block_radius of the cell of mu_i.  On an axis-aligned grid (each row
+     * of L one non-zero entry, in distinct columns) a voxel's world coordinate along world axis
+     * a is (v_j - t_j) / L[j][a] for the index axis j mapped to it, and the voxels form a box.
+     * On any other grid (rotated stacks) it is ((m_a0 x + m_a1 y) + m_a2 z) + m_a3 with m the
+     * index->world affine of gm_index_to_world (binary64, that association), the voxels do not
+     * form a box: the record carries a box that contains them (from the block's world box,
+     * widened by 1e-9 world and 1e-6 index units) and every kernel tests each voxel of it, and
+     * the pair counts (box_volume, box_pairs) count that box.  The means' cells are clamped to
+     * [-2^30, 2^30].  0: the sigma box. */
     int32_t block_radius;
     int32_t cell_resolution;
 } gm_bin_opts;
@@ -116,7 +121,9 @@ typedef struct gm_bin_opts {
  *               Gaussian) whose tile holds the box's lower corner (its "home" tile)
  *   grid_grads  [n_grids][n_gauss][10] float: written by gm_backward / gm_grid_partials
  *               (grid-frame partials d amp, d c(3), d K(6))
- *   scratch     scratch_bytes of device memory for sorting                              */
+ *   scratch     scratch_bytes of device memory for sorting; with the block query it also
+ *               holds each Gaussian's cell, which the renders and the backward read on
+ *               rotated grids until the next gm_bin                                       */
 typedef struct gm_bins {
     int32_t n_grids;
     int32_t reserved;
@@ -141,6 +148,8 @@ typedef struct gm_bins {
     int64_t list_start[GM_MAX_GRIDS + 1]; /* pair_gauss entries of grid k are
                                             [list_start[k], list_start[k + 1])           */
     double cutoff_sigma;
+    int32_t block_radius;                /* the gm_bin_opts of the last gm_bin (0: sigma box) */
+    int32_t cell_resolution;
 } gm_bins;
 
 /* Library identity. */

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgm.so")
 
 GM_MAX_GRIDS = 8
-ABI_VERSION = 4          # struct layouts of include/gm.h this binding mirrors
+ABI_VERSION = 5          # struct layouts of include/gm.h this binding mirrors
 GM_RECORD_FLOATS = 16
 GM_GRID_GRAD_FLOATS = 10
 GM_REDUCE_WORKSPACE_BYTES = 16384
@@ -63,7 +63,8 @@ class GmBins(ctypes.Structure):
                 ("tile_base", ctypes.c_int64 * (GM_MAX_GRIDS + 1)),
                 ("n_pairs", ctypes.c_int64), ("box_pairs", ctypes.c_int64 * GM_MAX_GRIDS),
                 ("list_start", ctypes.c_int64 * (GM_MAX_GRIDS + 1)),
-                ("cutoff_sigma", ctypes.c_double)]
+                ("cutoff_sigma", ctypes.c_double), ("block_radius", ctypes.c_int32),
+                ("cell_resolution", ctypes.c_int32)]
 
 
 class GmNrfGrads(ctypes.Structure):

@@ -63,13 +63,16 @@ def _compile(src: str) -> str:
     return obj
 
 
-# kernels with counter summaries (profiles/<kernel>_traffic_*.md) and their source files
-DIGESTED = {"k_partials": "backward.hip", "k_render": "render.hip"}
+# kernels with counter summaries (profiles/<kernel>_traffic_*.md): source file and the
+# kernel's symbol as it appears mangled (the instantiation the benchmark runs)
+DIGESTED = {"k_partials": ("backward.hip", "10k_partialsILb0E"),
+            "k_render": ("render.hip", "8k_renderE")}
 DIGESTS = os.path.join(HERE, "kernel_digests.json")
 
 
 def _kernel_asm_digest(src: str, kernels) -> dict:
-    """SHA-256 of each kernel's gfx950 assembly (its function body, labels included)."""
+    """SHA-256 of each kernel's gfx950 assembly (its function body, labels included);
+    kernels maps a name to its mangled symbol fragment."""
     flags = _flags(src)
     out = os.path.join(BUILD, os.path.splitext(src)[0] + ".s")
     cmd = [hipcc()] + flags + ["--cuda-device-only", "-S", os.path.join(CSRC, src), "-o", out]
@@ -79,11 +82,11 @@ def _kernel_asm_digest(src: str, kernels) -> dict:
     with open(out) as f:
         lines = f.read().splitlines()
     res = {}
-    for k in kernels:
+    for k, tag in kernels.items():
         body, inside = [], False
         for ln in lines:
             head = ln.split(";")[0].strip()
-            if not inside and head.endswith(":") and k in head and not head.startswith("."):
+            if not inside and head.endswith(":") and tag in head and not head.startswith("."):
                 inside = True
             if inside:
                 body.append(ln)
@@ -105,8 +108,8 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
     by_src = {}
-    for k, src in DIGESTED.items():
-        by_src.setdefault(src, []).append(k)
+    for k, (src, tag) in DIGESTED.items():
+        by_src.setdefault(src, {})[k] = tag
     with cf.ThreadPoolExecutor(max_workers=len(by_src)) as ex:
         parts = list(ex.map(lambda kv: _kernel_asm_digest(*kv), by_src.items()))
     digests = {k: v for d in parts for k, v in d.items()}

@@ -10,7 +10,10 @@
 // owns one (x, z) column of the box at a time and walks it along y, summing g E, g E dy and
 // g E dy^2; the column's share of the ten moments follows from those three sums and its
 // (dx, dz).  The moments are reduced across the eight lanes with DPP and turned into the
-// partials once per (grid, Gaussian).  No global atomics are needed.
+// partials once per (grid, Gaussian).  No global atomics are needed.  With the paper's block
+// query on a rotated grid (k_partials<true>) every Gaussian of that grid takes the global-memory
+// path and each voxel of its box is also tested against its cell block (Eqs. 4-6): the sums
+// run over the voxels that pass.
 //
 // K8 (chain rule, FP64): thread per Gaussian.  The partials of every grid are pulled back
 // through c = L mu + t, C = Sigma_g^-1, amp = alpha sqrt(det Sigma_idx / det Sigma_g),
@@ -130,18 +133,22 @@ __device__ __forceinline__ Rec load_record(const BackwardArgs& a, int gi, uint32
     return r;
 }
 
-template <int G, bool FROM_LDS>
+template <int G, bool FROM_LDS, bool MASK = false>
 __device__ __forceinline__ void group_of_gaussians(const BackwardArgs& a, int kk, uint32_t mine,
                                                    bool gvalid, const Rec& rec,
                                                    const float* __restrict__ region,
-                                                   int t0x, int t0y, int t0z)
+                                                   int t0x, int t0y, int t0z, bool mk = false)
 {
+    static_assert(!(MASK && FROM_LDS), "masked grids read dL/dI from global memory");
     const int ql = threadIdx.x & (G - 1);
     const int gi = a.grid_index[kk];
     const int nx = a.nx[kk], ny = a.ny[kk];
     const float* __restrict__ g = a.dl_di[kk];
     const int64_t gid = min((int64_t)(mine & GM_ID_MASK), a.n - 1);
     const float4 r0 = rec.r0, r1 = rec.r1, r2 = rec.r2, r3 = rec.r3;
+    // masked grid: the Gaussian's cell and the grid's index -> world affine
+    const int4 cm = (MASK && mk) ? a.bq.cells[gid] : make_int4(0, 0, 0, 0);
+    const double* mw = a.m[kk];
     const int lox = __float_as_int(r2.z), loy = __float_as_int(r2.w), loz = __float_as_int(r3.x);
     const int hix = __float_as_int(r3.y), hiy = __float_as_int(r3.z), hiz = __float_as_int(r3.w);
     // a listed Gaussian's box is never empty; an invalid lane group (past the round's end)
@@ -227,6 +234,8 @@ __device__ __forceinline__ void group_of_gaussians(const BackwardArgs& a, int kk
                 }
             }
         } else {
+            // masked grid: the column's voxel (vx, loy + k, vz)
+            const int vx = lox + (int)xh, vz = loz + (int)zf;
             float gv[8];
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
@@ -239,6 +248,13 @@ __device__ __forceinline__ void group_of_gaussians(const BackwardArgs& a, int kk
                         gv[k] = k < ncol ? t : 0.0f;
                     }
                 }
+            }
+            if (MASK && mk) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (k < max_wy &&
+                        !voxel_in_block(mw, a.bq.res, a.bq.radius, vx, loy + k, vz, cm))
+                        gv[k] = 0.0f;
             }
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
@@ -257,7 +273,11 @@ __device__ __forceinline__ void group_of_gaussians(const BackwardArgs& a, int kk
         for (int k = 8; k < max_wy; ++k) {  // boxes longer than 8 voxels in y
             const int kc = min(k, ncol - 1);
             const float t = FROM_LDS ? region[off + kc * RX] : g[(size_t)kc * ystride + off];
-            const float gk = k < ncol ? t : 0.0f;
+            float gk = k < ncol ? t : 0.0f;
+            if (MASK && mk &&
+                !voxel_in_block(mw, a.bq.res, a.bq.radius, lox + (int)xh, loy + k, loz + (int)zf,
+                                cm))
+                gk = 0.0f;
             const float fk = (float)k;
             const float ge = gk * __builtin_amdgcn_exp2f(A + fk * (B + fk * kyy));
             s0 += ge;
@@ -349,6 +369,7 @@ __device__ __forceinline__ void scan_keys(int* hist, int lane)
 // partials come from its own eight lanes only and do not depend on which others share its
 // round, so the order the atomics give within a key does not change any result bit.
 // Gaussians with an empty box are in no list; gm_bin wrote their zeros.
+template <bool MASK>
 __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
 {
     __shared__ float region[RZ * RZS];
@@ -370,13 +391,16 @@ __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
     const float* __restrict__ g = a.dl_di[kk];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int gi = a.grid_index[kk];
+    const bool mk = MASK && a.masked[kk];   // block query on a rotated grid
 
     // list entry -> its sort key (-1: not a home entry) and the z planes its box reaches in
-    // the region (0 when it reaches past the region)
+    // the region (0 when it reaches past the region; always on a masked grid, whose voxels
+    // are tested in the global-memory path)
     auto classify = [&](int entry, uint32_t& v, int& zreach) -> int {
         zreach = 0;
         v = entry < e1 ? a.pair_gauss[entry] : 0u;
         if (entry >= e1 || !(v & GM_HOME_BIT)) return -1;
+        if (mk) return NKEY - 1;
         const int4* rc = reinterpret_cast<const int4*>(
             a.records + ((size_t)gi * a.n + min((int64_t)(v & GM_ID_MASK), a.n - 1)) * 16);
         const int4 r2 = rc[2], r3 = rc[3];     // (kxz, kyz, lox, loy), (loz, hix, hiy, hiz)
@@ -437,7 +461,8 @@ __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
             const bool valid = ix < n_all;
             const uint32_t mine = valid ? order[ix] : 0u;
             const Rec rec = load_record(a, gi, mine);
-            group_of_gaussians<BWD_G, false>(a, kk, mine, valid, rec, region, t0x, t0y, t0z);
+            group_of_gaussians<BWD_G, false, MASK>(a, kk, mine, valid, rec, region, t0x, t0y,
+                                                   t0z, mk);
         }
     };
 
@@ -771,7 +796,12 @@ hipError_t launch_backward_partials(const BackwardArgs& a, hipStream_t s)
     if (a.n == 0 || a.n_ids == 0) return hipSuccess;
     const int32_t blocks = a.block_start[a.n_ids];   // one per tile of the listed grids
     if (blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_partials, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    bool masked = false;
+    for (int k = 0; k < a.n_ids; ++k) masked = masked || a.masked[k];
+    if (masked)
+        hipLaunchKernelGGL(k_partials<true>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_partials<false>, dim3((unsigned)blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

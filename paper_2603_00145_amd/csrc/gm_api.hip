@@ -116,6 +116,7 @@ struct BinScratch {
     void* radix_ws;
     BinReport* report;
     uint32_t* tile_box;  // [n_grids * n][3]
+    int4* cells;         // [n]: the Gaussians' cells (block query)
     size_t bytes;
 };
 
@@ -134,6 +135,7 @@ BinScratch scratch_layout(char* base, int64_t n, int32_t n_grids, int64_t cap)
     s.radix_ws = take(radix_workspace_bytes(c));
     s.report = reinterpret_cast<BinReport*>(take(sizeof(BinReport)));
     s.tile_box = reinterpret_cast<uint32_t*>(take((size_t)(m > 0 ? m : 1) * 12));
+    s.cells = reinterpret_cast<int4*>(take((size_t)(n > 0 ? n : 1) * 16));
     s.bytes = o;
     return s;
 }
@@ -152,6 +154,17 @@ gm_status check_gauss(const gm_gaussians* g)
     return GM_OK;
 }
 
+// The block query's state in the bins (the cells live in the binning scratch)
+BlockQuery block_query(const gm_bins* b)
+{
+    BlockQuery q;
+    q.cells = scratch_layout(reinterpret_cast<char*>(b->scratch), b->n_gauss, b->n_grids,
+                             b->capacity_pairs).cells;
+    q.res = (double)b->cell_resolution;
+    q.radius = b->block_radius;
+    return q;
+}
+
 gm_status check_bins(const gm_bins* b, bool need_lists)
 {
     if (!b) return fail(GM_ERR_INVALID_ARGUMENT, "bins is NULL");
@@ -163,6 +176,12 @@ gm_status check_bins(const gm_bins* b, bool need_lists)
                     "bins hold no valid tile lists (last gm_bin needed %lld pairs, capacity %lld)",
                     (long long)b->n_pairs, (long long)b->capacity_pairs);
     return GM_OK;
+}
+
+// The block query on a grid that is not axis-aligned: its kernels test every voxel
+bool grid_masked(const gm_bins* b, int id)
+{
+    return b->block_radius > 0 && make_const(b->grids[id], 0).waxis[0] < 0;
 }
 
 gm_status check_ids(const gm_bins* b, const int32_t* ids, int32_t n_ids)
@@ -392,12 +411,6 @@ gm_status gm_bin(const gm_gaussians* g, const gm_grid* grids, int32_t n_grids,
         return fail(GM_ERR_INVALID_ARGUMENT, "scratch_bytes %zu < required %zu",
                     bins->scratch_bytes, need_scratch);
 
-    if (block_radius > 0)
-        for (int k = 0; k < n_grids; ++k)
-            if (make_const(grids[k], 0).waxis[0] < 0)
-                return fail(GM_ERR_UNSUPPORTED, "the block query needs axis-aligned grids (grid %d "
-                                                "is rotated)", k);
-
     // host fields
     int64_t base = 0;
     PreprocessArgs pa;
@@ -410,6 +423,8 @@ gm_status gm_bin(const gm_gaussians* g, const gm_grid* grids, int32_t n_grids,
     }
     bins->tile_base[n_grids] = base;
     bins->cutoff_sigma = cutoff;
+    bins->block_radius = block_radius;
+    bins->cell_resolution = block_radius > 0 ? cell_res : 0;
     bins->n_pairs = -1;
 
     const int64_t n = g->n;
@@ -424,6 +439,7 @@ gm_status gm_bin(const gm_gaussians* g, const gm_grid* grids, int32_t n_grids,
     pa.cutoff = cutoff;
     pa.block_radius = block_radius;
     pa.cell_res = cell_res;
+    pa.cells = sc.cells;
     pa.mean = g->mean;
     pa.quat = g->quat;
     pa.log_scale = g->log_scale;
@@ -580,8 +596,13 @@ static gm_status render_impl(const gm_bins* bins, const int32_t* ids, int32_t n_
         r.first_block = (int32_t)blocks;
         r.bin_tile_base = bins->tile_base[ids[k]];
         r.out = outs ? outs[k] : nullptr;
-        if (nrf && !index_to_world(g, r.index_to_world))
+        r.masked = grid_masked(bins, ids[k]) ? 1 : 0;
+        if ((nrf || r.masked) && !index_to_world(g, r.index_to_world))
             return fail(GM_ERR_INVALID_ARGUMENT, "grid %d: singular affine", ids[k]);
+        if (r.masked && !ra.bq.cells) {
+            REQ_PTR(bins->scratch, "bins->scratch");
+            ra.bq = block_query(bins);
+        }
         blocks += grid_tiles(g);
     }
     if (blocks >= 0x7fffffffLL) return fail(GM_ERR_INVALID_ARGUMENT, "too many tiles");
@@ -991,6 +1012,15 @@ gm_status backward_impl(const gm_gaussians* g, const gm_bins* bins, const int32_
         ba.nx[k] = gr.nx;
         ba.ny[k] = gr.ny;
         ba.nz[k] = gr.nz;
+        if (partials && grid_masked(bins, grid_ids[k])) {
+            ba.masked[k] = 1;
+            if (!index_to_world(gr, ba.m[k]))
+                return fail(GM_ERR_INVALID_ARGUMENT, "grid %d: singular affine", grid_ids[k]);
+            if (!ba.bq.cells) {
+                REQ_PTR(bins->scratch, "bins->scratch");
+                ba.bq = block_query(bins);
+            }
+        }
         ca.grid_index[k] = grid_ids[k];
         ca.g[k] = make_const(gr, bins->tile_base[grid_ids[k]]);
     }

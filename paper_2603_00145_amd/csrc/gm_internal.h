@@ -30,6 +30,36 @@ struct GridConst {
     int32_t waxis[3];        // world axis of each index axis (axis-aligned grids), else -1
 };
 
+// The paper's cell-neighbourhood query (Sec. 3.3.1, Eqs. 4-6) on a grid that is not
+// axis-aligned: a voxel takes a Gaussian when, on every world axis, the Eq. 4 cell of the
+// voxel's world position lies within the block radius of the cell of the Gaussian's mean.
+// Such a voxel set is not a box, so the binning gives each Gaussian a box that contains it and
+// the kernels test every voxel of that box.
+struct BlockQuery {
+    const int4* cells;   // [n]: each Gaussian's cell (x, y, z, 0), clamped to [-2^30, 2^30]
+    double res;          // cells per axis of [-1, 1]
+    int32_t radius;      // block radius (> 0)
+};
+
+// The voxel's world position ((m_a0 x + m_a1 y) + m_a2 z) + m_a3 per world axis a (m the
+// grid's index -> world affine, row-major 3x4) and its cell floor(((w + 1) res) / 2), in
+// binary64 without contraction; true when every axis is within radius of cm.
+__device__ __forceinline__ bool voxel_in_block(const double* m, double res, int radius, int x,
+                                               int y, int z, int4 cm)
+{
+#pragma clang fp contract(off)
+    const double xd = (double)x, yd = (double)y, zd = (double)z, r = (double)radius;
+    const double c[3] = {(double)cm.x, (double)cm.y, (double)cm.z};
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double w = ((m[4 * a] * xd + m[4 * a + 1] * yd) + m[4 * a + 2] * zd) + m[4 * a + 3];
+        const double cell = floor(((w + 1.0) * res) / 2.0);
+        in = in && cell >= c[a] - r && cell <= c[a] + r;
+    }
+    return in;
+}
+
 // ---- launchers (one per kernel family) --------------------------------------------------
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
 
@@ -61,6 +91,7 @@ struct PreprocessArgs {
     float* grid_grads;       // [n_grids][n][10] or NULL: zeroed for empty boxes
     uint32_t* tile_box;      // [n_grids][n][3]: the box's tile range (lo, hi) as 16-bit
                              // fields x | y << 16, z | X << 16, Y | Z << 16 (lo > hi: empty)
+    int4* cells;             // block query: each Gaussian's cell (written once per Gaussian)
     GridConst g[GM_MAX_GRIDS];
 };
 hipError_t launch_preprocess(const PreprocessArgs& a, hipStream_t s);
@@ -100,7 +131,8 @@ struct RenderGrid {
     float* out;              // rendered values, or NULL (loss mode only)
     const float* target;     // loss mode: the stack's data
     float* dl;               // loss mode: dL/dI of the smooth-L1 term
-    double index_to_world[12]; // with a residual field: the grid's index -> world affine
+    double index_to_world[12]; // with a residual field or a masked grid: index -> world
+    int32_t masked;          // the block query on a rotated grid: test every voxel
 };
 struct RenderArgs {
     int32_t n_render;
@@ -112,6 +144,7 @@ struct RenderArgs {
     double* loss_part;       // loss mode (non-NULL): per-block smooth-L1 sums [total_blocks]
     float* loss;             // loss mode: the mean, written by the finishing kernel
     double inv_n;            // loss mode: 1 / voxels of the listed grids
+    BlockQuery bq;           // read on masked grids
     RenderGrid rg[GM_MAX_GRIDS];
 };
 hipError_t launch_render(const RenderArgs& a, hipStream_t s);
@@ -133,6 +166,9 @@ struct BackwardArgs {
     int64_t tile_base[GM_MAX_GRIDS];    // global id of each listed grid's first tile
     int32_t ntx[GM_MAX_GRIDS], nty[GM_MAX_GRIDS];
     int32_t block_start[GM_MAX_GRIDS + 1];  // first block (= tile) of each listed grid
+    BlockQuery bq;                      // read on masked grids
+    int32_t masked[GM_MAX_GRIDS];       // the block query on a rotated grid
+    double m[GM_MAX_GRIDS][12];         // masked grids: index -> world affine
 };
 hipError_t launch_backward_partials(const BackwardArgs& a, hipStream_t s);
 

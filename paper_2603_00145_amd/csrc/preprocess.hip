@@ -11,7 +11,8 @@
 //   Sigma_g = Sigma_idx + sig^2 e_z e_z^T,  C = Sigma_g^-1,
 //   amp = alpha sqrt(det Sigma_idx / det Sigma_g)       (Gaussian (x) normalised profile).
 // The box is +-cutoff marginal standard deviations sqrt((Sigma_g)_jj) around c, or, with a
-// block radius, the paper's cell-neighbourhood query (Eqs. 4-6) on axis-aligned grids.
+// block radius, the paper's cell-neighbourhood query (Eqs. 4-6): exactly its voxels on
+// axis-aligned grids, a box holding them on rotated grids (whose voxels the kernels test).
 #include "gm_internal.h"
 
 namespace {
@@ -115,6 +116,17 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a)
                 e[1] > 0.0 && e[2] > 0.0;
         if (!valid) atomicOr(a.flags, 1u);
         const double alpha = 1.0 / (1.0 + exp(-lg));
+        // block query: the mean's cell on each world axis (Eq. 4), clamped to [-2^30, 2^30],
+        // kept for the kernels that test voxels of rotated grids
+        double cmw[3] = {0.0, 0.0, 0.0};
+        if (a.block_radius > 0) {
+            const double res = (double)a.cell_res, CC = 1073741824.0;
+            const double mus[3] = {mu0, mu1, mu2};
+#pragma unroll
+            for (int w_ = 0; w_ < 3; ++w_)
+                cmw[w_] = valid ? fmin(fmax(cell_of(mus[w_], res), -CC), CC) : 0.0;
+            a.cells[i] = make_int4((int)cmw[0], (int)cmw[1], (int)cmw[2], 0);
+        }
 
         for (int k = 0; k < a.n_grids; ++k) {
             const GridConst& G = a.g[k];
@@ -143,7 +155,41 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a)
             int lo[3], hi[3];
             bool nonempty = valid;
             const double CL = 1073741824.0;
-            if (a.block_radius > 0) {
+            if (a.block_radius > 0 && G.waxis[0] < 0) {
+                // rotated grid: the block's world box (Eq. 5 solved for x), widened by 1e-9
+                // (relative), mapped to index space (the bounds of a linear map over a box),
+                // widened by 1e-6 (relative) and rounded outwards.  It holds every voxel whose
+                // cell test passes; the kernels test each voxel of it.
+                const double res = (double)a.cell_res, r = (double)a.block_radius;
+                double x0[3], x1[3];
+#pragma unroll
+                for (int w_ = 0; w_ < 3; ++w_) {
+                    const double u0 = ((cmw[w_] - r) * 2.0) / res - 1.0;
+                    const double u1 = ((cmw[w_] + r + 1.0) * 2.0) / res - 1.0;
+                    x0[w_] = u0 - 1e-9 * (1.0 + fabs(u0));
+                    x1[w_] = u1 + 1e-9 * (1.0 + fabs(u1));
+                }
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    double vmin = G.t[j], vmax = G.t[j];
+#pragma unroll
+                    for (int w_ = 0; w_ < 3; ++w_) {
+                        const double p = G.L[3 * j + w_] * x0[w_], q = G.L[3 * j + w_] * x1[w_];
+                        vmin = vmin + fmin(p, q);
+                        vmax = vmax + fmax(p, q);
+                    }
+                    double l = ceil(vmin - 1e-6 * (1.0 + fabs(vmin)));
+                    double h = floor(vmax + 1e-6 * (1.0 + fabs(vmax)));
+                    l = (l != l) ? CL : fmin(fmax(l, -CL), CL);
+                    h = (h != h) ? -CL : fmin(fmax(h, -CL), CL);
+                    int li = (int)l, hj = (int)h;
+                    li = li < 0 ? 0 : li;
+                    hj = hj > dims[j] - 1 ? dims[j] - 1 : hj;
+                    lo[j] = li;
+                    hi[j] = hj;
+                    nonempty = nonempty && (li <= hj);
+                }
+            } else if (a.block_radius > 0) {
                 const double mus[3] = {mu0, mu1, mu2};
                 const double res = (double)a.cell_res, r = (double)a.block_radius;
 #pragma unroll

@@ -11,6 +11,10 @@
 // at most 64 columns share the wave (the first piece's columns on the low lanes); the first
 // piece's lanes add into the tile before the second's, so every voxel's sum is still formed
 // in ascending Gaussian order and the result is the same on every run.
+//
+// With the paper's block query on a rotated grid (k_render_block, and k_render_field's MASK
+// form) a Gaussian's voxels are not its box: each evaluated voxel of the box is also tested
+// against the Gaussian's cell block (Eqs. 4-6) and gets zero when it fails.
 #include "nrf_core.h"
 
 namespace {
@@ -63,6 +67,33 @@ __device__ __forceinline__ void eval_column(const Piece& p, float fh, float (&w)
     }
 }
 
+// The block query on a masked grid (Sec. 3.3.1, Eqs. 4-6): per piece of the batch, its first
+// voxel in grid coordinates and its Gaussian's cell; per tile, the grid's index -> world affine
+// and the query's resolution and radius.
+struct PieceCell {
+    int ix0, iy0, iz0, pad;
+    int4 cm;
+};
+struct MaskCtx {
+    const PieceCell* pcc;   // the wavefront's batch
+    const double* m;
+    double res;
+    int radius;
+};
+
+// w[k] = 0 for the voxels of column fh of piece p (as eval_column maps it) outside the block
+template <int KM>
+__device__ __forceinline__ void mask_column(const Piece& p, const PieceCell& q, const MaskCtx& mc,
+                                            float fh, float (&w)[KM])
+{
+    const float yf = floorf(fh * p.inv_wx);
+    const float xh = fmaf(-yf, p.wxf, fh);        // x + 1/2 within the piece
+    const int x = q.ix0 + (int)xh, y = q.iy0 + (int)yf;
+#pragma unroll
+    for (int k = 0; k < KM; ++k)
+        if (!voxel_in_block(mc.m, mc.res, mc.radius, x, y, q.iz0 + k, q.cm)) w[k] = 0.0f;
+}
+
 // acc[column voxel at z-step k] += w[k] for k < KZ (the piece's exact z extent; KZ <= the
 // length of w).  The z-steps are distinct voxels, so all reads are issued before the writes.
 template <int KZ, int KM>
@@ -77,8 +108,10 @@ __device__ __forceinline__ void add_column(float* acc, int idx, const float (&w)
 }
 
 // One piece on the whole wave: columns f0 + lane, KM z-steps each (lane_fh = lane + 1/2).
-template <int KM>
-__device__ __forceinline__ void single_piece(const Piece& p, float* acc, int F, float lane_fh)
+// MASK: mc (non-null on a masked grid) and the piece's batch slot jq.
+template <int KM, bool MASK>
+__device__ __forceinline__ void single_piece(const Piece& p, float* acc, int F, float lane_fh,
+                                             const MaskCtx* mc, int jq)
 {
     float fh = lane_fh;
 #pragma unroll 1
@@ -86,6 +119,7 @@ __device__ __forceinline__ void single_piece(const Piece& p, float* acc, int F, 
         float w[KM];
         int idx;
         eval_column<KM>(p, fh, w, idx);
+        if (MASK && mc) mask_column<KM>(p, mc->pcc[jq], *mc, fh, w);
         if (fh < p.Ff) add_column<KM, KM>(acc, idx, w);
         fh += 64.0f;
     }
@@ -95,9 +129,9 @@ __device__ __forceinline__ void single_piece(const Piece& p, float* acc, int F, 
 // and ZB, evaluated over the larger of the two.  The first piece's read-add-writes complete
 // before the second piece's are issued.  Both extents are template parameters, so a pass
 // dispatches once on the pair and its two add phases carry no branches of their own.
-template <int ZA, int ZB>
+template <int ZA, int ZB, bool MASK>
 __device__ __forceinline__ void paired_pieces(const Piece& p, float* acc, bool act, bool first,
-                                              float fh)
+                                              float fh, const MaskCtx* mc, int jq)
 {
     constexpr int KM = ZA > ZB ? ZA : ZB;
     // every lane evaluates (a lane past its piece's footprint computes values it never
@@ -105,6 +139,7 @@ __device__ __forceinline__ void paired_pieces(const Piece& p, float* acc, bool a
     float w[KM];
     int idx;
     eval_column<KM>(p, fh, w, idx);
+    if (MASK && mc) mask_column<KM>(p, mc->pcc[jq], *mc, fh, w);
     lds_order();
     if (act && first) add_column<ZA, KM>(acc, idx, w);
     lds_order();
@@ -113,18 +148,20 @@ __device__ __forceinline__ void paired_pieces(const Piece& p, float* acc, bool a
 }
 
 // paired_pieces for uniform z extents wza, wzb in [1, GM_TZ]
+template <bool MASK>
 __device__ __forceinline__ void paired_pieces_kz(const Piece& p, float* acc, bool act,
-                                                 bool first, float fh, int wza, int wzb)
+                                                 bool first, float fh, int wza, int wzb,
+                                                 const MaskCtx* mc, int jq)
 {
     static_assert(GM_TZ == 4, "z extents 1..4 are dispatched below");
 #define GM_PAIR_CASE(A, B) \
-    case (A - 1) * 4 + (B - 1): paired_pieces<A, B>(p, acc, act, first, fh); break;
+    case (A - 1) * 4 + (B - 1): paired_pieces<A, B, MASK>(p, acc, act, first, fh, mc, jq); break;
     switch ((wza - 1) * 4 + (wzb - 1)) {
     GM_PAIR_CASE(1, 1) GM_PAIR_CASE(1, 2) GM_PAIR_CASE(1, 3) GM_PAIR_CASE(1, 4)
     GM_PAIR_CASE(2, 1) GM_PAIR_CASE(2, 2) GM_PAIR_CASE(2, 3) GM_PAIR_CASE(2, 4)
     GM_PAIR_CASE(3, 1) GM_PAIR_CASE(3, 2) GM_PAIR_CASE(3, 3) GM_PAIR_CASE(3, 4)
     GM_PAIR_CASE(4, 1) GM_PAIR_CASE(4, 2) GM_PAIR_CASE(4, 3)
-    default: paired_pieces<4, 4>(p, acc, act, first, fh); break;
+    default: paired_pieces<4, 4, MASK>(p, acc, act, first, fh, mc, jq); break;
     }
 #undef GM_PAIR_CASE
 }
@@ -191,10 +228,11 @@ __device__ __forceinline__ void load_targets(const TilePos& P, int lane, float (
 }
 
 // acc (the tile's voxels, LDS) = the sum over the tile's list of Gaussians, in list order.
-// Ends with a tile_sync, so every lane may read any voxel afterwards.
-template <bool BLOCK>
+// Ends with a tile_sync, so every lane may read any voxel afterwards.  MASK: on a masked grid
+// every voxel is also tested against its Gaussian's cell block (pcc: the batch's PieceCells).
+template <bool BLOCK, bool MASK>
 __device__ __forceinline__ void accumulate_tile(const RenderArgs& a, const TilePos& P, float* acc,
-                                                Piece* pc, int lane)
+                                                Piece* pc, int lane, PieceCell* pcc)
 {
     const RenderGrid& G = *P.G;
     const int t0x = P.t0x, t0y = P.t0y, t0z = P.t0z;
@@ -228,14 +266,23 @@ __device__ __forceinline__ void accumulate_tile(const RenderArgs& a, const TileP
             n3 = src[3];
         }
     };
-    load_rec(load_id(s));
+    int id_rec = load_id(s);     // the entry whose record is in n0..n3
+    load_rec(id_rec);
     int id_next = load_id(s + RB);
+    MaskCtx mcv;
+    mcv.pcc = pcc;
+    mcv.m = G.index_to_world;
+    mcv.res = a.bq.res;
+    mcv.radius = a.bq.radius;
+    const MaskCtx* mc = (MASK && G.masked) ? &mcv : nullptr;
 
 #pragma unroll 1
     for (int b0 = s; b0 < e; b0 += RB) {
         const int nb = min(RB, e - b0);
         const float4 r0 = n0, r1 = n1, r2 = n2, r3 = n3;
+        const int my_entry = id_rec;
         load_rec(id_next);
+        id_rec = id_next;
         id_next = load_id(b0 + 2 * RB);
         tile_sync<BLOCK>();
         int myF = 0, myWz = 0;  // this lane's piece: footprint area and z extent
@@ -267,6 +314,15 @@ __device__ __forceinline__ void accumulate_tile(const RenderArgs& a, const TileP
             p.Ff = (float)myF;
             p.basef = (float)(((iz0 - t0z) * GM_TY + (iy0 - t0y)) * GM_TX + (ix0 - t0x)) - 0.5f;
             pc[lane] = p;
+            if (MASK && mc) {
+                PieceCell q;
+                q.ix0 = ix0;
+                q.iy0 = iy0;
+                q.iz0 = iz0;
+                q.pad = 0;
+                q.cm = a.bq.cells[(uint32_t)my_entry & GM_ID_MASK];
+                pcc[lane] = q;
+            }
         }
         // bit j: pieces j and j + 1 fit side by side in the wave (footprints summing to <= 64)
         const int nextF = __shfl_down(myF, 1, 64);
@@ -287,17 +343,17 @@ __device__ __forceinline__ void accumulate_tile(const RenderArgs& a, const TileP
                     reinterpret_cast<const char*>(pc + j) + (first ? 0 : (int)sizeof(Piece)));
                 const float fh = lane_fh - (first ? 0.0f : (float)Fa);
                 const bool act = fh < p.Ff;
-                paired_pieces_kz(p, acc, act, first, fh, wza, wzb);
+                paired_pieces_kz<MASK>(p, acc, act, first, fh, wza, wzb, mc, first ? j : j + 1);
                 j += 2;
             } else {
                 const Piece p = pc[j];
                 const int F = k >> 6, wz = k & 7;
                 switch (wz) {
                 case 0: break;
-                case 1: single_piece<1>(p, acc, F, lane_fh); break;
-                case 2: single_piece<2>(p, acc, F, lane_fh); break;
-                case 3: single_piece<3>(p, acc, F, lane_fh); break;
-                default: single_piece<GM_TZ>(p, acc, F, lane_fh); break;
+                case 1: single_piece<1, MASK>(p, acc, F, lane_fh, mc, j); break;
+                case 2: single_piece<2, MASK>(p, acc, F, lane_fh, mc, j); break;
+                case 3: single_piece<3, MASK>(p, acc, F, lane_fh, mc, j); break;
+                default: single_piece<GM_TZ, MASK>(p, acc, F, lane_fh, mc, j); break;
                 }
                 j += 1;
             }
@@ -356,7 +412,22 @@ __global__ __launch_bounds__(64) void k_render(const RenderArgs a)
     const TilePos P = tile_pos(a, blk);
     float tv[VPL];
     if (a.loss_part) load_targets(P, lane, tv);
-    accumulate_tile<true>(a, P, acc, pc, lane);
+    accumulate_tile<true, false>(a, P, acc, pc, lane, nullptr);
+    finish_tile(a, P, acc, tv, lane, blk);
+}
+
+// k_render for launches that hold a masked grid (the block query on a rotated grid)
+__global__ __launch_bounds__(64) void k_render_block(const RenderArgs a)
+{
+    __shared__ float acc[GM_TILE_VOX];
+    __shared__ Piece pc[RB];
+    __shared__ PieceCell pcc[RB];
+    const int lane = threadIdx.x;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const TilePos P = tile_pos(a, blk);
+    float tv[VPL];
+    if (a.loss_part) load_targets(P, lane, tv);
+    accumulate_tile<true, true>(a, P, acc, pc, lane, pcc);
     finish_tile(a, P, acc, tv, lane, blk);
 }
 
@@ -370,12 +441,13 @@ __global__ __launch_bounds__(64) void k_render(const RenderArgs a)
 // for bit the render followed by gm_nrf_forward (and the loss the same terms).
 constexpr int FW = 8;
 
-template <int KT, int DEPTH>
+template <int KT, int DEPTH, bool MASK>
 __global__ __launch_bounds__(64 * FW) void k_render_field(const RenderArgs a, const NrfArgs f)
 {
     __shared__ nrfcore::Lds<KT, DEPTH> sw;
     __shared__ float accs[FW][GM_TILE_VOX];
     __shared__ Piece pcs[FW][RB];
+    __shared__ PieceCell pccs[MASK ? FW : 1][RB];
     nrfcore::load_weights<KT, DEPTH>(f, sw);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, row = lane & 15;
     nrfcore::v4s wo[4];
@@ -392,7 +464,7 @@ __global__ __launch_bounds__(64 * FW) void k_render_field(const RenderArgs a, co
         const RenderGrid& G = *P.G;
         float tv[VPL];
         if (a.loss_part) load_targets(P, lane, tv);
-        accumulate_tile<false>(a, P, acc, pc, lane);
+        accumulate_tile<false, MASK>(a, P, acc, pc, lane, pccs[MASK ? w : 0]);
 #pragma unroll 1
         for (int q = 0; q < GM_TILE_VOX / 16; ++q) {
             const int vy = P.t0y + (q % GM_TY), vz = P.t0z + q / GM_TY, vx = P.t0x + row;
@@ -444,26 +516,44 @@ __global__ __launch_bounds__(FIN_THREADS) void k_render_loss_finish(const double
 hipError_t launch_render(const RenderArgs& a, hipStream_t s)
 {
     if (a.total_blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_render, dim3((unsigned)a.total_blocks), dim3(64), 0, s, a);
+    bool masked = false;
+    for (int k = 0; k < a.n_render; ++k) masked = masked || a.rg[k].masked;
+    if (masked)
+        hipLaunchKernelGGL(k_render_block, dim3((unsigned)a.total_blocks), dim3(64), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_render, dim3((unsigned)a.total_blocks), dim3(64), 0, s, a);
     if (a.loss_part)
         hipLaunchKernelGGL(k_render_loss_finish, dim3(1), dim3(FIN_THREADS), 0, s, a.loss_part,
                            a.total_blocks, a.inv_n, a.loss);
     return hipGetLastError();
 }
 
-template <int KT, int DEPTH>
-static void launch_field_t(const RenderArgs& a, const NrfArgs& f, hipStream_t s)
+template <int KT, int DEPTH, bool MASK>
+static void launch_field_mt(const RenderArgs& a, const NrfArgs& f, hipStream_t s)
 {
     // every block resident at once, a multiple of 8 (one share per XCD), capped by the tiles
     int dev = 0, cus = 0, per_cu = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_render_field<KT, DEPTH>, 64 * FW, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_render_field<KT, DEPTH, MASK>,
+                                                       64 * FW, 0);
     int64_t full = (int64_t)(cus > 0 ? cus : 256) * (per_cu > 0 ? per_cu : 1);
     int64_t need = ((int64_t)a.total_blocks + FW - 1) / FW;
     int64_t nb = need < full ? need : full;
     nb = (nb + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_render_field<KT, DEPTH>), dim3((unsigned)nb), dim3(64 * FW), 0, s, a, f);
+    hipLaunchKernelGGL((k_render_field<KT, DEPTH, MASK>), dim3((unsigned)nb), dim3(64 * FW), 0, s,
+                       a, f);
+}
+
+template <int KT, int DEPTH>
+static void launch_field_t(const RenderArgs& a, const NrfArgs& f, hipStream_t s)
+{
+    bool masked = false;
+    for (int k = 0; k < a.n_render; ++k) masked = masked || a.rg[k].masked;
+    if (masked)
+        launch_field_mt<KT, DEPTH, true>(a, f, s);
+    else
+        launch_field_mt<KT, DEPTH, false>(a, f, s);
 }
 
 hipError_t launch_render_field(const RenderArgs& a, const NrfArgs& f, hipStream_t s)

@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 def test_host_only_calls():
     from paper_2603_00145_amd import _lib
     lib = _lib.load()
-    assert lib.gm_abi_version() == 4
+    assert lib.gm_abi_version() == 5
     assert _lib.tile_dims() == (16, 16, 4)
     # host-side validation needs no device
     g = _lib.GmGrid()
@@ -54,7 +54,7 @@ def test_host_only_calls():
 
 
 def test_host_validation_of_the_extension_entry_points():
-    """Host-side checks of the SSIM, pose, lattice and block-query entry points (they return
+    """Host-side checks of the SSIM, pose, lattice and binning entry points (they return
     before anything is launched, so no device is needed)."""
     from paper_2603_00145_amd import _lib
     lib = _lib.load()
@@ -79,7 +79,7 @@ def test_host_validation_of_the_extension_entry_points():
     # pose gradient: NULL Gaussians
     assert lib.gm_grid_pose_grads(None, None, None, 0, fake, fake, 0, None) == \
         _lib.GM_ERR_INVALID_ARGUMENT
-    # block query: a rotated grid is refused before any launch
+    # block query: a cell resolution of 0 is refused before any launch
     grid = _lib.GmGrid()
     grid.nx, grid.ny, grid.nz = 16, 16, 4
     c, s_ = 0.8, 0.6
@@ -91,12 +91,7 @@ def test_host_validation_of_the_extension_entry_points():
     for f in ("records", "tile_count", "box_volume", "tile_start", "pair_gauss", "scratch"):
         setattr(b, f, 0x1000)
     b.scratch_bytes = 1 << 30
-    opts = _lib.GmBinOpts(3.0, 2, 8)
     npairs = ctypes.c_int64()
-    st = lib.gm_bin(ctypes.byref(g), ctypes.byref(grid), 1, ctypes.byref(opts), ctypes.byref(b),
-                    ctypes.byref(npairs), None)
-    assert st == _lib.GM_ERR_UNSUPPORTED
-    assert b"axis-aligned" in lib.gm_last_error()
     opts = _lib.GmBinOpts(3.0, 2, 0)
     st = lib.gm_bin(ctypes.byref(g), ctypes.byref(grid), 1, ctypes.byref(opts), ctypes.byref(b),
                     ctypes.byref(npairs), None)

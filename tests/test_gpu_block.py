@@ -1,6 +1,9 @@
 """The paper's block-radius query (Eqs. 4-6) on the GPU: boxes, tile counts and pair totals
 bit-exact against the oracle on the 64^3 workload's axis-aligned stacks and volume, voxel
-values at sampled voxels, rotated grids refused, and a reconstruction running on it."""
+values at sampled voxels; on rotated stacks (voxel sets that are not boxes, tested voxel by
+voxel) every voxel's value and every Gaussian's grid-frame partials against the oracle's
+brute-force sums over the same sets, the fused render + field + loss against its parts, and
+reconstructions running on both."""
 import sys
 
 import numpy as np
@@ -58,15 +61,109 @@ def test_block_boxes_and_values(mods, res, r):
         assert err <= TOL
 
 
-def test_rotated_grid_refused(mods):
+def normwise(a, r):
+    r = np.asarray(r, np.float64)
+    return np.max(np.abs(np.asarray(a, np.float64) - r)) / max(np.max(np.abs(r)), 1e-30)
+
+
+def rotated_problem(rng, n=41, n_g=900):
+    """Two rotated stacks (2 and 20 degrees; ragged tiles), an unrotated stack and the volume:
+    one launch holds masked and unmasked grids."""
+    g = inputs.init_anisotropic(n, n_g, rng)
+    grids = [inputs.stack_grid("axial", n, 11, 1.0, *inputs.random_rigid(rng, 2, 1, n)),
+             inputs.stack_grid("coronal", 30, 7, 1.0, *inputs.random_rigid(rng, 20, 2, 30)),
+             inputs.stack_grid("sagittal", n, 9, 1.0),
+             inputs.volume_grid(n)]
+    return g, grids
+
+
+@pytest.mark.parametrize("res,r", [(12, 1), (24, 2), (40, 1)])
+def test_block_query_on_rotated_grids(mods, res, r):
     _lib, api = mods
-    rng = np.random.default_rng(0)
-    w = inputs.workload("small", with_data=False)          # stacks with rigid offsets
-    p = api.GaussParams.from_host(w.gauss)
-    b = api.Bins(p.n, w.stacks, block_radius=2, cell_resolution=12)
-    with pytest.raises(_lib.GmError) as e:
-        b.bin(p)
-    assert "axis-aligned" in str(e.value)
+    rng = np.random.default_rng(100 + res + r)
+    g, grids = rotated_problem(rng)
+    ids = list(range(len(grids)))
+    say(f"block query on rotated grids: res {res} r {r}")
+    p = api.GaussParams.from_host(g)
+    b = api.Bins(p.n, grids, block_radius=r, cell_resolution=res)
+    b.bin(p)
+    outs = api.render(b, ids)
+    dl = inputs.random_dl_di(grids, rng)
+    api.grid_partials(p, b, ids, [torch.from_numpy(d).cuda() for d in dl])
+    torch.cuda.synchronize()
+    mean, quat, ls, logit = gauss.params64(g)
+    gcell = recipe.mean_cells(g.mean, res)
+    kappa = -0.5 / np.log(2.0)
+    for k, grid in enumerate(grids):
+        gt = gauss.grid_terms(mean, quat, ls, logit, grid)
+        aligned = recipe.world_axes(grid) is not None
+        if aligned:
+            lo, hi, ne, _ = recipe.block_boxes(g.mean, g.quat, g.log_scale, g.logit, grid, res, r)
+            ref = gauss.render(grid, gt, lo, hi, ne)
+            d_amp, d_c, G_C = gauss.grid_partials(grid, gt, lo, hi, ne, dl[k])
+        else:
+            _, _, _, valid = recipe.boxes(g.mean, g.quat, g.log_scale, g.logit, grid)
+            vcell = recipe.voxel_cells(grid, res)
+            ref = gauss.render_cells(grid, gt, vcell, gcell, valid, r)
+            d_amp, d_c, G_C = gauss.grid_partials_cells(grid, gt, vcell, gcell, valid, r, dl[k])
+            # the GPU box holds every voxel of the set
+            glo, ghi = (t.cpu().numpy() for t in b.boxes(k))
+            z, y, x = np.meshgrid(np.arange(grid.nz), np.arange(grid.ny), np.arange(grid.nx),
+                                  indexing="ij")
+            vox = np.stack([x, y, z], -1).reshape(-1, 3)
+            member = (np.abs(vcell[None, :, :] - gcell[:, None, :]) <= r).all(2) & valid[:, None]
+            for i in np.flatnonzero(member.any(1)):
+                v = vox[member[i]]
+                assert (v >= glo[i]).all() and (v <= ghi[i]).all(), (grid.name, i)
+        err = normwise(outs[k].cpu().numpy(), ref)
+        pg = b.grid_grads[k, :g.n].cpu().numpy().astype(np.float64)
+        dK = np.stack([G_C[:, 0, 0], G_C[:, 1, 1], G_C[:, 2, 2], G_C[:, 0, 1], G_C[:, 0, 2],
+                       G_C[:, 1, 2]], 1) / kappa
+        e_p = [normwise(pg[:, 0], d_amp), normwise(pg[:, 1:4], d_c), normwise(pg[:, 4:10], dK)]
+        say(f"  {grid.name} ({'aligned' if aligned else 'rotated'}): values {err:.2e}, "
+            f"partials {max(e_p):.2e}")
+        assert err <= TOL, grid.name
+        assert max(e_p) <= TOL, grid.name
+
+
+def test_fused_render_field_loss_on_rotated_block_query(mods):
+    """The masked form of the fused render + field + loss against the render, the field's
+    forward and the loss called one after the other (bit for bit; the loss to 1e-6)."""
+    _lib, api = mods
+    from paper_2603_00145_amd import nrf
+    rng = np.random.default_rng(5)
+    g, grids = rotated_problem(rng, n_g=600)
+    ids = list(range(len(grids)))
+    say("fused render + field + loss, block query on rotated grids")
+    targ = [torch.from_numpy(rng.normal(0.3, 1.0, size=gr.shape).astype(np.float32)).cuda()
+            for gr in grids]
+    b = api.Bins(g.n, grids, block_radius=2, cell_resolution=20)
+    b.bin(api.GaussParams.from_host(g))
+    net = nrf.NRF(n_freq=16, depth=3, seed=3, zero_last=False)
+    outs = api.render(b, ids)
+    for k in ids:
+        net.forward_add(grids[k], outs[k])
+    ref_loss, ref_dl = api.smooth_l1(outs, targ)
+    stored = [torch.full(gr.shape, float("nan"), device="cuda") for gr in grids]
+    loss, dl = api.render_loss(b, ids, targ, outs=stored, nrf=net)
+    torch.cuda.synchronize()
+    for k in ids:
+        assert torch.equal(stored[k], outs[k]), f"grid {k}: rendering + field differs"
+        assert torch.equal(dl[k], ref_dl[k]), f"grid {k}: dL/dI differs"
+    assert float(loss) == pytest.approx(float(ref_loss), rel=1e-6)
+
+
+def test_reconstruction_with_block_query_on_rotated_stacks(mods):
+    _lib, api = mods
+    from paper_2603_00145_amd import recon
+    w = inputs.workload("small", device="cuda")           # stacks with rigid offsets
+    data = [torch.as_tensor(d) for d in w.stack_data]
+    cfg = recon.TrainConfig(n_iter=40, block_radius=2, cell_resolution=12)
+    r = recon.Reconstruction(w.stacks, data, api.devox_init(12, w.stacks, data), cfg, w.volume,
+                             w.phantom)
+    hist = r.run()
+    say(f"  rotated stacks, block r=2 psnr {hist[0]['psnr']:.2f} -> {hist[-1]['psnr']:.2f}")
+    assert hist[-1]["psnr"] > hist[0]["psnr"]
 
 
 def test_reconstruction_with_block_query(mods):

@@ -104,7 +104,7 @@ def pair_roof(flop_per_pair, exps_per_pair, p_f=FP32_PEAK, p_e=EXP_RATE_MEASURED
 def recorded_counters(kernel):
     """Per-launch VALU instruction counts of `kernel` from its committed counter summary
     (profiles/<kernel>_valu_c256.md), if taken on the kernel as built now, else None."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_valu_c256.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel.split('<')[0]}_valu_c256.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -129,7 +129,7 @@ def recorded_counters(kernel):
 def recorded_traffic(kernel):
     """HBM bytes per launch of `kernel` from its committed counter summary, if that summary
     was taken on the kernel as it is built now (the same gfx950 assembly digest), else None."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic_c256.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel.split('<')[0]}_traffic_c256.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -342,7 +342,7 @@ def main():
         if stage == "render":
             flop, instr, kname = FLOP_FWD, FWD_VALU_INSTR + EXP_SLOTS, "k_render"
         else:
-            flop, instr, kname = FLOP_BWD, 2 * FWD_VALU_INSTR + EXP_SLOTS, "k_partials"
+            flop, instr, kname = FLOP_BWD, 2 * FWD_VALU_INSTR + EXP_SLOTS, "k_partials<false>"
         sec = stage_ms[stage] / 1e3
         achieved = flop * pairs / sec / 1e12
         peak = FP32_PEAK / 1e12

@@ -41,10 +41,12 @@ DIGESTS = os.path.join(ROOT, "paper_2603_00145_amd", "kernel_digests.json")
 
 
 def kernel_digest(kernel):
-    """SHA-256 of the kernel's assembly in the current build (None without a build)."""
+    """SHA-256 of the kernel's assembly in the current build (None without a build); a
+    template kernel is recorded under its name without arguments (the build digests the
+    instantiation the benchmark runs)."""
     try:
         with open(DIGESTS) as f:
-            return json.load(f).get(kernel)
+            return json.load(f).get(kernel.split("<")[0])
     except (OSError, ValueError):
         return None
 

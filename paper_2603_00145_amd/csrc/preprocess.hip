@@ -76,7 +76,11 @@ __device__ bool block_interval(double l, double t, double cm, double r, double r
     return v0 > v1 || (in(v0) && in(v1));
 }
 
-__global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a)
+// BLOCK: the block query (a.block_radius > 0); the sigma box otherwise.  Two kernels, so that
+// the sigma-box kernel carries none of the block rule's registers (and fits five wavefronts per
+// SIMD).
+template <bool BLOCK>
+__device__ __forceinline__ void preprocess_body(const PreprocessArgs& a)
 {
     __shared__ unsigned long long s_vol[GM_MAX_GRIDS];
     if (threadIdx.x < GM_MAX_GRIDS) s_vol[threadIdx.x] = 0ull;
@@ -119,7 +123,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a)
         // block query: the mean's cell on each world axis (Eq. 4), clamped to [-2^30, 2^30],
         // kept for the kernels that test voxels of rotated grids
         double cmw[3] = {0.0, 0.0, 0.0};
-        if (a.block_radius > 0) {
+        if (BLOCK) {
             const double res = (double)a.cell_res, CC = 1073741824.0;
             const double mus[3] = {mu0, mu1, mu2};
 #pragma unroll
@@ -155,7 +159,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a)
             int lo[3], hi[3];
             bool nonempty = valid;
             const double CL = 1073741824.0;
-            if (a.block_radius > 0 && G.waxis[0] < 0) {
+            if (BLOCK && G.waxis[0] < 0) {
                 // rotated grid: the block's world box (Eq. 5 solved for x), widened by 1e-9
                 // (relative), mapped to index space (the bounds of a linear map over a box),
                 // widened by 1e-6 (relative) and rounded outwards.  It holds every voxel whose
@@ -189,7 +193,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a)
                     hi[j] = hj;
                     nonempty = nonempty && (li <= hj);
                 }
-            } else if (a.block_radius > 0) {
+            } else if (BLOCK) {
                 const double mus[3] = {mu0, mu1, mu2};
                 const double res = (double)a.cell_res, r = (double)a.block_radius;
 #pragma unroll
@@ -297,12 +301,26 @@ __global__ __launch_bounds__(256) void k_preprocess(const PreprocessArgs a)
         atomicAdd(&a.box_volume[threadIdx.x], s_vol[threadIdx.x]);
 }
 
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_preprocess(
+    const PreprocessArgs a)
+{
+    preprocess_body<false>(a);
+}
+
+__global__ __launch_bounds__(256) void k_preprocess_block(const PreprocessArgs a)
+{
+    preprocess_body<true>(a);
+}
+
 }  // namespace
 
 hipError_t launch_preprocess(const PreprocessArgs& a, hipStream_t s)
 {
     if (a.n == 0) return hipSuccess;
     const int64_t blocks = (a.n + 255) / 256;
-    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    if (a.block_radius > 0)
+        hipLaunchKernelGGL(k_preprocess_block, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_preprocess, dim3((unsigned)blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }

@@ -330,6 +330,7 @@ def workload(name: str, with_data: bool = True, seed: Optional[int] = None,
              device="cpu") -> Workload:
     """The synthetic workloads.
 
+    (Gaussians in raster order of their voxel, as a devoxelised lattice stores them)
     small     : 24^3 volume, 3 stacks 24x24x6, 300 anisotropic Gaussians (fast tests)
     c64       : 64^3, 12 ellipsoids, 3 x 64x64x16, FWHM 4 voxels, 20k isotropic 1-voxel
                 Gaussians at distinct voxel centres
@@ -358,6 +359,8 @@ def workload(name: str, with_data: bool = True, seed: Optional[int] = None,
         g = init_isotropic(n, cfg["ng"], r_init)
     else:
         g = init_anisotropic(n, cfg["ng"], r_init)
+    # stored in raster order of their voxel, as a devoxelised lattice stores its Gaussians
+    g = g.subset(raster_order(g.mean, n))
     w = Workload(name, n, stacks, vol, g)
     if with_data:
         w.phantom = make_phantom(n, cfg["ell"], r_ph, bias=cfg["bias"], device=device)
@@ -366,6 +369,13 @@ def workload(name: str, with_data: bool = True, seed: Optional[int] = None,
             w.phantom = w.phantom.numpy()
             w.stack_data = [d.numpy() for d in w.stack_data]
     return w
+
+
+def raster_order(mean: np.ndarray, n: int) -> np.ndarray:
+    """Permutation that sorts Gaussians by the voxel of an n^3 grid over [-1, 1]^3 holding
+    their mean, x fastest (stable)."""
+    v = np.floor((np.asarray(mean, np.float64) + 1.0) * n / 2.0).astype(np.int64).clip(0, n - 1)
+    return np.argsort((v[:, 2] * n + v[:, 1]) * n + v[:, 0], kind="stable")
 
 
 def random_dl_di(grids: Sequence[Grid], rng: np.random.Generator, scale: float = 1.0):

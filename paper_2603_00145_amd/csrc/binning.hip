@@ -192,8 +192,10 @@ static_assert(RS_BLOCK_KEYS % (4 * RS_HIST_THREADS) == 0, "whole 16-byte loads p
 static_assert(RS_THREADS >= 256 && RS_THREADS % 256 == 0, "the digit phase uses the first 256 threads");
 
 // Digit counts of one scatter block's keys.  Each wave counts into its own LDS histogram
-// (fewer colliding atomics), full blocks read four keys per 16-byte load, and the four
-// histograms are summed per digit at the end.
+// (fewer colliding atomics), full blocks read four keys per 16-byte load and add each run of
+// equal digits among a load's four keys once (keys emitted for Gaussians close in space share
+// tiles, so runs are common and fewer lanes collide), and the four histograms are summed per
+// digit at the end.
 __global__ __launch_bounds__(RS_HIST_THREADS) void k_rs_hist(const uint32_t* keys, int64_t n,
                                                               int shift, uint32_t mask,
                                                               int32_t* ghist, int64_t nblocks)
@@ -215,10 +217,18 @@ __global__ __launch_bounds__(RS_HIST_THREADS) void k_rs_hist(const uint32_t* key
             v[j] = k4[threadIdx.x + j * RS_HIST_THREADS];
 #pragma unroll
         for (int j = 0; j < RS_BLOCK_KEYS / 4 / RS_HIST_THREADS; ++j) {
-            atomicAdd(&hw[(v[j].x >> shift) & mask], 1u);
-            atomicAdd(&hw[(v[j].y >> shift) & mask], 1u);
-            atomicAdd(&hw[(v[j].z >> shift) & mask], 1u);
-            atomicAdd(&hw[(v[j].w >> shift) & mask], 1u);
+            const uint32_t d0 = (v[j].x >> shift) & mask, d1 = (v[j].y >> shift) & mask;
+            const uint32_t d2 = (v[j].z >> shift) & mask, d3 = (v[j].w >> shift) & mask;
+            // run lengths from each key to the end of its run of equal digits
+            const uint32_t l3 = 1u;
+            const uint32_t l2 = d3 == d2 ? l3 + 1u : 1u;
+            const uint32_t l1 = d2 == d1 ? l2 + 1u : 1u;
+            const uint32_t l0 = d1 == d0 ? l1 + 1u : 1u;
+            // each run counted once, at its first key
+            atomicAdd(&hw[d0], l0);
+            if (d1 != d0) atomicAdd(&hw[d1], l1);
+            if (d2 != d1) atomicAdd(&hw[d2], l2);
+            if (d3 != d2) atomicAdd(&hw[d3], l3);
         }
     } else {
         for (int k = threadIdx.x; k < nk; k += RS_HIST_THREADS)

@@ -283,7 +283,8 @@ typedef struct gm_nrf_grads {
 gm_status gm_nrf_workspace(const gm_nrf* nrf, int64_t n_points, size_t* bytes);
 
 /* Backward of scale * sum_{k < n_points} dl_dr[v_k] r(x_{v_k}) over the voxels v_k = idx[k]
- * (linear indices into grid; idx NULL = every voxel in order) with respect to every weight
+ * (linear indices into grid; idx NULL = every voxel in order, n_points then the grid's voxels
+ * or 0) with respect to every weight
  * and bias of the field; accumulates into grads.  dl_dr is grid-sized [nz][ny][nx].  With a
  * random subset of n voxels and scale = (grid voxels) / n this is an unbiased estimate of the
  * full gradient (the paper trains on sampled points).  Recomputes the forward, writes the

@@ -808,9 +808,9 @@ gm_status nrf_backward_grid(const gm_nrf* nrf, int k, const gm_grid& grid, const
     if (st != GM_OK) return st;
     if (n_points < 0 || n_points > 0x7fffffffLL)
         return fail(GM_ERR_INVALID_ARGUMENT, "grid %d: n_points outside [0, 2^31)", k);
-    if (!idx && n_points != (int64_t)grid.nx * grid.ny * grid.nz)
-        return fail(GM_ERR_INVALID_ARGUMENT, "grid %d: idx NULL requires n_points = grid voxels",
-                    k);
+    if (!idx && n_points != 0 && n_points != (int64_t)grid.nx * grid.ny * grid.nz)
+        return fail(GM_ERR_INVALID_ARGUMENT,
+                    "grid %d: idx NULL requires n_points = 0 or the grid's voxels", k);
     if (!isfinite(scale)) return fail(GM_ERR_INVALID_ARGUMENT, "grid %d: scale not finite", k);
     if (n_points > 0) REQ_PTR(dl_dr, "dl_dr");
     double M[12];

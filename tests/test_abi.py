@@ -128,6 +128,10 @@ def test_host_validation_of_the_multi_grid_field_backward():
     gr = _lib.GmNrfGrads(fake, fake, fake, fake, fake, fake)
     assert lib.gm_nrf_backward_grids(ctypes.byref(nrf), 2, grids, idx, zero, dl, sc,
                                      ctypes.byref(gr), None, 0, None) == 0
+    # no points and no index list (an empty sample): nothing to do
+    none = (P * 2)(P(0), P(0))
+    assert lib.gm_nrf_backward_grids(ctypes.byref(nrf), 2, grids, none, zero, dl, sc,
+                                     ctypes.byref(gr), None, 0, None) == 0
     # a grid with no idx must name every voxel; errors name the grid
     idx[1] = P(0)
     bad = (ctypes.c_int64 * 2)(5, 7)

@@ -43,21 +43,29 @@ struct BlockQuery {
 
 // The voxel's world position ((m_a0 x + m_a1 y) + m_a2 z) + m_a3 per world axis a (m the
 // grid's index -> world affine, row-major 3x4) and its cell floor(((w + 1) res) / 2), in
-// binary64 without contraction; true when every axis is within radius of cm.
-__device__ __forceinline__ bool voxel_in_block(const double* m, double res, int radius, int x,
-                                               int y, int z, int4 cm)
+// binary64 without contraction.
+__device__ __forceinline__ void voxel_cells(const double* m, double res, int x, int y, int z,
+                                            double (&cell)[3])
 {
 #pragma clang fp contract(off)
-    const double xd = (double)x, yd = (double)y, zd = (double)z, r = (double)radius;
-    const double c[3] = {(double)cm.x, (double)cm.y, (double)cm.z};
-    bool in = true;
+    const double xd = (double)x, yd = (double)y, zd = (double)z;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const double w = ((m[4 * a] * xd + m[4 * a + 1] * yd) + m[4 * a + 2] * zd) + m[4 * a + 3];
-        const double cell = floor(((w + 1.0) * res) / 2.0);
-        in = in && cell >= c[a] - r && cell <= c[a] + r;
+        cell[a] = floor(((w + 1.0) * res) / 2.0);
     }
-    return in;
+}
+
+// true when every axis of the voxel's cell is within radius of cm
+__device__ __forceinline__ bool voxel_in_block(const double* m, double res, int radius, int x,
+                                               int y, int z, int4 cm)
+{
+    double cell[3];
+    voxel_cells(m, res, x, y, z, cell);
+    const double r = (double)radius;
+    return cell[0] >= (double)cm.x - r && cell[0] <= (double)cm.x + r &&
+           cell[1] >= (double)cm.y - r && cell[1] <= (double)cm.y + r &&
+           cell[2] >= (double)cm.z - r && cell[2] <= (double)cm.z + r;
 }
 
 // ---- launchers (one per kernel family) --------------------------------------------------

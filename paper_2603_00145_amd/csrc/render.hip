@@ -14,7 +14,9 @@
 //
 // With the paper's block query on a rotated grid (k_render_block, and k_render_field's MASK
 // form) a Gaussian's voxels are not its box: each evaluated voxel of the box is also tested
-// against the Gaussian's cell block (Eqs. 4-6) and gets zero when it fails.
+// against the Gaussian's cell block (Eqs. 4-6) and gets zero when it fails (k_render_block
+// forms the tile's voxel cells once per tile in LDS; the field kernel, short of LDS, forms
+// them per voxel).
 #include "nrf_core.h"
 
 namespace {
@@ -75,17 +77,35 @@ struct PieceCell {
     int4 cm;
 };
 struct MaskCtx {
+    bool on;                // the tile's grid is masked
     const PieceCell* pcc;   // the wavefront's batch
     const double* m;
     double res;
     int radius;
+    const int* vc;          // the tile's voxel cells [3][GM_TILE_VOX] (x, y, z planes), or NULL
 };
 
-// w[k] = 0 for the voxels of column fh of piece p (as eval_column maps it) outside the block
+// w[k] = 0 for the voxels of column fh of piece p (as eval_column maps it, LDS index idx at
+// k = 0) outside the block: from the tile's voxel cells when they are staged, else formed here
 template <int KM>
 __device__ __forceinline__ void mask_column(const Piece& p, const PieceCell& q, const MaskCtx& mc,
-                                            float fh, float (&w)[KM])
+                                            float fh, int idx, float (&w)[KM])
 {
+    if (mc.vc) {
+        const long long r = mc.radius;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            // a lane past its piece (or a z step past the tile) reads some voxel's cells and
+            // stores nothing
+            const int vi = min(max(idx + k * GM_TX * GM_TY, 0), GM_TILE_VOX - 1);
+            const long long dx = (long long)mc.vc[vi] - q.cm.x;
+            const long long dy = (long long)mc.vc[GM_TILE_VOX + vi] - q.cm.y;
+            const long long dz = (long long)mc.vc[2 * GM_TILE_VOX + vi] - q.cm.z;
+            const bool in = dx >= -r && dx <= r && dy >= -r && dy <= r && dz >= -r && dz <= r;
+            if (!in) w[k] = 0.0f;
+        }
+        return;
+    }
     const float yf = floorf(fh * p.inv_wx);
     const float xh = fmaf(-yf, p.wxf, fh);        // x + 1/2 within the piece
     const int x = q.ix0 + (int)xh, y = q.iy0 + (int)yf;
@@ -108,10 +128,10 @@ __device__ __forceinline__ void add_column(float* acc, int idx, const float (&w)
 }
 
 // One piece on the whole wave: columns f0 + lane, KM z-steps each (lane_fh = lane + 1/2).
-// MASK: mc (non-null on a masked grid) and the piece's batch slot jq.
+// MASK: mc (mc.on on a masked grid) and the piece's batch slot jq.
 template <int KM, bool MASK>
 __device__ __forceinline__ void single_piece(const Piece& p, float* acc, int F, float lane_fh,
-                                             const MaskCtx* mc, int jq)
+                                             const MaskCtx& mc, int jq)
 {
     float fh = lane_fh;
 #pragma unroll 1
@@ -119,7 +139,7 @@ __device__ __forceinline__ void single_piece(const Piece& p, float* acc, int F, 
         float w[KM];
         int idx;
         eval_column<KM>(p, fh, w, idx);
-        if (MASK && mc) mask_column<KM>(p, mc->pcc[jq], *mc, fh, w);
+        if (MASK && mc.on) mask_column<KM>(p, mc.pcc[jq], mc, fh, idx, w);
         if (fh < p.Ff) add_column<KM, KM>(acc, idx, w);
         fh += 64.0f;
     }
@@ -131,7 +151,7 @@ __device__ __forceinline__ void single_piece(const Piece& p, float* acc, int F, 
 // dispatches once on the pair and its two add phases carry no branches of their own.
 template <int ZA, int ZB, bool MASK>
 __device__ __forceinline__ void paired_pieces(const Piece& p, float* acc, bool act, bool first,
-                                              float fh, const MaskCtx* mc, int jq)
+                                              float fh, const MaskCtx& mc, int jq)
 {
     constexpr int KM = ZA > ZB ? ZA : ZB;
     // every lane evaluates (a lane past its piece's footprint computes values it never
@@ -139,7 +159,7 @@ __device__ __forceinline__ void paired_pieces(const Piece& p, float* acc, bool a
     float w[KM];
     int idx;
     eval_column<KM>(p, fh, w, idx);
-    if (MASK && mc) mask_column<KM>(p, mc->pcc[jq], *mc, fh, w);
+    if (MASK && mc.on) mask_column<KM>(p, mc.pcc[jq], mc, fh, idx, w);
     lds_order();
     if (act && first) add_column<ZA, KM>(acc, idx, w);
     lds_order();
@@ -151,7 +171,7 @@ __device__ __forceinline__ void paired_pieces(const Piece& p, float* acc, bool a
 template <bool MASK>
 __device__ __forceinline__ void paired_pieces_kz(const Piece& p, float* acc, bool act,
                                                  bool first, float fh, int wza, int wzb,
-                                                 const MaskCtx* mc, int jq)
+                                                 const MaskCtx& mc, int jq)
 {
     static_assert(GM_TZ == 4, "z extents 1..4 are dispatched below");
 #define GM_PAIR_CASE(A, B) \
@@ -229,10 +249,12 @@ __device__ __forceinline__ void load_targets(const TilePos& P, int lane, float (
 
 // acc (the tile's voxels, LDS) = the sum over the tile's list of Gaussians, in list order.
 // Ends with a tile_sync, so every lane may read any voxel afterwards.  MASK: on a masked grid
-// every voxel is also tested against its Gaussian's cell block (pcc: the batch's PieceCells).
+// every voxel is also tested against its Gaussian's cell block (pcc: the batch's PieceCells;
+// vcell, when given: LDS for the tile's voxel cells, formed once per tile).
 template <bool BLOCK, bool MASK>
 __device__ __forceinline__ void accumulate_tile(const RenderArgs& a, const TilePos& P, float* acc,
-                                                Piece* pc, int lane, PieceCell* pcc)
+                                                Piece* pc, int lane, PieceCell* pcc,
+                                                int* vcell = nullptr)
 {
     const RenderGrid& G = *P.G;
     const int t0x = P.t0x, t0y = P.t0y, t0z = P.t0z;
@@ -274,7 +296,23 @@ __device__ __forceinline__ void accumulate_tile(const RenderArgs& a, const TileP
     mcv.m = G.index_to_world;
     mcv.res = a.bq.res;
     mcv.radius = a.bq.radius;
-    const MaskCtx* mc = (MASK && G.masked) ? &mcv : nullptr;
+    mcv.vc = vcell;
+    mcv.on = MASK && G.masked;
+    const MaskCtx& mc = mcv;
+    if (MASK && mc.on && vcell) {
+        // the cells of the tile's voxels (the tile_sync at the first batch orders these
+        // stores before their reads), clamped to [-2^30, 2^30] as the means' cells are
+#pragma unroll 1
+        for (int j = 0; j < GM_TILE_VOX / 64; ++j) {
+            const int i = j * 64 + lane;
+            double c[3];
+            voxel_cells(G.index_to_world, a.bq.res, t0x + i % GM_TX, t0y + (i / GM_TX) % GM_TY,
+                        t0z + i / (GM_TX * GM_TY), c);
+#pragma unroll
+            for (int u = 0; u < 3; ++u)
+                vcell[u * GM_TILE_VOX + i] = (int)fmin(fmax(c[u], -1073741824.0), 1073741824.0);
+        }
+    }
 
 #pragma unroll 1
     for (int b0 = s; b0 < e; b0 += RB) {
@@ -314,7 +352,7 @@ __device__ __forceinline__ void accumulate_tile(const RenderArgs& a, const TileP
             p.Ff = (float)myF;
             p.basef = (float)(((iz0 - t0z) * GM_TY + (iy0 - t0y)) * GM_TX + (ix0 - t0x)) - 0.5f;
             pc[lane] = p;
-            if (MASK && mc) {
+            if (MASK && mc.on) {
                 PieceCell q;
                 q.ix0 = ix0;
                 q.iy0 = iy0;
@@ -422,12 +460,13 @@ __global__ __launch_bounds__(64) void k_render_block(const RenderArgs a)
     __shared__ float acc[GM_TILE_VOX];
     __shared__ Piece pc[RB];
     __shared__ PieceCell pcc[RB];
+    __shared__ int vcell[3 * GM_TILE_VOX];
     const int lane = threadIdx.x;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const TilePos P = tile_pos(a, blk);
     float tv[VPL];
     if (a.loss_part) load_targets(P, lane, tv);
-    accumulate_tile<true, true>(a, P, acc, pc, lane, pcc);
+    accumulate_tile<true, true>(a, P, acc, pc, lane, pcc, vcell);
     finish_tile(a, P, acc, tv, lane, blk);
 }
 

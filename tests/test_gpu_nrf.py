@@ -178,6 +178,33 @@ def test_nrf_backward_over_several_grids(mods):
         assert e_one <= 1e-5, name
 
 
+def test_nrf_backward_over_several_grids_training_size(mods):
+    """The one-call backward as training takes it (2^18 sampled voxels on each of three
+    256x256x64 stacks) against the three single-grid calls: the same dZ and activations, only
+    the split of the weight-gradient sums over the points differs (to 1e-5)."""
+    _lib, api, nrf = mods
+    w = inputs.workload("c256", with_data=False)
+    rng = np.random.default_rng(31)
+    net = nrf.NRF(n_freq=16, depth=3, seed=4, zero_last=False)
+    dls = [torch.from_numpy((rng.normal(size=g.shape) * 1e-6).astype(np.float32)).cuda()
+           for g in w.stacks]
+    idxs = [torch.from_numpy(rng.choice(g.n_voxels, size=1 << 18, replace=False)
+                             .astype(np.int32)).cuda() for g in w.stacks]
+    say("  nrf backward, 3 x 2^18 points: one call against three")
+    net.zero_grad()
+    net.backward_grids(w.stacks, dls, idxs=idxs)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in net.g.items()}
+    net.zero_grad()
+    for g, d, i in zip(w.stacks, dls, idxs):
+        net.backward(g, d, idx=i)
+    torch.cuda.synchronize()
+    for k, v in net.g.items():
+        err = normwise(got[k], v.cpu().numpy())
+        say(f"  {k}: {err:.2e}")
+        assert err <= 1e-5, k
+
+
 def test_render_volume_with_nrf(mods):
     _lib, api, nrf = mods
     g = inputs.init_anisotropic(20, 200, np.random.default_rng(1))

@@ -160,6 +160,25 @@ void oracle_render_cells(int64_t nx, int64_t ny, int64_t nz, int64_t n, const do
     }
 }
 
+/* oracle_render_points with the block test in place of the box test: pcell[k] is the cell
+ * of point k's world position. */
+void oracle_render_points_cells(int64_t npts, const int64_t* pts, const int64_t* pcell,
+                                int64_t n, const double* c, const double* C, const double* amp,
+                                const int64_t* gcell, const uint8_t* valid, int64_t radius,
+                                double* out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < npts; ++k) {
+        const int64_t x = pts[3 * k], y = pts[3 * k + 1], z = pts[3 * k + 2];
+        double acc = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            if (!valid[i] || !in_block(pcell + 3 * k, gcell + 3 * i, radius)) continue;
+            acc += gauss_value(c + 3 * i, C + 9 * i, amp[i], (double)x, (double)y, (double)z);
+        }
+        out[k] = acc;
+    }
+}
+
 /* oracle_partials over the voxels the block test gives each Gaussian. */
 void oracle_partials_cells(int64_t nx, int64_t ny, int64_t nz, int64_t n, const double* c,
                            const double* C, const double* amp, const int64_t* vcell,

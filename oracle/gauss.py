@@ -54,6 +54,8 @@ def _lib():
         lib.oracle_render_cells.argtypes = [I, I, I, I, P, P, P, P, P, P, I, P]
         lib.oracle_render_cells.restype = None
         lib.oracle_partials_cells.argtypes = [I, I, I, I, P, P, P, P, P, P, I, P, P, P, P]
+        lib.oracle_render_points_cells.argtypes = [I, P, P, I, P, P, P, P, P, I, P]
+        lib.oracle_render_points_cells.restype = None
         lib.oracle_partials_cells.restype = None
         lib.oracle_threads.restype = ctypes.c_int
         lib.oracle_threads.argtypes = []
@@ -219,6 +221,23 @@ def render_cells(grid, gt, vcell, gcell, valid, radius):
     assert vc.shape[0] == grid.n_voxels and gc.shape[0] == n and va.shape[0] == n
     lib.oracle_render_cells(grid.nx, grid.ny, grid.nz, n, _ptr(c), _ptr(C), _ptr(amp), _ptr(vc),
                             _ptr(gc), _ptr(va), int(radius), _ptr(out))
+    return out
+
+
+def render_points_cells(points, pcell, gt, gcell, valid, radius):
+    """render_cells at selected voxels points[k] = (x, y, z) whose world positions have the
+    cells pcell[k] (recipe.voxel_cells of those voxels), brute force over all Gaussians."""
+    lib = _lib()
+    pts = np.ascontiguousarray(points, np.int64).reshape(-1, 3)
+    pc = np.ascontiguousarray(pcell, np.int64).reshape(-1, 3)
+    n = gt["c"].shape[0]
+    out = np.zeros(pts.shape[0], np.float64)
+    c, C, amp = _f64c(gt["c"]), _f64c(gt["C"]), _f64c(gt["amp"])
+    gc = np.ascontiguousarray(gcell, np.int64).reshape(-1, 3)
+    va = np.ascontiguousarray(valid, np.uint8)
+    assert pc.shape[0] == pts.shape[0] and gc.shape[0] == n and va.shape[0] == n
+    lib.oracle_render_points_cells(pts.shape[0], _ptr(pts), _ptr(pc), n, _ptr(c), _ptr(C),
+                                   _ptr(amp), _ptr(gc), _ptr(va), int(radius), _ptr(out))
     return out
 
 

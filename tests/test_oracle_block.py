@@ -154,3 +154,23 @@ def test_voxel_cells_on_a_rotated_grid_follow_the_world_position():
         member[sets[i]] = True
         assert (member <= inside).all() and (strict <= member).all()
         assert member.any()
+
+
+def test_point_sums_with_the_cell_test_equal_the_grid_sums():
+    """The point form of the cell-test sum gives the grid form's values at those voxels."""
+    from oracle import gauss
+    rng = np.random.default_rng(9)
+    res, r = 12, 1
+    grid = inputs.stack_grid("coronal", 20, 5, 1.0, *inputs.random_rigid(rng, 15.0, 1.0, 20))
+    mean, quat, ls, logit = gaussians(50, rng, spread=0.9)
+    g = inputs.Gaussians(mean, quat, ls, logit)
+    (gt, _, _, _, valid), = gauss.prepare(g, [grid])
+    vcell = recipe.voxel_cells(grid, res)
+    gcell = recipe.mean_cells(mean, res)
+    full = gauss.render_cells(grid, gt, vcell, gcell, valid, r).reshape(-1)
+    sel = rng.choice(grid.n_voxels, 200, replace=False)
+    z, rem = np.divmod(sel, grid.nx * grid.ny)
+    y, x = np.divmod(rem, grid.nx)
+    pts = np.stack([x, y, z], 1)
+    got = gauss.render_points_cells(pts, vcell[sel], gt, gcell, valid, r)
+    np.testing.assert_array_equal(got, full[sel])

@@ -129,7 +129,8 @@ def test_block_query_on_rotated_grids(mods, res, r):
 def test_block_query_on_the_rotated_128_stacks(mods):
     """The full 128^3 workload (200k Gaussians, three 128x128x32 stacks rotated by up to 2
     degrees) under the block query: 600 sampled voxels per stack against the oracle's
-    brute-force sum over every Gaussian with the cell test."""
+    brute-force sum over every Gaussian with the cell test, and the grid-frame partials of 400
+    sampled Gaussians per stack against the oracle's sums over every voxel of the stack."""
     _lib, api = mods
     res, r = 64, 2
     w = inputs.workload("c128", with_data=False)
@@ -138,10 +139,13 @@ def test_block_query_on_the_rotated_128_stacks(mods):
     b = api.Bins(p.n, w.stacks, block_radius=r, cell_resolution=res)
     b.bin(p)
     outs = api.render(b, list(range(len(w.stacks))))
+    rng = np.random.default_rng(128)
+    dl = inputs.random_dl_di(w.stacks, rng)
+    api.grid_partials(p, b, list(range(len(w.stacks))), [torch.from_numpy(d).cuda() for d in dl])
     torch.cuda.synchronize()
     mean, quat, ls, logit = gauss.params64(g)
     gcell = recipe.mean_cells(g.mean, res)
-    rng = np.random.default_rng(128)
+    kappa = -0.5 / np.log(2.0)
     for k, grid in enumerate(w.stacks):
         assert recipe.world_axes(grid) is None          # rotated: the masked path
         gt = gauss.grid_terms(mean, quat, ls, logit, grid)
@@ -153,9 +157,21 @@ def test_block_query_on_the_rotated_128_stacks(mods):
         ref = gauss.render_points_cells(np.stack([x, y, z], 1), pcell, gt, gcell, valid, r)
         got = outs[k].cpu().numpy().reshape(-1)[sel]
         err = normwise(got, ref)
+        # partials of sampled Gaussians whose block reaches the stack
+        sub = np.sort(rng.choice(g.n, 400, replace=False))
+        gs = {key: (v[sub] if isinstance(v, np.ndarray) and v.shape[:1] == (g.n,) else v)
+              for key, v in gt.items()}
+        vcell = recipe.voxel_cells(grid, res)
+        d_amp, d_c, G_C = gauss.grid_partials_cells(grid, gs, vcell, gcell[sub], valid[sub], r,
+                                                    dl[k])
+        pg = b.grid_grads[k, sub].cpu().numpy().astype(np.float64)
+        dK = np.stack([G_C[:, 0, 0], G_C[:, 1, 1], G_C[:, 2, 2], G_C[:, 0, 1], G_C[:, 0, 2],
+                       G_C[:, 1, 2]], 1) / kappa
+        e_p = max(normwise(pg[:, 0], d_amp), normwise(pg[:, 1:4], d_c), normwise(pg[:, 4:10], dK))
         say(f"  c128 {grid.name}, block r={r} res={res}: {b.box_pairs_host[k]} box pairs, "
-            f"sampled values normwise {err:.2e}")
+            f"sampled values normwise {err:.2e}, sampled partials {e_p:.2e}")
         assert err <= TOL, grid.name
+        assert e_p <= TOL, grid.name
 
 
 def test_fused_render_field_loss_on_rotated_block_query(mods):

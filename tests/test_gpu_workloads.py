@@ -148,6 +148,34 @@ def test_c320_volume_crop_fp32_and_bf16(mods):
     assert e_all <= TOL_BF16
 
 
+def test_c256_fused_render_field_loss_equals_its_parts(mods):
+    """The field-on training step's first pass at full size (1M Gaussians, three 256x256x64
+    stacks, 12288 tiles: the loss finish's multi-round loop and every block of the fused
+    kernel's resident grid): renderings and dL/dI bit for bit against render, the field's
+    forward and the smooth-L1 called one after the other, the loss to 1e-6."""
+    _lib, api, nrf = mods
+    w = inputs.workload("c256", with_data=True, device="cuda")
+    p = api.GaussParams.from_host(w.gauss)
+    b = api.Bins(p.n, w.stacks, capacity=int(12 * p.n * len(w.stacks)))
+    b.bin(p)
+    ids = list(range(len(w.stacks)))
+    targ = [d.contiguous() for d in w.stack_data]
+    net = nrf.NRF(n_freq=16, depth=3, seed=0, zero_last=False)
+    say("c256 fused render + field + loss against its parts")
+    outs = api.render(b, ids)
+    for k in ids:
+        net.forward_add(w.stacks[k], outs[k])
+    ref_loss, ref_dl = api.smooth_l1(outs, targ)
+    stored = [torch.full(s.shape, float("nan"), device="cuda") for s in w.stacks]
+    loss, dl = api.render_loss(b, ids, targ, outs=stored, nrf=net)
+    torch.cuda.synchronize()
+    for k in ids:
+        assert torch.equal(stored[k], outs[k]), f"stack {k}: rendering + field differs"
+        assert torch.equal(dl[k], ref_dl[k]), f"stack {k}: dL/dI differs"
+    say(f"  loss {float(loss):.9g} against {float(ref_loss):.9g}")
+    assert float(loss) == pytest.approx(float(ref_loss), rel=1e-6)
+
+
 def test_c256_training_step_every_voxel_and_gaussian(mods):
     """The benchmark's training iteration on the 256^3 workload (1M Gaussians, three
     256x256x64 stacks: gm_bin, the render with the smooth-L1 epilogue over 12k tiles, the grid

@@ -93,7 +93,7 @@ class NRF:
             idx = torch.randint(0, nvox, (n_sample,), device=dl_dr.device, dtype=torch.int32,
                                 generator=generator)
         npts = nvox if idx is None else int(idx.numel())
-        scale = nvox / npts if idx is not None else 1.0
+        scale = nvox / npts if idx is not None and npts > 0 else 1.0
         nb = ctypes.c_size_t()
         s = self.struct()
         check(load().gm_nrf_workspace(ctypes.byref(s), npts, ctypes.byref(nb)))
@@ -125,7 +125,7 @@ class NRF:
                                     generator=generator)
             idx_l.append(idx)
             npts.append(nvox if idx is None else int(idx.numel()))
-            scales.append(nvox / npts[-1] if idx is not None else 1.0)
+            scales.append(nvox / npts[-1] if idx is not None and npts[-1] > 0 else 1.0)
         s = self.struct()
         n_pts = (ctypes.c_int64 * n)(*npts)
         nb = ctypes.c_size_t()

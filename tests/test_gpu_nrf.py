@@ -143,6 +143,13 @@ def test_nrf_backward_over_several_grids(mods):
     _, scales = net.backward_grids(grids, dls_d, idxs=idx_d)
     torch.cuda.synchronize()
     got = {k: v.cpu().numpy().astype(np.float64) for k, v in net.g.items()}
+    # a fourth grid with an empty sample changes nothing
+    net.zero_grad()
+    empty = torch.zeros(0, dtype=torch.int32, device="cuda")
+    net.backward_grids(grids + [grids[0]], dls_d + [dls_d[0]], idxs=idx_d + [empty])
+    torch.cuda.synchronize()
+    for k, v in net.g.items():
+        assert normwise(v.cpu().numpy(), got[k]) <= 1e-5, f"{k} with an empty grid"
     net.zero_grad()
     for g, d, i in zip(grids, dls_d, idx_d):
         net.backward(g, d, idx=i)

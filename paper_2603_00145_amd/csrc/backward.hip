@@ -200,6 +200,10 @@ __device__ __forceinline__ void group_of_gaussians(const BackwardArgs& a, int kk
         const float Aq = fmaf(dx, fmaf(kxx, dx, fmaf(kxz, dz, g1)), fmaf(dz, fmaf(kzz, dz, g2), A0));
         const float A = act ? Aq : -__builtin_inff();
         const float B = fmaf(kxy, dx, fmaf(kyz, dz, B0));
+        // the global-memory path's centred form: Q = qxz + dy (by + kyy dy)
+        const float by = fmaf(kxy, dx, kyz * dz);
+        const float qxz = act ? fmaf(dx, fmaf(kxx, dx, kxz * dz), kzz * dz * dz)
+                              : -__builtin_inff();
         uint32_t off = 0u;
         if (act) {
             off = FROM_LDS ? (uint32_t)fmaf(zf, (float)RZS, xh + obase)
@@ -256,16 +260,18 @@ __device__ __forceinline__ void group_of_gaussians(const BackwardArgs& a, int kk
                         !voxel_in_block(mw, a.bq.res, a.bq.radius, vx, loy + k, vz, cm))
                         gv[k] = 0.0f;
             }
+            // centred in y: Q = qxz + dy (by + kyy dy) with dy = dy0 + k, and the column sums
+            // in dy itself (s1 = sum dy gE, s2 = sum dy^2 gE), so that a box much wider than
+            // its Gaussian (the block query) adds no large terms that cancel
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 if (k < max_wy) {
-                    const float Q = k == 0 ? A : A + (float)k * (B + (float)k * kyy);
+                    const float dy = dy0 + (float)k;
+                    const float Q = fmaf(dy, fmaf(kyy, dy, by), qxz);
                     const float ge = gv[k] * __builtin_amdgcn_exp2f(Q);
                     s0 += ge;
-                    if (k > 0) {
-                        s1 += (float)k * ge;
-                        s2 += (float)(k * k) * ge;
-                    }
+                    s1 = fmaf(dy, ge, s1);
+                    s2 = fmaf(dy * dy, ge, s2);
                 }
             }
         }
@@ -279,10 +285,18 @@ __device__ __forceinline__ void group_of_gaussians(const BackwardArgs& a, int kk
                                 cm))
                 gk = 0.0f;
             const float fk = (float)k;
-            const float ge = gk * __builtin_amdgcn_exp2f(A + fk * (B + fk * kyy));
-            s0 += ge;
-            s1 += fk * ge;
-            s2 += fk * fk * ge;
+            if (FROM_LDS) {
+                const float ge = gk * __builtin_amdgcn_exp2f(A + fk * (B + fk * kyy));
+                s0 += ge;
+                s1 += fk * ge;
+                s2 += fk * fk * ge;
+            } else {
+                const float dy = dy0 + fk;
+                const float ge = gk * __builtin_amdgcn_exp2f(fmaf(dy, fmaf(kyy, dy, by), qxz));
+                s0 += ge;
+                s1 = fmaf(dy, ge, s1);
+                s2 = fmaf(dy * dy, ge, s2);
+            }
         }
         // the column's share in the step index k (moments in dy = dy0 + k follow below)
         const float ax = s0 * dx, az = s0 * dz;
@@ -300,10 +314,11 @@ __device__ __forceinline__ void group_of_gaussians(const BackwardArgs& a, int kk
     // from sums over the step index k to moments in dy = dy0 + k (dy0 is the Gaussian's):
     // sum (dy0 + k) gE = k1 + dy0 m0, sum (dy0 + k)^2 gE = k2 + dy0 (2 k1 + dy0 m0), and
     // the products with dx and dz likewise
-    float my = fmaf(dy0, m0, k1);
-    float myy = fmaf(dy0, fmaf(2.0f, k1, dy0 * m0), k2);
-    float mxy = fmaf(dy0, mx, k1x);
-    float myz = fmaf(dy0, mz, k1z);
+    // (the global-memory path summed in dy already: k1, k2, k1x, k1z are the moments)
+    float my = FROM_LDS ? fmaf(dy0, m0, k1) : k1;
+    float myy = FROM_LDS ? fmaf(dy0, fmaf(2.0f, k1, dy0 * m0), k2) : k2;
+    float mxy = FROM_LDS ? fmaf(dy0, mx, k1x) : k1x;
+    float myz = FROM_LDS ? fmaf(dy0, mz, k1z) : k1z;
     m0 = group_sum<G>(m0);
     mx = group_sum<G>(mx);
     my = group_sum<G>(my);
@@ -406,6 +421,13 @@ __global__ __launch_bounds__(256) void k_partials(const BackwardArgs a)
         const int4 r2 = rc[2], r3 = rc[3];     // (kxz, kyz, lox, loy), (loz, hix, hiy, hiz)
         const int lx = r2.z, ly = r2.w, lz = r3.x, hx = r3.y, hy = r3.z, hz = r3.w;
         if (!(hx - t0x < RX && hy - t0y < RY && hz - t0z < RZ)) return NKEY - 1;
+        if (a.block_query) {
+            // a box much wider in y than its Gaussian (|kyy| wy^2 > 64; a 3-sigma box stays
+            // below about 50) takes the global-memory path, whose walk is centred
+            const float kyy = __int_as_float(rc[1].y);
+            const float wyf = (float)(hy - ly + 1);
+            if (fabsf(kyy) * wyf * wyf > 64.0f) return NKEY - 1;
+        }
         zreach = hz - t0z + 1;
         const int chunks = ((hx - lx + 1) * (hz - lz + 1) + BWD_G - 1) / BWD_G;
         return (min(chunks, 8) - 1) * 16 + (min(hy - ly + 1, 16) - 1);

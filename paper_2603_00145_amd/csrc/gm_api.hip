@@ -995,6 +995,7 @@ gm_status backward_impl(const gm_gaussians* g, const gm_bins* bins, const int32_
     ba.grid_grads = bins->grid_grads;
     ba.pair_gauss = reinterpret_cast<const uint32_t*>(bins->pair_gauss);
     ba.tile_start = bins->tile_start;
+    ba.block_query = bins->block_radius > 0 ? 1 : 0;
     for (int k = 0; k < n_ids; ++k) {
         const gm_grid& gr = bins->grids[grid_ids[k]];
         if (partials) {

@@ -175,6 +175,7 @@ struct BackwardArgs {
     int32_t ntx[GM_MAX_GRIDS], nty[GM_MAX_GRIDS];
     int32_t block_start[GM_MAX_GRIDS + 1];  // first block (= tile) of each listed grid
     BlockQuery bq;                      // read on masked grids
+    int32_t block_query;                // the bins come from the block query (any grid)
     int32_t masked[GM_MAX_GRIDS];       // the block query on a rotated grid
     double m[GM_MAX_GRIDS][12];         // masked grids: index -> world affine
 };

@@ -77,11 +77,16 @@ def rotated_problem(rng, n=41, n_g=900):
     return g, grids
 
 
-@pytest.mark.parametrize("res,r", [(12, 1), (24, 2), (40, 1)])
+@pytest.mark.parametrize("res,r", [(12, 1), (24, 2), (40, 1), (1, 1), (7, 9)])
 def test_block_query_on_rotated_grids(mods, res, r):
+    """(1, 1): one cell, every voxel of every grid in every block; (7, 9): blocks wider than
+    the cell grid.  A tenth of the Gaussians sit outside [-1, 1]^3 (negative or beyond-last
+    cells)."""
     _lib, api = mods
     rng = np.random.default_rng(100 + res + r)
     g, grids = rotated_problem(rng)
+    out = rng.choice(g.n, g.n // 10, replace=False)
+    g.mean[out] = rng.uniform(-1.3, 1.3, (len(out), 3)).astype(np.float32)
     ids = list(range(len(grids)))
     say(f"block query on rotated grids: res {res} r {r}")
     p = api.GaussParams.from_host(g)
